@@ -1,0 +1,205 @@
+"""Seeded synthetic inputs for the P3MaZe mesh step.
+
+This module only draws particle configurations: positions, charges, masses,
+velocities and box sizes.  It holds none of the method's arithmetic, so both
+the HIP path and the CPU oracle can be fed from it without sharing any code.
+
+Recipes (the paper's own systems are replaced by these synthetic stand-ins;
+no dataset is involved):
+
+* ``nacl``  -- molten-salt-like rock-salt ions: the first half Na (+1 e,
+  22.99 amu), the second half Cl (-1 e, 35.45 amu), placed uniformly at
+  random with a hard-core rejection on the minimum-image pair distance.
+* ``water`` -- point-charge water: O (-0.82 e, 15.999 amu) placed uniformly
+  at random with an O-O hard core, two H (+0.41 e, 1.008 amu) at a fixed
+  O-H length and H-O-H angle with a uniformly random orientation, redrawn
+  while any intermolecular pair is closer than a second hard core.
+  Atoms are stored molecule by molecule as O, H, H.
+
+Velocities are Maxwell-Boltzmann at the requested temperature with the
+centre-of-mass velocity removed.  Units: Angstrom, e, amu, fs, K.
+
+All randomness comes from ``numpy.random.Generator(PCG64(seed))``.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+from scipy.spatial import cKDTree
+
+KB_EV = 8.617333262e-5            # Boltzmann constant [eV/K]
+EV_PER_AMU_A2_FS2 = 103.6427      # 1 amu*A^2/fs^2 expressed in eV
+AMU_G = 1.66053906660e-24         # 1 amu in grams
+
+NA_Q, CL_Q = 1.0, -1.0
+NA_M, CL_M = 22.99, 35.45
+O_Q, H_Q = -0.82, 0.41
+O_M, H_M = 15.999, 1.008
+
+
+@dataclasses.dataclass
+class System:
+    """One periodic particle system (host numpy arrays, float64)."""
+    pos: np.ndarray        # [n, 3] Angstrom, inside [0, box)
+    charges: np.ndarray    # [n] e
+    masses: np.ndarray     # [n] amu
+    vel: np.ndarray        # [n, 3] Angstrom/fs
+    box: float             # cubic edge [Angstrom]
+    kind: str              # "nacl" | "water" | "lattice"
+
+    @property
+    def n(self) -> int:
+        return int(self.pos.shape[0])
+
+    def density_g_cm3(self) -> float:
+        return float(self.masses.sum() * AMU_G / (self.box * 1e-8) ** 3)
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def hard_core_points(rng: np.random.Generator, n: int, box: float, dmin: float,
+                     max_rounds: int = 400) -> np.ndarray:
+    """Uniform random points in a periodic cube, no pair closer than ``dmin``.
+
+    Batched random sequential addition: each round draws a batch of uniform
+    candidates, drops those within ``dmin`` (minimum image) of an accepted
+    point, and of every conflicting pair inside the batch keeps only the
+    lower-indexed candidate.  Accepted points keep their draw order.
+    """
+    acc = np.zeros((0, 3))
+    for _ in range(max_rounds):
+        need = n - acc.shape[0]
+        if need <= 0:
+            break
+        m = int(need * 1.5) + 64
+        cand = rng.uniform(0.0, box, size=(m, 3))
+        cand = np.minimum(cand, np.nextafter(box, 0.0))
+        ok = np.ones(m, dtype=bool)
+        if acc.shape[0]:
+            tree = cKDTree(acc, boxsize=box)
+            d, _ = tree.query(cand, k=1, distance_upper_bound=dmin)
+            ok &= ~(d < dmin)
+        idx = np.nonzero(ok)[0]
+        if idx.size > 1:
+            ct = cKDTree(cand[idx], boxsize=box)
+            pairs = ct.query_pairs(dmin, output_type="ndarray")
+            if pairs.size:
+                drop = np.unique(np.maximum(pairs[:, 0], pairs[:, 1]))
+                keep = np.ones(idx.size, dtype=bool)
+                keep[drop] = False
+                idx = idx[keep]
+        acc = np.concatenate([acc, cand[idx[:need]]], axis=0)
+    if acc.shape[0] < n:
+        raise RuntimeError(f"could not place {n} points with separation {dmin} in box {box}")
+    return acc
+
+
+def maxwell_boltzmann(rng: np.random.Generator, masses: np.ndarray, temp_k: float) -> np.ndarray:
+    """Velocities [A/fs] at temperature ``temp_k`` with zero total momentum."""
+    s = np.sqrt(KB_EV * temp_k / (masses * EV_PER_AMU_A2_FS2))
+    v = rng.standard_normal((masses.size, 3)) * s[:, None]
+    vcm = (masses[:, None] * v).sum(axis=0) / masses.sum()
+    return v - vcm
+
+
+def nacl(n_ions: int, box: float, temp_k: float, seed: int, dmin: float = 2.0) -> System:
+    """Molten-salt-like ions: indices [0, n/2) Na+, [n/2, n) Cl-."""
+    if n_ions % 2:
+        raise ValueError("n_ions must be even for a neutral salt")
+    rng = _rng(seed)
+    pos = hard_core_points(rng, n_ions, box, dmin)
+    half = n_ions // 2
+    q = np.concatenate([np.full(half, NA_Q), np.full(half, CL_Q)])
+    m = np.concatenate([np.full(half, NA_M), np.full(half, CL_M)])
+    vel = maxwell_boltzmann(rng, m, temp_k)
+    return System(pos, q, m, vel, float(box), "nacl")
+
+
+def _random_rotations(rng: np.random.Generator, k: int) -> np.ndarray:
+    """Uniform random rotation matrices from normalised Gaussian quaternions."""
+    qv = rng.standard_normal((k, 4))
+    qv /= np.linalg.norm(qv, axis=1, keepdims=True)
+    w, x, y, z = qv.T
+    return np.stack([
+        np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)], -1),
+        np.stack([2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)], -1),
+        np.stack([2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)], -1),
+    ], axis=1)
+
+
+def water(n_mol: int, box: float, temp_k: float, seed: int, r_oh: float = 1.0,
+          angle_deg: float = 109.47, d_oo: float = 2.4, d_inter: float = 1.2,
+          max_rounds: int = 200) -> System:
+    """Point-charge water; atoms ordered O, H, H per molecule."""
+    rng = _rng(seed)
+    opos = hard_core_points(rng, n_mol, box, d_oo)
+    half = math.radians(angle_deg) / 2.0
+    tmpl = np.array([[0.0, 0.0, 0.0],
+                     [r_oh * math.sin(half), 0.0, r_oh * math.cos(half)],
+                     [-r_oh * math.sin(half), 0.0, r_oh * math.cos(half)]])
+    rot = _random_rotations(rng, n_mol)
+    mol_id = np.repeat(np.arange(n_mol), 3)
+
+    def build(rmats):
+        return opos[:, None, :] + np.einsum("mij,aj->mai", rmats, tmpl)
+
+    pos = build(rot)
+    for _ in range(max_rounds):
+        flat = np.mod(pos.reshape(-1, 3), box)
+        flat = np.minimum(flat, np.nextafter(box, 0.0))
+        tree = cKDTree(flat, boxsize=box)
+        pairs = tree.query_pairs(d_inter, output_type="ndarray")
+        if pairs.size:
+            inter = mol_id[pairs[:, 0]] != mol_id[pairs[:, 1]]
+            pairs = pairs[inter]
+        if pairs.size == 0:
+            break
+        bad = np.unique(np.concatenate([mol_id[pairs[:, 0]], mol_id[pairs[:, 1]]]))
+        rot[bad] = _random_rotations(rng, bad.size)
+        pos = build(rot)
+    else:
+        raise RuntimeError("could not orient water molecules without overlaps")
+    pos = pos.reshape(-1, 3)
+    q = np.tile([O_Q, H_Q, H_Q], n_mol)
+    m = np.tile([O_M, H_M, H_M], n_mol)
+    vel = maxwell_boltzmann(rng, m, temp_k)
+    # positions stay unwrapped so molecules are whole; the mesh step wraps.
+    return System(pos, q, m, vel, float(box), "water")
+
+
+def rock_salt(n_cells: int, a: float, shift: float = 0.0) -> System:
+    """Perfect rock-salt crystal of ``n_cells``^3 conventional cells (8 ions each).
+
+    ``a`` is the conventional lattice constant (nearest-neighbour distance a/2);
+    ``shift`` translates the whole crystal along (1,1,1).
+    """
+    base = np.array([[0, 0, 0], [0, .5, .5], [.5, 0, .5], [.5, .5, 0]])
+    cells = np.array([[i, j, k] for k in range(n_cells) for j in range(n_cells)
+                      for i in range(n_cells)], dtype=float)
+    na = (cells[:, None, :] + base[None]).reshape(-1, 3)
+    cl = (cells[:, None, :] + base[None] + np.array([.5, 0, 0])).reshape(-1, 3)
+    pos = np.concatenate([na, cl]) * a + shift
+    box = n_cells * a
+    pos = np.mod(pos, box)
+    n = pos.shape[0]
+    q = np.concatenate([np.full(n // 2, NA_Q), np.full(n // 2, CL_Q)])
+    m = np.concatenate([np.full(n // 2, NA_M), np.full(n // 2, CL_M)])
+    return System(pos, q, m, np.zeros_like(pos), float(box), "lattice")
+
+
+def random_neutral(n: int, box: float, seed: int, dmin: float = 0.0) -> System:
+    """Small test systems: random positions, alternating +-1 charges."""
+    rng = _rng(seed)
+    if dmin > 0:
+        pos = hard_core_points(rng, n, box, dmin)
+    else:
+        pos = rng.uniform(0.0, box, size=(n, 3))
+    q = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    if n % 2:
+        q[-1] = 0.0
+    m = np.full(n, 20.0)
+    return System(pos, q, m, np.zeros_like(pos), float(box), "random")
