@@ -1,0 +1,179 @@
+/*
+ * p3maze.h -- C ABI of the MI355X (gfx950) P3MaZe long-range electrostatics step.
+ *
+ * The problem is the one stated in the paper's Theory section: point charges
+ * Q_b at positions r_b in a cubic periodic box of edge L, a Gaussian
+ * screening of width sigma (Eq. 4) that splits the Coulomb energy into a
+ * short-range pair sum, a smooth long-range mesh part and a self term
+ * (Eqs. 5-7), a real-space cutoff R_c (Eq. 6), a cubic mesh of spacing
+ * h = L/N carrying the potential of the smooth charges (Eq. 10), and a
+ * B-spline assignment/interpolation order.  Each compute call is one step of
+ * the constrained ("Mass-Zero") dynamics of the mesh potential: Verlet
+ * prediction, correction problem M y = sigma_p (Eqs. 16-17) solved by
+ * multigrid V-cycles to a max-norm residual tolerance (Eq. 26), field update
+ * (Supporting Information, numerical integration), forces by interpolating a
+ * central-difference mesh gradient (Eq. 21) plus the screened pair forces
+ * (Eq. 20).
+ *
+ * Conventions shared by every entry point:
+ *   - Return value: p3mz_status.  Negative = error, outputs undefined; the
+ *     message is available from p3mz_last_error() (per thread).  Positive =
+ *     warning, outputs valid.  No C++ exception crosses this boundary.
+ *   - Pointers named *_dev are device pointers (hipMalloc'd or torch CUDA
+ *     tensors' data_ptr) on the device the context was created on;
+ *     *_host are host pointers.  The caller owns them; the library never
+ *     frees or keeps them beyond the call.
+ *   - stream: a hipStream_t passed as void* (NULL = the default stream).
+ *     Work is enqueued on it; a call returns after enqueueing, except where
+ *     a comment says it synchronises.
+ *   - Particle arrays are array-of-structures [n][3] doubles; positions may
+ *     be in any periodic image.  Mesh arrays are [N][N][N] doubles with x
+ *     fastest.
+ *   - Units are the caller's: lengths as the box, charges as given, energies
+ *     and forces scaled by coulomb_k.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef P3MAZE_H
+#define P3MAZE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  P3MZ_OK = 0,
+  P3MZ_WARN_NOT_CONVERGED = 1,   /* cycle cap reached; results written, stats hold the residual */
+  P3MZ_ERR_INVALID_ARG = -1,     /* NULL pointer, parameter out of range, r_cut > L/2 ... */
+  P3MZ_ERR_NOT_NEUTRAL = -2,     /* |sum Q| > 1e-10 sum |Q|: the periodic problem has no solution */
+  P3MZ_ERR_MESH_SHAPE = -3,      /* N not 4*2^m (m >= 1), or h too coarse for sigma */
+  P3MZ_ERR_OUT_OF_MEMORY = -4,
+  P3MZ_ERR_HIP = -5,             /* a HIP runtime call failed */
+  P3MZ_ERR_NAN = -6,             /* non-finite position */
+  P3MZ_ERR_STATE = -7,           /* call not valid in the context's state (e.g. bad state blob) */
+  P3MZ_ERR_DENSITY = -8          /* too many atoms in one spatial bin for the deterministic sort */
+} p3mz_status;
+
+typedef enum { P3MZ_PREC_FP64 = 0, P3MZ_PREC_MIXED = 1 } p3mz_precision;
+
+/* Control parameters of the problem statement (Theory; protocol paragraphs
+ * of the molten-salt and water results). */
+typedef struct {
+  double box;          /* cubic edge L > 0                                             */
+  double alpha;        /* Ewald splitting > 0; Gaussian width sigma = 1/(sqrt(2) alpha) */
+  double r_cut;        /* real-space cutoff R_c, 0 < R_c <= L/2 (minimum image)        */
+  int32_t mesh;        /* N points per edge, N = 4*2^m, 1 <= m <= 7 (8, 16, ..., 512)   */
+  int32_t order;       /* B-spline order p, 2..7 (the paper uses cubic, p = 4)          */
+  double tol;          /* residual tolerance > 0                                        */
+  int32_t tol_mode;    /* 0: max|M y - sigma_p| <= tol * max|q^s|; 1: <= tol (absolute) */
+  int32_t max_cycles;  /* V-cycle cap per step, 0..64                                   */
+  int32_t predictor;   /* multiplier predictor: 0 (Verlet prediction only, the in-house
+                          real-space P3M start), 1: y^k, 2: 2y^k - y^{k-1},
+                          3: 3y^k - 3y^{k-1} + y^{k-2}                                  */
+  int32_t precision;   /* p3mz_precision                                                */
+  double coulomb_k;    /* Coulomb constant k_e (1 for Gaussian units)                   */
+  int32_t nu_pre;      /* red-black Gauss-Seidel sweeps before restriction, >= 0;
+                          -1: the autotuned or default (2) value                       */
+  int32_t nu_post;     /* ... after prolongation; -1 as above; nu_pre+nu_post >= 1      */
+  int32_t excl_group;  /* 0: no exclusions; g > 0: atoms i, j with i/g == j/g interact
+                          only through the mesh minus its erf part (rigid-molecule
+                          exclusion, e.g. g = 3 for O,H,H water)                      */
+} p3mz_params;
+
+typedef struct {
+  int32_t status;            /* status of the last compute                            */
+  int32_t cycles;            /* V-cycles of the last compute                          */
+  int32_t cold;              /* 1 if the last compute was a cold solve               */
+  int32_t m_eff;             /* predictor order actually used (ramped by history)    */
+  int32_t nu_pre, nu_post;   /* resolved sweep counts                                 */
+  int32_t K;                 /* smoothing steps per dimension                         */
+  int32_t levels;            /* multigrid levels down to 4^3                          */
+  double nu_smooth;          /* smoothing step weight                                 */
+  double thresh;             /* residual threshold of the last compute               */
+  double norm_qs;            /* max |q^s|                                             */
+  double res_hist[65];       /* residual before cycle c, c = 0..cycles                */
+  double e_sr, e_lr, e_self, e_total;
+  int64_t steps;             /* completed compute calls since create/load            */
+} p3mz_stats;
+
+typedef struct p3mz_ctx p3mz_ctx;
+
+/* Allocate a context for n_atoms charges (host array, copied).  Plans the
+ * mesh hierarchy and allocates every workspace on the current HIP device, so
+ * compute never allocates.  Errors: INVALID_ARG, MESH_SHAPE, NOT_NEUTRAL,
+ * OUT_OF_MEMORY, HIP.  On error *out is NULL. */
+p3mz_status p3mz_create(const p3mz_params* params, int64_t n_atoms, const double* charges_host,
+                        p3mz_ctx** out);
+
+/* One mesh step at positions pos_dev [n][3].  Writes force_dev [n][3]
+ * (short-range + long-range electrostatic force, overwritten) and
+ * energy_dev [4] = {E_sr, E_lr, E_self, E_total}.  The first call after
+ * create/reset is a cold solve from a zero potential; later calls warm-start
+ * from the stored potential and multiplier history.  Synchronises the stream
+ * while deciding the number of V-cycles.  force_dev / energy_dev may be NULL
+ * to skip those outputs (the mesh potential is still advanced).  Errors:
+ * INVALID_ARG, NAN, DENSITY, HIP; warning NOT_CONVERGED. */
+p3mz_status p3mz_compute(p3mz_ctx* ctx, const double* pos_dev, double* force_dev,
+                         double* energy_dev, void* stream);
+
+/* Copy an internal mesh of the last compute to phi_dev ([N][N][N] doubles,
+ * x fastest): which = 0 assigned charges q, 1 smoothed q^s, 2 sigma_p
+ * (zero-mean), 3 multiplier y, 4 potential phi^{k+1}, 5 previous potential.
+ * FP32 meshes of the mixed mode are widened exactly. */
+p3mz_status p3mz_get_mesh(p3mz_ctx* ctx, int32_t which, double* out_dev, void* stream);
+
+/* One V-cycle of the context's schedule for M e = r on the finest mesh:
+ * r_dev, e_dev [N][N][N] doubles (e is overwritten).  In mixed mode r is
+ * rounded to FP32 and the cycle runs in the mixed precision of the step.
+ * Leaves the potential history untouched. */
+p3mz_status p3mz_vcycle(p3mz_ctx* ctx, const double* r_dev, double* e_dev, void* stream);
+
+/* Statistics of the last compute (host struct). */
+p3mz_status p3mz_get_stats(const p3mz_ctx* ctx, p3mz_stats* out);
+
+/* Forget the potential/multiplier history: the next compute is a cold solve. */
+p3mz_status p3mz_reset_history(p3mz_ctx* ctx);
+
+/* Serialise the history {phi^k, phi^{k-1}, stored multipliers, counters} into
+ * host_buf.  With host_buf == NULL, *bytes receives the size.  Synchronises. */
+p3mz_status p3mz_save_state(const p3mz_ctx* ctx, void* host_buf, size_t* bytes);
+/* Restore a blob written by p3mz_save_state of a context with the same mesh
+ * and precision.  Errors: STATE if the blob does not match. */
+p3mz_status p3mz_load_state(p3mz_ctx* ctx, const void* host_buf, size_t bytes);
+
+/* Non-electrostatic terms for p3mz_md_run (eV / Angstrom / amu / fs style
+ * units are the caller's choice, fixed by the two conversion factors). */
+typedef struct {
+  int32_t model;        /* 0 none, 1 stand-in Born-Mayer repulsion between all pairs,
+                           2 flexible three-site water (atoms O,H,H per molecule)   */
+  double bm_a, bm_rho;  /* model 1: A exp(-r/rho), shifted to zero at r_cut         */
+  double lj_eps, lj_sigma;   /* model 2: O-O Lennard-Jones, shifted to zero at r_cut */
+  double k_bond, r0;    /* model 2: 0.5 k (r - r0)^2 per O-H bond                   */
+  double k_angle, theta0;    /* model 2: 0.5 k (theta - theta0)^2, radians          */
+  double force_to_acc;  /* acceleration = force / mass * force_to_acc              */
+  double mv2_to_energy; /* kinetic energy = 0.5 m v^2 * mv2_to_energy               */
+} p3mz_mdterms;
+
+/* n_steps of velocity Verlet (Theory, numerical integration) driving one
+ * mesh step per MD step.  pos_dev/vel_dev [n][3] are advanced in place;
+ * mass_dev [n].  energy_log_dev [n_steps][6] = {E_sr, E_lr, E_self,
+ * E_other, E_kin, E_total}; cycles_log_dev [n_steps] V-cycles per step
+ * (either may be NULL).  The first call computes the forces at the initial
+ * positions (a cold solve) before the first step.  Synchronises once per
+ * step.  Errors as p3mz_compute. */
+p3mz_status p3mz_md_run(p3mz_ctx* ctx, double* pos_dev, double* vel_dev, const double* mass_dev,
+                        const p3mz_mdterms* terms, double dt, int32_t n_steps,
+                        double* energy_log_dev, int32_t* cycles_log_dev, void* stream);
+
+void p3mz_destroy(p3mz_ctx* ctx);
+const char* p3mz_status_string(p3mz_status s);
+const char* p3mz_last_error(void);
+/* Library version string, e.g. "p3maze-gfx950 0.1". */
+const char* p3mz_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

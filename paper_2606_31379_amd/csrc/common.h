@@ -1,0 +1,133 @@
+// Internal declarations shared by the HIP translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define P3MZ_MAX_CYCLES 64
+#define P3MZ_MAX_LEVELS 16
+#define P3MZ_MAX_ORDER 7
+#define P3MZ_TAIL_MAX 16        // levels of at most 16^3 run in one LDS-resident workgroup
+#define P3MZ_WAVE 64
+
+// Device-side control block of one mesh step.  Kernels of the V-cycle read
+// `done` first and return at once when the solve has converged, so a fixed
+// launch sequence can hold more cycles than the step needs.
+struct Ctl {
+  int done;              // 1: converged or cycle cap reached
+  int cycles;            // V-cycles applied this step
+  int status;            // 0 ok, 1 cycle cap reached
+  int final_buf;         // which y ping-pong buffer holds the final multiplier
+  unsigned int ticket;   // arrival counter for the last-block reductions
+  unsigned int ticket2;
+  unsigned int ticket3;
+  int nan_flag;          // non-finite position seen by the binning kernel
+  int overflow_flag;     // bin with more atoms than the sort handles
+  int pad_;
+  double thresh;         // residual threshold
+  double norm_qs;        // max |q^s|
+  double mean_sigma;     // mean of the unprojected sigma_p
+  double mean_y;         // mean of the final multiplier
+  double sum_y;          // running sum of the current multiplier (per outer kernel)
+  double e_lr, e_sr;
+  double res_hist[P3MZ_MAX_CYCLES + 1];
+};
+
+// --- wave / block reductions (wave64) ------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Block-wide sum / max with a fixed reduction tree (deterministic for a fixed
+// block size).  `sh` needs blockDim.x/64 doubles.  Result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < nw; i++) r += sh[i];
+  return r;
+}
+__device__ __forceinline__ double block_max(double v, double* sh) {
+  v = wave_max(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < nw; i++) r = fmax(r, sh[i]);
+  return r;
+}
+
+// Last-block pattern: every block stores its partial, then the block that
+// arrives last reads all partials in index order.  Returns true in the last
+// block (all threads).  `ticket` is reset for the next use.
+__device__ __forceinline__ bool last_block_arrives(unsigned int* ticket, int* sh_flag) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned int t = atomicAdd(ticket, 1u);
+    *sh_flag = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  bool last = *sh_flag;
+  if (last) {
+    __threadfence();
+    if (threadIdx.x == 0) *ticket = 0u;
+  }
+  return last;
+}
+
+// Deterministic sum of n partials by one block: fixed strided split + fixed tree.
+__device__ __forceinline__ double reduce_partials_sum(const double* p, int n, double* sh) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) acc += p[i];
+  return block_sum(acc, sh);
+}
+__device__ __forceinline__ double reduce_partials_max(const double* p, int n, double* sh) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) acc = fmax(acc, p[i]);
+  return block_max(acc, sh);
+}
+
+// --- mesh indexing ---------------------------------------------------------
+// Natural layout: x fastest.  Colour-split layout: the points of colour
+// c = (i+j+k)&1 of each row (j,k) are packed, index ((k*n + j)*(n/2) + i/2).
+__device__ __forceinline__ int nat_idx(int n, int i, int j, int k) { return (k * n + j) * n + i; }
+__device__ __forceinline__ int cs_idx(int n, int i, int j, int k) { return (k * n + j) * (n >> 1) + (i >> 1); }
+__device__ __forceinline__ int wrapn(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// B-spline weights of order p at fractional offset tau in [0,1):
+// w[j] = M_p(tau + p - 1 - j), built by the triangular de Boor recursion
+// w_j^(k) = ((tau + k-1-j) w_{j-1}^(k-1) + (1 - tau + j) w_j^(k-1)) / (k-1).
+template <typename T>
+__device__ __forceinline__ void bspline_weights(int p, T tau, T* w) {
+  w[0] = T(1);
+  for (int k = 2; k <= p; k++) {
+    T inv = T(1) / T(k - 1);
+    T prev = T(0);   // w_{j-1}^{(k-1)}
+    for (int j = 0; j < k; j++) {
+      T cur = (j < k - 1) ? w[j] : T(0);
+      w[j] = ((tau + T(k - 1 - j)) * prev + (T(1) - tau + T(j)) * cur) * inv;
+      prev = cur;
+    }
+  }
+}
+
+// Host-side error helper.
+#define P3MZ_HIP_TRY(expr)                        \
+  do {                                            \
+    hipError_t e_ = (expr);                       \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr, __FILE__, __LINE__); \
+  } while (0)

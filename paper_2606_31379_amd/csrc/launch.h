@@ -1,0 +1,86 @@
+// Host-side launchers of the kernels, one function per kernel family.
+// Every launcher enqueues on `s` and returns the launch status.
+#pragma once
+
+#include "common.h"
+
+// ---- particles (particles.hip) ------------------------------------------
+// Per-atom stencil base, B-spline weights (precision T) and tile key for
+// the spread; slot = arrival rank inside the key's bin.
+hipError_t launch_bin_stencil(bool fp64, int n_atoms, const double* pos, double box, int n, int p,
+                              int tile, int ntx, int* base, void* w, int* key, int* slot, int* count,
+                              Ctl* ctl, hipStream_t s);
+// Cell key of each atom for the short-range cell list (nc cells per edge).
+hipError_t launch_bin_cells(int n_atoms, const double* pos, double box, int nc, int* key, int* slot,
+                            int* count, Ctl* ctl, hipStream_t s);
+// Exclusive scan of count[0..nbins) into start[0..nbins], zeroing count.
+hipError_t launch_scan(int nbins, int* count, int* start, hipStream_t s);
+// perm_raw[start[key[a]] + slot[a]] = a.
+hipError_t launch_scatter(int n_atoms, const int* key, const int* slot, const int* start, int* perm_raw,
+                          hipStream_t s);
+// Sort every bin's atom list by atom index (makes all later sums deterministic).
+hipError_t launch_sort_bins(int nbins, const int* start, const int* perm_raw, int* perm, Ctl* ctl,
+                            hipStream_t s);
+// Owner-computes spread: q (natural layout, precision T) from the binned atoms.
+hipError_t launch_spread(bool fp64, int n, int p, int tile, int ntx, const int* start, const int* perm,
+                         const int* base, const void* w, const double* qa, void* q, hipStream_t s);
+// Long-range force and energy by interpolating the central-difference
+// gradient of phi (precision of phi: fp64 or float).
+hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, double h, double k_e, const int* perm,
+                         const int* base, const void* w, const double* qa, const void* phi,
+                         double* force, double* partial, Ctl* ctl, hipStream_t s);
+// Short-range erfc pairs on the cell list, exclusion correction, energy
+// assembly into energy_out[4] (may be NULL).  force += F_sr.
+hipError_t launch_sr(int n_atoms, const double* pos, const double* qa, double box, double alpha,
+                     double r_cut, double k_e, int nc, int excl_group, const int* cstart,
+                     const int* cperm, double* force, double e_self, double* energy_out,
+                     double* partial, Ctl* ctl, hipStream_t s);
+
+// ---- mesh (mesh.hip) -----------------------------------------------------
+// Folded periodic smoothing filter along one axis: out = sum_m c[m] v[i+m-K].
+hipError_t launch_smooth(bool fp64, int n, int axis, int ntaps, int half, const void* taps,
+                         const void* in, void* out, hipStream_t s);
+// sigma_p = (h/4pi) M (2 phi_k - phi_km1) + q^s (cold: q^s), predictor y0 into y,
+// last block: mean of sigma_p, max|q^s|, threshold, resets the step's control.
+hipError_t launch_sigma(bool fp64, int n, double h, int cold, int m_eff, const void* qs,
+                        const double* phi_k, const double* phi_km1, const double* yh0,
+                        const double* yh1, const double* yh2, double* sigma, double* y,
+                        double tol, int tol_mode, double* partial, Ctl* ctl, hipStream_t s);
+// Outer residual of cycle c: y_out = y_in + e (c > 0), r = sigma - mean - M y_out,
+// r written colour-split in T; last block records res_hist[c] and the stop decision.
+hipError_t launch_outer(bool fp64, int n, int c, int max_cycles, const double* sigma,
+                        const double* y_in, double* y_out, const void* e0, const void* e1,
+                        void* r0, void* r1, double* partial, Ctl* ctl, hipStream_t s);
+struct LevelBufs {
+  int n;
+  void* e0; void* e1;   // colour-split correction
+  void* r0; void* r1;   // colour-split right-hand side
+};
+// One V-cycle on the colour-split level hierarchy lv[0..levels-1]; the
+// levels from `tail` on run in one LDS-resident workgroup.
+hipError_t launch_vcycle(bool fp64, const LevelBufs* lv, int levels, int tail, int nu1, int nu2,
+                         const double* green, Ctl* ctl, hipStream_t s);
+// phi update and history push: phi_out = phi_p - (4pi/h)(y - mean y).
+hipError_t launch_phi_update(int n, double h, int cold, const double* phi_k, const double* phi_km1,
+                             const double* ya, const double* yb, double* phi_out, double* phi_copy,
+                             double* y_hist_out, float* phi32, Ctl* ctl, hipStream_t s);
+// Layout conversions for inspection and the stand-alone V-cycle.
+hipError_t launch_widen(bool fp64, int64_t count, const void* in, double* out, hipStream_t s);
+hipError_t launch_cs_to_nat(bool fp64, int n, const void* c0, const void* c1, double* out, hipStream_t s);
+hipError_t launch_nat_to_cs(bool fp64, int n, const double* in, void* c0, void* c1, hipStream_t s);
+hipError_t launch_set_ctl_open(Ctl* ctl, hipStream_t s);
+// out = in - *sub (device scalar).
+hipError_t launch_sub_scalar(int64_t count, const double* in, double* out, const double* sub, hipStream_t s);
+hipError_t tail_configure(bool fp64, int n_tail, int levels_tail, size_t* lds_bytes);
+
+// ---- molecular dynamics (md.hip) ----------------------------------------
+hipError_t launch_kick_drift(int n_atoms, double* pos, double* vel, const double* force,
+                             const double* mass, double dt, double f2a, int drift, hipStream_t s);
+hipError_t launch_nonelec(int n_atoms, const double* pos, double box, double r_cut, int model,
+                          double p0, double p1, double p2, double p3, double p4, double p5,
+                          int nc, const int* cstart, const int* cperm, double* force,
+                          double* partial, double* e_out, unsigned int* ticket, hipStream_t s);
+hipError_t launch_kinetic_log(int n_atoms, const double* vel, const double* mass, double mv2e,
+                              const double* energy4, const double* e_other, double* log_row,
+                              int* cycles_row, const Ctl* ctl, double* partial,
+                              unsigned int* ticket, hipStream_t s);

@@ -1,0 +1,184 @@
+// Molecular-dynamics support kernels: velocity-Verlet kicks and drift, the
+// non-electrostatic terms of the two model systems, and the energy log.
+#include "launch.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline int blocks_for(int64_t n, int b) { return (int)((n + b - 1) / b); }
+
+__global__ void __launch_bounds__(kBlock)
+k_kick_drift(int n_atoms, double* __restrict__ pos, double* __restrict__ vel, const double* __restrict__ f,
+             const double* __restrict__ mass, double dt, double f2a, int drift) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 3 * n_atoms) return;
+  const int a = t / 3;
+  double v = vel[t] + 0.5 * dt * f[t] / mass[a] * f2a;
+  vel[t] = v;
+  if (drift) pos[t] += dt * v;
+}
+
+__device__ __forceinline__ double mi(double d, double box, double inv_box) { return d - box * rint(d * inv_box); }
+
+// model 1: stand-in Born-Mayer repulsion between all pairs (shifted at r_cut);
+// model 2: flexible three-site water -- intermolecular O-O Lennard-Jones
+// (shifted at r_cut) plus harmonic O-H bonds and H-O-H angle.  One thread
+// per atom; each thread recomputes its molecule's bonded terms and keeps
+// the part acting on its own atom (no atomics).  force += F_other.
+__global__ void __launch_bounds__(kBlock)
+k_nonelec(int n_atoms, const double* __restrict__ pos, double box, double rc2, int model, double p0,
+          double p1, double p2, double p3, double p4, double p5, int nc, const int* __restrict__ cstart,
+          const int* __restrict__ cperm, double* __restrict__ force, double* __restrict__ partial,
+          double* __restrict__ e_out, unsigned int* ticket) {
+  __shared__ double sh[kBlock / 64];
+  __shared__ int flag;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  double en = 0.0;
+  if (t < n_atoms && model != 0) {
+    const int i = cperm[t];
+    const double inv_box = 1.0 / box;
+    const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
+    double fx = 0, fy = 0, fz = 0;
+    const bool pair_atom = model == 1 || (i % 3 == 0);
+    if (pair_atom) {
+      int c[3];
+      const double xs[3] = {xi, yi, zi};
+      for (int d = 0; d < 3; d++) {
+        double s = xs[d] * inv_box;
+        s -= floor(s);
+        int ci = (int)(s * nc);
+        c[d] = ci >= nc ? nc - 1 : ci;
+      }
+      const int span = nc >= 3 ? 1 : 0;
+      const int lo = nc >= 3 ? -1 : 0, hi = nc >= 3 ? 1 : nc - 1;
+      double shift = 0.0;
+      if (model == 1) shift = p0 * exp(-sqrt(rc2) / p1);
+      else {
+        const double s6 = (p1 * p1 / rc2) * (p1 * p1 / rc2) * (p1 * p1 / rc2);
+        shift = 4.0 * p0 * (s6 * s6 - s6);
+      }
+      for (int oz = lo; oz <= hi; oz++)
+        for (int oy = lo; oy <= hi; oy++)
+          for (int ox = lo; ox <= hi; ox++) {
+            const int cx = span ? (c[0] + ox + nc) % nc : ox;
+            const int cy = span ? (c[1] + oy + nc) % nc : oy;
+            const int cz = span ? (c[2] + oz + nc) % nc : oz;
+            const int cell = (cz * nc + cy) * nc + cx;
+            for (int jj = cstart[cell]; jj < cstart[cell + 1]; jj++) {
+              const int j = cperm[jj];
+              if (j == i) continue;
+              if (model == 2 && (j % 3 != 0 || j / 3 == i / 3)) continue;
+              const double dx = mi(xi - pos[3 * j], box, inv_box);
+              const double dy = mi(yi - pos[3 * j + 1], box, inv_box);
+              const double dz = mi(zi - pos[3 * j + 2], box, inv_box);
+              const double r2 = dx * dx + dy * dy + dz * dz;
+              if (r2 >= rc2) continue;
+              double f;
+              if (model == 1) {
+                const double r = sqrt(r2);
+                const double v = p0 * exp(-r / p1);
+                f = v / p1 / r;
+                en += 0.5 * (v - shift);
+              } else {
+                const double sr2 = p1 * p1 / r2;
+                const double sr6 = sr2 * sr2 * sr2;
+                f = 24.0 * p0 * (2.0 * sr6 * sr6 - sr6) / r2;
+                en += 0.5 * (4.0 * p0 * (sr6 * sr6 - sr6) - shift);
+              }
+              fx += f * dx; fy += f * dy; fz += f * dz;
+            }
+          }
+    }
+    if (model == 2) {
+      const int o = (i / 3) * 3;
+      double a[3], b[3];
+      for (int d = 0; d < 3; d++) {
+        a[d] = mi(pos[3 * (o + 1) + d] - pos[3 * o + d], box, inv_box);
+        b[d] = mi(pos[3 * (o + 2) + d] - pos[3 * o + d], box, inv_box);
+      }
+      const double la = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+      const double lb = sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+      const double fa = -p2 * (la - p3) / la, fb = -p2 * (lb - p3) / lb;
+      double cth = (a[0] * b[0] + a[1] * b[1] + a[2] * b[2]) / (la * lb);
+      cth = fmin(1.0, fmax(-1.0, cth));
+      const double th = acos(cth);
+      const double sth = fmax(sqrt(1.0 - cth * cth), 1e-12);
+      const double g = p4 * (th - p5) / sth;
+      double f1[3], f2[3];
+      for (int d = 0; d < 3; d++) {
+        f1[d] = fa * a[d] + g * (b[d] / (la * lb) - cth * a[d] / (la * la));
+        f2[d] = fb * b[d] + g * (a[d] / (la * lb) - cth * b[d] / (lb * lb));
+      }
+      const int role = i - o;
+      const double* fr = role == 1 ? f1 : f2;
+      if (role == 0) {
+        fx -= f1[0] + f2[0]; fy -= f1[1] + f2[1]; fz -= f1[2] + f2[2];
+        en += 0.5 * p2 * ((la - p3) * (la - p3) + (lb - p3) * (lb - p3)) + 0.5 * p4 * (th - p5) * (th - p5);
+      } else {
+        fx += fr[0]; fy += fr[1]; fz += fr[2];
+      }
+    }
+    force[3 * i] += fx;
+    force[3 * i + 1] += fy;
+    force[3 * i + 2] += fz;
+  }
+  double bs = block_sum(en, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = bs;
+  if (last_block_arrives(ticket, &flag)) {
+    double tot = reduce_partials_sum(partial, gridDim.x, sh);
+    if (threadIdx.x == 0) *e_out = tot;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_kinetic_log(int n_atoms, const double* __restrict__ vel, const double* __restrict__ mass, double mv2e,
+              const double* __restrict__ e4, const double* __restrict__ e_other, double* __restrict__ row,
+              int* __restrict__ crow, const Ctl* ctl, double* __restrict__ partial, unsigned int* ticket) {
+  __shared__ double sh[kBlock / 64];
+  __shared__ int flag;
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  double ke = 0.0;
+  if (a < n_atoms) {
+    const double vx = vel[3 * a], vy = vel[3 * a + 1], vz = vel[3 * a + 2];
+    ke = 0.5 * mass[a] * (vx * vx + vy * vy + vz * vz) * mv2e;
+  }
+  double bs = block_sum(ke, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = bs;
+  if (last_block_arrives(ticket, &flag)) {
+    double tot = reduce_partials_sum(partial, gridDim.x, sh);
+    if (threadIdx.x == 0) {
+      if (row) {
+        row[0] = e4[0]; row[1] = e4[1]; row[2] = e4[2]; row[3] = *e_other; row[4] = tot;
+        row[5] = e4[3] + *e_other + tot;
+      }
+      if (crow) *crow = ctl->cycles;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_kick_drift(int n_atoms, double* pos, double* vel, const double* force, const double* mass,
+                             double dt, double f2a, int drift, hipStream_t s) {
+  hipLaunchKernelGGL(k_kick_drift, dim3(blocks_for(3 * (int64_t)n_atoms, kBlock)), dim3(kBlock), 0, s, n_atoms,
+                     pos, vel, force, mass, dt, f2a, drift);
+  return hipGetLastError();
+}
+
+hipError_t launch_nonelec(int n_atoms, const double* pos, double box, double r_cut, int model, double p0,
+                          double p1, double p2, double p3, double p4, double p5, int nc, const int* cstart,
+                          const int* cperm, double* force, double* partial, double* e_out, unsigned int* ticket,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_nonelec, dim3(blocks_for(n_atoms, kBlock)), dim3(kBlock), 0, s, n_atoms, pos, box,
+                     r_cut * r_cut, model, p0, p1, p2, p3, p4, p5, nc, cstart, cperm, force, partial, e_out, ticket);
+  return hipGetLastError();
+}
+
+hipError_t launch_kinetic_log(int n_atoms, const double* vel, const double* mass, double mv2e,
+                              const double* energy4, const double* e_other, double* log_row, int* cycles_row,
+                              const Ctl* ctl, double* partial, unsigned int* ticket, hipStream_t s) {
+  hipLaunchKernelGGL(k_kinetic_log, dim3(blocks_for(n_atoms, kBlock)), dim3(kBlock), 0, s, n_atoms, vel, mass,
+                     mv2e, energy4, e_other, log_row, cycles_row, ctl, partial, ticket);
+  return hipGetLastError();
+}

@@ -1,0 +1,722 @@
+// Mesh-side kernels of the step: charge smoothing, constraint at the Verlet
+// prediction, outer FP64 residual, the multigrid V-cycle on colour-split
+// (red/black) storage, and the field update.
+#include "launch.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr double kPi = 3.14159265358979323846;
+
+inline int blocks_for(int64_t n, int b) { return (int)((n + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// Smoothing: one periodic line filter along `AXIS` (0 = x, 1 = y, 2 = z).
+// The K-fold diffusion step [nu, 1-2nu, nu] is applied as its (2K+1)-tap
+// convolution, folded onto the periodic line when 2K+1 > n.  A workgroup
+// stages W whole lines in LDS (for y/z: W consecutive x columns, so global
+// accesses stay coalesced along x).
+// ---------------------------------------------------------------------------
+template <typename T, int AXIS, int W>
+__global__ void __launch_bounds__(kBlock)
+k_smooth(int n, int ntaps, int half, const T* __restrict__ taps, const T* __restrict__ in,
+         T* __restrict__ out) {
+  extern __shared__ unsigned char smem_raw[];
+  T* line = reinterpret_cast<T*>(smem_raw);        // [W][n] for x, [n][W] for y/z
+  T* tp = line + (size_t)W * n;                    // [ntaps]
+  for (int i = threadIdx.x; i < ntaps; i += kBlock) tp[i] = taps[i];
+  const int total = W * n;
+  // block -> group of W lines
+  int g = blockIdx.x;
+  if (AXIS == 0) {
+    const size_t row0 = (size_t)g * W;             // rows (j,k) flattened
+    for (int e = threadIdx.x; e < total; e += kBlock) line[e] = in[row0 * n + e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < total; e += kBlock) {
+      const int r = e / n, i = e - r * n;
+      const T* L = line + (size_t)r * n;
+      T acc = T(0);
+      int src = i - half;
+      src += src < 0 ? n : 0;
+      for (int m = 0; m < ntaps; m++) {
+        acc += tp[m] * L[src];
+        src = (src + 1 == n) ? 0 : src + 1;
+      }
+      out[row0 * n + e] = acc;
+    }
+  } else {
+    const int ncol = n / W;
+    const int cb = g % ncol;                       // x block
+    const int o = g / ncol;                        // the other coordinate (z for AXIS 1, y for AXIS 2)
+    const int x0 = cb * W;
+    for (int e = threadIdx.x; e < total; e += kBlock) {
+      const int t = e / W, c = e - t * W;
+      size_t a = AXIS == 1 ? ((size_t)o * n + t) * n + x0 + c : ((size_t)t * n + o) * n + x0 + c;
+      line[e] = in[a];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < total; e += kBlock) {
+      const int t = e / W, c = e - t * W;
+      T acc = T(0);
+      int src = t - half;
+      src += src < 0 ? n : 0;
+      for (int m = 0; m < ntaps; m++) {
+        acc += tp[m] * line[src * W + c];
+        src = (src + 1 == n) ? 0 : src + 1;
+      }
+      size_t a = AXIS == 1 ? ((size_t)o * n + t) * n + x0 + c : ((size_t)t * n + o) * n + x0 + c;
+      out[a] = acc;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Constraint at the Verlet prediction (Eq. 17) and multiplier predictor.
+// ---------------------------------------------------------------------------
+template <typename TQ>
+__global__ void __launch_bounds__(kBlock)
+k_sigma(int n, double h, int cold, int m_eff, const TQ* __restrict__ qs, const double* __restrict__ pk,
+        const double* __restrict__ pkm1, const double* __restrict__ y0, const double* __restrict__ y1,
+        const double* __restrict__ y2, double* __restrict__ sigma, double* __restrict__ y, double tol,
+        int tol_mode, double* __restrict__ partial, Ctl* ctl) {
+  __shared__ double sh[kBlock / 64];
+  __shared__ int flag;
+  const int n3 = n * n * n;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  double sv = 0.0, qmax = 0.0;
+  if (t < n3) {
+    const int i = t % n, j = (t / n) % n, k = t / (n * n);
+    const double q = (double)qs[t];
+    double s = q;
+    if (!cold) {
+      const int im = wrapn(i - 1, n), ip = wrapn(i + 1, n), jm = wrapn(j - 1, n), jp = wrapn(j + 1, n);
+      const int km = wrapn(k - 1, n), kp = wrapn(k + 1, n);
+      auto P = [&](int a) { return 2.0 * pk[a] - pkm1[a]; };
+      const double nb = ((P(nat_idx(n, im, j, k)) + P(nat_idx(n, ip, j, k))) +
+                         (P(nat_idx(n, i, jm, k)) + P(nat_idx(n, i, jp, k)))) +
+                        (P(nat_idx(n, i, j, km)) + P(nat_idx(n, i, j, kp)));
+      const double mphi = nb - 6.0 * P(t);
+      s = h / (4.0 * kPi) * mphi + q;
+    }
+    sigma[t] = s;
+    double yv = 0.0;
+    if (m_eff == 1) yv = y0[t];
+    else if (m_eff == 2) yv = 2.0 * y0[t] - y1[t];
+    else if (m_eff == 3) yv = 3.0 * y0[t] - 3.0 * y1[t] + y2[t];
+    y[t] = yv;
+    sv = s;
+    qmax = fabs(q);
+  }
+  double bs = block_sum(sv, sh);
+  double bm = block_max(qmax, sh);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = bs;
+    partial[gridDim.x + blockIdx.x] = bm;
+  }
+  if (last_block_arrives(&ctl->ticket, &flag)) {
+    double tot = reduce_partials_sum(partial, gridDim.x, sh);
+    double mx = reduce_partials_max(partial + gridDim.x, gridDim.x, sh);
+    if (threadIdx.x == 0) {
+      ctl->mean_sigma = tot / (double)n3;
+      ctl->norm_qs = mx;
+      ctl->thresh = tol_mode == 0 ? tol * mx : tol;
+      ctl->done = 0;
+      ctl->cycles = 0;
+      ctl->status = 0;
+      ctl->final_buf = 0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Outer residual of cycle c in FP64 (Eq. 26): y_out = y_in + e (the V-cycle
+// correction, c > 0), r = (sigma - mean) - M y_out; r handed to the next
+// V-cycle in precision T, colour-split.  The last block records the residual,
+// the running mean of y, and the stop decision.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_outer(int n, int c, int max_cycles, const double* __restrict__ sigma, const double* __restrict__ y_in,
+        double* __restrict__ y_out, const T* __restrict__ e0, const T* __restrict__ e1,
+        T* __restrict__ r0, T* __restrict__ r1, double* __restrict__ partial, Ctl* ctl) {
+  __shared__ double sh[kBlock / 64];
+  __shared__ int flag;
+  if (ctl->done) return;
+  const int n3 = n * n * n;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  double rmax = 0.0, ysum = 0.0;
+  if (t < n3) {
+    const int i = t % n, j = (t / n) % n, k = t / (n * n);
+    const int im = wrapn(i - 1, n), ip = wrapn(i + 1, n), jm = wrapn(j - 1, n), jp = wrapn(j + 1, n);
+    const int km = wrapn(k - 1, n), kp = wrapn(k + 1, n);
+    auto Y = [&](int a, int b, int d) {
+      double v = y_in[nat_idx(n, a, b, d)];
+      if (c > 0) {
+        const T* ec = ((a + b + d) & 1) ? e1 : e0;
+        v += (double)ec[cs_idx(n, a, b, d)];
+      }
+      return v;
+    };
+    const double yc = Y(i, j, k);
+    const double nb = ((Y(im, j, k) + Y(ip, j, k)) + (Y(i, jm, k) + Y(i, jp, k))) + (Y(i, j, km) + Y(i, j, kp));
+    const double r = (sigma[t] - ctl->mean_sigma) - (nb - 6.0 * yc);
+    if (c > 0) y_out[t] = yc;
+    T* rc = ((i + j + k) & 1) ? r1 : r0;
+    rc[cs_idx(n, i, j, k)] = (T)r;
+    rmax = fabs(r);
+    ysum = yc;
+  }
+  double bm = block_max(rmax, sh);
+  double bs = block_sum(ysum, sh);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = bm;
+    partial[gridDim.x + blockIdx.x] = bs;
+  }
+  if (last_block_arrives(&ctl->ticket, &flag)) {
+    double res = reduce_partials_max(partial, gridDim.x, sh);
+    double ys = reduce_partials_sum(partial + gridDim.x, gridDim.x, sh);
+    if (threadIdx.x == 0) {
+      ctl->res_hist[c] = res;
+      ctl->mean_y = ys / (double)n3;
+      ctl->cycles = c;
+      ctl->final_buf = c & 1;
+      if (res <= ctl->thresh) {
+        ctl->done = 1;
+      } else if (c >= max_cycles) {
+        ctl->done = 1;
+        ctl->status = 1;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle kernels on colour-split storage.  A thread owns index t of a
+// colour array: m = t % (n/2), row (j,k) = t / (n/2), and the point of
+// colour c is i = 2m + ((c+j+k)&1).  All neighbours of a point have the
+// other colour: x-neighbours at (i+-1)/2 of the same row, y/z neighbours at
+// the same m of the adjacent rows.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T nbr6(const T* __restrict__ o, int n, int i, int j, int k) {
+  const int im = wrapn(i - 1, n), ip = wrapn(i + 1, n), jm = wrapn(j - 1, n), jp = wrapn(j + 1, n);
+  const int km = wrapn(k - 1, n), kp = wrapn(k + 1, n);
+  return ((o[cs_idx(n, im, j, k)] + o[cs_idx(n, ip, j, k)]) + (o[cs_idx(n, i, jm, k)] + o[cs_idx(n, i, jp, k)])) +
+         (o[cs_idx(n, i, j, km)] + o[cs_idx(n, i, j, kp)]);
+}
+
+__device__ __forceinline__ void decode_half(int t, int n, int* m, int* j, int* k) {
+  const int hn = n >> 1;
+  *m = t % hn;
+  const int row = t / hn;
+  *j = row % n;
+  *k = row / n;
+}
+
+// First pre-smoothing sweep from e = 0: red = -r/6, then black from those reds.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_sweep_zero(int n, const T* __restrict__ r0, const T* __restrict__ r1, T* __restrict__ e0,
+             T* __restrict__ e1, const Ctl* ctl) {
+  if (ctl->done) return;
+  const int half = n * n * n / 2;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= half) return;
+  int m, j, k;
+  decode_half(t, n, &m, &j, &k);
+  const T sixth = T(1.0 / 6.0);
+  e0[t] = -r0[t] * sixth;
+  const int ib = 2 * m + ((1 + j + k) & 1);
+  const int im = wrapn(ib - 1, n), ip = wrapn(ib + 1, n), jm = wrapn(j - 1, n), jp = wrapn(j + 1, n);
+  const int km = wrapn(k - 1, n), kp = wrapn(k + 1, n);
+  auto R = [&](int a, int b, int d) { return -r0[cs_idx(n, a, b, d)] * sixth; };
+  const T nb = ((R(im, j, k) + R(ip, j, k)) + (R(ib, jm, k) + R(ib, jp, k))) + (R(ib, j, km) + R(ib, j, kp));
+  e1[t] = (nb - r1[t]) * sixth;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_halfsweep(int n, int colour, T* __restrict__ ec, const T* __restrict__ eo, const T* __restrict__ rc,
+            const Ctl* ctl) {
+  if (ctl->done) return;
+  const int half = n * n * n / 2;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= half) return;
+  int m, j, k;
+  decode_half(t, n, &m, &j, &k);
+  const int i = 2 * m + ((colour + j + k) & 1);
+  ec[t] = (nbr6(eo, n, i, j, k) - rc[t]) * T(1.0 / 6.0);
+}
+
+template <typename T>
+__device__ __forceinline__ T cs_load(const T* __restrict__ c0, const T* __restrict__ c1, int n, int i, int j, int k) {
+  const T* a = ((i + j + k) & 1) ? c1 : c0;
+  return a[cs_idx(n, i, j, k)];
+}
+
+// Residual rho = r - M e at the 27 fine points around 2I, full weighting,
+// times 4 (coarse operator rediscretised on 2h).  One thread per coarse point.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_resid_restrict(int n, const T* __restrict__ e0, const T* __restrict__ e1, const T* __restrict__ r0,
+                 const T* __restrict__ r1, T* __restrict__ rc0, T* __restrict__ rc1, const Ctl* ctl) {
+  if (ctl->done) return;
+  const int nc = n >> 1;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nc * nc * nc) return;
+  const int I = t % nc, J = (t / nc) % nc, K = t / (nc * nc);
+  const T wt[3] = {T(0.25), T(0.5), T(0.25)};
+  T s = T(0);
+  for (int c = -1; c <= 1; c++) {
+    const int z = wrapn(2 * K + c, n);
+    for (int b = -1; b <= 1; b++) {
+      const int y = wrapn(2 * J + b, n);
+      T row = T(0);
+      for (int a = -1; a <= 1; a++) {
+        const int x = wrapn(2 * I + a, n);
+        const bool odd = (x + y + z) & 1;
+        const T* eo = odd ? e0 : e1;     // neighbours have the other colour
+        const T ev = odd ? e1[cs_idx(n, x, y, z)] : e0[cs_idx(n, x, y, z)];
+        const T rv = odd ? r1[cs_idx(n, x, y, z)] : r0[cs_idx(n, x, y, z)];
+        const T rho = rv - (nbr6(eo, n, x, y, z) - T(6) * ev);
+        row += wt[a + 1] * rho;
+      }
+      s += wt[b + 1] * wt[c + 1] * row;
+    }
+  }
+  T* out = ((I + J + K) & 1) ? rc1 : rc0;
+  out[cs_idx(nc, I, J, K)] = T(4) * s;
+}
+
+// Trilinear interpolation of the coarse correction at fine point (x,y,z).
+template <typename T>
+__device__ __forceinline__ T prolong_at(const T* __restrict__ c0, const T* __restrict__ c1, int nc, int x,
+                                        int y, int z) {
+  const int x0 = x >> 1, y0 = y >> 1, z0 = z >> 1;
+  const int x1 = (x & 1) ? (x0 + 1 == nc ? 0 : x0 + 1) : x0;
+  const int y1 = (y & 1) ? (y0 + 1 == nc ? 0 : y0 + 1) : y0;
+  const int z1 = (z & 1) ? (z0 + 1 == nc ? 0 : z0 + 1) : z0;
+  const T hx = (x & 1) ? T(0.5) : T(1), hy = (y & 1) ? T(0.5) : T(1), hz = (z & 1) ? T(0.5) : T(1);
+  T s = T(0);
+  const int xs[2] = {x0, x1}, ys[2] = {y0, y1}, zs[2] = {z0, z1};
+  const int nx = (x & 1) ? 2 : 1, ny = (y & 1) ? 2 : 1, nz = (z & 1) ? 2 : 1;
+  for (int c = 0; c < nz; c++)
+    for (int b = 0; b < ny; b++)
+      for (int a = 0; a < nx; a++) s += hx * hy * hz * cs_load(c0, c1, nc, xs[a], ys[b], zs[c]);
+  return s;
+}
+
+// After prolongation the next red half-sweep overwrites every red value and
+// only reads corrected black neighbours, so the correction of black points is
+// applied on the fly here and the red values are written directly.
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_prolong_red(int n, T* __restrict__ e0, const T* __restrict__ e1, const T* __restrict__ ec0,
+              const T* __restrict__ ec1, const T* __restrict__ r0, const Ctl* ctl) {
+  if (ctl->done) return;
+  const int half = n * n * n / 2;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= half) return;
+  int m, j, k;
+  decode_half(t, n, &m, &j, &k);
+  const int i = 2 * m + ((j + k) & 1);
+  const int nc = n >> 1;
+  const int im = wrapn(i - 1, n), ip = wrapn(i + 1, n), jm = wrapn(j - 1, n), jp = wrapn(j + 1, n);
+  const int km = wrapn(k - 1, n), kp = wrapn(k + 1, n);
+  auto B = [&](int a, int b, int d) { return e1[cs_idx(n, a, b, d)] + prolong_at(ec0, ec1, nc, a, b, d); };
+  const T nb = ((B(im, j, k) + B(ip, j, k)) + (B(i, jm, k) + B(i, jp, k))) + (B(i, j, km) + B(i, j, kp));
+  e0[t] = (nb - r0[t]) * T(1.0 / 6.0);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_prolong_add(int n, T* __restrict__ e0, T* __restrict__ e1, const T* __restrict__ ec0,
+              const T* __restrict__ ec1, const Ctl* ctl) {
+  if (ctl->done) return;
+  const int half = n * n * n / 2;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= half) return;
+  int m, j, k;
+  decode_half(t, n, &m, &j, &k);
+  const int nc = n >> 1;
+  const int ir = 2 * m + ((j + k) & 1), ib = 2 * m + ((1 + j + k) & 1);
+  e0[t] += prolong_at(ec0, ec1, nc, ir, j, k);
+  e1[t] += prolong_at(ec0, ec1, nc, ib, j, k);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fill_zero(int64_t count, T* __restrict__ a, T* __restrict__ b,
+                                                      const Ctl* ctl) {
+  if (ctl->done) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) {
+    a[t] = T(0);
+    b[t] = T(0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tail of the V-cycle: all levels from n0 <= 16 down to 4^3 and back in one
+// workgroup, LDS-resident in natural layout, with the exact coarsest solve
+// e = G * r (G the periodic 4^3 Green's function of M, FP64 accumulation).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T lds_nbr(const T* v, int n, int i, int j, int k) {
+  const int im = (i - 1) & (n - 1), ip = (i + 1) & (n - 1), jm = (j - 1) & (n - 1), jp = (j + 1) & (n - 1);
+  const int km = (k - 1) & (n - 1), kp = (k + 1) & (n - 1);
+  return ((v[(k * n + j) * n + im] + v[(k * n + j) * n + ip]) + (v[(k * n + jm) * n + i] + v[(k * n + jp) * n + i])) +
+         (v[(km * n + j) * n + i] + v[(kp * n + j) * n + i]);
+}
+
+template <typename T>
+__device__ void tail_rbgs(T* e, const T* r, int n, int colour) {
+  const int n3 = n * n * n;
+  for (int p = threadIdx.x; p < n3 / 2; p += blockDim.x) {
+    const int hn = n >> 1;
+    const int m = p % hn, row = p / hn, j = row % n, k = row / n;
+    const int i = 2 * m + ((colour + j + k) & 1);
+    const int a = (k * n + j) * n + i;
+    e[a] = (lds_nbr(e, n, i, j, k) - r[a]) * T(1.0 / 6.0);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024)
+k_tail(int n0, int levels, int nu1, int nu2, const T* __restrict__ r0g, const T* __restrict__ r1g,
+       T* __restrict__ e0g, T* __restrict__ e1g, const double* __restrict__ green, const Ctl* ctl) {
+  if (ctl && ctl->done) return;
+  extern __shared__ unsigned char smem_raw[];
+  T* base = reinterpret_cast<T*>(smem_raw);
+  T* E[P3MZ_MAX_LEVELS];
+  T* R[P3MZ_MAX_LEVELS];
+  int off = 0;
+  for (int q = 0; q < levels; q++) {
+    const int nq = n0 >> q, c = nq * nq * nq;
+    E[q] = base + off; off += c;
+    R[q] = base + off; off += c;
+  }
+  T* rho = base + off;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  {
+    const int n3 = n0 * n0 * n0;
+    for (int p = tid; p < n3; p += nt) {
+      const int i = p % n0, j = (p / n0) % n0, k = p / (n0 * n0);
+      const T* src = ((i + j + k) & 1) ? r1g : r0g;
+      R[0][p] = src[cs_idx(n0, i, j, k)];
+    }
+  }
+  __syncthreads();
+  for (int q = 0; q + 1 < levels; q++) {
+    const int n = n0 >> q, n3 = n * n * n, nc = n >> 1;
+    for (int p = tid; p < n3; p += nt) E[q][p] = T(0);
+    __syncthreads();
+    for (int s = 0; s < nu1; s++) {
+      tail_rbgs(E[q], R[q], n, 0);
+      __syncthreads();
+      tail_rbgs(E[q], R[q], n, 1);
+      __syncthreads();
+    }
+    for (int p = tid; p < n3; p += nt) {
+      const int i = p % n, j = (p / n) % n, k = p / (n * n);
+      rho[p] = R[q][p] - (lds_nbr(E[q], n, i, j, k) - T(6) * E[q][p]);
+    }
+    __syncthreads();
+    const T wt[3] = {T(0.25), T(0.5), T(0.25)};
+    for (int p = tid; p < nc * nc * nc; p += nt) {
+      const int I = p % nc, J = (p / nc) % nc, K = p / (nc * nc);
+      T s = T(0);
+      for (int c = -1; c <= 1; c++) {
+        const int z = (2 * K + c) & (n - 1);
+        for (int b = -1; b <= 1; b++) {
+          const int y = (2 * J + b) & (n - 1);
+          T row = T(0);
+          for (int a = -1; a <= 1; a++) row += wt[a + 1] * rho[(z * n + y) * n + ((2 * I + a) & (n - 1))];
+          s += wt[b + 1] * wt[c + 1] * row;
+        }
+      }
+      R[q + 1][p] = T(4) * s;
+    }
+    __syncthreads();
+  }
+  {
+    const int q = levels - 1;   // 4^3
+    if (tid < 64) {
+      const int x = tid & 3, y = (tid >> 2) & 3, z = tid >> 4;
+      double s = 0.0;
+      for (int mm = 0; mm < 64; mm++) {
+        const int a = mm & 3, b = (mm >> 2) & 3, c = mm >> 4;
+        s += green[(((z - c) & 3) * 4 + ((y - b) & 3)) * 4 + ((x - a) & 3)] * (double)R[q][mm];
+      }
+      E[q][tid] = (T)s;
+    }
+    __syncthreads();
+  }
+  for (int q = levels - 2; q >= 0; q--) {
+    const int n = n0 >> q, n3 = n * n * n, nc = n >> 1;
+    for (int p = tid; p < n3; p += nt) {
+      const int x = p % n, y = (p / n) % n, z = p / (n * n);
+      const int x0 = x >> 1, y0 = y >> 1, z0 = z >> 1;
+      const int x1 = (x & 1) ? ((x0 + 1) & (nc - 1)) : x0;
+      const int y1 = (y & 1) ? ((y0 + 1) & (nc - 1)) : y0;
+      const int z1 = (z & 1) ? ((z0 + 1) & (nc - 1)) : z0;
+      const T hx = (x & 1) ? T(0.5) : T(1), hy = (y & 1) ? T(0.5) : T(1), hz = (z & 1) ? T(0.5) : T(1);
+      const int xs[2] = {x0, x1}, ys[2] = {y0, y1}, zs[2] = {z0, z1};
+      const int nx = (x & 1) ? 2 : 1, ny = (y & 1) ? 2 : 1, nz = (z & 1) ? 2 : 1;
+      T s = T(0);
+      for (int c = 0; c < nz; c++)
+        for (int b = 0; b < ny; b++)
+          for (int a = 0; a < nx; a++) s += hx * hy * hz * E[q + 1][(zs[c] * nc + ys[b]) * nc + xs[a]];
+      E[q][p] += s;
+    }
+    __syncthreads();
+    for (int s = 0; s < nu2; s++) {
+      tail_rbgs(E[q], R[q], n, 0);
+      __syncthreads();
+      tail_rbgs(E[q], R[q], n, 1);
+      __syncthreads();
+    }
+  }
+  {
+    const int n3 = n0 * n0 * n0;
+    for (int p = tid; p < n3; p += nt) {
+      const int i = p % n0, j = (p / n0) % n0, k = p / (n0 * n0);
+      T* dst = ((i + j + k) & 1) ? e1g : e0g;
+      dst[cs_idx(n0, i, j, k)] = E[0][p];
+    }
+  }
+}
+
+size_t tail_lds_bytes(int n0, int levels, size_t elem) {
+  size_t tot = 0;
+  for (int q = 0; q < levels; q++) {
+    size_t nq = (size_t)(n0 >> q);
+    tot += 2 * nq * nq * nq;
+  }
+  tot += (size_t)n0 * n0 * n0;
+  return tot * elem;
+}
+
+// ---------------------------------------------------------------------------
+// Field update (Supporting Information, numerical integration):
+// phi^{k+1} = phi_p - (4 pi / h) y*, with y* projected to zero mean; the
+// multiplier is pushed into the history on warm steps.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBlock)
+k_phi_update(int n3, double h, int cold, const double* pk, const double* pkm1,
+             const double* __restrict__ ya, const double* __restrict__ yb, double* phi_out,
+             double* __restrict__ phi_copy, double* __restrict__ yh_out, float* __restrict__ phi32,
+             const Ctl* ctl) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n3) return;
+  const double* ysrc = ctl->final_buf ? yb : ya;
+  const double y = ysrc[t] - ctl->mean_y;
+  const double phi_p = cold ? 0.0 : 2.0 * pk[t] - pkm1[t];
+  const double phi = phi_p - 4.0 * kPi / h * y;
+  phi_out[t] = phi;
+  if (phi_copy) phi_copy[t] = phi;
+  if (yh_out) yh_out[t] = y;
+  if (phi32) phi32[t] = (float)phi;
+}
+
+template <typename T>
+__global__ void k_widen(int64_t count, const T* __restrict__ in, double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) out[t] = (double)in[t];
+}
+
+template <typename T>
+__global__ void k_cs_to_nat(int n, const T* __restrict__ c0, const T* __restrict__ c1, double* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * n * n) return;
+  const int i = t % n, j = (t / n) % n, k = t / (n * n);
+  out[t] = (double)cs_load(c0, c1, n, i, j, k);
+}
+
+template <typename T>
+__global__ void k_nat_to_cs(int n, const double* __restrict__ in, T* __restrict__ c0, T* __restrict__ c1) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * n * n) return;
+  const int i = t % n, j = (t / n) % n, k = t / (n * n);
+  T* d = ((i + j + k) & 1) ? c1 : c0;
+  d[cs_idx(n, i, j, k)] = (T)in[t];
+}
+
+__global__ void k_sub_scalar(int64_t count, const double* __restrict__ in, double* __restrict__ out,
+                             const double* __restrict__ sub) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) out[t] = in[t] - *sub;
+}
+
+__global__ void k_set_open(Ctl* ctl) {
+  ctl->done = 0;
+  ctl->cycles = 0;
+  ctl->status = 0;
+}
+
+template <typename T>
+hipError_t vcycle_impl(const LevelBufs* lv, int levels, int tail, int nu1, int nu2, const double* green,
+                       Ctl* ctl, hipStream_t s) {
+  for (int l = 0; l < tail; l++) {
+    const int n = lv[l].n, half = n * n * n / 2, nb = blocks_for(half, kBlock);
+    T *e0 = (T*)lv[l].e0, *e1 = (T*)lv[l].e1, *r0 = (T*)lv[l].r0, *r1 = (T*)lv[l].r1;
+    if (nu1 >= 1) {
+      hipLaunchKernelGGL(k_sweep_zero<T>, dim3(nb), dim3(kBlock), 0, s, n, r0, r1, e0, e1, ctl);
+      for (int it = 1; it < nu1; it++) {
+        hipLaunchKernelGGL(k_halfsweep<T>, dim3(nb), dim3(kBlock), 0, s, n, 0, e0, e1, r0, ctl);
+        hipLaunchKernelGGL(k_halfsweep<T>, dim3(nb), dim3(kBlock), 0, s, n, 1, e1, e0, r1, ctl);
+      }
+    } else {
+      hipLaunchKernelGGL(k_fill_zero<T>, dim3(nb), dim3(kBlock), 0, s, (int64_t)half, e0, e1, ctl);
+    }
+    const int nc = n / 2;
+    hipLaunchKernelGGL(k_resid_restrict<T>, dim3(blocks_for(nc * nc * nc, kBlock)), dim3(kBlock), 0, s, n,
+                       e0, e1, r0, r1, (T*)lv[l + 1].r0, (T*)lv[l + 1].r1, ctl);
+  }
+  {
+    const int lt = levels - tail;
+    size_t lds = tail_lds_bytes(lv[tail].n, lt, sizeof(T));
+    hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(1024), lds, s, lv[tail].n, lt, nu1, nu2, (const T*)lv[tail].r0,
+                       (const T*)lv[tail].r1, (T*)lv[tail].e0, (T*)lv[tail].e1, green, ctl);
+  }
+  for (int l = tail - 1; l >= 0; l--) {
+    const int n = lv[l].n, half = n * n * n / 2, nb = blocks_for(half, kBlock);
+    T *e0 = (T*)lv[l].e0, *e1 = (T*)lv[l].e1, *r0 = (T*)lv[l].r0, *r1 = (T*)lv[l].r1;
+    const T *c0 = (const T*)lv[l + 1].e0, *c1 = (const T*)lv[l + 1].e1;
+    if (nu2 >= 1) {
+      hipLaunchKernelGGL(k_prolong_red<T>, dim3(nb), dim3(kBlock), 0, s, n, e0, e1, c0, c1, r0, ctl);
+      hipLaunchKernelGGL(k_halfsweep<T>, dim3(nb), dim3(kBlock), 0, s, n, 1, e1, e0, r1, ctl);
+      for (int it = 1; it < nu2; it++) {
+        hipLaunchKernelGGL(k_halfsweep<T>, dim3(nb), dim3(kBlock), 0, s, n, 0, e0, e1, r0, ctl);
+        hipLaunchKernelGGL(k_halfsweep<T>, dim3(nb), dim3(kBlock), 0, s, n, 1, e1, e0, r1, ctl);
+      }
+    } else {
+      hipLaunchKernelGGL(k_prolong_add<T>, dim3(nb), dim3(kBlock), 0, s, n, e0, e1, c0, c1, ctl);
+    }
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_smooth(bool fp64, int n, int axis, int ntaps, int half, const void* taps, const void* in,
+                         void* out, hipStream_t s) {
+  const size_t elem = fp64 ? 8 : 4;
+  int W;
+  dim3 grid;
+  if (axis == 0) {
+    W = n >= 256 ? 2 : (n >= 64 ? 4 : 8);
+    W = W > n * n ? n * n : W;
+    grid = dim3((unsigned)((size_t)n * n / W));
+  } else {
+    W = n >= 16 ? 16 : n;
+    grid = dim3((unsigned)((n / W) * n));
+  }
+  const size_t lds = ((size_t)W * n + ntaps) * elem;
+#define P3MZ_SMOOTH_LAUNCH(TT, AX, WW)                                                             \
+  hipLaunchKernelGGL((k_smooth<TT, AX, WW>), grid, dim3(kBlock), lds, s, n, ntaps, half, (const TT*)taps, \
+                     (const TT*)in, (TT*)out)
+  if (axis == 0) {
+    if (fp64) {
+      if (W == 2) P3MZ_SMOOTH_LAUNCH(double, 0, 2); else if (W == 4) P3MZ_SMOOTH_LAUNCH(double, 0, 4); else P3MZ_SMOOTH_LAUNCH(double, 0, 8);
+    } else {
+      if (W == 2) P3MZ_SMOOTH_LAUNCH(float, 0, 2); else if (W == 4) P3MZ_SMOOTH_LAUNCH(float, 0, 4); else P3MZ_SMOOTH_LAUNCH(float, 0, 8);
+    }
+  } else if (axis == 1) {
+    if (W != 16 && W != 8) return hipErrorInvalidValue;
+    if (fp64) { if (W == 16) P3MZ_SMOOTH_LAUNCH(double, 1, 16); else P3MZ_SMOOTH_LAUNCH(double, 1, 8); }
+    else { if (W == 16) P3MZ_SMOOTH_LAUNCH(float, 1, 16); else P3MZ_SMOOTH_LAUNCH(float, 1, 8); }
+  } else {
+    if (W != 16 && W != 8) return hipErrorInvalidValue;
+    if (fp64) { if (W == 16) P3MZ_SMOOTH_LAUNCH(double, 2, 16); else P3MZ_SMOOTH_LAUNCH(double, 2, 8); }
+    else { if (W == 16) P3MZ_SMOOTH_LAUNCH(float, 2, 16); else P3MZ_SMOOTH_LAUNCH(float, 2, 8); }
+  }
+#undef P3MZ_SMOOTH_LAUNCH
+  return hipGetLastError();
+}
+
+hipError_t launch_sigma(bool fp64, int n, double h, int cold, int m_eff, const void* qs, const double* phi_k,
+                        const double* phi_km1, const double* yh0, const double* yh1, const double* yh2,
+                        double* sigma, double* y, double tol, int tol_mode, double* partial, Ctl* ctl,
+                        hipStream_t s) {
+  const int n3 = n * n * n, nb = blocks_for(n3, kBlock);
+  if (fp64)
+    hipLaunchKernelGGL(k_sigma<double>, dim3(nb), dim3(kBlock), 0, s, n, h, cold, m_eff, (const double*)qs, phi_k,
+                       phi_km1, yh0, yh1, yh2, sigma, y, tol, tol_mode, partial, ctl);
+  else
+    hipLaunchKernelGGL(k_sigma<float>, dim3(nb), dim3(kBlock), 0, s, n, h, cold, m_eff, (const float*)qs, phi_k,
+                       phi_km1, yh0, yh1, yh2, sigma, y, tol, tol_mode, partial, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_outer(bool fp64, int n, int c, int max_cycles, const double* sigma, const double* y_in,
+                        double* y_out, const void* e0, const void* e1, void* r0, void* r1, double* partial,
+                        Ctl* ctl, hipStream_t s) {
+  const int n3 = n * n * n, nb = blocks_for(n3, kBlock);
+  if (fp64)
+    hipLaunchKernelGGL(k_outer<double>, dim3(nb), dim3(kBlock), 0, s, n, c, max_cycles, sigma, y_in, y_out,
+                       (const double*)e0, (const double*)e1, (double*)r0, (double*)r1, partial, ctl);
+  else
+    hipLaunchKernelGGL(k_outer<float>, dim3(nb), dim3(kBlock), 0, s, n, c, max_cycles, sigma, y_in, y_out,
+                       (const float*)e0, (const float*)e1, (float*)r0, (float*)r1, partial, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_vcycle(bool fp64, const LevelBufs* lv, int levels, int tail, int nu1, int nu2,
+                         const double* green, Ctl* ctl, hipStream_t s) {
+  return fp64 ? vcycle_impl<double>(lv, levels, tail, nu1, nu2, green, ctl, s)
+              : vcycle_impl<float>(lv, levels, tail, nu1, nu2, green, ctl, s);
+}
+
+hipError_t tail_configure(bool fp64, int n_tail, int levels_tail, size_t* lds_bytes) {
+  size_t b = tail_lds_bytes(n_tail, levels_tail, fp64 ? 8 : 4);
+  *lds_bytes = b;
+  hipError_t e = fp64 ? hipFuncSetAttribute((const void*)k_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b)
+                      : hipFuncSetAttribute((const void*)k_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b);
+  return e;
+}
+
+hipError_t launch_phi_update(int n, double h, int cold, const double* phi_k, const double* phi_km1,
+                             const double* ya, const double* yb, double* phi_out, double* phi_copy,
+                             double* y_hist_out, float* phi32, Ctl* ctl, hipStream_t s) {
+  const int n3 = n * n * n;
+  hipLaunchKernelGGL(k_phi_update, dim3(blocks_for(n3, kBlock)), dim3(kBlock), 0, s, n3, h, cold, phi_k, phi_km1,
+                     ya, yb, phi_out, phi_copy, y_hist_out, phi32, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_widen(bool fp64, int64_t count, const void* in, double* out, hipStream_t s) {
+  const int nb = blocks_for(count, kBlock);
+  if (fp64)
+    hipLaunchKernelGGL(k_widen<double>, dim3(nb), dim3(kBlock), 0, s, count, (const double*)in, out);
+  else
+    hipLaunchKernelGGL(k_widen<float>, dim3(nb), dim3(kBlock), 0, s, count, (const float*)in, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cs_to_nat(bool fp64, int n, const void* c0, const void* c1, double* out, hipStream_t s) {
+  const int nb = blocks_for(n * n * n, kBlock);
+  if (fp64)
+    hipLaunchKernelGGL(k_cs_to_nat<double>, dim3(nb), dim3(kBlock), 0, s, n, (const double*)c0, (const double*)c1, out);
+  else
+    hipLaunchKernelGGL(k_cs_to_nat<float>, dim3(nb), dim3(kBlock), 0, s, n, (const float*)c0, (const float*)c1, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_nat_to_cs(bool fp64, int n, const double* in, void* c0, void* c1, hipStream_t s) {
+  const int nb = blocks_for(n * n * n, kBlock);
+  if (fp64)
+    hipLaunchKernelGGL(k_nat_to_cs<double>, dim3(nb), dim3(kBlock), 0, s, n, in, (double*)c0, (double*)c1);
+  else
+    hipLaunchKernelGGL(k_nat_to_cs<float>, dim3(nb), dim3(kBlock), 0, s, n, in, (float*)c0, (float*)c1);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_scalar(int64_t count, const double* in, double* out, const double* sub, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub_scalar, dim3(blocks_for(count, kBlock)), dim3(kBlock), 0, s, count, in, out, sub);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_ctl_open(Ctl* ctl, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_open, dim3(1), dim3(1), 0, s, ctl);
+  return hipGetLastError();
+}

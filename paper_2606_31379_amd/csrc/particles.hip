@@ -1,0 +1,439 @@
+// Particle-side kernels: binning, deterministic bin sort, owner-computes
+// charge spread, force/energy gather and the short-range pair term.
+#include "launch.h"
+
+namespace {
+
+constexpr int kBlock = 256;
+
+// Mesh coordinate u = (x/L - floor(x/L)) * N in FP64, then the first stencil
+// index and the fractional offset tau in [0,1) with weight j = M_p(tau+p-1-j)
+// (even p: nearest p points around u; odd p: centred on the nearest point).
+__device__ __forceinline__ void stencil_origin(double x, double box, int n, int p, int* first,
+                                               double* tau) {
+  double s = x / box;
+  s -= floor(s);
+  double u = s * n;
+  if (p & 1) {
+    double f = floor(u + 0.5);
+    *first = (int)f - (p - 1) / 2;
+    *tau = u + 0.5 - f;
+  } else {
+    double f = floor(u);
+    *first = (int)f - p / 2 + 1;
+    *tau = u - f;
+  }
+  if (*tau >= 1.0) *tau = 0.0, *first += 1;   // u rounded up onto the next knot
+  if (*tau < 0.0) *tau = 0.0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_bin_stencil(int n_atoms, const double* __restrict__ pos, double box, int n, int p, int tile,
+              int ntx, int* __restrict__ base, T* __restrict__ w, int* __restrict__ key,
+              int* __restrict__ slot, int* __restrict__ count, Ctl* ctl) {
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n_atoms) return;
+  int tk[3];
+  for (int d = 0; d < 3; d++) {
+    double x = pos[3 * a + d];
+    if (!isfinite(x)) {
+      ctl->nan_flag = 1;
+      x = 0.0;
+    }
+    int first;
+    double tau;
+    stencil_origin(x, box, n, p, &first, &tau);
+    int f = first % n;
+    if (f < 0) f += n;
+    base[3 * a + d] = f;
+    T wl[P3MZ_MAX_ORDER];
+    bspline_weights<T>(p, (T)tau, wl);
+    for (int j = 0; j < p; j++) w[(3 * a + d) * p + j] = wl[j];
+    tk[d] = f / tile;
+  }
+  int k = (tk[2] * ntx + tk[1]) * ntx + tk[0];
+  key[a] = k;
+  slot[a] = atomicAdd(&count[k], 1);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_bin_cells(int n_atoms, const double* __restrict__ pos, double box, int nc, int* __restrict__ key,
+            int* __restrict__ slot, int* __restrict__ count, Ctl* ctl) {
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n_atoms) return;
+  int c[3];
+  for (int d = 0; d < 3; d++) {
+    double x = pos[3 * a + d];
+    if (!isfinite(x)) {
+      ctl->nan_flag = 1;
+      x = 0.0;
+    }
+    double s = x / box;
+    s -= floor(s);
+    int ci = (int)(s * nc);
+    c[d] = ci >= nc ? nc - 1 : ci;
+  }
+  int k = (c[2] * nc + c[1]) * nc + c[0];
+  key[a] = k;
+  slot[a] = atomicAdd(&count[k], 1);
+}
+
+// Single-workgroup exclusive scan (1024 threads, contiguous chunk per thread).
+__global__ void __launch_bounds__(1024) k_scan(int nbins, int* __restrict__ count, int* __restrict__ start) {
+  __shared__ int sh[1024];
+  const int t = threadIdx.x;
+  const int chunk = (nbins + 1023) / 1024;
+  const int b0 = t * chunk, b1 = min(nbins, b0 + chunk);
+  int local = 0;
+  for (int b = b0; b < b1; b++) local += count[b];
+  sh[t] = local;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    int v = (t >= off) ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += v;
+    __syncthreads();
+  }
+  int run = sh[t] - local;   // exclusive prefix of this chunk
+  for (int b = b0; b < b1; b++) {
+    int c = count[b];
+    start[b] = run;
+    run += c;
+    count[b] = 0;
+  }
+  if (t == 1023) start[nbins] = sh[1023];
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_scatter(int n_atoms, const int* __restrict__ key, const int* __restrict__ slot,
+          const int* __restrict__ start, int* __restrict__ perm_raw) {
+  int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n_atoms) return;
+  perm_raw[start[key[a]] + slot[a]] = a;
+}
+
+// One wave per bin: rank of each entry = number of smaller atom indices in
+// the bin (indices are distinct), so perm[start + rank] is the sorted list.
+__global__ void __launch_bounds__(kBlock)
+k_sort_bins(int nbins, const int* __restrict__ start, const int* __restrict__ perm_raw,
+            int* __restrict__ perm) {
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (wave >= nbins) return;
+  const int s0 = start[wave], cnt = start[wave + 1] - s0;
+  for (int i0 = 0; i0 < cnt; i0 += 64) {
+    const int i = i0 + lane;
+    const int v = (i < cnt) ? perm_raw[s0 + i] : 0x7fffffff;
+    int rank = 0;
+    for (int j0 = 0; j0 < cnt; j0 += 64) {
+      const int vj_own = (j0 + lane < cnt) ? perm_raw[s0 + j0 + lane] : 0x7fffffff;
+      const int lim = min(64, cnt - j0);
+      for (int jj = 0; jj < lim; jj++) {
+        int vj = __shfl(vj_own, jj, 64);
+        rank += (vj < v);
+      }
+    }
+    if (i < cnt) perm[s0 + rank] = v;
+  }
+}
+
+// Owner-computes spread.  One workgroup per TS^3 tile of the mesh; atoms are
+// keyed by the tile holding their first stencil index, so only the tile
+// itself and its lower neighbours (per axis) can reach it.  Each wave adds
+// whole atoms, one stencil point per lane, into its own LDS copy of the tile
+// (lanes of one atom touch distinct points), in the fixed order of the
+// sorted bins; the four wave copies are then summed in a fixed order.  No
+// global atomics, bitwise-reproducible.
+template <typename T, int TS>
+__global__ void __launch_bounds__(kBlock)
+k_spread(int n, int p, int ntx, const int* __restrict__ start, const int* __restrict__ perm,
+         const int* __restrict__ base, const T* __restrict__ w, const double* __restrict__ qa,
+         T* __restrict__ q) {
+  constexpr int V = TS * TS * TS;
+  __shared__ T acc[kBlock / 64][V];
+  const int t = blockIdx.x;
+  const int tx = t % ntx, ty = (t / ntx) % ntx, tz = t / (ntx * ntx);
+  const int ox = tx * TS, oy = ty * TS, oz = tz * TS;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int i = threadIdx.x; i < (kBlock / 64) * V; i += kBlock) (&acc[0][0])[i] = T(0);
+  __syncthreads();
+  const int nd = ntx > 1 ? 2 : 1;
+  const int p2 = p * p, p3 = p2 * p;
+  for (int dz = 0; dz < nd; dz++)
+    for (int dy = 0; dy < nd; dy++)
+      for (int dx = 0; dx < nd; dx++) {
+        int sx = tx - dx, sy = ty - dy, sz = tz - dz;
+        sx += sx < 0 ? ntx : 0;
+        sy += sy < 0 ? ntx : 0;
+        sz += sz < 0 ? ntx : 0;
+        const int sb = (sz * ntx + sy) * ntx + sx;
+        const int a0 = start[sb], a1 = start[sb + 1];
+        for (int j = a0 + wv; j < a1; j += kBlock / 64) {
+          const int a = perm[j];
+          const int bx = base[3 * a], by = base[3 * a + 1], bz = base[3 * a + 2];
+          const T qv = (T)qa[a];
+          for (int l = lane; l < p3; l += 64) {
+            const int ax = l % p, ay = (l / p) % p, az = l / p2;
+            int gx = bx + ax, gy = by + ay, gz = bz + az;
+            gx -= gx >= n ? n : 0;
+            gy -= gy >= n ? n : 0;
+            gz -= gz >= n ? n : 0;
+            const int lx = gx - ox, ly = gy - oy, lz = gz - oz;
+            if ((unsigned)lx < (unsigned)TS && (unsigned)ly < (unsigned)TS && (unsigned)lz < (unsigned)TS) {
+              const T c = qv * w[(3 * a) * p + ax] * w[(3 * a + 1) * p + ay] * w[(3 * a + 2) * p + az];
+              acc[wv][(lz * TS + ly) * TS + lx] += c;
+            }
+          }
+        }
+      }
+  __syncthreads();
+  for (int i = threadIdx.x; i < V; i += kBlock) {
+    T s = acc[0][i];
+    for (int k = 1; k < kBlock / 64; k++) s += acc[k][i];
+    const int lx = i % TS, ly = (i / TS) % TS, lz = i / (TS * TS);
+    q[nat_idx(n, ox + lx, oy + ly, oz + lz)] = s;
+  }
+}
+
+// Gather: F = -k Q sum_n W(r - r_n) (D phi)_n with the central difference D,
+// rewritten as derivative weights on a (p+2)^3 neighbourhood, and the
+// per-atom energy 1/2 k Q (W * phi)(r).  Accumulation in FP64.
+template <typename T, typename TP>
+__global__ void __launch_bounds__(kBlock)
+k_gather(int n_atoms, int n, int p, double h, double k_e, const int* __restrict__ perm,
+         const int* __restrict__ base, const T* __restrict__ w, const double* __restrict__ qa,
+         const TP* __restrict__ phi, double* __restrict__ force, double* __restrict__ partial,
+         Ctl* ctl) {
+  __shared__ double sh[kBlock / 64];
+  __shared__ int flag;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  double e_atom = 0.0;
+  if (t < n_atoms) {
+    const int a = perm[t];
+    const int pe = p + 2;
+    T wx[P3MZ_MAX_ORDER + 2], wy[P3MZ_MAX_ORDER + 2], wz[P3MZ_MAX_ORDER + 2];
+    T dx[P3MZ_MAX_ORDER + 2], dy[P3MZ_MAX_ORDER + 2], dz[P3MZ_MAX_ORDER + 2];
+    const T inv2h = (T)(0.5 / h);
+    for (int j = 0; j < pe; j++) {
+      wx[j] = (j >= 1 && j <= p) ? w[(3 * a) * p + j - 1] : T(0);
+      wy[j] = (j >= 1 && j <= p) ? w[(3 * a + 1) * p + j - 1] : T(0);
+      wz[j] = (j >= 1 && j <= p) ? w[(3 * a + 2) * p + j - 1] : T(0);
+    }
+    for (int j = 0; j < pe; j++) {
+      // extended index j <-> stencil offset j-1; d[j] = (w[j-1] - w[j+1]) / 2h
+      const T lo = j >= 1 ? wx[j - 1] : T(0), hi = j + 1 < pe ? wx[j + 1] : T(0);
+      dx[j] = (lo - hi) * inv2h;
+      const T loy = j >= 1 ? wy[j - 1] : T(0), hiy = j + 1 < pe ? wy[j + 1] : T(0);
+      dy[j] = (loy - hiy) * inv2h;
+      const T loz = j >= 1 ? wz[j - 1] : T(0), hiz = j + 1 < pe ? wz[j + 1] : T(0);
+      dz[j] = (loz - hiz) * inv2h;
+    }
+    const int bx = base[3 * a] - 1 + n, by = base[3 * a + 1] - 1 + n, bz = base[3 * a + 2] - 1 + n;
+    int ix[P3MZ_MAX_ORDER + 2];
+    for (int j = 0; j < pe; j++) ix[j] = (bx + j) % n;
+    double fx = 0, fy = 0, fz = 0, pot = 0;
+    for (int c = 0; c < pe; c++) {
+      const int iz = (bz + c) % n;
+      for (int b = 0; b < pe; b++) {
+        const int iy = (by + b) % n;
+        const TP* row = phi + (size_t)(iz * n + iy) * n;
+        T sx = T(0), s0 = T(0);
+        for (int j = 0; j < pe; j++) {
+          const T v = (T)row[ix[j]];
+          sx += dx[j] * v;
+          s0 += wx[j] * v;
+        }
+        fx += (double)(wy[b] * wz[c]) * (double)sx;
+        fy += (double)(dy[b] * wz[c]) * (double)s0;
+        fz += (double)(wy[b] * dz[c]) * (double)s0;
+        pot += (double)(wy[b] * wz[c]) * (double)s0;
+      }
+    }
+    const double kq = k_e * qa[a];
+    if (force) {
+      force[3 * a] = -kq * fx;
+      force[3 * a + 1] = -kq * fy;
+      force[3 * a + 2] = -kq * fz;
+    }
+    e_atom = 0.5 * kq * pot;
+  }
+  double bs = block_sum(e_atom, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = bs;
+  if (last_block_arrives(&ctl->ticket2, &flag)) {
+    double tot = reduce_partials_sum(partial, gridDim.x, sh);
+    if (threadIdx.x == 0) ctl->e_lr = tot;
+  }
+}
+
+// Short-range pairs (Eq. 20 force, Eq. 6 energy) over the cell list with the
+// minimum image; pairs inside one exclusion group instead get the Ewald
+// exclusion correction -k Q Q erf(alpha r)/r.  force += F_sr.
+__global__ void __launch_bounds__(kBlock)
+k_sr(int n_atoms, const double* __restrict__ pos, const double* __restrict__ qa, double box,
+     double alpha, double rc2, double k_e, int nc, int excl_group, const int* __restrict__ cstart,
+     const int* __restrict__ cperm, double* __restrict__ force, double e_self,
+     double* __restrict__ energy_out, double* __restrict__ partial, Ctl* ctl) {
+  __shared__ double sh[kBlock / 64];
+  __shared__ int flag;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  double en = 0.0;
+  if (t < n_atoms) {
+    const int i = cperm[t];
+    const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
+    const double qi = qa[i];
+    const double inv_box = 1.0 / box;
+    const double tapi = 2.0 * alpha / sqrt(M_PI);
+    double fx = 0, fy = 0, fz = 0;
+    int c[3];
+    const double xs[3] = {xi, yi, zi};
+    for (int d = 0; d < 3; d++) {
+      double s = xs[d] * inv_box;
+      s -= floor(s);
+      int ci = (int)(s * nc);
+      c[d] = ci >= nc ? nc - 1 : ci;
+    }
+    const int gi = excl_group > 0 ? i / excl_group : -1;
+    const int span = nc >= 3 ? 1 : 0;
+    const int lo = nc >= 3 ? -1 : 0, hi = nc >= 3 ? 1 : nc - 1;
+    for (int oz = lo; oz <= hi; oz++)
+      for (int oy = lo; oy <= hi; oy++)
+        for (int ox = lo; ox <= hi; ox++) {
+          int cx = span ? (c[0] + ox + nc) % nc : ox;
+          int cy = span ? (c[1] + oy + nc) % nc : oy;
+          int cz = span ? (c[2] + oz + nc) % nc : oz;
+          const int cell = (cz * nc + cy) * nc + cx;
+          const int j0 = cstart[cell], j1 = cstart[cell + 1];
+          for (int jj = j0; jj < j1; jj++) {
+            const int j = cperm[jj];
+            if (j == i) continue;
+            if (gi >= 0 && j / excl_group == gi) continue;
+            double dx = xi - pos[3 * j], dy = yi - pos[3 * j + 1], dz = zi - pos[3 * j + 2];
+            dx -= box * rint(dx * inv_box);
+            dy -= box * rint(dy * inv_box);
+            dz -= box * rint(dz * inv_box);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 >= rc2) continue;
+            const double r = sqrt(r2);
+            const double ec = erfc(alpha * r);
+            const double qq = k_e * qi * qa[j];
+            const double f = qq * (ec / (r2 * r) + tapi * exp(-alpha * alpha * r2) / r2);
+            fx += f * dx; fy += f * dy; fz += f * dz;
+            en += 0.5 * qq * ec / r;
+          }
+        }
+    if (gi >= 0) {
+      for (int j = gi * excl_group; j < gi * excl_group + excl_group && j < n_atoms; j++) {
+        if (j == i) continue;
+        double dx = xi - pos[3 * j], dy = yi - pos[3 * j + 1], dz = zi - pos[3 * j + 2];
+        dx -= box * rint(dx * inv_box);
+        dy -= box * rint(dy * inv_box);
+        dz -= box * rint(dz * inv_box);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double r = sqrt(r2);
+        const double er = erf(alpha * r);
+        const double qq = k_e * qi * qa[j];
+        const double f = qq * (tapi * exp(-alpha * alpha * r2) / r - er / r2) / r;
+        fx += f * dx; fy += f * dy; fz += f * dz;
+        en += -0.5 * qq * er / r;
+      }
+    }
+    if (force) {
+      force[3 * i] += fx;
+      force[3 * i + 1] += fy;
+      force[3 * i + 2] += fz;
+    }
+  }
+  double bs = block_sum(en, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = bs;
+  if (last_block_arrives(&ctl->ticket3, &flag)) {
+    double tot = reduce_partials_sum(partial, gridDim.x, sh);
+    if (threadIdx.x == 0) {
+      ctl->e_sr = tot;
+      if (energy_out) {
+        energy_out[0] = tot;
+        energy_out[1] = ctl->e_lr;
+        energy_out[2] = e_self;
+        energy_out[3] = tot + ctl->e_lr + e_self;
+      }
+    }
+  }
+}
+
+inline int blocks_for(int64_t n, int b) { return (int)((n + b - 1) / b); }
+
+}  // namespace
+
+hipError_t launch_bin_stencil(bool fp64, int n_atoms, const double* pos, double box, int n, int p,
+                              int tile, int ntx, int* base, void* w, int* key, int* slot, int* count,
+                              Ctl* ctl, hipStream_t s) {
+  if (fp64)
+    hipLaunchKernelGGL(k_bin_stencil<double>, dim3(blocks_for(n_atoms, kBlock)), dim3(kBlock), 0, s,
+                       n_atoms, pos, box, n, p, tile, ntx, base, (double*)w, key, slot, count, ctl);
+  else
+    hipLaunchKernelGGL(k_bin_stencil<float>, dim3(blocks_for(n_atoms, kBlock)), dim3(kBlock), 0, s,
+                       n_atoms, pos, box, n, p, tile, ntx, base, (float*)w, key, slot, count, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_cells(int n_atoms, const double* pos, double box, int nc, int* key, int* slot,
+                            int* count, Ctl* ctl, hipStream_t s) {
+  hipLaunchKernelGGL(k_bin_cells, dim3(blocks_for(n_atoms, kBlock)), dim3(kBlock), 0, s, n_atoms, pos,
+                     box, nc, key, slot, count, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(int nbins, int* count, int* start, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, nbins, count, start);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(int n_atoms, const int* key, const int* slot, const int* start, int* perm_raw,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n_atoms, kBlock)), dim3(kBlock), 0, s, n_atoms, key,
+                     slot, start, perm_raw);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_bins(int nbins, const int* start, const int* perm_raw, int* perm, Ctl*,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_sort_bins, dim3(blocks_for((int64_t)nbins * 64, kBlock)), dim3(kBlock), 0, s,
+                     nbins, start, perm_raw, perm);
+  return hipGetLastError();
+}
+
+hipError_t launch_spread(bool fp64, int n, int p, int tile, int ntx, const int* start, const int* perm,
+                         const int* base, const void* w, const double* qa, void* q, hipStream_t s) {
+  const int ntiles = ntx * ntx * ntx;
+  if (tile != 8) return hipErrorInvalidValue;
+  if (fp64)
+    hipLaunchKernelGGL((k_spread<double, 8>), dim3(ntiles), dim3(kBlock), 0, s, n, p, ntx, start, perm,
+                       base, (const double*)w, qa, (double*)q);
+  else
+    hipLaunchKernelGGL((k_spread<float, 8>), dim3(ntiles), dim3(kBlock), 0, s, n, p, ntx, start, perm,
+                       base, (const float*)w, qa, (float*)q);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, double h, double k_e, const int* perm,
+                         const int* base, const void* w, const double* qa, const void* phi,
+                         double* force, double* partial, Ctl* ctl, hipStream_t s) {
+  const int nb = blocks_for(n_atoms, kBlock);
+  if (fp64)
+    hipLaunchKernelGGL((k_gather<double, double>), dim3(nb), dim3(kBlock), 0, s, n_atoms, n, p, h, k_e,
+                       perm, base, (const double*)w, qa, (const double*)phi, force, partial, ctl);
+  else
+    hipLaunchKernelGGL((k_gather<float, float>), dim3(nb), dim3(kBlock), 0, s, n_atoms, n, p, h, k_e,
+                       perm, base, (const float*)w, qa, (const float*)phi, force, partial, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_sr(int n_atoms, const double* pos, const double* qa, double box, double alpha,
+                     double r_cut, double k_e, int nc, int excl_group, const int* cstart,
+                     const int* cperm, double* force, double e_self, double* energy_out,
+                     double* partial, Ctl* ctl, hipStream_t s) {
+  hipLaunchKernelGGL(k_sr, dim3(blocks_for(n_atoms, kBlock)), dim3(kBlock), 0, s, n_atoms, pos, qa, box,
+                     alpha, r_cut * r_cut, k_e, nc, excl_group, cstart, cperm, force, e_self, energy_out,
+                     partial, ctl);
+  return hipGetLastError();
+}

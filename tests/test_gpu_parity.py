@@ -1,0 +1,252 @@
+"""GPU parity: the HIP path through the C ABI against the CPU FP64 oracle on
+the same seeded inputs, element by element.
+
+Bars: FP64 mode relative RMS force error <= 1e-10 and identical V-cycle
+counts; mixed mode (FP32 spread, smoothing, sweeps and transfers; FP64
+residual, projections, coarsest solve and refinement) relative RMS force
+error <= 1e-5 and identical V-cycle counts.  Intermediate meshes are checked
+at the rounding level of each mode.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2606_31379_amd import configs, inputs
+
+from .gpu_util import K_E, GpuCtx, params_pair, rel_rms, trajectory
+
+pytestmark = pytest.mark.gpu
+
+FP64_BAR = 1e-10
+MIXED_BAR = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no HIP device")
+    return _t
+
+
+def run_pair(torch, system, gp, op, steps, dt=0.5):
+    g = GpuCtx(gp, system.charges, torch)
+    o = O.Oracle(op, system.charges)
+    out = []
+    try:
+        for k, pos in enumerate(trajectory(system, steps, dt)):
+            fg, eg, rcg = g.compute(pos)
+            fo, eo, rco = o.compute(pos)
+            out.append(dict(fg=fg, fo=fo, eg=eg, eo=eo, sg=g.stats(), so=o.stats(), rcg=rcg, rco=rco,
+                            phig=g.get_mesh(4), phio=o.get_mesh(O.MESH_PHI)))
+    finally:
+        g.close()
+    return out
+
+
+# ---------------------------------------------------------------------------
+# stage parity
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("order", [2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("mesh", [8, 16, 32])
+def test_spread_and_smoothing_fp64(torch, order, mesh):
+    s = inputs.random_neutral(37, 10.0, seed=order * 10 + mesh, dmin=0.8)  # ragged atom count
+    alpha = 0.45 if mesh >= 16 else 0.25
+    gp, op = params_pair(10.0, alpha, 4.0, mesh, order)
+    g = GpuCtx(gp, s.charges, torch)
+    o = O.Oracle(op, s.charges)
+    try:
+        g.compute(s.pos)
+        o.compute(s.pos)
+        for which, ow in [(0, O.MESH_Q), (1, O.MESH_QS), (2, O.MESH_SIGMA_P)]:
+            a, b = g.get_mesh(which), o.get_mesh(ow)
+            assert np.max(np.abs(a - b)) <= 1e-13 * max(1.0, np.max(np.abs(b))), (which, np.max(np.abs(a - b)))
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("mesh", [8, 16, 32, 64])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_vcycle_matches_oracle(torch, mesh, precision):
+    rng = np.random.default_rng(mesh)
+    r = rng.normal(size=(mesh,) * 3)
+    r -= r.mean()
+    gp, op = params_pair(20.0, 0.25 if mesh < 32 else 0.3, 9.0, mesh, 4, precision=precision)
+    g = GpuCtx(gp, np.array([1.0, -1.0]), torch)
+    o = O.Oracle(op, np.array([1.0, -1.0]))
+    try:
+        eg = g.vcycle(r)
+        eo = o.vcycle(r)
+        err = np.max(np.abs(eg - eo)) / np.max(np.abs(eo))
+        assert err < (1e-12 if precision == 0 else 2e-5), err
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("nu", [(1, 1), (2, 1), (0, 2), (3, 0)])
+def test_vcycle_schedules(torch, nu):
+    rng = np.random.default_rng(5)
+    r = rng.normal(size=(32,) * 3)
+    r -= r.mean()
+    gp, op = params_pair(20.0, 0.3, 9.0, 32, 4, nu_pre=nu[0], nu_post=nu[1])
+    g = GpuCtx(gp, np.array([1.0, -1.0]), torch)
+    o = O.Oracle(op, np.array([1.0, -1.0]))
+    try:
+        eg, eo = g.vcycle(r), o.vcycle(r)
+        assert np.max(np.abs(eg - eo)) < 1e-12 * np.max(np.abs(eo))
+    finally:
+        g.close()
+
+
+# ---------------------------------------------------------------------------
+# whole-step parity on the two small workloads
+# ---------------------------------------------------------------------------
+def check_steps(res, bar):
+    for k, r in enumerate(res):
+        assert r["rcg"] == r["rco"], k
+        assert r["sg"].cycles == r["so"].cycles, (k, r["sg"].cycles, r["so"].cycles,
+                                                  list(r["sg"].res_hist)[:r["sg"].cycles + 1],
+                                                  list(r["so"].res_hist)[:r["so"].cycles + 1])
+        assert r["sg"].m_eff == r["so"].m_eff
+        e = rel_rms(r["fg"], r["fo"])
+        assert e <= bar, (k, e)
+        assert np.max(np.abs(r["eg"] - r["eo"])) <= bar * np.max(np.abs(r["eo"])) * 10, (k, r["eg"], r["eo"])
+        dphi = np.max(np.abs(r["phig"] - r["phio"])) / np.max(np.abs(r["phio"]))
+        assert dphi <= bar * 10, (k, dphi)
+
+
+@pytest.mark.parametrize("precision,bar", [(0, FP64_BAR), (1, MIXED_BAR)])
+def test_nacl_512_steps(torch, precision, bar):
+    w = configs.nacl_512()
+    s = w.system()
+    gp, op = params_pair(w.box, w.alpha, w.r_cut, w.mesh, w.order, tol=w.tol, precision=precision,
+                         k_e=K_E, predictor=3)
+    res = run_pair(torch, s, gp, op, steps=6)
+    check_steps(res, bar)
+    assert res[0]["sg"].cold == 1 and res[1]["sg"].cold == 0
+
+
+@pytest.mark.parametrize("precision,bar", [(0, FP64_BAR), (1, MIXED_BAR)])
+def test_water_3000_steps(torch, precision, bar):
+    w = configs.water_3000()
+    s = w.system()
+    gp, op = params_pair(w.box, w.alpha, w.r_cut, w.mesh, w.order, tol=w.tol, precision=precision,
+                         k_e=K_E, predictor=3, excl_group=3)
+    res = run_pair(torch, s, gp, op, steps=4)
+    check_steps(res, bar)
+
+
+@pytest.mark.parametrize("pred", [0, 1, 2])
+def test_predictor_ramp_and_counts(torch, pred):
+    s = inputs.nacl(128, 25.2 * (128 / 512) ** (1 / 3), 1300.0, seed=77)
+    gp, op = params_pair(s.box, 0.45, 6.0, 16, 4, tol=1e-9, predictor=pred)
+    res = run_pair(torch, s, gp, op, steps=6, dt=2.0)
+    check_steps(res, FP64_BAR)
+
+
+# ---------------------------------------------------------------------------
+# edge cases
+# ---------------------------------------------------------------------------
+def test_positions_on_knots_boundaries_and_far_images(torch):
+    L, n = 8.0, 16
+    h = L / n
+    pos = np.array([[0.0, 0.0, 0.0], [L, L, L], [-L, 2 * L, 3 * h], [5 * h, 7 * h, 1e-12],
+                    [L - 1e-13, 3.0, 4.0], [-3.7, 11.9, -0.2], [2.5, 2.5, 2.5], [6.1, 0.3, 7.7]])
+    q = np.array([1.0, -1.0, 0.5, -0.5, 2.0, -2.0, 1.0, -1.0])
+    s = inputs.System(pos, q, np.ones(8), np.zeros_like(pos), L, "edge")
+    for order in (3, 4, 5):
+        gp, op = params_pair(L, 0.6, 3.5, n, order, tol=1e-10)
+        res = run_pair(torch, s, gp, op, steps=1)
+        check_steps(res, FP64_BAR)
+
+
+def test_two_atoms_and_single_tile_mesh(torch):
+    s = inputs.random_neutral(2, 6.0, seed=3)
+    gp, op = params_pair(6.0, 0.6, 3.0, 8, 4, tol=1e-10)
+    res = run_pair(torch, s, gp, op, steps=3)
+    check_steps(res, FP64_BAR)
+
+
+def test_cycle_cap_returns_warning_with_results(torch):
+    s = inputs.random_neutral(30, 10.0, seed=4, dmin=1.0)
+    gp, op = params_pair(10.0, 0.5, 5.0, 16, 4, tol=1e-12, max_cycles=1)
+    res = run_pair(torch, s, gp, op, steps=2)
+    for r in res:
+        assert r["rcg"] == 1 and r["rco"] == 1
+        assert r["sg"].cycles == 1
+    check_steps(res, FP64_BAR)
+
+
+def test_zero_cycles_when_prediction_meets_tolerance(torch):
+    s = inputs.random_neutral(30, 10.0, seed=6, dmin=1.0)
+    gp, op = params_pair(10.0, 0.5, 5.0, 16, 4, tol=1e-6, tol_mode=0)
+    pos = [s.pos] * 4            # a static configuration: the prediction is exact
+    g = GpuCtx(gp, s.charges, torch)
+    o = O.Oracle(op, s.charges)
+    try:
+        for x in pos:
+            g.compute(x)
+            o.compute(x)
+            assert g.stats().cycles == o.stats().cycles
+        assert g.stats().cycles == 0
+    finally:
+        g.close()
+
+
+def test_nan_position_is_an_error(torch):
+    from paper_2606_31379_amd import p3maze as P
+    s = inputs.random_neutral(10, 10.0, seed=8)
+    gp, _ = params_pair(10.0, 0.5, 5.0, 16, 4)
+    g = GpuCtx(gp, s.charges, torch)
+    try:
+        pos = s.pos.copy()
+        pos[3, 1] = np.nan
+        with pytest.raises(P.P3MZError) as ei:
+            g.compute(pos)
+        assert ei.value.code == P.P3MZ_ERR_NAN
+        f, e, rc = g.compute(s.pos)          # recovers with a cold solve
+        assert rc == 0 and g.stats().cold == 1 and np.all(np.isfinite(f))
+    finally:
+        g.close()
+
+
+# ---------------------------------------------------------------------------
+# determinism and restart
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", [0, 1])
+def test_bitwise_reproducible(torch, precision):
+    w = configs.nacl_512()
+    s = w.system()
+    gp, _ = params_pair(w.box, w.alpha, w.r_cut, w.mesh, w.order, tol=w.tol, precision=precision, k_e=K_E)
+    runs = []
+    for _ in range(2):
+        g = GpuCtx(gp, s.charges, torch)
+        try:
+            runs.append([g.compute(p)[0] for p in trajectory(s, 4)])
+        finally:
+            g.close()
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)
+
+
+def test_save_load_continues_bitwise(torch):
+    w = configs.nacl_512()
+    s = w.system()
+    gp, _ = params_pair(w.box, w.alpha, w.r_cut, w.mesh, w.order, tol=w.tol, k_e=K_E)
+    traj = trajectory(s, 7)
+    a = GpuCtx(gp, s.charges, torch)
+    b = GpuCtx(gp, s.charges, torch)
+    c = GpuCtx(gp, s.charges, torch)
+    try:
+        full = [a.compute(p)[0] for p in traj]
+        for p in traj[:4]:
+            b.compute(p)
+        blob = b.P.p3mz_save_state(b.h)
+        c.P.p3mz_load_state(c.h, blob)
+        rest = [c.compute(p)[0] for p in traj[4:]]
+        for u, v in zip(full[4:], rest):
+            assert np.array_equal(u, v)
+        with pytest.raises(c.P.P3MZError):
+            c.P.p3mz_load_state(c.h, blob[:-8])
+    finally:
+        a.close(); b.close(); c.close()
