@@ -1,0 +1,254 @@
+#!/usr/bin/env python
+"""Benchmark of the P3MaZe long-range mesh step on one MI355X.
+
+python bench.py [--steps K] [--warmup W] [--workload water-3000] [--gpus 1]
+
+One "step" is one velocity-Verlet MD step that drives one mesh step (bin,
+spread, smoothing, warm-started multigrid constraint solve, field update,
+gather) plus the short-range pairs and the non-electrostatic terms.  The
+headline value is the mesh-step time per atom (spread + smoothing + solve +
+gather, from HIP events around those stages) in the mixed-precision mode; the
+plain FP64 mode is measured the same way and reported beside it.  Inputs are
+seeded synthetic systems generated on the host and resident in HBM before
+the timed region.
+
+Extra fields of the JSON line:
+  roofline      the dominant kernel family's algorithmic bytes per launch over
+                its average event-timed launch duration in the timed region,
+                against the 8 TB/s HBM peak
+  cpu_baseline  the CPU FP64 oracle timed on this host on a bounded sample
+                (first mesh steps along the initial velocities)
+  parity        both GPU modes against the oracle on that sample
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "mesh-step ns/atom (spread+MG+gather) & HBM GB/s vs roofline, mixed vs FP64"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def md_terms(P, kind):
+    t = P.p3mz_mdterms()
+    t.force_to_acc = 1.0 / 103.6427
+    t.mv2_to_energy = 103.6427
+    if kind == "nacl":
+        t.model, t.bm_a, t.bm_rho = 1, 4000.0, 0.317
+    else:
+        kc = 0.0433641
+        t.model = 2
+        t.lj_eps, t.lj_sigma = 0.1554253 * kc, 3.165492
+        t.k_bond, t.r0 = 1059.162 * kc, 1.012
+        t.k_angle, t.theta0 = 75.90 * kc, math.radians(113.24)
+    return t
+
+
+def make_params(P, w, precision):
+    return P.make_params(w.box, w.alpha, w.r_cut, w.mesh, w.order, tol=w.tol, predictor=w.predictor,
+                         precision=precision, coulomb_k=14.3996454784, nu_pre=2, nu_post=2,
+                         excl_group=w.excl_group)
+
+
+def copy_ceiling_gbps(torch, nbytes=1 << 30, reps=10):
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+def run_mode(torch, P, w, system, precision, warmup, steps, kernel):
+    """Warm up, pick the dominant kernel family, then time `steps` MD steps."""
+    import numpy as np
+    dev = torch.device("cuda")
+    ctx = P.p3mz_create(make_params(P, w, precision), system.charges)
+    try:
+        pos = torch.from_numpy(np.ascontiguousarray(system.pos)).to(dev)
+        vel = torch.from_numpy(np.ascontiguousarray(system.vel)).to(dev)
+        mass = torch.from_numpy(np.ascontiguousarray(system.masses)).to(dev)
+        elog = torch.zeros((max(steps, 1), 6), dtype=torch.float64, device=dev)
+        clog = torch.zeros(max(steps, 1), dtype=torch.int32, device=dev)
+        terms = md_terms(P, w.kind)
+        stream = torch.cuda.current_stream().cuda_stream
+        dt = w.dt_fs
+
+        def md(n, with_logs=False, offset=0):
+            for k in range(n):
+                P.p3mz_md_run(ctx, pos.data_ptr(), vel.data_ptr(), mass.data_ptr(), terms, dt, 1,
+                              elog[offset + k].data_ptr() if with_logs else None,
+                              clog[offset + k].data_ptr() if with_logs else None, stream)
+
+        md(warmup)
+        # which kernel family takes the most time per step
+        shares = {}
+        P.p3mz_set_timing(ctx, True)
+        probe = max(2, min(5, steps))
+        for name, kid in P.KERNELS.items():
+            P.p3mz_set_kernel_timer(ctx, kid)
+            md(probe)
+            ms, n, _ = P.p3mz_get_kernel_timer(ctx)
+            shares[name] = ms / probe
+        # the roofline is taken for the mesh step (the short-range pair kernel is
+        # outside the measured metric)
+        mesh_shares = {k: v for k, v in shares.items() if k != "sr"}
+        dominant = kernel if kernel != "auto" else max(mesh_shares, key=mesh_shares.get)
+        log(f"[{'fp64' if precision == 0 else 'mixed'}] kernel ms/step: "
+            + ", ".join(f"{k}={v:.4f}" for k, v in sorted(shares.items(), key=lambda x: -x[1])))
+        P.p3mz_set_kernel_timer(ctx, P.KERNELS[dominant])
+        stage_ms = np.zeros(4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            md(1, with_logs=True, offset=k)
+            stage_ms += np.array(P.p3mz_get_stats(ctx).ms_stage)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kms, klaunch, kbytes = P.p3mz_get_kernel_timer(ctx)
+        cycles = clog.cpu().numpy()[:steps]
+        energies = elog.cpu().numpy()[:steps]
+        mesh_ms = stage_ms[:3].sum() / steps
+        avg_launch_ms = kms / max(klaunch, 1)
+        bytes_per_launch = kbytes / max(klaunch, 1)
+        out = dict(
+            ns_per_atom=mesh_ms * 1e6 / system.n,
+            mesh_ms_per_step=mesh_ms,
+            md_ms_per_step=wall * 1e3 / steps,
+            stage_ms_per_step=dict(spread_smooth=stage_ms[0] / steps, solve=stage_ms[1] / steps,
+                                   gather=stage_ms[2] / steps, short_range=stage_ms[3] / steps),
+            vcycles_per_step=float(cycles.mean()), vcycles_min=int(cycles.min()), vcycles_max=int(cycles.max()),
+            energy_drift_per_step=float(np.polyfit(np.arange(steps), energies[:, 5], 1)[0]) if steps > 2 else None,
+            kernel_ms_per_step=shares, dominant=dominant,
+            dominant_avg_launch_us=avg_launch_ms * 1e3, dominant_launches=klaunch,
+            dominant_bytes_per_launch=bytes_per_launch,
+            dominant_gbps=bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9 if klaunch else None,
+        )
+        return out
+    finally:
+        P.p3mz_destroy(ctx)
+
+
+def parity_and_baseline(torch, P, w, system, sample_steps):
+    """Oracle on a bounded sample (cold solve + warm steps along the initial
+    velocities), the GPU modes on the same positions, and the oracle's time."""
+    import numpy as np
+    from oracle import oracle as O
+    traj = [system.pos + k * w.dt_fs * system.vel for k in range(sample_steps)]
+    op = O.make_params(w.box, w.alpha, w.r_cut, w.mesh, w.order, tol=w.tol, predictor=w.predictor,
+                       coulomb_k=14.3996454784, nu_pre=2, nu_post=2, excl_group=w.excl_group)
+    orc = O.Oracle(op, system.charges)
+    ref, cyc_ref, t_mesh = [], [], []
+    for k, x in enumerate(traj):
+        f, e, _ = orc.compute(x)
+        st = orc.stats()
+        ref.append(f)
+        cyc_ref.append(st.cycles)
+        if k > 0:
+            t_mesh.append(st.t_spread + st.t_solve + st.t_gather)
+        log(f"[oracle] step {k} cycles={st.cycles} mesh_s={st.t_spread + st.t_solve + st.t_gather:.3f}")
+    out = {}
+    dev = torch.device("cuda")
+    for precision, name in ((0, "fp64"), (1, "mixed")):
+        ctx = P.p3mz_create(make_params(P, w, precision), system.charges)
+        try:
+            pos = torch.zeros((system.n, 3), dtype=torch.float64, device=dev)
+            frc = torch.zeros_like(pos)
+            errs, cyc = [], []
+            for k, x in enumerate(traj):
+                pos.copy_(torch.from_numpy(np.ascontiguousarray(x)))
+                P.p3mz_compute(ctx, pos.data_ptr(), frc.data_ptr(), None, torch.cuda.current_stream().cuda_stream)
+                torch.cuda.synchronize()
+                fg = frc.cpu().numpy()
+                errs.append(float(np.sqrt(((fg - ref[k]) ** 2).sum() / (ref[k] ** 2).sum())))
+                cyc.append(P.p3mz_get_stats(ctx).cycles)
+            out[name] = dict(max_rel_rms_force_err=max(errs), vcycles_gpu=cyc, vcycles_oracle=cyc_ref,
+                             vcycles_equal=cyc == cyc_ref)
+        finally:
+            P.p3mz_destroy(ctx)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    mean_s = float(np.mean(t_mesh)) if t_mesh else float("nan")
+    baseline = dict(value=mean_s * 1e9 / system.n, unit="ns/atom/step", cores=cores, kind="oracle",
+                    sample=f"{sample_steps} mesh steps of {w.name} along the initial velocities "
+                           f"(dt {w.dt_fs} fs); cold first step excluded from the mean; "
+                           f"spread+smoothing+solve+gather only")
+    return out, baseline
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="water-3000")
+    ap.add_argument("--kernel", default="auto", help="kernel family for the roofline (default: dominant)")
+    ap.add_argument("--cpu-sample-steps", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(domain decomposition is design-only); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2606_31379_amd import configs
+    from paper_2606_31379_amd import p3maze as P
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    w = configs.WORKLOADS[args.workload]()
+    log(f"workload {w.name}: generating inputs")
+    system = w.system()
+    log(f"atoms {system.n} box {system.box} mesh {w.mesh}^3 order {w.order} tol {w.tol}")
+    ceiling = copy_ceiling_gbps(torch)
+    log(f"device copy ceiling {ceiling:.0f} GB/s")
+    res = {}
+    for precision, name in ((0, "fp64"), (1, "mixed")):
+        log(f"[{name}] warmup {args.warmup}, timed {args.steps}")
+        res[name] = run_mode(torch, P, w, system, precision, args.warmup, args.steps, args.kernel)
+        log(f"[{name}] {json.dumps({k: v for k, v in res[name].items() if k != 'kernel_ms_per_step'})}")
+    parity, baseline = None, None
+    if not args.no_cpu_baseline:
+        sample = args.cpu_sample_steps or (8 if system.n <= 4000 else 3)
+        parity, baseline = parity_and_baseline(torch, P, w, system, sample)
+    m, f = res["mixed"], res["fp64"]
+    roof = dict(bound="hbm", kernel=m["dominant"], achieved=m["dominant_gbps"], peak=HBM_PEAK_GBPS,
+                unit="GB/s", frac=(m["dominant_gbps"] / HBM_PEAK_GBPS) if m["dominant_gbps"] else None,
+                traffic=None, avg_launch_us=m["dominant_avg_launch_us"],
+                alg_bytes_per_launch=m["dominant_bytes_per_launch"], copy_ceiling_GBps=ceiling)
+    line = dict(
+        metric=METRIC, value=m["ns_per_atom"], unit="ns/atom/step", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=m["md_ms_per_step"], higher_is_better=False, scaling="weak",
+        vs_baseline=None, dtype="f32+f64", data="synthetic",
+        config=dict(workload=w.name, n_atoms=system.n, box=w.box, mesh=w.mesh, order=w.order,
+                    alpha=w.alpha, r_cut=w.r_cut, tol=w.tol, predictor=w.predictor, dt_fs=w.dt_fs,
+                    precision="mixed"),
+        mixed=m, fp64=f,
+        speedup_mixed_vs_fp64=f["mesh_ms_per_step"] / m["mesh_ms_per_step"],
+        roofline=roof, cpu_baseline=baseline, parity=parity,
+    )
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -72,7 +72,11 @@ typedef struct {
   int32_t predictor;   /* multiplier predictor: 0 (Verlet prediction only, the in-house
                           real-space P3M start), 1: y^k, 2: 2y^k - y^{k-1},
                           3: 3y^k - 3y^{k-1} + y^{k-2}                                  */
-  int32_t precision;   /* p3mz_precision                                                */
+  int32_t precision;   /* p3mz_precision.  MIXED: V-cycle sweeps, restriction and
+                          prolongation, and the force gather in FP32; charge
+                          assignment, smoothing, sigma_p, the outer residual,
+                          zero-mean projections, coarsest solve and the
+                          multiplier/potential updates in FP64                */
   double coulomb_k;    /* Coulomb constant k_e (1 for Gaussian units)                   */
   int32_t nu_pre;      /* red-black Gauss-Seidel sweeps before restriction, >= 0;
                           -1: the autotuned or default (2) value                       */
@@ -96,6 +100,9 @@ typedef struct {
   double res_hist[65];       /* residual before cycle c, c = 0..cycles                */
   double e_sr, e_lr, e_self, e_total;
   int64_t steps;             /* completed compute calls since create/load            */
+  double ms_stage[4];        /* with p3mz_set_timing on: milliseconds of the last
+                                compute in {spread+smoothing, constraint solve and
+                                field update, gather, short-range pairs}          */
 } p3mz_stats;
 
 typedef struct p3mz_ctx p3mz_ctx;
@@ -166,6 +173,33 @@ typedef struct {
 p3mz_status p3mz_md_run(p3mz_ctx* ctx, double* pos_dev, double* vel_dev, const double* mass_dev,
                         const p3mz_mdterms* terms, double dt, int32_t n_steps,
                         double* energy_log_dev, int32_t* cycles_log_dev, void* stream);
+
+/* Record HIP events between the stages of every compute (on = 1) so that
+ * p3mz_stats.ms_stage holds their durations; on = 0 stops it.  Costs five
+ * event records per compute. */
+p3mz_status p3mz_set_timing(p3mz_ctx* ctx, int32_t on);
+
+/* Kernel families on the finest mesh level that can be timed launch by
+ * launch with HIP events on the compute stream. */
+enum {
+  P3MZ_KERNEL_HALFSWEEP = 0,  /* red or black Gauss-Seidel half-sweep             */
+  P3MZ_KERNEL_OUTER = 1,      /* FP64 outer residual + multiplier update          */
+  P3MZ_KERNEL_SMOOTH = 2,     /* one axis of the charge smoothing                 */
+  P3MZ_KERNEL_RESTRICT = 3,   /* fused residual + full-weighting restriction      */
+  P3MZ_KERNEL_PROLONG = 4,    /* prolongation fused with the first red half-sweep */
+  P3MZ_KERNEL_SWEEP0 = 5,     /* first sweep from a zero correction               */
+  P3MZ_KERNEL_TAIL = 6,       /* LDS-resident coarse levels (<= 16^3) + 4^3 solve */
+  P3MZ_KERNEL_SPREAD = 7, P3MZ_KERNEL_GATHER = 8, P3MZ_KERNEL_SR = 9,
+  P3MZ_KERNEL_SIGMA = 10, P3MZ_KERNEL_PHI = 11
+};
+/* Start timing one kernel family (kernel_id as above, -1 = off) and zero the
+ * totals.  Up to 2048 launches per compute are timed. */
+p3mz_status p3mz_set_kernel_timer(p3mz_ctx* ctx, int32_t kernel_id);
+/* Totals since p3mz_set_kernel_timer: summed event milliseconds, number of
+ * timed launches and the summed algorithmic HBM bytes of those launches
+ * (the bytes the method must move per launch, independent of caching). */
+p3mz_status p3mz_get_kernel_timer(const p3mz_ctx* ctx, double* total_ms, int64_t* launches,
+                                  double* total_bytes);
 
 void p3mz_destroy(p3mz_ctx* ctx);
 const char* p3mz_status_string(p3mz_status s);

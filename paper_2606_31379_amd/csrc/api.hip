@@ -155,7 +155,6 @@ struct p3mz_ctx {
   // md
   double* d_md_force = nullptr;
   double* d_e_other = nullptr;
-  unsigned int* d_md_ticket = nullptr;
   bool md_have_force = false;
   // history
   int have_hist = 0, n_yh = 0, k_idx = 0;
@@ -164,6 +163,15 @@ struct p3mz_ctx {
   int64_t steps = 0;
   p3mz_stats st{};
   std::vector<void*> allocs;
+  // optional timing: stage events and one kernel family's per-launch events
+  bool timing = false;
+  hipEvent_t stage_ev[5] = {};
+  int kt_id = -1;
+  std::vector<hipEvent_t> kt_ev;
+  std::vector<double> kt_bytes;
+  int kt_used = 0;
+  double kt_total_ms = 0.0, kt_total_bytes = 0.0;
+  int64_t kt_launches = 0;
 
   template <typename T>
   p3mz_status alloc(T** p, size_t count) {
@@ -185,8 +193,28 @@ struct p3mz_ctx {
   ~p3mz_ctx() {
     for (void* v : allocs) (void)hipFree(v);
     if (h_ctl) (void)hipHostFree(h_ctl);
+    for (hipEvent_t e : stage_ev)
+      if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : kt_ev) (void)hipEventDestroy(e);
   }
 };
+
+// The context whose compute is being enqueued (kernel-timer hooks read it).
+static p3mz_ctx* g_active = nullptr;
+
+void kt_begin(int id, int level, hipStream_t s) {
+  p3mz_ctx* c = g_active;
+  if (!c || c->kt_id != id || level != 0 || c->kt_used + 2 > (int)c->kt_ev.size()) return;
+  (void)hipEventRecord(c->kt_ev[c->kt_used], s);
+}
+
+void kt_end(int id, int level, double bytes, hipStream_t s) {
+  p3mz_ctx* c = g_active;
+  if (!c || c->kt_id != id || level != 0 || c->kt_used + 2 > (int)c->kt_ev.size()) return;
+  (void)hipEventRecord(c->kt_ev[c->kt_used + 1], s);
+  c->kt_bytes[c->kt_used / 2] = bytes;
+  c->kt_used += 2;
+}
 
 namespace {
 
@@ -216,13 +244,11 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   std::vector<double> taps;
   smoothing_taps(n, pl.K, pl.nu_s, &taps, &c->half);
   c->ntaps = (int)taps.size();
-  P3MZ_TRY(c->allocb(&c->d_taps, taps.size() * c->tsz));
-  if (c->fp64) {
-    P3MZ_HIP_TRY(hipMemcpy(c->d_taps, taps.data(), taps.size() * 8, hipMemcpyHostToDevice));
-  } else {
-    std::vector<float> tf(taps.begin(), taps.end());
-    P3MZ_HIP_TRY(hipMemcpy(c->d_taps, tf.data(), tf.size() * 4, hipMemcpyHostToDevice));
-  }
+  // The charge source (weights, spread, smoothing, sigma_p) is FP64 in both
+  // modes: FP32 rounding of q^s (~1e-7 relative) would exceed the residual
+  // tolerance and change the V-cycle counts of the warm-started solve.
+  P3MZ_TRY(c->allocb(&c->d_taps, taps.size() * 8));
+  P3MZ_HIP_TRY(hipMemcpy(c->d_taps, taps.data(), taps.size() * 8, hipMemcpyHostToDevice));
   double g[64];
   coarse_green(g);
   P3MZ_TRY(c->alloc(&c->d_green, 64));
@@ -232,7 +258,7 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   c->ntx = n / kTile;
   c->nbins = c->ntx * c->ntx * c->ntx;
   P3MZ_TRY(c->alloc(&c->d_base, 3 * na));
-  P3MZ_TRY(c->allocb(&c->d_w, (size_t)3 * na * pl.p * c->tsz));
+  P3MZ_TRY(c->allocb(&c->d_w, (size_t)3 * na * pl.p * 8));
   P3MZ_TRY(c->alloc(&c->d_key, na));
   P3MZ_TRY(c->alloc(&c->d_slot, na));
   P3MZ_TRY(c->alloc(&c->d_perm_raw, na));
@@ -253,9 +279,9 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   P3MZ_HIP_TRY(hipMemset(c->d_ccount, 0, sizeof(int) * c->ncells));
   // mesh
   const size_t n3 = (size_t)c->n3;
-  P3MZ_TRY(c->allocb(&c->d_q, n3 * c->tsz));
-  P3MZ_TRY(c->allocb(&c->d_qs, n3 * c->tsz));
-  P3MZ_TRY(c->allocb(&c->d_tmp, n3 * c->tsz));
+  P3MZ_TRY(c->allocb(&c->d_q, n3 * 8));
+  P3MZ_TRY(c->allocb(&c->d_qs, n3 * 8));
+  P3MZ_TRY(c->allocb(&c->d_tmp, n3 * 8));
   P3MZ_TRY(c->alloc(&c->d_sigma, n3));
   for (int i = 0; i < 2; i++) P3MZ_TRY(c->alloc(&c->d_y[i], n3));
   for (int i = 0; i < 2; i++) {
@@ -283,8 +309,6 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   P3MZ_TRY(c->alloc(&c->d_energy, 4));
   P3MZ_TRY(c->alloc(&c->d_md_force, 3 * na));
   P3MZ_TRY(c->alloc(&c->d_e_other, 1));
-  P3MZ_TRY(c->alloc(&c->d_md_ticket, 4));
-  P3MZ_HIP_TRY(hipMemset(c->d_md_ticket, 0, 4 * sizeof(unsigned int)));
   size_t lds = 0;
   P3MZ_HIP_TRY(tail_configure(c->fp64, n >> pl.tail, pl.levels - pl.tail, &lds));
   P3MZ_HIP_TRY(hipDeviceSynchronize());
@@ -304,37 +328,59 @@ p3mz_status compute_step(p3mz_ctx* c, const double* pos, double* force, double* 
   const Plan& pl = c->pl;
   const int n = pl.n, na = (int)c->n_atoms;
   const bool f64 = c->fp64;
+  const double N3 = (double)c->n3, ts = (double)c->tsz;
+  g_active = c;
+  struct Reset { ~Reset() { g_active = nullptr; } } reset_active;
+  auto stage = [&](int i) {
+    if (c->timing) (void)hipEventRecord(c->stage_ev[i], s);
+  };
+  stage(0);
   // 1. binning and deterministic order
-  P3MZ_HIP_TRY(launch_bin_stencil(f64, na, pos, c->P.box, n, pl.p, kTile, c->ntx, c->d_base, c->d_w, c->d_key,
+  P3MZ_HIP_TRY(launch_bin_stencil(true, na, pos, c->P.box, n, pl.p, kTile, c->ntx, c->d_base, c->d_w, c->d_key,
                                   c->d_slot, c->d_count, c->d_ctl, s));
   P3MZ_HIP_TRY(launch_scan(c->nbins, c->d_count, c->d_start, s));
   P3MZ_HIP_TRY(launch_scatter(na, c->d_key, c->d_slot, c->d_start, c->d_perm_raw, s));
   P3MZ_HIP_TRY(launch_sort_bins(c->nbins, c->d_start, c->d_perm_raw, c->d_perm, c->d_ctl, s));
   // 2. spread and smoothing
-  P3MZ_HIP_TRY(launch_spread(f64, n, pl.p, kTile, c->ntx, c->d_start, c->d_perm, c->d_base, c->d_w, c->d_qa, c->d_q, s));
-  P3MZ_HIP_TRY(launch_smooth(f64, n, 0, c->ntaps, c->half, c->d_taps, c->d_q, c->d_qs, s));
-  P3MZ_HIP_TRY(launch_smooth(f64, n, 1, c->ntaps, c->half, c->d_taps, c->d_qs, c->d_tmp, s));
-  P3MZ_HIP_TRY(launch_smooth(f64, n, 2, c->ntaps, c->half, c->d_taps, c->d_tmp, c->d_qs, s));
+  kt_begin(KT_SPREAD, 0, s);
+  P3MZ_HIP_TRY(launch_spread(true, n, pl.p, kTile, c->ntx, c->d_start, c->d_perm, c->d_base, c->d_w, c->d_qa, c->d_q, s));
+  kt_end(KT_SPREAD, 0, 8.0 * N3 + (double)na * (24.0 * pl.p + 24.0), s);
+  kt_begin(KT_SMOOTH, 0, s);
+  P3MZ_HIP_TRY(launch_smooth(true, n, 0, c->ntaps, c->half, c->d_taps, c->d_q, c->d_qs, s));
+  kt_end(KT_SMOOTH, 0, 16.0 * N3, s);
+  kt_begin(KT_SMOOTH, 0, s);
+  P3MZ_HIP_TRY(launch_smooth(true, n, 1, c->ntaps, c->half, c->d_taps, c->d_qs, c->d_tmp, s));
+  kt_end(KT_SMOOTH, 0, 16.0 * N3, s);
+  kt_begin(KT_SMOOTH, 0, s);
+  P3MZ_HIP_TRY(launch_smooth(true, n, 2, c->ntaps, c->half, c->d_taps, c->d_tmp, c->d_qs, s));
+  kt_end(KT_SMOOTH, 0, 16.0 * N3, s);
+  stage(1);
   // 3. constraint at the Verlet prediction and multiplier predictor
   const int cold = !c->have_hist;
   const int m_eff = cold ? 0 : std::min(c->P.predictor, c->n_yh);
   double* pk = c->d_phi[c->k_idx];
   double* pkm1 = c->d_phi[1 - c->k_idx];
-  P3MZ_HIP_TRY(launch_sigma(f64, n, pl.h, cold, m_eff, c->d_qs, pk, pkm1, c->d_yh[c->yh_order[0]],
+  kt_begin(KT_SIGMA, 0, s);
+  P3MZ_HIP_TRY(launch_sigma(true, n, pl.h, cold, m_eff, c->d_qs, pk, pkm1, c->d_yh[c->yh_order[0]],
                             c->d_yh[c->yh_order[1]], c->d_yh[c->yh_order[2]], c->d_sigma, c->d_y[0], c->P.tol,
                             c->P.tol_mode, c->d_partial, c->d_ctl, s));
+  kt_end(KT_SIGMA, 0, (cold ? 24.0 : 40.0 + 8.0 * m_eff) * N3, s);
   // 4. V-cycles; the host enqueues the expected number of cycles, then
   // checks the device flag and continues one cycle at a time if needed.
   const LevelBufs& f = c->lv[0];
+  kt_begin(KT_OUTER, 0, s);
   P3MZ_HIP_TRY(launch_outer(f64, n, 0, c->P.max_cycles, c->d_sigma, c->d_y[0], c->d_y[0], f.e0, f.e1, f.r0, f.r1,
                             c->d_partial, c->d_ctl, s));
+  kt_end(KT_OUTER, 0, (16.0 + ts) * N3, s);
   int cyc = 1;
   int batch = std::max(1, c->last_cycles);
   while (cyc <= c->P.max_cycles) {
     for (int b = 0; b < batch && cyc <= c->P.max_cycles; b++, cyc++) {
       P3MZ_HIP_TRY(launch_vcycle(f64, c->lv, pl.levels, pl.tail, c->nu1, c->nu2, c->d_green, c->d_ctl, s));
+      kt_begin(KT_OUTER, 0, s);
       P3MZ_HIP_TRY(launch_outer(f64, n, cyc, c->P.max_cycles, c->d_sigma, c->d_y[(cyc - 1) & 1], c->d_y[cyc & 1],
                                 f.e0, f.e1, f.r0, f.r1, c->d_partial, c->d_ctl, s));
+      kt_end(KT_OUTER, 0, (24.0 + 2.0 * ts) * N3, s);
     }
     if (cyc > c->P.max_cycles) break;
     P3MZ_HIP_TRY(hipMemcpyAsync(&c->h_ctl->done, &c->d_ctl->done, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -343,6 +389,7 @@ p3mz_status compute_step(p3mz_ctx* c, const double* pos, double* force, double* 
     batch = 1;
   }
   // 5. field update and history
+  kt_begin(KT_PHI, 0, s);
   if (cold) {
     P3MZ_HIP_TRY(launch_phi_update(n, pl.h, 1, pk, pkm1, c->d_y[0], c->d_y[1], pk, pkm1, nullptr, c->d_phi32,
                                    c->d_ctl, s));
@@ -351,19 +398,41 @@ p3mz_status compute_step(p3mz_ctx* c, const double* pos, double* force, double* 
     P3MZ_HIP_TRY(launch_phi_update(n, pl.h, 0, pk, pkm1, c->d_y[0], c->d_y[1], pkm1, nullptr, c->d_yh[slot],
                                    c->d_phi32, c->d_ctl, s));
   }
+  kt_end(KT_PHI, 0, (cold ? 16.0 : 40.0) * N3 + (f64 ? 0.0 : 4.0 * N3), s);
+  stage(2);
   // 6. gather on the new potential, short-range pairs, energies
   const double* phi_new = cold ? pk : pkm1;
   const void* phi_read = f64 ? (const void*)phi_new : (const void*)c->d_phi32;
+  kt_begin(KT_GATHER, 0, s);
   P3MZ_HIP_TRY(launch_gather(f64, na, n, pl.p, pl.h, c->P.coulomb_k, c->d_perm, c->d_base, c->d_w, c->d_qa, phi_read,
                              force, c->d_partial, c->d_ctl, s));
+  const double pe = pl.p + 2.0;
+  kt_end(KT_GATHER, 0, (double)na * (48.0 + 24.0 * pl.p + pe * pe * pe * (f64 ? 8.0 : 4.0)), s);
+  stage(3);
   P3MZ_HIP_TRY(launch_bin_cells(na, pos, c->P.box, c->nc, c->d_ckey, c->d_cslot, c->d_ccount, c->d_ctl, s));
   P3MZ_HIP_TRY(launch_scan(c->ncells, c->d_ccount, c->d_cstart, s));
   P3MZ_HIP_TRY(launch_scatter(na, c->d_ckey, c->d_cslot, c->d_cstart, c->d_cperm_raw, s));
   P3MZ_HIP_TRY(launch_sort_bins(c->ncells, c->d_cstart, c->d_cperm_raw, c->d_cperm, c->d_ctl, s));
+  kt_begin(KT_SR, 0, s);
   P3MZ_HIP_TRY(launch_sr(na, pos, c->d_qa, c->P.box, c->P.alpha, c->P.r_cut, c->P.coulomb_k, c->nc, c->P.excl_group,
                          c->d_cstart, c->d_cperm, force, c->e_self, energy ? energy : c->d_energy,
                          c->d_partial, c->d_ctl, s));
+  kt_end(KT_SR, 0, (double)na * 56.0, s);
+  stage(4);
   P3MZ_TRY(finish_step(c, s));
+  if (c->timing) {
+    float ms[4];
+    for (int i = 0; i < 4; i++) P3MZ_HIP_TRY(hipEventElapsedTime(&ms[i], c->stage_ev[i], c->stage_ev[i + 1]));
+    for (int i = 0; i < 4; i++) c->st.ms_stage[i] = ms[i];
+  }
+  for (int i = 0; i + 1 < c->kt_used; i += 2) {
+    float ms = 0.f;
+    P3MZ_HIP_TRY(hipEventElapsedTime(&ms, c->kt_ev[i], c->kt_ev[i + 1]));
+    c->kt_total_ms += ms;
+    c->kt_total_bytes += c->kt_bytes[i / 2];
+    c->kt_launches++;
+  }
+  c->kt_used = 0;
   const Ctl& h = *c->h_ctl;
   if (h.nan_flag) {
     P3MZ_HIP_TRY(hipMemsetAsync(&c->d_ctl->nan_flag, 0, sizeof(int), s));
@@ -452,8 +521,8 @@ p3mz_status p3mz_get_mesh(p3mz_ctx* ctx, int32_t which, double* out_dev, void* s
   hipStream_t s = (hipStream_t)stream;
   const size_t n3 = (size_t)ctx->n3;
   switch (which) {
-    case 0: P3MZ_HIP_TRY(launch_widen(ctx->fp64, n3, ctx->d_q, out_dev, s)); break;
-    case 1: P3MZ_HIP_TRY(launch_widen(ctx->fp64, n3, ctx->d_qs, out_dev, s)); break;
+    case 0: P3MZ_HIP_TRY(launch_widen(true, n3, ctx->d_q, out_dev, s)); break;
+    case 1: P3MZ_HIP_TRY(launch_widen(true, n3, ctx->d_qs, out_dev, s)); break;
     case 2: {
       // zero-mean sigma_p = stored sigma - mean (mean kept in the control block)
       P3MZ_HIP_TRY(launch_sub_scalar(n3, ctx->d_sigma, out_dev, &ctx->d_ctl->mean_sigma, s));
@@ -581,7 +650,7 @@ p3mz_status p3mz_md_run(p3mz_ctx* ctx, double* pos_dev, double* vel_dev, const d
     // the cell list of the short-range pass is still valid for these positions
     hipError_t e = launch_nonelec(na, pos_dev, ctx->P.box, ctx->P.r_cut, terms->model, p[0], p[1], p[2], p[3], p[4],
                                   p[5], ctx->nc, ctx->d_cstart, ctx->d_cperm, ctx->d_md_force, ctx->d_partial,
-                                  ctx->d_e_other, ctx->d_md_ticket, s);
+                                  ctx->d_e_other, s);
     if (e != hipSuccess) return hip_fail(e, "launch_nonelec", __FILE__, __LINE__);
     return st;
   };
@@ -599,11 +668,43 @@ p3mz_status p3mz_md_run(p3mz_ctx* ctx, double* pos_dev, double* vel_dev, const d
     P3MZ_HIP_TRY(launch_kick_drift(na, pos_dev, vel_dev, ctx->d_md_force, mass_dev, dt, terms->force_to_acc, 0, s));
     P3MZ_HIP_TRY(launch_kinetic_log(na, vel_dev, mass_dev, terms->mv2_to_energy, ctx->d_energy, ctx->d_e_other,
                                     energy_log_dev ? energy_log_dev + 6 * (size_t)step : nullptr,
-                                    cycles_log_dev ? cycles_log_dev + step : nullptr, ctx->d_ctl, ctx->d_partial,
-                                    ctx->d_md_ticket + 1, s));
+                                    cycles_log_dev ? cycles_log_dev + step : nullptr, ctx->d_ctl, ctx->d_partial, s));
   }
   P3MZ_HIP_TRY(hipStreamSynchronize(s));
   return worst;
+}
+
+p3mz_status p3mz_set_timing(p3mz_ctx* ctx, int32_t on) {
+  if (!ctx) return fail(P3MZ_ERR_INVALID_ARG, "ctx is NULL");
+  if (on && !ctx->stage_ev[0])
+    for (hipEvent_t& e : ctx->stage_ev) P3MZ_HIP_TRY(hipEventCreate(&e));
+  ctx->timing = on != 0;
+  for (double& v : ctx->st.ms_stage) v = 0.0;
+  return P3MZ_OK;
+}
+
+p3mz_status p3mz_set_kernel_timer(p3mz_ctx* ctx, int32_t kernel_id) {
+  if (!ctx) return fail(P3MZ_ERR_INVALID_ARG, "ctx is NULL");
+  if (kernel_id < -1 || kernel_id >= KT_COUNT) return fail(P3MZ_ERR_INVALID_ARG, "unknown kernel id");
+  if (kernel_id >= 0 && ctx->kt_ev.empty()) {
+    ctx->kt_ev.resize(2 * 2048);
+    ctx->kt_bytes.resize(2048);
+    for (hipEvent_t& e : ctx->kt_ev) P3MZ_HIP_TRY(hipEventCreate(&e));
+  }
+  ctx->kt_id = kernel_id;
+  ctx->kt_used = 0;
+  ctx->kt_total_ms = 0.0;
+  ctx->kt_total_bytes = 0.0;
+  ctx->kt_launches = 0;
+  return P3MZ_OK;
+}
+
+p3mz_status p3mz_get_kernel_timer(const p3mz_ctx* ctx, double* total_ms, int64_t* launches, double* total_bytes) {
+  if (!ctx || !total_ms || !launches || !total_bytes) return fail(P3MZ_ERR_INVALID_ARG, "NULL argument");
+  *total_ms = ctx->kt_total_ms;
+  *launches = ctx->kt_launches;
+  *total_bytes = ctx->kt_total_bytes;
+  return P3MZ_OK;
 }
 
 void p3mz_destroy(p3mz_ctx* ctx) {

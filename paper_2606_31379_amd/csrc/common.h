@@ -18,11 +18,7 @@ struct Ctl {
   int cycles;            // V-cycles applied this step
   int status;            // 0 ok, 1 cycle cap reached
   int final_buf;         // which y ping-pong buffer holds the final multiplier
-  unsigned int ticket;   // arrival counter for the last-block reductions
-  unsigned int ticket2;
-  unsigned int ticket3;
   int nan_flag;          // non-finite position seen by the binning kernel
-  int overflow_flag;     // bin with more atoms than the sort handles
   int pad_;
   double thresh;         // residual threshold
   double norm_qs;        // max |q^s|
@@ -70,26 +66,10 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
   return r;
 }
 
-// Last-block pattern: every block stores its partial, then the block that
-// arrives last reads all partials in index order.  Returns true in the last
-// block (all threads).  `ticket` is reset for the next use.
-__device__ __forceinline__ bool last_block_arrives(unsigned int* ticket, int* sh_flag) {
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned int t = atomicAdd(ticket, 1u);
-    *sh_flag = (t == gridDim.x - 1);
-  }
-  __syncthreads();
-  bool last = *sh_flag;
-  if (last) {
-    __threadfence();
-    if (threadIdx.x == 0) *ticket = 0u;
-  }
-  return last;
-}
-
-// Deterministic sum of n partials by one block: fixed strided split + fixed tree.
+// Reductions are two-pass: every workgroup of a kernel stores its partial,
+// then a one-workgroup kernel reads them in index order (kernel boundaries
+// make the partials visible across XCDs without device-scope fences in the
+// hot kernels).  Deterministic sum of n partials: fixed strided split + fixed tree.
 __device__ __forceinline__ double reduce_partials_sum(const double* p, int n, double* sh) {
   double acc = 0.0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) acc += p[i];

@@ -4,6 +4,17 @@
 
 #include "common.h"
 
+// Kernel families that can be timed individually with HIP events.
+enum KernelId {
+  KT_HALFSWEEP = 0, KT_OUTER = 1, KT_SMOOTH = 2, KT_RESTRICT = 3, KT_PROLONG = 4, KT_SWEEP0 = 5,
+  KT_TAIL = 6, KT_SPREAD = 7, KT_GATHER = 8, KT_SR = 9, KT_SIGMA = 10, KT_PHI = 11, KT_COUNT = 12
+};
+// Bracket one launch of kernel family `id` on multigrid level `level` with
+// events when that family/level is being timed (no-ops otherwise).
+// `bytes` is the launch's algorithmic HBM traffic.
+void kt_begin(int id, int level, hipStream_t s);
+void kt_end(int id, int level, double bytes, hipStream_t s);
+
 // ---- particles (particles.hip) ------------------------------------------
 // Per-atom stencil base, B-spline weights (precision T) and tile key for
 // the spread; slot = arrival rank inside the key's bin.
@@ -79,8 +90,7 @@ hipError_t launch_kick_drift(int n_atoms, double* pos, double* vel, const double
 hipError_t launch_nonelec(int n_atoms, const double* pos, double box, double r_cut, int model,
                           double p0, double p1, double p2, double p3, double p4, double p5,
                           int nc, const int* cstart, const int* cperm, double* force,
-                          double* partial, double* e_out, unsigned int* ticket, hipStream_t s);
+                          double* partial, double* e_out, hipStream_t s);
 hipError_t launch_kinetic_log(int n_atoms, const double* vel, const double* mass, double mv2e,
                               const double* energy4, const double* e_other, double* log_row,
-                              int* cycles_row, const Ctl* ctl, double* partial,
-                              unsigned int* ticket, hipStream_t s);
+                              int* cycles_row, const Ctl* ctl, double* partial, hipStream_t s);

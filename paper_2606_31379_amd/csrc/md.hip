@@ -23,23 +23,23 @@ __device__ __forceinline__ double mi(double d, double box, double inv_box) { ret
 
 // model 1: stand-in Born-Mayer repulsion between all pairs (shifted at r_cut);
 // model 2: flexible three-site water -- intermolecular O-O Lennard-Jones
-// (shifted at r_cut) plus harmonic O-H bonds and H-O-H angle.  One thread
-// per atom; each thread recomputes its molecule's bonded terms and keeps
-// the part acting on its own atom (no atomics).  force += F_other.
+// (shifted at r_cut) plus harmonic O-H bonds and H-O-H angle.  One wave per
+// atom: lanes stride the neighbour cells' lists, lane 0 adds the bonded
+// terms of the atom's molecule that act on it (each atom's wave recomputes
+// them; no atomics), a fixed shuffle tree sums the lanes.  force += F_other.
 __global__ void __launch_bounds__(kBlock)
 k_nonelec(int n_atoms, const double* __restrict__ pos, double box, double rc2, int model, double p0,
           double p1, double p2, double p3, double p4, double p5, int nc, const int* __restrict__ cstart,
-          const int* __restrict__ cperm, double* __restrict__ force, double* __restrict__ partial,
-          double* __restrict__ e_out, unsigned int* ticket) {
+          const int* __restrict__ cperm, double* __restrict__ force, double* __restrict__ partial) {
   __shared__ double sh[kBlock / 64];
-  __shared__ int flag;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  double en = 0.0;
-  if (t < n_atoms && model != 0) {
-    const int i = cperm[t];
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  double en = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+  int i = -1;
+  if (wave < n_atoms && model != 0) {
+    i = cperm[wave];
     const double inv_box = 1.0 / box;
     const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
-    double fx = 0, fy = 0, fz = 0;
     const bool pair_atom = model == 1 || (i % 3 == 0);
     if (pair_atom) {
       int c[3];
@@ -52,10 +52,11 @@ k_nonelec(int n_atoms, const double* __restrict__ pos, double box, double rc2, i
       }
       const int span = nc >= 3 ? 1 : 0;
       const int lo = nc >= 3 ? -1 : 0, hi = nc >= 3 ? 1 : nc - 1;
-      double shift = 0.0;
-      if (model == 1) shift = p0 * exp(-sqrt(rc2) / p1);
-      else {
-        const double s6 = (p1 * p1 / rc2) * (p1 * p1 / rc2) * (p1 * p1 / rc2);
+      double shift;
+      if (model == 1) {
+        shift = p0 * exp(-sqrt(rc2) / p1);
+      } else {
+        const double s2 = p1 * p1 / rc2, s6 = s2 * s2 * s2;
         shift = 4.0 * p0 * (s6 * s6 - s6);
       }
       for (int oz = lo; oz <= hi; oz++)
@@ -65,7 +66,7 @@ k_nonelec(int n_atoms, const double* __restrict__ pos, double box, double rc2, i
             const int cy = span ? (c[1] + oy + nc) % nc : oy;
             const int cz = span ? (c[2] + oz + nc) % nc : oz;
             const int cell = (cz * nc + cy) * nc + cx;
-            for (int jj = cstart[cell]; jj < cstart[cell + 1]; jj++) {
+            for (int jj = cstart[cell] + lane; jj < cstart[cell + 1]; jj += 64) {
               const int j = cperm[jj];
               if (j == i) continue;
               if (model == 2 && (j % 3 != 0 || j / 3 == i / 3)) continue;
@@ -90,7 +91,7 @@ k_nonelec(int n_atoms, const double* __restrict__ pos, double box, double rc2, i
             }
           }
     }
-    if (model == 2) {
+    if (model == 2 && lane == 0) {
       const int o = (i / 3) * 3;
       double a[3], b[3];
       for (int d = 0; d < 3; d++) {
@@ -111,49 +112,66 @@ k_nonelec(int n_atoms, const double* __restrict__ pos, double box, double rc2, i
         f2[d] = fb * b[d] + g * (a[d] / (la * lb) - cth * b[d] / (lb * lb));
       }
       const int role = i - o;
-      const double* fr = role == 1 ? f1 : f2;
       if (role == 0) {
         fx -= f1[0] + f2[0]; fy -= f1[1] + f2[1]; fz -= f1[2] + f2[2];
         en += 0.5 * p2 * ((la - p3) * (la - p3) + (lb - p3) * (lb - p3)) + 0.5 * p4 * (th - p5) * (th - p5);
       } else {
+        const double* fr = role == 1 ? f1 : f2;
         fx += fr[0]; fy += fr[1]; fz += fr[2];
       }
     }
-    force[3 * i] += fx;
-    force[3 * i + 1] += fy;
-    force[3 * i + 2] += fz;
   }
-  double bs = block_sum(en, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = bs;
-  if (last_block_arrives(ticket, &flag)) {
-    double tot = reduce_partials_sum(partial, gridDim.x, sh);
-    if (threadIdx.x == 0) *e_out = tot;
+  fx = wave_sum(fx);
+  fy = wave_sum(fy);
+  fz = wave_sum(fz);
+  en = wave_sum(en);
+  if (lane == 0) {
+    if (i >= 0) {
+      force[3 * i] += fx;
+      force[3 * i + 1] += fy;
+      force[3 * i + 2] += fz;
+    }
+    sh[threadIdx.x >> 6] = en;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int k = 0; k < kBlock / 64; k++) s += sh[k];
+    partial[blockIdx.x] = s;
   }
 }
 
-__global__ void __launch_bounds__(kBlock)
-k_kinetic_log(int n_atoms, const double* __restrict__ vel, const double* __restrict__ mass, double mv2e,
-              const double* __restrict__ e4, const double* __restrict__ e_other, double* __restrict__ row,
-              int* __restrict__ crow, const Ctl* ctl, double* __restrict__ partial, unsigned int* ticket) {
+__global__ void __launch_bounds__(kBlock) k_fin_other(int nb, const double* __restrict__ partial, double* e_out) {
   __shared__ double sh[kBlock / 64];
-  __shared__ int flag;
+  const double tot = reduce_partials_sum(partial, nb, sh);
+  if (threadIdx.x == 0) *e_out = tot;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_kinetic(int n_atoms, const double* __restrict__ vel, const double* __restrict__ mass, double mv2e,
+          double* __restrict__ partial) {
+  __shared__ double sh[kBlock / 64];
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
   double ke = 0.0;
   if (a < n_atoms) {
     const double vx = vel[3 * a], vy = vel[3 * a + 1], vz = vel[3 * a + 2];
     ke = 0.5 * mass[a] * (vx * vx + vy * vy + vz * vz) * mv2e;
   }
-  double bs = block_sum(ke, sh);
+  const double bs = block_sum(ke, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = bs;
-  if (last_block_arrives(ticket, &flag)) {
-    double tot = reduce_partials_sum(partial, gridDim.x, sh);
-    if (threadIdx.x == 0) {
-      if (row) {
-        row[0] = e4[0]; row[1] = e4[1]; row[2] = e4[2]; row[3] = *e_other; row[4] = tot;
-        row[5] = e4[3] + *e_other + tot;
-      }
-      if (crow) *crow = ctl->cycles;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_fin_log(int nb, const double* __restrict__ partial, const double* __restrict__ e4,
+          const double* __restrict__ e_other, double* row, int* crow, const Ctl* ctl) {
+  __shared__ double sh[kBlock / 64];
+  const double tot = reduce_partials_sum(partial, nb, sh);
+  if (threadIdx.x == 0) {
+    if (row) {
+      row[0] = e4[0]; row[1] = e4[1]; row[2] = e4[2]; row[3] = *e_other; row[4] = tot;
+      row[5] = e4[3] + *e_other + tot;
     }
+    if (crow) *crow = ctl->cycles;
   }
 }
 
@@ -168,17 +186,19 @@ hipError_t launch_kick_drift(int n_atoms, double* pos, double* vel, const double
 
 hipError_t launch_nonelec(int n_atoms, const double* pos, double box, double r_cut, int model, double p0,
                           double p1, double p2, double p3, double p4, double p5, int nc, const int* cstart,
-                          const int* cperm, double* force, double* partial, double* e_out, unsigned int* ticket,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(k_nonelec, dim3(blocks_for(n_atoms, kBlock)), dim3(kBlock), 0, s, n_atoms, pos, box,
-                     r_cut * r_cut, model, p0, p1, p2, p3, p4, p5, nc, cstart, cperm, force, partial, e_out, ticket);
+                          const int* cperm, double* force, double* partial, double* e_out, hipStream_t s) {
+  const int nb = blocks_for((int64_t)n_atoms * 64, kBlock);
+  hipLaunchKernelGGL(k_nonelec, dim3(nb), dim3(kBlock), 0, s, n_atoms, pos, box, r_cut * r_cut, model, p0, p1, p2,
+                     p3, p4, p5, nc, cstart, cperm, force, partial);
+  hipLaunchKernelGGL(k_fin_other, dim3(1), dim3(kBlock), 0, s, nb, partial, e_out);
   return hipGetLastError();
 }
 
 hipError_t launch_kinetic_log(int n_atoms, const double* vel, const double* mass, double mv2e,
                               const double* energy4, const double* e_other, double* log_row, int* cycles_row,
-                              const Ctl* ctl, double* partial, unsigned int* ticket, hipStream_t s) {
-  hipLaunchKernelGGL(k_kinetic_log, dim3(blocks_for(n_atoms, kBlock)), dim3(kBlock), 0, s, n_atoms, vel, mass,
-                     mv2e, energy4, e_other, log_row, cycles_row, ctl, partial, ticket);
+                              const Ctl* ctl, double* partial, hipStream_t s) {
+  const int nb = blocks_for(n_atoms, kBlock);
+  hipLaunchKernelGGL(k_kinetic, dim3(nb), dim3(kBlock), 0, s, n_atoms, vel, mass, mv2e, partial);
+  hipLaunchKernelGGL(k_fin_log, dim3(1), dim3(kBlock), 0, s, nb, partial, energy4, e_other, log_row, cycles_row, ctl);
   return hipGetLastError();
 }

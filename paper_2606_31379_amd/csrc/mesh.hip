@@ -77,10 +77,9 @@ template <typename TQ>
 __global__ void __launch_bounds__(kBlock)
 k_sigma(int n, double h, int cold, int m_eff, const TQ* __restrict__ qs, const double* __restrict__ pk,
         const double* __restrict__ pkm1, const double* __restrict__ y0, const double* __restrict__ y1,
-        const double* __restrict__ y2, double* __restrict__ sigma, double* __restrict__ y, double tol,
-        int tol_mode, double* __restrict__ partial, Ctl* ctl) {
+        const double* __restrict__ y2, double* __restrict__ sigma, double* __restrict__ y,
+        double* __restrict__ partial) {
   __shared__ double sh[kBlock / 64];
-  __shared__ int flag;
   const int n3 = n * n * n;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   double sv = 0.0, qmax = 0.0;
@@ -113,18 +112,22 @@ k_sigma(int n, double h, int cold, int m_eff, const TQ* __restrict__ qs, const d
     partial[blockIdx.x] = bs;
     partial[gridDim.x + blockIdx.x] = bm;
   }
-  if (last_block_arrives(&ctl->ticket, &flag)) {
-    double tot = reduce_partials_sum(partial, gridDim.x, sh);
-    double mx = reduce_partials_max(partial + gridDim.x, gridDim.x, sh);
-    if (threadIdx.x == 0) {
-      ctl->mean_sigma = tot / (double)n3;
-      ctl->norm_qs = mx;
-      ctl->thresh = tol_mode == 0 ? tol * mx : tol;
-      ctl->done = 0;
-      ctl->cycles = 0;
-      ctl->status = 0;
-      ctl->final_buf = 0;
-    }
+}
+
+// One workgroup: mean of sigma_p, max|q^s|, threshold; opens the step's solve.
+__global__ void __launch_bounds__(kBlock)
+k_fin_sigma(int nb, int n3, double tol, int tol_mode, const double* __restrict__ partial, Ctl* ctl) {
+  __shared__ double sh[kBlock / 64];
+  const double tot = reduce_partials_sum(partial, nb, sh);
+  const double mx = reduce_partials_max(partial + nb, nb, sh);
+  if (threadIdx.x == 0) {
+    ctl->mean_sigma = tot / (double)n3;
+    ctl->norm_qs = mx;
+    ctl->thresh = tol_mode == 0 ? tol * mx : tol;
+    ctl->done = 0;
+    ctl->cycles = 0;
+    ctl->status = 0;
+    ctl->final_buf = 0;
   }
 }
 
@@ -136,11 +139,10 @@ k_sigma(int n, double h, int cold, int m_eff, const TQ* __restrict__ qs, const d
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_outer(int n, int c, int max_cycles, const double* __restrict__ sigma, const double* __restrict__ y_in,
+k_outer(int n, int c, const double* __restrict__ sigma, const double* __restrict__ y_in,
         double* __restrict__ y_out, const T* __restrict__ e0, const T* __restrict__ e1,
-        T* __restrict__ r0, T* __restrict__ r1, double* __restrict__ partial, Ctl* ctl) {
+        T* __restrict__ r0, T* __restrict__ r1, double* __restrict__ partial, const Ctl* ctl) {
   __shared__ double sh[kBlock / 64];
-  __shared__ int flag;
   if (ctl->done) return;
   const int n3 = n * n * n;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -172,20 +174,25 @@ k_outer(int n, int c, int max_cycles, const double* __restrict__ sigma, const do
     partial[blockIdx.x] = bm;
     partial[gridDim.x + blockIdx.x] = bs;
   }
-  if (last_block_arrives(&ctl->ticket, &flag)) {
-    double res = reduce_partials_max(partial, gridDim.x, sh);
-    double ys = reduce_partials_sum(partial + gridDim.x, gridDim.x, sh);
-    if (threadIdx.x == 0) {
-      ctl->res_hist[c] = res;
-      ctl->mean_y = ys / (double)n3;
-      ctl->cycles = c;
-      ctl->final_buf = c & 1;
-      if (res <= ctl->thresh) {
-        ctl->done = 1;
-      } else if (c >= max_cycles) {
-        ctl->done = 1;
-        ctl->status = 1;
-      }
+}
+
+// One workgroup: residual of cycle c, running mean of y, stop decision.
+__global__ void __launch_bounds__(kBlock)
+k_fin_outer(int c, int max_cycles, int nb, int n3, const double* __restrict__ partial, Ctl* ctl) {
+  __shared__ double sh[kBlock / 64];
+  if (ctl->done) return;
+  const double res = reduce_partials_max(partial, nb, sh);
+  const double ys = reduce_partials_sum(partial + nb, nb, sh);
+  if (threadIdx.x == 0) {
+    ctl->res_hist[c] = res;
+    ctl->mean_y = ys / (double)n3;
+    ctl->cycles = c;
+    ctl->final_buf = c & 1;
+    if (res <= ctl->thresh) {
+      ctl->done = 1;
+    } else if (c >= max_cycles) {
+      ctl->done = 1;
+      ctl->status = 1;
     }
   }
 }
@@ -256,10 +263,14 @@ __device__ __forceinline__ T cs_load(const T* __restrict__ c0, const T* __restri
 
 // Residual rho = r - M e at the 27 fine points around 2I, full weighting,
 // times 4 (coarse operator rediscretised on 2h).  One thread per coarse point.
+// When the last pre-smoothing operation was a black half-sweep, the black
+// residuals are zero up to rounding (Gauss-Seidel just solved those rows), so
+// only the 13 red points of the 27-point stencil are evaluated (red_only).
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_resid_restrict(int n, const T* __restrict__ e0, const T* __restrict__ e1, const T* __restrict__ r0,
-                 const T* __restrict__ r1, T* __restrict__ rc0, T* __restrict__ rc1, const Ctl* ctl) {
+k_resid_restrict(int n, int red_only, const T* __restrict__ e0, const T* __restrict__ e1,
+                 const T* __restrict__ r0, const T* __restrict__ r1, T* __restrict__ rc0, T* __restrict__ rc1,
+                 const Ctl* ctl) {
   if (ctl->done) return;
   const int nc = n >> 1;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -275,6 +286,7 @@ k_resid_restrict(int n, const T* __restrict__ e0, const T* __restrict__ e1, cons
       for (int a = -1; a <= 1; a++) {
         const int x = wrapn(2 * I + a, n);
         const bool odd = (x + y + z) & 1;
+        if (red_only && odd) continue;
         const T* eo = odd ? e0 : e1;     // neighbours have the other colour
         const T ev = odd ? e1[cs_idx(n, x, y, z)] : e0[cs_idx(n, x, y, z)];
         const T rv = odd ? r1[cs_idx(n, x, y, z)] : r0[cs_idx(n, x, y, z)];
@@ -361,22 +373,27 @@ __global__ void __launch_bounds__(kBlock) k_fill_zero(int64_t count, T* __restri
 // e = G * r (G the periodic 4^3 Green's function of M, FP64 accumulation).
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ T lds_nbr(const T* v, int n, int i, int j, int k) {
-  const int im = (i - 1) & (n - 1), ip = (i + 1) & (n - 1), jm = (j - 1) & (n - 1), jp = (j + 1) & (n - 1);
-  const int km = (k - 1) & (n - 1), kp = (k + 1) & (n - 1);
-  return ((v[(k * n + j) * n + im] + v[(k * n + j) * n + ip]) + (v[(k * n + jm) * n + i] + v[(k * n + jp) * n + i])) +
-         (v[(km * n + j) * n + i] + v[(kp * n + j) * n + i]);
+__device__ __forceinline__ T lds_nbr(const T* v, int n, int l2, int i, int j, int k) {
+  const int msk = n - 1;
+  const int row = (k << l2) + j;
+  const int rjm = (k << l2) + ((j - 1) & msk), rjp = (k << l2) + ((j + 1) & msk);
+  const int rkm = (((k - 1) & msk) << l2) + j, rkp = (((k + 1) & msk) << l2) + j;
+  return ((v[(row << l2) + ((i - 1) & msk)] + v[(row << l2) + ((i + 1) & msk)]) +
+          (v[(rjm << l2) + i] + v[(rjp << l2) + i])) +
+         (v[(rkm << l2) + i] + v[(rkp << l2) + i]);
 }
 
+// One red (colour 0) or black half-sweep over an LDS-resident level of edge
+// n = 2^l2, natural layout.
 template <typename T>
-__device__ void tail_rbgs(T* e, const T* r, int n, int colour) {
-  const int n3 = n * n * n;
-  for (int p = threadIdx.x; p < n3 / 2; p += blockDim.x) {
-    const int hn = n >> 1;
-    const int m = p % hn, row = p / hn, j = row % n, k = row / n;
+__device__ __forceinline__ void tail_rbgs(T* e, const T* r, int n, int l2, int colour) {
+  const int half = 1 << (3 * l2 - 1);
+  for (int p = threadIdx.x; p < half; p += blockDim.x) {
+    const int m = p & ((n >> 1) - 1), row = p >> (l2 - 1);
+    const int j = row & (n - 1), k = row >> l2;
     const int i = 2 * m + ((colour + j + k) & 1);
-    const int a = (k * n + j) * n + i;
-    e[a] = (lds_nbr(e, n, i, j, k) - r[a]) * T(1.0 / 6.0);
+    const int a = (row << l2) + i;
+    e[a] = (lds_nbr(e, n, l2, i, j, k) - r[a]) * T(1.0 / 6.0);
   }
 }
 
@@ -386,51 +403,58 @@ k_tail(int n0, int levels, int nu1, int nu2, const T* __restrict__ r0g, const T*
        T* __restrict__ e0g, T* __restrict__ e1g, const double* __restrict__ green, const Ctl* ctl) {
   if (ctl && ctl->done) return;
   extern __shared__ unsigned char smem_raw[];
+  __shared__ double G[64];
   T* base = reinterpret_cast<T*>(smem_raw);
   T* E[P3MZ_MAX_LEVELS];
   T* R[P3MZ_MAX_LEVELS];
+  int l20 = 0;
+  while ((1 << l20) < n0) l20++;
   int off = 0;
   for (int q = 0; q < levels; q++) {
-    const int nq = n0 >> q, c = nq * nq * nq;
+    const int c = 1 << (3 * (l20 - q));
     E[q] = base + off; off += c;
     R[q] = base + off; off += c;
   }
   T* rho = base + off;
   const int tid = threadIdx.x, nt = blockDim.x;
+  if (tid < 64) G[tid] = green[tid];
   {
-    const int n3 = n0 * n0 * n0;
+    const int n3 = 1 << (3 * l20), msk = n0 - 1;
     for (int p = tid; p < n3; p += nt) {
-      const int i = p % n0, j = (p / n0) % n0, k = p / (n0 * n0);
+      const int i = p & msk, j = (p >> l20) & msk, k = p >> (2 * l20);
       const T* src = ((i + j + k) & 1) ? r1g : r0g;
       R[0][p] = src[cs_idx(n0, i, j, k)];
     }
   }
   __syncthreads();
+  const T wt[3] = {T(0.25), T(0.5), T(0.25)};
   for (int q = 0; q + 1 < levels; q++) {
-    const int n = n0 >> q, n3 = n * n * n, nc = n >> 1;
-    for (int p = tid; p < n3; p += nt) E[q][p] = T(0);
+    const int l2 = l20 - q, n = 1 << l2, n3 = 1 << (3 * l2), msk = n - 1;
+    const int lc = l2 - 1, nc = n >> 1, nc3 = 1 << (3 * lc);
+    T* e = E[q];
+    const T* r = R[q];
+    for (int p = tid; p < n3; p += nt) e[p] = T(0);
     __syncthreads();
     for (int s = 0; s < nu1; s++) {
-      tail_rbgs(E[q], R[q], n, 0);
+      tail_rbgs(e, r, n, l2, 0);
       __syncthreads();
-      tail_rbgs(E[q], R[q], n, 1);
+      tail_rbgs(e, r, n, l2, 1);
       __syncthreads();
     }
     for (int p = tid; p < n3; p += nt) {
-      const int i = p % n, j = (p / n) % n, k = p / (n * n);
-      rho[p] = R[q][p] - (lds_nbr(E[q], n, i, j, k) - T(6) * E[q][p]);
+      const int i = p & msk, j = (p >> l2) & msk, k = p >> (2 * l2);
+      rho[p] = r[p] - (lds_nbr(e, n, l2, i, j, k) - T(6) * e[p]);
     }
     __syncthreads();
-    const T wt[3] = {T(0.25), T(0.5), T(0.25)};
-    for (int p = tid; p < nc * nc * nc; p += nt) {
-      const int I = p % nc, J = (p / nc) % nc, K = p / (nc * nc);
+    for (int p = tid; p < nc3; p += nt) {
+      const int I = p & (nc - 1), J = (p >> lc) & (nc - 1), K = p >> (2 * lc);
       T s = T(0);
       for (int c = -1; c <= 1; c++) {
-        const int z = (2 * K + c) & (n - 1);
+        const int z = (2 * K + c) & msk;
         for (int b = -1; b <= 1; b++) {
-          const int y = (2 * J + b) & (n - 1);
-          T row = T(0);
-          for (int a = -1; a <= 1; a++) row += wt[a + 1] * rho[(z * n + y) * n + ((2 * I + a) & (n - 1))];
+          const int y = (2 * J + b) & msk;
+          const T* rowp = rho + (((z << l2) + y) << l2);
+          const T row = wt[0] * rowp[(2 * I - 1) & msk] + wt[1] * rowp[2 * I] + wt[2] * rowp[(2 * I + 1) & msk];
           s += wt[b + 1] * wt[c + 1] * row;
         }
       }
@@ -439,47 +463,50 @@ k_tail(int n0, int levels, int nu1, int nu2, const T* __restrict__ r0g, const T*
     __syncthreads();
   }
   {
-    const int q = levels - 1;   // 4^3
+    const int q = levels - 1;   // 4^3: e = G * r, FP64 accumulation
     if (tid < 64) {
       const int x = tid & 3, y = (tid >> 2) & 3, z = tid >> 4;
       double s = 0.0;
       for (int mm = 0; mm < 64; mm++) {
         const int a = mm & 3, b = (mm >> 2) & 3, c = mm >> 4;
-        s += green[(((z - c) & 3) * 4 + ((y - b) & 3)) * 4 + ((x - a) & 3)] * (double)R[q][mm];
+        s += G[(((z - c) & 3) * 4 + ((y - b) & 3)) * 4 + ((x - a) & 3)] * (double)R[q][mm];
       }
       E[q][tid] = (T)s;
     }
     __syncthreads();
   }
   for (int q = levels - 2; q >= 0; q--) {
-    const int n = n0 >> q, n3 = n * n * n, nc = n >> 1;
+    const int l2 = l20 - q, n = 1 << l2, n3 = 1 << (3 * l2), msk = n - 1;
+    const int lc = l2 - 1, nc = n >> 1, cm = nc - 1;
+    T* e = E[q];
+    const T* ec = E[q + 1];
     for (int p = tid; p < n3; p += nt) {
-      const int x = p % n, y = (p / n) % n, z = p / (n * n);
+      const int x = p & msk, y = (p >> l2) & msk, z = p >> (2 * l2);
       const int x0 = x >> 1, y0 = y >> 1, z0 = z >> 1;
-      const int x1 = (x & 1) ? ((x0 + 1) & (nc - 1)) : x0;
-      const int y1 = (y & 1) ? ((y0 + 1) & (nc - 1)) : y0;
-      const int z1 = (z & 1) ? ((z0 + 1) & (nc - 1)) : z0;
+      const int x1 = (x & 1) ? ((x0 + 1) & cm) : x0;
+      const int y1 = (y & 1) ? ((y0 + 1) & cm) : y0;
+      const int z1 = (z & 1) ? ((z0 + 1) & cm) : z0;
       const T hx = (x & 1) ? T(0.5) : T(1), hy = (y & 1) ? T(0.5) : T(1), hz = (z & 1) ? T(0.5) : T(1);
       const int xs[2] = {x0, x1}, ys[2] = {y0, y1}, zs[2] = {z0, z1};
       const int nx = (x & 1) ? 2 : 1, ny = (y & 1) ? 2 : 1, nz = (z & 1) ? 2 : 1;
       T s = T(0);
       for (int c = 0; c < nz; c++)
         for (int b = 0; b < ny; b++)
-          for (int a = 0; a < nx; a++) s += hx * hy * hz * E[q + 1][(zs[c] * nc + ys[b]) * nc + xs[a]];
-      E[q][p] += s;
+          for (int a = 0; a < nx; a++) s += hx * hy * hz * ec[(((zs[c] << lc) + ys[b]) << lc) + xs[a]];
+      e[p] += s;
     }
     __syncthreads();
     for (int s = 0; s < nu2; s++) {
-      tail_rbgs(E[q], R[q], n, 0);
+      tail_rbgs(e, R[q], n, l2, 0);
       __syncthreads();
-      tail_rbgs(E[q], R[q], n, 1);
+      tail_rbgs(e, R[q], n, l2, 1);
       __syncthreads();
     }
   }
   {
-    const int n3 = n0 * n0 * n0;
+    const int n3 = 1 << (3 * l20), msk = n0 - 1;
     for (int p = tid; p < n3; p += nt) {
-      const int i = p % n0, j = (p / n0) % n0, k = p / (n0 * n0);
+      const int i = p & msk, j = (p >> l20) & msk, k = p >> (2 * l20);
       T* dst = ((i + j + k) & 1) ? e1g : e0g;
       dst[cs_idx(n0, i, j, k)] = E[0][p];
     }
@@ -556,41 +583,65 @@ __global__ void k_set_open(Ctl* ctl) {
 template <typename T>
 hipError_t vcycle_impl(const LevelBufs* lv, int levels, int tail, int nu1, int nu2, const double* green,
                        Ctl* ctl, hipStream_t s) {
+  const double ts = sizeof(T);
   for (int l = 0; l < tail; l++) {
     const int n = lv[l].n, half = n * n * n / 2, nb = blocks_for(half, kBlock);
+    const double n3 = (double)n * n * n;
     T *e0 = (T*)lv[l].e0, *e1 = (T*)lv[l].e1, *r0 = (T*)lv[l].r0, *r1 = (T*)lv[l].r1;
     if (nu1 >= 1) {
+      kt_begin(KT_SWEEP0, l, s);
       hipLaunchKernelGGL(k_sweep_zero<T>, dim3(nb), dim3(kBlock), 0, s, n, r0, r1, e0, e1, ctl);
+      kt_end(KT_SWEEP0, l, 2.0 * ts * n3, s);
       for (int it = 1; it < nu1; it++) {
+        kt_begin(KT_HALFSWEEP, l, s);
         hipLaunchKernelGGL(k_halfsweep<T>, dim3(nb), dim3(kBlock), 0, s, n, 0, e0, e1, r0, ctl);
+        kt_end(KT_HALFSWEEP, l, 1.5 * ts * n3, s);
+        kt_begin(KT_HALFSWEEP, l, s);
         hipLaunchKernelGGL(k_halfsweep<T>, dim3(nb), dim3(kBlock), 0, s, n, 1, e1, e0, r1, ctl);
+        kt_end(KT_HALFSWEEP, l, 1.5 * ts * n3, s);
       }
     } else {
       hipLaunchKernelGGL(k_fill_zero<T>, dim3(nb), dim3(kBlock), 0, s, (int64_t)half, e0, e1, ctl);
     }
     const int nc = n / 2;
+    kt_begin(KT_RESTRICT, l, s);
     hipLaunchKernelGGL(k_resid_restrict<T>, dim3(blocks_for(nc * nc * nc, kBlock)), dim3(kBlock), 0, s, n,
-                       e0, e1, r0, r1, (T*)lv[l + 1].r0, (T*)lv[l + 1].r1, ctl);
+                       nu1 >= 1 ? 1 : 0, e0, e1, r0, r1, (T*)lv[l + 1].r0, (T*)lv[l + 1].r1, ctl);
+    kt_end(KT_RESTRICT, l, 2.125 * ts * n3, s);
   }
   {
     const int lt = levels - tail;
+    const double nt3 = (double)lv[tail].n * lv[tail].n * lv[tail].n;
     size_t lds = tail_lds_bytes(lv[tail].n, lt, sizeof(T));
+    kt_begin(KT_TAIL, 0, s);
     hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(1024), lds, s, lv[tail].n, lt, nu1, nu2, (const T*)lv[tail].r0,
                        (const T*)lv[tail].r1, (T*)lv[tail].e0, (T*)lv[tail].e1, green, ctl);
+    kt_end(KT_TAIL, 0, 2.0 * ts * nt3, s);
   }
   for (int l = tail - 1; l >= 0; l--) {
     const int n = lv[l].n, half = n * n * n / 2, nb = blocks_for(half, kBlock);
+    const double n3 = (double)n * n * n;
     T *e0 = (T*)lv[l].e0, *e1 = (T*)lv[l].e1, *r0 = (T*)lv[l].r0, *r1 = (T*)lv[l].r1;
     const T *c0 = (const T*)lv[l + 1].e0, *c1 = (const T*)lv[l + 1].e1;
     if (nu2 >= 1) {
+      kt_begin(KT_PROLONG, l, s);
       hipLaunchKernelGGL(k_prolong_red<T>, dim3(nb), dim3(kBlock), 0, s, n, e0, e1, c0, c1, r0, ctl);
+      kt_end(KT_PROLONG, l, 1.625 * ts * n3, s);
+      kt_begin(KT_HALFSWEEP, l, s);
       hipLaunchKernelGGL(k_halfsweep<T>, dim3(nb), dim3(kBlock), 0, s, n, 1, e1, e0, r1, ctl);
+      kt_end(KT_HALFSWEEP, l, 1.5 * ts * n3, s);
       for (int it = 1; it < nu2; it++) {
+        kt_begin(KT_HALFSWEEP, l, s);
         hipLaunchKernelGGL(k_halfsweep<T>, dim3(nb), dim3(kBlock), 0, s, n, 0, e0, e1, r0, ctl);
+        kt_end(KT_HALFSWEEP, l, 1.5 * ts * n3, s);
+        kt_begin(KT_HALFSWEEP, l, s);
         hipLaunchKernelGGL(k_halfsweep<T>, dim3(nb), dim3(kBlock), 0, s, n, 1, e1, e0, r1, ctl);
+        kt_end(KT_HALFSWEEP, l, 1.5 * ts * n3, s);
       }
     } else {
+      kt_begin(KT_PROLONG, l, s);
       hipLaunchKernelGGL(k_prolong_add<T>, dim3(nb), dim3(kBlock), 0, s, n, e0, e1, c0, c1, ctl);
+      kt_end(KT_PROLONG, l, 2.125 * ts * n3, s);
     }
   }
   return hipGetLastError();
@@ -641,10 +692,11 @@ hipError_t launch_sigma(bool fp64, int n, double h, int cold, int m_eff, const v
   const int n3 = n * n * n, nb = blocks_for(n3, kBlock);
   if (fp64)
     hipLaunchKernelGGL(k_sigma<double>, dim3(nb), dim3(kBlock), 0, s, n, h, cold, m_eff, (const double*)qs, phi_k,
-                       phi_km1, yh0, yh1, yh2, sigma, y, tol, tol_mode, partial, ctl);
+                       phi_km1, yh0, yh1, yh2, sigma, y, partial);
   else
     hipLaunchKernelGGL(k_sigma<float>, dim3(nb), dim3(kBlock), 0, s, n, h, cold, m_eff, (const float*)qs, phi_k,
-                       phi_km1, yh0, yh1, yh2, sigma, y, tol, tol_mode, partial, ctl);
+                       phi_km1, yh0, yh1, yh2, sigma, y, partial);
+  hipLaunchKernelGGL(k_fin_sigma, dim3(1), dim3(kBlock), 0, s, nb, n3, tol, tol_mode, partial, ctl);
   return hipGetLastError();
 }
 
@@ -653,11 +705,12 @@ hipError_t launch_outer(bool fp64, int n, int c, int max_cycles, const double* s
                         Ctl* ctl, hipStream_t s) {
   const int n3 = n * n * n, nb = blocks_for(n3, kBlock);
   if (fp64)
-    hipLaunchKernelGGL(k_outer<double>, dim3(nb), dim3(kBlock), 0, s, n, c, max_cycles, sigma, y_in, y_out,
+    hipLaunchKernelGGL(k_outer<double>, dim3(nb), dim3(kBlock), 0, s, n, c, sigma, y_in, y_out,
                        (const double*)e0, (const double*)e1, (double*)r0, (double*)r1, partial, ctl);
   else
-    hipLaunchKernelGGL(k_outer<float>, dim3(nb), dim3(kBlock), 0, s, n, c, max_cycles, sigma, y_in, y_out,
+    hipLaunchKernelGGL(k_outer<float>, dim3(nb), dim3(kBlock), 0, s, n, c, sigma, y_in, y_out,
                        (const float*)e0, (const float*)e1, (float*)r0, (float*)r1, partial, ctl);
+  hipLaunchKernelGGL(k_fin_outer, dim3(1), dim3(kBlock), 0, s, c, max_cycles, nb, n3, partial, ctl);
   return hipGetLastError();
 }
 

@@ -198,15 +198,14 @@ k_spread(int n, int p, int ntx, const int* __restrict__ start, const int* __rest
 
 // Gather: F = -k Q sum_n W(r - r_n) (D phi)_n with the central difference D,
 // rewritten as derivative weights on a (p+2)^3 neighbourhood, and the
-// per-atom energy 1/2 k Q (W * phi)(r).  Accumulation in FP64.
+// per-atom energy 1/2 k Q (W * phi)(r).  Row sums in precision T (the
+// weights are rounded to T), accumulation over rows in FP64.
 template <typename T, typename TP>
 __global__ void __launch_bounds__(kBlock)
 k_gather(int n_atoms, int n, int p, double h, double k_e, const int* __restrict__ perm,
-         const int* __restrict__ base, const T* __restrict__ w, const double* __restrict__ qa,
-         const TP* __restrict__ phi, double* __restrict__ force, double* __restrict__ partial,
-         Ctl* ctl) {
+         const int* __restrict__ base, const double* __restrict__ w, const double* __restrict__ qa,
+         const TP* __restrict__ phi, double* __restrict__ force, double* __restrict__ partial) {
   __shared__ double sh[kBlock / 64];
-  __shared__ int flag;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   double e_atom = 0.0;
   if (t < n_atoms) {
@@ -216,9 +215,9 @@ k_gather(int n_atoms, int n, int p, double h, double k_e, const int* __restrict_
     T dx[P3MZ_MAX_ORDER + 2], dy[P3MZ_MAX_ORDER + 2], dz[P3MZ_MAX_ORDER + 2];
     const T inv2h = (T)(0.5 / h);
     for (int j = 0; j < pe; j++) {
-      wx[j] = (j >= 1 && j <= p) ? w[(3 * a) * p + j - 1] : T(0);
-      wy[j] = (j >= 1 && j <= p) ? w[(3 * a + 1) * p + j - 1] : T(0);
-      wz[j] = (j >= 1 && j <= p) ? w[(3 * a + 2) * p + j - 1] : T(0);
+      wx[j] = (j >= 1 && j <= p) ? (T)w[(3 * a) * p + j - 1] : T(0);
+      wy[j] = (j >= 1 && j <= p) ? (T)w[(3 * a + 1) * p + j - 1] : T(0);
+      wz[j] = (j >= 1 && j <= p) ? (T)w[(3 * a + 2) * p + j - 1] : T(0);
     }
     for (int j = 0; j < pe; j++) {
       // extended index j <-> stencil offset j-1; d[j] = (w[j-1] - w[j+1]) / 2h
@@ -260,31 +259,51 @@ k_gather(int n_atoms, int n, int p, double h, double k_e, const int* __restrict_
   }
   double bs = block_sum(e_atom, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = bs;
-  if (last_block_arrives(&ctl->ticket2, &flag)) {
-    double tot = reduce_partials_sum(partial, gridDim.x, sh);
-    if (threadIdx.x == 0) ctl->e_lr = tot;
+}
+
+// One workgroup: *dst = sum of the nb partials (fixed order).
+__global__ void __launch_bounds__(kBlock) k_fin_sum(int nb, const double* __restrict__ partial, double* dst) {
+  __shared__ double sh[kBlock / 64];
+  const double tot = reduce_partials_sum(partial, nb, sh);
+  if (threadIdx.x == 0) *dst = tot;
+}
+
+// One workgroup: E_sr and the energy assembly {E_sr, E_lr, E_self, E_total}.
+__global__ void __launch_bounds__(kBlock)
+k_fin_energy(int nb, const double* __restrict__ partial, Ctl* ctl, double e_self, double* energy_out) {
+  __shared__ double sh[kBlock / 64];
+  const double tot = reduce_partials_sum(partial, nb, sh);
+  if (threadIdx.x == 0) {
+    ctl->e_sr = tot;
+    if (energy_out) {
+      energy_out[0] = tot;
+      energy_out[1] = ctl->e_lr;
+      energy_out[2] = e_self;
+      energy_out[3] = tot + ctl->e_lr + e_self;
+    }
   }
 }
 
 // Short-range pairs (Eq. 20 force, Eq. 6 energy) over the cell list with the
 // minimum image; pairs inside one exclusion group instead get the Ewald
-// exclusion correction -k Q Q erf(alpha r)/r.  force += F_sr.
+// exclusion correction -k Q Q erf(alpha r)/r.  One wave per atom: lanes take
+// fixed strides of each neighbour cell's list, then a fixed shuffle tree
+// adds the lane sums (deterministic).  force += F_sr.
 __global__ void __launch_bounds__(kBlock)
 k_sr(int n_atoms, const double* __restrict__ pos, const double* __restrict__ qa, double box,
      double alpha, double rc2, double k_e, int nc, int excl_group, const int* __restrict__ cstart,
-     const int* __restrict__ cperm, double* __restrict__ force, double e_self,
-     double* __restrict__ energy_out, double* __restrict__ partial, Ctl* ctl) {
+     const int* __restrict__ cperm, double* __restrict__ force, double* __restrict__ partial) {
   __shared__ double sh[kBlock / 64];
-  __shared__ int flag;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  double en = 0.0;
-  if (t < n_atoms) {
-    const int i = cperm[t];
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  double en = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+  int i = -1;
+  if (wave < n_atoms) {
+    i = cperm[wave];
     const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
     const double qi = qa[i];
     const double inv_box = 1.0 / box;
     const double tapi = 2.0 * alpha / sqrt(M_PI);
-    double fx = 0, fy = 0, fz = 0;
     int c[3];
     const double xs[3] = {xi, yi, zi};
     for (int d = 0; d < 3; d++) {
@@ -299,12 +318,12 @@ k_sr(int n_atoms, const double* __restrict__ pos, const double* __restrict__ qa,
     for (int oz = lo; oz <= hi; oz++)
       for (int oy = lo; oy <= hi; oy++)
         for (int ox = lo; ox <= hi; ox++) {
-          int cx = span ? (c[0] + ox + nc) % nc : ox;
-          int cy = span ? (c[1] + oy + nc) % nc : oy;
-          int cz = span ? (c[2] + oz + nc) % nc : oz;
+          const int cx = span ? (c[0] + ox + nc) % nc : ox;
+          const int cy = span ? (c[1] + oy + nc) % nc : oy;
+          const int cz = span ? (c[2] + oz + nc) % nc : oz;
           const int cell = (cz * nc + cy) * nc + cx;
           const int j0 = cstart[cell], j1 = cstart[cell + 1];
-          for (int jj = j0; jj < j1; jj++) {
+          for (int jj = j0 + lane; jj < j1; jj += 64) {
             const int j = cperm[jj];
             if (j == i) continue;
             if (gi >= 0 && j / excl_group == gi) continue;
@@ -322,9 +341,9 @@ k_sr(int n_atoms, const double* __restrict__ pos, const double* __restrict__ qa,
             en += 0.5 * qq * ec / r;
           }
         }
-    if (gi >= 0) {
-      for (int j = gi * excl_group; j < gi * excl_group + excl_group && j < n_atoms; j++) {
-        if (j == i) continue;
+    if (gi >= 0 && lane < excl_group) {
+      const int j = gi * excl_group + lane;
+      if (j != i && j < n_atoms) {
         double dx = xi - pos[3 * j], dy = yi - pos[3 * j + 1], dz = zi - pos[3 * j + 2];
         dx -= box * rint(dx * inv_box);
         dy -= box * rint(dy * inv_box);
@@ -338,25 +357,24 @@ k_sr(int n_atoms, const double* __restrict__ pos, const double* __restrict__ qa,
         en += -0.5 * qq * er / r;
       }
     }
-    if (force) {
+  }
+  fx = wave_sum(fx);
+  fy = wave_sum(fy);
+  fz = wave_sum(fz);
+  en = wave_sum(en);
+  if (lane == 0) {
+    if (i >= 0 && force) {
       force[3 * i] += fx;
       force[3 * i + 1] += fy;
       force[3 * i + 2] += fz;
     }
+    sh[threadIdx.x >> 6] = en;
   }
-  double bs = block_sum(en, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = bs;
-  if (last_block_arrives(&ctl->ticket3, &flag)) {
-    double tot = reduce_partials_sum(partial, gridDim.x, sh);
-    if (threadIdx.x == 0) {
-      ctl->e_sr = tot;
-      if (energy_out) {
-        energy_out[0] = tot;
-        energy_out[1] = ctl->e_lr;
-        energy_out[2] = e_self;
-        energy_out[3] = tot + ctl->e_lr + e_self;
-      }
-    }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int k = 0; k < kBlock / 64; k++) s += sh[k];
+    partial[blockIdx.x] = s;
   }
 }
 
@@ -421,10 +439,11 @@ hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, double h, double 
   const int nb = blocks_for(n_atoms, kBlock);
   if (fp64)
     hipLaunchKernelGGL((k_gather<double, double>), dim3(nb), dim3(kBlock), 0, s, n_atoms, n, p, h, k_e,
-                       perm, base, (const double*)w, qa, (const double*)phi, force, partial, ctl);
+                       perm, base, (const double*)w, qa, (const double*)phi, force, partial);
   else
     hipLaunchKernelGGL((k_gather<float, float>), dim3(nb), dim3(kBlock), 0, s, n_atoms, n, p, h, k_e,
-                       perm, base, (const float*)w, qa, (const float*)phi, force, partial, ctl);
+                       perm, base, (const double*)w, qa, (const float*)phi, force, partial);
+  hipLaunchKernelGGL(k_fin_sum, dim3(1), dim3(kBlock), 0, s, nb, partial, &ctl->e_lr);
   return hipGetLastError();
 }
 
@@ -432,8 +451,9 @@ hipError_t launch_sr(int n_atoms, const double* pos, const double* qa, double bo
                      double r_cut, double k_e, int nc, int excl_group, const int* cstart,
                      const int* cperm, double* force, double e_self, double* energy_out,
                      double* partial, Ctl* ctl, hipStream_t s) {
-  hipLaunchKernelGGL(k_sr, dim3(blocks_for(n_atoms, kBlock)), dim3(kBlock), 0, s, n_atoms, pos, qa, box,
-                     alpha, r_cut * r_cut, k_e, nc, excl_group, cstart, cperm, force, e_self, energy_out,
-                     partial, ctl);
+  const int nb = blocks_for((int64_t)n_atoms * 64, kBlock);
+  hipLaunchKernelGGL(k_sr, dim3(nb), dim3(kBlock), 0, s, n_atoms, pos, qa, box, alpha, r_cut * r_cut, k_e, nc,
+                     excl_group, cstart, cperm, force, partial);
+  hipLaunchKernelGGL(k_fin_energy, dim3(1), dim3(kBlock), 0, s, nb, partial, ctl, e_self, energy_out);
   return hipGetLastError();
 }

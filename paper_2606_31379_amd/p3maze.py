@@ -31,7 +31,10 @@ MESH_Q, MESH_QS, MESH_SIGMA_P, MESH_Y, MESH_PHI, MESH_PHI_PREV = range(6)
 # every symbol include/p3maze.h declares
 EXPORTS = ["p3mz_create", "p3mz_compute", "p3mz_get_mesh", "p3mz_vcycle", "p3mz_get_stats",
            "p3mz_reset_history", "p3mz_save_state", "p3mz_load_state", "p3mz_md_run",
+           "p3mz_set_timing", "p3mz_set_kernel_timer", "p3mz_get_kernel_timer",
            "p3mz_destroy", "p3mz_status_string", "p3mz_last_error", "p3mz_version"]
+KERNELS = {"halfsweep": 0, "outer": 1, "smooth": 2, "restrict": 3, "prolong": 4, "sweep0": 5,
+           "tail": 6, "spread": 7, "gather": 8, "sr": 9, "sigma": 10, "phi": 11}
 
 
 class p3mz_params(C.Structure):
@@ -48,7 +51,7 @@ class p3mz_stats(C.Structure):
                 ("K", C.c_int32), ("levels", C.c_int32), ("nu_smooth", C.c_double),
                 ("thresh", C.c_double), ("norm_qs", C.c_double), ("res_hist", C.c_double * 65),
                 ("e_sr", C.c_double), ("e_lr", C.c_double), ("e_self", C.c_double),
-                ("e_total", C.c_double), ("steps", C.c_int64)]
+                ("e_total", C.c_double), ("steps", C.c_int64), ("ms_stage", C.c_double * 4)]
 
 
 class p3mz_mdterms(C.Structure):
@@ -81,6 +84,9 @@ def _load() -> C.CDLL:
         "p3mz_load_state": ([vp, vp, C.c_size_t], C.c_int),
         "p3mz_md_run": ([vp, vp, vp, vp, C.POINTER(p3mz_mdterms), C.c_double, C.c_int32, vp, vp, vp],
                         C.c_int),
+        "p3mz_set_timing": ([vp, C.c_int32], C.c_int),
+        "p3mz_set_kernel_timer": ([vp, C.c_int32], C.c_int),
+        "p3mz_get_kernel_timer": ([vp, dp, C.POINTER(C.c_int64), dp], C.c_int),
         "p3mz_destroy": ([vp], None),
         "p3mz_status_string": ([C.c_int], C.c_char_p),
         "p3mz_last_error": ([], C.c_char_p),
@@ -152,6 +158,21 @@ def p3mz_md_run(ctx: int, pos_dev: int, vel_dev: int, mass_dev: int, terms: p3mz
                 stream: int | None = None) -> int:
     return _check(lib.p3mz_md_run(ctx, pos_dev, vel_dev, mass_dev, C.byref(terms), dt, n_steps,
                                   energy_log_dev, cycles_log_dev, stream), "p3mz_md_run")
+
+
+def p3mz_set_timing(ctx: int, on: bool) -> int:
+    return _check(lib.p3mz_set_timing(ctx, int(on)), "p3mz_set_timing")
+
+
+def p3mz_set_kernel_timer(ctx: int, kernel_id: int) -> int:
+    return _check(lib.p3mz_set_kernel_timer(ctx, kernel_id), "p3mz_set_kernel_timer")
+
+
+def p3mz_get_kernel_timer(ctx: int) -> tuple[float, int, float]:
+    """(total event milliseconds, timed launches, total algorithmic bytes)."""
+    ms, n, b = C.c_double(), C.c_int64(), C.c_double()
+    _check(lib.p3mz_get_kernel_timer(ctx, C.byref(ms), C.byref(n), C.byref(b)), "p3mz_get_kernel_timer")
+    return ms.value, n.value, b.value
 
 
 def p3mz_destroy(ctx: int) -> None:

@@ -150,7 +150,9 @@ def test_predictor_ramp_and_counts(torch, pred):
 def test_positions_on_knots_boundaries_and_far_images(torch):
     L, n = 8.0, 16
     h = L / n
-    pos = np.array([[0.0, 0.0, 0.0], [L, L, L], [-L, 2 * L, 3 * h], [5 * h, 7 * h, 1e-12],
+    # exact knots, the box faces, far periodic images and sub-ulp offsets; no two
+    # atoms coincide modulo L
+    pos = np.array([[0.0, 0.0, 0.0], [L, L, L - 2 * h], [-L, 2 * L, 3 * h], [5 * h, 7 * h, 1e-12],
                     [L - 1e-13, 3.0, 4.0], [-3.7, 11.9, -0.2], [2.5, 2.5, 2.5], [6.1, 0.3, 7.7]])
     q = np.array([1.0, -1.0, 0.5, -0.5, 2.0, -2.0, 1.0, -1.0])
     s = inputs.System(pos, q, np.ones(8), np.zeros_like(pos), L, "edge")
