@@ -174,6 +174,13 @@ p3mz_status p3mz_md_run(p3mz_ctx* ctx, double* pos_dev, double* vel_dev, const d
                         const p3mz_mdterms* terms, double dt, int32_t n_steps,
                         double* energy_log_dev, int32_t* cycles_log_dev, void* stream);
 
+/* Launch mode.  By default (on = 1) each step is enqueued as three captured
+ * HIP graphs -- before the solve, one V-cycle (replayed once per cycle), after
+ * the solve -- captured on a private stream at first use and re-captured only
+ * when the caller's buffer pointers change; on = 0 launches every kernel
+ * directly.  Results are bitwise identical.  Synchronises the device. */
+p3mz_status p3mz_set_graphs(p3mz_ctx* ctx, int32_t on);
+
 /* Record HIP events between the stages of every compute (on = 1) so that
  * p3mz_stats.ms_stage holds their durations; on = 0 stops it.  Costs five
  * event records per compute. */
@@ -193,13 +200,24 @@ enum {
   P3MZ_KERNEL_SIGMA = 10, P3MZ_KERNEL_PHI = 11
 };
 /* Start timing one kernel family (kernel_id as above, -1 = off) and zero the
- * totals.  Up to 2048 launches per compute are timed. */
+ * totals.  Up to 2048 launches per compute are timed.  While a family is timed
+ * the step is launched kernel by kernel (no graphs). */
 p3mz_status p3mz_set_kernel_timer(p3mz_ctx* ctx, int32_t kernel_id);
 /* Totals since p3mz_set_kernel_timer: summed event milliseconds, number of
  * timed launches and the summed algorithmic HBM bytes of those launches
  * (the bytes the method must move per launch, independent of caching). */
 p3mz_status p3mz_get_kernel_timer(const p3mz_ctx* ctx, double* total_ms, int64_t* launches,
                                   double* total_bytes);
+
+/* Back-to-back timing of one finest-level kernel on the context's current
+ * buffers: `reps` launches between two HIP events on `stream`; *avg_ms is the
+ * mean launch duration and *bytes_per_launch its algorithmic HBM traffic.
+ * Families: HALFSWEEP, SWEEP0, RESTRICT, PROLONG, TAIL, SMOOTH (x axis).
+ * Overwrites multigrid scratch only; the potential history is untouched.
+ * Synchronises the stream.  Errors: INVALID_ARG for other families or a mesh
+ * without that kernel. */
+p3mz_status p3mz_kernel_bench(p3mz_ctx* ctx, int32_t kernel_id, int32_t reps, void* stream, double* avg_ms,
+                              double* bytes_per_launch);
 
 void p3mz_destroy(p3mz_ctx* ctx);
 const char* p3mz_status_string(p3mz_status s);

@@ -118,6 +118,19 @@ void coarse_green(double* g) {
 
 }  // namespace
 
+struct GraphSlot {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<uint64_t> key;
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    key.clear();
+  }
+};
+
 struct p3mz_ctx {
   p3mz_params P{};
   Plan pl;
@@ -140,7 +153,7 @@ struct p3mz_ctx {
   int nc = 1, ncells = 1;
   int *d_ckey = nullptr, *d_cslot = nullptr, *d_ccount = nullptr, *d_cstart = nullptr, *d_cperm_raw = nullptr,
       *d_cperm = nullptr;
-  void *d_q = nullptr, *d_qs = nullptr, *d_tmp = nullptr;
+  double *d_q = nullptr, *d_qs = nullptr, *d_tmp = nullptr;
   double* d_sigma = nullptr;
   double* d_y[2] = {nullptr, nullptr};
   double* d_phi[2] = {nullptr, nullptr};
@@ -149,20 +162,21 @@ struct p3mz_ctx {
   LevelBufs lv[P3MZ_MAX_LEVELS];
   double* d_partial = nullptr;
   Ctl* d_ctl = nullptr;
-  Ctl* h_ctl = nullptr;
+  Ctl* h_ctl = nullptr;         // pinned mirror
   double* d_energy = nullptr;   // internal energy4 when the caller passes none
-  double* d_vscratch = nullptr; // FP64 natural buffer for p3mz_vcycle
   // md
   double* d_md_force = nullptr;
   double* d_e_other = nullptr;
   bool md_have_force = false;
-  // history
-  int have_hist = 0, n_yh = 0, k_idx = 0;
-  int yh_order[3] = {0, 1, 2};   // newest first
+  // host mirror of the device history state (refreshed after every step)
+  Ctl mirror{};
   int last_cycles = 0;
-  int64_t steps = 0;
   p3mz_stats st{};
   std::vector<void*> allocs;
+  // graphs: captured on a private stream, launched on the caller's stream
+  bool use_graphs = true;
+  hipStream_t cap = nullptr;
+  GraphSlot g_pre, g_cycle, g_post, g_md_pre, g_md_post;
   // optional timing: stage events and one kernel family's per-launch events
   bool timing = false;
   hipEvent_t stage_ev[5] = {};
@@ -190,16 +204,25 @@ struct p3mz_ctx {
     *p = v;
     return P3MZ_OK;
   }
+  void drop_graphs() {
+    g_pre.reset();
+    g_cycle.reset();
+    g_post.reset();
+    g_md_pre.reset();
+    g_md_post.reset();
+  }
   ~p3mz_ctx() {
+    drop_graphs();
     for (void* v : allocs) (void)hipFree(v);
     if (h_ctl) (void)hipHostFree(h_ctl);
     for (hipEvent_t e : stage_ev)
       if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : kt_ev) (void)hipEventDestroy(e);
+    if (cap) (void)hipStreamDestroy(cap);
   }
 };
 
-// The context whose compute is being enqueued (kernel-timer hooks read it).
+// The context whose work is being enqueued (kernel-timer hooks read it).
 static p3mz_ctx* g_active = nullptr;
 
 void kt_begin(int id, int level, hipStream_t s) {
@@ -224,6 +247,12 @@ namespace {
     if (s_ != P3MZ_OK) return s_;   \
   } while (0)
 
+uint64_t bits(double v) {
+  uint64_t u;
+  memcpy(&u, &v, 8);
+  return u;
+}
+
 p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   const Plan& pl = c->pl;
   const int n = pl.n;
@@ -234,26 +263,24 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   c->nu2 = c->P.nu_post >= 0 ? c->P.nu_post : 2;
   if (c->nu1 + c->nu2 < 1) return fail(P3MZ_ERR_INVALID_ARG, "nu_pre + nu_post must be >= 1");
   P3MZ_HIP_TRY(hipGetDevice(&c->dev));
-  // charges
+  P3MZ_HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
   double e_self = 0.0;
   for (int64_t a = 0; a < c->n_atoms; a++) e_self -= c->P.coulomb_k * c->P.alpha / sqrt(kPi) * charges_host[a] * charges_host[a];
   c->e_self = e_self;
   P3MZ_TRY(c->alloc(&c->d_qa, c->n_atoms));
   P3MZ_HIP_TRY(hipMemcpy(c->d_qa, charges_host, sizeof(double) * c->n_atoms, hipMemcpyHostToDevice));
-  // smoothing taps
-  std::vector<double> taps;
-  smoothing_taps(n, pl.K, pl.nu_s, &taps, &c->half);
-  c->ntaps = (int)taps.size();
   // The charge source (weights, spread, smoothing, sigma_p) is FP64 in both
   // modes: FP32 rounding of q^s (~1e-7 relative) would exceed the residual
   // tolerance and change the V-cycle counts of the warm-started solve.
+  std::vector<double> taps;
+  smoothing_taps(n, pl.K, pl.nu_s, &taps, &c->half);
+  c->ntaps = (int)taps.size();
   P3MZ_TRY(c->allocb(&c->d_taps, taps.size() * 8));
   P3MZ_HIP_TRY(hipMemcpy(c->d_taps, taps.data(), taps.size() * 8, hipMemcpyHostToDevice));
   double g[64];
   coarse_green(g);
   P3MZ_TRY(c->alloc(&c->d_green, 64));
   P3MZ_HIP_TRY(hipMemcpy(c->d_green, g, sizeof g, hipMemcpyHostToDevice));
-  // atoms / bins
   const int64_t na = c->n_atoms;
   c->ntx = n / kTile;
   c->nbins = c->ntx * c->ntx * c->ntx;
@@ -277,11 +304,10 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   P3MZ_TRY(c->alloc(&c->d_ccount, c->ncells));
   P3MZ_TRY(c->alloc(&c->d_cstart, c->ncells + 1));
   P3MZ_HIP_TRY(hipMemset(c->d_ccount, 0, sizeof(int) * c->ncells));
-  // mesh
   const size_t n3 = (size_t)c->n3;
-  P3MZ_TRY(c->allocb(&c->d_q, n3 * 8));
-  P3MZ_TRY(c->allocb(&c->d_qs, n3 * 8));
-  P3MZ_TRY(c->allocb(&c->d_tmp, n3 * 8));
+  P3MZ_TRY(c->alloc(&c->d_q, n3));
+  P3MZ_TRY(c->alloc(&c->d_qs, n3));
+  P3MZ_TRY(c->alloc(&c->d_tmp, n3));
   P3MZ_TRY(c->alloc(&c->d_sigma, n3));
   for (int i = 0; i < 2; i++) P3MZ_TRY(c->alloc(&c->d_y[i], n3));
   for (int i = 0; i < 2; i++) {
@@ -303,9 +329,14 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   const size_t max_blocks = (std::max<size_t>(n3, (size_t)na) + 255) / 256 + 1;
   P3MZ_TRY(c->alloc(&c->d_partial, 2 * max_blocks));
   P3MZ_TRY(c->alloc(&c->d_ctl, 1));
-  P3MZ_HIP_TRY(hipMemset(c->d_ctl, 0, sizeof(Ctl)));
   P3MZ_HIP_TRY(hipHostMalloc((void**)&c->h_ctl, sizeof(Ctl), hipHostMallocDefault));
-  memset(c->h_ctl, 0, sizeof(Ctl));
+  memset(&c->mirror, 0, sizeof(Ctl));
+  c->mirror.cold = 1;
+  c->mirror.yh0 = 0;
+  c->mirror.yh1 = 1;
+  c->mirror.yh2 = 2;
+  c->mirror.predictor = c->P.predictor;
+  P3MZ_HIP_TRY(hipMemcpy(c->d_ctl, &c->mirror, sizeof(Ctl), hipMemcpyHostToDevice));
   P3MZ_TRY(c->alloc(&c->d_energy, 4));
   P3MZ_TRY(c->alloc(&c->d_md_force, 3 * na));
   P3MZ_TRY(c->alloc(&c->d_e_other, 1));
@@ -315,100 +346,78 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   return P3MZ_OK;
 }
 
-p3mz_status finish_step(p3mz_ctx* c, hipStream_t s) {
-  P3MZ_HIP_TRY(hipMemcpyAsync(c->h_ctl, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-  P3MZ_HIP_TRY(hipStreamSynchronize(s));
-  return P3MZ_OK;
+// ---------------------------------------------------------------------------
+// The step, as three launch sequences.  Each is enqueued either directly
+// (eager) or once into a captured graph that is replayed every step.
+// ---------------------------------------------------------------------------
+void stage(p3mz_ctx* c, int i, hipStream_t s) {
+  if (c->timing) (void)hipEventRecord(c->stage_ev[i], s);
 }
 
-// The step: bin + sort atoms, spread, smooth, constraint at the prediction,
-// V-cycles until the FP64 residual meets the tolerance, field update,
-// gather, short-range pairs.
-p3mz_status compute_step(p3mz_ctx* c, const double* pos, double* force, double* energy, hipStream_t s) {
+// bin + deterministic order, spread, smoothing, sigma_p and predictor, first residual
+p3mz_status enq_pre(p3mz_ctx* c, const double* pos, hipStream_t s) {
   const Plan& pl = c->pl;
   const int n = pl.n, na = (int)c->n_atoms;
-  const bool f64 = c->fp64;
   const double N3 = (double)c->n3, ts = (double)c->tsz;
-  g_active = c;
-  struct Reset { ~Reset() { g_active = nullptr; } } reset_active;
-  auto stage = [&](int i) {
-    if (c->timing) (void)hipEventRecord(c->stage_ev[i], s);
-  };
-  stage(0);
-  // 1. binning and deterministic order
+  stage(c, 0, s);
   P3MZ_HIP_TRY(launch_bin_stencil(true, na, pos, c->P.box, n, pl.p, kTile, c->ntx, c->d_base, c->d_w, c->d_key,
                                   c->d_slot, c->d_count, c->d_ctl, s));
   P3MZ_HIP_TRY(launch_scan(c->nbins, c->d_count, c->d_start, s));
   P3MZ_HIP_TRY(launch_scatter(na, c->d_key, c->d_slot, c->d_start, c->d_perm_raw, s));
   P3MZ_HIP_TRY(launch_sort_bins(c->nbins, c->d_start, c->d_perm_raw, c->d_perm, c->d_ctl, s));
-  // 2. spread and smoothing
   kt_begin(KT_SPREAD, 0, s);
   P3MZ_HIP_TRY(launch_spread(true, n, pl.p, kTile, c->ntx, c->d_start, c->d_perm, c->d_base, c->d_w, c->d_qa, c->d_q, s));
   kt_end(KT_SPREAD, 0, 8.0 * N3 + (double)na * (24.0 * pl.p + 24.0), s);
-  kt_begin(KT_SMOOTH, 0, s);
-  P3MZ_HIP_TRY(launch_smooth(true, n, 0, c->ntaps, c->half, c->d_taps, c->d_q, c->d_qs, s));
-  kt_end(KT_SMOOTH, 0, 16.0 * N3, s);
-  kt_begin(KT_SMOOTH, 0, s);
-  P3MZ_HIP_TRY(launch_smooth(true, n, 1, c->ntaps, c->half, c->d_taps, c->d_qs, c->d_tmp, s));
-  kt_end(KT_SMOOTH, 0, 16.0 * N3, s);
-  kt_begin(KT_SMOOTH, 0, s);
-  P3MZ_HIP_TRY(launch_smooth(true, n, 2, c->ntaps, c->half, c->d_taps, c->d_tmp, c->d_qs, s));
-  kt_end(KT_SMOOTH, 0, 16.0 * N3, s);
-  stage(1);
-  // 3. constraint at the Verlet prediction and multiplier predictor
-  const int cold = !c->have_hist;
-  const int m_eff = cold ? 0 : std::min(c->P.predictor, c->n_yh);
-  double* pk = c->d_phi[c->k_idx];
-  double* pkm1 = c->d_phi[1 - c->k_idx];
+  double* src[3] = {c->d_q, c->d_qs, c->d_tmp};
+  double* dst[3] = {c->d_qs, c->d_tmp, c->d_qs};
+  for (int axis = 0; axis < 3; axis++) {
+    kt_begin(KT_SMOOTH, 0, s);
+    P3MZ_HIP_TRY(launch_smooth(true, n, axis, c->ntaps, c->half, c->d_taps, src[axis], dst[axis], s));
+    kt_end(KT_SMOOTH, 0, 16.0 * N3, s);
+  }
+  stage(c, 1, s);
   kt_begin(KT_SIGMA, 0, s);
-  P3MZ_HIP_TRY(launch_sigma(true, n, pl.h, cold, m_eff, c->d_qs, pk, pkm1, c->d_yh[c->yh_order[0]],
-                            c->d_yh[c->yh_order[1]], c->d_yh[c->yh_order[2]], c->d_sigma, c->d_y[0], c->P.tol,
-                            c->P.tol_mode, c->d_partial, c->d_ctl, s));
-  kt_end(KT_SIGMA, 0, (cold ? 24.0 : 40.0 + 8.0 * m_eff) * N3, s);
-  // 4. V-cycles; the host enqueues the expected number of cycles, then
-  // checks the device flag and continues one cycle at a time if needed.
+  P3MZ_HIP_TRY(launch_sigma(n, pl.h, c->d_qs, c->d_phi[0], c->d_phi[1], c->d_yh[0], c->d_yh[1], c->d_yh[2],
+                            c->d_sigma, c->d_y[0], c->P.tol, c->P.tol_mode, c->d_partial, c->d_ctl, s));
+  kt_end(KT_SIGMA, 0, 64.0 * N3, s);
   const LevelBufs& f = c->lv[0];
   kt_begin(KT_OUTER, 0, s);
-  P3MZ_HIP_TRY(launch_outer(f64, n, 0, c->P.max_cycles, c->d_sigma, c->d_y[0], c->d_y[0], f.e0, f.e1, f.r0, f.r1,
+  P3MZ_HIP_TRY(launch_outer(c->fp64, n, 1, c->P.max_cycles, c->d_sigma, c->d_y[0], c->d_y[1], f.e0, f.e1, f.r0, f.r1,
                             c->d_partial, c->d_ctl, s));
   kt_end(KT_OUTER, 0, (16.0 + ts) * N3, s);
-  int cyc = 1;
-  int batch = std::max(1, c->last_cycles);
-  while (cyc <= c->P.max_cycles) {
-    for (int b = 0; b < batch && cyc <= c->P.max_cycles; b++, cyc++) {
-      P3MZ_HIP_TRY(launch_vcycle(f64, c->lv, pl.levels, pl.tail, c->nu1, c->nu2, c->d_green, c->d_ctl, s));
-      kt_begin(KT_OUTER, 0, s);
-      P3MZ_HIP_TRY(launch_outer(f64, n, cyc, c->P.max_cycles, c->d_sigma, c->d_y[(cyc - 1) & 1], c->d_y[cyc & 1],
-                                f.e0, f.e1, f.r0, f.r1, c->d_partial, c->d_ctl, s));
-      kt_end(KT_OUTER, 0, (24.0 + 2.0 * ts) * N3, s);
-    }
-    if (cyc > c->P.max_cycles) break;
-    P3MZ_HIP_TRY(hipMemcpyAsync(&c->h_ctl->done, &c->d_ctl->done, sizeof(int), hipMemcpyDeviceToHost, s));
-    P3MZ_HIP_TRY(hipStreamSynchronize(s));
-    if (c->h_ctl->done) break;
-    batch = 1;
-  }
-  // 5. field update and history
+  return P3MZ_OK;
+}
+
+// one V-cycle and the following outer residual
+p3mz_status enq_cycle(p3mz_ctx* c, hipStream_t s) {
+  const Plan& pl = c->pl;
+  const LevelBufs& f = c->lv[0];
+  const double N3 = (double)c->n3, ts = (double)c->tsz;
+  P3MZ_HIP_TRY(launch_vcycle(c->fp64, c->lv, pl.levels, pl.tail, c->nu1, c->nu2, c->d_green, c->d_ctl, s));
+  kt_begin(KT_OUTER, 0, s);
+  P3MZ_HIP_TRY(launch_outer(c->fp64, pl.n, 0, c->P.max_cycles, c->d_sigma, c->d_y[0], c->d_y[1], f.e0, f.e1, f.r0,
+                            f.r1, c->d_partial, c->d_ctl, s));
+  kt_end(KT_OUTER, 0, (24.0 + 2.0 * ts) * N3, s);
+  return P3MZ_OK;
+}
+
+// field update, gather on the new potential, short-range pairs, energies,
+// history rotation
+p3mz_status enq_post(p3mz_ctx* c, const double* pos, double* force, double* energy, hipStream_t s) {
+  const Plan& pl = c->pl;
+  const int n = pl.n, na = (int)c->n_atoms;
+  const double N3 = (double)c->n3;
   kt_begin(KT_PHI, 0, s);
-  if (cold) {
-    P3MZ_HIP_TRY(launch_phi_update(n, pl.h, 1, pk, pkm1, c->d_y[0], c->d_y[1], pk, pkm1, nullptr, c->d_phi32,
-                                   c->d_ctl, s));
-  } else {
-    const int slot = c->yh_order[2];
-    P3MZ_HIP_TRY(launch_phi_update(n, pl.h, 0, pk, pkm1, c->d_y[0], c->d_y[1], pkm1, nullptr, c->d_yh[slot],
-                                   c->d_phi32, c->d_ctl, s));
-  }
-  kt_end(KT_PHI, 0, (cold ? 16.0 : 40.0) * N3 + (f64 ? 0.0 : 4.0 * N3), s);
-  stage(2);
-  // 6. gather on the new potential, short-range pairs, energies
-  const double* phi_new = cold ? pk : pkm1;
-  const void* phi_read = f64 ? (const void*)phi_new : (const void*)c->d_phi32;
+  P3MZ_HIP_TRY(launch_phi_update(n, pl.h, c->d_phi[0], c->d_phi[1], c->d_y[0], c->d_y[1], c->d_yh[0], c->d_yh[1],
+                                 c->d_yh[2], c->d_phi32, c->d_ctl, s));
+  kt_end(KT_PHI, 0, 40.0 * N3 + (c->fp64 ? 0.0 : 4.0 * N3), s);
+  stage(c, 2, s);
   kt_begin(KT_GATHER, 0, s);
-  P3MZ_HIP_TRY(launch_gather(f64, na, n, pl.p, pl.h, c->P.coulomb_k, c->d_perm, c->d_base, c->d_w, c->d_qa, phi_read,
-                             force, c->d_partial, c->d_ctl, s));
+  P3MZ_HIP_TRY(launch_gather(c->fp64, na, n, pl.p, pl.h, c->P.coulomb_k, c->d_perm, c->d_base, c->d_w, c->d_qa,
+                             c->d_phi[0], c->d_phi[1], c->d_phi32, force, c->d_partial, c->d_ctl, s));
   const double pe = pl.p + 2.0;
-  kt_end(KT_GATHER, 0, (double)na * (48.0 + 24.0 * pl.p + pe * pe * pe * (f64 ? 8.0 : 4.0)), s);
-  stage(3);
+  kt_end(KT_GATHER, 0, (double)na * (48.0 + 24.0 * pl.p + pe * pe * pe * (c->fp64 ? 8.0 : 4.0)), s);
+  stage(c, 3, s);
   P3MZ_HIP_TRY(launch_bin_cells(na, pos, c->P.box, c->nc, c->d_ckey, c->d_cslot, c->d_ccount, c->d_ctl, s));
   P3MZ_HIP_TRY(launch_scan(c->ncells, c->d_ccount, c->d_cstart, s));
   P3MZ_HIP_TRY(launch_scatter(na, c->d_ckey, c->d_cslot, c->d_cstart, c->d_cperm_raw, s));
@@ -418,12 +427,136 @@ p3mz_status compute_step(p3mz_ctx* c, const double* pos, double* force, double* 
                          c->d_cstart, c->d_cperm, force, c->e_self, energy ? energy : c->d_energy,
                          c->d_partial, c->d_ctl, s));
   kt_end(KT_SR, 0, (double)na * 56.0, s);
-  stage(4);
-  P3MZ_TRY(finish_step(c, s));
+  stage(c, 4, s);
+  P3MZ_HIP_TRY(launch_advance(c->d_ctl, s));
+  return P3MZ_OK;
+}
+
+struct MdArgs {
+  double *pos, *vel, *elog;
+  const double* mass;
+  int* clog;
+  double dt, f2a, mv2e, p[6];
+  int model;
+};
+
+p3mz_status enq_md_pre(p3mz_ctx* c, const MdArgs& m, hipStream_t s) {
+  P3MZ_HIP_TRY(launch_kick_drift((int)c->n_atoms, m.pos, m.vel, c->d_md_force, m.mass, m.dt, m.f2a, 1, s));
+  return enq_pre(c, m.pos, s);
+}
+
+p3mz_status enq_md_post(p3mz_ctx* c, const MdArgs& m, hipStream_t s) {
+  const int na = (int)c->n_atoms;
+  P3MZ_TRY(enq_post(c, m.pos, c->d_md_force, c->d_energy, s));
+  // the cell list of the short-range pass is still valid for these positions
+  P3MZ_HIP_TRY(launch_nonelec(na, m.pos, c->P.box, c->P.r_cut, m.model, m.p[0], m.p[1], m.p[2], m.p[3], m.p[4],
+                              m.p[5], c->nc, c->d_cstart, c->d_cperm, c->d_md_force, c->d_partial, c->d_e_other, s));
+  P3MZ_HIP_TRY(launch_kick_drift(na, m.pos, m.vel, c->d_md_force, m.mass, m.dt, m.f2a, 0, s));
+  P3MZ_HIP_TRY(launch_kinetic_log(na, m.vel, m.mass, m.mv2e, c->d_energy, c->d_e_other, m.elog, m.clog, c->d_ctl,
+                                  c->d_partial, s));
+  return P3MZ_OK;
+}
+
+// Enqueue `body` on s: eagerly, or through the graph in `slot` (captured on
+// the private stream when the key changes).  A failed capture switches the
+// context to eager launches for good.
+template <typename F>
+p3mz_status run_seq(p3mz_ctx* c, GraphSlot& slot, const std::vector<uint64_t>& key, hipStream_t s, F body) {
+  if (!c->use_graphs || c->kt_id >= 0) return body(s);
+  if (!slot.exec || slot.key != key) {
+    slot.reset();
+    P3MZ_HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    p3mz_status st = body(c->cap);
+    hipError_t e = hipStreamEndCapture(c->cap, &slot.graph);
+    if (st != P3MZ_OK || e != hipSuccess) {
+      slot.reset();
+      (void)hipGetLastError();
+      c->use_graphs = false;
+      return body(s);
+    }
+    e = hipGraphInstantiate(&slot.exec, slot.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      slot.reset();
+      (void)hipGetLastError();
+      c->use_graphs = false;
+      return body(s);
+    }
+    slot.key = key;
+  }
+  P3MZ_HIP_TRY(hipGraphLaunch(slot.exec, s));
+  return P3MZ_OK;
+}
+
+// Copies the head of the control block (done, cycles, status, final_buf,
+// nan_flag) to the pinned mirror and waits for it.
+p3mz_status read_head(p3mz_ctx* c, hipStream_t s) {
+  P3MZ_HIP_TRY(hipMemcpyAsync(c->h_ctl, c->d_ctl, 5 * sizeof(int), hipMemcpyDeviceToHost, s));
+  P3MZ_HIP_TRY(hipStreamSynchronize(s));
+  return P3MZ_OK;
+}
+
+// V-cycles: the expected number (the last step's count) is enqueued at
+// once, then the device flag is checked and cycles follow one at a time.
+// Returns the head of the control block after the solve.
+p3mz_status run_solve(p3mz_ctx* c, hipStream_t s) {
+  int issued = 0;
+  int batch = std::max(1, c->last_cycles);
+  const std::vector<uint64_t> key = {1};
+  while (issued < c->P.max_cycles) {
+    for (int b = 0; b < batch && issued < c->P.max_cycles; b++, issued++)
+      P3MZ_TRY(run_seq(c, c->g_cycle, key, s, [&](hipStream_t q) { return enq_cycle(c, q); }));
+    P3MZ_TRY(read_head(c, s));
+    if (c->h_ctl->done || c->h_ctl->nan_flag) return P3MZ_OK;
+    batch = 1;
+  }
+  return read_head(c, s);
+}
+
+p3mz_status on_nan(p3mz_ctx* c) {
+  // drop the history: the next step is a cold solve
+  P3MZ_HIP_TRY(hipMemcpy(&c->mirror, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+  c->mirror.nan_flag = 0;
+  c->mirror.cold = 1;
+  c->mirror.n_yh = 0;
+  c->mirror.m_eff = 0;
+  P3MZ_HIP_TRY(hipMemcpy(c->d_ctl, &c->mirror, sizeof(Ctl), hipMemcpyHostToDevice));
+  c->last_cycles = 0;
+  c->md_have_force = false;
+  return fail(P3MZ_ERR_NAN, "non-finite position");
+}
+
+// After the post sequence: read the whole control block and fill the stats.
+p3mz_status finish(p3mz_ctx* c, hipStream_t s) {
+  P3MZ_HIP_TRY(hipMemcpyAsync(c->h_ctl, c->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  P3MZ_HIP_TRY(hipStreamSynchronize(s));
+  const Ctl& h = *c->h_ctl;
+  const int was_cold = c->mirror.cold, m_eff = c->mirror.m_eff;
+  c->mirror = h;
+  c->last_cycles = h.cycles;
+  p3mz_stats& st = c->st;
+  st.status = h.status ? P3MZ_WARN_NOT_CONVERGED : P3MZ_OK;
+  st.cycles = h.cycles;
+  st.cold = was_cold;
+  st.m_eff = m_eff;
+  st.nu_pre = c->nu1;
+  st.nu_post = c->nu2;
+  st.K = c->pl.K;
+  st.levels = c->pl.levels;
+  st.nu_smooth = c->pl.nu_s;
+  st.thresh = h.thresh;
+  st.norm_qs = h.norm_qs;
+  for (int i = 0; i <= P3MZ_MAX_CYCLES; i++) st.res_hist[i] = i <= h.cycles ? h.res_hist[i] : 0.0;
+  st.e_sr = h.e_sr;
+  st.e_lr = h.e_lr;
+  st.e_self = c->e_self;
+  st.e_total = h.e_sr + h.e_lr + c->e_self;
+  st.steps = h.steps;
   if (c->timing) {
-    float ms[4];
-    for (int i = 0; i < 4; i++) P3MZ_HIP_TRY(hipEventElapsedTime(&ms[i], c->stage_ev[i], c->stage_ev[i + 1]));
-    for (int i = 0; i < 4; i++) c->st.ms_stage[i] = ms[i];
+    for (int i = 0; i < 4; i++) {
+      float ms = 0.f;
+      P3MZ_HIP_TRY(hipEventElapsedTime(&ms, c->stage_ev[i], c->stage_ev[i + 1]));
+      st.ms_stage[i] = ms;
+    }
   }
   for (int i = 0; i + 1 < c->kt_used; i += 2) {
     float ms = 0.f;
@@ -433,46 +566,24 @@ p3mz_status compute_step(p3mz_ctx* c, const double* pos, double* force, double* 
     c->kt_launches++;
   }
   c->kt_used = 0;
-  const Ctl& h = *c->h_ctl;
-  if (h.nan_flag) {
-    P3MZ_HIP_TRY(hipMemsetAsync(&c->d_ctl->nan_flag, 0, sizeof(int), s));
-    c->have_hist = 0;
-    c->n_yh = 0;
-    return fail(P3MZ_ERR_NAN, "non-finite position");
-  }
-  // history bookkeeping (mirrors the device writes above)
-  if (cold) {
-    c->n_yh = 0;
-  } else {
-    c->k_idx = 1 - c->k_idx;
-    const int slot = c->yh_order[2];
-    c->yh_order[2] = c->yh_order[1];
-    c->yh_order[1] = c->yh_order[0];
-    c->yh_order[0] = slot;
-    c->n_yh = std::min(3, c->n_yh + 1);
-  }
-  c->have_hist = 1;
-  c->last_cycles = h.cycles;
-  c->steps++;
-  p3mz_stats& st = c->st;
-  st.status = h.status ? P3MZ_WARN_NOT_CONVERGED : P3MZ_OK;
-  st.cycles = h.cycles;
-  st.cold = cold;
-  st.m_eff = m_eff;
-  st.nu_pre = c->nu1;
-  st.nu_post = c->nu2;
-  st.K = pl.K;
-  st.levels = pl.levels;
-  st.nu_smooth = pl.nu_s;
-  st.thresh = h.thresh;
-  st.norm_qs = h.norm_qs;
-  for (int i = 0; i <= P3MZ_MAX_CYCLES; i++) st.res_hist[i] = i <= h.cycles ? h.res_hist[i] : 0.0;
-  st.e_sr = h.e_sr;
-  st.e_lr = h.e_lr;
-  st.e_self = c->e_self;
-  st.e_total = h.e_sr + h.e_lr + c->e_self;
-  st.steps = c->steps;
-  if (h.status) {
+  return P3MZ_OK;
+}
+
+struct ActiveGuard {
+  explicit ActiveGuard(p3mz_ctx* c) { g_active = c; }
+  ~ActiveGuard() { g_active = nullptr; }
+};
+
+p3mz_status compute_step(p3mz_ctx* c, const double* pos, double* force, double* energy, hipStream_t s) {
+  ActiveGuard guard(c);
+  const uint64_t tm = c->timing;
+  P3MZ_TRY(run_seq(c, c->g_pre, {(uint64_t)(uintptr_t)pos, tm}, s, [&](hipStream_t q) { return enq_pre(c, pos, q); }));
+  P3MZ_TRY(run_solve(c, s));
+  if (c->h_ctl->nan_flag) return on_nan(c);
+  P3MZ_TRY(run_seq(c, c->g_post, {(uint64_t)(uintptr_t)pos, (uint64_t)(uintptr_t)force, (uint64_t)(uintptr_t)energy, tm},
+                   s, [&](hipStream_t q) { return enq_post(c, pos, force, energy, q); }));
+  P3MZ_TRY(finish(c, s));
+  if (c->st.status) {
     g_last_error = "V-cycle cap reached before the tolerance";
     return P3MZ_WARN_NOT_CONVERGED;
   }
@@ -513,6 +624,7 @@ p3mz_status p3mz_create(const p3mz_params* params, int64_t n_atoms, const double
 
 p3mz_status p3mz_compute(p3mz_ctx* ctx, const double* pos_dev, double* force_dev, double* energy_dev, void* stream) {
   if (!ctx || !pos_dev) return fail(P3MZ_ERR_INVALID_ARG, "ctx or pos_dev is NULL");
+  ctx->md_have_force = false;
   return compute_step(ctx, pos_dev, force_dev, energy_dev, (hipStream_t)stream);
 }
 
@@ -520,23 +632,21 @@ p3mz_status p3mz_get_mesh(p3mz_ctx* ctx, int32_t which, double* out_dev, void* s
   if (!ctx || !out_dev) return fail(P3MZ_ERR_INVALID_ARG, "ctx or out_dev is NULL");
   hipStream_t s = (hipStream_t)stream;
   const size_t n3 = (size_t)ctx->n3;
+  const Ctl& m = ctx->mirror;
   switch (which) {
-    case 0: P3MZ_HIP_TRY(launch_widen(true, n3, ctx->d_q, out_dev, s)); break;
-    case 1: P3MZ_HIP_TRY(launch_widen(true, n3, ctx->d_qs, out_dev, s)); break;
-    case 2: {
-      // zero-mean sigma_p = stored sigma - mean (mean kept in the control block)
-      P3MZ_HIP_TRY(launch_sub_scalar(n3, ctx->d_sigma, out_dev, &ctx->d_ctl->mean_sigma, s));
-      break;
-    }
+    case 0: P3MZ_HIP_TRY(hipMemcpyAsync(out_dev, ctx->d_q, n3 * 8, hipMemcpyDeviceToDevice, s)); break;
+    case 1: P3MZ_HIP_TRY(hipMemcpyAsync(out_dev, ctx->d_qs, n3 * 8, hipMemcpyDeviceToDevice, s)); break;
+    case 2: P3MZ_HIP_TRY(launch_sub_scalar(n3, ctx->d_sigma, out_dev, &ctx->d_ctl->mean_sigma, s)); break;
     case 3: {
-      // the final multiplier after the zero-mean projection is the newest history slot
-      // on warm steps; on cold steps it is not stored, so it is rebuilt from phi.
+      // the final multiplier after the zero-mean projection is the newest
+      // stored one after a warm step; a cold solve stores none
       if (ctx->st.cold) return fail(P3MZ_ERR_STATE, "multiplier of a cold solve is not kept");
-      P3MZ_HIP_TRY(hipMemcpyAsync(out_dev, ctx->d_yh[ctx->yh_order[0]], n3 * 8, hipMemcpyDeviceToDevice, s));
+      const int slot = m.yh0;
+      P3MZ_HIP_TRY(hipMemcpyAsync(out_dev, ctx->d_yh[slot], n3 * 8, hipMemcpyDeviceToDevice, s));
       break;
     }
-    case 4: P3MZ_HIP_TRY(hipMemcpyAsync(out_dev, ctx->d_phi[ctx->k_idx], n3 * 8, hipMemcpyDeviceToDevice, s)); break;
-    case 5: P3MZ_HIP_TRY(hipMemcpyAsync(out_dev, ctx->d_phi[1 - ctx->k_idx], n3 * 8, hipMemcpyDeviceToDevice, s)); break;
+    case 4: P3MZ_HIP_TRY(hipMemcpyAsync(out_dev, ctx->d_phi[m.k_idx], n3 * 8, hipMemcpyDeviceToDevice, s)); break;
+    case 5: P3MZ_HIP_TRY(hipMemcpyAsync(out_dev, ctx->d_phi[1 - m.k_idx], n3 * 8, hipMemcpyDeviceToDevice, s)); break;
     default: return fail(P3MZ_ERR_INVALID_ARG, "unknown mesh id");
   }
   return P3MZ_OK;
@@ -562,16 +672,20 @@ p3mz_status p3mz_get_stats(const p3mz_ctx* ctx, p3mz_stats* out) {
 
 p3mz_status p3mz_reset_history(p3mz_ctx* ctx) {
   if (!ctx) return fail(P3MZ_ERR_INVALID_ARG, "ctx is NULL");
-  ctx->have_hist = 0;
-  ctx->n_yh = 0;
+  P3MZ_HIP_TRY(hipDeviceSynchronize());
+  P3MZ_HIP_TRY(hipMemcpy(&ctx->mirror, ctx->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+  ctx->mirror.cold = 1;
+  ctx->mirror.n_yh = 0;
+  ctx->mirror.m_eff = 0;
+  P3MZ_HIP_TRY(hipMemcpy(ctx->d_ctl, &ctx->mirror, sizeof(Ctl), hipMemcpyHostToDevice));
   ctx->last_cycles = 0;
   ctx->md_have_force = false;
   return P3MZ_OK;
 }
 
-// blob: magic, n, precision, have_hist, n_yh, steps, last_cycles, then
+// blob: magic, n, precision, cold, n_yh, steps, last_cycles, then
 // phi^k, phi^{k-1}, y^k, y^{k-1}, y^{k-2} (FP64, natural layout).
-static const int64_t kMagic = 0x50334d5a53543031LL;   // "P3MZST01"
+static const int64_t kMagic = 0x50334d5a53543032LL;   // "P3MZST02"
 
 p3mz_status p3mz_save_state(const p3mz_ctx* ctx, void* host_buf, size_t* bytes) {
   if (!ctx || !bytes) return fail(P3MZ_ERR_INVALID_ARG, "NULL argument");
@@ -582,13 +696,15 @@ p3mz_status p3mz_save_state(const p3mz_ctx* ctx, void* host_buf, size_t* bytes) 
     return P3MZ_OK;
   }
   if (*bytes < need) return fail(P3MZ_ERR_INVALID_ARG, "buffer too small");
-  int64_t hdr[7] = {kMagic, ctx->pl.n, ctx->P.precision, ctx->have_hist, ctx->n_yh, ctx->steps, ctx->last_cycles};
+  P3MZ_HIP_TRY(hipDeviceSynchronize());
+  Ctl m;
+  P3MZ_HIP_TRY(hipMemcpy(&m, ctx->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+  int64_t hdr[7] = {kMagic, ctx->pl.n, ctx->P.precision, m.cold, m.n_yh, m.steps, ctx->last_cycles};
   char* b = (char*)host_buf;
   memcpy(b, hdr, sizeof hdr);
   b += sizeof hdr;
-  const double* arr[5] = {ctx->d_phi[ctx->k_idx], ctx->d_phi[1 - ctx->k_idx], ctx->d_yh[ctx->yh_order[0]],
-                          ctx->d_yh[ctx->yh_order[1]], ctx->d_yh[ctx->yh_order[2]]};
-  P3MZ_HIP_TRY(hipDeviceSynchronize());
+  const double* arr[5] = {ctx->d_phi[m.k_idx], ctx->d_phi[1 - m.k_idx], ctx->d_yh[m.yh0], ctx->d_yh[m.yh1],
+                          ctx->d_yh[m.yh2]};
   for (int i = 0; i < 5; i++) {
     P3MZ_HIP_TRY(hipMemcpy(b, arr[i], n3 * 8, hipMemcpyDeviceToHost));
     b += n3 * 8;
@@ -606,21 +722,27 @@ p3mz_status p3mz_load_state(p3mz_ctx* ctx, const void* host_buf, size_t bytes) {
   const char* b = (const char*)host_buf;
   memcpy(hdr, b, sizeof hdr);
   b += sizeof hdr;
-  if (hdr[0] != kMagic || hdr[1] != ctx->pl.n || hdr[2] != ctx->P.precision || hdr[4] < 0 || hdr[4] > 3)
+  if (hdr[0] != kMagic || hdr[1] != ctx->pl.n || hdr[2] != ctx->P.precision || hdr[4] < 0 || hdr[4] > 3 ||
+      hdr[3] < 0 || hdr[3] > 1)
     return fail(P3MZ_ERR_STATE, "state blob does not match this context");
-  ctx->k_idx = 0;
-  ctx->yh_order[0] = 0;
-  ctx->yh_order[1] = 1;
-  ctx->yh_order[2] = 2;
-  double* arr[5] = {ctx->d_phi[0], ctx->d_phi[1], ctx->d_yh[0], ctx->d_yh[1], ctx->d_yh[2]};
   P3MZ_HIP_TRY(hipDeviceSynchronize());
+  double* arr[5] = {ctx->d_phi[0], ctx->d_phi[1], ctx->d_yh[0], ctx->d_yh[1], ctx->d_yh[2]};
   for (int i = 0; i < 5; i++) {
     P3MZ_HIP_TRY(hipMemcpy(arr[i], b, n3 * 8, hipMemcpyHostToDevice));
     b += n3 * 8;
   }
-  ctx->have_hist = (int)hdr[3];
-  ctx->n_yh = (int)hdr[4];
-  ctx->steps = hdr[5];
+  P3MZ_HIP_TRY(hipMemcpy(&ctx->mirror, ctx->d_ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+  Ctl& m = ctx->mirror;
+  m.cold = (int)hdr[3];
+  m.n_yh = (int)hdr[4];
+  m.steps = hdr[5];
+  m.k_idx = 0;
+  m.yh0 = 0;
+  m.yh1 = 1;
+  m.yh2 = 2;
+  m.m_eff = m.cold ? 0 : std::min(ctx->P.predictor, m.n_yh);
+  m.nan_flag = 0;
+  P3MZ_HIP_TRY(hipMemcpy(ctx->d_ctl, &m, sizeof(Ctl), hipMemcpyHostToDevice));
   ctx->last_cycles = (int)hdr[6];
   ctx->md_have_force = false;
   return P3MZ_OK;
@@ -635,42 +757,59 @@ p3mz_status p3mz_md_run(p3mz_ctx* ctx, double* pos_dev, double* vel_dev, const d
   if (terms->model == 2 && ctx->n_atoms % 3 != 0)
     return fail(P3MZ_ERR_INVALID_ARG, "the water model needs O,H,H triples");
   hipStream_t s = (hipStream_t)stream;
-  const int na = (int)ctx->n_atoms;
-  double p[6] = {0, 0, 0, 0, 0, 0};
+  ActiveGuard guard(ctx);
+  MdArgs m{};
+  m.pos = pos_dev;
+  m.vel = vel_dev;
+  m.mass = mass_dev;
+  m.elog = energy_log_dev;
+  m.clog = cycles_log_dev;
+  m.dt = dt;
+  m.f2a = terms->force_to_acc;
+  m.mv2e = terms->mv2_to_energy;
+  m.model = terms->model;
   if (terms->model == 1) {
-    p[0] = terms->bm_a;
-    p[1] = terms->bm_rho;
+    m.p[0] = terms->bm_a;
+    m.p[1] = terms->bm_rho;
   } else if (terms->model == 2) {
-    p[0] = terms->lj_eps; p[1] = terms->lj_sigma; p[2] = terms->k_bond; p[3] = terms->r0;
-    p[4] = terms->k_angle; p[5] = terms->theta0;
+    m.p[0] = terms->lj_eps; m.p[1] = terms->lj_sigma; m.p[2] = terms->k_bond; m.p[3] = terms->r0;
+    m.p[4] = terms->k_angle; m.p[5] = terms->theta0;
   }
-  auto forces = [&](double* e4) -> p3mz_status {
-    p3mz_status st = compute_step(ctx, pos_dev, ctx->d_md_force, e4, s);
-    if (st < 0) return st;
-    // the cell list of the short-range pass is still valid for these positions
-    hipError_t e = launch_nonelec(na, pos_dev, ctx->P.box, ctx->P.r_cut, terms->model, p[0], p[1], p[2], p[3], p[4],
-                                  p[5], ctx->nc, ctx->d_cstart, ctx->d_cperm, ctx->d_md_force, ctx->d_partial,
-                                  ctx->d_e_other, s);
-    if (e != hipSuccess) return hip_fail(e, "launch_nonelec", __FILE__, __LINE__);
-    return st;
-  };
-  p3mz_status worst = P3MZ_OK;
+  const uint64_t tm = ctx->timing;
+  std::vector<uint64_t> key_pre = {(uint64_t)(uintptr_t)pos_dev, (uint64_t)(uintptr_t)vel_dev,
+                                   (uint64_t)(uintptr_t)mass_dev, bits(dt), bits(m.f2a), tm};
+  std::vector<uint64_t> key_post = key_pre;
+  key_post.push_back((uint64_t)(uintptr_t)energy_log_dev);
+  key_post.push_back((uint64_t)(uintptr_t)cycles_log_dev);
+  key_post.push_back((uint64_t)m.model);
+  key_post.push_back(bits(m.mv2e));
+  for (double v : m.p) key_post.push_back(bits(v));
+  P3MZ_HIP_TRY(hipMemsetAsync(&ctx->d_ctl->md_step, 0, sizeof(int), s));   // eager, never captured
   if (!ctx->md_have_force) {
-    p3mz_status st = forces(ctx->d_energy);
-    if (st < 0) return st;
+    // forces at the initial positions (a cold solve on first use)
+    P3MZ_TRY(run_seq(ctx, ctx->g_pre, {(uint64_t)(uintptr_t)pos_dev, tm}, s,
+                     [&](hipStream_t q) { return enq_pre(ctx, pos_dev, q); }));
+    P3MZ_TRY(run_solve(ctx, s));
+    if (ctx->h_ctl->nan_flag) return on_nan(ctx);
+    P3MZ_TRY(run_seq(ctx, ctx->g_post, {(uint64_t)(uintptr_t)pos_dev, (uint64_t)(uintptr_t)ctx->d_md_force,
+                                        (uint64_t)(uintptr_t)ctx->d_energy, tm},
+                     s, [&](hipStream_t q) { return enq_post(ctx, pos_dev, ctx->d_md_force, ctx->d_energy, q); }));
+    P3MZ_HIP_TRY(launch_nonelec((int)ctx->n_atoms, pos_dev, ctx->P.box, ctx->P.r_cut, m.model, m.p[0], m.p[1], m.p[2],
+                                m.p[3], m.p[4], m.p[5], ctx->nc, ctx->d_cstart, ctx->d_cperm, ctx->d_md_force,
+                                ctx->d_partial, ctx->d_e_other, s));
+    P3MZ_TRY(finish(ctx, s));
     ctx->md_have_force = true;
   }
+  p3mz_status worst = P3MZ_OK;
   for (int step = 0; step < n_steps; step++) {
-    P3MZ_HIP_TRY(launch_kick_drift(na, pos_dev, vel_dev, ctx->d_md_force, mass_dev, dt, terms->force_to_acc, 1, s));
-    p3mz_status st = forces(ctx->d_energy);
-    if (st < 0) return st;
-    if (st > worst) worst = st;
-    P3MZ_HIP_TRY(launch_kick_drift(na, pos_dev, vel_dev, ctx->d_md_force, mass_dev, dt, terms->force_to_acc, 0, s));
-    P3MZ_HIP_TRY(launch_kinetic_log(na, vel_dev, mass_dev, terms->mv2_to_energy, ctx->d_energy, ctx->d_e_other,
-                                    energy_log_dev ? energy_log_dev + 6 * (size_t)step : nullptr,
-                                    cycles_log_dev ? cycles_log_dev + step : nullptr, ctx->d_ctl, ctx->d_partial, s));
+    P3MZ_TRY(run_seq(ctx, ctx->g_md_pre, key_pre, s, [&](hipStream_t q) { return enq_md_pre(ctx, m, q); }));
+    P3MZ_TRY(run_solve(ctx, s));
+    if (ctx->h_ctl->nan_flag) return on_nan(ctx);
+    if (ctx->h_ctl->status) worst = P3MZ_WARN_NOT_CONVERGED;
+    ctx->last_cycles = ctx->h_ctl->cycles;
+    P3MZ_TRY(run_seq(ctx, ctx->g_md_post, key_post, s, [&](hipStream_t q) { return enq_md_post(ctx, m, q); }));
   }
-  P3MZ_HIP_TRY(hipStreamSynchronize(s));
+  P3MZ_TRY(finish(ctx, s));
   return worst;
 }
 
@@ -680,6 +819,14 @@ p3mz_status p3mz_set_timing(p3mz_ctx* ctx, int32_t on) {
     for (hipEvent_t& e : ctx->stage_ev) P3MZ_HIP_TRY(hipEventCreate(&e));
   ctx->timing = on != 0;
   for (double& v : ctx->st.ms_stage) v = 0.0;
+  return P3MZ_OK;
+}
+
+p3mz_status p3mz_set_graphs(p3mz_ctx* ctx, int32_t on) {
+  if (!ctx) return fail(P3MZ_ERR_INVALID_ARG, "ctx is NULL");
+  P3MZ_HIP_TRY(hipDeviceSynchronize());
+  ctx->drop_graphs();
+  ctx->use_graphs = on != 0;
   return P3MZ_OK;
 }
 
@@ -707,6 +854,40 @@ p3mz_status p3mz_get_kernel_timer(const p3mz_ctx* ctx, double* total_ms, int64_t
   return P3MZ_OK;
 }
 
+p3mz_status p3mz_kernel_bench(p3mz_ctx* ctx, int32_t kernel_id, int32_t reps, void* stream, double* avg_ms,
+                              double* bytes_per_launch) {
+  if (!ctx || !avg_ms || !bytes_per_launch || reps < 1) return fail(P3MZ_ERR_INVALID_ARG, "bad kernel_bench arguments");
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  P3MZ_HIP_TRY(hipEventCreate(&e0));
+  P3MZ_HIP_TRY(hipEventCreate(&e1));
+  double bytes = 0.0;
+  p3mz_status st = P3MZ_OK;
+  P3MZ_HIP_TRY(launch_set_ctl_open(ctx->d_ctl, s));
+  P3MZ_HIP_TRY(hipEventRecord(e0, s));
+  for (int r = 0; r < reps && st == P3MZ_OK; r++) {
+    hipError_t e;
+    if (kernel_id == KT_SMOOTH) {
+      e = launch_smooth(true, ctx->pl.n, 0, ctx->ntaps, ctx->half, ctx->d_taps, ctx->d_q, ctx->d_tmp, s);
+      bytes = 16.0 * (double)ctx->n3;
+    } else {
+      e = launch_vcycle_kernel(ctx->fp64, kernel_id, ctx->lv, ctx->pl.levels, ctx->pl.tail, ctx->nu1, ctx->nu2,
+                               ctx->d_green, ctx->d_ctl, s, &bytes);
+    }
+    if (e != hipSuccess) st = fail(P3MZ_ERR_INVALID_ARG, "kernel not available for timing on this mesh");
+  }
+  P3MZ_HIP_TRY(hipEventRecord(e1, s));
+  P3MZ_HIP_TRY(hipEventSynchronize(e1));
+  float ms = 0.f;
+  P3MZ_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  // the control block now says "open"; the next compute resets it anyway
+  *avg_ms = ms / reps;
+  *bytes_per_launch = bytes;
+  return st;
+}
+
 void p3mz_destroy(p3mz_ctx* ctx) {
   if (!ctx) return;
   (void)hipDeviceSynchronize();
@@ -731,6 +912,6 @@ const char* p3mz_status_string(p3mz_status s) {
 
 const char* p3mz_last_error(void) { return g_last_error.c_str(); }
 
-const char* p3mz_version(void) { return "p3maze-gfx950 0.1"; }
+const char* p3mz_version(void) { return "p3maze-gfx950 0.2"; }
 
 }  // extern "C"

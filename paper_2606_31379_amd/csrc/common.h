@@ -10,21 +10,32 @@
 #define P3MZ_TAIL_MAX 16        // levels of at most 16^3 run in one LDS-resident workgroup
 #define P3MZ_WAVE 64
 
-// Device-side control block of one mesh step.  Kernels of the V-cycle read
-// `done` first and return at once when the solve has converged, so a fixed
-// launch sequence can hold more cycles than the step needs.
+// Device-side control block.  Kernels of the V-cycle read `done` first and
+// return at once when the solve has converged, so a fixed launch sequence
+// (or a replayed graph) can hold more cycles than a step needs.  The cycle
+// index and the rotation of the potential/multiplier history also live here,
+// so captured graphs never need new kernel arguments.
 struct Ctl {
+  // solve state of the current step (read back by the host after the solve)
   int done;              // 1: converged or cycle cap reached
   int cycles;            // V-cycles applied this step
   int status;            // 0 ok, 1 cycle cap reached
   int final_buf;         // which y ping-pong buffer holds the final multiplier
-  int nan_flag;          // non-finite position seen by the binning kernel
-  int pad_;
+  int nan_flag;          // non-finite position seen by a binning kernel
+  // history: advanced on the device at the end of every step
+  int cold;              // this step starts from a zero potential
+  int m_eff;             // predictor order of this step
+  int n_yh;              // stored warm multipliers (0..3)
+  int k_idx;             // phi buffer holding phi^k
+  int yh0, yh1, yh2;     // multiplier buffers, newest first
+  int predictor;         // requested predictor order
+  int md_step;           // row of the MD energy log
+  int pad0, pad1;
+  long long steps;       // completed steps
   double thresh;         // residual threshold
   double norm_qs;        // max |q^s|
   double mean_sigma;     // mean of the unprojected sigma_p
-  double mean_y;         // mean of the final multiplier
-  double sum_y;          // running sum of the current multiplier (per outer kernel)
+  double mean_y;         // mean of the current multiplier
   double e_lr, e_sr;
   double res_hist[P3MZ_MAX_CYCLES + 1];
 };

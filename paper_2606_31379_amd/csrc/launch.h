@@ -37,9 +37,12 @@ hipError_t launch_spread(bool fp64, int n, int p, int tile, int ntx, const int* 
                          const int* base, const void* w, const double* qa, void* q, hipStream_t s);
 // Long-range force and energy by interpolating the central-difference
 // gradient of phi (precision of phi: fp64 or float).
+// phi: FP64 mode reads the new potential from phi0/phi1 (selected on the
+// device), mixed mode reads the FP32 copy phi32.
 hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, double h, double k_e, const int* perm,
-                         const int* base, const void* w, const double* qa, const void* phi,
-                         double* force, double* partial, Ctl* ctl, hipStream_t s);
+                         const int* base, const void* w, const double* qa, const double* phi0,
+                         const double* phi1, const float* phi32, double* force, double* partial, Ctl* ctl,
+                         hipStream_t s);
 // Short-range erfc pairs on the cell list, exclusion correction, energy
 // assembly into energy_out[4] (may be NULL).  force += F_sr.
 hipError_t launch_sr(int n_atoms, const double* pos, const double* qa, double box, double alpha,
@@ -51,17 +54,19 @@ hipError_t launch_sr(int n_atoms, const double* pos, const double* qa, double bo
 // Folded periodic smoothing filter along one axis: out = sum_m c[m] v[i+m-K].
 hipError_t launch_smooth(bool fp64, int n, int axis, int ntaps, int half, const void* taps,
                          const void* in, void* out, hipStream_t s);
-// sigma_p = (h/4pi) M (2 phi_k - phi_km1) + q^s (cold: q^s), predictor y0 into y,
-// last block: mean of sigma_p, max|q^s|, threshold, resets the step's control.
-hipError_t launch_sigma(bool fp64, int n, double h, int cold, int m_eff, const void* qs,
-                        const double* phi_k, const double* phi_km1, const double* yh0,
-                        const double* yh1, const double* yh2, double* sigma, double* y,
+// sigma_p = (h/4pi) M (2 phi^k - phi^{k-1}) + q^s (cold: q^s) and the
+// multiplier predictor into y; a one-workgroup pass then forms the mean of
+// sigma_p, max|q^s| and the threshold and opens the solve.  History buffers
+// are selected on the device from the control block.
+hipError_t launch_sigma(int n, double h, const double* qs, const double* phi0, const double* phi1,
+                        const double* yb0, const double* yb1, const double* yb2, double* sigma, double* y,
                         double tol, int tol_mode, double* partial, Ctl* ctl, hipStream_t s);
-// Outer residual of cycle c: y_out = y_in + e (c > 0), r = sigma - mean - M y_out,
-// r written colour-split in T; last block records res_hist[c] and the stop decision.
-hipError_t launch_outer(bool fp64, int n, int c, int max_cycles, const double* sigma,
-                        const double* y_in, double* y_out, const void* e0, const void* e1,
-                        void* r0, void* r1, double* partial, Ctl* ctl, hipStream_t s);
+// Outer residual: cycle c = 0 (first) or the device's next cycle: y_out =
+// y_in + e (c > 0), r = sigma - mean - M y_out written colour-split in T; the
+// finalize pass records res_hist[c] and the stop decision.
+hipError_t launch_outer(bool fp64, int n, int first, int max_cycles, const double* sigma, double* ya,
+                        double* yb, const void* e0, const void* e1, void* r0, void* r1, double* partial,
+                        Ctl* ctl, hipStream_t s);
 struct LevelBufs {
   int n;
   void* e0; void* e1;   // colour-split correction
@@ -71,10 +76,17 @@ struct LevelBufs {
 // levels from `tail` on run in one LDS-resident workgroup.
 hipError_t launch_vcycle(bool fp64, const LevelBufs* lv, int levels, int tail, int nu1, int nu2,
                          const double* green, Ctl* ctl, hipStream_t s);
-// phi update and history push: phi_out = phi_p - (4pi/h)(y - mean y).
-hipError_t launch_phi_update(int n, double h, int cold, const double* phi_k, const double* phi_km1,
-                             const double* ya, const double* yb, double* phi_out, double* phi_copy,
-                             double* y_hist_out, float* phi32, Ctl* ctl, hipStream_t s);
+// One finest-level launch of a V-cycle kernel family (KT_HALFSWEEP, KT_SWEEP0,
+// KT_RESTRICT, KT_PROLONG, KT_TAIL) on the current buffers; *bytes = its
+// algorithmic traffic.
+hipError_t launch_vcycle_kernel(bool fp64, int kid, const LevelBufs* lv, int levels, int tail, int nu1, int nu2,
+                                const double* green, Ctl* ctl, hipStream_t s, double* bytes);
+// phi update and history push: phi^{k+1} = phi_p - (4pi/h)(y - mean y);
+// buffers selected on the device.
+hipError_t launch_phi_update(int n, double h, double* phi0, double* phi1, const double* ya, const double* yb,
+                             double* yh0, double* yh1, double* yh2, float* phi32, Ctl* ctl, hipStream_t s);
+// End-of-step rotation of the history on the device.
+hipError_t launch_advance(Ctl* ctl, hipStream_t s);
 // Layout conversions for inspection and the stand-alone V-cycle.
 hipError_t launch_widen(bool fp64, int64_t count, const void* in, double* out, hipStream_t s);
 hipError_t launch_cs_to_nat(bool fp64, int n, const void* c0, const void* c1, double* out, hipStream_t s);
@@ -91,6 +103,7 @@ hipError_t launch_nonelec(int n_atoms, const double* pos, double box, double r_c
                           double p0, double p1, double p2, double p3, double p4, double p5,
                           int nc, const int* cstart, const int* cperm, double* force,
                           double* partial, double* e_out, hipStream_t s);
+// Kinetic energy and one row (ctl->md_step, then advanced) of the logs.
 hipError_t launch_kinetic_log(int n_atoms, const double* vel, const double* mass, double mv2e,
-                              const double* energy4, const double* e_other, double* log_row,
-                              int* cycles_row, const Ctl* ctl, double* partial, hipStream_t s);
+                              const double* energy4, const double* e_other, double* log_base,
+                              int* clog_base, Ctl* ctl, double* partial, hipStream_t s);

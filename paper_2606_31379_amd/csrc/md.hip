@@ -161,17 +161,21 @@ k_kinetic(int n_atoms, const double* __restrict__ vel, const double* __restrict_
   if (threadIdx.x == 0) partial[blockIdx.x] = bs;
 }
 
+// Log row ctl->md_step of the energy/cycle logs, then advance the row.
 __global__ void __launch_bounds__(kBlock)
 k_fin_log(int nb, const double* __restrict__ partial, const double* __restrict__ e4,
-          const double* __restrict__ e_other, double* row, int* crow, const Ctl* ctl) {
+          const double* __restrict__ e_other, double* log_base, int* clog_base, Ctl* ctl) {
   __shared__ double sh[kBlock / 64];
   const double tot = reduce_partials_sum(partial, nb, sh);
   if (threadIdx.x == 0) {
-    if (row) {
+    const int k = ctl->md_step;
+    if (log_base) {
+      double* row = log_base + 6 * (size_t)k;
       row[0] = e4[0]; row[1] = e4[1]; row[2] = e4[2]; row[3] = *e_other; row[4] = tot;
       row[5] = e4[3] + *e_other + tot;
     }
-    if (crow) *crow = ctl->cycles;
+    if (clog_base) clog_base[k] = ctl->cycles;
+    ctl->md_step = k + 1;
   }
 }
 
@@ -195,10 +199,10 @@ hipError_t launch_nonelec(int n_atoms, const double* pos, double box, double r_c
 }
 
 hipError_t launch_kinetic_log(int n_atoms, const double* vel, const double* mass, double mv2e,
-                              const double* energy4, const double* e_other, double* log_row, int* cycles_row,
-                              const Ctl* ctl, double* partial, hipStream_t s) {
+                              const double* energy4, const double* e_other, double* log_base, int* clog_base,
+                              Ctl* ctl, double* partial, hipStream_t s) {
   const int nb = blocks_for(n_atoms, kBlock);
   hipLaunchKernelGGL(k_kinetic, dim3(nb), dim3(kBlock), 0, s, n_atoms, vel, mass, mv2e, partial);
-  hipLaunchKernelGGL(k_fin_log, dim3(1), dim3(kBlock), 0, s, nb, partial, energy4, e_other, log_row, cycles_row, ctl);
+  hipLaunchKernelGGL(k_fin_log, dim3(1), dim3(kBlock), 0, s, nb, partial, energy4, e_other, log_base, clog_base, ctl);
   return hipGetLastError();
 }

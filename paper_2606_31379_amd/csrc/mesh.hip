@@ -75,13 +75,20 @@ k_smooth(int n, int ntaps, int half, const T* __restrict__ taps, const T* __rest
 // ---------------------------------------------------------------------------
 template <typename TQ>
 __global__ void __launch_bounds__(kBlock)
-k_sigma(int n, double h, int cold, int m_eff, const TQ* __restrict__ qs, const double* __restrict__ pk,
-        const double* __restrict__ pkm1, const double* __restrict__ y0, const double* __restrict__ y1,
-        const double* __restrict__ y2, double* __restrict__ sigma, double* __restrict__ y,
-        double* __restrict__ partial) {
+k_sigma(int n, double h, const TQ* __restrict__ qs, const double* __restrict__ phi0,
+        const double* __restrict__ phi1, const double* __restrict__ yb0, const double* __restrict__ yb1,
+        const double* __restrict__ yb2, double* __restrict__ sigma, double* __restrict__ y,
+        double* __restrict__ partial, const Ctl* ctl) {
   __shared__ double sh[kBlock / 64];
   const int n3 = n * n * n;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int cold = ctl->cold, m_eff = ctl->m_eff;
+  const double* pk = ctl->k_idx ? phi1 : phi0;
+  const double* pkm1 = ctl->k_idx ? phi0 : phi1;
+  const double* const yb[3] = {yb0, yb1, yb2};
+  const double* y0 = yb[ctl->yh0];
+  const double* y1 = yb[ctl->yh1];
+  const double* y2 = yb[ctl->yh2];
   double sv = 0.0, qmax = 0.0;
   if (t < n3) {
     const int i = t % n, j = (t / n) % n, k = t / (n * n);
@@ -139,11 +146,14 @@ k_fin_sigma(int nb, int n3, double tol, int tol_mode, const double* __restrict__
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_outer(int n, int c, const double* __restrict__ sigma, const double* __restrict__ y_in,
-        double* __restrict__ y_out, const T* __restrict__ e0, const T* __restrict__ e1,
+k_outer(int n, int first, const double* __restrict__ sigma, double* __restrict__ ya,
+        double* __restrict__ yb, const T* __restrict__ e0, const T* __restrict__ e1,
         T* __restrict__ r0, T* __restrict__ r1, double* __restrict__ partial, const Ctl* ctl) {
   __shared__ double sh[kBlock / 64];
   if (ctl->done) return;
+  const int c = first ? 0 : ctl->cycles + 1;
+  const double* y_in = (c == 0 || ((c - 1) & 1) == 0) ? ya : yb;
+  double* y_out = (c & 1) ? yb : ya;
   const int n3 = n * n * n;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   double rmax = 0.0, ysum = 0.0;
@@ -178,9 +188,10 @@ k_outer(int n, int c, const double* __restrict__ sigma, const double* __restrict
 
 // One workgroup: residual of cycle c, running mean of y, stop decision.
 __global__ void __launch_bounds__(kBlock)
-k_fin_outer(int c, int max_cycles, int nb, int n3, const double* __restrict__ partial, Ctl* ctl) {
+k_fin_outer(int first, int max_cycles, int nb, int n3, const double* __restrict__ partial, Ctl* ctl) {
   __shared__ double sh[kBlock / 64];
   if (ctl->done) return;
+  const int c = first ? 0 : ctl->cycles + 1;
   const double res = reduce_partials_max(partial, nb, sh);
   const double ys = reduce_partials_sum(partial + nb, nb, sh);
   if (threadIdx.x == 0) {
@@ -220,8 +231,11 @@ __device__ __forceinline__ void decode_half(int t, int n, int* m, int* j, int* k
   *k = row / n;
 }
 
+// Kernels below carry a FIN template flag that is 1 only on the finest level,
+// so profiles report the finest-level instances under their own names.
+
 // First pre-smoothing sweep from e = 0: red = -r/6, then black from those reds.
-template <typename T>
+template <typename T, int FIN>
 __global__ void __launch_bounds__(kBlock)
 k_sweep_zero(int n, const T* __restrict__ r0, const T* __restrict__ r1, T* __restrict__ e0,
              T* __restrict__ e1, const Ctl* ctl) {
@@ -241,7 +255,7 @@ k_sweep_zero(int n, const T* __restrict__ r0, const T* __restrict__ r1, T* __res
   e1[t] = (nb - r1[t]) * sixth;
 }
 
-template <typename T>
+template <typename T, int FIN>
 __global__ void __launch_bounds__(kBlock)
 k_halfsweep(int n, int colour, T* __restrict__ ec, const T* __restrict__ eo, const T* __restrict__ rc,
             const Ctl* ctl) {
@@ -266,7 +280,7 @@ __device__ __forceinline__ T cs_load(const T* __restrict__ c0, const T* __restri
 // When the last pre-smoothing operation was a black half-sweep, the black
 // residuals are zero up to rounding (Gauss-Seidel just solved those rows), so
 // only the 13 red points of the 27-point stencil are evaluated (red_only).
-template <typename T>
+template <typename T, int FIN>
 __global__ void __launch_bounds__(kBlock)
 k_resid_restrict(int n, int red_only, const T* __restrict__ e0, const T* __restrict__ e1,
                  const T* __restrict__ r0, const T* __restrict__ r1, T* __restrict__ rc0, T* __restrict__ rc1,
@@ -321,7 +335,7 @@ __device__ __forceinline__ T prolong_at(const T* __restrict__ c0, const T* __res
 // After prolongation the next red half-sweep overwrites every red value and
 // only reads corrected black neighbours, so the correction of black points is
 // applied on the fly here and the red values are written directly.
-template <typename T>
+template <typename T, int FIN>
 __global__ void __launch_bounds__(kBlock)
 k_prolong_red(int n, T* __restrict__ e0, const T* __restrict__ e1, const T* __restrict__ ec0,
               const T* __restrict__ ec1, const T* __restrict__ r0, const Ctl* ctl) {
@@ -529,20 +543,46 @@ size_t tail_lds_bytes(int n0, int levels, size_t elem) {
 // multiplier is pushed into the history on warm steps.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock)
-k_phi_update(int n3, double h, int cold, const double* pk, const double* pkm1,
-             const double* __restrict__ ya, const double* __restrict__ yb, double* phi_out,
-             double* __restrict__ phi_copy, double* __restrict__ yh_out, float* __restrict__ phi32,
-             const Ctl* ctl) {
+k_phi_update(int n3, double h, double* __restrict__ phi0, double* __restrict__ phi1,
+             const double* __restrict__ ya, const double* __restrict__ yb, double* __restrict__ yh0,
+             double* __restrict__ yh1, double* __restrict__ yh2, float* __restrict__ phi32, const Ctl* ctl) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n3) return;
+  const int cold = ctl->cold;
+  double* pk = ctl->k_idx ? phi1 : phi0;
+  double* pkm1 = ctl->k_idx ? phi0 : phi1;
   const double* ysrc = ctl->final_buf ? yb : ya;
   const double y = ysrc[t] - ctl->mean_y;
   const double phi_p = cold ? 0.0 : 2.0 * pk[t] - pkm1[t];
   const double phi = phi_p - 4.0 * kPi / h * y;
-  phi_out[t] = phi;
-  if (phi_copy) phi_copy[t] = phi;
-  if (yh_out) yh_out[t] = y;
+  if (cold) {
+    pk[t] = phi;
+    pkm1[t] = phi;
+  } else {
+    pkm1[t] = phi;   // becomes phi^k after the rotation
+    double* const yh[3] = {yh0, yh1, yh2};
+    yh[ctl->yh2][t] = y;   // the oldest slot becomes the newest multiplier
+  }
   if (phi32) phi32[t] = (float)phi;
+}
+
+// End of a step: rotate the potential and multiplier history (cold solves
+// store no multiplier) and ramp the predictor order with the stored history.
+__global__ void k_advance(Ctl* ctl) {
+  if (threadIdx.x != 0) return;
+  if (ctl->cold) {
+    ctl->n_yh = 0;
+  } else {
+    ctl->k_idx = 1 - ctl->k_idx;
+    const int newest = ctl->yh2;
+    ctl->yh2 = ctl->yh1;
+    ctl->yh1 = ctl->yh0;
+    ctl->yh0 = newest;
+    ctl->n_yh = ctl->n_yh < 3 ? ctl->n_yh + 1 : 3;
+  }
+  ctl->cold = 0;
+  ctl->m_eff = ctl->predictor < ctl->n_yh ? ctl->predictor : ctl->n_yh;
+  ctl->steps += 1;
 }
 
 template <typename T>
@@ -580,6 +620,27 @@ __global__ void k_set_open(Ctl* ctl) {
   ctl->status = 0;
 }
 
+template <typename T, int FIN>
+void launch_sweep0(int n, int nb, T* r0, T* r1, T* e0, T* e1, Ctl* ctl, hipStream_t s) {
+  hipLaunchKernelGGL((k_sweep_zero<T, FIN>), dim3(nb), dim3(kBlock), 0, s, n, r0, r1, e0, e1, ctl);
+}
+template <typename T, int FIN>
+void launch_half(int n, int nb, int colour, T* ec, const T* eo, const T* rc, Ctl* ctl, hipStream_t s) {
+  hipLaunchKernelGGL((k_halfsweep<T, FIN>), dim3(nb), dim3(kBlock), 0, s, n, colour, ec, eo, rc, ctl);
+}
+template <typename T, int FIN>
+void launch_restrict(int n, int red_only, const T* e0, const T* e1, const T* r0, const T* r1, T* rc0, T* rc1,
+                     Ctl* ctl, hipStream_t s) {
+  const int nc = n / 2;
+  hipLaunchKernelGGL((k_resid_restrict<T, FIN>), dim3(blocks_for(nc * nc * nc, kBlock)), dim3(kBlock), 0, s, n,
+                     red_only, e0, e1, r0, r1, rc0, rc1, ctl);
+}
+template <typename T, int FIN>
+void launch_prolong_red(int n, int nb, T* e0, const T* e1, const T* c0, const T* c1, const T* r0, Ctl* ctl,
+                        hipStream_t s) {
+  hipLaunchKernelGGL((k_prolong_red<T, FIN>), dim3(nb), dim3(kBlock), 0, s, n, e0, e1, c0, c1, r0, ctl);
+}
+
 template <typename T>
 hipError_t vcycle_impl(const LevelBufs* lv, int levels, int tail, int nu1, int nu2, const double* green,
                        Ctl* ctl, hipStream_t s) {
@@ -590,23 +651,27 @@ hipError_t vcycle_impl(const LevelBufs* lv, int levels, int tail, int nu1, int n
     T *e0 = (T*)lv[l].e0, *e1 = (T*)lv[l].e1, *r0 = (T*)lv[l].r0, *r1 = (T*)lv[l].r1;
     if (nu1 >= 1) {
       kt_begin(KT_SWEEP0, l, s);
-      hipLaunchKernelGGL(k_sweep_zero<T>, dim3(nb), dim3(kBlock), 0, s, n, r0, r1, e0, e1, ctl);
+      if (l == 0) launch_sweep0<T, 1>(n, nb, r0, r1, e0, e1, ctl, s);
+      else launch_sweep0<T, 0>(n, nb, r0, r1, e0, e1, ctl, s);
       kt_end(KT_SWEEP0, l, 2.0 * ts * n3, s);
       for (int it = 1; it < nu1; it++) {
-        kt_begin(KT_HALFSWEEP, l, s);
-        hipLaunchKernelGGL(k_halfsweep<T>, dim3(nb), dim3(kBlock), 0, s, n, 0, e0, e1, r0, ctl);
-        kt_end(KT_HALFSWEEP, l, 1.5 * ts * n3, s);
-        kt_begin(KT_HALFSWEEP, l, s);
-        hipLaunchKernelGGL(k_halfsweep<T>, dim3(nb), dim3(kBlock), 0, s, n, 1, e1, e0, r1, ctl);
-        kt_end(KT_HALFSWEEP, l, 1.5 * ts * n3, s);
+        for (int colour = 0; colour < 2; colour++) {
+          T* ec = colour ? e1 : e0;
+          const T* eo = colour ? e0 : e1;
+          const T* rc = colour ? r1 : r0;
+          kt_begin(KT_HALFSWEEP, l, s);
+          if (l == 0) launch_half<T, 1>(n, nb, colour, ec, eo, rc, ctl, s);
+          else launch_half<T, 0>(n, nb, colour, ec, eo, rc, ctl, s);
+          kt_end(KT_HALFSWEEP, l, 1.5 * ts * n3, s);
+        }
       }
     } else {
       hipLaunchKernelGGL(k_fill_zero<T>, dim3(nb), dim3(kBlock), 0, s, (int64_t)half, e0, e1, ctl);
     }
-    const int nc = n / 2;
     kt_begin(KT_RESTRICT, l, s);
-    hipLaunchKernelGGL(k_resid_restrict<T>, dim3(blocks_for(nc * nc * nc, kBlock)), dim3(kBlock), 0, s, n,
-                       nu1 >= 1 ? 1 : 0, e0, e1, r0, r1, (T*)lv[l + 1].r0, (T*)lv[l + 1].r1, ctl);
+    T *c0 = (T*)lv[l + 1].r0, *c1 = (T*)lv[l + 1].r1;
+    if (l == 0) launch_restrict<T, 1>(n, nu1 >= 1, e0, e1, r0, r1, c0, c1, ctl, s);
+    else launch_restrict<T, 0>(n, nu1 >= 1, e0, e1, r0, r1, c0, c1, ctl, s);
     kt_end(KT_RESTRICT, l, 2.125 * ts * n3, s);
   }
   {
@@ -625,24 +690,71 @@ hipError_t vcycle_impl(const LevelBufs* lv, int levels, int tail, int nu1, int n
     const T *c0 = (const T*)lv[l + 1].e0, *c1 = (const T*)lv[l + 1].e1;
     if (nu2 >= 1) {
       kt_begin(KT_PROLONG, l, s);
-      hipLaunchKernelGGL(k_prolong_red<T>, dim3(nb), dim3(kBlock), 0, s, n, e0, e1, c0, c1, r0, ctl);
+      if (l == 0) launch_prolong_red<T, 1>(n, nb, e0, e1, c0, c1, r0, ctl, s);
+      else launch_prolong_red<T, 0>(n, nb, e0, e1, c0, c1, r0, ctl, s);
       kt_end(KT_PROLONG, l, 1.625 * ts * n3, s);
       kt_begin(KT_HALFSWEEP, l, s);
-      hipLaunchKernelGGL(k_halfsweep<T>, dim3(nb), dim3(kBlock), 0, s, n, 1, e1, e0, r1, ctl);
+      if (l == 0) launch_half<T, 1>(n, nb, 1, e1, e0, r1, ctl, s);
+      else launch_half<T, 0>(n, nb, 1, e1, e0, r1, ctl, s);
       kt_end(KT_HALFSWEEP, l, 1.5 * ts * n3, s);
       for (int it = 1; it < nu2; it++) {
-        kt_begin(KT_HALFSWEEP, l, s);
-        hipLaunchKernelGGL(k_halfsweep<T>, dim3(nb), dim3(kBlock), 0, s, n, 0, e0, e1, r0, ctl);
-        kt_end(KT_HALFSWEEP, l, 1.5 * ts * n3, s);
-        kt_begin(KT_HALFSWEEP, l, s);
-        hipLaunchKernelGGL(k_halfsweep<T>, dim3(nb), dim3(kBlock), 0, s, n, 1, e1, e0, r1, ctl);
-        kt_end(KT_HALFSWEEP, l, 1.5 * ts * n3, s);
+        for (int colour = 0; colour < 2; colour++) {
+          T* ec = colour ? e1 : e0;
+          const T* eo = colour ? e0 : e1;
+          const T* rc = colour ? r1 : r0;
+          kt_begin(KT_HALFSWEEP, l, s);
+          if (l == 0) launch_half<T, 1>(n, nb, colour, ec, eo, rc, ctl, s);
+          else launch_half<T, 0>(n, nb, colour, ec, eo, rc, ctl, s);
+          kt_end(KT_HALFSWEEP, l, 1.5 * ts * n3, s);
+        }
       }
     } else {
       kt_begin(KT_PROLONG, l, s);
       hipLaunchKernelGGL(k_prolong_add<T>, dim3(nb), dim3(kBlock), 0, s, n, e0, e1, c0, c1, ctl);
       kt_end(KT_PROLONG, l, 2.125 * ts * n3, s);
     }
+  }
+  return hipGetLastError();
+}
+
+// One launch of a finest-level V-cycle kernel family on the current buffers
+// (for back-to-back timing); returns its algorithmic bytes.
+template <typename T>
+hipError_t one_kernel(int kid, const LevelBufs* lv, int levels, int tail, int nu1, int nu2, const double* green,
+                      Ctl* ctl, hipStream_t s, double* bytes) {
+  const int n = lv[0].n, half = n * n * n / 2, nb = blocks_for(half, kBlock);
+  const double n3 = (double)n * n * n, ts = sizeof(T);
+  T *e0 = (T*)lv[0].e0, *e1 = (T*)lv[0].e1, *r0 = (T*)lv[0].r0, *r1 = (T*)lv[0].r1;
+  switch (kid) {
+    case KT_HALFSWEEP:
+      launch_half<T, 1>(n, nb, 0, e0, e1, r0, ctl, s);
+      *bytes = 1.5 * ts * n3;
+      break;
+    case KT_SWEEP0:
+      launch_sweep0<T, 1>(n, nb, r0, r1, e0, e1, ctl, s);
+      *bytes = 2.0 * ts * n3;
+      break;
+    case KT_RESTRICT:
+      if (tail == 0) return hipErrorInvalidValue;
+      launch_restrict<T, 1>(n, nu1 >= 1, e0, e1, r0, r1, (T*)lv[1].r0, (T*)lv[1].r1, ctl, s);
+      *bytes = 2.125 * ts * n3;
+      break;
+    case KT_PROLONG:
+      if (tail == 0) return hipErrorInvalidValue;
+      launch_prolong_red<T, 1>(n, nb, e0, e1, (const T*)lv[1].e0, (const T*)lv[1].e1, r0, ctl, s);
+      *bytes = 1.625 * ts * n3;
+      break;
+    case KT_TAIL: {
+      const int lt = levels - tail;
+      const double nt3 = (double)lv[tail].n * lv[tail].n * lv[tail].n;
+      hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(1024), tail_lds_bytes(lv[tail].n, lt, sizeof(T)), s, lv[tail].n, lt,
+                         nu1, nu2, (const T*)lv[tail].r0, (const T*)lv[tail].r1, (T*)lv[tail].e0, (T*)lv[tail].e1,
+                         green, ctl);
+      *bytes = 2.0 * ts * nt3;
+      break;
+    }
+    default:
+      return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
@@ -685,32 +797,27 @@ hipError_t launch_smooth(bool fp64, int n, int axis, int ntaps, int half, const 
   return hipGetLastError();
 }
 
-hipError_t launch_sigma(bool fp64, int n, double h, int cold, int m_eff, const void* qs, const double* phi_k,
-                        const double* phi_km1, const double* yh0, const double* yh1, const double* yh2,
-                        double* sigma, double* y, double tol, int tol_mode, double* partial, Ctl* ctl,
-                        hipStream_t s) {
+hipError_t launch_sigma(int n, double h, const double* qs, const double* phi0, const double* phi1,
+                        const double* yb0, const double* yb1, const double* yb2, double* sigma, double* y,
+                        double tol, int tol_mode, double* partial, Ctl* ctl, hipStream_t s) {
   const int n3 = n * n * n, nb = blocks_for(n3, kBlock);
-  if (fp64)
-    hipLaunchKernelGGL(k_sigma<double>, dim3(nb), dim3(kBlock), 0, s, n, h, cold, m_eff, (const double*)qs, phi_k,
-                       phi_km1, yh0, yh1, yh2, sigma, y, partial);
-  else
-    hipLaunchKernelGGL(k_sigma<float>, dim3(nb), dim3(kBlock), 0, s, n, h, cold, m_eff, (const float*)qs, phi_k,
-                       phi_km1, yh0, yh1, yh2, sigma, y, partial);
+  hipLaunchKernelGGL(k_sigma<double>, dim3(nb), dim3(kBlock), 0, s, n, h, qs, phi0, phi1, yb0, yb1, yb2, sigma, y,
+                     partial, ctl);
   hipLaunchKernelGGL(k_fin_sigma, dim3(1), dim3(kBlock), 0, s, nb, n3, tol, tol_mode, partial, ctl);
   return hipGetLastError();
 }
 
-hipError_t launch_outer(bool fp64, int n, int c, int max_cycles, const double* sigma, const double* y_in,
-                        double* y_out, const void* e0, const void* e1, void* r0, void* r1, double* partial,
-                        Ctl* ctl, hipStream_t s) {
+hipError_t launch_outer(bool fp64, int n, int first, int max_cycles, const double* sigma, double* ya, double* yb,
+                        const void* e0, const void* e1, void* r0, void* r1, double* partial, Ctl* ctl,
+                        hipStream_t s) {
   const int n3 = n * n * n, nb = blocks_for(n3, kBlock);
   if (fp64)
-    hipLaunchKernelGGL(k_outer<double>, dim3(nb), dim3(kBlock), 0, s, n, c, sigma, y_in, y_out,
-                       (const double*)e0, (const double*)e1, (double*)r0, (double*)r1, partial, ctl);
+    hipLaunchKernelGGL(k_outer<double>, dim3(nb), dim3(kBlock), 0, s, n, first, sigma, ya, yb, (const double*)e0,
+                       (const double*)e1, (double*)r0, (double*)r1, partial, ctl);
   else
-    hipLaunchKernelGGL(k_outer<float>, dim3(nb), dim3(kBlock), 0, s, n, c, sigma, y_in, y_out,
-                       (const float*)e0, (const float*)e1, (float*)r0, (float*)r1, partial, ctl);
-  hipLaunchKernelGGL(k_fin_outer, dim3(1), dim3(kBlock), 0, s, c, max_cycles, nb, n3, partial, ctl);
+    hipLaunchKernelGGL(k_outer<float>, dim3(nb), dim3(kBlock), 0, s, n, first, sigma, ya, yb, (const float*)e0,
+                       (const float*)e1, (float*)r0, (float*)r1, partial, ctl);
+  hipLaunchKernelGGL(k_fin_outer, dim3(1), dim3(kBlock), 0, s, first, max_cycles, nb, n3, partial, ctl);
   return hipGetLastError();
 }
 
@@ -718,6 +825,12 @@ hipError_t launch_vcycle(bool fp64, const LevelBufs* lv, int levels, int tail, i
                          const double* green, Ctl* ctl, hipStream_t s) {
   return fp64 ? vcycle_impl<double>(lv, levels, tail, nu1, nu2, green, ctl, s)
               : vcycle_impl<float>(lv, levels, tail, nu1, nu2, green, ctl, s);
+}
+
+hipError_t launch_vcycle_kernel(bool fp64, int kid, const LevelBufs* lv, int levels, int tail, int nu1, int nu2,
+                                const double* green, Ctl* ctl, hipStream_t s, double* bytes) {
+  return fp64 ? one_kernel<double>(kid, lv, levels, tail, nu1, nu2, green, ctl, s, bytes)
+              : one_kernel<float>(kid, lv, levels, tail, nu1, nu2, green, ctl, s, bytes);
 }
 
 hipError_t tail_configure(bool fp64, int n_tail, int levels_tail, size_t* lds_bytes) {
@@ -728,12 +841,16 @@ hipError_t tail_configure(bool fp64, int n_tail, int levels_tail, size_t* lds_by
   return e;
 }
 
-hipError_t launch_phi_update(int n, double h, int cold, const double* phi_k, const double* phi_km1,
-                             const double* ya, const double* yb, double* phi_out, double* phi_copy,
-                             double* y_hist_out, float* phi32, Ctl* ctl, hipStream_t s) {
+hipError_t launch_phi_update(int n, double h, double* phi0, double* phi1, const double* ya, const double* yb,
+                             double* yh0, double* yh1, double* yh2, float* phi32, Ctl* ctl, hipStream_t s) {
   const int n3 = n * n * n;
-  hipLaunchKernelGGL(k_phi_update, dim3(blocks_for(n3, kBlock)), dim3(kBlock), 0, s, n3, h, cold, phi_k, phi_km1,
-                     ya, yb, phi_out, phi_copy, y_hist_out, phi32, ctl);
+  hipLaunchKernelGGL(k_phi_update, dim3(blocks_for(n3, kBlock)), dim3(kBlock), 0, s, n3, h, phi0, phi1, ya, yb,
+                     yh0, yh1, yh2, phi32, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance(Ctl* ctl, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, ctl);
   return hipGetLastError();
 }
 

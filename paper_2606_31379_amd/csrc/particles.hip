@@ -204,8 +204,11 @@ template <typename T, typename TP>
 __global__ void __launch_bounds__(kBlock)
 k_gather(int n_atoms, int n, int p, double h, double k_e, const int* __restrict__ perm,
          const int* __restrict__ base, const double* __restrict__ w, const double* __restrict__ qa,
-         const TP* __restrict__ phi, double* __restrict__ force, double* __restrict__ partial) {
+         const TP* __restrict__ phi0, const TP* __restrict__ phi1, double* __restrict__ force,
+         double* __restrict__ partial, const Ctl* ctl) {
   __shared__ double sh[kBlock / 64];
+  // the new potential: written over phi^k on a cold solve, over phi^{k-1} otherwise
+  const TP* phi = (ctl->cold ? ctl->k_idx : 1 - ctl->k_idx) ? phi1 : phi0;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   double e_atom = 0.0;
   if (t < n_atoms) {
@@ -434,15 +437,16 @@ hipError_t launch_spread(bool fp64, int n, int p, int tile, int ntx, const int* 
 }
 
 hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, double h, double k_e, const int* perm,
-                         const int* base, const void* w, const double* qa, const void* phi,
-                         double* force, double* partial, Ctl* ctl, hipStream_t s) {
+                         const int* base, const void* w, const double* qa, const double* phi0,
+                         const double* phi1, const float* phi32, double* force, double* partial, Ctl* ctl,
+                         hipStream_t s) {
   const int nb = blocks_for(n_atoms, kBlock);
   if (fp64)
     hipLaunchKernelGGL((k_gather<double, double>), dim3(nb), dim3(kBlock), 0, s, n_atoms, n, p, h, k_e,
-                       perm, base, (const double*)w, qa, (const double*)phi, force, partial);
+                       perm, base, (const double*)w, qa, phi0, phi1, force, partial, ctl);
   else
     hipLaunchKernelGGL((k_gather<float, float>), dim3(nb), dim3(kBlock), 0, s, n_atoms, n, p, h, k_e,
-                       perm, base, (const double*)w, qa, (const float*)phi, force, partial);
+                       perm, base, (const double*)w, qa, phi32, phi32, force, partial, ctl);
   hipLaunchKernelGGL(k_fin_sum, dim3(1), dim3(kBlock), 0, s, nb, partial, &ctl->e_lr);
   return hipGetLastError();
 }

@@ -31,7 +31,8 @@ MESH_Q, MESH_QS, MESH_SIGMA_P, MESH_Y, MESH_PHI, MESH_PHI_PREV = range(6)
 # every symbol include/p3maze.h declares
 EXPORTS = ["p3mz_create", "p3mz_compute", "p3mz_get_mesh", "p3mz_vcycle", "p3mz_get_stats",
            "p3mz_reset_history", "p3mz_save_state", "p3mz_load_state", "p3mz_md_run",
-           "p3mz_set_timing", "p3mz_set_kernel_timer", "p3mz_get_kernel_timer",
+           "p3mz_set_graphs", "p3mz_set_timing", "p3mz_set_kernel_timer", "p3mz_get_kernel_timer",
+           "p3mz_kernel_bench",
            "p3mz_destroy", "p3mz_status_string", "p3mz_last_error", "p3mz_version"]
 KERNELS = {"halfsweep": 0, "outer": 1, "smooth": 2, "restrict": 3, "prolong": 4, "sweep0": 5,
            "tail": 6, "spread": 7, "gather": 8, "sr": 9, "sigma": 10, "phi": 11}
@@ -84,7 +85,9 @@ def _load() -> C.CDLL:
         "p3mz_load_state": ([vp, vp, C.c_size_t], C.c_int),
         "p3mz_md_run": ([vp, vp, vp, vp, C.POINTER(p3mz_mdterms), C.c_double, C.c_int32, vp, vp, vp],
                         C.c_int),
+        "p3mz_set_graphs": ([vp, C.c_int32], C.c_int),
         "p3mz_set_timing": ([vp, C.c_int32], C.c_int),
+        "p3mz_kernel_bench": ([vp, C.c_int32, C.c_int32, vp, dp, dp], C.c_int),
         "p3mz_set_kernel_timer": ([vp, C.c_int32], C.c_int),
         "p3mz_get_kernel_timer": ([vp, dp, C.POINTER(C.c_int64), dp], C.c_int),
         "p3mz_destroy": ([vp], None),
@@ -158,6 +161,17 @@ def p3mz_md_run(ctx: int, pos_dev: int, vel_dev: int, mass_dev: int, terms: p3mz
                 stream: int | None = None) -> int:
     return _check(lib.p3mz_md_run(ctx, pos_dev, vel_dev, mass_dev, C.byref(terms), dt, n_steps,
                                   energy_log_dev, cycles_log_dev, stream), "p3mz_md_run")
+
+
+def p3mz_set_graphs(ctx: int, on: bool) -> int:
+    return _check(lib.p3mz_set_graphs(ctx, int(on)), "p3mz_set_graphs")
+
+
+def p3mz_kernel_bench(ctx: int, kernel_id: int, reps: int, stream: int | None = None) -> tuple[float, float]:
+    """(mean launch milliseconds, algorithmic bytes per launch)."""
+    ms, b = C.c_double(), C.c_double()
+    _check(lib.p3mz_kernel_bench(ctx, kernel_id, reps, stream, C.byref(ms), C.byref(b)), "p3mz_kernel_bench")
+    return ms.value, b.value
 
 
 def p3mz_set_timing(ctx: int, on: bool) -> int:
