@@ -115,12 +115,15 @@ def run_mode(torch, P, w, system, precision, warmup, steps, kernel):
         log(f"[{'fp64' if precision == 0 else 'mixed'}] kernel ms/step: "
             + ", ".join(f"{k}={v:.4f}" for k, v in sorted(shares.items(), key=lambda x: -x[1])))
         P.p3mz_set_kernel_timer(ctx, -1)      # timed region runs with captured graphs
-        stage_ms = np.zeros(4)
+        mesh_ms_tot, sr_ms_tot, graphs = 0.0, 0.0, 1
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(steps):
             md(1, with_logs=True, offset=k)
-            stage_ms += np.array(P.p3mz_get_stats(ctx).ms_stage)
+            st = P.p3mz_get_stats(ctx)
+            mesh_ms_tot += st.ms_mesh
+            sr_ms_tot += st.ms_short_range
+            graphs &= st.graphs
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         # the dominant kernel timed back to back on the live buffers of the last step
@@ -130,15 +133,14 @@ def run_mode(torch, P, w, system, precision, warmup, steps, kernel):
         kms, kbytes = kms * klaunch, kbytes * klaunch
         cycles = clog.cpu().numpy()[:steps]
         energies = elog.cpu().numpy()[:steps]
-        mesh_ms = stage_ms[:3].sum() / steps
+        mesh_ms = mesh_ms_tot / steps
         avg_launch_ms = kms / max(klaunch, 1)
         bytes_per_launch = kbytes / max(klaunch, 1)
         out = dict(
             ns_per_atom=mesh_ms * 1e6 / system.n,
             mesh_ms_per_step=mesh_ms,
             md_ms_per_step=wall * 1e3 / steps,
-            stage_ms_per_step=dict(spread_smooth=stage_ms[0] / steps, solve=stage_ms[1] / steps,
-                                   gather=stage_ms[2] / steps, short_range=stage_ms[3] / steps),
+            short_range_ms_per_step=sr_ms_tot / steps, graphs=bool(graphs),
             vcycles_per_step=float(cycles.mean()), vcycles_min=int(cycles.min()), vcycles_max=int(cycles.max()),
             energy_drift_per_step=float(np.polyfit(np.arange(steps), energies[:, 5], 1)[0]) if steps > 2 else None,
             kernel_ms_per_step=shares, dominant=dominant,

@@ -100,9 +100,13 @@ typedef struct {
   double res_hist[65];       /* residual before cycle c, c = 0..cycles                */
   double e_sr, e_lr, e_self, e_total;
   int64_t steps;             /* completed compute calls since create/load            */
-  double ms_stage[4];        /* with p3mz_set_timing on: milliseconds of the last
-                                compute in {spread+smoothing, constraint solve and
-                                field update, gather, short-range pairs}          */
+  int32_t graphs;            /* 1 if the last step ran from captured graphs         */
+  /* with p3mz_set_timing on, milliseconds of the last step from HIP events on
+   * the caller's stream: the mesh step (binning, spread, smoothing, constraint
+   * solve, field update, gather) and the short-range pairs; the split of the
+   * mesh step into spread+smoothing / solve+update / gather only when the
+   * step was launched kernel by kernel (else -1). */
+  double ms_mesh, ms_short_range, ms_spread, ms_solve, ms_gather;
 } p3mz_stats;
 
 typedef struct p3mz_ctx p3mz_ctx;
@@ -193,7 +197,7 @@ enum {
   P3MZ_KERNEL_OUTER = 1,      /* FP64 outer residual + multiplier update          */
   P3MZ_KERNEL_SMOOTH = 2,     /* one axis of the charge smoothing                 */
   P3MZ_KERNEL_RESTRICT = 3,   /* fused residual + full-weighting restriction      */
-  P3MZ_KERNEL_PROLONG = 4,    /* prolongation fused with the first red half-sweep */
+  P3MZ_KERNEL_PROLONG = 4,    /* trilinear correction of the black points         */
   P3MZ_KERNEL_SWEEP0 = 5,     /* first sweep from a zero correction               */
   P3MZ_KERNEL_TAIL = 6,       /* LDS-resident coarse levels (<= 16^3) + 4^3 solve */
   P3MZ_KERNEL_SPREAD = 7, P3MZ_KERNEL_GATHER = 8, P3MZ_KERNEL_SR = 9,

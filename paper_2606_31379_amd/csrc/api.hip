@@ -149,13 +149,13 @@ struct p3mz_ctx {
   int *d_base = nullptr, *d_key = nullptr, *d_slot = nullptr, *d_perm_raw = nullptr, *d_perm = nullptr;
   void* d_w = nullptr;
   int ntx = 0, nbins = 0;
-  int *d_count = nullptr, *d_start = nullptr;
+  int *d_count = nullptr, *d_start = nullptr, *d_bsum = nullptr;
   int nc = 1, ncells = 1;
   int *d_ckey = nullptr, *d_cslot = nullptr, *d_ccount = nullptr, *d_cstart = nullptr, *d_cperm_raw = nullptr,
       *d_cperm = nullptr;
   double *d_q = nullptr, *d_qs = nullptr, *d_tmp = nullptr;
   double* d_sigma = nullptr;
-  double* d_y[2] = {nullptr, nullptr};
+  double* d_y[2] = {nullptr, nullptr};   // d_y[0]: multiplier; d_y[1]: FP64 outer residual
   double* d_phi[2] = {nullptr, nullptr};
   double* d_yh[3] = {nullptr, nullptr, nullptr};
   float* d_phi32 = nullptr;
@@ -175,8 +175,11 @@ struct p3mz_ctx {
   std::vector<void*> allocs;
   // graphs: captured on a private stream, launched on the caller's stream
   bool use_graphs = true;
+  bool capturing = false;        // enqueueing into a graph capture right now
+  bool sub_events = false;       // the sub-stage events were recorded this step
+  bool ran_graphs = false;       // the last step was launched from graphs
   hipStream_t cap = nullptr;
-  GraphSlot g_pre, g_cycle, g_post, g_md_pre, g_md_post;
+  GraphSlot g_pre, g_cycle, g_post1, g_post2, g_md_post2;
   // optional timing: stage events and one kernel family's per-launch events
   bool timing = false;
   hipEvent_t stage_ev[5] = {};
@@ -207,9 +210,9 @@ struct p3mz_ctx {
   void drop_graphs() {
     g_pre.reset();
     g_cycle.reset();
-    g_post.reset();
-    g_md_pre.reset();
-    g_md_post.reset();
+    g_post1.reset();
+    g_post2.reset();
+    g_md_post2.reset();
   }
   ~p3mz_ctx() {
     drop_graphs();
@@ -304,6 +307,7 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   P3MZ_TRY(c->alloc(&c->d_ccount, c->ncells));
   P3MZ_TRY(c->alloc(&c->d_cstart, c->ncells + 1));
   P3MZ_HIP_TRY(hipMemset(c->d_ccount, 0, sizeof(int) * c->ncells));
+  P3MZ_TRY(c->alloc(&c->d_bsum, std::max(scan_partials(c->nbins), scan_partials(c->ncells))));
   const size_t n3 = (size_t)c->n3;
   P3MZ_TRY(c->alloc(&c->d_q, n3));
   P3MZ_TRY(c->alloc(&c->d_qs, n3));
@@ -342,6 +346,7 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   P3MZ_TRY(c->alloc(&c->d_e_other, 1));
   size_t lds = 0;
   P3MZ_HIP_TRY(tail_configure(c->fp64, n >> pl.tail, pl.levels - pl.tail, &lds));
+  P3MZ_HIP_TRY(smooth_configure(n));
   P3MZ_HIP_TRY(hipDeviceSynchronize());
   return P3MZ_OK;
 }
@@ -350,8 +355,13 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
 // The step, as three launch sequences.  Each is enqueued either directly
 // (eager) or once into a captured graph that is replayed every step.
 // ---------------------------------------------------------------------------
+// Stage events are recorded only on the caller's stream between graph
+// launches (events recorded inside a graph cannot be timed); the sub-stage
+// boundaries 1 and 2 exist only when the step is launched kernel by kernel.
 void stage(p3mz_ctx* c, int i, hipStream_t s) {
-  if (c->timing) (void)hipEventRecord(c->stage_ev[i], s);
+  if (!c->timing || c->capturing) return;
+  (void)hipEventRecord(c->stage_ev[i], s);
+  if (i == 1 || i == 2) c->sub_events = true;
 }
 
 // bin + deterministic order, spread, smoothing, sigma_p and predictor, first residual
@@ -359,10 +369,9 @@ p3mz_status enq_pre(p3mz_ctx* c, const double* pos, hipStream_t s) {
   const Plan& pl = c->pl;
   const int n = pl.n, na = (int)c->n_atoms;
   const double N3 = (double)c->n3, ts = (double)c->tsz;
-  stage(c, 0, s);
   P3MZ_HIP_TRY(launch_bin_stencil(true, na, pos, c->P.box, n, pl.p, kTile, c->ntx, c->d_base, c->d_w, c->d_key,
                                   c->d_slot, c->d_count, c->d_ctl, s));
-  P3MZ_HIP_TRY(launch_scan(c->nbins, c->d_count, c->d_start, s));
+  P3MZ_HIP_TRY(launch_scan(c->nbins, c->d_count, c->d_start, c->d_bsum, s));
   P3MZ_HIP_TRY(launch_scatter(na, c->d_key, c->d_slot, c->d_start, c->d_perm_raw, s));
   P3MZ_HIP_TRY(launch_sort_bins(c->nbins, c->d_start, c->d_perm_raw, c->d_perm, c->d_ctl, s));
   kt_begin(KT_SPREAD, 0, s);
@@ -384,7 +393,7 @@ p3mz_status enq_pre(p3mz_ctx* c, const double* pos, hipStream_t s) {
   kt_begin(KT_OUTER, 0, s);
   P3MZ_HIP_TRY(launch_outer(c->fp64, n, 1, c->P.max_cycles, c->d_sigma, c->d_y[0], c->d_y[1], f.e0, f.e1, f.r0, f.r1,
                             c->d_partial, c->d_ctl, s));
-  kt_end(KT_OUTER, 0, (16.0 + ts) * N3, s);
+  kt_end(KT_OUTER, 0, (24.0 + ts) * N3, s);
   return P3MZ_OK;
 }
 
@@ -397,13 +406,12 @@ p3mz_status enq_cycle(p3mz_ctx* c, hipStream_t s) {
   kt_begin(KT_OUTER, 0, s);
   P3MZ_HIP_TRY(launch_outer(c->fp64, pl.n, 0, c->P.max_cycles, c->d_sigma, c->d_y[0], c->d_y[1], f.e0, f.e1, f.r0,
                             f.r1, c->d_partial, c->d_ctl, s));
-  kt_end(KT_OUTER, 0, (24.0 + 2.0 * ts) * N3, s);
+  kt_end(KT_OUTER, 0, (32.0 + 2.0 * ts) * N3, s);
   return P3MZ_OK;
 }
 
-// field update, gather on the new potential, short-range pairs, energies,
-// history rotation
-p3mz_status enq_post(p3mz_ctx* c, const double* pos, double* force, double* energy, hipStream_t s) {
+// field update and gather on the new potential
+p3mz_status enq_post1(p3mz_ctx* c, double* force, hipStream_t s) {
   const Plan& pl = c->pl;
   const int n = pl.n, na = (int)c->n_atoms;
   const double N3 = (double)c->n3;
@@ -417,9 +425,14 @@ p3mz_status enq_post(p3mz_ctx* c, const double* pos, double* force, double* ener
                              c->d_phi[0], c->d_phi[1], c->d_phi32, force, c->d_partial, c->d_ctl, s));
   const double pe = pl.p + 2.0;
   kt_end(KT_GATHER, 0, (double)na * (48.0 + 24.0 * pl.p + pe * pe * pe * (c->fp64 ? 8.0 : 4.0)), s);
-  stage(c, 3, s);
+  return P3MZ_OK;
+}
+
+// short-range pairs on a fresh cell list, energies, history rotation
+p3mz_status enq_post2(p3mz_ctx* c, const double* pos, double* force, double* energy, hipStream_t s) {
+  const int na = (int)c->n_atoms;
   P3MZ_HIP_TRY(launch_bin_cells(na, pos, c->P.box, c->nc, c->d_ckey, c->d_cslot, c->d_ccount, c->d_ctl, s));
-  P3MZ_HIP_TRY(launch_scan(c->ncells, c->d_ccount, c->d_cstart, s));
+  P3MZ_HIP_TRY(launch_scan(c->ncells, c->d_ccount, c->d_cstart, c->d_bsum, s));
   P3MZ_HIP_TRY(launch_scatter(na, c->d_ckey, c->d_cslot, c->d_cstart, c->d_cperm_raw, s));
   P3MZ_HIP_TRY(launch_sort_bins(c->ncells, c->d_cstart, c->d_cperm_raw, c->d_cperm, c->d_ctl, s));
   kt_begin(KT_SR, 0, s);
@@ -427,7 +440,6 @@ p3mz_status enq_post(p3mz_ctx* c, const double* pos, double* force, double* ener
                          c->d_cstart, c->d_cperm, force, c->e_self, energy ? energy : c->d_energy,
                          c->d_partial, c->d_ctl, s));
   kt_end(KT_SR, 0, (double)na * 56.0, s);
-  stage(c, 4, s);
   P3MZ_HIP_TRY(launch_advance(c->d_ctl, s));
   return P3MZ_OK;
 }
@@ -440,14 +452,11 @@ struct MdArgs {
   int model;
 };
 
-p3mz_status enq_md_pre(p3mz_ctx* c, const MdArgs& m, hipStream_t s) {
-  P3MZ_HIP_TRY(launch_kick_drift((int)c->n_atoms, m.pos, m.vel, c->d_md_force, m.mass, m.dt, m.f2a, 1, s));
-  return enq_pre(c, m.pos, s);
-}
-
-p3mz_status enq_md_post(p3mz_ctx* c, const MdArgs& m, hipStream_t s) {
+// the rest of an MD step after the mesh step: pairs, non-electrostatic
+// terms, closing half-kick and the energy log
+p3mz_status enq_md_post2(p3mz_ctx* c, const MdArgs& m, hipStream_t s) {
   const int na = (int)c->n_atoms;
-  P3MZ_TRY(enq_post(c, m.pos, c->d_md_force, c->d_energy, s));
+  P3MZ_TRY(enq_post2(c, m.pos, c->d_md_force, c->d_energy, s));
   // the cell list of the short-range pass is still valid for these positions
   P3MZ_HIP_TRY(launch_nonelec(na, m.pos, c->P.box, c->P.r_cut, m.model, m.p[0], m.p[1], m.p[2], m.p[3], m.p[4],
                               m.p[5], c->nc, c->d_cstart, c->d_cperm, c->d_md_force, c->d_partial, c->d_e_other, s));
@@ -466,7 +475,9 @@ p3mz_status run_seq(p3mz_ctx* c, GraphSlot& slot, const std::vector<uint64_t>& k
   if (!slot.exec || slot.key != key) {
     slot.reset();
     P3MZ_HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    c->capturing = true;
     p3mz_status st = body(c->cap);
+    c->capturing = false;
     hipError_t e = hipStreamEndCapture(c->cap, &slot.graph);
     if (st != P3MZ_OK || e != hipSuccess) {
       slot.reset();
@@ -484,6 +495,7 @@ p3mz_status run_seq(p3mz_ctx* c, GraphSlot& slot, const std::vector<uint64_t>& k
     slot.key = key;
   }
   P3MZ_HIP_TRY(hipGraphLaunch(slot.exec, s));
+  c->ran_graphs = true;
   return P3MZ_OK;
 }
 
@@ -551,11 +563,21 @@ p3mz_status finish(p3mz_ctx* c, hipStream_t s) {
   st.e_self = c->e_self;
   st.e_total = h.e_sr + h.e_lr + c->e_self;
   st.steps = h.steps;
+  st.graphs = c->ran_graphs;
   if (c->timing) {
-    for (int i = 0; i < 4; i++) {
-      float ms = 0.f;
-      P3MZ_HIP_TRY(hipEventElapsedTime(&ms, c->stage_ev[i], c->stage_ev[i + 1]));
-      st.ms_stage[i] = ms;
+    float ms = 0.f;
+    P3MZ_HIP_TRY(hipEventElapsedTime(&ms, c->stage_ev[0], c->stage_ev[3]));
+    st.ms_mesh = ms;
+    P3MZ_HIP_TRY(hipEventElapsedTime(&ms, c->stage_ev[3], c->stage_ev[4]));
+    st.ms_short_range = ms;
+    st.ms_spread = st.ms_solve = st.ms_gather = -1.0;
+    if (c->sub_events) {
+      P3MZ_HIP_TRY(hipEventElapsedTime(&ms, c->stage_ev[0], c->stage_ev[1]));
+      st.ms_spread = ms;
+      P3MZ_HIP_TRY(hipEventElapsedTime(&ms, c->stage_ev[1], c->stage_ev[2]));
+      st.ms_solve = ms;
+      P3MZ_HIP_TRY(hipEventElapsedTime(&ms, c->stage_ev[2], c->stage_ev[3]));
+      st.ms_gather = ms;
     }
   }
   for (int i = 0; i + 1 < c->kt_used; i += 2) {
@@ -574,14 +596,33 @@ struct ActiveGuard {
   ~ActiveGuard() { g_active = nullptr; }
 };
 
-p3mz_status compute_step(p3mz_ctx* c, const double* pos, double* force, double* energy, hipStream_t s) {
-  ActiveGuard guard(c);
+// The mesh step on positions `pos` (launch order: [pre] [cycles...] [post1]
+// [post2], with the stage events between the launches).
+p3mz_status mesh_step(p3mz_ctx* c, const double* pos, double* force, double* energy, hipStream_t s,
+                      std::vector<uint64_t> post2_key, bool md, const MdArgs* m) {
   const uint64_t tm = c->timing;
+  c->sub_events = false;
+  c->ran_graphs = false;
+  stage(c, 0, s);
   P3MZ_TRY(run_seq(c, c->g_pre, {(uint64_t)(uintptr_t)pos, tm}, s, [&](hipStream_t q) { return enq_pre(c, pos, q); }));
   P3MZ_TRY(run_solve(c, s));
   if (c->h_ctl->nan_flag) return on_nan(c);
-  P3MZ_TRY(run_seq(c, c->g_post, {(uint64_t)(uintptr_t)pos, (uint64_t)(uintptr_t)force, (uint64_t)(uintptr_t)energy, tm},
-                   s, [&](hipStream_t q) { return enq_post(c, pos, force, energy, q); }));
+  P3MZ_TRY(run_seq(c, c->g_post1, {(uint64_t)(uintptr_t)force, tm}, s,
+                   [&](hipStream_t q) { return enq_post1(c, force, q); }));
+  stage(c, 3, s);
+  if (md)
+    P3MZ_TRY(run_seq(c, c->g_md_post2, post2_key, s, [&](hipStream_t q) { return enq_md_post2(c, *m, q); }));
+  else
+    P3MZ_TRY(run_seq(c, c->g_post2, post2_key, s, [&](hipStream_t q) { return enq_post2(c, pos, force, energy, q); }));
+  stage(c, 4, s);
+  return P3MZ_OK;
+}
+
+p3mz_status compute_step(p3mz_ctx* c, const double* pos, double* force, double* energy, hipStream_t s) {
+  ActiveGuard guard(c);
+  P3MZ_TRY(mesh_step(c, pos, force, energy, s,
+                     {(uint64_t)(uintptr_t)pos, (uint64_t)(uintptr_t)force, (uint64_t)(uintptr_t)energy}, false,
+                     nullptr));
   P3MZ_TRY(finish(c, s));
   if (c->st.status) {
     g_last_error = "V-cycle cap reached before the tolerance";
@@ -775,25 +816,18 @@ p3mz_status p3mz_md_run(p3mz_ctx* ctx, double* pos_dev, double* vel_dev, const d
     m.p[0] = terms->lj_eps; m.p[1] = terms->lj_sigma; m.p[2] = terms->k_bond; m.p[3] = terms->r0;
     m.p[4] = terms->k_angle; m.p[5] = terms->theta0;
   }
-  const uint64_t tm = ctx->timing;
-  std::vector<uint64_t> key_pre = {(uint64_t)(uintptr_t)pos_dev, (uint64_t)(uintptr_t)vel_dev,
-                                   (uint64_t)(uintptr_t)mass_dev, bits(dt), bits(m.f2a), tm};
-  std::vector<uint64_t> key_post = key_pre;
-  key_post.push_back((uint64_t)(uintptr_t)energy_log_dev);
-  key_post.push_back((uint64_t)(uintptr_t)cycles_log_dev);
-  key_post.push_back((uint64_t)m.model);
-  key_post.push_back(bits(m.mv2e));
-  for (double v : m.p) key_post.push_back(bits(v));
+  std::vector<uint64_t> key_post2 = {(uint64_t)(uintptr_t)pos_dev, (uint64_t)(uintptr_t)vel_dev,
+                                     (uint64_t)(uintptr_t)mass_dev, bits(dt), bits(m.f2a),
+                                     (uint64_t)(uintptr_t)energy_log_dev, (uint64_t)(uintptr_t)cycles_log_dev,
+                                     (uint64_t)m.model, bits(m.mv2e)};
+  for (double v : m.p) key_post2.push_back(bits(v));
   P3MZ_HIP_TRY(hipMemsetAsync(&ctx->d_ctl->md_step, 0, sizeof(int), s));   // eager, never captured
   if (!ctx->md_have_force) {
-    // forces at the initial positions (a cold solve on first use)
-    P3MZ_TRY(run_seq(ctx, ctx->g_pre, {(uint64_t)(uintptr_t)pos_dev, tm}, s,
-                     [&](hipStream_t q) { return enq_pre(ctx, pos_dev, q); }));
-    P3MZ_TRY(run_solve(ctx, s));
-    if (ctx->h_ctl->nan_flag) return on_nan(ctx);
-    P3MZ_TRY(run_seq(ctx, ctx->g_post, {(uint64_t)(uintptr_t)pos_dev, (uint64_t)(uintptr_t)ctx->d_md_force,
-                                        (uint64_t)(uintptr_t)ctx->d_energy, tm},
-                     s, [&](hipStream_t q) { return enq_post(ctx, pos_dev, ctx->d_md_force, ctx->d_energy, q); }));
+    // forces at the initial positions (a cold solve on first use); no log row
+    P3MZ_TRY(mesh_step(ctx, pos_dev, ctx->d_md_force, ctx->d_energy, s,
+                       {(uint64_t)(uintptr_t)pos_dev, (uint64_t)(uintptr_t)ctx->d_md_force,
+                        (uint64_t)(uintptr_t)ctx->d_energy},
+                       false, nullptr));
     P3MZ_HIP_TRY(launch_nonelec((int)ctx->n_atoms, pos_dev, ctx->P.box, ctx->P.r_cut, m.model, m.p[0], m.p[1], m.p[2],
                                 m.p[3], m.p[4], m.p[5], ctx->nc, ctx->d_cstart, ctx->d_cperm, ctx->d_md_force,
                                 ctx->d_partial, ctx->d_e_other, s));
@@ -802,12 +836,10 @@ p3mz_status p3mz_md_run(p3mz_ctx* ctx, double* pos_dev, double* vel_dev, const d
   }
   p3mz_status worst = P3MZ_OK;
   for (int step = 0; step < n_steps; step++) {
-    P3MZ_TRY(run_seq(ctx, ctx->g_md_pre, key_pre, s, [&](hipStream_t q) { return enq_md_pre(ctx, m, q); }));
-    P3MZ_TRY(run_solve(ctx, s));
-    if (ctx->h_ctl->nan_flag) return on_nan(ctx);
+    P3MZ_HIP_TRY(launch_kick_drift((int)ctx->n_atoms, pos_dev, vel_dev, ctx->d_md_force, mass_dev, dt, m.f2a, 1, s));
+    P3MZ_TRY(mesh_step(ctx, pos_dev, ctx->d_md_force, ctx->d_energy, s, key_post2, true, &m));
     if (ctx->h_ctl->status) worst = P3MZ_WARN_NOT_CONVERGED;
     ctx->last_cycles = ctx->h_ctl->cycles;
-    P3MZ_TRY(run_seq(ctx, ctx->g_md_post, key_post, s, [&](hipStream_t q) { return enq_md_post(ctx, m, q); }));
   }
   P3MZ_TRY(finish(ctx, s));
   return worst;
@@ -818,7 +850,8 @@ p3mz_status p3mz_set_timing(p3mz_ctx* ctx, int32_t on) {
   if (on && !ctx->stage_ev[0])
     for (hipEvent_t& e : ctx->stage_ev) P3MZ_HIP_TRY(hipEventCreate(&e));
   ctx->timing = on != 0;
-  for (double& v : ctx->st.ms_stage) v = 0.0;
+  ctx->st.ms_mesh = ctx->st.ms_short_range = 0.0;
+  ctx->st.ms_spread = ctx->st.ms_solve = ctx->st.ms_gather = -1.0;
   return P3MZ_OK;
 }
 

@@ -92,6 +92,35 @@ __device__ __forceinline__ double reduce_partials_max(const double* p, int n, do
   return block_max(acc, sh);
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on
+// XCD b % 8).  Renumbering them so that each XCD walks one contiguous eighth
+// of the index space keeps stencil neighbours (adjacent rows and planes) in
+// the same XCD's L2 instead of re-reading them from HBM on another XCD.
+__device__ __forceinline__ int xcd_block() {
+  const int g = gridDim.x, b = blockIdx.x;
+  if (g & 7) return b;
+  return (b & 7) * (g >> 3) + (b >> 3);
+}
+
+// Reduction kernels use a capped grid: each (XCD-renumbered) workgroup walks
+// one contiguous chunk of the index space, a multiple of the block size.
+constexpr int kRedBlock = 256;
+constexpr int kMaxRedBlocks = 2048;
+inline int red_blocks(int64_t count) {
+  int64_t b = (count + kRedBlock - 1) / kRedBlock;
+  if (b > kMaxRedBlocks) b = kMaxRedBlocks;
+  if (b >= 8) b &= ~7LL;
+  return (int)(b < 1 ? 1 : b);
+}
+__device__ __forceinline__ void chunk_range(int64_t count, int* lo, int* hi) {
+  const int64_t g = gridDim.x;
+  int64_t per = (count + g - 1) / g;
+  per = (per + kRedBlock - 1) / kRedBlock * kRedBlock;
+  const int64_t l = (int64_t)xcd_block() * per;
+  *lo = (int)(l < count ? l : count);
+  *hi = (int)(l + per < count ? l + per : count);
+}
+
 // --- mesh indexing ---------------------------------------------------------
 // Natural layout: x fastest.  Colour-split layout: the points of colour
 // c = (i+j+k)&1 of each row (j,k) are packed, index ((k*n + j)*(n/2) + i/2).

@@ -24,8 +24,10 @@ hipError_t launch_bin_stencil(bool fp64, int n_atoms, const double* pos, double 
 // Cell key of each atom for the short-range cell list (nc cells per edge).
 hipError_t launch_bin_cells(int n_atoms, const double* pos, double box, int nc, int* key, int* slot,
                             int* count, Ctl* ctl, hipStream_t s);
-// Exclusive scan of count[0..nbins) into start[0..nbins], zeroing count.
-hipError_t launch_scan(int nbins, int* count, int* start, hipStream_t s);
+// Exclusive scan of count[0..nbins) into start[0..nbins], zeroing count;
+// bsum needs scan_partials(nbins) ints.
+int scan_partials(int nbins);
+hipError_t launch_scan(int nbins, int* count, int* start, int* bsum, hipStream_t s);
 // perm_raw[start[key[a]] + slot[a]] = a.
 hipError_t launch_scatter(int n_atoms, const int* key, const int* slot, const int* start, int* perm_raw,
                           hipStream_t s);
@@ -61,12 +63,12 @@ hipError_t launch_smooth(bool fp64, int n, int axis, int ntaps, int half, const 
 hipError_t launch_sigma(int n, double h, const double* qs, const double* phi0, const double* phi1,
                         const double* yb0, const double* yb1, const double* yb2, double* sigma, double* y,
                         double tol, int tol_mode, double* partial, Ctl* ctl, hipStream_t s);
-// Outer residual: cycle c = 0 (first) or the device's next cycle: y_out =
-// y_in + e (c > 0), r = sigma - mean - M y_out written colour-split in T; the
+// Outer FP64 residual: cycle 0 (first) r = sigma - mean - M y; later cycles
+// y += e, r -= M e; r written colour-split in T for the next V-cycle; the
 // finalize pass records res_hist[c] and the stop decision.
-hipError_t launch_outer(bool fp64, int n, int first, int max_cycles, const double* sigma, double* ya,
-                        double* yb, const void* e0, const void* e1, void* r0, void* r1, double* partial,
-                        Ctl* ctl, hipStream_t s);
+hipError_t launch_outer(bool fp64, int n, int first, int max_cycles, const double* sigma, double* y, double* r64,
+                        const void* e0, const void* e1, void* r0, void* r1, double* partial, Ctl* ctl,
+                        hipStream_t s);
 struct LevelBufs {
   int n;
   void* e0; void* e1;   // colour-split correction
@@ -95,6 +97,8 @@ hipError_t launch_set_ctl_open(Ctl* ctl, hipStream_t s);
 // out = in - *sub (device scalar).
 hipError_t launch_sub_scalar(int64_t count, const double* in, double* out, const double* sub, hipStream_t s);
 hipError_t tail_configure(bool fp64, int n_tail, int levels_tail, size_t* lds_bytes);
+// Allows the smoothing kernels the LDS they need on an n^3 mesh.
+hipError_t smooth_configure(int n);
 
 // ---- molecular dynamics (md.hip) ----------------------------------------
 hipError_t launch_kick_drift(int n_atoms, double* pos, double* vel, const double* force,

@@ -1,5 +1,7 @@
 // Molecular-dynamics support kernels: velocity-Verlet kicks and drift, the
 // non-electrostatic terms of the two model systems, and the energy log.
+#include <algorithm>
+
 #include "launch.h"
 
 namespace {
@@ -32,12 +34,12 @@ k_nonelec(int n_atoms, const double* __restrict__ pos, double box, double rc2, i
           double p1, double p2, double p3, double p4, double p5, int nc, const int* __restrict__ cstart,
           const int* __restrict__ cperm, double* __restrict__ force, double* __restrict__ partial) {
   __shared__ double sh[kBlock / 64];
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
-  double en = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
-  int i = -1;
-  if (wave < n_atoms && model != 0) {
-    i = cperm[wave];
+  const int nwaves = gridDim.x * (kBlock / 64);
+  double en = 0.0;
+  for (int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; wave < n_atoms && model != 0; wave += nwaves) {
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    const int i = cperm[wave];
     const double inv_box = 1.0 / box;
     const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
     const bool pair_atom = model == 1 || (i % 3 == 0);
@@ -120,19 +122,17 @@ k_nonelec(int n_atoms, const double* __restrict__ pos, double box, double rc2, i
         fx += fr[0]; fy += fr[1]; fz += fr[2];
       }
     }
-  }
-  fx = wave_sum(fx);
-  fy = wave_sum(fy);
-  fz = wave_sum(fz);
-  en = wave_sum(en);
-  if (lane == 0) {
-    if (i >= 0) {
+    fx = wave_sum(fx);
+    fy = wave_sum(fy);
+    fz = wave_sum(fz);
+    if (lane == 0) {
       force[3 * i] += fx;
       force[3 * i + 1] += fy;
       force[3 * i + 2] += fz;
     }
-    sh[threadIdx.x >> 6] = en;
   }
+  en = wave_sum(en);
+  if (lane == 0) sh[threadIdx.x >> 6] = en;
   __syncthreads();
   if (threadIdx.x == 0) {
     double s = 0.0;
@@ -151,11 +151,10 @@ __global__ void __launch_bounds__(kBlock)
 k_kinetic(int n_atoms, const double* __restrict__ vel, const double* __restrict__ mass, double mv2e,
           double* __restrict__ partial) {
   __shared__ double sh[kBlock / 64];
-  const int a = blockIdx.x * blockDim.x + threadIdx.x;
   double ke = 0.0;
-  if (a < n_atoms) {
+  for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < n_atoms; a += gridDim.x * blockDim.x) {
     const double vx = vel[3 * a], vy = vel[3 * a + 1], vz = vel[3 * a + 2];
-    ke = 0.5 * mass[a] * (vx * vx + vy * vy + vz * vz) * mv2e;
+    ke += 0.5 * mass[a] * (vx * vx + vy * vy + vz * vz) * mv2e;
   }
   const double bs = block_sum(ke, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = bs;
@@ -191,7 +190,7 @@ hipError_t launch_kick_drift(int n_atoms, double* pos, double* vel, const double
 hipError_t launch_nonelec(int n_atoms, const double* pos, double box, double r_cut, int model, double p0,
                           double p1, double p2, double p3, double p4, double p5, int nc, const int* cstart,
                           const int* cperm, double* force, double* partial, double* e_out, hipStream_t s) {
-  const int nb = blocks_for((int64_t)n_atoms * 64, kBlock);
+  const int nb = std::min(blocks_for((int64_t)n_atoms * 64, kBlock), 2 * kMaxRedBlocks);
   hipLaunchKernelGGL(k_nonelec, dim3(nb), dim3(kBlock), 0, s, n_atoms, pos, box, r_cut * r_cut, model, p0, p1, p2,
                      p3, p4, p5, nc, cstart, cperm, force, partial);
   hipLaunchKernelGGL(k_fin_other, dim3(1), dim3(kBlock), 0, s, nb, partial, e_out);
@@ -201,7 +200,7 @@ hipError_t launch_nonelec(int n_atoms, const double* pos, double box, double r_c
 hipError_t launch_kinetic_log(int n_atoms, const double* vel, const double* mass, double mv2e,
                               const double* energy4, const double* e_other, double* log_base, int* clog_base,
                               Ctl* ctl, double* partial, hipStream_t s) {
-  const int nb = blocks_for(n_atoms, kBlock);
+  const int nb = std::min(blocks_for(n_atoms, kBlock), kMaxRedBlocks);
   hipLaunchKernelGGL(k_kinetic, dim3(nb), dim3(kBlock), 0, s, n_atoms, vel, mass, mv2e, partial);
   hipLaunchKernelGGL(k_fin_log, dim3(1), dim3(kBlock), 0, s, nb, partial, energy4, e_other, log_base, clog_base, ctl);
   return hipGetLastError();

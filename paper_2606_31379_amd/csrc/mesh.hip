@@ -10,68 +10,116 @@ constexpr double kPi = 3.14159265358979323846;
 
 inline int blocks_for(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
+// Geometry of one power-of-two level in colour-split layout (see the V-cycle
+// kernels below); all index arithmetic is shifts and masks.
+struct CsGeo {
+  int l2, n, hn, plane;   // edge n = 2^l2, half edge, elements per z-plane of one colour
+  __device__ explicit CsGeo(int n_) : l2(__builtin_ctz(n_)), n(n_), hn(n_ >> 1), plane(n_ * (n_ >> 1)) {}
+};
+
+__device__ __forceinline__ void cs_decode(const CsGeo& g, int t, int* m, int* j, int* k) {
+  *m = t & (g.hn - 1);
+  const int row = t >> (g.l2 - 1);
+  *j = row & (g.n - 1);
+  *k = row >> g.l2;
+}
+
+__device__ __forceinline__ int cs_index(const CsGeo& g, int i, int j, int k) {
+  return (((k << g.l2) + j) << (g.l2 - 1)) + (i >> 1);
+}
+
+
 // ---------------------------------------------------------------------------
 // Smoothing: one periodic line filter along `AXIS` (0 = x, 1 = y, 2 = z).
 // The K-fold diffusion step [nu, 1-2nu, nu] is applied as its (2K+1)-tap
 // convolution, folded onto the periodic line when 2K+1 > n.  A workgroup
-// stages W whole lines in LDS (for y/z: W consecutive x columns, so global
-// accesses stay coalesced along x).
+// stages W whole lines in LDS; each thread produces R consecutive outputs of
+// one line from a sliding window (ntaps+R-1 LDS reads for R outputs); the
+// taps sit in LDS and every lane reads the same one (broadcast).  y/z lines are W consecutive x columns
+// (coalesced), staged position-major; x lines are W rows, staged row-major
+// and written back through a second LDS buffer so global stores stay
+// coalesced.  Both layouts carry one element of padding per row/position to
+// spread the sliding-window reads over the LDS banks.
 // ---------------------------------------------------------------------------
-template <typename T, int AXIS, int W>
+template <typename T, int AXIS, int W, int R>
 __global__ void __launch_bounds__(kBlock)
-k_smooth(int n, int ntaps, int half, const T* __restrict__ taps, const T* __restrict__ in,
+k_smooth(int n, int ntaps, int half, const T* __restrict__ taps_g, const T* __restrict__ in,
          T* __restrict__ out) {
   extern __shared__ unsigned char smem_raw[];
-  T* line = reinterpret_cast<T*>(smem_raw);        // [W][n] for x, [n][W] for y/z
-  T* tp = line + (size_t)W * n;                    // [ntaps]
-  for (int i = threadIdx.x; i < ntaps; i += kBlock) tp[i] = taps[i];
-  const int total = W * n;
-  // block -> group of W lines
-  int g = blockIdx.x;
+  T* taps = reinterpret_cast<T*>(smem_raw);          // [ntaps], broadcast reads
+  T* buf = taps + ((ntaps + 1) & ~1);
+  const int g = xcd_block();
+  const int tid = threadIdx.x;
+  for (int i = tid; i < ntaps; i += kBlock) taps[i] = taps_g[i];
+  const int ld = AXIS == 0 ? n + 1 : W + 1;         // padded LDS stride between rows / positions
+  size_t row0 = 0;
+  int x0 = 0, o = 0;
   if (AXIS == 0) {
-    const size_t row0 = (size_t)g * W;             // rows (j,k) flattened
-    for (int e = threadIdx.x; e < total; e += kBlock) line[e] = in[row0 * n + e];
-    __syncthreads();
-    for (int e = threadIdx.x; e < total; e += kBlock) {
+    row0 = (size_t)g * W;
+    for (int e = tid; e < W * n; e += kBlock) {
       const int r = e / n, i = e - r * n;
-      const T* L = line + (size_t)r * n;
-      T acc = T(0);
-      int src = i - half;
-      src += src < 0 ? n : 0;
-      for (int m = 0; m < ntaps; m++) {
-        acc += tp[m] * L[src];
-        src = (src + 1 == n) ? 0 : src + 1;
-      }
-      out[row0 * n + e] = acc;
+      buf[r * ld + i] = in[(row0 + r) * n + i];
     }
   } else {
     const int ncol = n / W;
-    const int cb = g % ncol;                       // x block
-    const int o = g / ncol;                        // the other coordinate (z for AXIS 1, y for AXIS 2)
-    const int x0 = cb * W;
-    for (int e = threadIdx.x; e < total; e += kBlock) {
+    x0 = (g % ncol) * W;
+    o = g / ncol;
+    for (int e = tid; e < W * n; e += kBlock) {
       const int t = e / W, c = e - t * W;
-      size_t a = AXIS == 1 ? ((size_t)o * n + t) * n + x0 + c : ((size_t)t * n + o) * n + x0 + c;
-      line[e] = in[a];
+      const size_t a = AXIS == 1 ? ((size_t)o * n + t) * n + x0 + c : ((size_t)t * n + o) * n + x0 + c;
+      buf[t * ld + c] = in[a];
     }
-    __syncthreads();
-    for (int e = threadIdx.x; e < total; e += kBlock) {
-      const int t = e / W, c = e - t * W;
-      T acc = T(0);
-      int src = t - half;
-      src += src < 0 ? n : 0;
-      for (int m = 0; m < ntaps; m++) {
-        acc += tp[m] * line[src * W + c];
-        src = (src + 1 == n) ? 0 : src + 1;
+  }
+  __syncthreads();
+  T* obuf = buf + (AXIS == 0 ? W * ld : 0);
+  const int groups = n / R;
+  for (int task = tid; task < W * groups; task += kBlock) {
+    const int c = task % W, i0 = (task / W) * R;
+    T acc[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) acc[r] = T(0);
+    int src = i0 - half;
+    src += src < 0 ? n : 0;
+    const int span = ntaps + R - 1;
+    for (int mm = 0; mm < span; mm++) {
+      const T v = AXIS == 0 ? buf[c * ld + src] : buf[src * ld + c];
+      src = (src + 1 == n) ? 0 : src + 1;
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        const int tap = mm - r;
+        if (tap >= 0 && tap < ntaps) acc[r] += taps[tap] * v;
       }
-      size_t a = AXIS == 1 ? ((size_t)o * n + t) * n + x0 + c : ((size_t)t * n + o) * n + x0 + c;
-      out[a] = acc;
+    }
+    if (AXIS == 0) {
+#pragma unroll
+      for (int r = 0; r < R; r++) obuf[c * ld + i0 + r] = acc[r];
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; r++) {
+        const int t = i0 + r;
+        const size_t a = AXIS == 1 ? ((size_t)o * n + t) * n + x0 + c : ((size_t)t * n + o) * n + x0 + c;
+        out[a] = acc[r];
+      }
+    }
+  }
+  if (AXIS == 0) {
+    __syncthreads();
+    for (int e = tid; e < W * n; e += kBlock) {
+      const int r = e / n, i = e - r * n;
+      out[(row0 + r) * n + i] = obuf[r * ld + i];
     }
   }
 }
 
+size_t smooth_lds_bytes(int n, int axis, int W, int ntaps, size_t elem) {
+  const size_t tp = (size_t)((ntaps + 1) & ~1);
+  return (tp + (axis == 0 ? (size_t)2 * W * (n + 1) : (size_t)(W + 1) * n)) * elem;
+}
+
 // ---------------------------------------------------------------------------
 // Constraint at the Verlet prediction (Eq. 17) and multiplier predictor.
+// Reduction kernels run on a capped grid (each workgroup walks one contiguous
+// chunk), so their one-workgroup finalize pass reads few partials.
 // ---------------------------------------------------------------------------
 template <typename TQ>
 __global__ void __launch_bounds__(kBlock)
@@ -81,7 +129,8 @@ k_sigma(int n, double h, const TQ* __restrict__ qs, const double* __restrict__ p
         double* __restrict__ partial, const Ctl* ctl) {
   __shared__ double sh[kBlock / 64];
   const int n3 = n * n * n;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int lo, hi;
+  chunk_range(n3, &lo, &hi);
   const int cold = ctl->cold, m_eff = ctl->m_eff;
   const double* pk = ctl->k_idx ? phi1 : phi0;
   const double* pkm1 = ctl->k_idx ? phi0 : phi1;
@@ -90,13 +139,14 @@ k_sigma(int n, double h, const TQ* __restrict__ qs, const double* __restrict__ p
   const double* y1 = yb[ctl->yh1];
   const double* y2 = yb[ctl->yh2];
   double sv = 0.0, qmax = 0.0;
-  if (t < n3) {
-    const int i = t % n, j = (t / n) % n, k = t / (n * n);
+  const int l2 = __builtin_ctz(n), msk = n - 1;
+  for (int t = lo + threadIdx.x; t < hi; t += kBlock) {
+    const int i = t & msk, j = (t >> l2) & msk, k = t >> (2 * l2);
     const double q = (double)qs[t];
     double s = q;
     if (!cold) {
-      const int im = wrapn(i - 1, n), ip = wrapn(i + 1, n), jm = wrapn(j - 1, n), jp = wrapn(j + 1, n);
-      const int km = wrapn(k - 1, n), kp = wrapn(k + 1, n);
+      const int im = (i - 1) & msk, ip = (i + 1) & msk, jm = (j - 1) & msk, jp = (j + 1) & msk;
+      const int km = (k - 1) & msk, kp = (k + 1) & msk;
       auto P = [&](int a) { return 2.0 * pk[a] - pkm1[a]; };
       const double nb = ((P(nat_idx(n, im, j, k)) + P(nat_idx(n, ip, j, k))) +
                          (P(nat_idx(n, i, jm, k)) + P(nat_idx(n, i, jp, k)))) +
@@ -110,8 +160,8 @@ k_sigma(int n, double h, const TQ* __restrict__ qs, const double* __restrict__ p
     else if (m_eff == 2) yv = 2.0 * y0[t] - y1[t];
     else if (m_eff == 3) yv = 3.0 * y0[t] - 3.0 * y1[t] + y2[t];
     y[t] = yv;
-    sv = s;
-    qmax = fabs(q);
+    sv += s;
+    qmax = fmax(qmax, fabs(q));
   }
   double bs = block_sum(sv, sh);
   double bm = block_max(qmax, sh);
@@ -139,44 +189,53 @@ k_fin_sigma(int nb, int n3, double tol, int tol_mode, const double* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Outer residual of cycle c in FP64 (Eq. 26): y_out = y_in + e (the V-cycle
-// correction, c > 0), r = (sigma - mean) - M y_out; r handed to the next
-// V-cycle in precision T, colour-split.  The last block records the residual,
-// the running mean of y, and the stop decision.
+// Outer residual in FP64 (Eq. 26) for M y = sigma_p.  Cycle 0 forms
+// r = (sigma_p - mean) - M y0 from the predicted multiplier; cycle c > 0
+// applies the V-cycle correction e in FP64, y += e and r -= M e, which equals
+// sigma_p - M y up to FP64 rounding and needs no FP64 stencil.  r goes to the
+// next V-cycle in precision T, colour-split; the finalize pass records the
+// residual, the running mean of y and the stop decision.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_outer(int n, int first, const double* __restrict__ sigma, double* __restrict__ ya,
-        double* __restrict__ yb, const T* __restrict__ e0, const T* __restrict__ e1,
-        T* __restrict__ r0, T* __restrict__ r1, double* __restrict__ partial, const Ctl* ctl) {
+k_outer(int n, int first, const double* __restrict__ sigma, double* __restrict__ y, double* __restrict__ r64,
+        const T* __restrict__ e0, const T* __restrict__ e1, T* __restrict__ r0, T* __restrict__ r1,
+        double* __restrict__ partial, const Ctl* ctl) {
   __shared__ double sh[kBlock / 64];
   if (ctl->done) return;
   const int c = first ? 0 : ctl->cycles + 1;
-  const double* y_in = (c == 0 || ((c - 1) & 1) == 0) ? ya : yb;
-  double* y_out = (c & 1) ? yb : ya;
-  const int n3 = n * n * n;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const CsGeo g(n);
+  const int n3 = n * n * n, msk = n - 1;
+  int lo, hi;
+  chunk_range(n3, &lo, &hi);
+  const double mean_sigma = ctl->mean_sigma;
   double rmax = 0.0, ysum = 0.0;
-  if (t < n3) {
-    const int i = t % n, j = (t / n) % n, k = t / (n * n);
-    const int im = wrapn(i - 1, n), ip = wrapn(i + 1, n), jm = wrapn(j - 1, n), jp = wrapn(j + 1, n);
-    const int km = wrapn(k - 1, n), kp = wrapn(k + 1, n);
-    auto Y = [&](int a, int b, int d) {
-      double v = y_in[nat_idx(n, a, b, d)];
-      if (c > 0) {
+  for (int t = lo + threadIdx.x; t < hi; t += kBlock) {
+    const int i = t & msk, j = (t >> g.l2) & msk, k = t >> (2 * g.l2);
+    const int im = (i - 1) & msk, ip = (i + 1) & msk, jm = (j - 1) & msk, jp = (j + 1) & msk;
+    const int km = (k - 1) & msk, kp = (k + 1) & msk;
+    double r, yv;
+    if (c == 0) {
+      auto Y = [&](int a, int b, int d) { return y[(((d << g.l2) + b) << g.l2) + a]; };
+      yv = y[t];
+      const double nb = ((Y(im, j, k) + Y(ip, j, k)) + (Y(i, jm, k) + Y(i, jp, k))) + (Y(i, j, km) + Y(i, j, kp));
+      r = (sigma[t] - mean_sigma) - (nb - 6.0 * yv);
+    } else {
+      auto E = [&](int a, int b, int d) -> double {
         const T* ec = ((a + b + d) & 1) ? e1 : e0;
-        v += (double)ec[cs_idx(n, a, b, d)];
-      }
-      return v;
-    };
-    const double yc = Y(i, j, k);
-    const double nb = ((Y(im, j, k) + Y(ip, j, k)) + (Y(i, jm, k) + Y(i, jp, k))) + (Y(i, j, km) + Y(i, j, kp));
-    const double r = (sigma[t] - ctl->mean_sigma) - (nb - 6.0 * yc);
-    if (c > 0) y_out[t] = yc;
+        return (double)ec[cs_index(g, a, b, d)];
+      };
+      const double ev = E(i, j, k);
+      const double nb = ((E(im, j, k) + E(ip, j, k)) + (E(i, jm, k) + E(i, jp, k))) + (E(i, j, km) + E(i, j, kp));
+      yv = y[t] + ev;
+      y[t] = yv;
+      r = r64[t] - (nb - 6.0 * ev);
+    }
+    r64[t] = r;
     T* rc = ((i + j + k) & 1) ? r1 : r0;
-    rc[cs_idx(n, i, j, k)] = (T)r;
-    rmax = fabs(r);
-    ysum = yc;
+    rc[cs_index(g, i, j, k)] = (T)r;
+    rmax = fmax(rmax, fabs(r));
+    ysum += yv;
   }
   double bm = block_max(rmax, sh);
   double bs = block_sum(ysum, sh);
@@ -198,7 +257,7 @@ k_fin_outer(int first, int max_cycles, int nb, int n3, const double* __restrict_
     ctl->res_hist[c] = res;
     ctl->mean_y = ys / (double)n3;
     ctl->cycles = c;
-    ctl->final_buf = c & 1;
+    ctl->final_buf = 0;
     if (res <= ctl->thresh) {
       ctl->done = 1;
     } else if (c >= max_cycles) {
@@ -213,22 +272,22 @@ k_fin_outer(int first, int max_cycles, int nb, int n3, const double* __restrict_
 // colour array: m = t % (n/2), row (j,k) = t / (n/2), and the point of
 // colour c is i = 2m + ((c+j+k)&1).  All neighbours of a point have the
 // other colour: x-neighbours at (i+-1)/2 of the same row, y/z neighbours at
-// the same m of the adjacent rows.
+// the same m of the adjacent rows, i.e. at t +- n/2 and t +- n^2/2.  Every
+// level has a power-of-two edge, so indices are shifts and masks.
 // ---------------------------------------------------------------------------
+// Sum of the six neighbours (other colour array o) of the point at
+// colour-split index t with x = 2m + s in row (j,k), in the fixed order
+// ((x- + x+) + (y- + y+)) + (z- + z+).
 template <typename T>
-__device__ __forceinline__ T nbr6(const T* __restrict__ o, int n, int i, int j, int k) {
-  const int im = wrapn(i - 1, n), ip = wrapn(i + 1, n), jm = wrapn(j - 1, n), jp = wrapn(j + 1, n);
-  const int km = wrapn(k - 1, n), kp = wrapn(k + 1, n);
-  return ((o[cs_idx(n, im, j, k)] + o[cs_idx(n, ip, j, k)]) + (o[cs_idx(n, i, jm, k)] + o[cs_idx(n, i, jp, k)])) +
-         (o[cs_idx(n, i, j, km)] + o[cs_idx(n, i, j, kp)]);
-}
-
-__device__ __forceinline__ void decode_half(int t, int n, int* m, int* j, int* k) {
-  const int hn = n >> 1;
-  *m = t % hn;
-  const int row = t / hn;
-  *j = row % n;
-  *k = row / n;
+__device__ __forceinline__ T cs_nbr6(const T* __restrict__ o, const CsGeo& g, int t, int m, int j, int k, int s) {
+  const int row = t - m;
+  const int xm = s ? m : (m == 0 ? g.hn - 1 : m - 1);
+  const int xp = s ? (m + 1 == g.hn ? 0 : m + 1) : m;
+  const int ym = j == 0 ? t + (g.n - 1) * g.hn : t - g.hn;
+  const int yp = j == g.n - 1 ? t - (g.n - 1) * g.hn : t + g.hn;
+  const int zm = k == 0 ? t + (g.n - 1) * g.plane : t - g.plane;
+  const int zp = k == g.n - 1 ? t - (g.n - 1) * g.plane : t + g.plane;
+  return ((o[row + xm] + o[row + xp]) + (o[ym] + o[yp])) + (o[zm] + o[zp]);
 }
 
 // Kernels below carry a FIN template flag that is 1 only on the finest level,
@@ -240,18 +299,24 @@ __global__ void __launch_bounds__(kBlock)
 k_sweep_zero(int n, const T* __restrict__ r0, const T* __restrict__ r1, T* __restrict__ e0,
              T* __restrict__ e1, const Ctl* ctl) {
   if (ctl->done) return;
-  const int half = n * n * n / 2;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const CsGeo g(n);
+  const int half = n * g.hn * n;
+  const int t = xcd_block() * blockDim.x + threadIdx.x;
   if (t >= half) return;
   int m, j, k;
-  decode_half(t, n, &m, &j, &k);
+  cs_decode(g, t, &m, &j, &k);
   const T sixth = T(1.0 / 6.0);
   e0[t] = -r0[t] * sixth;
-  const int ib = 2 * m + ((1 + j + k) & 1);
-  const int im = wrapn(ib - 1, n), ip = wrapn(ib + 1, n), jm = wrapn(j - 1, n), jp = wrapn(j + 1, n);
-  const int km = wrapn(k - 1, n), kp = wrapn(k + 1, n);
-  auto R = [&](int a, int b, int d) { return -r0[cs_idx(n, a, b, d)] * sixth; };
-  const T nb = ((R(im, j, k) + R(ip, j, k)) + (R(ib, jm, k) + R(ib, jp, k))) + (R(ib, j, km) + R(ib, j, kp));
+  const int s = (1 + j + k) & 1;
+  const int row = t - m;
+  const int xm = s ? m : (m == 0 ? g.hn - 1 : m - 1);
+  const int xp = s ? (m + 1 == g.hn ? 0 : m + 1) : m;
+  const int ym = j == 0 ? t + (g.n - 1) * g.hn : t - g.hn;
+  const int yp = j == g.n - 1 ? t - (g.n - 1) * g.hn : t + g.hn;
+  const int zm = k == 0 ? t + (g.n - 1) * g.plane : t - g.plane;
+  const int zp = k == g.n - 1 ? t - (g.n - 1) * g.plane : t + g.plane;
+  auto R = [&](int a) { return -r0[a] * sixth; };
+  const T nb = ((R(row + xm) + R(row + xp)) + (R(ym) + R(yp))) + (R(zm) + R(zp));
   e1[t] = (nb - r1[t]) * sixth;
 }
 
@@ -260,19 +325,13 @@ __global__ void __launch_bounds__(kBlock)
 k_halfsweep(int n, int colour, T* __restrict__ ec, const T* __restrict__ eo, const T* __restrict__ rc,
             const Ctl* ctl) {
   if (ctl->done) return;
-  const int half = n * n * n / 2;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const CsGeo g(n);
+  const int half = n * g.hn * n;
+  const int t = xcd_block() * blockDim.x + threadIdx.x;
   if (t >= half) return;
   int m, j, k;
-  decode_half(t, n, &m, &j, &k);
-  const int i = 2 * m + ((colour + j + k) & 1);
-  ec[t] = (nbr6(eo, n, i, j, k) - rc[t]) * T(1.0 / 6.0);
-}
-
-template <typename T>
-__device__ __forceinline__ T cs_load(const T* __restrict__ c0, const T* __restrict__ c1, int n, int i, int j, int k) {
-  const T* a = ((i + j + k) & 1) ? c1 : c0;
-  return a[cs_idx(n, i, j, k)];
+  cs_decode(g, t, &m, &j, &k);
+  ec[t] = (cs_nbr6(eo, g, t, m, j, k, (colour + j + k) & 1) - rc[t]) * T(1.0 / 6.0);
 }
 
 // Residual rho = r - M e at the 27 fine points around 2I, full weighting,
@@ -286,72 +345,74 @@ k_resid_restrict(int n, int red_only, const T* __restrict__ e0, const T* __restr
                  const T* __restrict__ r0, const T* __restrict__ r1, T* __restrict__ rc0, T* __restrict__ rc1,
                  const Ctl* ctl) {
   if (ctl->done) return;
-  const int nc = n >> 1;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const CsGeo g(n), gc(n >> 1);
+  const int nc = gc.n;
+  const int t = xcd_block() * blockDim.x + threadIdx.x;
   if (t >= nc * nc * nc) return;
-  const int I = t % nc, J = (t / nc) % nc, K = t / (nc * nc);
+  const int I = t & (nc - 1), J = (t >> gc.l2) & (nc - 1), K = t >> (2 * gc.l2);
   const T wt[3] = {T(0.25), T(0.5), T(0.25)};
+  const int msk = n - 1;
   T s = T(0);
   for (int c = -1; c <= 1; c++) {
-    const int z = wrapn(2 * K + c, n);
+    const int z = (2 * K + c) & msk;
     for (int b = -1; b <= 1; b++) {
-      const int y = wrapn(2 * J + b, n);
+      const int y = (2 * J + b) & msk;
       T row = T(0);
       for (int a = -1; a <= 1; a++) {
-        const int x = wrapn(2 * I + a, n);
-        const bool odd = (x + y + z) & 1;
+        const int x = (2 * I + a) & msk;
+        const int odd = (x + y + z) & 1;
         if (red_only && odd) continue;
-        const T* eo = odd ? e0 : e1;     // neighbours have the other colour
-        const T ev = odd ? e1[cs_idx(n, x, y, z)] : e0[cs_idx(n, x, y, z)];
-        const T rv = odd ? r1[cs_idx(n, x, y, z)] : r0[cs_idx(n, x, y, z)];
-        const T rho = rv - (nbr6(eo, n, x, y, z) - T(6) * ev);
+        const int ti = cs_index(g, x, y, z);
+        const T ev = odd ? e1[ti] : e0[ti];
+        const T rv = odd ? r1[ti] : r0[ti];
+        const T rho = rv - (cs_nbr6(odd ? e0 : e1, g, ti, x >> 1, y, z, x & 1) - T(6) * ev);
         row += wt[a + 1] * rho;
       }
       s += wt[b + 1] * wt[c + 1] * row;
     }
   }
   T* out = ((I + J + K) & 1) ? rc1 : rc0;
-  out[cs_idx(nc, I, J, K)] = T(4) * s;
+  out[cs_index(gc, I, J, K)] = T(4) * s;
 }
 
-// Trilinear interpolation of the coarse correction at fine point (x,y,z).
+// Trilinear interpolation of the coarse correction (colour-split, geometry
+// gc) at fine point (x,y,z).
 template <typename T>
-__device__ __forceinline__ T prolong_at(const T* __restrict__ c0, const T* __restrict__ c1, int nc, int x,
+__device__ __forceinline__ T prolong_at(const T* __restrict__ c0, const T* __restrict__ c1, const CsGeo& gc, int x,
                                         int y, int z) {
+  const int cm = gc.n - 1;
   const int x0 = x >> 1, y0 = y >> 1, z0 = z >> 1;
-  const int x1 = (x & 1) ? (x0 + 1 == nc ? 0 : x0 + 1) : x0;
-  const int y1 = (y & 1) ? (y0 + 1 == nc ? 0 : y0 + 1) : y0;
-  const int z1 = (z & 1) ? (z0 + 1 == nc ? 0 : z0 + 1) : z0;
+  const int x1 = (x & 1) ? ((x0 + 1) & cm) : x0;
+  const int y1 = (y & 1) ? ((y0 + 1) & cm) : y0;
+  const int z1 = (z & 1) ? ((z0 + 1) & cm) : z0;
   const T hx = (x & 1) ? T(0.5) : T(1), hy = (y & 1) ? T(0.5) : T(1), hz = (z & 1) ? T(0.5) : T(1);
   T s = T(0);
   const int xs[2] = {x0, x1}, ys[2] = {y0, y1}, zs[2] = {z0, z1};
   const int nx = (x & 1) ? 2 : 1, ny = (y & 1) ? 2 : 1, nz = (z & 1) ? 2 : 1;
   for (int c = 0; c < nz; c++)
     for (int b = 0; b < ny; b++)
-      for (int a = 0; a < nx; a++) s += hx * hy * hz * cs_load(c0, c1, nc, xs[a], ys[b], zs[c]);
+      for (int a = 0; a < nx; a++) {
+        const T* arr = ((xs[a] + ys[b] + zs[c]) & 1) ? c1 : c0;
+        s += hx * hy * hz * arr[cs_index(gc, xs[a], ys[b], zs[c])];
+      }
   return s;
 }
 
 // After prolongation the next red half-sweep overwrites every red value and
-// only reads corrected black neighbours, so the correction of black points is
-// applied on the fly here and the red values are written directly.
+// reads only black neighbours, so only the black points receive the
+// trilinear correction here; the red half-sweep follows.
 template <typename T, int FIN>
 __global__ void __launch_bounds__(kBlock)
-k_prolong_red(int n, T* __restrict__ e0, const T* __restrict__ e1, const T* __restrict__ ec0,
-              const T* __restrict__ ec1, const T* __restrict__ r0, const Ctl* ctl) {
+k_prolong_black(int n, T* __restrict__ e1, const T* __restrict__ ec0, const T* __restrict__ ec1, const Ctl* ctl) {
   if (ctl->done) return;
-  const int half = n * n * n / 2;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const CsGeo g(n), gc(n >> 1);
+  const int half = n * g.hn * n;
+  const int t = xcd_block() * blockDim.x + threadIdx.x;
   if (t >= half) return;
   int m, j, k;
-  decode_half(t, n, &m, &j, &k);
-  const int i = 2 * m + ((j + k) & 1);
-  const int nc = n >> 1;
-  const int im = wrapn(i - 1, n), ip = wrapn(i + 1, n), jm = wrapn(j - 1, n), jp = wrapn(j + 1, n);
-  const int km = wrapn(k - 1, n), kp = wrapn(k + 1, n);
-  auto B = [&](int a, int b, int d) { return e1[cs_idx(n, a, b, d)] + prolong_at(ec0, ec1, nc, a, b, d); };
-  const T nb = ((B(im, j, k) + B(ip, j, k)) + (B(i, jm, k) + B(i, jp, k))) + (B(i, j, km) + B(i, j, kp));
-  e0[t] = (nb - r0[t]) * T(1.0 / 6.0);
+  cs_decode(g, t, &m, &j, &k);
+  const int ib = 2 * m + ((1 + j + k) & 1);
+  e1[t] += prolong_at(ec0, ec1, gc, ib, j, k);
 }
 
 template <typename T>
@@ -359,22 +420,22 @@ __global__ void __launch_bounds__(kBlock)
 k_prolong_add(int n, T* __restrict__ e0, T* __restrict__ e1, const T* __restrict__ ec0,
               const T* __restrict__ ec1, const Ctl* ctl) {
   if (ctl->done) return;
-  const int half = n * n * n / 2;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const CsGeo g(n), gc(n >> 1);
+  const int half = n * g.hn * n;
+  const int t = xcd_block() * blockDim.x + threadIdx.x;
   if (t >= half) return;
   int m, j, k;
-  decode_half(t, n, &m, &j, &k);
-  const int nc = n >> 1;
+  cs_decode(g, t, &m, &j, &k);
   const int ir = 2 * m + ((j + k) & 1), ib = 2 * m + ((1 + j + k) & 1);
-  e0[t] += prolong_at(ec0, ec1, nc, ir, j, k);
-  e1[t] += prolong_at(ec0, ec1, nc, ib, j, k);
+  e0[t] += prolong_at(ec0, ec1, gc, ir, j, k);
+  e1[t] += prolong_at(ec0, ec1, gc, ib, j, k);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_fill_zero(int64_t count, T* __restrict__ a, T* __restrict__ b,
                                                       const Ctl* ctl) {
   if (ctl->done) return;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
   if (t < count) {
     a[t] = T(0);
     b[t] = T(0);
@@ -546,7 +607,7 @@ __global__ void __launch_bounds__(kBlock)
 k_phi_update(int n3, double h, double* __restrict__ phi0, double* __restrict__ phi1,
              const double* __restrict__ ya, const double* __restrict__ yb, double* __restrict__ yh0,
              double* __restrict__ yh1, double* __restrict__ yh2, float* __restrict__ phi32, const Ctl* ctl) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = xcd_block() * blockDim.x + threadIdx.x;
   if (t >= n3) return;
   const int cold = ctl->cold;
   double* pk = ctl->k_idx ? phi1 : phi0;
@@ -589,6 +650,12 @@ template <typename T>
 __global__ void k_widen(int64_t count, const T* __restrict__ in, double* __restrict__ out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < count) out[t] = (double)in[t];
+}
+
+template <typename T>
+__device__ __forceinline__ T cs_load(const T* __restrict__ c0, const T* __restrict__ c1, int n, int i, int j, int k) {
+  const T* a = ((i + j + k) & 1) ? c1 : c0;
+  return a[cs_idx(n, i, j, k)];
 }
 
 template <typename T>
@@ -636,9 +703,8 @@ void launch_restrict(int n, int red_only, const T* e0, const T* e1, const T* r0,
                      red_only, e0, e1, r0, r1, rc0, rc1, ctl);
 }
 template <typename T, int FIN>
-void launch_prolong_red(int n, int nb, T* e0, const T* e1, const T* c0, const T* c1, const T* r0, Ctl* ctl,
-                        hipStream_t s) {
-  hipLaunchKernelGGL((k_prolong_red<T, FIN>), dim3(nb), dim3(kBlock), 0, s, n, e0, e1, c0, c1, r0, ctl);
+void launch_prolong_black(int n, int nb, T* e1, const T* c0, const T* c1, Ctl* ctl, hipStream_t s) {
+  hipLaunchKernelGGL((k_prolong_black<T, FIN>), dim3(nb), dim3(kBlock), 0, s, n, e1, c0, c1, ctl);
 }
 
 template <typename T>
@@ -690,14 +756,10 @@ hipError_t vcycle_impl(const LevelBufs* lv, int levels, int tail, int nu1, int n
     const T *c0 = (const T*)lv[l + 1].e0, *c1 = (const T*)lv[l + 1].e1;
     if (nu2 >= 1) {
       kt_begin(KT_PROLONG, l, s);
-      if (l == 0) launch_prolong_red<T, 1>(n, nb, e0, e1, c0, c1, r0, ctl, s);
-      else launch_prolong_red<T, 0>(n, nb, e0, e1, c0, c1, r0, ctl, s);
-      kt_end(KT_PROLONG, l, 1.625 * ts * n3, s);
-      kt_begin(KT_HALFSWEEP, l, s);
-      if (l == 0) launch_half<T, 1>(n, nb, 1, e1, e0, r1, ctl, s);
-      else launch_half<T, 0>(n, nb, 1, e1, e0, r1, ctl, s);
-      kt_end(KT_HALFSWEEP, l, 1.5 * ts * n3, s);
-      for (int it = 1; it < nu2; it++) {
+      if (l == 0) launch_prolong_black<T, 1>(n, nb, e1, c0, c1, ctl, s);
+      else launch_prolong_black<T, 0>(n, nb, e1, c0, c1, ctl, s);
+      kt_end(KT_PROLONG, l, 1.125 * ts * n3, s);
+      for (int it = 0; it < nu2; it++) {
         for (int colour = 0; colour < 2; colour++) {
           T* ec = colour ? e1 : e0;
           const T* eo = colour ? e0 : e1;
@@ -741,8 +803,8 @@ hipError_t one_kernel(int kid, const LevelBufs* lv, int levels, int tail, int nu
       break;
     case KT_PROLONG:
       if (tail == 0) return hipErrorInvalidValue;
-      launch_prolong_red<T, 1>(n, nb, e0, e1, (const T*)lv[1].e0, (const T*)lv[1].e1, r0, ctl, s);
-      *bytes = 1.625 * ts * n3;
+      launch_prolong_black<T, 1>(n, nb, e1, (const T*)lv[1].e0, (const T*)lv[1].e1, ctl, s);
+      *bytes = 1.125 * ts * n3;
       break;
     case KT_TAIL: {
       const int lt = levels - tail;
@@ -761,61 +823,60 @@ hipError_t one_kernel(int kid, const LevelBufs* lv, int levels, int tail, int nu
 
 }  // namespace
 
+// smoothing launch shape: W lines per workgroup, R outputs per thread
+constexpr int kSmoothW = 4;
+constexpr int kSmoothR = 4;
+
 hipError_t launch_smooth(bool fp64, int n, int axis, int ntaps, int half, const void* taps, const void* in,
                          void* out, hipStream_t s) {
-  const size_t elem = fp64 ? 8 : 4;
-  int W;
-  dim3 grid;
-  if (axis == 0) {
-    W = n >= 256 ? 2 : (n >= 64 ? 4 : 8);
-    W = W > n * n ? n * n : W;
-    grid = dim3((unsigned)((size_t)n * n / W));
-  } else {
-    W = n >= 16 ? 16 : n;
-    grid = dim3((unsigned)((n / W) * n));
-  }
-  const size_t lds = ((size_t)W * n + ntaps) * elem;
-#define P3MZ_SMOOTH_LAUNCH(TT, AX, WW)                                                             \
-  hipLaunchKernelGGL((k_smooth<TT, AX, WW>), grid, dim3(kBlock), lds, s, n, ntaps, half, (const TT*)taps, \
-                     (const TT*)in, (TT*)out)
-  if (axis == 0) {
-    if (fp64) {
-      if (W == 2) P3MZ_SMOOTH_LAUNCH(double, 0, 2); else if (W == 4) P3MZ_SMOOTH_LAUNCH(double, 0, 4); else P3MZ_SMOOTH_LAUNCH(double, 0, 8);
-    } else {
-      if (W == 2) P3MZ_SMOOTH_LAUNCH(float, 0, 2); else if (W == 4) P3MZ_SMOOTH_LAUNCH(float, 0, 4); else P3MZ_SMOOTH_LAUNCH(float, 0, 8);
-    }
-  } else if (axis == 1) {
-    if (W != 16 && W != 8) return hipErrorInvalidValue;
-    if (fp64) { if (W == 16) P3MZ_SMOOTH_LAUNCH(double, 1, 16); else P3MZ_SMOOTH_LAUNCH(double, 1, 8); }
-    else { if (W == 16) P3MZ_SMOOTH_LAUNCH(float, 1, 16); else P3MZ_SMOOTH_LAUNCH(float, 1, 8); }
-  } else {
-    if (W != 16 && W != 8) return hipErrorInvalidValue;
-    if (fp64) { if (W == 16) P3MZ_SMOOTH_LAUNCH(double, 2, 16); else P3MZ_SMOOTH_LAUNCH(double, 2, 8); }
-    else { if (W == 16) P3MZ_SMOOTH_LAUNCH(float, 2, 16); else P3MZ_SMOOTH_LAUNCH(float, 2, 8); }
-  }
-#undef P3MZ_SMOOTH_LAUNCH
+  if (!fp64) return hipErrorInvalidValue;   // the charge source is FP64 in both modes
+  const int W = kSmoothW;
+  if (n % W || n % kSmoothR) return hipErrorInvalidValue;
+  const dim3 grid = axis == 0 ? dim3((unsigned)((size_t)n * n / W)) : dim3((unsigned)((n / W) * n));
+  const size_t lds = smooth_lds_bytes(n, axis, W, ntaps, 8);
+  if (axis == 0)
+    hipLaunchKernelGGL((k_smooth<double, 0, kSmoothW, kSmoothR>), grid, dim3(kBlock), lds, s, n, ntaps, half,
+                       (const double*)taps, (const double*)in, (double*)out);
+  else if (axis == 1)
+    hipLaunchKernelGGL((k_smooth<double, 1, kSmoothW, kSmoothR>), grid, dim3(kBlock), lds, s, n, ntaps, half,
+                       (const double*)taps, (const double*)in, (double*)out);
+  else
+    hipLaunchKernelGGL((k_smooth<double, 2, kSmoothW, kSmoothR>), grid, dim3(kBlock), lds, s, n, ntaps, half,
+                       (const double*)taps, (const double*)in, (double*)out);
   return hipGetLastError();
+}
+
+hipError_t smooth_configure(int n) {
+  const int bytes = (int)smooth_lds_bytes(n, 0, kSmoothW, n, 8);
+  hipError_t e = hipFuncSetAttribute((const void*)k_smooth<double, 0, kSmoothW, kSmoothR>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_smooth<double, 1, kSmoothW, kSmoothR>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_smooth<double, 2, kSmoothW, kSmoothR>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 hipError_t launch_sigma(int n, double h, const double* qs, const double* phi0, const double* phi1,
                         const double* yb0, const double* yb1, const double* yb2, double* sigma, double* y,
                         double tol, int tol_mode, double* partial, Ctl* ctl, hipStream_t s) {
-  const int n3 = n * n * n, nb = blocks_for(n3, kBlock);
+  const int n3 = n * n * n, nb = red_blocks(n3);
   hipLaunchKernelGGL(k_sigma<double>, dim3(nb), dim3(kBlock), 0, s, n, h, qs, phi0, phi1, yb0, yb1, yb2, sigma, y,
                      partial, ctl);
   hipLaunchKernelGGL(k_fin_sigma, dim3(1), dim3(kBlock), 0, s, nb, n3, tol, tol_mode, partial, ctl);
   return hipGetLastError();
 }
 
-hipError_t launch_outer(bool fp64, int n, int first, int max_cycles, const double* sigma, double* ya, double* yb,
+hipError_t launch_outer(bool fp64, int n, int first, int max_cycles, const double* sigma, double* y, double* r64,
                         const void* e0, const void* e1, void* r0, void* r1, double* partial, Ctl* ctl,
                         hipStream_t s) {
-  const int n3 = n * n * n, nb = blocks_for(n3, kBlock);
+  const int n3 = n * n * n, nb = red_blocks(n3);
   if (fp64)
-    hipLaunchKernelGGL(k_outer<double>, dim3(nb), dim3(kBlock), 0, s, n, first, sigma, ya, yb, (const double*)e0,
+    hipLaunchKernelGGL(k_outer<double>, dim3(nb), dim3(kBlock), 0, s, n, first, sigma, y, r64, (const double*)e0,
                        (const double*)e1, (double*)r0, (double*)r1, partial, ctl);
   else
-    hipLaunchKernelGGL(k_outer<float>, dim3(nb), dim3(kBlock), 0, s, n, first, sigma, ya, yb, (const float*)e0,
+    hipLaunchKernelGGL(k_outer<float>, dim3(nb), dim3(kBlock), 0, s, n, first, sigma, y, r64, (const float*)e0,
                        (const float*)e1, (float*)r0, (float*)r1, partial, ctl);
   hipLaunchKernelGGL(k_fin_outer, dim3(1), dim3(kBlock), 0, s, first, max_cycles, nb, n3, partial, ctl);
   return hipGetLastError();

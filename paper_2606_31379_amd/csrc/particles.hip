@@ -1,5 +1,7 @@
 // Particle-side kernels: binning, deterministic bin sort, owner-computes
 // charge spread, force/energy gather and the short-range pair term.
+#include <algorithm>
+
 #include "launch.h"
 
 namespace {
@@ -79,30 +81,78 @@ k_bin_cells(int n_atoms, const double* __restrict__ pos, double box, int nc, int
   slot[a] = atomicAdd(&count[k], 1);
 }
 
-// Single-workgroup exclusive scan (1024 threads, contiguous chunk per thread).
-__global__ void __launch_bounds__(1024) k_scan(int nbins, int* __restrict__ count, int* __restrict__ start) {
+// Exclusive scan of the bin counts in three passes: per-chunk sums, one
+// workgroup scanning the chunk sums, then each chunk rescanned with its
+// offset (integers: exact and order-independent).  Counts are zeroed for
+// the next binning.
+constexpr int kScanPer = 16;                     // counts per thread
+constexpr int kScanChunk = kBlock * kScanPer;    // counts per workgroup
+
+__global__ void __launch_bounds__(kBlock) k_scan_sums(int nbins, const int* __restrict__ count, int* __restrict__ bsum) {
+  __shared__ int sh[kBlock];
+  const int base = blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
+  int s = 0;
+  for (int q = 0; q < kScanPer; q++) s += base + q < nbins ? count[base + q] : 0;
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(1024) k_scan_top(int nb, int* __restrict__ bsum) {
   __shared__ int sh[1024];
   const int t = threadIdx.x;
-  const int chunk = (nbins + 1023) / 1024;
-  const int b0 = t * chunk, b1 = min(nbins, b0 + chunk);
+  const int per = (nb + 1023) / 1024;
+  const int b0 = t * per, b1 = min(nb, b0 + per);
   int local = 0;
-  for (int b = b0; b < b1; b++) local += count[b];
+  for (int b = b0; b < b1; b++) local += bsum[b];
   sh[t] = local;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
-    int v = (t >= off) ? sh[t - off] : 0;
+    const int v = t >= off ? sh[t - off] : 0;
     __syncthreads();
     sh[t] += v;
     __syncthreads();
   }
-  int run = sh[t] - local;   // exclusive prefix of this chunk
+  int run = sh[t] - local;
   for (int b = b0; b < b1; b++) {
-    int c = count[b];
-    start[b] = run;
-    run += c;
-    count[b] = 0;
+    const int v = bsum[b];
+    bsum[b] = run;
+    run += v;
   }
-  if (t == 1023) start[nbins] = sh[1023];
+  if (t == 1023) bsum[nb] = sh[1023];
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_scan_fill(int nbins, int* __restrict__ count, int* __restrict__ start, const int* __restrict__ bsum, int nb) {
+  __shared__ int sh[kBlock];
+  const int base = blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
+  int v[kScanPer];
+  int s = 0;
+  for (int q = 0; q < kScanPer; q++) {
+    v[q] = base + q < nbins ? count[base + q] : 0;
+    s += v[q];
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < kBlock; off <<= 1) {
+    const int u = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += u;
+    __syncthreads();
+  }
+  int run = bsum[blockIdx.x] + sh[threadIdx.x] - s;
+  for (int q = 0; q < kScanPer; q++) {
+    if (base + q < nbins) {
+      start[base + q] = run;
+      count[base + q] = 0;
+    }
+    run += v[q];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) start[nbins] = bsum[nb];
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -209,9 +259,8 @@ k_gather(int n_atoms, int n, int p, double h, double k_e, const int* __restrict_
   __shared__ double sh[kBlock / 64];
   // the new potential: written over phi^k on a cold solve, over phi^{k-1} otherwise
   const TP* phi = (ctl->cold ? ctl->k_idx : 1 - ctl->k_idx) ? phi1 : phi0;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
   double e_atom = 0.0;
-  if (t < n_atoms) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n_atoms; t += gridDim.x * blockDim.x) {
     const int a = perm[t];
     const int pe = p + 2;
     T wx[P3MZ_MAX_ORDER + 2], wy[P3MZ_MAX_ORDER + 2], wz[P3MZ_MAX_ORDER + 2];
@@ -258,7 +307,7 @@ k_gather(int n_atoms, int n, int p, double h, double k_e, const int* __restrict_
       force[3 * a + 1] = -kq * fy;
       force[3 * a + 2] = -kq * fz;
     }
-    e_atom = 0.5 * kq * pot;
+    e_atom += 0.5 * kq * pot;
   }
   double bs = block_sum(e_atom, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = bs;
@@ -297,12 +346,12 @@ k_sr(int n_atoms, const double* __restrict__ pos, const double* __restrict__ qa,
      double alpha, double rc2, double k_e, int nc, int excl_group, const int* __restrict__ cstart,
      const int* __restrict__ cperm, double* __restrict__ force, double* __restrict__ partial) {
   __shared__ double sh[kBlock / 64];
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
-  double en = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
-  int i = -1;
-  if (wave < n_atoms) {
-    i = cperm[wave];
+  const int nwaves = gridDim.x * (kBlock / 64);
+  double en = 0.0;
+  for (int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; wave < n_atoms; wave += nwaves) {
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    const int i = cperm[wave];
     const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
     const double qi = qa[i];
     const double inv_box = 1.0 / box;
@@ -360,19 +409,17 @@ k_sr(int n_atoms, const double* __restrict__ pos, const double* __restrict__ qa,
         en += -0.5 * qq * er / r;
       }
     }
-  }
-  fx = wave_sum(fx);
-  fy = wave_sum(fy);
-  fz = wave_sum(fz);
-  en = wave_sum(en);
-  if (lane == 0) {
-    if (i >= 0 && force) {
+    fx = wave_sum(fx);
+    fy = wave_sum(fy);
+    fz = wave_sum(fz);
+    if (lane == 0 && force) {
       force[3 * i] += fx;
       force[3 * i + 1] += fy;
       force[3 * i + 2] += fz;
     }
-    sh[threadIdx.x >> 6] = en;
   }
+  en = wave_sum(en);
+  if (lane == 0) sh[threadIdx.x >> 6] = en;
   __syncthreads();
   if (threadIdx.x == 0) {
     double s = 0.0;
@@ -404,8 +451,13 @@ hipError_t launch_bin_cells(int n_atoms, const double* pos, double box, int nc, 
   return hipGetLastError();
 }
 
-hipError_t launch_scan(int nbins, int* count, int* start, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, nbins, count, start);
+int scan_partials(int nbins) { return (nbins + kScanChunk - 1) / kScanChunk + 1; }
+
+hipError_t launch_scan(int nbins, int* count, int* start, int* bsum, hipStream_t s) {
+  const int nb = (nbins + kScanChunk - 1) / kScanChunk;
+  hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(kBlock), 0, s, nbins, count, bsum);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, nb, bsum);
+  hipLaunchKernelGGL(k_scan_fill, dim3(nb), dim3(kBlock), 0, s, nbins, count, start, bsum, nb);
   return hipGetLastError();
 }
 
@@ -440,7 +492,7 @@ hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, double h, double 
                          const int* base, const void* w, const double* qa, const double* phi0,
                          const double* phi1, const float* phi32, double* force, double* partial, Ctl* ctl,
                          hipStream_t s) {
-  const int nb = blocks_for(n_atoms, kBlock);
+  const int nb = std::min(blocks_for(n_atoms, kBlock), kMaxRedBlocks);
   if (fp64)
     hipLaunchKernelGGL((k_gather<double, double>), dim3(nb), dim3(kBlock), 0, s, n_atoms, n, p, h, k_e,
                        perm, base, (const double*)w, qa, phi0, phi1, force, partial, ctl);
@@ -455,7 +507,7 @@ hipError_t launch_sr(int n_atoms, const double* pos, const double* qa, double bo
                      double r_cut, double k_e, int nc, int excl_group, const int* cstart,
                      const int* cperm, double* force, double e_self, double* energy_out,
                      double* partial, Ctl* ctl, hipStream_t s) {
-  const int nb = blocks_for((int64_t)n_atoms * 64, kBlock);
+  const int nb = std::min(blocks_for((int64_t)n_atoms * 64, kBlock), 2 * kMaxRedBlocks);
   hipLaunchKernelGGL(k_sr, dim3(nb), dim3(kBlock), 0, s, n_atoms, pos, qa, box, alpha, r_cut * r_cut, k_e, nc,
                      excl_group, cstart, cperm, force, partial);
   hipLaunchKernelGGL(k_fin_energy, dim3(1), dim3(kBlock), 0, s, nb, partial, ctl, e_self, energy_out);

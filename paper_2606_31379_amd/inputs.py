@@ -66,23 +66,28 @@ def hard_core_points(rng: np.random.Generator, n: int, box: float, dmin: float,
     """Uniform random points in a periodic cube, no pair closer than ``dmin``.
 
     Batched random sequential addition: each round draws a batch of uniform
-    candidates, drops those within ``dmin`` (minimum image) of an accepted
-    point, and of every conflicting pair inside the batch keeps only the
-    lower-indexed candidate.  Accepted points keep their draw order.
+    candidates, drops those within ``dmin`` (minimum image) of a point
+    accepted in an earlier round, and of every conflicting pair inside the
+    batch keeps only the lower-indexed candidate.  Accepted points keep their
+    draw order.  One KD-tree is built per round over that round's points.
     """
-    acc = np.zeros((0, 3))
+    chunks: list[np.ndarray] = []
+    trees: list[cKDTree] = []
+    have = 0
     for _ in range(max_rounds):
-        need = n - acc.shape[0]
+        need = n - have
         if need <= 0:
             break
         m = int(need * 1.5) + 64
         cand = rng.uniform(0.0, box, size=(m, 3))
         cand = np.minimum(cand, np.nextafter(box, 0.0))
         ok = np.ones(m, dtype=bool)
-        if acc.shape[0]:
-            tree = cKDTree(acc, boxsize=box)
-            d, _ = tree.query(cand, k=1, distance_upper_bound=dmin)
-            ok &= ~(d < dmin)
+        for tree in trees:
+            idx = np.nonzero(ok)[0]
+            if idx.size == 0:
+                break
+            d, _ = tree.query(cand[idx], k=1, distance_upper_bound=dmin)
+            ok[idx[d < dmin]] = False
         idx = np.nonzero(ok)[0]
         if idx.size > 1:
             ct = cKDTree(cand[idx], boxsize=box)
@@ -92,10 +97,14 @@ def hard_core_points(rng: np.random.Generator, n: int, box: float, dmin: float,
                 keep = np.ones(idx.size, dtype=bool)
                 keep[drop] = False
                 idx = idx[keep]
-        acc = np.concatenate([acc, cand[idx[:need]]], axis=0)
-    if acc.shape[0] < n:
+        new = cand[idx[:need]]
+        if new.shape[0]:
+            chunks.append(new)
+            trees.append(cKDTree(new, boxsize=box))
+            have += new.shape[0]
+    if have < n:
         raise RuntimeError(f"could not place {n} points with separation {dmin} in box {box}")
-    return acc
+    return np.concatenate(chunks, axis=0)
 
 
 def maxwell_boltzmann(rng: np.random.Generator, masses: np.ndarray, temp_k: float) -> np.ndarray:
@@ -148,19 +157,31 @@ def water(n_mol: int, box: float, temp_k: float, seed: int, r_oh: float = 1.0,
         return opos[:, None, :] + np.einsum("mij,aj->mai", rmats, tmpl)
 
     pos = build(rot)
+    check = np.arange(n_mol)          # molecules whose contacts must be (re)checked
     for _ in range(max_rounds):
         flat = np.mod(pos.reshape(-1, 3), box)
         flat = np.minimum(flat, np.nextafter(box, 0.0))
         tree = cKDTree(flat, boxsize=box)
-        pairs = tree.query_pairs(d_inter, output_type="ndarray")
-        if pairs.size:
-            inter = mol_id[pairs[:, 0]] != mol_id[pairs[:, 1]]
-            pairs = pairs[inter]
-        if pairs.size == 0:
+        if check.size == n_mol:
+            pairs = tree.query_pairs(d_inter, output_type="ndarray")
+            pairs = pairs[mol_id[pairs[:, 0]] != mol_id[pairs[:, 1]]] if pairs.size else pairs
+            bad = np.unique(mol_id[pairs.ravel()]) if pairs.size else np.zeros(0, dtype=int)
+        else:
+            atoms = (3 * check[:, None] + np.arange(3)[None, :]).ravel()
+            hits = tree.query_ball_point(flat[atoms], d_inter, return_sorted=False)
+            found = set()
+            for a, lst in zip(atoms, hits):
+                ma = mol_id[a]
+                for b in lst:
+                    if mol_id[b] != ma:
+                        found.add(int(ma))
+                        found.add(int(mol_id[b]))
+            bad = np.array(sorted(found), dtype=int)
+        if bad.size == 0:
             break
-        bad = np.unique(np.concatenate([mol_id[pairs[:, 0]], mol_id[pairs[:, 1]]]))
         rot[bad] = _random_rotations(rng, bad.size)
         pos = build(rot)
+        check = bad
     else:
         raise RuntimeError("could not orient water molecules without overlaps")
     pos = pos.reshape(-1, 3)

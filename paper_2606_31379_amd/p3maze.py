@@ -52,7 +52,9 @@ class p3mz_stats(C.Structure):
                 ("K", C.c_int32), ("levels", C.c_int32), ("nu_smooth", C.c_double),
                 ("thresh", C.c_double), ("norm_qs", C.c_double), ("res_hist", C.c_double * 65),
                 ("e_sr", C.c_double), ("e_lr", C.c_double), ("e_self", C.c_double),
-                ("e_total", C.c_double), ("steps", C.c_int64), ("ms_stage", C.c_double * 4)]
+                ("e_total", C.c_double), ("steps", C.c_int64), ("graphs", C.c_int32),
+                ("ms_mesh", C.c_double), ("ms_short_range", C.c_double), ("ms_spread", C.c_double),
+                ("ms_solve", C.c_double), ("ms_gather", C.c_double)]
 
 
 class p3mz_mdterms(C.Structure):

@@ -105,15 +105,21 @@ def test_kernel_timers(torch):
         ms, n, b = P.p3mz_get_kernel_timer(g.h)
         assert n > 0 and ms > 0 and math.isclose(b / n, 1.5 * 4 * 64 ** 3)
         st = g.stats()
-        assert all(v > 0 for v in st.ms_stage)
+        # the kernel timer forces direct launches, so the sub-stages are timed too
+        assert st.graphs == 0 and st.ms_mesh > 0 and st.ms_short_range > 0
+        assert st.ms_spread > 0 and st.ms_solve > 0 and st.ms_gather > 0
+        assert abs(st.ms_spread + st.ms_solve + st.ms_gather - st.ms_mesh) < 1e-3 * st.ms_mesh + 1e-3
         P.p3mz_set_kernel_timer(g.h, -1)
         for name in ("halfsweep", "sweep0", "restrict", "prolong", "tail", "smooth"):
             ms, b = P.p3mz_kernel_bench(g.h, P.KERNELS[name], 5, g.stream())
             assert ms > 0 and b > 0, name
         with pytest.raises(P.P3MZError):
             P.p3mz_kernel_bench(g.h, P.KERNELS["sr"], 1, g.stream())
-        # timing and the bursts leave the step itself unchanged
+        # timing and the bursts leave the step itself unchanged; graphs again
         f1, _, _ = g.compute(traj[-1])
         assert np.all(np.isfinite(f1))
+        f1, _, _ = g.compute(traj[-1])
+        st = g.stats()
+        assert st.graphs == 1 and st.ms_mesh > 0 and st.ms_spread == -1.0
     finally:
         g.close()
