@@ -290,34 +290,83 @@ __device__ __forceinline__ T cs_nbr6(const T* __restrict__ o, const CsGeo& g, in
   return ((o[row + xm] + o[row + xp]) + (o[ym] + o[yp])) + (o[zm] + o[zp]);
 }
 
+// Vector width of the half-sweeps: 16-byte accesses (4 floats, 2 doubles).
+// Every level a half-sweep runs on has n/2 divisible by 4, so a vector never
+// crosses a row.
+template <typename T> struct Vec;
+template <> struct Vec<float> { using type = float4; static constexpr int W = 4; };
+template <> struct Vec<double> { using type = double2; static constexpr int W = 2; };
+template <typename T> __device__ __forceinline__ T vget(const typename Vec<T>::type& v, int q);
+template <> __device__ __forceinline__ float vget<float>(const float4& v, int q) {
+  return q == 0 ? v.x : q == 1 ? v.y : q == 2 ? v.z : v.w;
+}
+template <> __device__ __forceinline__ double vget<double>(const double2& v, int q) { return q == 0 ? v.x : v.y; }
+template <typename T> __device__ __forceinline__ void vset(typename Vec<T>::type& v, int q, T x);
+template <> __device__ __forceinline__ void vset<float>(float4& v, int q, float x) {
+  if (q == 0) v.x = x; else if (q == 1) v.y = x; else if (q == 2) v.z = x; else v.w = x;
+}
+template <> __device__ __forceinline__ void vset<double>(double2& v, int q, double x) {
+  if (q == 0) v.x = x; else v.y = x;
+}
+
+// cs_nbr6 for the W points t..t+W-1 of one row (same colour, same x-parity
+// s), each neighbour value passed through f first.  x-neighbours come from
+// the row's own vector plus one edge element, y/z neighbours from the vectors
+// at t +- n/2 and t +- n^2/2; per point the sum order is that of cs_nbr6.
+template <typename T, typename F>
+__device__ __forceinline__ void cs_nbr6_vec(const T* __restrict__ o, const CsGeo& g, int t, int m, int j, int k,
+                                            int s, F f, T* out) {
+  constexpr int W = Vec<T>::W;
+  using V = typename Vec<T>::type;
+  const int row = t - m;
+  const V own = *reinterpret_cast<const V*>(o + t);
+  const T edge = f(s ? o[row + (m + W == g.hn ? 0 : m + W)] : o[row + (m == 0 ? g.hn - 1 : m - 1)]);
+  const int ym = j == 0 ? t + (g.n - 1) * g.hn : t - g.hn;
+  const int yp = j == g.n - 1 ? t - (g.n - 1) * g.hn : t + g.hn;
+  const int zm = k == 0 ? t + (g.n - 1) * g.plane : t - g.plane;
+  const int zp = k == g.n - 1 ? t - (g.n - 1) * g.plane : t + g.plane;
+  const V vym = *reinterpret_cast<const V*>(o + ym), vyp = *reinterpret_cast<const V*>(o + yp);
+  const V vzm = *reinterpret_cast<const V*>(o + zm), vzp = *reinterpret_cast<const V*>(o + zp);
+#pragma unroll
+  for (int q = 0; q < W; q++) {
+    const T xm = s ? f(vget<T>(own, q)) : (q == 0 ? edge : f(vget<T>(own, q - 1)));
+    const T xp = s ? (q == W - 1 ? edge : f(vget<T>(own, q + 1))) : f(vget<T>(own, q));
+    out[q] = ((xm + xp) + (f(vget<T>(vym, q)) + f(vget<T>(vyp, q)))) + (f(vget<T>(vzm, q)) + f(vget<T>(vzp, q)));
+  }
+}
+
 // Kernels below carry a FIN template flag that is 1 only on the finest level,
 // so profiles report the finest-level instances under their own names.
 
-// First pre-smoothing sweep from e = 0: red = -r/6, then black from those reds.
+// First pre-smoothing sweep from e = 0: red = -r/6, then black from those reds
+// (one thread per W consecutive points of a row).
 template <typename T, int FIN>
 __global__ void __launch_bounds__(kBlock)
 k_sweep_zero(int n, const T* __restrict__ r0, const T* __restrict__ r1, T* __restrict__ e0,
              T* __restrict__ e1, const Ctl* ctl) {
   if (ctl->done) return;
+  constexpr int W = Vec<T>::W;
+  using V = typename Vec<T>::type;
   const CsGeo g(n);
   const int half = n * g.hn * n;
-  const int t = xcd_block() * blockDim.x + threadIdx.x;
+  const int t = (xcd_block() * blockDim.x + threadIdx.x) * W;
   if (t >= half) return;
   int m, j, k;
   cs_decode(g, t, &m, &j, &k);
   const T sixth = T(1.0 / 6.0);
-  e0[t] = -r0[t] * sixth;
-  const int s = (1 + j + k) & 1;
-  const int row = t - m;
-  const int xm = s ? m : (m == 0 ? g.hn - 1 : m - 1);
-  const int xp = s ? (m + 1 == g.hn ? 0 : m + 1) : m;
-  const int ym = j == 0 ? t + (g.n - 1) * g.hn : t - g.hn;
-  const int yp = j == g.n - 1 ? t - (g.n - 1) * g.hn : t + g.hn;
-  const int zm = k == 0 ? t + (g.n - 1) * g.plane : t - g.plane;
-  const int zp = k == g.n - 1 ? t - (g.n - 1) * g.plane : t + g.plane;
-  auto R = [&](int a) { return -r0[a] * sixth; };
-  const T nb = ((R(row + xm) + R(row + xp)) + (R(ym) + R(yp))) + (R(zm) + R(zp));
-  e1[t] = (nb - r1[t]) * sixth;
+  const V rr = *reinterpret_cast<const V*>(r0 + t);
+  V er;
+#pragma unroll
+  for (int q = 0; q < W; q++) vset<T>(er, q, -vget<T>(rr, q) * sixth);
+  *reinterpret_cast<V*>(e0 + t) = er;
+  // black points of the same row: their neighbours are the red values -r0/6
+  T nb[W];
+  cs_nbr6_vec(r0, g, t, m, j, k, (1 + j + k) & 1, [sixth](T x) { return -x * sixth; }, nb);
+  const V rb = *reinterpret_cast<const V*>(r1 + t);
+  V eb;
+#pragma unroll
+  for (int q = 0; q < W; q++) vset<T>(eb, q, (nb[q] - vget<T>(rb, q)) * sixth);
+  *reinterpret_cast<V*>(e1 + t) = eb;
 }
 
 template <typename T, int FIN>
@@ -325,13 +374,21 @@ __global__ void __launch_bounds__(kBlock)
 k_halfsweep(int n, int colour, T* __restrict__ ec, const T* __restrict__ eo, const T* __restrict__ rc,
             const Ctl* ctl) {
   if (ctl->done) return;
+  constexpr int W = Vec<T>::W;
+  using V = typename Vec<T>::type;
   const CsGeo g(n);
   const int half = n * g.hn * n;
-  const int t = xcd_block() * blockDim.x + threadIdx.x;
+  const int t = (xcd_block() * blockDim.x + threadIdx.x) * W;
   if (t >= half) return;
   int m, j, k;
   cs_decode(g, t, &m, &j, &k);
-  ec[t] = (cs_nbr6(eo, g, t, m, j, k, (colour + j + k) & 1) - rc[t]) * T(1.0 / 6.0);
+  T nb[W];
+  cs_nbr6_vec(eo, g, t, m, j, k, (colour + j + k) & 1, [](T x) { return x; }, nb);
+  const V r = *reinterpret_cast<const V*>(rc + t);
+  V out;
+#pragma unroll
+  for (int q = 0; q < W; q++) vset<T>(out, q, (nb[q] - vget<T>(r, q)) * T(1.0 / 6.0));
+  *reinterpret_cast<V*>(ec + t) = out;
 }
 
 // Residual rho = r - M e at the 27 fine points around 2I, full weighting,
@@ -687,13 +744,19 @@ __global__ void k_set_open(Ctl* ctl) {
   ctl->status = 0;
 }
 
-template <typename T, int FIN>
-void launch_sweep0(int n, int nb, T* r0, T* r1, T* e0, T* e1, Ctl* ctl, hipStream_t s) {
-  hipLaunchKernelGGL((k_sweep_zero<T, FIN>), dim3(nb), dim3(kBlock), 0, s, n, r0, r1, e0, e1, ctl);
+// Vectorized sweeps: one thread per Vec<T>::W points, so half / W threads.
+template <typename T>
+int sweep_blocks(int n) {
+  return blocks_for((int64_t)n * n * n / 2 / Vec<T>::W, kBlock);
 }
 template <typename T, int FIN>
-void launch_half(int n, int nb, int colour, T* ec, const T* eo, const T* rc, Ctl* ctl, hipStream_t s) {
-  hipLaunchKernelGGL((k_halfsweep<T, FIN>), dim3(nb), dim3(kBlock), 0, s, n, colour, ec, eo, rc, ctl);
+void launch_sweep0(int n, T* r0, T* r1, T* e0, T* e1, Ctl* ctl, hipStream_t s) {
+  hipLaunchKernelGGL((k_sweep_zero<T, FIN>), dim3(sweep_blocks<T>(n)), dim3(kBlock), 0, s, n, r0, r1, e0, e1, ctl);
+}
+template <typename T, int FIN>
+void launch_half(int n, int colour, T* ec, const T* eo, const T* rc, Ctl* ctl, hipStream_t s) {
+  hipLaunchKernelGGL((k_halfsweep<T, FIN>), dim3(sweep_blocks<T>(n)), dim3(kBlock), 0, s, n, colour, ec, eo, rc,
+                     ctl);
 }
 template <typename T, int FIN>
 void launch_restrict(int n, int red_only, const T* e0, const T* e1, const T* r0, const T* r1, T* rc0, T* rc1,
@@ -717,8 +780,8 @@ hipError_t vcycle_impl(const LevelBufs* lv, int levels, int tail, int nu1, int n
     T *e0 = (T*)lv[l].e0, *e1 = (T*)lv[l].e1, *r0 = (T*)lv[l].r0, *r1 = (T*)lv[l].r1;
     if (nu1 >= 1) {
       kt_begin(KT_SWEEP0, l, s);
-      if (l == 0) launch_sweep0<T, 1>(n, nb, r0, r1, e0, e1, ctl, s);
-      else launch_sweep0<T, 0>(n, nb, r0, r1, e0, e1, ctl, s);
+      if (l == 0) launch_sweep0<T, 1>(n, r0, r1, e0, e1, ctl, s);
+      else launch_sweep0<T, 0>(n, r0, r1, e0, e1, ctl, s);
       kt_end(KT_SWEEP0, l, 2.0 * ts * n3, s);
       for (int it = 1; it < nu1; it++) {
         for (int colour = 0; colour < 2; colour++) {
@@ -726,8 +789,8 @@ hipError_t vcycle_impl(const LevelBufs* lv, int levels, int tail, int nu1, int n
           const T* eo = colour ? e0 : e1;
           const T* rc = colour ? r1 : r0;
           kt_begin(KT_HALFSWEEP, l, s);
-          if (l == 0) launch_half<T, 1>(n, nb, colour, ec, eo, rc, ctl, s);
-          else launch_half<T, 0>(n, nb, colour, ec, eo, rc, ctl, s);
+          if (l == 0) launch_half<T, 1>(n, colour, ec, eo, rc, ctl, s);
+          else launch_half<T, 0>(n, colour, ec, eo, rc, ctl, s);
           kt_end(KT_HALFSWEEP, l, 1.5 * ts * n3, s);
         }
       }
@@ -765,8 +828,8 @@ hipError_t vcycle_impl(const LevelBufs* lv, int levels, int tail, int nu1, int n
           const T* eo = colour ? e0 : e1;
           const T* rc = colour ? r1 : r0;
           kt_begin(KT_HALFSWEEP, l, s);
-          if (l == 0) launch_half<T, 1>(n, nb, colour, ec, eo, rc, ctl, s);
-          else launch_half<T, 0>(n, nb, colour, ec, eo, rc, ctl, s);
+          if (l == 0) launch_half<T, 1>(n, colour, ec, eo, rc, ctl, s);
+          else launch_half<T, 0>(n, colour, ec, eo, rc, ctl, s);
           kt_end(KT_HALFSWEEP, l, 1.5 * ts * n3, s);
         }
       }
@@ -787,13 +850,14 @@ hipError_t one_kernel(int kid, const LevelBufs* lv, int levels, int tail, int nu
   const int n = lv[0].n, half = n * n * n / 2, nb = blocks_for(half, kBlock);
   const double n3 = (double)n * n * n, ts = sizeof(T);
   T *e0 = (T*)lv[0].e0, *e1 = (T*)lv[0].e1, *r0 = (T*)lv[0].r0, *r1 = (T*)lv[0].r1;
+  if ((kid == KT_HALFSWEEP || kid == KT_SWEEP0) && (n / 2) % Vec<T>::W != 0) return hipErrorInvalidValue;
   switch (kid) {
     case KT_HALFSWEEP:
-      launch_half<T, 1>(n, nb, 0, e0, e1, r0, ctl, s);
+      launch_half<T, 1>(n, 0, e0, e1, r0, ctl, s);
       *bytes = 1.5 * ts * n3;
       break;
     case KT_SWEEP0:
-      launch_sweep0<T, 1>(n, nb, r0, r1, e0, e1, ctl, s);
+      launch_sweep0<T, 1>(n, r0, r1, e0, e1, ctl, s);
       *bytes = 2.0 * ts * n3;
       break;
     case KT_RESTRICT:
