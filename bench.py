@@ -61,6 +61,36 @@ def make_params(P, w, precision):
                          excl_group=w.excl_group)
 
 
+def source_digest() -> str:
+    """SHA-256 over the HIP sources: a changed kernel invalidates stored counters."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2606_31379_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        with open(os.path.join(d, name), "rb") as fh:
+            h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload, mode):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary for this workload (FETCH_SIZE and WRITE_SIZE passes, each scaled
+    by the same counter's reading for a copy of known size), or None when
+    there is no summary or the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{workload}_{mode}.md")
+    if not os.path.exists(path):
+        return None, f"no counter summary {os.path.relpath(path, ROOT)}"
+    vals = {}
+    with open(path) as fh:
+        for ln in fh:
+            if ln.startswith("- ") and ": " in ln:
+                k, v = ln[2:].split(": ", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_sha256") != source_digest():
+        return None, f"{os.path.relpath(path, ROOT)} predates the current kernels"
+    return float(vals["hbm_bytes_per_launch"]), os.path.relpath(path, ROOT)
+
+
 def copy_ceiling_gbps(torch, nbytes=1 << 30, reps=10):
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
@@ -114,7 +144,7 @@ def run_mode(torch, P, w, system, precision, warmup, steps, kernel):
         dominant = kernel if kernel != "auto" else max(mesh_shares, key=mesh_shares.get)
         log(f"[{'fp64' if precision == 0 else 'mixed'}] kernel ms/step: "
             + ", ".join(f"{k}={v:.4f}" for k, v in sorted(shares.items(), key=lambda x: -x[1])))
-        P.p3mz_set_kernel_timer(ctx, -1)      # timed region runs with captured graphs
+        P.p3mz_set_kernel_timer(ctx, -1)      # the headline region runs with captured graphs
         mesh_ms_tot, sr_ms_tot, graphs = 0.0, 0.0, 1
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -126,13 +156,18 @@ def run_mode(torch, P, w, system, precision, warmup, steps, kernel):
             graphs &= st.graphs
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        # the dominant kernel timed back to back on the live buffers of the last step
-        burst_ok = dominant in ("halfsweep", "sweep0", "restrict", "prolong", "tail", "smooth")
-        kms, kbytes = P.p3mz_kernel_bench(ctx, P.KERNELS[dominant], 200, stream) if burst_ok else (float("nan"), 0.0)
-        klaunch = 200 if burst_ok else 0
-        kms, kbytes = kms * klaunch, kbytes * klaunch
         cycles = clog.cpu().numpy()[:steps]
         energies = elog.cpu().numpy()[:steps]
+        # Roofline: the dominant family's finest-level kernel launched back to
+        # back on the live buffers of the last timed step, HIP events on the
+        # library's stream.  (Events around every single in-step launch add a
+        # few microseconds of event overhead to a ~3 us kernel; back-to-back
+        # launches agree with the profiler's per-dispatch durations.)
+        burst_ok = dominant in ("halfsweep", "sweep0", "restrict", "prolong", "tail", "smooth")
+        reps = 200
+        kms, kbytes = P.p3mz_kernel_bench(ctx, P.KERNELS[dominant], reps, stream) if burst_ok else (float("nan"), 0.0)
+        klaunch = reps if burst_ok else 0
+        kms, kbytes = kms * klaunch, kbytes * klaunch
         mesh_ms = mesh_ms_tot / steps
         avg_launch_ms = kms / max(klaunch, 1)
         bytes_per_launch = kbytes / max(klaunch, 1)
@@ -144,7 +179,7 @@ def run_mode(torch, P, w, system, precision, warmup, steps, kernel):
             vcycles_per_step=float(cycles.mean()), vcycles_min=int(cycles.min()), vcycles_max=int(cycles.max()),
             energy_drift_per_step=float(np.polyfit(np.arange(steps), energies[:, 5], 1)[0]) if steps > 2 else None,
             kernel_ms_per_step=shares, dominant=dominant,
-            dominant_avg_launch_us=avg_launch_ms * 1e3, dominant_launches=klaunch,
+            dominant_avg_launch_us=avg_launch_ms * 1e3, dominant_launches=int(klaunch),
             dominant_bytes_per_launch=bytes_per_launch,
             dominant_gbps=bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9 if klaunch else None,
         )
@@ -208,6 +243,7 @@ def main():
     ap.add_argument("--kernel", default="auto", help="kernel family for the roofline (default: dominant)")
     ap.add_argument("--cpu-sample-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--modes", default="fp64,mixed", help="precision modes to run (the headline is mixed)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -229,7 +265,10 @@ def main():
     ceiling = copy_ceiling_gbps(torch)
     log(f"device copy ceiling {ceiling:.0f} GB/s")
     res = {}
+    modes = args.modes.split(",")
     for precision, name in ((0, "fp64"), (1, "mixed")):
+        if name not in modes:
+            continue
         log(f"[{name}] warmup {args.warmup}, timed {args.steps}")
         res[name] = run_mode(torch, P, w, system, precision, args.warmup, args.steps, args.kernel)
         log(f"[{name}] {json.dumps({k: v for k, v in res[name].items() if k != 'kernel_ms_per_step'})}")
@@ -237,20 +276,23 @@ def main():
     if not args.no_cpu_baseline:
         sample = args.cpu_sample_steps or (8 if system.n <= 4000 else 3)
         parity, baseline = parity_and_baseline(torch, P, w, system, sample)
-    m, f = res["mixed"], res["fp64"]
-    roof = dict(bound="hbm", kernel=m["dominant"], achieved=m["dominant_gbps"], peak=HBM_PEAK_GBPS,
-                unit="GB/s", frac=(m["dominant_gbps"] / HBM_PEAK_GBPS) if m["dominant_gbps"] else None,
-                traffic=None, avg_launch_us=m["dominant_avg_launch_us"],
-                alg_bytes_per_launch=m["dominant_bytes_per_launch"], copy_ceiling_GBps=ceiling)
+    m, f = res.get("mixed"), res.get("fp64")
+    head = m if m is not None else f
+    traffic, traffic_note = measured_traffic(head["dominant"], w.name, "mixed" if m is not None else "fp64")
+    roof = dict(bound="hbm", kernel=head["dominant"], achieved=head["dominant_gbps"], peak=HBM_PEAK_GBPS,
+                unit="GB/s", frac=(head["dominant_gbps"] / HBM_PEAK_GBPS) if head["dominant_gbps"] else None,
+                traffic=traffic, traffic_source=traffic_note, avg_launch_us=head["dominant_avg_launch_us"],
+                alg_bytes_per_launch=head["dominant_bytes_per_launch"], launches=head["dominant_launches"],
+                copy_ceiling_GBps=ceiling)
     line = dict(
-        metric=METRIC, value=m["ns_per_atom"], unit="ns/atom/step", n_gpus=1, steps=args.steps,
-        warmup=args.warmup, ms_per_step=m["md_ms_per_step"], higher_is_better=False, scaling="weak",
-        vs_baseline=None, dtype="f32+f64", data="synthetic",
+        metric=METRIC, value=head["ns_per_atom"], unit="ns/atom/step", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=head["md_ms_per_step"], higher_is_better=False, scaling="weak",
+        vs_baseline=None, dtype="f32+f64" if m is not None else "f64", data="synthetic",
         config=dict(workload=w.name, n_atoms=system.n, box=w.box, mesh=w.mesh, order=w.order,
                     alpha=w.alpha, r_cut=w.r_cut, tol=w.tol, predictor=w.predictor, dt_fs=w.dt_fs,
-                    precision="mixed"),
+                    precision="mixed" if m is not None else "fp64"),
         mixed=m, fp64=f,
-        speedup_mixed_vs_fp64=f["mesh_ms_per_step"] / m["mesh_ms_per_step"],
+        speedup_mixed_vs_fp64=(f["mesh_ms_per_step"] / m["mesh_ms_per_step"]) if (m and f) else None,
         roofline=roof, cpu_baseline=baseline, parity=parity,
     )
     print(json.dumps(line), flush=True)
