@@ -224,6 +224,54 @@ p3mz_status p3mz_kernel_bench(p3mz_ctx* ctx, int32_t kernel_id, int32_t reps, vo
                               double* bytes_per_launch);
 
 void p3mz_destroy(p3mz_ctx* ctx);
+
+/* ---- Batched replicas ------------------------------------------------------
+ * Many independent systems (uneven atom counts and meshes) advanced together:
+ * every kernel of the step is launched once for all systems, with one
+ * workgroup row per system, so small systems share the GPU instead of
+ * leaving it idle.  Each system runs exactly the algorithm of a single
+ * context with its own parameters and history (same results, bitwise), and
+ * converges on its own: the V-cycle launches of a system that has met its
+ * tolerance return at once.  All systems of a batch need the same precision.
+ *
+ * Packed layout: system s owns atoms [off_s, off_s + n_atoms[s]) of every
+ * packed per-atom array, off_s = sum of the earlier n_atoms; positions,
+ * forces and velocities are [atom][3] FP64, masses [atom].  The caller owns
+ * every device pointer; launches are recorded (and captured as HIP graphs)
+ * against the pointers of the first call and recorded again when they
+ * change. */
+typedef struct p3mz_batch p3mz_batch;
+
+/* per_sys[n_sys] parameters and n_atoms[n_sys] atom counts; host charges,
+ * packed.  Each system is validated as by p3mz_create (same errors); all
+ * device memory is allocated here.  Errors: INVALID_ARG when precisions
+ * differ. */
+p3mz_status p3mz_batch_create(int32_t n_sys, const p3mz_params* per_sys, const int64_t* n_atoms,
+                              const double* charges_packed_host, p3mz_batch** out);
+/* One mesh step (as p3mz_compute) for every system: pos_dev packed, read
+ * only; force_dev packed (SR+LR, overwritten); energies_dev [n_sys][4] =
+ * {E_sr, E_lr, E_self, E_total} per system.  Per-system statistics via
+ * p3mz_batch_get_stats.  WARN_NOT_CONVERGED if any system hit its cycle cap;
+ * NAN if any system saw a non-finite position (that system's history is
+ * dropped).  Synchronises once per V-cycle batch. */
+p3mz_status p3mz_batch_compute(p3mz_batch* b, const double* pos_dev, double* force_dev, double* energies_dev,
+                               void* stream);
+/* n_steps of velocity Verlet for every system (as p3mz_md_run, one MD step
+ * of all systems per iteration).  energy_log_dev [n_sys][n_steps][6] and
+ * cycles_log_dev [n_sys][n_steps] (either may be NULL). */
+p3mz_status p3mz_batch_md_run(p3mz_batch* b, double* pos_dev, double* vel_dev, const double* mass_dev,
+                              const p3mz_mdterms* terms, double dt, int32_t n_steps, double* energy_log_dev,
+                              int32_t* cycles_log_dev, void* stream);
+/* Statistics of system `sys` after the last batched step. */
+p3mz_status p3mz_batch_get_stats(const p3mz_batch* b, int32_t sys, p3mz_stats* out);
+/* Events around the mesh part (spread .. gather) and the pair part of every
+ * batched step (on = 1); p3mz_batch_get_timing returns the last step's
+ * milliseconds and whether it ran from captured graphs. */
+p3mz_status p3mz_batch_set_timing(p3mz_batch* b, int32_t on);
+p3mz_status p3mz_batch_get_timing(const p3mz_batch* b, double* ms_mesh, double* ms_short_range, int32_t* graphs);
+/* Captured graphs (default) or direct launches; results are identical. */
+p3mz_status p3mz_batch_set_graphs(p3mz_batch* b, int32_t on);
+void p3mz_batch_destroy(p3mz_batch* b);
 const char* p3mz_status_string(p3mz_status s);
 const char* p3mz_last_error(void);
 /* Library version string, e.g. "p3maze-gfx950 0.1". */

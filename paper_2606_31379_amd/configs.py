@@ -98,6 +98,33 @@ def nacl_batch(n_sys: int = 64, seed: int = 4000) -> list[Replica]:
     return out
 
 
+@dataclasses.dataclass
+class BatchWorkload:
+    """Batched NaCl replicas sharing the electrostatic control parameters."""
+    name: str
+    replicas: list
+    alpha: float = 0.30
+    r_cut: float = 9.0
+    order: int = 4
+    tol: float = 1e-8
+    dt_fs: float = 0.5
+    md_steps: int = 100
+    predictor: int = 3
+
+    @property
+    def n_atoms(self) -> int:
+        return sum(r.n_atoms for r in self.replicas)
+
+    def systems(self) -> list:
+        return [inputs.nacl(r.n_atoms, r.box, r.temp_k, r.seed) for r in self.replicas]
+
+
+def nacl_batch_64() -> BatchWorkload:
+    """64 NaCl replicas, log-uniform sizes in [512, 32768], meshes 16^3-64^3, order 4, tol 1e-8."""
+    reps = nacl_batch(64)
+    return BatchWorkload(f"nacl-batch64-{sum(r.n_atoms for r in reps)}", reps)
+
+
 WORKLOADS = {
     "nacl-512": nacl_512,
     "water-3000": water_3000,

@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "kern.h"
 #include "launch.h"
 #include "p3maze.h"
 
@@ -228,6 +229,8 @@ struct p3mz_ctx {
 // The context whose work is being enqueued (kernel-timer hooks read it).
 static p3mz_ctx* g_active = nullptr;
 
+thread_local Recorder* g_recorder = nullptr;
+
 void kt_begin(int id, int level, hipStream_t s) {
   p3mz_ctx* c = g_active;
   if (!c || c->kt_id != id || level != 0 || c->kt_used + 2 > (int)c->kt_ev.size()) return;
@@ -369,27 +372,35 @@ p3mz_status enq_pre(p3mz_ctx* c, const double* pos, hipStream_t s) {
   const Plan& pl = c->pl;
   const int n = pl.n, na = (int)c->n_atoms;
   const double N3 = (double)c->n3, ts = (double)c->tsz;
+  rec_key(100);
   P3MZ_HIP_TRY(launch_bin_stencil(true, na, pos, c->P.box, n, pl.p, kTile, c->ntx, c->d_base, c->d_w, c->d_key,
                                   c->d_slot, c->d_count, c->d_ctl, s));
+  rec_key(101);
   P3MZ_HIP_TRY(launch_scan(c->nbins, c->d_count, c->d_start, c->d_bsum, s));
+  rec_key(102);
   P3MZ_HIP_TRY(launch_scatter(na, c->d_key, c->d_slot, c->d_start, c->d_perm_raw, s));
+  rec_key(103);
   P3MZ_HIP_TRY(launch_sort_bins(c->nbins, c->d_start, c->d_perm_raw, c->d_perm, c->d_ctl, s));
+  rec_key(104);
   kt_begin(KT_SPREAD, 0, s);
   P3MZ_HIP_TRY(launch_spread(true, n, pl.p, kTile, c->ntx, c->d_start, c->d_perm, c->d_base, c->d_w, c->d_qa, c->d_q, s));
   kt_end(KT_SPREAD, 0, 8.0 * N3 + (double)na * (24.0 * pl.p + 24.0), s);
   double* src[3] = {c->d_q, c->d_qs, c->d_tmp};
   double* dst[3] = {c->d_qs, c->d_tmp, c->d_qs};
   for (int axis = 0; axis < 3; axis++) {
+    rec_key(105 + axis);
     kt_begin(KT_SMOOTH, 0, s);
     P3MZ_HIP_TRY(launch_smooth(true, n, axis, c->ntaps, c->half, c->d_taps, src[axis], dst[axis], s));
     kt_end(KT_SMOOTH, 0, 16.0 * N3, s);
   }
   stage(c, 1, s);
+  rec_key(110);
   kt_begin(KT_SIGMA, 0, s);
   P3MZ_HIP_TRY(launch_sigma(n, pl.h, c->d_qs, c->d_phi[0], c->d_phi[1], c->d_yh[0], c->d_yh[1], c->d_yh[2],
                             c->d_sigma, c->d_y[0], c->P.tol, c->P.tol_mode, c->d_partial, c->d_ctl, s));
   kt_end(KT_SIGMA, 0, 64.0 * N3, s);
   const LevelBufs& f = c->lv[0];
+  rec_key(111);
   kt_begin(KT_OUTER, 0, s);
   P3MZ_HIP_TRY(launch_outer(c->fp64, n, 1, c->P.max_cycles, c->d_sigma, c->d_y[0], c->d_y[1], f.e0, f.e1, f.r0, f.r1,
                             c->d_partial, c->d_ctl, s));
@@ -403,6 +414,7 @@ p3mz_status enq_cycle(p3mz_ctx* c, hipStream_t s) {
   const LevelBufs& f = c->lv[0];
   const double N3 = (double)c->n3, ts = (double)c->tsz;
   P3MZ_HIP_TRY(launch_vcycle(c->fp64, c->lv, pl.levels, pl.tail, c->nu1, c->nu2, c->d_green, c->d_ctl, s));
+  rec_key(4100);
   kt_begin(KT_OUTER, 0, s);
   P3MZ_HIP_TRY(launch_outer(c->fp64, pl.n, 0, c->P.max_cycles, c->d_sigma, c->d_y[0], c->d_y[1], f.e0, f.e1, f.r0,
                             f.r1, c->d_partial, c->d_ctl, s));
@@ -415,11 +427,13 @@ p3mz_status enq_post1(p3mz_ctx* c, double* force, hipStream_t s) {
   const Plan& pl = c->pl;
   const int n = pl.n, na = (int)c->n_atoms;
   const double N3 = (double)c->n3;
+  rec_key(5000);
   kt_begin(KT_PHI, 0, s);
   P3MZ_HIP_TRY(launch_phi_update(n, pl.h, c->d_phi[0], c->d_phi[1], c->d_y[0], c->d_y[1], c->d_yh[0], c->d_yh[1],
                                  c->d_yh[2], c->d_phi32, c->d_ctl, s));
   kt_end(KT_PHI, 0, 40.0 * N3 + (c->fp64 ? 0.0 : 4.0 * N3), s);
   stage(c, 2, s);
+  rec_key(5001);
   kt_begin(KT_GATHER, 0, s);
   P3MZ_HIP_TRY(launch_gather(c->fp64, na, n, pl.p, pl.h, c->P.coulomb_k, c->d_perm, c->d_base, c->d_w, c->d_qa,
                              c->d_phi[0], c->d_phi[1], c->d_phi32, force, c->d_partial, c->d_ctl, s));
@@ -431,15 +445,21 @@ p3mz_status enq_post1(p3mz_ctx* c, double* force, hipStream_t s) {
 // short-range pairs on a fresh cell list, energies, history rotation
 p3mz_status enq_post2(p3mz_ctx* c, const double* pos, double* force, double* energy, hipStream_t s) {
   const int na = (int)c->n_atoms;
+  rec_key(6000);
   P3MZ_HIP_TRY(launch_bin_cells(na, pos, c->P.box, c->nc, c->d_ckey, c->d_cslot, c->d_ccount, c->d_ctl, s));
+  rec_key(6001);
   P3MZ_HIP_TRY(launch_scan(c->ncells, c->d_ccount, c->d_cstart, c->d_bsum, s));
+  rec_key(6002);
   P3MZ_HIP_TRY(launch_scatter(na, c->d_ckey, c->d_cslot, c->d_cstart, c->d_cperm_raw, s));
+  rec_key(6003);
   P3MZ_HIP_TRY(launch_sort_bins(c->ncells, c->d_cstart, c->d_cperm_raw, c->d_cperm, c->d_ctl, s));
+  rec_key(6004);
   kt_begin(KT_SR, 0, s);
   P3MZ_HIP_TRY(launch_sr(na, pos, c->d_qa, c->P.box, c->P.alpha, c->P.r_cut, c->P.coulomb_k, c->nc, c->P.excl_group,
                          c->d_cstart, c->d_cperm, force, c->e_self, energy ? energy : c->d_energy,
                          c->d_partial, c->d_ctl, s));
   kt_end(KT_SR, 0, (double)na * 56.0, s);
+  rec_key(6005);
   P3MZ_HIP_TRY(launch_advance(c->d_ctl, s));
   return P3MZ_OK;
 }
@@ -458,9 +478,12 @@ p3mz_status enq_md_post2(p3mz_ctx* c, const MdArgs& m, hipStream_t s) {
   const int na = (int)c->n_atoms;
   P3MZ_TRY(enq_post2(c, m.pos, c->d_md_force, c->d_energy, s));
   // the cell list of the short-range pass is still valid for these positions
+  rec_key(6100);
   P3MZ_HIP_TRY(launch_nonelec(na, m.pos, c->P.box, c->P.r_cut, m.model, m.p[0], m.p[1], m.p[2], m.p[3], m.p[4],
                               m.p[5], c->nc, c->d_cstart, c->d_cperm, c->d_md_force, c->d_partial, c->d_e_other, s));
+  rec_key(6101);
   P3MZ_HIP_TRY(launch_kick_drift(na, m.pos, m.vel, c->d_md_force, m.mass, m.dt, m.f2a, 0, s));
+  rec_key(6102);
   P3MZ_HIP_TRY(launch_kinetic_log(na, m.vel, m.mass, m.mv2e, c->d_energy, c->d_e_other, m.elog, m.clog, c->d_ctl,
                                   c->d_partial, s));
   return P3MZ_OK;
@@ -628,6 +651,396 @@ p3mz_status compute_step(p3mz_ctx* c, const double* pos, double* force, double* 
     g_last_error = "V-cycle cap reached before the tolerance";
     return P3MZ_WARN_NOT_CONVERGED;
   }
+  return P3MZ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched replicas.  A batch owns one ordinary context per system.  Each
+// part of the step (kick, pre, one cycle, post1, post2) is enqueued once per
+// system with a Recorder installed; the recorded launches of all systems are
+// merged by sequence key into one k_many launch per key (blockIdx.y = system),
+// so every launch of the batched step covers every system that has that
+// launch, and each system's own order is kept.  Systems that converge earlier
+// return from the remaining cycle kernels through their own control block.
+// ---------------------------------------------------------------------------
+struct BatchLaunch {
+  ManyFn many;
+  size_t off;   // byte offset of the packed arguments in the set's device block
+  int count, gx;
+  size_t lds;
+};
+
+enum { BQ_KICK = 0, BQ_PRE, BQ_CYCLE, BQ_POST1, BQ_POST2, BQ_EXTRA, BQ_COUNT };
+
+struct BatchSet {
+  std::vector<uint64_t> key;           // caller pointers/values the launches were recorded with
+  std::vector<BatchLaunch> q[BQ_COUNT];
+  void* d_args = nullptr;
+  size_t cap = 0;
+  GraphSlot g[BQ_COUNT];
+  void drop() {
+    for (GraphSlot& x : g) x.reset();
+    key.clear();
+  }
+};
+
+__global__ void k_batch_head(const Ctl* const* __restrict__ ctls, int n, int* __restrict__ out) {
+  __shared__ int all_done, any_nan, cmax;
+  if (threadIdx.x == 0) {
+    all_done = 1;
+    any_nan = 0;
+    cmax = 0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const Ctl* c = ctls[i];
+    if (!c->done) atomicAnd(&all_done, 0);
+    if (c->nan_flag) atomicOr(&any_nan, 1);
+    atomicMax(&cmax, c->cycles);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[0] = all_done;
+    out[1] = any_nan;
+    out[2] = cmax;
+  }
+}
+
+// Copies every system's control block into one array (one workgroup each).
+__global__ void k_batch_collect(const Ctl* const* __restrict__ ctls, Ctl* __restrict__ dst) {
+  const int* src = reinterpret_cast<const int*>(ctls[blockIdx.x]);
+  int* d = reinterpret_cast<int*>(dst + blockIdx.x);
+  for (int i = threadIdx.x; i < (int)(sizeof(Ctl) / sizeof(int)); i += blockDim.x) d[i] = src[i];
+}
+
+__global__ void k_batch_md_reset(Ctl* const* __restrict__ ctls, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) ctls[i]->md_step = 0;
+}
+
+}  // namespace
+
+struct p3mz_batch {
+  std::vector<p3mz_ctx*> sys;
+  std::vector<int64_t> off;        // first atom of each system in the packed arrays
+  int64_t n_total = 0;
+  bool fp64 = false;
+  Ctl** d_ctls = nullptr;          // device array of the systems' control blocks
+  Ctl* d_ctl_all = nullptr;        // collected control blocks
+  Ctl* h_ctl_all = nullptr;        // pinned
+  int* d_head = nullptr;
+  int* h_head = nullptr;           // pinned {all done, any nan, max cycles}
+  BatchSet compute, md;
+  bool use_graphs = true;
+  bool md_have_force = false;
+  int last_cycles = 0;
+  hipStream_t cap = nullptr;
+  bool timing = false;
+  hipEvent_t ev[3] = {};
+  double ms_mesh = 0.0, ms_sr = 0.0;
+  int ran_graphs = 0;
+  int64_t steps = 0;
+  ~p3mz_batch() {
+    compute.drop();
+    md.drop();
+    for (BatchSet* b : {&compute, &md})
+      if (b->d_args) (void)hipFree(b->d_args);
+    if (d_ctls) (void)hipFree(d_ctls);
+    if (d_ctl_all) (void)hipFree(d_ctl_all);
+    if (d_head) (void)hipFree(d_head);
+    if (h_ctl_all) (void)hipHostFree(h_ctl_all);
+    if (h_head) (void)hipHostFree(h_head);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (cap) (void)hipStreamDestroy(cap);
+    for (p3mz_ctx* c : sys) delete c;
+  }
+};
+
+namespace {
+
+// Record part `part` of every system with enq(system index) and merge the
+// launches by key into set->q[part]; packed arguments are appended to `args`.
+template <typename F>
+p3mz_status batch_record(p3mz_batch* b, BatchSet* set, int part, std::vector<unsigned char>* args, F enq) {
+  const int R = (int)b->sys.size();
+  std::vector<std::vector<LaunchRec>> recs(R);
+  for (int r = 0; r < R; r++) {
+    Recorder rec;
+    g_recorder = &rec;
+    p3mz_status st = enq(r);
+    g_recorder = nullptr;
+    if (st != P3MZ_OK) return st;
+    for (size_t i = 1; i < rec.recs.size(); i++)
+      if (rec.recs[i].key <= rec.recs[i - 1].key) return fail(P3MZ_ERR_STATE, "internal: launch keys out of order");
+    recs[r] = std::move(rec.recs);
+  }
+  std::vector<size_t> pos(R, 0);
+  std::vector<BatchLaunch>& out = set->q[part];
+  out.clear();
+  for (;;) {
+    uint32_t k = UINT32_MAX;
+    for (int r = 0; r < R; r++)
+      if (pos[r] < recs[r].size()) k = std::min(k, recs[r][pos[r]].key);
+    if (k == UINT32_MAX) break;
+    BatchLaunch L{nullptr, 0, 0, 0, 0};
+    size_t elem = 0;
+    args->resize((args->size() + 255) & ~(size_t)255);
+    L.off = args->size();
+    for (int r = 0; r < R; r++) {
+      if (pos[r] >= recs[r].size() || recs[r][pos[r]].key != k) continue;
+      const LaunchRec& x = recs[r][pos[r]++];
+      if (!L.many) {
+        L.many = x.many;
+        elem = x.args.size();
+      } else if (L.many != x.many || elem != x.args.size()) {
+        return fail(P3MZ_ERR_STATE, "systems of one batch need the same precision and sweep structure");
+      }
+      args->insert(args->end(), x.args.begin(), x.args.end());
+      L.count++;
+      L.gx = std::max(L.gx, x.grid);
+      L.lds = std::max(L.lds, x.lds);
+    }
+    // round the grid up to a multiple of 8 so the XCD renumbering applies
+    if (L.gx >= 8) L.gx = (L.gx + 7) & ~7;
+    out.push_back(L);
+  }
+  return P3MZ_OK;
+}
+
+p3mz_status batch_upload(BatchSet* set, const std::vector<unsigned char>& args) {
+  // launches of the previous recording may still read the old arguments
+  P3MZ_HIP_TRY(hipDeviceSynchronize());
+  if (args.size() > set->cap) {
+    if (set->d_args) P3MZ_HIP_TRY(hipFree(set->d_args));
+    set->d_args = nullptr;
+    set->cap = 0;
+    P3MZ_HIP_TRY(hipMalloc(&set->d_args, args.size()));
+    set->cap = args.size();
+  }
+  if (!args.empty()) P3MZ_HIP_TRY(hipMemcpy(set->d_args, args.data(), args.size(), hipMemcpyHostToDevice));
+  return P3MZ_OK;
+}
+
+p3mz_status batch_run_part(p3mz_batch* b, BatchSet* set, int part, hipStream_t s) {
+  auto body = [&](hipStream_t q) -> p3mz_status {
+    for (const BatchLaunch& L : set->q[part])
+      P3MZ_HIP_TRY(L.many((const char*)set->d_args + L.off, L.count, L.gx, L.lds, q));
+    return P3MZ_OK;
+  };
+  if (set->q[part].empty()) return P3MZ_OK;
+  if (!b->use_graphs) return body(s);
+  GraphSlot& slot = set->g[part];
+  if (!slot.exec) {
+    slot.reset();
+    P3MZ_HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    p3mz_status st = body(b->cap);
+    hipError_t e = hipStreamEndCapture(b->cap, &slot.graph);
+    if (st != P3MZ_OK || e != hipSuccess || hipGraphInstantiate(&slot.exec, slot.graph, nullptr, nullptr, 0) != hipSuccess) {
+      slot.reset();
+      (void)hipGetLastError();
+      b->use_graphs = false;
+      return body(s);
+    }
+  }
+  P3MZ_HIP_TRY(hipGraphLaunch(slot.exec, s));
+  b->ran_graphs = 1;
+  return P3MZ_OK;
+}
+
+p3mz_status batch_read_head(p3mz_batch* b, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_head, dim3(1), dim3(256), 0, s, (const Ctl* const*)b->d_ctls, (int)b->sys.size(),
+                     b->d_head);
+  P3MZ_HIP_TRY(hipGetLastError());
+  P3MZ_HIP_TRY(hipMemcpyAsync(b->h_head, b->d_head, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+  P3MZ_HIP_TRY(hipStreamSynchronize(s));
+  return P3MZ_OK;
+}
+
+// Statistics of every system after a batched step, from one collected copy
+// of all control blocks (same fields as a single context's finish()).
+p3mz_status batch_finish(p3mz_batch* b, hipStream_t s) {
+  const int R = (int)b->sys.size();
+  hipLaunchKernelGGL(k_batch_collect, dim3(R), dim3(64), 0, s, (const Ctl* const*)b->d_ctls, b->d_ctl_all);
+  P3MZ_HIP_TRY(hipGetLastError());
+  P3MZ_HIP_TRY(hipMemcpyAsync(b->h_ctl_all, b->d_ctl_all, R * sizeof(Ctl), hipMemcpyDeviceToHost, s));
+  P3MZ_HIP_TRY(hipStreamSynchronize(s));
+  int cmax = 0;
+  for (int r = 0; r < R; r++) {
+    p3mz_ctx* c = b->sys[r];
+    const Ctl& h = b->h_ctl_all[r];
+    const int was_cold = c->mirror.cold, m_eff = c->mirror.m_eff;
+    c->mirror = h;
+    *c->h_ctl = h;
+    c->last_cycles = h.cycles;
+    cmax = std::max(cmax, h.cycles);
+    p3mz_stats& st = c->st;
+    st.status = h.status ? P3MZ_WARN_NOT_CONVERGED : P3MZ_OK;
+    st.cycles = h.cycles;
+    st.cold = was_cold;
+    st.m_eff = m_eff;
+    st.nu_pre = c->nu1;
+    st.nu_post = c->nu2;
+    st.K = c->pl.K;
+    st.levels = c->pl.levels;
+    st.nu_smooth = c->pl.nu_s;
+    st.thresh = h.thresh;
+    st.norm_qs = h.norm_qs;
+    for (int i = 0; i <= P3MZ_MAX_CYCLES; i++) st.res_hist[i] = i <= h.cycles ? h.res_hist[i] : 0.0;
+    st.e_sr = h.e_sr;
+    st.e_lr = h.e_lr;
+    st.e_self = c->e_self;
+    st.e_total = h.e_sr + h.e_lr + c->e_self;
+    st.steps = h.steps;
+    st.graphs = b->ran_graphs;
+    st.ms_mesh = st.ms_short_range = st.ms_spread = st.ms_solve = st.ms_gather = -1.0;
+  }
+  b->last_cycles = cmax;
+  if (b->timing) {
+    float ms = 0.f;
+    P3MZ_HIP_TRY(hipEventElapsedTime(&ms, b->ev[0], b->ev[1]));
+    b->ms_mesh = ms;
+    P3MZ_HIP_TRY(hipEventElapsedTime(&ms, b->ev[1], b->ev[2]));
+    b->ms_sr = ms;
+  }
+  return P3MZ_OK;
+}
+
+// One batched mesh step with the launches of `set` (kick and extra parts run
+// when `kick` / `extra` are set).  Returns NAN when a system saw a non-finite
+// position (that system's history is dropped, as for a single context).
+p3mz_status batch_step(p3mz_batch* b, BatchSet* set, hipStream_t s, bool kick, bool extra, bool* not_converged) {
+  b->ran_graphs = 0;
+  if (kick) P3MZ_TRY(batch_run_part(b, set, BQ_KICK, s));
+  if (b->timing) P3MZ_HIP_TRY(hipEventRecord(b->ev[0], s));
+  P3MZ_TRY(batch_run_part(b, set, BQ_PRE, s));
+  int max_c = 0;
+  for (p3mz_ctx* c : b->sys) max_c = std::max(max_c, c->P.max_cycles);
+  int issued = 0, batch = std::max(1, b->last_cycles);
+  for (;;) {
+    for (int k = 0; k < batch && issued < max_c; k++, issued++) P3MZ_TRY(batch_run_part(b, set, BQ_CYCLE, s));
+    P3MZ_TRY(batch_read_head(b, s));
+    if (b->h_head[0] || b->h_head[1] || issued >= max_c) break;
+    batch = 1;
+  }
+  if (b->h_head[1]) {
+    P3MZ_TRY(batch_finish(b, s));
+    for (p3mz_ctx* c : b->sys)
+      if (c->mirror.nan_flag) (void)on_nan(c);
+    b->md_have_force = false;
+    b->last_cycles = 0;
+    return fail(P3MZ_ERR_NAN, "non-finite position in a batched system");
+  }
+  P3MZ_TRY(batch_run_part(b, set, BQ_POST1, s));
+  if (b->timing) P3MZ_HIP_TRY(hipEventRecord(b->ev[1], s));
+  P3MZ_TRY(batch_run_part(b, set, BQ_POST2, s));
+  if (extra) P3MZ_TRY(batch_run_part(b, set, BQ_EXTRA, s));
+  if (b->timing) P3MZ_HIP_TRY(hipEventRecord(b->ev[2], s));
+  P3MZ_TRY(batch_finish(b, s));
+  bool nc = false;
+  for (p3mz_ctx* c : b->sys) nc |= c->st.status != P3MZ_OK;
+  *not_converged = nc;
+  b->steps++;
+  return P3MZ_OK;
+}
+
+MdArgs md_args_for(const p3mz_mdterms* t, double dt) {
+  MdArgs m{};
+  m.dt = dt;
+  m.f2a = t->force_to_acc;
+  m.mv2e = t->mv2_to_energy;
+  m.model = t->model;
+  if (t->model == 1) {
+    m.p[0] = t->bm_a;
+    m.p[1] = t->bm_rho;
+  } else if (t->model == 2) {
+    m.p[0] = t->lj_eps; m.p[1] = t->lj_sigma; m.p[2] = t->k_bond; m.p[3] = t->r0;
+    m.p[4] = t->k_angle; m.p[5] = t->theta0;
+  }
+  return m;
+}
+
+std::vector<uint64_t> md_key(const MdArgs& m) {
+  std::vector<uint64_t> k = {(uint64_t)m.model, bits(m.dt), bits(m.f2a), bits(m.mv2e)};
+  for (double v : m.p) k.push_back(bits(v));
+  return k;
+}
+
+// (Re)record the compute set for caller buffers pos/force/energy (packed;
+// force and energy NULL: each system's internal MD buffers).  With `init`
+// (forces before the first MD step) the non-electrostatic terms are added.
+p3mz_status batch_prepare_compute(p3mz_batch* b, const double* pos, double* force, double* energy,
+                                  const MdArgs* init) {
+  std::vector<uint64_t> key = {(uint64_t)(uintptr_t)pos, (uint64_t)(uintptr_t)force, (uint64_t)(uintptr_t)energy,
+                               (uint64_t)(init != nullptr)};
+  if (init) {
+    const std::vector<uint64_t> k2 = md_key(*init);
+    key.insert(key.end(), k2.begin(), k2.end());
+  }
+  if (b->compute.key == key) return P3MZ_OK;
+  b->compute.drop();
+  std::vector<unsigned char> args;
+  auto F = [&](int r) { return force ? force + 3 * b->off[r] : b->sys[r]->d_md_force; };
+  auto E = [&](int r) { return energy ? energy + 4 * r : b->sys[r]->d_energy; };
+  auto X = [&](int r) { return pos + 3 * b->off[r]; };
+  P3MZ_TRY(batch_record(b, &b->compute, BQ_PRE, &args, [&](int r) { return enq_pre(b->sys[r], X(r), nullptr); }));
+  P3MZ_TRY(batch_record(b, &b->compute, BQ_CYCLE, &args, [&](int r) { return enq_cycle(b->sys[r], nullptr); }));
+  P3MZ_TRY(batch_record(b, &b->compute, BQ_POST1, &args,
+                        [&](int r) { return enq_post1(b->sys[r], F(r), nullptr); }));
+  P3MZ_TRY(batch_record(b, &b->compute, BQ_POST2, &args,
+                        [&](int r) { return enq_post2(b->sys[r], X(r), F(r), E(r), nullptr); }));
+  b->compute.q[BQ_KICK].clear();
+  b->compute.q[BQ_EXTRA].clear();
+  if (init) {
+    P3MZ_TRY(batch_record(b, &b->compute, BQ_EXTRA, &args, [&](int r) -> p3mz_status {
+      p3mz_ctx* c = b->sys[r];
+      rec_key(6100);
+      P3MZ_HIP_TRY(launch_nonelec((int)c->n_atoms, X(r), c->P.box, c->P.r_cut, init->model, init->p[0], init->p[1],
+                                  init->p[2], init->p[3], init->p[4], init->p[5], c->nc, c->d_cstart, c->d_cperm,
+                                  c->d_md_force, c->d_partial, c->d_e_other, nullptr));
+      return P3MZ_OK;
+    }));
+  }
+  P3MZ_TRY(batch_upload(&b->compute, args));
+  b->compute.key = key;
+  return P3MZ_OK;
+}
+
+// (Re)record the MD set: kick + drift, mesh step, pairs, non-electrostatic
+// terms, closing kick and the per-system logs ([system][step] rows).
+p3mz_status batch_prepare_md(p3mz_batch* b, double* pos, double* vel, const double* mass, const MdArgs& m0,
+                             double* elog, int32_t* clog, int n_steps) {
+  std::vector<uint64_t> key = {(uint64_t)(uintptr_t)pos, (uint64_t)(uintptr_t)vel, (uint64_t)(uintptr_t)mass,
+                               (uint64_t)(uintptr_t)elog, (uint64_t)(uintptr_t)clog, (uint64_t)n_steps};
+  const std::vector<uint64_t> k2 = md_key(m0);
+  key.insert(key.end(), k2.begin(), k2.end());
+  if (b->md.key == key) return P3MZ_OK;
+  b->md.drop();
+  std::vector<unsigned char> args;
+  auto M = [&](int r) {
+    MdArgs m = m0;
+    m.pos = pos + 3 * b->off[r];
+    m.vel = vel + 3 * b->off[r];
+    m.mass = mass + b->off[r];
+    m.elog = elog ? elog + (size_t)6 * n_steps * r : nullptr;
+    m.clog = clog ? clog + (size_t)n_steps * r : nullptr;
+    return m;
+  };
+  P3MZ_TRY(batch_record(b, &b->md, BQ_KICK, &args, [&](int r) -> p3mz_status {
+    p3mz_ctx* c = b->sys[r];
+    const MdArgs m = M(r);
+    rec_key(90);
+    P3MZ_HIP_TRY(launch_kick_drift((int)c->n_atoms, m.pos, m.vel, c->d_md_force, m.mass, m.dt, m.f2a, 1, nullptr));
+    return P3MZ_OK;
+  }));
+  P3MZ_TRY(batch_record(b, &b->md, BQ_PRE, &args, [&](int r) { return enq_pre(b->sys[r], M(r).pos, nullptr); }));
+  P3MZ_TRY(batch_record(b, &b->md, BQ_CYCLE, &args, [&](int r) { return enq_cycle(b->sys[r], nullptr); }));
+  P3MZ_TRY(batch_record(b, &b->md, BQ_POST1, &args,
+                        [&](int r) { return enq_post1(b->sys[r], b->sys[r]->d_md_force, nullptr); }));
+  P3MZ_TRY(batch_record(b, &b->md, BQ_POST2, &args, [&](int r) { return enq_md_post2(b->sys[r], M(r), nullptr); }));
+  b->md.q[BQ_EXTRA].clear();
+  P3MZ_TRY(batch_upload(&b->md, args));
+  b->md.key = key;
   return P3MZ_OK;
 }
 
@@ -945,6 +1358,134 @@ const char* p3mz_status_string(p3mz_status s) {
 
 const char* p3mz_last_error(void) { return g_last_error.c_str(); }
 
-const char* p3mz_version(void) { return "p3maze-gfx950 0.2"; }
+const char* p3mz_version(void) { return "p3maze-gfx950 0.3"; }
+
+p3mz_status p3mz_batch_create(int32_t n_sys, const p3mz_params* per_sys, const int64_t* n_atoms,
+                              const double* charges_packed_host, p3mz_batch** out) {
+  if (!out) return fail(P3MZ_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (n_sys < 1 || n_sys > 65535 || !per_sys || !n_atoms || !charges_packed_host)
+    return fail(P3MZ_ERR_INVALID_ARG, "bad batch arguments");
+  for (int r = 0; r < n_sys; r++)
+    if (per_sys[r].precision != per_sys[0].precision)
+      return fail(P3MZ_ERR_INVALID_ARG, "all systems of a batch need the same precision");
+  p3mz_batch* b = new (std::nothrow) p3mz_batch();
+  if (!b) return fail(P3MZ_ERR_OUT_OF_MEMORY, "batch allocation");
+  int64_t off = 0;
+  for (int r = 0; r < n_sys; r++) {
+    p3mz_ctx* c = nullptr;
+    p3mz_status st = p3mz_create(&per_sys[r], n_atoms[r], charges_packed_host + off, &c);
+    if (st != P3MZ_OK) {
+      delete b;
+      return st;
+    }
+    b->sys.push_back(c);
+    b->off.push_back(off);
+    off += n_atoms[r];
+  }
+  b->n_total = off;
+  b->fp64 = per_sys[0].precision == P3MZ_PREC_FP64;
+  std::vector<Ctl*> ctls;
+  for (p3mz_ctx* c : b->sys) ctls.push_back(c->d_ctl);
+  auto bail = [&](p3mz_status st) {
+    delete b;
+    return st;
+  };
+#define P3MZ_BTRY(expr)                                                              \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess) return bail(hip_fail(e_, #expr, __FILE__, __LINE__));      \
+  } while (0)
+  P3MZ_BTRY(hipMalloc((void**)&b->d_ctls, n_sys * sizeof(Ctl*)));
+  P3MZ_BTRY(hipMemcpy(b->d_ctls, ctls.data(), n_sys * sizeof(Ctl*), hipMemcpyHostToDevice));
+  P3MZ_BTRY(hipMalloc((void**)&b->d_ctl_all, n_sys * sizeof(Ctl)));
+  P3MZ_BTRY(hipHostMalloc((void**)&b->h_ctl_all, n_sys * sizeof(Ctl), hipHostMallocDefault));
+  P3MZ_BTRY(hipMalloc((void**)&b->d_head, 4 * sizeof(int)));
+  P3MZ_BTRY(hipHostMalloc((void**)&b->h_head, 4 * sizeof(int), hipHostMallocDefault));
+  P3MZ_BTRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+#undef P3MZ_BTRY
+  *out = b;
+  return P3MZ_OK;
+}
+
+p3mz_status p3mz_batch_compute(p3mz_batch* b, const double* pos_dev, double* force_dev, double* energies_dev,
+                               void* stream) {
+  if (!b || !pos_dev) return fail(P3MZ_ERR_INVALID_ARG, "batch or pos_dev is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  b->md_have_force = false;
+  P3MZ_TRY(batch_prepare_compute(b, pos_dev, force_dev, energies_dev, nullptr));
+  bool nc = false;
+  P3MZ_TRY(batch_step(b, &b->compute, s, false, false, &nc));
+  if (nc) return fail(P3MZ_WARN_NOT_CONVERGED, "V-cycle cap reached before the tolerance in a batched system");
+  return P3MZ_OK;
+}
+
+p3mz_status p3mz_batch_md_run(p3mz_batch* b, double* pos_dev, double* vel_dev, const double* mass_dev,
+                              const p3mz_mdterms* terms, double dt, int32_t n_steps, double* energy_log_dev,
+                              int32_t* cycles_log_dev, void* stream) {
+  if (!b || !pos_dev || !vel_dev || !mass_dev || !terms || n_steps < 0 || !(dt > 0))
+    return fail(P3MZ_ERR_INVALID_ARG, "bad batch md_run arguments");
+  if (terms->model < 0 || terms->model > 2) return fail(P3MZ_ERR_INVALID_ARG, "unknown model");
+  if (terms->model == 2)
+    for (p3mz_ctx* c : b->sys)
+      if (c->n_atoms % 3) return fail(P3MZ_ERR_INVALID_ARG, "the water model needs O,H,H triples");
+  hipStream_t s = (hipStream_t)stream;
+  const MdArgs m0 = md_args_for(terms, dt);
+  bool nc = false;
+  if (!b->md_have_force) {
+    P3MZ_TRY(batch_prepare_compute(b, pos_dev, nullptr, nullptr, &m0));
+    P3MZ_TRY(batch_step(b, &b->compute, s, false, true, &nc));
+    b->md_have_force = true;
+  }
+  P3MZ_TRY(batch_prepare_md(b, pos_dev, vel_dev, mass_dev, m0, energy_log_dev, cycles_log_dev, n_steps));
+  hipLaunchKernelGGL(k_batch_md_reset, dim3((b->sys.size() + 255) / 256), dim3(256), 0, s, b->d_ctls,
+                     (int)b->sys.size());
+  P3MZ_HIP_TRY(hipGetLastError());
+  bool worst = false;
+  for (int step = 0; step < n_steps; step++) {
+    P3MZ_TRY(batch_step(b, &b->md, s, true, false, &nc));
+    worst |= nc;
+  }
+  if (worst) return fail(P3MZ_WARN_NOT_CONVERGED, "V-cycle cap reached before the tolerance in a batched system");
+  return P3MZ_OK;
+}
+
+p3mz_status p3mz_batch_get_stats(const p3mz_batch* b, int32_t sys, p3mz_stats* out) {
+  if (!b || !out || sys < 0 || sys >= (int)b->sys.size()) return fail(P3MZ_ERR_INVALID_ARG, "bad batch stats arguments");
+  *out = b->sys[sys]->st;
+  return P3MZ_OK;
+}
+
+p3mz_status p3mz_batch_set_timing(p3mz_batch* b, int32_t on) {
+  if (!b) return fail(P3MZ_ERR_INVALID_ARG, "batch is NULL");
+  if (on && !b->ev[0])
+    for (hipEvent_t& e : b->ev) P3MZ_HIP_TRY(hipEventCreate(&e));
+  b->timing = on != 0;
+  b->ms_mesh = b->ms_sr = -1.0;
+  return P3MZ_OK;
+}
+
+p3mz_status p3mz_batch_set_graphs(p3mz_batch* b, int32_t on) {
+  if (!b) return fail(P3MZ_ERR_INVALID_ARG, "batch is NULL");
+  P3MZ_HIP_TRY(hipDeviceSynchronize());
+  for (BatchSet* x : {&b->compute, &b->md})
+    for (GraphSlot& g : x->g) g.reset();
+  b->use_graphs = on != 0;
+  return P3MZ_OK;
+}
+
+p3mz_status p3mz_batch_get_timing(const p3mz_batch* b, double* ms_mesh, double* ms_short_range, int32_t* graphs) {
+  if (!b || !ms_mesh || !ms_short_range || !graphs) return fail(P3MZ_ERR_INVALID_ARG, "NULL argument");
+  *ms_mesh = b->ms_mesh;
+  *ms_short_range = b->ms_sr;
+  *graphs = b->ran_graphs;
+  return P3MZ_OK;
+}
+
+void p3mz_batch_destroy(p3mz_batch* b) {
+  if (!b) return;
+  (void)hipDeviceSynchronize();
+  delete b;
+}
 
 }  // extern "C"

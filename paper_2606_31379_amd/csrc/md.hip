@@ -2,6 +2,7 @@
 // non-electrostatic terms of the two model systems, and the energy log.
 #include <algorithm>
 
+#include "kern.h"
 #include "launch.h"
 
 namespace {
@@ -10,10 +11,24 @@ constexpr int kBlock = 256;
 
 inline int blocks_for(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
-__global__ void __launch_bounds__(kBlock)
-k_kick_drift(int n_atoms, double* __restrict__ pos, double* __restrict__ vel, const double* __restrict__ f,
-             const double* __restrict__ mass, double dt, double f2a, int drift) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+struct KickDrift {
+  struct Args {
+    int n_atoms, drift;
+    double dt, f2a;
+    double *pos, *vel;
+    const double *f, *mass;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G);
+};
+__device__ void KickDrift::run(const Args& A, Grid G) {
+  const int n_atoms = A.n_atoms, drift = A.drift;
+  const double dt = A.dt, f2a = A.f2a;
+  double* __restrict__ pos = A.pos;
+  double* __restrict__ vel = A.vel;
+  const double* __restrict__ f = A.f;
+  const double* __restrict__ mass = A.mass;
+  const int t = G.b * kBlock + threadIdx.x;
   if (t >= 3 * n_atoms) return;
   const int a = t / 3;
   double v = vel[t] + 0.5 * dt * f[t] / mass[a] * f2a;
@@ -29,15 +44,30 @@ __device__ __forceinline__ double mi(double d, double box, double inv_box) { ret
 // atom: lanes stride the neighbour cells' lists, lane 0 adds the bonded
 // terms of the atom's molecule that act on it (each atom's wave recomputes
 // them; no atomics), a fixed shuffle tree sums the lanes.  force += F_other.
-__global__ void __launch_bounds__(kBlock)
-k_nonelec(int n_atoms, const double* __restrict__ pos, double box, double rc2, int model, double p0,
-          double p1, double p2, double p3, double p4, double p5, int nc, const int* __restrict__ cstart,
-          const int* __restrict__ cperm, double* __restrict__ force, double* __restrict__ partial) {
+struct NonElec {
+  struct Args {
+    int n_atoms, model, nc;
+    double box, rc2, p0, p1, p2, p3, p4, p5;
+    const double* pos;
+    const int *cstart, *cperm;
+    double *force, *partial;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G);
+};
+__device__ void NonElec::run(const Args& A, Grid G) {
+  const int n_atoms = A.n_atoms, model = A.model, nc = A.nc;
+  const double box = A.box, rc2 = A.rc2, p0 = A.p0, p1 = A.p1, p2 = A.p2, p3 = A.p3, p4 = A.p4, p5 = A.p5;
+  const double* __restrict__ pos = A.pos;
+  const int* __restrict__ cstart = A.cstart;
+  const int* __restrict__ cperm = A.cperm;
+  double* __restrict__ force = A.force;
+  double* __restrict__ partial = A.partial;
   __shared__ double sh[kBlock / 64];
   const int lane = threadIdx.x & 63;
-  const int nwaves = gridDim.x * (kBlock / 64);
+  const int nwaves = G.g * (kBlock / 64);
   double en = 0.0;
-  for (int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; wave < n_atoms && model != 0; wave += nwaves) {
+  for (int wave = (G.b * kBlock + threadIdx.x) >> 6; wave < n_atoms && model != 0; wave += nwaves) {
     double fx = 0.0, fy = 0.0, fz = 0.0;
     const int i = cperm[wave];
     const double inv_box = 1.0 / box;
@@ -137,35 +167,66 @@ k_nonelec(int n_atoms, const double* __restrict__ pos, double box, double rc2, i
   if (threadIdx.x == 0) {
     double s = 0.0;
     for (int k = 0; k < kBlock / 64; k++) s += sh[k];
-    partial[blockIdx.x] = s;
+    partial[G.b] = s;
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_fin_other(int nb, const double* __restrict__ partial, double* e_out) {
-  __shared__ double sh[kBlock / 64];
-  const double tot = reduce_partials_sum(partial, nb, sh);
-  if (threadIdx.x == 0) *e_out = tot;
-}
-
-__global__ void __launch_bounds__(kBlock)
-k_kinetic(int n_atoms, const double* __restrict__ vel, const double* __restrict__ mass, double mv2e,
-          double* __restrict__ partial) {
-  __shared__ double sh[kBlock / 64];
-  double ke = 0.0;
-  for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < n_atoms; a += gridDim.x * blockDim.x) {
-    const double vx = vel[3 * a], vy = vel[3 * a + 1], vz = vel[3 * a + 2];
-    ke += 0.5 * mass[a] * (vx * vx + vy * vy + vz * vz) * mv2e;
+struct FinOther {
+  struct Args {
+    int nb;
+    const double* partial;
+    double* e_out;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid) {
+    __shared__ double sh[kBlock / 64];
+    const double tot = reduce_partials_sum(A.partial, A.nb, sh);
+    if (threadIdx.x == 0) *A.e_out = tot;
   }
-  const double bs = block_sum(ke, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = bs;
-}
+};
+
+struct Kinetic {
+  struct Args {
+    int n_atoms;
+    double mv2e;
+    const double *vel, *mass;
+    double* partial;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G) {
+    __shared__ double sh[kBlock / 64];
+    const double* __restrict__ vel = A.vel;
+    const double* __restrict__ mass = A.mass;
+    double ke = 0.0;
+    for (int a = G.b * kBlock + threadIdx.x; a < A.n_atoms; a += G.g * kBlock) {
+      const double vx = vel[3 * a], vy = vel[3 * a + 1], vz = vel[3 * a + 2];
+      ke += 0.5 * mass[a] * (vx * vx + vy * vy + vz * vz) * A.mv2e;
+    }
+    const double bs = block_sum(ke, sh);
+    if (threadIdx.x == 0) A.partial[G.b] = bs;
+  }
+};
 
 // Log row ctl->md_step of the energy/cycle logs, then advance the row.
-__global__ void __launch_bounds__(kBlock)
-k_fin_log(int nb, const double* __restrict__ partial, const double* __restrict__ e4,
-          const double* __restrict__ e_other, double* log_base, int* clog_base, Ctl* ctl) {
+struct FinLog {
+  struct Args {
+    int nb;
+    const double *partial, *e4, *e_other;
+    double* log_base;
+    int* clog_base;
+    Ctl* ctl;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G);
+};
+__device__ void FinLog::run(const Args& A, Grid) {
+  const double* __restrict__ e4 = A.e4;
+  const double* __restrict__ e_other = A.e_other;
+  double* log_base = A.log_base;
+  int* clog_base = A.clog_base;
+  Ctl* ctl = A.ctl;
   __shared__ double sh[kBlock / 64];
-  const double tot = reduce_partials_sum(partial, nb, sh);
+  const double tot = reduce_partials_sum(A.partial, A.nb, sh);
   if (threadIdx.x == 0) {
     const int k = ctl->md_step;
     if (log_base) {
@@ -182,26 +243,25 @@ k_fin_log(int nb, const double* __restrict__ partial, const double* __restrict__
 
 hipError_t launch_kick_drift(int n_atoms, double* pos, double* vel, const double* force, const double* mass,
                              double dt, double f2a, int drift, hipStream_t s) {
-  hipLaunchKernelGGL(k_kick_drift, dim3(blocks_for(3 * (int64_t)n_atoms, kBlock)), dim3(kBlock), 0, s, n_atoms,
-                     pos, vel, force, mass, dt, f2a, drift);
-  return hipGetLastError();
+  return go<KickDrift>({n_atoms, drift, dt, f2a, pos, vel, force, mass}, blocks_for(3 * (int64_t)n_atoms, kBlock), 0,
+                       s);
 }
 
 hipError_t launch_nonelec(int n_atoms, const double* pos, double box, double r_cut, int model, double p0,
                           double p1, double p2, double p3, double p4, double p5, int nc, const int* cstart,
                           const int* cperm, double* force, double* partial, double* e_out, hipStream_t s) {
   const int nb = std::min(blocks_for((int64_t)n_atoms * 64, kBlock), 2 * kMaxRedBlocks);
-  hipLaunchKernelGGL(k_nonelec, dim3(nb), dim3(kBlock), 0, s, n_atoms, pos, box, r_cut * r_cut, model, p0, p1, p2,
-                     p3, p4, p5, nc, cstart, cperm, force, partial);
-  hipLaunchKernelGGL(k_fin_other, dim3(1), dim3(kBlock), 0, s, nb, partial, e_out);
-  return hipGetLastError();
+  hipError_t e = go<NonElec>({n_atoms, model, nc, box, r_cut * r_cut, p0, p1, p2, p3, p4, p5, pos, cstart, cperm,
+                              force, partial}, nb, 0, s);
+  if (e != hipSuccess) return e;
+  return go<FinOther>({nb, partial, e_out}, 1, 0, s);
 }
 
 hipError_t launch_kinetic_log(int n_atoms, const double* vel, const double* mass, double mv2e,
                               const double* energy4, const double* e_other, double* log_base, int* clog_base,
                               Ctl* ctl, double* partial, hipStream_t s) {
   const int nb = std::min(blocks_for(n_atoms, kBlock), kMaxRedBlocks);
-  hipLaunchKernelGGL(k_kinetic, dim3(nb), dim3(kBlock), 0, s, n_atoms, vel, mass, mv2e, partial);
-  hipLaunchKernelGGL(k_fin_log, dim3(1), dim3(kBlock), 0, s, nb, partial, energy4, e_other, log_base, clog_base, ctl);
-  return hipGetLastError();
+  hipError_t e = go<Kinetic>({n_atoms, mv2e, vel, mass, partial}, nb, 0, s);
+  if (e != hipSuccess) return e;
+  return go<FinLog>({nb, partial, energy4, e_other, log_base, clog_base, ctl}, 1, 0, s);
 }

@@ -1,6 +1,7 @@
 // Mesh-side kernels of the step: charge smoothing, constraint at the Verlet
 // prediction, outer FP64 residual, the multigrid V-cycle on colour-split
 // (red/black) storage, and the field update.
+#include "kern.h"
 #include "launch.h"
 
 namespace {
@@ -42,13 +43,25 @@ __device__ __forceinline__ int cs_index(const CsGeo& g, int i, int j, int k) {
 // spread the sliding-window reads over the LDS banks.
 // ---------------------------------------------------------------------------
 template <typename T, int AXIS, int W, int R>
-__global__ void __launch_bounds__(kBlock)
-k_smooth(int n, int ntaps, int half, const T* __restrict__ taps_g, const T* __restrict__ in,
-         T* __restrict__ out) {
+struct Smooth {
+  struct Args {
+    int n, ntaps, half;
+    const T *taps, *in;
+    T* out;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G);
+};
+template <typename T, int AXIS, int W, int R>
+__device__ void Smooth<T, AXIS, W, R>::run(const Args& A, Grid G) {
+  const int n = A.n, ntaps = A.ntaps, half = A.half;
+  const T* __restrict__ taps_g = A.taps;
+  const T* __restrict__ in = A.in;
+  T* __restrict__ out = A.out;
   extern __shared__ unsigned char smem_raw[];
   T* taps = reinterpret_cast<T*>(smem_raw);          // [ntaps], broadcast reads
   T* buf = taps + ((ntaps + 1) & ~1);
-  const int g = xcd_block();
+  const int g = G.b;
   const int tid = threadIdx.x;
   for (int i = tid; i < ntaps; i += kBlock) taps[i] = taps_g[i];
   const int ld = AXIS == 0 ? n + 1 : W + 1;         // padded LDS stride between rows / positions
@@ -122,15 +135,36 @@ size_t smooth_lds_bytes(int n, int axis, int W, int ntaps, size_t elem) {
 // chunk), so their one-workgroup finalize pass reads few partials.
 // ---------------------------------------------------------------------------
 template <typename TQ>
-__global__ void __launch_bounds__(kBlock)
-k_sigma(int n, double h, const TQ* __restrict__ qs, const double* __restrict__ phi0,
-        const double* __restrict__ phi1, const double* __restrict__ yb0, const double* __restrict__ yb1,
-        const double* __restrict__ yb2, double* __restrict__ sigma, double* __restrict__ y,
-        double* __restrict__ partial, const Ctl* ctl) {
+struct Sigma {
+  struct Args {
+    int n;
+    double h;
+    const TQ* qs;
+    const double *phi0, *phi1, *yb0, *yb1, *yb2;
+    double *sigma, *y, *partial;
+    const Ctl* ctl;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G);
+};
+template <typename TQ>
+__device__ void Sigma<TQ>::run(const Args& A, Grid G) {
+  const int n = A.n;
+  const double h = A.h;
+  const TQ* __restrict__ qs = A.qs;
+  const double* __restrict__ phi0 = A.phi0;
+  const double* __restrict__ phi1 = A.phi1;
+  const double* __restrict__ yb0 = A.yb0;
+  const double* __restrict__ yb1 = A.yb1;
+  const double* __restrict__ yb2 = A.yb2;
+  double* __restrict__ sigma = A.sigma;
+  double* __restrict__ y = A.y;
+  double* __restrict__ partial = A.partial;
+  const Ctl* ctl = A.ctl;
   __shared__ double sh[kBlock / 64];
   const int n3 = n * n * n;
   int lo, hi;
-  chunk_range(n3, &lo, &hi);
+  chunk_range(G, n3, &lo, &hi);
   const int cold = ctl->cold, m_eff = ctl->m_eff;
   const double* pk = ctl->k_idx ? phi1 : phi0;
   const double* pkm1 = ctl->k_idx ? phi0 : phi1;
@@ -166,14 +200,27 @@ k_sigma(int n, double h, const TQ* __restrict__ qs, const double* __restrict__ p
   double bs = block_sum(sv, sh);
   double bm = block_max(qmax, sh);
   if (threadIdx.x == 0) {
-    partial[blockIdx.x] = bs;
-    partial[gridDim.x + blockIdx.x] = bm;
+    partial[G.b] = bs;
+    partial[G.g + G.b] = bm;
   }
 }
 
 // One workgroup: mean of sigma_p, max|q^s|, threshold; opens the step's solve.
-__global__ void __launch_bounds__(kBlock)
-k_fin_sigma(int nb, int n3, double tol, int tol_mode, const double* __restrict__ partial, Ctl* ctl) {
+struct FinSigma {
+  struct Args {
+    int nb, n3, tol_mode;
+    double tol;
+    const double* partial;
+    Ctl* ctl;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G);
+};
+__device__ void FinSigma::run(const Args& A, Grid) {
+  const int nb = A.nb, n3 = A.n3, tol_mode = A.tol_mode;
+  const double tol = A.tol;
+  const double* __restrict__ partial = A.partial;
+  Ctl* ctl = A.ctl;
   __shared__ double sh[kBlock / 64];
   const double tot = reduce_partials_sum(partial, nb, sh);
   const double mx = reduce_partials_max(partial + nb, nb, sh);
@@ -197,17 +244,38 @@ k_fin_sigma(int nb, int n3, double tol, int tol_mode, const double* __restrict__
 // residual, the running mean of y and the stop decision.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(kBlock)
-k_outer(int n, int first, const double* __restrict__ sigma, double* __restrict__ y, double* __restrict__ r64,
-        const T* __restrict__ e0, const T* __restrict__ e1, T* __restrict__ r0, T* __restrict__ r1,
-        double* __restrict__ partial, const Ctl* ctl) {
+struct Outer {
+  struct Args {
+    int n, first;
+    const double* sigma;
+    double *y, *r64;
+    const T *e0, *e1;
+    T *r0, *r1;
+    double* partial;
+    const Ctl* ctl;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G);
+};
+template <typename T>
+__device__ void Outer<T>::run(const Args& A, Grid G) {
+  const int n = A.n, first = A.first;
+  const double* __restrict__ sigma = A.sigma;
+  double* __restrict__ y = A.y;
+  double* __restrict__ r64 = A.r64;
+  const T* __restrict__ e0 = A.e0;
+  const T* __restrict__ e1 = A.e1;
+  T* __restrict__ r0 = A.r0;
+  T* __restrict__ r1 = A.r1;
+  double* __restrict__ partial = A.partial;
+  const Ctl* ctl = A.ctl;
   __shared__ double sh[kBlock / 64];
   if (ctl->done) return;
   const int c = first ? 0 : ctl->cycles + 1;
   const CsGeo g(n);
   const int n3 = n * n * n, msk = n - 1;
   int lo, hi;
-  chunk_range(n3, &lo, &hi);
+  chunk_range(G, n3, &lo, &hi);
   const double mean_sigma = ctl->mean_sigma;
   double rmax = 0.0, ysum = 0.0;
   for (int t = lo + threadIdx.x; t < hi; t += kBlock) {
@@ -240,14 +308,25 @@ k_outer(int n, int first, const double* __restrict__ sigma, double* __restrict__
   double bm = block_max(rmax, sh);
   double bs = block_sum(ysum, sh);
   if (threadIdx.x == 0) {
-    partial[blockIdx.x] = bm;
-    partial[gridDim.x + blockIdx.x] = bs;
+    partial[G.b] = bm;
+    partial[G.g + G.b] = bs;
   }
 }
 
 // One workgroup: residual of cycle c, running mean of y, stop decision.
-__global__ void __launch_bounds__(kBlock)
-k_fin_outer(int first, int max_cycles, int nb, int n3, const double* __restrict__ partial, Ctl* ctl) {
+struct FinOuter {
+  struct Args {
+    int first, max_cycles, nb, n3;
+    const double* partial;
+    Ctl* ctl;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G);
+};
+__device__ void FinOuter::run(const Args& A, Grid) {
+  const int first = A.first, max_cycles = A.max_cycles, nb = A.nb, n3 = A.n3;
+  const double* __restrict__ partial = A.partial;
+  Ctl* ctl = A.ctl;
   __shared__ double sh[kBlock / 64];
   if (ctl->done) return;
   const int c = first ? 0 : ctl->cycles + 1;
@@ -341,15 +420,29 @@ __device__ __forceinline__ void cs_nbr6_vec(const T* __restrict__ o, const CsGeo
 // First pre-smoothing sweep from e = 0: red = -r/6, then black from those reds
 // (one thread per W consecutive points of a row).
 template <typename T, int FIN>
-__global__ void __launch_bounds__(kBlock)
-k_sweep_zero(int n, const T* __restrict__ r0, const T* __restrict__ r1, T* __restrict__ e0,
-             T* __restrict__ e1, const Ctl* ctl) {
-  if (ctl->done) return;
+struct SweepZero {
+  struct Args {
+    int n;
+    const T *r0, *r1;
+    T *e0, *e1;
+    const Ctl* ctl;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G);
+};
+template <typename T, int FIN>
+__device__ void SweepZero<T, FIN>::run(const Args& A, Grid G) {
+  const int n = A.n;
+  const T* __restrict__ r0 = A.r0;
+  const T* __restrict__ r1 = A.r1;
+  T* __restrict__ e0 = A.e0;
+  T* __restrict__ e1 = A.e1;
+  if (A.ctl->done) return;
   constexpr int W = Vec<T>::W;
   using V = typename Vec<T>::type;
   const CsGeo g(n);
   const int half = n * g.hn * n;
-  const int t = (xcd_block() * blockDim.x + threadIdx.x) * W;
+  const int t = (G.b * kBlock + threadIdx.x) * W;
   if (t >= half) return;
   int m, j, k;
   cs_decode(g, t, &m, &j, &k);
@@ -370,15 +463,28 @@ k_sweep_zero(int n, const T* __restrict__ r0, const T* __restrict__ r1, T* __res
 }
 
 template <typename T, int FIN>
-__global__ void __launch_bounds__(kBlock)
-k_halfsweep(int n, int colour, T* __restrict__ ec, const T* __restrict__ eo, const T* __restrict__ rc,
-            const Ctl* ctl) {
-  if (ctl->done) return;
+struct Halfsweep {
+  struct Args {
+    int n, colour;
+    T* ec;
+    const T *eo, *rc;
+    const Ctl* ctl;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G);
+};
+template <typename T, int FIN>
+__device__ void Halfsweep<T, FIN>::run(const Args& A, Grid G) {
+  const int n = A.n, colour = A.colour;
+  T* __restrict__ ec = A.ec;
+  const T* __restrict__ eo = A.eo;
+  const T* __restrict__ rc = A.rc;
+  if (A.ctl->done) return;
   constexpr int W = Vec<T>::W;
   using V = typename Vec<T>::type;
   const CsGeo g(n);
   const int half = n * g.hn * n;
-  const int t = (xcd_block() * blockDim.x + threadIdx.x) * W;
+  const int t = (G.b * kBlock + threadIdx.x) * W;
   if (t >= half) return;
   int m, j, k;
   cs_decode(g, t, &m, &j, &k);
@@ -397,14 +503,29 @@ k_halfsweep(int n, int colour, T* __restrict__ ec, const T* __restrict__ eo, con
 // residuals are zero up to rounding (Gauss-Seidel just solved those rows), so
 // only the 13 red points of the 27-point stencil are evaluated (red_only).
 template <typename T, int FIN>
-__global__ void __launch_bounds__(kBlock)
-k_resid_restrict(int n, int red_only, const T* __restrict__ e0, const T* __restrict__ e1,
-                 const T* __restrict__ r0, const T* __restrict__ r1, T* __restrict__ rc0, T* __restrict__ rc1,
-                 const Ctl* ctl) {
-  if (ctl->done) return;
+struct ResidRestrict {
+  struct Args {
+    int n, red_only;
+    const T *e0, *e1, *r0, *r1;
+    T *rc0, *rc1;
+    const Ctl* ctl;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G);
+};
+template <typename T, int FIN>
+__device__ void ResidRestrict<T, FIN>::run(const Args& A, Grid G) {
+  const int n = A.n, red_only = A.red_only;
+  const T* __restrict__ e0 = A.e0;
+  const T* __restrict__ e1 = A.e1;
+  const T* __restrict__ r0 = A.r0;
+  const T* __restrict__ r1 = A.r1;
+  T* __restrict__ rc0 = A.rc0;
+  T* __restrict__ rc1 = A.rc1;
+  if (A.ctl->done) return;
   const CsGeo g(n), gc(n >> 1);
   const int nc = gc.n;
-  const int t = xcd_block() * blockDim.x + threadIdx.x;
+  const int t = G.b * kBlock + threadIdx.x;
   if (t >= nc * nc * nc) return;
   const int I = t & (nc - 1), J = (t >> gc.l2) & (nc - 1), K = t >> (2 * gc.l2);
   const T wt[3] = {T(0.25), T(0.5), T(0.25)};
@@ -459,12 +580,26 @@ __device__ __forceinline__ T prolong_at(const T* __restrict__ c0, const T* __res
 // reads only black neighbours, so only the black points receive the
 // trilinear correction here; the red half-sweep follows.
 template <typename T, int FIN>
-__global__ void __launch_bounds__(kBlock)
-k_prolong_black(int n, T* __restrict__ e1, const T* __restrict__ ec0, const T* __restrict__ ec1, const Ctl* ctl) {
-  if (ctl->done) return;
+struct ProlongBlack {
+  struct Args {
+    int n;
+    T* e1;
+    const T *ec0, *ec1;
+    const Ctl* ctl;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G);
+};
+template <typename T, int FIN>
+__device__ void ProlongBlack<T, FIN>::run(const Args& A, Grid G) {
+  const int n = A.n;
+  T* __restrict__ e1 = A.e1;
+  const T* __restrict__ ec0 = A.ec0;
+  const T* __restrict__ ec1 = A.ec1;
+  if (A.ctl->done) return;
   const CsGeo g(n), gc(n >> 1);
   const int half = n * g.hn * n;
-  const int t = xcd_block() * blockDim.x + threadIdx.x;
+  const int t = G.b * kBlock + threadIdx.x;
   if (t >= half) return;
   int m, j, k;
   cs_decode(g, t, &m, &j, &k);
@@ -473,13 +608,27 @@ k_prolong_black(int n, T* __restrict__ e1, const T* __restrict__ ec0, const T* _
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock)
-k_prolong_add(int n, T* __restrict__ e0, T* __restrict__ e1, const T* __restrict__ ec0,
-              const T* __restrict__ ec1, const Ctl* ctl) {
-  if (ctl->done) return;
+struct ProlongAdd {
+  struct Args {
+    int n;
+    T *e0, *e1;
+    const T *ec0, *ec1;
+    const Ctl* ctl;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G);
+};
+template <typename T>
+__device__ void ProlongAdd<T>::run(const Args& A, Grid G) {
+  const int n = A.n;
+  T* __restrict__ e0 = A.e0;
+  T* __restrict__ e1 = A.e1;
+  const T* __restrict__ ec0 = A.ec0;
+  const T* __restrict__ ec1 = A.ec1;
+  if (A.ctl->done) return;
   const CsGeo g(n), gc(n >> 1);
   const int half = n * g.hn * n;
-  const int t = xcd_block() * blockDim.x + threadIdx.x;
+  const int t = G.b * kBlock + threadIdx.x;
   if (t >= half) return;
   int m, j, k;
   cs_decode(g, t, &m, &j, &k);
@@ -489,15 +638,22 @@ k_prolong_add(int n, T* __restrict__ e0, T* __restrict__ e1, const T* __restrict
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_fill_zero(int64_t count, T* __restrict__ a, T* __restrict__ b,
-                                                      const Ctl* ctl) {
-  if (ctl->done) return;
-  const int64_t t = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
-  if (t < count) {
-    a[t] = T(0);
-    b[t] = T(0);
+struct FillZero {
+  struct Args {
+    int64_t count;
+    T *a, *b;
+    const Ctl* ctl;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G) {
+    if (A.ctl->done) return;
+    const int64_t t = (int64_t)G.b * kBlock + threadIdx.x;
+    if (t < A.count) {
+      A.a[t] = T(0);
+      A.b[t] = T(0);
+    }
   }
-}
+};
 
 // ---------------------------------------------------------------------------
 // Tail of the V-cycle: all levels from n0 <= 16 down to 4^3 and back in one
@@ -530,9 +686,26 @@ __device__ __forceinline__ void tail_rbgs(T* e, const T* r, int n, int l2, int c
 }
 
 template <typename T>
-__global__ void __launch_bounds__(1024)
-k_tail(int n0, int levels, int nu1, int nu2, const T* __restrict__ r0g, const T* __restrict__ r1g,
-       T* __restrict__ e0g, T* __restrict__ e1g, const double* __restrict__ green, const Ctl* ctl) {
+struct Tail {
+  struct Args {
+    int n0, levels, nu1, nu2;
+    const T *r0, *r1;
+    T *e0, *e1;
+    const double* green;
+    const Ctl* ctl;
+  };
+  static constexpr int kThreads = 1024;
+  __device__ static void run(const Args& A, Grid G);
+};
+template <typename T>
+__device__ void Tail<T>::run(const Args& A, Grid) {
+  const int n0 = A.n0, levels = A.levels, nu1 = A.nu1, nu2 = A.nu2;
+  const T* __restrict__ r0g = A.r0;
+  const T* __restrict__ r1g = A.r1;
+  T* __restrict__ e0g = A.e0;
+  T* __restrict__ e1g = A.e1;
+  const double* __restrict__ green = A.green;
+  const Ctl* ctl = A.ctl;
   if (ctl && ctl->done) return;
   extern __shared__ unsigned char smem_raw[];
   __shared__ double G[64];
@@ -660,11 +833,32 @@ size_t tail_lds_bytes(int n0, int levels, size_t elem) {
 // phi^{k+1} = phi_p - (4 pi / h) y*, with y* projected to zero mean; the
 // multiplier is pushed into the history on warm steps.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock)
-k_phi_update(int n3, double h, double* __restrict__ phi0, double* __restrict__ phi1,
-             const double* __restrict__ ya, const double* __restrict__ yb, double* __restrict__ yh0,
-             double* __restrict__ yh1, double* __restrict__ yh2, float* __restrict__ phi32, const Ctl* ctl) {
-  const int t = xcd_block() * blockDim.x + threadIdx.x;
+struct PhiUpdate {
+  struct Args {
+    int n3;
+    double h;
+    double *phi0, *phi1;
+    const double *ya, *yb;
+    double *yh0, *yh1, *yh2;
+    float* phi32;
+    const Ctl* ctl;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G);
+};
+__device__ void PhiUpdate::run(const Args& A, Grid G) {
+  const int n3 = A.n3;
+  const double h = A.h;
+  double* __restrict__ phi0 = A.phi0;
+  double* __restrict__ phi1 = A.phi1;
+  const double* __restrict__ ya = A.ya;
+  const double* __restrict__ yb = A.yb;
+  double* __restrict__ yh0 = A.yh0;
+  double* __restrict__ yh1 = A.yh1;
+  double* __restrict__ yh2 = A.yh2;
+  float* __restrict__ phi32 = A.phi32;
+  const Ctl* ctl = A.ctl;
+  const int t = G.b * kBlock + threadIdx.x;
   if (t >= n3) return;
   const int cold = ctl->cold;
   double* pk = ctl->k_idx ? phi1 : phi0;
@@ -686,7 +880,15 @@ k_phi_update(int n3, double h, double* __restrict__ phi0, double* __restrict__ p
 
 // End of a step: rotate the potential and multiplier history (cold solves
 // store no multiplier) and ramp the predictor order with the stored history.
-__global__ void k_advance(Ctl* ctl) {
+struct Advance {
+  struct Args {
+    Ctl* ctl;
+  };
+  static constexpr int kThreads = 64;
+  __device__ static void run(const Args& A, Grid G);
+};
+__device__ void Advance::run(const Args& A, Grid) {
+  Ctl* ctl = A.ctl;
   if (threadIdx.x != 0) return;
   if (ctl->cold) {
     ctl->n_yh = 0;
@@ -750,66 +952,89 @@ int sweep_blocks(int n) {
   return blocks_for((int64_t)n * n * n / 2 / Vec<T>::W, kBlock);
 }
 template <typename T, int FIN>
-void launch_sweep0(int n, T* r0, T* r1, T* e0, T* e1, Ctl* ctl, hipStream_t s) {
-  hipLaunchKernelGGL((k_sweep_zero<T, FIN>), dim3(sweep_blocks<T>(n)), dim3(kBlock), 0, s, n, r0, r1, e0, e1, ctl);
+hipError_t launch_sweep0(int n, T* r0, T* r1, T* e0, T* e1, Ctl* ctl, hipStream_t s) {
+  return go<SweepZero<T, FIN>>({n, r0, r1, e0, e1, ctl}, sweep_blocks<T>(n), 0, s);
 }
 template <typename T, int FIN>
-void launch_half(int n, int colour, T* ec, const T* eo, const T* rc, Ctl* ctl, hipStream_t s) {
-  hipLaunchKernelGGL((k_halfsweep<T, FIN>), dim3(sweep_blocks<T>(n)), dim3(kBlock), 0, s, n, colour, ec, eo, rc,
-                     ctl);
+hipError_t launch_half(int n, int colour, T* ec, const T* eo, const T* rc, Ctl* ctl, hipStream_t s) {
+  return go<Halfsweep<T, FIN>>({n, colour, ec, eo, rc, ctl}, sweep_blocks<T>(n), 0, s);
 }
 template <typename T, int FIN>
-void launch_restrict(int n, int red_only, const T* e0, const T* e1, const T* r0, const T* r1, T* rc0, T* rc1,
-                     Ctl* ctl, hipStream_t s) {
+hipError_t launch_restrict(int n, int red_only, const T* e0, const T* e1, const T* r0, const T* r1, T* rc0, T* rc1,
+                           Ctl* ctl, hipStream_t s) {
   const int nc = n / 2;
-  hipLaunchKernelGGL((k_resid_restrict<T, FIN>), dim3(blocks_for(nc * nc * nc, kBlock)), dim3(kBlock), 0, s, n,
-                     red_only, e0, e1, r0, r1, rc0, rc1, ctl);
+  return go<ResidRestrict<T, FIN>>({n, red_only, e0, e1, r0, r1, rc0, rc1, ctl}, blocks_for(nc * nc * nc, kBlock), 0,
+                                   s);
 }
 template <typename T, int FIN>
-void launch_prolong_black(int n, int nb, T* e1, const T* c0, const T* c1, Ctl* ctl, hipStream_t s) {
-  hipLaunchKernelGGL((k_prolong_black<T, FIN>), dim3(nb), dim3(kBlock), 0, s, n, e1, c0, c1, ctl);
+hipError_t launch_prolong_black(int n, int nb, T* e1, const T* c0, const T* c1, Ctl* ctl, hipStream_t s) {
+  return go<ProlongBlack<T, FIN>>({n, e1, c0, c1, ctl}, nb, 0, s);
 }
+template <typename T>
+hipError_t launch_tail(const LevelBufs* lv, int levels, int tail, int nu1, int nu2, const double* green, Ctl* ctl,
+                       hipStream_t s) {
+  const int lt = levels - tail;
+  return go<Tail<T>>({lv[tail].n, lt, nu1, nu2, (const T*)lv[tail].r0, (const T*)lv[tail].r1, (T*)lv[tail].e0,
+                      (T*)lv[tail].e1, green, ctl},
+                     1, tail_lds_bytes(lv[tail].n, lt, sizeof(T)), s);
+}
+
+#define P3MZ_LAUNCH(...)             \
+  do {                               \
+    hipError_t e_ = (__VA_ARGS__);   \
+    if (e_ != hipSuccess) return e_; \
+  } while (0)
+
+// Sequence keys of the V-cycle launches (merge keys of batched systems):
+// level l from the finest going down, the tail, then the levels going up in
+// reverse, so systems with fewer levels keep their own order in a batch.
+// Sub-keys: 0..32 sweeps and prolongation, 62 zero fill, 63 restriction /
+// plain prolongation.
+inline uint32_t key_down(int l, int sub) { return 1000u + 64u * (uint32_t)l + (uint32_t)sub; }
+inline uint32_t key_up(int l, int sub) { return 3000u + 64u * (uint32_t)(P3MZ_MAX_LEVELS - 1 - l) + (uint32_t)sub; }
+constexpr uint32_t kKeyTail = 2100u;
 
 template <typename T>
 hipError_t vcycle_impl(const LevelBufs* lv, int levels, int tail, int nu1, int nu2, const double* green,
                        Ctl* ctl, hipStream_t s) {
   const double ts = sizeof(T);
   for (int l = 0; l < tail; l++) {
-    const int n = lv[l].n, half = n * n * n / 2, nb = blocks_for(half, kBlock);
+    const int n = lv[l].n, half = n * n * n / 2;
     const double n3 = (double)n * n * n;
     T *e0 = (T*)lv[l].e0, *e1 = (T*)lv[l].e1, *r0 = (T*)lv[l].r0, *r1 = (T*)lv[l].r1;
     if (nu1 >= 1) {
+      rec_key(key_down(l, 0));
       kt_begin(KT_SWEEP0, l, s);
-      if (l == 0) launch_sweep0<T, 1>(n, r0, r1, e0, e1, ctl, s);
-      else launch_sweep0<T, 0>(n, r0, r1, e0, e1, ctl, s);
+      P3MZ_LAUNCH(l == 0 ? launch_sweep0<T, 1>(n, r0, r1, e0, e1, ctl, s) : launch_sweep0<T, 0>(n, r0, r1, e0, e1, ctl, s));
       kt_end(KT_SWEEP0, l, 2.0 * ts * n3, s);
       for (int it = 1; it < nu1; it++) {
         for (int colour = 0; colour < 2; colour++) {
           T* ec = colour ? e1 : e0;
           const T* eo = colour ? e0 : e1;
           const T* rc = colour ? r1 : r0;
+          rec_key(key_down(l, 1 + 2 * (it - 1) + colour));
           kt_begin(KT_HALFSWEEP, l, s);
-          if (l == 0) launch_half<T, 1>(n, colour, ec, eo, rc, ctl, s);
-          else launch_half<T, 0>(n, colour, ec, eo, rc, ctl, s);
+          P3MZ_LAUNCH(l == 0 ? launch_half<T, 1>(n, colour, ec, eo, rc, ctl, s)
+                             : launch_half<T, 0>(n, colour, ec, eo, rc, ctl, s));
           kt_end(KT_HALFSWEEP, l, 1.5 * ts * n3, s);
         }
       }
     } else {
-      hipLaunchKernelGGL(k_fill_zero<T>, dim3(nb), dim3(kBlock), 0, s, (int64_t)half, e0, e1, ctl);
+      rec_key(key_down(l, 62));
+      P3MZ_LAUNCH(go<FillZero<T>>({(int64_t)half, e0, e1, ctl}, blocks_for(half, kBlock), 0, s));
     }
+    rec_key(key_down(l, 63));
     kt_begin(KT_RESTRICT, l, s);
     T *c0 = (T*)lv[l + 1].r0, *c1 = (T*)lv[l + 1].r1;
-    if (l == 0) launch_restrict<T, 1>(n, nu1 >= 1, e0, e1, r0, r1, c0, c1, ctl, s);
-    else launch_restrict<T, 0>(n, nu1 >= 1, e0, e1, r0, r1, c0, c1, ctl, s);
+    P3MZ_LAUNCH(l == 0 ? launch_restrict<T, 1>(n, nu1 >= 1, e0, e1, r0, r1, c0, c1, ctl, s)
+                       : launch_restrict<T, 0>(n, nu1 >= 1, e0, e1, r0, r1, c0, c1, ctl, s));
     kt_end(KT_RESTRICT, l, 2.125 * ts * n3, s);
   }
   {
-    const int lt = levels - tail;
     const double nt3 = (double)lv[tail].n * lv[tail].n * lv[tail].n;
-    size_t lds = tail_lds_bytes(lv[tail].n, lt, sizeof(T));
+    rec_key(kKeyTail);
     kt_begin(KT_TAIL, 0, s);
-    hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(1024), lds, s, lv[tail].n, lt, nu1, nu2, (const T*)lv[tail].r0,
-                       (const T*)lv[tail].r1, (T*)lv[tail].e0, (T*)lv[tail].e1, green, ctl);
+    P3MZ_LAUNCH(launch_tail<T>(lv, levels, tail, nu1, nu2, green, ctl, s));
     kt_end(KT_TAIL, 0, 2.0 * ts * nt3, s);
   }
   for (int l = tail - 1; l >= 0; l--) {
@@ -818,28 +1043,31 @@ hipError_t vcycle_impl(const LevelBufs* lv, int levels, int tail, int nu1, int n
     T *e0 = (T*)lv[l].e0, *e1 = (T*)lv[l].e1, *r0 = (T*)lv[l].r0, *r1 = (T*)lv[l].r1;
     const T *c0 = (const T*)lv[l + 1].e0, *c1 = (const T*)lv[l + 1].e1;
     if (nu2 >= 1) {
+      rec_key(key_up(l, 0));
       kt_begin(KT_PROLONG, l, s);
-      if (l == 0) launch_prolong_black<T, 1>(n, nb, e1, c0, c1, ctl, s);
-      else launch_prolong_black<T, 0>(n, nb, e1, c0, c1, ctl, s);
+      P3MZ_LAUNCH(l == 0 ? launch_prolong_black<T, 1>(n, nb, e1, c0, c1, ctl, s)
+                         : launch_prolong_black<T, 0>(n, nb, e1, c0, c1, ctl, s));
       kt_end(KT_PROLONG, l, 1.125 * ts * n3, s);
       for (int it = 0; it < nu2; it++) {
         for (int colour = 0; colour < 2; colour++) {
           T* ec = colour ? e1 : e0;
           const T* eo = colour ? e0 : e1;
           const T* rc = colour ? r1 : r0;
+          rec_key(key_up(l, 1 + 2 * it + colour));
           kt_begin(KT_HALFSWEEP, l, s);
-          if (l == 0) launch_half<T, 1>(n, colour, ec, eo, rc, ctl, s);
-          else launch_half<T, 0>(n, colour, ec, eo, rc, ctl, s);
+          P3MZ_LAUNCH(l == 0 ? launch_half<T, 1>(n, colour, ec, eo, rc, ctl, s)
+                             : launch_half<T, 0>(n, colour, ec, eo, rc, ctl, s));
           kt_end(KT_HALFSWEEP, l, 1.5 * ts * n3, s);
         }
       }
     } else {
+      rec_key(key_up(l, 63));
       kt_begin(KT_PROLONG, l, s);
-      hipLaunchKernelGGL(k_prolong_add<T>, dim3(nb), dim3(kBlock), 0, s, n, e0, e1, c0, c1, ctl);
+      P3MZ_LAUNCH(go<ProlongAdd<T>>({n, e0, e1, c0, c1, ctl}, nb, 0, s));
       kt_end(KT_PROLONG, l, 2.125 * ts * n3, s);
     }
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 // One launch of a finest-level V-cycle kernel family on the current buffers
@@ -853,36 +1081,25 @@ hipError_t one_kernel(int kid, const LevelBufs* lv, int levels, int tail, int nu
   if ((kid == KT_HALFSWEEP || kid == KT_SWEEP0) && (n / 2) % Vec<T>::W != 0) return hipErrorInvalidValue;
   switch (kid) {
     case KT_HALFSWEEP:
-      launch_half<T, 1>(n, 0, e0, e1, r0, ctl, s);
       *bytes = 1.5 * ts * n3;
-      break;
+      return launch_half<T, 1>(n, 0, e0, e1, r0, ctl, s);
     case KT_SWEEP0:
-      launch_sweep0<T, 1>(n, r0, r1, e0, e1, ctl, s);
       *bytes = 2.0 * ts * n3;
-      break;
+      return launch_sweep0<T, 1>(n, r0, r1, e0, e1, ctl, s);
     case KT_RESTRICT:
       if (tail == 0) return hipErrorInvalidValue;
-      launch_restrict<T, 1>(n, nu1 >= 1, e0, e1, r0, r1, (T*)lv[1].r0, (T*)lv[1].r1, ctl, s);
       *bytes = 2.125 * ts * n3;
-      break;
+      return launch_restrict<T, 1>(n, nu1 >= 1, e0, e1, r0, r1, (T*)lv[1].r0, (T*)lv[1].r1, ctl, s);
     case KT_PROLONG:
       if (tail == 0) return hipErrorInvalidValue;
-      launch_prolong_black<T, 1>(n, nb, e1, (const T*)lv[1].e0, (const T*)lv[1].e1, ctl, s);
       *bytes = 1.125 * ts * n3;
-      break;
-    case KT_TAIL: {
-      const int lt = levels - tail;
-      const double nt3 = (double)lv[tail].n * lv[tail].n * lv[tail].n;
-      hipLaunchKernelGGL(k_tail<T>, dim3(1), dim3(1024), tail_lds_bytes(lv[tail].n, lt, sizeof(T)), s, lv[tail].n, lt,
-                         nu1, nu2, (const T*)lv[tail].r0, (const T*)lv[tail].r1, (T*)lv[tail].e0, (T*)lv[tail].e1,
-                         green, ctl);
-      *bytes = 2.0 * ts * nt3;
-      break;
-    }
+      return launch_prolong_black<T, 1>(n, nb, e1, (const T*)lv[1].e0, (const T*)lv[1].e1, ctl, s);
+    case KT_TAIL:
+      *bytes = 2.0 * ts * (double)lv[tail].n * lv[tail].n * lv[tail].n;
+      return launch_tail<T>(lv, levels, tail, nu1, nu2, green, ctl, s);
     default:
       return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 }  // namespace
@@ -896,40 +1113,34 @@ hipError_t launch_smooth(bool fp64, int n, int axis, int ntaps, int half, const 
   if (!fp64) return hipErrorInvalidValue;   // the charge source is FP64 in both modes
   const int W = kSmoothW;
   if (n % W || n % kSmoothR) return hipErrorInvalidValue;
-  const dim3 grid = axis == 0 ? dim3((unsigned)((size_t)n * n / W)) : dim3((unsigned)((n / W) * n));
+  const int grid = axis == 0 ? (int)((size_t)n * n / W) : (n / W) * n;
   const size_t lds = smooth_lds_bytes(n, axis, W, ntaps, 8);
-  if (axis == 0)
-    hipLaunchKernelGGL((k_smooth<double, 0, kSmoothW, kSmoothR>), grid, dim3(kBlock), lds, s, n, ntaps, half,
-                       (const double*)taps, (const double*)in, (double*)out);
-  else if (axis == 1)
-    hipLaunchKernelGGL((k_smooth<double, 1, kSmoothW, kSmoothR>), grid, dim3(kBlock), lds, s, n, ntaps, half,
-                       (const double*)taps, (const double*)in, (double*)out);
-  else
-    hipLaunchKernelGGL((k_smooth<double, 2, kSmoothW, kSmoothR>), grid, dim3(kBlock), lds, s, n, ntaps, half,
-                       (const double*)taps, (const double*)in, (double*)out);
-  return hipGetLastError();
+  const double *tp = (const double*)taps, *ip = (const double*)in;
+  double* op = (double*)out;
+  if (axis == 0) return go<Smooth<double, 0, kSmoothW, kSmoothR>>({n, ntaps, half, tp, ip, op}, grid, lds, s);
+  if (axis == 1) return go<Smooth<double, 1, kSmoothW, kSmoothR>>({n, ntaps, half, tp, ip, op}, grid, lds, s);
+  return go<Smooth<double, 2, kSmoothW, kSmoothR>>({n, ntaps, half, tp, ip, op}, grid, lds, s);
 }
 
+// Dynamic-LDS limits only ever grow, so contexts of different mesh sizes can
+// coexist in one process.
 hipError_t smooth_configure(int n) {
+  static int granted = 0;
   const int bytes = (int)smooth_lds_bytes(n, 0, kSmoothW, n, 8);
-  hipError_t e = hipFuncSetAttribute((const void*)k_smooth<double, 0, kSmoothW, kSmoothR>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_smooth<double, 1, kSmoothW, kSmoothR>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_smooth<double, 2, kSmoothW, kSmoothR>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (bytes <= granted) return hipSuccess;
+  P3MZ_LAUNCH(allow_lds<Smooth<double, 0, kSmoothW, kSmoothR>>(bytes));
+  P3MZ_LAUNCH(allow_lds<Smooth<double, 1, kSmoothW, kSmoothR>>(bytes));
+  P3MZ_LAUNCH(allow_lds<Smooth<double, 2, kSmoothW, kSmoothR>>(bytes));
+  granted = bytes;
+  return hipSuccess;
 }
 
 hipError_t launch_sigma(int n, double h, const double* qs, const double* phi0, const double* phi1,
                         const double* yb0, const double* yb1, const double* yb2, double* sigma, double* y,
                         double tol, int tol_mode, double* partial, Ctl* ctl, hipStream_t s) {
   const int n3 = n * n * n, nb = red_blocks(n3);
-  hipLaunchKernelGGL(k_sigma<double>, dim3(nb), dim3(kBlock), 0, s, n, h, qs, phi0, phi1, yb0, yb1, yb2, sigma, y,
-                     partial, ctl);
-  hipLaunchKernelGGL(k_fin_sigma, dim3(1), dim3(kBlock), 0, s, nb, n3, tol, tol_mode, partial, ctl);
-  return hipGetLastError();
+  P3MZ_LAUNCH(go<Sigma<double>>({n, h, qs, phi0, phi1, yb0, yb1, yb2, sigma, y, partial, ctl}, nb, 0, s));
+  return go<FinSigma>({nb, n3, tol_mode, tol, partial, ctl}, 1, 0, s);
 }
 
 hipError_t launch_outer(bool fp64, int n, int first, int max_cycles, const double* sigma, double* y, double* r64,
@@ -937,13 +1148,12 @@ hipError_t launch_outer(bool fp64, int n, int first, int max_cycles, const doubl
                         hipStream_t s) {
   const int n3 = n * n * n, nb = red_blocks(n3);
   if (fp64)
-    hipLaunchKernelGGL(k_outer<double>, dim3(nb), dim3(kBlock), 0, s, n, first, sigma, y, r64, (const double*)e0,
-                       (const double*)e1, (double*)r0, (double*)r1, partial, ctl);
+    P3MZ_LAUNCH(go<Outer<double>>({n, first, sigma, y, r64, (const double*)e0, (const double*)e1, (double*)r0,
+                                   (double*)r1, partial, ctl}, nb, 0, s));
   else
-    hipLaunchKernelGGL(k_outer<float>, dim3(nb), dim3(kBlock), 0, s, n, first, sigma, y, r64, (const float*)e0,
-                       (const float*)e1, (float*)r0, (float*)r1, partial, ctl);
-  hipLaunchKernelGGL(k_fin_outer, dim3(1), dim3(kBlock), 0, s, first, max_cycles, nb, n3, partial, ctl);
-  return hipGetLastError();
+    P3MZ_LAUNCH(go<Outer<float>>({n, first, sigma, y, r64, (const float*)e0, (const float*)e1, (float*)r0,
+                                  (float*)r1, partial, ctl}, nb, 0, s));
+  return go<FinOuter>({first, max_cycles, nb, n3, partial, ctl}, 1, 0, s);
 }
 
 hipError_t launch_vcycle(bool fp64, const LevelBufs* lv, int levels, int tail, int nu1, int nu2,
@@ -959,25 +1169,22 @@ hipError_t launch_vcycle_kernel(bool fp64, int kid, const LevelBufs* lv, int lev
 }
 
 hipError_t tail_configure(bool fp64, int n_tail, int levels_tail, size_t* lds_bytes) {
-  size_t b = tail_lds_bytes(n_tail, levels_tail, fp64 ? 8 : 4);
+  static int granted[2] = {0, 0};
+  const size_t b = tail_lds_bytes(n_tail, levels_tail, fp64 ? 8 : 4);
   *lds_bytes = b;
-  hipError_t e = fp64 ? hipFuncSetAttribute((const void*)k_tail<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b)
-                      : hipFuncSetAttribute((const void*)k_tail<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b);
-  return e;
+  if ((int)b <= granted[fp64]) return hipSuccess;
+  P3MZ_LAUNCH(fp64 ? allow_lds<Tail<double>>((int)b) : allow_lds<Tail<float>>((int)b));
+  granted[fp64] = (int)b;
+  return hipSuccess;
 }
 
 hipError_t launch_phi_update(int n, double h, double* phi0, double* phi1, const double* ya, const double* yb,
                              double* yh0, double* yh1, double* yh2, float* phi32, Ctl* ctl, hipStream_t s) {
   const int n3 = n * n * n;
-  hipLaunchKernelGGL(k_phi_update, dim3(blocks_for(n3, kBlock)), dim3(kBlock), 0, s, n3, h, phi0, phi1, ya, yb,
-                     yh0, yh1, yh2, phi32, ctl);
-  return hipGetLastError();
+  return go<PhiUpdate>({n3, h, phi0, phi1, ya, yb, yh0, yh1, yh2, phi32, ctl}, blocks_for(n3, kBlock), 0, s);
 }
 
-hipError_t launch_advance(Ctl* ctl, hipStream_t s) {
-  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, ctl);
-  return hipGetLastError();
-}
+hipError_t launch_advance(Ctl* ctl, hipStream_t s) { return go<Advance>({ctl}, 1, 0, s); }
 
 hipError_t launch_widen(bool fp64, int64_t count, const void* in, double* out, hipStream_t s) {
   const int nb = blocks_for(count, kBlock);

@@ -2,6 +2,7 @@
 // charge spread, force/energy gather and the short-range pair term.
 #include <algorithm>
 
+#include "kern.h"
 #include "launch.h"
 
 namespace {
@@ -30,11 +31,30 @@ __device__ __forceinline__ void stencil_origin(double x, double box, int n, int 
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock)
-k_bin_stencil(int n_atoms, const double* __restrict__ pos, double box, int n, int p, int tile,
-              int ntx, int* __restrict__ base, T* __restrict__ w, int* __restrict__ key,
-              int* __restrict__ slot, int* __restrict__ count, Ctl* ctl) {
-  int a = blockIdx.x * blockDim.x + threadIdx.x;
+struct BinStencil {
+  struct Args {
+    int n_atoms, n, p, tile, ntx;
+    double box;
+    const double* pos;
+    int *base, *key, *slot, *count;
+    T* w;
+    Ctl* ctl;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G);
+};
+template <typename T>
+__device__ void BinStencil<T>::run(const Args& A, Grid G) {
+  const int n_atoms = A.n_atoms, n = A.n, p = A.p, tile = A.tile, ntx = A.ntx;
+  const double box = A.box;
+  const double* __restrict__ pos = A.pos;
+  int* __restrict__ base = A.base;
+  T* __restrict__ w = A.w;
+  int* __restrict__ key = A.key;
+  int* __restrict__ slot = A.slot;
+  int* __restrict__ count = A.count;
+  Ctl* ctl = A.ctl;
+  int a = G.b * kBlock + threadIdx.x;
   if (a >= n_atoms) return;
   int tk[3];
   for (int d = 0; d < 3; d++) {
@@ -59,10 +79,26 @@ k_bin_stencil(int n_atoms, const double* __restrict__ pos, double box, int n, in
   slot[a] = atomicAdd(&count[k], 1);
 }
 
-__global__ void __launch_bounds__(kBlock)
-k_bin_cells(int n_atoms, const double* __restrict__ pos, double box, int nc, int* __restrict__ key,
-            int* __restrict__ slot, int* __restrict__ count, Ctl* ctl) {
-  int a = blockIdx.x * blockDim.x + threadIdx.x;
+struct BinCells {
+  struct Args {
+    int n_atoms, nc;
+    double box;
+    const double* pos;
+    int *key, *slot, *count;
+    Ctl* ctl;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G);
+};
+__device__ void BinCells::run(const Args& A, Grid G) {
+  const int n_atoms = A.n_atoms, nc = A.nc;
+  const double box = A.box;
+  const double* __restrict__ pos = A.pos;
+  int* __restrict__ key = A.key;
+  int* __restrict__ slot = A.slot;
+  int* __restrict__ count = A.count;
+  Ctl* ctl = A.ctl;
+  int a = G.b * kBlock + threadIdx.x;
   if (a >= n_atoms) return;
   int c[3];
   for (int d = 0; d < 3; d++) {
@@ -88,9 +124,21 @@ k_bin_cells(int n_atoms, const double* __restrict__ pos, double box, int nc, int
 constexpr int kScanPer = 16;                     // counts per thread
 constexpr int kScanChunk = kBlock * kScanPer;    // counts per workgroup
 
-__global__ void __launch_bounds__(kBlock) k_scan_sums(int nbins, const int* __restrict__ count, int* __restrict__ bsum) {
+struct ScanSums {
+  struct Args {
+    int nbins;
+    const int* count;
+    int* bsum;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G);
+};
+__device__ void ScanSums::run(const Args& A, Grid G) {
+  const int nbins = A.nbins;
+  const int* __restrict__ count = A.count;
+  int* __restrict__ bsum = A.bsum;
   __shared__ int sh[kBlock];
-  const int base = blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
+  const int base = G.b * kScanChunk + threadIdx.x * kScanPer;
   int s = 0;
   for (int q = 0; q < kScanPer; q++) s += base + q < nbins ? count[base + q] : 0;
   sh[threadIdx.x] = s;
@@ -99,10 +147,20 @@ __global__ void __launch_bounds__(kBlock) k_scan_sums(int nbins, const int* __re
     if (threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) bsum[blockIdx.x] = sh[0];
+  if (threadIdx.x == 0) bsum[G.b] = sh[0];
 }
 
-__global__ void __launch_bounds__(1024) k_scan_top(int nb, int* __restrict__ bsum) {
+struct ScanTop {
+  struct Args {
+    int nb;
+    int* bsum;
+  };
+  static constexpr int kThreads = 1024;
+  __device__ static void run(const Args& A, Grid G);
+};
+__device__ void ScanTop::run(const Args& A, Grid) {
+  const int nb = A.nb;
+  int* __restrict__ bsum = A.bsum;
   __shared__ int sh[1024];
   const int t = threadIdx.x;
   const int per = (nb + 1023) / 1024;
@@ -117,19 +175,31 @@ __global__ void __launch_bounds__(1024) k_scan_top(int nb, int* __restrict__ bsu
     sh[t] += v;
     __syncthreads();
   }
-  int run = sh[t] - local;
+  int acc = sh[t] - local;
   for (int b = b0; b < b1; b++) {
     const int v = bsum[b];
-    bsum[b] = run;
-    run += v;
+    bsum[b] = acc;
+    acc += v;
   }
   if (t == 1023) bsum[nb] = sh[1023];
 }
 
-__global__ void __launch_bounds__(kBlock)
-k_scan_fill(int nbins, int* __restrict__ count, int* __restrict__ start, const int* __restrict__ bsum, int nb) {
+struct ScanFill {
+  struct Args {
+    int nbins, nb;
+    int *count, *start;
+    const int* bsum;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G);
+};
+__device__ void ScanFill::run(const Args& A, Grid G) {
+  const int nbins = A.nbins, nb = A.nb;
+  int* __restrict__ count = A.count;
+  int* __restrict__ start = A.start;
+  const int* __restrict__ bsum = A.bsum;
   __shared__ int sh[kBlock];
-  const int base = blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
+  const int base = G.b * kScanChunk + threadIdx.x * kScanPer;
   int v[kScanPer];
   int s = 0;
   for (int q = 0; q < kScanPer; q++) {
@@ -144,31 +214,48 @@ k_scan_fill(int nbins, int* __restrict__ count, int* __restrict__ start, const i
     sh[threadIdx.x] += u;
     __syncthreads();
   }
-  int run = bsum[blockIdx.x] + sh[threadIdx.x] - s;
+  int acc = bsum[G.b] + sh[threadIdx.x] - s;
   for (int q = 0; q < kScanPer; q++) {
     if (base + q < nbins) {
-      start[base + q] = run;
+      start[base + q] = acc;
       count[base + q] = 0;
     }
-    run += v[q];
+    acc += v[q];
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) start[nbins] = bsum[nb];
+  if (G.b == 0 && threadIdx.x == 0) start[nbins] = bsum[nb];
 }
 
-__global__ void __launch_bounds__(kBlock)
-k_scatter(int n_atoms, const int* __restrict__ key, const int* __restrict__ slot,
-          const int* __restrict__ start, int* __restrict__ perm_raw) {
-  int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= n_atoms) return;
-  perm_raw[start[key[a]] + slot[a]] = a;
-}
+struct Scatter {
+  struct Args {
+    int n_atoms;
+    const int *key, *slot, *start;
+    int* perm_raw;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G) {
+    int a = G.b * kBlock + threadIdx.x;
+    if (a >= A.n_atoms) return;
+    A.perm_raw[A.start[A.key[a]] + A.slot[a]] = a;
+  }
+};
 
 // One wave per bin: rank of each entry = number of smaller atom indices in
 // the bin (indices are distinct), so perm[start + rank] is the sorted list.
-__global__ void __launch_bounds__(kBlock)
-k_sort_bins(int nbins, const int* __restrict__ start, const int* __restrict__ perm_raw,
-            int* __restrict__ perm) {
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+struct SortBins {
+  struct Args {
+    int nbins;
+    const int *start, *perm_raw;
+    int* perm;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G);
+};
+__device__ void SortBins::run(const Args& A, Grid G) {
+  const int nbins = A.nbins;
+  const int* __restrict__ start = A.start;
+  const int* __restrict__ perm_raw = A.perm_raw;
+  int* __restrict__ perm = A.perm;
+  const int wave = (G.b * kBlock + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (wave >= nbins) return;
   const int s0 = start[wave], cnt = start[wave + 1] - s0;
@@ -196,13 +283,29 @@ k_sort_bins(int nbins, const int* __restrict__ start, const int* __restrict__ pe
 // sorted bins; the four wave copies are then summed in a fixed order.  No
 // global atomics, bitwise-reproducible.
 template <typename T, int TS>
-__global__ void __launch_bounds__(kBlock)
-k_spread(int n, int p, int ntx, const int* __restrict__ start, const int* __restrict__ perm,
-         const int* __restrict__ base, const T* __restrict__ w, const double* __restrict__ qa,
-         T* __restrict__ q) {
+struct Spread {
+  struct Args {
+    int n, p, ntx;
+    const int *start, *perm, *base;
+    const T* w;
+    const double* qa;
+    T* q;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G);
+};
+template <typename T, int TS>
+__device__ void Spread<T, TS>::run(const Args& A, Grid G) {
+  const int n = A.n, p = A.p, ntx = A.ntx;
+  const int* __restrict__ start = A.start;
+  const int* __restrict__ perm = A.perm;
+  const int* __restrict__ base = A.base;
+  const T* __restrict__ w = A.w;
+  const double* __restrict__ qa = A.qa;
+  T* __restrict__ q = A.q;
   constexpr int V = TS * TS * TS;
   __shared__ T acc[kBlock / 64][V];
-  const int t = blockIdx.x;
+  const int t = G.b;
   const int tx = t % ntx, ty = (t / ntx) % ntx, tz = t / (ntx * ntx);
   const int ox = tx * TS, oy = ty * TS, oz = tz * TS;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -251,16 +354,37 @@ k_spread(int n, int p, int ntx, const int* __restrict__ start, const int* __rest
 // per-atom energy 1/2 k Q (W * phi)(r).  Row sums in precision T (the
 // weights are rounded to T), accumulation over rows in FP64.
 template <typename T, typename TP>
-__global__ void __launch_bounds__(kBlock)
-k_gather(int n_atoms, int n, int p, double h, double k_e, const int* __restrict__ perm,
-         const int* __restrict__ base, const double* __restrict__ w, const double* __restrict__ qa,
-         const TP* __restrict__ phi0, const TP* __restrict__ phi1, double* __restrict__ force,
-         double* __restrict__ partial, const Ctl* ctl) {
+struct Gather {
+  struct Args {
+    int n_atoms, n, p;
+    double h, k_e;
+    const int *perm, *base;
+    const double *w, *qa;
+    const TP *phi0, *phi1;
+    double *force, *partial;
+    const Ctl* ctl;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G);
+};
+template <typename T, typename TP>
+__device__ void Gather<T, TP>::run(const Args& A, Grid G) {
+  const int n_atoms = A.n_atoms, n = A.n, p = A.p;
+  const double h = A.h, k_e = A.k_e;
+  const int* __restrict__ perm = A.perm;
+  const int* __restrict__ base = A.base;
+  const double* __restrict__ w = A.w;
+  const double* __restrict__ qa = A.qa;
+  const TP* __restrict__ phi0 = A.phi0;
+  const TP* __restrict__ phi1 = A.phi1;
+  double* __restrict__ force = A.force;
+  double* __restrict__ partial = A.partial;
+  const Ctl* ctl = A.ctl;
   __shared__ double sh[kBlock / 64];
   // the new potential: written over phi^k on a cold solve, over phi^{k-1} otherwise
   const TP* phi = (ctl->cold ? ctl->k_idx : 1 - ctl->k_idx) ? phi1 : phi0;
   double e_atom = 0.0;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n_atoms; t += gridDim.x * blockDim.x) {
+  for (int t = G.b * kBlock + threadIdx.x; t < n_atoms; t += G.g * kBlock) {
     const int a = perm[t];
     const int pe = p + 2;
     T wx[P3MZ_MAX_ORDER + 2], wy[P3MZ_MAX_ORDER + 2], wz[P3MZ_MAX_ORDER + 2];
@@ -310,21 +434,42 @@ k_gather(int n_atoms, int n, int p, double h, double k_e, const int* __restrict_
     e_atom += 0.5 * kq * pot;
   }
   double bs = block_sum(e_atom, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = bs;
+  if (threadIdx.x == 0) partial[G.b] = bs;
 }
 
 // One workgroup: *dst = sum of the nb partials (fixed order).
-__global__ void __launch_bounds__(kBlock) k_fin_sum(int nb, const double* __restrict__ partial, double* dst) {
-  __shared__ double sh[kBlock / 64];
-  const double tot = reduce_partials_sum(partial, nb, sh);
-  if (threadIdx.x == 0) *dst = tot;
-}
+struct FinSum {
+  struct Args {
+    int nb;
+    const double* partial;
+    double* dst;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid) {
+    __shared__ double sh[kBlock / 64];
+    const double tot = reduce_partials_sum(A.partial, A.nb, sh);
+    if (threadIdx.x == 0) *A.dst = tot;
+  }
+};
 
 // One workgroup: E_sr and the energy assembly {E_sr, E_lr, E_self, E_total}.
-__global__ void __launch_bounds__(kBlock)
-k_fin_energy(int nb, const double* __restrict__ partial, Ctl* ctl, double e_self, double* energy_out) {
+struct FinEnergy {
+  struct Args {
+    int nb;
+    double e_self;
+    const double* partial;
+    Ctl* ctl;
+    double* energy_out;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid);
+};
+__device__ void FinEnergy::run(const Args& A, Grid) {
+  Ctl* ctl = A.ctl;
+  const double e_self = A.e_self;
+  double* energy_out = A.energy_out;
   __shared__ double sh[kBlock / 64];
-  const double tot = reduce_partials_sum(partial, nb, sh);
+  const double tot = reduce_partials_sum(A.partial, A.nb, sh);
   if (threadIdx.x == 0) {
     ctl->e_sr = tot;
     if (energy_out) {
@@ -341,15 +486,31 @@ k_fin_energy(int nb, const double* __restrict__ partial, Ctl* ctl, double e_self
 // exclusion correction -k Q Q erf(alpha r)/r.  One wave per atom: lanes take
 // fixed strides of each neighbour cell's list, then a fixed shuffle tree
 // adds the lane sums (deterministic).  force += F_sr.
-__global__ void __launch_bounds__(kBlock)
-k_sr(int n_atoms, const double* __restrict__ pos, const double* __restrict__ qa, double box,
-     double alpha, double rc2, double k_e, int nc, int excl_group, const int* __restrict__ cstart,
-     const int* __restrict__ cperm, double* __restrict__ force, double* __restrict__ partial) {
+struct ShortRange {
+  struct Args {
+    int n_atoms, nc, excl_group;
+    double box, alpha, rc2, k_e;
+    const double *pos, *qa;
+    const int *cstart, *cperm;
+    double *force, *partial;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G);
+};
+__device__ void ShortRange::run(const Args& A, Grid G) {
+  const int n_atoms = A.n_atoms, nc = A.nc, excl_group = A.excl_group;
+  const double box = A.box, alpha = A.alpha, rc2 = A.rc2, k_e = A.k_e;
+  const double* __restrict__ pos = A.pos;
+  const double* __restrict__ qa = A.qa;
+  const int* __restrict__ cstart = A.cstart;
+  const int* __restrict__ cperm = A.cperm;
+  double* __restrict__ force = A.force;
+  double* __restrict__ partial = A.partial;
   __shared__ double sh[kBlock / 64];
   const int lane = threadIdx.x & 63;
-  const int nwaves = gridDim.x * (kBlock / 64);
+  const int nwaves = G.g * (kBlock / 64);
   double en = 0.0;
-  for (int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; wave < n_atoms; wave += nwaves) {
+  for (int wave = (G.b * kBlock + threadIdx.x) >> 6; wave < n_atoms; wave += nwaves) {
     double fx = 0.0, fy = 0.0, fz = 0.0;
     const int i = cperm[wave];
     const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
@@ -424,7 +585,7 @@ k_sr(int n_atoms, const double* __restrict__ pos, const double* __restrict__ qa,
   if (threadIdx.x == 0) {
     double s = 0.0;
     for (int k = 0; k < kBlock / 64; k++) s += sh[k];
-    partial[blockIdx.x] = s;
+    partial[G.b] = s;
   }
 }
 
@@ -435,44 +596,38 @@ inline int blocks_for(int64_t n, int b) { return (int)((n + b - 1) / b); }
 hipError_t launch_bin_stencil(bool fp64, int n_atoms, const double* pos, double box, int n, int p,
                               int tile, int ntx, int* base, void* w, int* key, int* slot, int* count,
                               Ctl* ctl, hipStream_t s) {
+  const int nb = blocks_for(n_atoms, kBlock);
   if (fp64)
-    hipLaunchKernelGGL(k_bin_stencil<double>, dim3(blocks_for(n_atoms, kBlock)), dim3(kBlock), 0, s,
-                       n_atoms, pos, box, n, p, tile, ntx, base, (double*)w, key, slot, count, ctl);
-  else
-    hipLaunchKernelGGL(k_bin_stencil<float>, dim3(blocks_for(n_atoms, kBlock)), dim3(kBlock), 0, s,
-                       n_atoms, pos, box, n, p, tile, ntx, base, (float*)w, key, slot, count, ctl);
-  return hipGetLastError();
+    return go<BinStencil<double>>({n_atoms, n, p, tile, ntx, box, pos, base, key, slot, count, (double*)w, ctl}, nb,
+                                  0, s);
+  return go<BinStencil<float>>({n_atoms, n, p, tile, ntx, box, pos, base, key, slot, count, (float*)w, ctl}, nb, 0,
+                               s);
 }
 
 hipError_t launch_bin_cells(int n_atoms, const double* pos, double box, int nc, int* key, int* slot,
                             int* count, Ctl* ctl, hipStream_t s) {
-  hipLaunchKernelGGL(k_bin_cells, dim3(blocks_for(n_atoms, kBlock)), dim3(kBlock), 0, s, n_atoms, pos,
-                     box, nc, key, slot, count, ctl);
-  return hipGetLastError();
+  return go<BinCells>({n_atoms, nc, box, pos, key, slot, count, ctl}, blocks_for(n_atoms, kBlock), 0, s);
 }
 
 int scan_partials(int nbins) { return (nbins + kScanChunk - 1) / kScanChunk + 1; }
 
 hipError_t launch_scan(int nbins, int* count, int* start, int* bsum, hipStream_t s) {
   const int nb = (nbins + kScanChunk - 1) / kScanChunk;
-  hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(kBlock), 0, s, nbins, count, bsum);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, nb, bsum);
-  hipLaunchKernelGGL(k_scan_fill, dim3(nb), dim3(kBlock), 0, s, nbins, count, start, bsum, nb);
-  return hipGetLastError();
+  hipError_t e = go<ScanSums>({nbins, count, bsum}, nb, 0, s);
+  if (e != hipSuccess) return e;
+  e = go<ScanTop>({nb, bsum}, 1, 0, s);
+  if (e != hipSuccess) return e;
+  return go<ScanFill>({nbins, nb, count, start, bsum}, nb, 0, s);
 }
 
 hipError_t launch_scatter(int n_atoms, const int* key, const int* slot, const int* start, int* perm_raw,
                           hipStream_t s) {
-  hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n_atoms, kBlock)), dim3(kBlock), 0, s, n_atoms, key,
-                     slot, start, perm_raw);
-  return hipGetLastError();
+  return go<Scatter>({n_atoms, key, slot, start, perm_raw}, blocks_for(n_atoms, kBlock), 0, s);
 }
 
 hipError_t launch_sort_bins(int nbins, const int* start, const int* perm_raw, int* perm, Ctl*,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_sort_bins, dim3(blocks_for((int64_t)nbins * 64, kBlock)), dim3(kBlock), 0, s,
-                     nbins, start, perm_raw, perm);
-  return hipGetLastError();
+  return go<SortBins>({nbins, start, perm_raw, perm}, blocks_for((int64_t)nbins * 64, kBlock), 0, s);
 }
 
 hipError_t launch_spread(bool fp64, int n, int p, int tile, int ntx, const int* start, const int* perm,
@@ -480,12 +635,8 @@ hipError_t launch_spread(bool fp64, int n, int p, int tile, int ntx, const int* 
   const int ntiles = ntx * ntx * ntx;
   if (tile != 8) return hipErrorInvalidValue;
   if (fp64)
-    hipLaunchKernelGGL((k_spread<double, 8>), dim3(ntiles), dim3(kBlock), 0, s, n, p, ntx, start, perm,
-                       base, (const double*)w, qa, (double*)q);
-  else
-    hipLaunchKernelGGL((k_spread<float, 8>), dim3(ntiles), dim3(kBlock), 0, s, n, p, ntx, start, perm,
-                       base, (const float*)w, qa, (float*)q);
-  return hipGetLastError();
+    return go<Spread<double, 8>>({n, p, ntx, start, perm, base, (const double*)w, qa, (double*)q}, ntiles, 0, s);
+  return go<Spread<float, 8>>({n, p, ntx, start, perm, base, (const float*)w, qa, (float*)q}, ntiles, 0, s);
 }
 
 hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, double h, double k_e, const int* perm,
@@ -493,14 +644,15 @@ hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, double h, double 
                          const double* phi1, const float* phi32, double* force, double* partial, Ctl* ctl,
                          hipStream_t s) {
   const int nb = std::min(blocks_for(n_atoms, kBlock), kMaxRedBlocks);
+  hipError_t e;
   if (fp64)
-    hipLaunchKernelGGL((k_gather<double, double>), dim3(nb), dim3(kBlock), 0, s, n_atoms, n, p, h, k_e,
-                       perm, base, (const double*)w, qa, phi0, phi1, force, partial, ctl);
+    e = go<Gather<double, double>>({n_atoms, n, p, h, k_e, perm, base, (const double*)w, qa, phi0, phi1, force,
+                                    partial, ctl}, nb, 0, s);
   else
-    hipLaunchKernelGGL((k_gather<float, float>), dim3(nb), dim3(kBlock), 0, s, n_atoms, n, p, h, k_e,
-                       perm, base, (const double*)w, qa, phi32, phi32, force, partial, ctl);
-  hipLaunchKernelGGL(k_fin_sum, dim3(1), dim3(kBlock), 0, s, nb, partial, &ctl->e_lr);
-  return hipGetLastError();
+    e = go<Gather<float, float>>({n_atoms, n, p, h, k_e, perm, base, (const double*)w, qa, phi32, phi32, force,
+                                  partial, ctl}, nb, 0, s);
+  if (e != hipSuccess) return e;
+  return go<FinSum>({nb, partial, &ctl->e_lr}, 1, 0, s);
 }
 
 hipError_t launch_sr(int n_atoms, const double* pos, const double* qa, double box, double alpha,
@@ -508,8 +660,8 @@ hipError_t launch_sr(int n_atoms, const double* pos, const double* qa, double bo
                      const int* cperm, double* force, double e_self, double* energy_out,
                      double* partial, Ctl* ctl, hipStream_t s) {
   const int nb = std::min(blocks_for((int64_t)n_atoms * 64, kBlock), 2 * kMaxRedBlocks);
-  hipLaunchKernelGGL(k_sr, dim3(nb), dim3(kBlock), 0, s, n_atoms, pos, qa, box, alpha, r_cut * r_cut, k_e, nc,
-                     excl_group, cstart, cperm, force, partial);
-  hipLaunchKernelGGL(k_fin_energy, dim3(1), dim3(kBlock), 0, s, nb, partial, ctl, e_self, energy_out);
-  return hipGetLastError();
+  hipError_t e = go<ShortRange>({n_atoms, nc, excl_group, box, alpha, r_cut * r_cut, k_e, pos, qa, cstart, cperm,
+                                 force, partial}, nb, 0, s);
+  if (e != hipSuccess) return e;
+  return go<FinEnergy>({nb, e_self, partial, ctl, energy_out}, 1, 0, s);
 }

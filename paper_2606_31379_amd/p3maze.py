@@ -33,7 +33,9 @@ EXPORTS = ["p3mz_create", "p3mz_compute", "p3mz_get_mesh", "p3mz_vcycle", "p3mz_
            "p3mz_reset_history", "p3mz_save_state", "p3mz_load_state", "p3mz_md_run",
            "p3mz_set_graphs", "p3mz_set_timing", "p3mz_set_kernel_timer", "p3mz_get_kernel_timer",
            "p3mz_kernel_bench",
-           "p3mz_destroy", "p3mz_status_string", "p3mz_last_error", "p3mz_version"]
+           "p3mz_destroy", "p3mz_batch_create", "p3mz_batch_compute", "p3mz_batch_md_run",
+           "p3mz_batch_get_stats", "p3mz_batch_set_timing", "p3mz_batch_get_timing", "p3mz_batch_set_graphs",
+           "p3mz_batch_destroy", "p3mz_status_string", "p3mz_last_error", "p3mz_version"]
 KERNELS = {"halfsweep": 0, "outer": 1, "smooth": 2, "restrict": 3, "prolong": 4, "sweep0": 5,
            "tail": 6, "spread": 7, "gather": 8, "sr": 9, "sigma": 10, "phi": 11}
 
@@ -93,6 +95,15 @@ def _load() -> C.CDLL:
         "p3mz_set_kernel_timer": ([vp, C.c_int32], C.c_int),
         "p3mz_get_kernel_timer": ([vp, dp, C.POINTER(C.c_int64), dp], C.c_int),
         "p3mz_destroy": ([vp], None),
+        "p3mz_batch_create": ([C.c_int32, C.POINTER(p3mz_params), C.POINTER(C.c_int64), dp, C.POINTER(vp)], C.c_int),
+        "p3mz_batch_compute": ([vp, vp, vp, vp, vp], C.c_int),
+        "p3mz_batch_md_run": ([vp, vp, vp, vp, C.POINTER(p3mz_mdterms), C.c_double, C.c_int32, vp, vp, vp],
+                              C.c_int),
+        "p3mz_batch_get_stats": ([vp, C.c_int32, C.POINTER(p3mz_stats)], C.c_int),
+        "p3mz_batch_set_timing": ([vp, C.c_int32], C.c_int),
+        "p3mz_batch_get_timing": ([vp, dp, dp, C.POINTER(C.c_int32)], C.c_int),
+        "p3mz_batch_set_graphs": ([vp, C.c_int32], C.c_int),
+        "p3mz_batch_destroy": ([vp], None),
         "p3mz_status_string": ([C.c_int], C.c_char_p),
         "p3mz_last_error": ([], C.c_char_p),
         "p3mz_version": ([], C.c_char_p),
@@ -193,6 +204,54 @@ def p3mz_get_kernel_timer(ctx: int) -> tuple[float, int, float]:
 
 def p3mz_destroy(ctx: int) -> None:
     lib.p3mz_destroy(ctx)
+
+
+def p3mz_batch_create(per_sys, n_atoms, charges_packed_host) -> int:
+    """per_sys: sequence of p3mz_params; n_atoms: sequence of ints; charges: packed float64 numpy array."""
+    n = len(per_sys)
+    arr = (p3mz_params * n)(*per_sys)
+    na = (C.c_int64 * n)(*[int(x) for x in n_atoms])
+    h = C.c_void_p()
+    _check(lib.p3mz_batch_create(n, arr, na, charges_packed_host.ctypes.data_as(C.POINTER(C.c_double)), C.byref(h)),
+           "p3mz_batch_create")
+    return h.value
+
+
+def p3mz_batch_compute(b: int, pos_dev: int, force_dev: int | None, energies_dev: int | None,
+                       stream: int | None = None) -> int:
+    return _check(lib.p3mz_batch_compute(b, pos_dev, force_dev, energies_dev, stream), "p3mz_batch_compute")
+
+
+def p3mz_batch_md_run(b: int, pos_dev: int, vel_dev: int, mass_dev: int, terms: p3mz_mdterms, dt: float,
+                      n_steps: int, energy_log_dev: int | None, cycles_log_dev: int | None,
+                      stream: int | None = None) -> int:
+    return _check(lib.p3mz_batch_md_run(b, pos_dev, vel_dev, mass_dev, C.byref(terms), dt, n_steps, energy_log_dev,
+                                        cycles_log_dev, stream), "p3mz_batch_md_run")
+
+
+def p3mz_batch_get_stats(b: int, sys: int) -> p3mz_stats:
+    st = p3mz_stats()
+    _check(lib.p3mz_batch_get_stats(b, sys, C.byref(st)), "p3mz_batch_get_stats")
+    return st
+
+
+def p3mz_batch_set_timing(b: int, on: bool) -> int:
+    return _check(lib.p3mz_batch_set_timing(b, int(on)), "p3mz_batch_set_timing")
+
+
+def p3mz_batch_get_timing(b: int) -> tuple[float, float, int]:
+    """(mesh ms, short-range ms, ran from graphs) of the last batched step."""
+    a, c, g = C.c_double(), C.c_double(), C.c_int32()
+    _check(lib.p3mz_batch_get_timing(b, C.byref(a), C.byref(c), C.byref(g)), "p3mz_batch_get_timing")
+    return a.value, c.value, g.value
+
+
+def p3mz_batch_set_graphs(b: int, on: bool) -> int:
+    return _check(lib.p3mz_batch_set_graphs(b, int(on)), "p3mz_batch_set_graphs")
+
+
+def p3mz_batch_destroy(b: int) -> None:
+    lib.p3mz_batch_destroy(b)
 
 
 def p3mz_status_string(code: int) -> str:
