@@ -1,7 +1,7 @@
 #!/usr/bin/env python
 """Benchmark of the P3MaZe long-range mesh step on one MI355X.
 
-python bench.py [--steps K] [--warmup W] [--workload water-3000] [--gpus 1]
+python bench.py [--steps K] [--warmup W] [--workload water-3000|nacl-batch64|...] [--gpus 1]
 
 One "step" is one velocity-Verlet MD step that drives one mesh step (bin,
 spread, smoothing, warm-started multigrid constraint solve, field update,
@@ -234,6 +234,193 @@ def parity_and_baseline(torch, P, w, system, sample_steps):
     return out, baseline
 
 
+def batch_params(P, w, r, precision):
+    return P.make_params(r.box, w.alpha, w.r_cut, r.mesh, w.order, tol=w.tol, predictor=w.predictor,
+                         precision=precision, coulomb_k=14.3996454784, nu_pre=2, nu_post=2)
+
+
+def run_batch_mode(torch, P, w, systems, precision, warmup, steps):
+    """All replicas advanced together: each MD step is one batched step
+    (every kernel launched once for all replicas, captured in graphs)."""
+    import numpy as np
+    dev = torch.device("cuda")
+    n = [s.n for s in systems]
+    b = P.p3mz_batch_create([batch_params(P, w, r, precision) for r in w.replicas], n,
+                            np.ascontiguousarray(np.concatenate([s.charges for s in systems])))
+    try:
+        cat = lambda key: torch.from_numpy(np.ascontiguousarray(np.concatenate([getattr(s, key) for s in systems]))).to(dev)
+        pos, vel, mass = cat("pos"), cat("vel"), cat("masses")
+        terms = md_terms(P, "nacl")
+        stream = torch.cuda.current_stream().cuda_stream
+        clog = torch.zeros((len(n), 1), dtype=torch.int32, device=dev)
+
+        def step():
+            P.p3mz_batch_md_run(b, pos.data_ptr(), vel.data_ptr(), mass.data_ptr(), terms, w.dt_fs, 1, None,
+                                clog.data_ptr(), stream)
+
+        for _ in range(warmup):
+            step()
+        P.p3mz_batch_set_timing(b, True)
+        mesh_ms, sr_ms, graphs, cyc = 0.0, 0.0, 1, []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+            m, sr, g = P.p3mz_batch_get_timing(b)
+            mesh_ms += m
+            sr_ms += sr
+            graphs &= g
+            cyc.append(clog[:, 0].cpu().numpy().copy())
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        P.p3mz_batch_set_timing(b, False)
+        reps = 100
+        kms, kbytes = P.p3mz_batch_kernel_bench(b, P.KERNELS["halfsweep"], reps, stream)
+        cyc = np.array(cyc)
+        total = sum(n)
+        return dict(ns_per_atom=mesh_ms / steps * 1e6 / total, mesh_ms_per_step=mesh_ms / steps,
+                    md_ms_per_step=wall * 1e3 / steps, short_range_ms_per_step=sr_ms / steps, graphs=bool(graphs),
+                    vcycles_mean=float(cyc.mean()), vcycles_max_per_step=float(cyc.max(axis=1).mean()),
+                    dominant="halfsweep", dominant_avg_launch_us=kms * 1e3, dominant_launches=reps,
+                    dominant_bytes_per_launch=kbytes, dominant_gbps=kbytes / (kms * 1e-3) / 1e9)
+    finally:
+        P.p3mz_batch_destroy(b)
+
+
+def run_unbatched(torch, P, w, systems, precision, warmup, steps):
+    """The same replicas one context each, stepped one after another."""
+    import numpy as np
+    dev = torch.device("cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    terms = md_terms(P, "nacl")
+    ctxs, bufs = [], []
+    try:
+        for r, s in zip(w.replicas, systems):
+            ctxs.append(P.p3mz_create(batch_params(P, w, r, precision), s.charges))
+            P.p3mz_set_timing(ctxs[-1], True)
+            bufs.append([torch.from_numpy(np.ascontiguousarray(getattr(s, k))).to(dev) for k in ("pos", "vel", "masses")])
+        def step():
+            ms = 0.0
+            for h, (p_, v_, m_) in zip(ctxs, bufs):
+                P.p3mz_md_run(h, p_.data_ptr(), v_.data_ptr(), m_.data_ptr(), terms, w.dt_fs, 1, None, None, stream)
+                ms += P.p3mz_get_stats(h).ms_mesh
+            return ms
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mesh_ms = sum(step() for _ in range(steps))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        total = sum(s.n for s in systems)
+        return dict(ns_per_atom=mesh_ms / steps * 1e6 / total, mesh_ms_per_step=mesh_ms / steps,
+                    md_ms_per_step=wall * 1e3 / steps)
+    finally:
+        for h in ctxs:
+            P.p3mz_destroy(h)
+
+
+def batch_parity_and_baseline(torch, P, w, systems, sample_atoms=64):
+    """Every replica: cold step + one warm step along its velocities on the
+    oracle (pair term only for `sample_atoms` seeded atoms per replica, so the
+    all-pairs sum stays bounded) and through the batched GPU path; forces
+    compared on the sampled atoms, V-cycle counts on every replica.  The
+    oracle's warm mesh-step time over all replicas is the CPU baseline."""
+    import numpy as np
+    from oracle import oracle as O
+    rng = np.random.Generator(np.random.PCG64(77))
+    dev = torch.device("cuda")
+    n = [s.n for s in systems]
+    trajs = [[s.pos, s.pos + w.dt_fs * s.vel] for s in systems]
+    targets = [np.sort(rng.choice(s.n, size=min(sample_atoms, s.n), replace=False)) for s in systems]
+    ref, cyc_ref, t_mesh = [], [], 0.0
+    for r, s, tr, tg in zip(w.replicas, systems, trajs, targets):
+        o = O.Oracle(O.make_params(r.box, w.alpha, w.r_cut, r.mesh, w.order, tol=w.tol, predictor=w.predictor,
+                                   coulomb_k=14.3996454784, nu_pre=2, nu_post=2), s.charges)
+        o.set_sr_targets(tg)
+        fr, cr = [], []
+        for k, x in enumerate(tr):
+            f, _, _ = o.compute(x)
+            st = o.stats()
+            fr.append(f[tg])
+            cr.append(st.cycles)
+            if k == 1:
+                t_mesh += st.t_spread + st.t_solve + st.t_gather
+        o.close()
+        ref.append(fr)
+        cyc_ref.append(cr)
+    log(f"[oracle] {len(systems)} replicas, warm mesh step total {t_mesh:.3f} s")
+    out = {}
+    for precision, name in ((0, "fp64"), (1, "mixed")):
+        b = P.p3mz_batch_create([batch_params(P, w, r, precision) for r in w.replicas], n,
+                                np.ascontiguousarray(np.concatenate([s.charges for s in systems])))
+        try:
+            pos = torch.zeros((sum(n), 3), dtype=torch.float64, device=dev)
+            frc = torch.zeros_like(pos)
+            errs, equal = [], True
+            for k in range(2):
+                pos.copy_(torch.from_numpy(np.ascontiguousarray(np.concatenate([tr[k] for tr in trajs]))))
+                P.p3mz_batch_compute(b, pos.data_ptr(), frc.data_ptr(), None, torch.cuda.current_stream().cuda_stream)
+                torch.cuda.synchronize()
+                fg = frc.cpu().numpy()
+                off = 0
+                for i, s in enumerate(systems):
+                    a, rf = fg[off:off + s.n][targets[i]], ref[i][k]
+                    errs.append(float(np.sqrt(((a - rf) ** 2).sum() / (rf ** 2).sum())))
+                    equal &= P.p3mz_batch_get_stats(b, i).cycles == cyc_ref[i][k]
+                    off += s.n
+            out[name] = dict(max_rel_rms_force_err=max(errs), vcycles_equal=bool(equal),
+                             sampled_atoms_per_replica=sample_atoms)
+        finally:
+            P.p3mz_batch_destroy(b)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    baseline = dict(value=t_mesh * 1e9 / sum(n), unit="ns/atom/step", cores=cores, kind="oracle",
+                    sample=f"one warm mesh step (after the cold solve) of each of the {len(systems)} replicas, "
+                           f"one after another; spread+smoothing+solve+gather only")
+    return out, baseline
+
+
+def main_batch(args, torch, P, w):
+    import numpy as np
+    log(f"workload {w.name}: generating {len(w.replicas)} replicas")
+    systems = w.systems()
+    log(f"atoms {sum(s.n for s in systems)}; meshes " +
+        ", ".join(f"{m}^3 x{sum(r.mesh == m for r in w.replicas)}" for m in sorted({r.mesh for r in w.replicas})))
+    ceiling = copy_ceiling_gbps(torch)
+    res = {}
+    for precision, name in ((0, "fp64"), (1, "mixed")):
+        if name not in args.modes.split(","):
+            continue
+        res[name] = run_batch_mode(torch, P, w, systems, precision, args.warmup, args.steps)
+        log(f"[batch {name}] {json.dumps(res[name])}")
+    unb = run_unbatched(torch, P, w, systems, 1, 2, max(3, min(args.steps, 10)))
+    log(f"[unbatched mixed] {json.dumps(unb)}")
+    parity, baseline = None, None
+    if not args.no_cpu_baseline:
+        parity, baseline = batch_parity_and_baseline(torch, P, w, systems)
+    m, f = res.get("mixed"), res.get("fp64")
+    head = m if m is not None else f
+    roof = dict(bound="hbm", kernel="halfsweep (one batched launch over every replica's finest level)",
+                achieved=head["dominant_gbps"], peak=HBM_PEAK_GBPS, unit="GB/s",
+                frac=head["dominant_gbps"] / HBM_PEAK_GBPS, traffic=None,
+                traffic_source="no counter summary for the batched launch",
+                avg_launch_us=head["dominant_avg_launch_us"], alg_bytes_per_launch=head["dominant_bytes_per_launch"],
+                launches=head["dominant_launches"], copy_ceiling_GBps=ceiling)
+    line = dict(
+        metric=METRIC, value=head["ns_per_atom"], unit="ns/atom/step", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=head["md_ms_per_step"], higher_is_better=False, scaling="weak",
+        vs_baseline=None, dtype="f32+f64" if m is not None else "f64", data="synthetic",
+        config=dict(workload=w.name, n_systems=len(systems), n_atoms=sum(s.n for s in systems), order=w.order,
+                    alpha=w.alpha, r_cut=w.r_cut, tol=w.tol, predictor=w.predictor, dt_fs=w.dt_fs,
+                    meshes=sorted({r.mesh for r in w.replicas}), precision="mixed" if m is not None else "fp64"),
+        mixed=m, fp64=f, unbatched_mixed=unb,
+        speedup_mixed_vs_fp64=(f["mesh_ms_per_step"] / m["mesh_ms_per_step"]) if (m and f) else None,
+        speedup_batched_vs_unbatched=unb["mesh_ms_per_step"] / head["mesh_ms_per_step"],
+        roofline=roof, cpu_baseline=baseline, parity=parity,
+    )
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -258,6 +445,8 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.workload == "nacl-batch64":
+        return main_batch(args, torch, P, configs.nacl_batch_64())
     w = configs.WORKLOADS[args.workload]()
     log(f"workload {w.name}: generating inputs")
     system = w.system()

@@ -271,6 +271,12 @@ p3mz_status p3mz_batch_set_timing(p3mz_batch* b, int32_t on);
 p3mz_status p3mz_batch_get_timing(const p3mz_batch* b, double* ms_mesh, double* ms_short_range, int32_t* graphs);
 /* Captured graphs (default) or direct launches; results are identical. */
 p3mz_status p3mz_batch_set_graphs(p3mz_batch* b, int32_t on);
+/* As p3mz_kernel_bench, for one batched launch of a V-cycle kernel family
+ * (HALFSWEEP, SWEEP0, RESTRICT, PROLONG, TAIL) over every system's finest
+ * level; *bytes_per_launch sums the systems' algorithmic bytes.  Leaves each
+ * system's control block open (the next step resets it). */
+p3mz_status p3mz_batch_kernel_bench(p3mz_batch* b, int32_t kernel_id, int32_t reps, void* stream, double* avg_ms,
+                                    double* bytes_per_launch);
 void p3mz_batch_destroy(p3mz_batch* b);
 const char* p3mz_status_string(p3mz_status s);
 const char* p3mz_last_error(void);

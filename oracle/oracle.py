@@ -129,6 +129,7 @@ def lib() -> C.CDLL:
         L.orc_destroy.restype = None
         L.orc_compute.argtypes = [C.c_void_p, dp, dp, dp]
         L.orc_get_stats.argtypes = [C.c_void_p, C.POINTER(Stats)]
+        L.orc_set_sr_targets.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.c_int64]
         L.orc_get_plan.argtypes = [C.c_void_p, C.POINTER(Plan)]
         L.orc_get_mesh.argtypes = [C.c_void_p, C.c_int, dp]
         L.orc_reset_history.argtypes = [C.c_void_p]
@@ -301,6 +302,17 @@ class Oracle:
         if rc < 0:
             raise OracleError(rc)
         return f, e, rc
+
+    def set_sr_targets(self, targets):
+        """Pair term only for these atom indices (None: all atoms; empty: none)."""
+        if targets is None:
+            rc = lib().orc_set_sr_targets(self._h, None, -1)
+        else:
+            self._targets = np.ascontiguousarray(targets, dtype=np.int64)
+            rc = lib().orc_set_sr_targets(self._h, self._targets.ctypes.data_as(C.POINTER(C.c_int64)),
+                                          self._targets.size)
+        if rc:
+            raise OracleError(rc)
 
     def stats(self) -> Stats:
         s = Stats()

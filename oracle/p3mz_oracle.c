@@ -67,6 +67,11 @@ struct orc_state {
   /* history: phi^k, phi^{k-1}, stored warm multipliers (newest first) */
   double *phi_k, *phi_km1, *yh[3];
   int n_yh, have_hist;
+  /* short-range subset: when sr_subset is set, pairs are summed only for
+   * the atoms listed in sr_targets (all partners), see orc_set_sr_targets */
+  int sr_subset;
+  int64_t n_sr_targets;
+  int64_t* sr_targets;
   /* per-level multigrid work arrays */
   double *rho[ORC_MAX_LEVELS], *rl[ORC_MAX_LEVELS], *el[ORC_MAX_LEVELS];
   orc_stats st;
@@ -482,7 +487,25 @@ void orc_destroy(orc_state* s) {
   free(s->r); free(s->e); free(s->phi_p); free(s->phi_k); free(s->phi_km1);
   for (int t = 0; t < 3; t++) free(s->yh[t]);
   for (int l = 0; l < ORC_MAX_LEVELS; l++) { free(s->rho[l]); free(s->rl[l]); free(s->el[l]); }
+  free(s->sr_targets);
   free(s);
+}
+
+int orc_set_sr_targets(orc_state* s, const int64_t* targets, int64_t n_targets) {
+  if (!s || n_targets < -1 || (n_targets > 0 && !targets)) return ORC_ERR_INVALID_ARG;
+  for (int64_t t = 0; t < n_targets; t++)
+    if (targets[t] < 0 || targets[t] >= s->n) return ORC_ERR_INVALID_ARG;
+  free(s->sr_targets);
+  s->sr_targets = NULL;
+  s->n_sr_targets = 0;
+  s->sr_subset = n_targets >= 0;
+  if (n_targets > 0) {
+    s->sr_targets = (int64_t*)malloc(sizeof(int64_t) * (size_t)n_targets);
+    if (!s->sr_targets) return ORC_ERR_OUT_OF_MEMORY;
+    memcpy(s->sr_targets, targets, sizeof(int64_t) * (size_t)n_targets);
+    s->n_sr_targets = n_targets;
+  }
+  return ORC_OK;
 }
 
 int orc_create(const orc_params* p, int64_t n_atoms, const double* charges, orc_state** out) {
@@ -647,13 +670,25 @@ int orc_compute(orc_state* s, const double* pos, double* force, double* energy4)
   /* short-range pairs (Eqs. 6, 20) and the Gaussian self term (Eq. 7) */
   double* f_sr = (double*)malloc(sizeof(double) * 3 * (size_t)s->n);
   if (!f_sr) { free(e_at); return ORC_ERR_OUT_OF_MEMORY; }
-  orc_sr(s->n, pos, s->Q, P->box, P->alpha, P->r_cut, P->coulomb_k, P->excl_group, NULL, 0,
-         f_sr, e_at);
   double e_sr = 0.0, e_self = 0.0;
-  for (int64_t a = 0; a < s->n; a++) {
-    e_sr += e_at[a];
-    e_self -= P->coulomb_k * P->alpha / sqrt(M_PI) * s->Q[a] * s->Q[a];
+  if (s->sr_subset) {
+    memset(f_sr, 0, sizeof(double) * 3 * (size_t)s->n);
+    if (s->n_sr_targets > 0) {
+      const int64_t nt = s->n_sr_targets;
+      double* ft = (double*)malloc(sizeof(double) * 3 * (size_t)nt);
+      if (!ft) { free(f_sr); free(e_at); return ORC_ERR_OUT_OF_MEMORY; }
+      orc_sr(s->n, pos, s->Q, P->box, P->alpha, P->r_cut, P->coulomb_k, P->excl_group, s->sr_targets, nt, ft,
+             NULL);
+      for (int64_t t = 0; t < nt; t++)
+        for (int d = 0; d < 3; d++) f_sr[3 * s->sr_targets[t] + d] = ft[3 * t + d];
+      free(ft);
+    }
+    e_sr = NAN;   /* only a subset of the pair sum was formed */
+  } else {
+    orc_sr(s->n, pos, s->Q, P->box, P->alpha, P->r_cut, P->coulomb_k, P->excl_group, NULL, 0, f_sr, e_at);
+    for (int64_t a = 0; a < s->n; a++) e_sr += e_at[a];
   }
+  for (int64_t a = 0; a < s->n; a++) e_self -= P->coulomb_k * P->alpha / sqrt(M_PI) * s->Q[a] * s->Q[a];
   if (force)
     for (size_t t = 0; t < 3 * (size_t)s->n; t++) force[t] += f_sr[t];
   free(f_sr);

@@ -116,6 +116,11 @@ int    orc_ewald(int64_t n_atoms, const double* pos, const double* q, double box
 int  orc_create(const orc_params* p, int64_t n_atoms, const double* charges, orc_state** out);
 void orc_destroy(orc_state* s);
 int  orc_compute(orc_state* s, const double* pos, double* force, double* energy4);
+/* Short-range subset for large systems: with n_targets >= 0 the pair term
+ * is formed only for the listed atoms (against all partners); the other
+ * atoms' forces are long-range only and e_sr / e_total become NaN.
+ * n_targets = 0 skips the pair term; n_targets = -1 restores the full sum. */
+int  orc_set_sr_targets(orc_state* s, const int64_t* targets, int64_t n_targets);
 int  orc_get_stats(const orc_state* s, orc_stats* out);
 int  orc_get_plan(const orc_state* s, orc_plan* out);
 int  orc_get_mesh(const orc_state* s, int which, double* out);

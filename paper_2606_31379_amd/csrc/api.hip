@@ -333,8 +333,8 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
     P3MZ_TRY(c->allocb(&b.r0, half * c->tsz));
     P3MZ_TRY(c->allocb(&b.r1, half * c->tsz));
   }
-  const size_t max_blocks = (std::max<size_t>(n3, (size_t)na) + 255) / 256 + 1;
-  P3MZ_TRY(c->alloc(&c->d_partial, 2 * max_blocks));
+  // every reduction grid is capped, so one fixed-size partial buffer fits all
+  P3MZ_TRY(c->alloc(&c->d_partial, kPartialSlots));
   P3MZ_TRY(c->alloc(&c->d_ctl, 1));
   P3MZ_HIP_TRY(hipHostMalloc((void**)&c->h_ctl, sizeof(Ctl), hipHostMallocDefault));
   memset(&c->mirror, 0, sizeof(Ctl));
@@ -1479,6 +1479,47 @@ p3mz_status p3mz_batch_get_timing(const p3mz_batch* b, double* ms_mesh, double* 
   *ms_mesh = b->ms_mesh;
   *ms_short_range = b->ms_sr;
   *graphs = b->ran_graphs;
+  return P3MZ_OK;
+}
+
+p3mz_status p3mz_batch_kernel_bench(p3mz_batch* b, int32_t kernel_id, int32_t reps, void* stream, double* avg_ms,
+                                    double* bytes_per_launch) {
+  if (!b || !avg_ms || !bytes_per_launch || reps < 1) return fail(P3MZ_ERR_INVALID_ARG, "bad kernel_bench arguments");
+  if (kernel_id != KT_HALFSWEEP && kernel_id != KT_SWEEP0 && kernel_id != KT_RESTRICT && kernel_id != KT_PROLONG &&
+      kernel_id != KT_TAIL)
+    return fail(P3MZ_ERR_INVALID_ARG, "kernel family not available for batched timing");
+  hipStream_t s = (hipStream_t)stream;
+  // one batched launch of the family on every system's finest level
+  BatchSet tmp;
+  std::vector<unsigned char> args;
+  double bytes = 0.0;
+  P3MZ_TRY(batch_record(b, &tmp, 0, &args, [&](int r) -> p3mz_status {
+    p3mz_ctx* c = b->sys[r];
+    double by = 0.0;
+    rec_key(1);
+    hipError_t e = launch_vcycle_kernel(c->fp64, kernel_id, c->lv, c->pl.levels, c->pl.tail, c->nu1, c->nu2,
+                                        c->d_green, c->d_ctl, nullptr, &by);
+    if (e != hipSuccess) return fail(P3MZ_ERR_INVALID_ARG, "kernel not available on every system's mesh");
+    bytes += by;
+    return P3MZ_OK;
+  }));
+  P3MZ_TRY(batch_upload(&tmp, args));
+  for (p3mz_ctx* c : b->sys) P3MZ_HIP_TRY(launch_set_ctl_open(c->d_ctl, s));
+  hipEvent_t e0, e1;
+  P3MZ_HIP_TRY(hipEventCreate(&e0));
+  P3MZ_HIP_TRY(hipEventCreate(&e1));
+  P3MZ_HIP_TRY(hipEventRecord(e0, s));
+  for (int r = 0; r < reps; r++)
+    for (const BatchLaunch& L : tmp.q[0]) P3MZ_HIP_TRY(L.many((const char*)tmp.d_args + L.off, L.count, L.gx, L.lds, s));
+  P3MZ_HIP_TRY(hipEventRecord(e1, s));
+  P3MZ_HIP_TRY(hipEventSynchronize(e1));
+  float ms = 0.f;
+  P3MZ_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  P3MZ_HIP_TRY(hipFree(tmp.d_args));
+  *avg_ms = ms / reps;
+  *bytes_per_launch = bytes;
   return P3MZ_OK;
 }
 

@@ -106,6 +106,12 @@ __device__ __forceinline__ int xcd_block() {
 // one contiguous chunk of the index space, a multiple of the block size.
 constexpr int kRedBlock = 256;
 constexpr int kMaxRedBlocks = 2048;
+// Capacity (doubles) of a context's partial-sum buffer.  Every reduction
+// launch writes at most this many partials: two per workgroup on grids of
+// at most kMaxRedBlocks (sigma, outer residual), one per workgroup on grids
+// of at most kPartialSlots (pair kernels, wave per atom) or kMaxRedBlocks
+// (gather, kinetic energy).
+constexpr int kPartialSlots = 2 * kMaxRedBlocks;
 inline int red_blocks(int64_t count) {
   int64_t b = (count + kRedBlock - 1) / kRedBlock;
   if (b > kMaxRedBlocks) b = kMaxRedBlocks;

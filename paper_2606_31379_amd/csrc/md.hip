@@ -250,7 +250,7 @@ hipError_t launch_kick_drift(int n_atoms, double* pos, double* vel, const double
 hipError_t launch_nonelec(int n_atoms, const double* pos, double box, double r_cut, int model, double p0,
                           double p1, double p2, double p3, double p4, double p5, int nc, const int* cstart,
                           const int* cperm, double* force, double* partial, double* e_out, hipStream_t s) {
-  const int nb = std::min(blocks_for((int64_t)n_atoms * 64, kBlock), 2 * kMaxRedBlocks);
+  const int nb = std::min(blocks_for((int64_t)n_atoms * 64, kBlock), kPartialSlots);
   hipError_t e = go<NonElec>({n_atoms, model, nc, box, r_cut * r_cut, p0, p1, p2, p3, p4, p5, pos, cstart, cperm,
                               force, partial}, nb, 0, s);
   if (e != hipSuccess) return e;

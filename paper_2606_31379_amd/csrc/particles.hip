@@ -659,7 +659,7 @@ hipError_t launch_sr(int n_atoms, const double* pos, const double* qa, double bo
                      double r_cut, double k_e, int nc, int excl_group, const int* cstart,
                      const int* cperm, double* force, double e_self, double* energy_out,
                      double* partial, Ctl* ctl, hipStream_t s) {
-  const int nb = std::min(blocks_for((int64_t)n_atoms * 64, kBlock), 2 * kMaxRedBlocks);
+  const int nb = std::min(blocks_for((int64_t)n_atoms * 64, kBlock), kPartialSlots);
   hipError_t e = go<ShortRange>({n_atoms, nc, excl_group, box, alpha, r_cut * r_cut, k_e, pos, qa, cstart, cperm,
                                  force, partial}, nb, 0, s);
   if (e != hipSuccess) return e;

@@ -35,7 +35,7 @@ EXPORTS = ["p3mz_create", "p3mz_compute", "p3mz_get_mesh", "p3mz_vcycle", "p3mz_
            "p3mz_kernel_bench",
            "p3mz_destroy", "p3mz_batch_create", "p3mz_batch_compute", "p3mz_batch_md_run",
            "p3mz_batch_get_stats", "p3mz_batch_set_timing", "p3mz_batch_get_timing", "p3mz_batch_set_graphs",
-           "p3mz_batch_destroy", "p3mz_status_string", "p3mz_last_error", "p3mz_version"]
+           "p3mz_batch_kernel_bench", "p3mz_batch_destroy", "p3mz_status_string", "p3mz_last_error", "p3mz_version"]
 KERNELS = {"halfsweep": 0, "outer": 1, "smooth": 2, "restrict": 3, "prolong": 4, "sweep0": 5,
            "tail": 6, "spread": 7, "gather": 8, "sr": 9, "sigma": 10, "phi": 11}
 
@@ -103,6 +103,7 @@ def _load() -> C.CDLL:
         "p3mz_batch_set_timing": ([vp, C.c_int32], C.c_int),
         "p3mz_batch_get_timing": ([vp, dp, dp, C.POINTER(C.c_int32)], C.c_int),
         "p3mz_batch_set_graphs": ([vp, C.c_int32], C.c_int),
+        "p3mz_batch_kernel_bench": ([vp, C.c_int32, C.c_int32, vp, dp, dp], C.c_int),
         "p3mz_batch_destroy": ([vp], None),
         "p3mz_status_string": ([C.c_int], C.c_char_p),
         "p3mz_last_error": ([], C.c_char_p),
@@ -248,6 +249,14 @@ def p3mz_batch_get_timing(b: int) -> tuple[float, float, int]:
 
 def p3mz_batch_set_graphs(b: int, on: bool) -> int:
     return _check(lib.p3mz_batch_set_graphs(b, int(on)), "p3mz_batch_set_graphs")
+
+
+def p3mz_batch_kernel_bench(b: int, kernel_id: int, reps: int, stream: int | None = None) -> tuple[float, float]:
+    """(mean batched launch milliseconds, algorithmic bytes per launch over all systems)."""
+    ms, by = C.c_double(), C.c_double()
+    _check(lib.p3mz_batch_kernel_bench(b, kernel_id, reps, stream, C.byref(ms), C.byref(by)),
+           "p3mz_batch_kernel_bench")
+    return ms.value, by.value
 
 
 def p3mz_batch_destroy(b: int) -> None:

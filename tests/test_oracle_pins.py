@@ -509,3 +509,27 @@ def test_nve_energy_is_conserved():
     assert drift < 0.02 * ekin.mean(), (drift, ekin.mean())
     assert np.std(etot) < 0.02 * ekin.mean()
     assert clog.max() <= 10
+
+
+def test_sr_subset_matches_full_sum():
+    """The short-range subset (used for systems too large for the all-pairs
+    sum) gives each listed atom exactly its full-sum force; unlisted atoms
+    keep the long-range force only."""
+    s = inputs.random_neutral(60, 14.0, seed=7, dmin=1.0)
+    p = O.make_params(14.0, 0.45, 6.0, 16, 4, tol=1e-10)
+    a = O.Oracle(p, s.charges)
+    b = O.Oracle(p, s.charges)
+    fa, ea, _ = a.compute(s.pos)
+    targets = np.array([0, 7, 31, 59])
+    b.set_sr_targets(targets)
+    fb, eb, _ = b.compute(s.pos)
+    assert np.array_equal(fa[targets], fb[targets])
+    c = O.Oracle(p, s.charges)
+    c.set_sr_targets([])
+    fc, ec, _ = c.compute(s.pos)
+    others = np.setdiff1d(np.arange(60), targets)
+    assert np.array_equal(fb[others], fc[others])
+    assert np.isnan(eb[0]) and np.isnan(ec[0]) and ea[1] == eb[1] == ec[1]
+    b.set_sr_targets(None)
+    fd, ed, _ = b.compute(s.pos)
+    assert np.isfinite(ed[0])
