@@ -223,6 +223,40 @@ p3mz_status p3mz_get_kernel_timer(const p3mz_ctx* ctx, double* total_ms, int64_t
 p3mz_status p3mz_kernel_bench(p3mz_ctx* ctx, int32_t kernel_id, int32_t reps, void* stream, double* avg_ms,
                               double* bytes_per_launch);
 
+/* Set the V-cycle schedule (red-black sweeps before restriction and after
+ * prolongation, 0..16 each, sum >= 1) and the smoothing launch shape
+ * (0 .. P3MZ_SMOOTH_TILES-1, shapes that divide the mesh edge; all shapes give
+ * identical results).  Synchronises the device; graphs are recaptured. */
+#define P3MZ_SMOOTH_TILES 7
+p3mz_status p3mz_set_schedule(p3mz_ctx* ctx, int32_t nu_pre, int32_t nu_post, int32_t smooth_tile);
+
+typedef struct {
+  int32_t nu_pre, nu_post;   /* chosen schedule                                        */
+  int32_t smooth_tile;       /* chosen smoothing launch shape                          */
+  int32_t n_candidates;      /* schedules tried                                        */
+  double ms_best;            /* mean mesh-step milliseconds per frame, chosen schedule */
+  double ms_default;         /* the same for the default (2, 2)                        */
+  double ms_smooth;          /* three smoothing passes with the chosen shape           */
+  int32_t cand_nu_pre[16], cand_nu_post[16], cand_cycles[16];
+  double cand_ms[16];
+} p3mz_tune_result;
+
+/* Autotuner.  Times the smoothing launch shapes back to back, then every
+ * candidate V-cycle schedule by time to tolerance: each candidate restarts
+ * from the context's current history and runs mesh steps on the caller's
+ * frames_dev [n_frames][n_atoms][3] (1 <= n_frames <= 64, e.g. the next
+ * positions of a trajectory), and the schedule with the least mean
+ * mesh-step time wins.  The context is left with its history unchanged and
+ * the chosen schedule applied; the choice is stored in the tuning cache
+ * (JSON; path from the environment variable P3MZ_TUNE_CACHE, default
+ * $HOME/.cache/p3maze/tune.json) under (device, mesh, order, precision),
+ * where contexts created with nu_pre or nu_post = -1 find it.  Results of a
+ * step depend on the schedule (cycle counts differ); a reference run must
+ * use the same schedule (p3mz_stats.nu_pre/nu_post).  Errors: INVALID_ARG
+ * when the cache cannot be written. */
+p3mz_status p3mz_autotune(p3mz_ctx* ctx, const double* frames_dev, int32_t n_frames, void* stream,
+                          p3mz_tune_result* out);
+
 void p3mz_destroy(p3mz_ctx* ctx);
 
 /* ---- Batched replicas ------------------------------------------------------

@@ -1,9 +1,11 @@
 // Host side of the library: planning, workspace allocation, the per-step
 // launch sequence and the C ABI declared in include/p3maze.h.
+#include <errno.h>
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <sys/stat.h>
 
 #include <algorithm>
 #include <string>
@@ -139,6 +141,7 @@ struct p3mz_ctx {
   bool fp64 = true;
   size_t tsz = 8;
   int nu1 = 2, nu2 = 2;
+  int smooth_tile = 0;     // smoothing launch shape (autotuned)
   int64_t n_atoms = 0;
   int64_t n3 = 0;
   double e_self = 0;
@@ -259,14 +262,103 @@ uint64_t bits(double v) {
   return u;
 }
 
+// ---------------------------------------------------------------------------
+// Tuning cache: one JSON object per line inside an "entries" array, keyed by
+// device, mesh edge, assignment order and precision.  Written by
+// p3mz_autotune, read when a context asks for the tuned sweep counts.
+// ---------------------------------------------------------------------------
+struct TuneEntry {
+  int nu_pre = 2, nu_post = 2, smooth_tile = 0;
+  double ms = 0.0;
+};
+
+std::string tune_path() {
+  const char* e = getenv("P3MZ_TUNE_CACHE");
+  if (e && *e) return e;
+  const char* home = getenv("HOME");
+  return std::string(home && *home ? home : "/tmp") + "/.cache/p3maze/tune.json";
+}
+
+std::string tune_key(int n, int p, int precision) {
+  hipDeviceProp_t prop;
+  int dev = 0;
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+  for (char& ch : arch)
+    if (ch == '"' || ch == ' ') ch = '_';
+  char buf[256];
+  snprintf(buf, sizeof buf, "%s/n%d/p%d/%s", arch.c_str(), n, p, precision == P3MZ_PREC_FP64 ? "fp64" : "mixed");
+  return buf;
+}
+
+// All entries of the cache file (key -> entry); a missing file is empty.
+std::vector<std::pair<std::string, TuneEntry>> tune_read() {
+  std::vector<std::pair<std::string, TuneEntry>> out;
+  FILE* f = fopen(tune_path().c_str(), "r");
+  if (!f) return out;
+  char line[1024], key[512];
+  while (fgets(line, sizeof line, f)) {
+    TuneEntry t;
+    if (sscanf(line, " {\"key\": \"%511[^\"]\", \"nu_pre\": %d, \"nu_post\": %d, \"smooth_tile\": %d, \"ms\": %lf",
+               key, &t.nu_pre, &t.nu_post, &t.smooth_tile, &t.ms) == 5)
+      out.emplace_back(key, t);
+  }
+  fclose(f);
+  return out;
+}
+
+bool tune_lookup(const std::string& key, TuneEntry* t) {
+  for (auto& kv : tune_read())
+    if (kv.first == key) {
+      *t = kv.second;
+      return true;
+    }
+  return false;
+}
+
+p3mz_status tune_store(const std::string& key, const TuneEntry& t) {
+  auto all = tune_read();
+  bool found = false;
+  for (auto& kv : all)
+    if (kv.first == key) {
+      kv.second = t;
+      found = true;
+    }
+  if (!found) all.emplace_back(key, t);
+  const std::string path = tune_path();
+  // create the parent directories
+  for (size_t i = 1; i < path.size(); i++)
+    if (path[i] == '/') {
+      const std::string d = path.substr(0, i);
+      if (mkdir(d.c_str(), 0755) != 0 && errno != EEXIST)
+        return fail(P3MZ_ERR_INVALID_ARG, "cannot create the tuning cache directory " + d);
+    }
+  const std::string tmp = path + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return fail(P3MZ_ERR_INVALID_ARG, "cannot write the tuning cache " + tmp);
+  fprintf(f, "{\"entries\": [\n");
+  for (size_t i = 0; i < all.size(); i++)
+    fprintf(f, "  {\"key\": \"%s\", \"nu_pre\": %d, \"nu_post\": %d, \"smooth_tile\": %d, \"ms\": %.6f}%s\n",
+            all[i].first.c_str(), all[i].second.nu_pre, all[i].second.nu_post, all[i].second.smooth_tile,
+            all[i].second.ms, i + 1 < all.size() ? "," : "");
+  fprintf(f, "]}\n");
+  if (fclose(f) != 0 || rename(tmp.c_str(), path.c_str()) != 0)
+    return fail(P3MZ_ERR_INVALID_ARG, "cannot write the tuning cache " + path);
+  return P3MZ_OK;
+}
+
 p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   const Plan& pl = c->pl;
   const int n = pl.n;
   c->n3 = (int64_t)n * n * n;
   c->fp64 = c->P.precision == P3MZ_PREC_FP64;
   c->tsz = c->fp64 ? 8 : 4;
-  c->nu1 = c->P.nu_pre >= 0 ? c->P.nu_pre : 2;
-  c->nu2 = c->P.nu_post >= 0 ? c->P.nu_post : 2;
+  TuneEntry tuned;
+  const bool have_tune = tune_lookup(tune_key(pl.n, pl.p, c->P.precision), &tuned);
+  c->nu1 = c->P.nu_pre >= 0 ? c->P.nu_pre : (have_tune ? tuned.nu_pre : 2);
+  c->nu2 = c->P.nu_post >= 0 ? c->P.nu_post : (have_tune ? tuned.nu_post : 2);
+  // the tile shape never changes results, so a tuned one is always taken
+  c->smooth_tile = have_tune && smooth_tile_ok(tuned.smooth_tile, n) ? tuned.smooth_tile : 0;
   if (c->nu1 + c->nu2 < 1) return fail(P3MZ_ERR_INVALID_ARG, "nu_pre + nu_post must be >= 1");
   P3MZ_HIP_TRY(hipGetDevice(&c->dev));
   P3MZ_HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
@@ -390,7 +482,7 @@ p3mz_status enq_pre(p3mz_ctx* c, const double* pos, hipStream_t s) {
   for (int axis = 0; axis < 3; axis++) {
     rec_key(105 + axis);
     kt_begin(KT_SMOOTH, 0, s);
-    P3MZ_HIP_TRY(launch_smooth(true, n, axis, c->ntaps, c->half, c->d_taps, src[axis], dst[axis], s));
+    P3MZ_HIP_TRY(launch_smooth(true, n, axis, c->smooth_tile, c->ntaps, c->half, c->d_taps, src[axis], dst[axis], s));
     kt_end(KT_SMOOTH, 0, 16.0 * N3, s);
   }
   stage(c, 1, s);
@@ -1314,7 +1406,8 @@ p3mz_status p3mz_kernel_bench(p3mz_ctx* ctx, int32_t kernel_id, int32_t reps, vo
   for (int r = 0; r < reps && st == P3MZ_OK; r++) {
     hipError_t e;
     if (kernel_id == KT_SMOOTH) {
-      e = launch_smooth(true, ctx->pl.n, 0, ctx->ntaps, ctx->half, ctx->d_taps, ctx->d_q, ctx->d_tmp, s);
+      e = launch_smooth(true, ctx->pl.n, 0, ctx->smooth_tile, ctx->ntaps, ctx->half, ctx->d_taps, ctx->d_q, ctx->d_tmp,
+                        s);
       bytes = 16.0 * (double)ctx->n3;
     } else {
       e = launch_vcycle_kernel(ctx->fp64, kernel_id, ctx->lv, ctx->pl.levels, ctx->pl.tail, ctx->nu1, ctx->nu2,
@@ -1332,6 +1425,108 @@ p3mz_status p3mz_kernel_bench(p3mz_ctx* ctx, int32_t kernel_id, int32_t reps, vo
   *avg_ms = ms / reps;
   *bytes_per_launch = bytes;
   return st;
+}
+
+p3mz_status p3mz_set_schedule(p3mz_ctx* ctx, int32_t nu_pre, int32_t nu_post, int32_t smooth_tile) {
+  if (!ctx) return fail(P3MZ_ERR_INVALID_ARG, "ctx is NULL");
+  if (nu_pre < 0 || nu_post < 0 || nu_pre > 16 || nu_post > 16 || nu_pre + nu_post < 1)
+    return fail(P3MZ_ERR_INVALID_ARG, "sweep counts must be in 0..16 with nu_pre + nu_post >= 1");
+  if (!smooth_tile_ok(smooth_tile, ctx->pl.n)) return fail(P3MZ_ERR_INVALID_ARG, "smoothing tile not valid on this mesh");
+  P3MZ_HIP_TRY(hipDeviceSynchronize());
+  ctx->drop_graphs();
+  ctx->nu1 = nu_pre;
+  ctx->nu2 = nu_post;
+  ctx->smooth_tile = smooth_tile;
+  return P3MZ_OK;
+}
+
+p3mz_status p3mz_autotune(p3mz_ctx* ctx, const double* frames_dev, int32_t n_frames, void* stream,
+                          p3mz_tune_result* out) {
+  if (!ctx || !frames_dev || n_frames < 1 || n_frames > 64 || !out)
+    return fail(P3MZ_ERR_INVALID_ARG, "bad autotune arguments");
+  hipStream_t s = (hipStream_t)stream;
+  memset(out, 0, sizeof *out);
+  const int n = ctx->pl.n;
+  // 1. smoothing launch shape: the three axis passes back to back, best of 3
+  hipEvent_t e0, e1;
+  P3MZ_HIP_TRY(hipEventCreate(&e0));
+  P3MZ_HIP_TRY(hipEventCreate(&e1));
+  int best_tile = ctx->smooth_tile;
+  double best_tile_ms = 1e300;
+  for (int t = 0; t < smooth_tile_count(); t++) {
+    if (!smooth_tile_ok(t, n)) continue;
+    double ms_min = 1e300;
+    for (int rep = 0; rep < 4; rep++) {
+      P3MZ_HIP_TRY(hipEventRecord(e0, s));
+      double* src[3] = {ctx->d_q, ctx->d_tmp, ctx->d_qs};
+      double* dst[3] = {ctx->d_tmp, ctx->d_qs, ctx->d_tmp};
+      for (int axis = 0; axis < 3; axis++)
+        P3MZ_HIP_TRY(launch_smooth(true, n, axis, t, ctx->ntaps, ctx->half, ctx->d_taps, src[axis], dst[axis], s));
+      P3MZ_HIP_TRY(hipEventRecord(e1, s));
+      P3MZ_HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      P3MZ_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (rep > 0) ms_min = std::min(ms_min, (double)ms);   // the first run warms up
+    }
+    if (ms_min < best_tile_ms) {
+      best_tile_ms = ms_min;
+      best_tile = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  out->smooth_tile = best_tile;
+  out->ms_smooth = best_tile_ms;
+  // 2. sweep schedule by time to tolerance over the caller's frames, each
+  //    candidate starting from the same saved history
+  size_t bytes = 0;
+  P3MZ_TRY(p3mz_save_state(ctx, nullptr, &bytes));
+  std::vector<char> blob(bytes);
+  P3MZ_TRY(p3mz_save_state(ctx, blob.data(), &bytes));
+  const int cand[][2] = {{2, 2}, {1, 1}, {1, 2}, {2, 1}, {0, 2}, {2, 3}, {3, 2}, {3, 3}, {4, 4}};
+  const int ncand = (int)(sizeof cand / sizeof cand[0]);
+  const int nu1_0 = ctx->nu1, nu2_0 = ctx->nu2;
+  const bool timing_0 = ctx->timing;
+  const bool have_force_0 = ctx->md_have_force;
+  P3MZ_TRY(p3mz_set_timing(ctx, 1));
+  int best = 0;
+  for (int k = 0; k < ncand; k++) {
+    P3MZ_TRY(p3mz_set_schedule(ctx, cand[k][0], cand[k][1], best_tile));
+    double total = 0.0;
+    int cycles = 0;
+    for (int pass = 0; pass < 2; pass++) {   // the first pass captures the graphs
+      P3MZ_TRY(p3mz_load_state(ctx, blob.data(), bytes));
+      total = 0.0;
+      cycles = 0;
+      for (int f = 0; f < n_frames; f++) {
+        p3mz_status st = compute_step(ctx, frames_dev + (size_t)3 * ctx->n_atoms * f, nullptr, nullptr, s);
+        if (st < 0) return st;
+        total += ctx->st.ms_mesh;
+        cycles += ctx->st.cycles;
+      }
+    }
+    out->cand_nu_pre[k] = cand[k][0];
+    out->cand_nu_post[k] = cand[k][1];
+    out->cand_ms[k] = total / n_frames;
+    out->cand_cycles[k] = cycles;
+    if (out->cand_ms[k] < out->cand_ms[best]) best = k;
+  }
+  out->n_candidates = ncand;
+  out->nu_pre = cand[best][0];
+  out->nu_post = cand[best][1];
+  out->ms_best = out->cand_ms[best];
+  out->ms_default = out->cand_ms[0];
+  // restore the history, apply the choice and store it
+  P3MZ_TRY(p3mz_load_state(ctx, blob.data(), bytes));
+  P3MZ_TRY(p3mz_set_timing(ctx, timing_0));
+  ctx->md_have_force = have_force_0 && nu1_0 == out->nu_pre && nu2_0 == out->nu_post;
+  P3MZ_TRY(p3mz_set_schedule(ctx, out->nu_pre, out->nu_post, out->smooth_tile));
+  TuneEntry t;
+  t.nu_pre = out->nu_pre;
+  t.nu_post = out->nu_post;
+  t.smooth_tile = out->smooth_tile;
+  t.ms = out->ms_best;
+  return tune_store(tune_key(n, ctx->pl.p, ctx->P.precision), t);
 }
 
 void p3mz_destroy(p3mz_ctx* ctx) {

@@ -53,9 +53,13 @@ hipError_t launch_sr(int n_atoms, const double* pos, const double* qa, double bo
                      double* partial, Ctl* ctl, hipStream_t s);
 
 // ---- mesh (mesh.hip) -----------------------------------------------------
-// Folded periodic smoothing filter along one axis: out = sum_m c[m] v[i+m-K].
-hipError_t launch_smooth(bool fp64, int n, int axis, int ntaps, int half, const void* taps,
+// Folded periodic smoothing filter along one axis: out = sum_m c[m] v[i+m-K],
+// launch shape `tile` (see smooth_tile_shape; 0 = default).
+hipError_t launch_smooth(bool fp64, int n, int axis, int tile, int ntaps, int half, const void* taps,
                          const void* in, void* out, hipStream_t s);
+int smooth_tile_count();
+bool smooth_tile_ok(int tile, int n);
+void smooth_tile_shape(int tile, int* lines_per_workgroup, int* outputs_per_thread);
 // sigma_p = (h/4pi) M (2 phi^k - phi^{k-1}) + q^s (cold: q^s) and the
 // multiplier predictor into y; a one-workgroup pass then forms the mean of
 // sigma_p, max|q^s| and the threshold and opens the solve.  History buffers

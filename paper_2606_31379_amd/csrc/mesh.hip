@@ -1105,33 +1105,72 @@ hipError_t one_kernel(int kid, const LevelBufs* lv, int levels, int tail, int nu
 }  // namespace
 
 // smoothing launch shape: W lines per workgroup, R outputs per thread
-constexpr int kSmoothW = 4;
-constexpr int kSmoothR = 4;
+// Smoothing launch shapes (W lines per workgroup, R outputs per thread);
+// variant 0 is the default, the others are candidates for the autotuner.
+constexpr int kSmoothTiles[][2] = {{4, 4}, {2, 4}, {8, 4}, {4, 2}, {4, 8}, {8, 2}, {2, 8}};
+constexpr int kSmoothTileCount = (int)(sizeof(kSmoothTiles) / sizeof(kSmoothTiles[0]));
 
-hipError_t launch_smooth(bool fp64, int n, int axis, int ntaps, int half, const void* taps, const void* in,
-                         void* out, hipStream_t s) {
-  if (!fp64) return hipErrorInvalidValue;   // the charge source is FP64 in both modes
-  const int W = kSmoothW;
-  if (n % W || n % kSmoothR) return hipErrorInvalidValue;
+namespace {
+template <int W, int R>
+hipError_t smooth_wr(int n, int axis, int ntaps, int half, const double* tp, const double* ip, double* op,
+                     hipStream_t s) {
   const int grid = axis == 0 ? (int)((size_t)n * n / W) : (n / W) * n;
   const size_t lds = smooth_lds_bytes(n, axis, W, ntaps, 8);
+  if (axis == 0) return go<Smooth<double, 0, W, R>>({n, ntaps, half, tp, ip, op}, grid, lds, s);
+  if (axis == 1) return go<Smooth<double, 1, W, R>>({n, ntaps, half, tp, ip, op}, grid, lds, s);
+  return go<Smooth<double, 2, W, R>>({n, ntaps, half, tp, ip, op}, grid, lds, s);
+}
+
+template <int W, int R>
+hipError_t smooth_allow(int n) {
+  const int bytes = (int)smooth_lds_bytes(n, 0, W, n, 8);   // the x axis needs the most
+  P3MZ_LAUNCH(allow_lds<Smooth<double, 0, W, R>>(bytes));
+  P3MZ_LAUNCH(allow_lds<Smooth<double, 1, W, R>>(bytes));
+  return allow_lds<Smooth<double, 2, W, R>>(bytes);
+}
+}  // namespace
+
+int smooth_tile_count() { return kSmoothTileCount; }
+
+bool smooth_tile_ok(int tile, int n) {
+  return tile >= 0 && tile < kSmoothTileCount && n % kSmoothTiles[tile][0] == 0 && n % kSmoothTiles[tile][1] == 0;
+}
+
+void smooth_tile_shape(int tile, int* w, int* r) {
+  *w = kSmoothTiles[tile][0];
+  *r = kSmoothTiles[tile][1];
+}
+
+hipError_t launch_smooth(bool fp64, int n, int axis, int tile, int ntaps, int half, const void* taps, const void* in,
+                         void* out, hipStream_t s) {
+  if (!fp64) return hipErrorInvalidValue;   // the charge source is FP64 in both modes
+  if (!smooth_tile_ok(tile, n)) return hipErrorInvalidValue;
   const double *tp = (const double*)taps, *ip = (const double*)in;
   double* op = (double*)out;
-  if (axis == 0) return go<Smooth<double, 0, kSmoothW, kSmoothR>>({n, ntaps, half, tp, ip, op}, grid, lds, s);
-  if (axis == 1) return go<Smooth<double, 1, kSmoothW, kSmoothR>>({n, ntaps, half, tp, ip, op}, grid, lds, s);
-  return go<Smooth<double, 2, kSmoothW, kSmoothR>>({n, ntaps, half, tp, ip, op}, grid, lds, s);
+  switch (tile) {
+    case 0: return smooth_wr<4, 4>(n, axis, ntaps, half, tp, ip, op, s);
+    case 1: return smooth_wr<2, 4>(n, axis, ntaps, half, tp, ip, op, s);
+    case 2: return smooth_wr<8, 4>(n, axis, ntaps, half, tp, ip, op, s);
+    case 3: return smooth_wr<4, 2>(n, axis, ntaps, half, tp, ip, op, s);
+    case 4: return smooth_wr<4, 8>(n, axis, ntaps, half, tp, ip, op, s);
+    case 5: return smooth_wr<8, 2>(n, axis, ntaps, half, tp, ip, op, s);
+    default: return smooth_wr<2, 8>(n, axis, ntaps, half, tp, ip, op, s);
+  }
 }
 
 // Dynamic-LDS limits only ever grow, so contexts of different mesh sizes can
 // coexist in one process.
 hipError_t smooth_configure(int n) {
   static int granted = 0;
-  const int bytes = (int)smooth_lds_bytes(n, 0, kSmoothW, n, 8);
-  if (bytes <= granted) return hipSuccess;
-  P3MZ_LAUNCH(allow_lds<Smooth<double, 0, kSmoothW, kSmoothR>>(bytes));
-  P3MZ_LAUNCH(allow_lds<Smooth<double, 1, kSmoothW, kSmoothR>>(bytes));
-  P3MZ_LAUNCH(allow_lds<Smooth<double, 2, kSmoothW, kSmoothR>>(bytes));
-  granted = bytes;
+  if (n <= granted) return hipSuccess;
+  P3MZ_LAUNCH(smooth_allow<4, 4>(n));
+  P3MZ_LAUNCH(smooth_allow<2, 4>(n));
+  P3MZ_LAUNCH(smooth_allow<8, 4>(n));
+  P3MZ_LAUNCH(smooth_allow<4, 2>(n));
+  P3MZ_LAUNCH(smooth_allow<4, 8>(n));
+  P3MZ_LAUNCH(smooth_allow<8, 2>(n));
+  P3MZ_LAUNCH(smooth_allow<2, 8>(n));
+  granted = n;
   return hipSuccess;
 }
 

@@ -32,7 +32,7 @@ MESH_Q, MESH_QS, MESH_SIGMA_P, MESH_Y, MESH_PHI, MESH_PHI_PREV = range(6)
 EXPORTS = ["p3mz_create", "p3mz_compute", "p3mz_get_mesh", "p3mz_vcycle", "p3mz_get_stats",
            "p3mz_reset_history", "p3mz_save_state", "p3mz_load_state", "p3mz_md_run",
            "p3mz_set_graphs", "p3mz_set_timing", "p3mz_set_kernel_timer", "p3mz_get_kernel_timer",
-           "p3mz_kernel_bench",
+           "p3mz_kernel_bench", "p3mz_set_schedule", "p3mz_autotune",
            "p3mz_destroy", "p3mz_batch_create", "p3mz_batch_compute", "p3mz_batch_md_run",
            "p3mz_batch_get_stats", "p3mz_batch_set_timing", "p3mz_batch_get_timing", "p3mz_batch_set_graphs",
            "p3mz_batch_kernel_bench", "p3mz_batch_destroy", "p3mz_status_string", "p3mz_last_error", "p3mz_version"]
@@ -66,6 +66,16 @@ class p3mz_mdterms(C.Structure):
                 ("force_to_acc", C.c_double), ("mv2_to_energy", C.c_double)]
 
 
+class p3mz_tune_result(C.Structure):
+    _fields_ = [("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("smooth_tile", C.c_int32),
+                ("n_candidates", C.c_int32), ("ms_best", C.c_double), ("ms_default", C.c_double),
+                ("ms_smooth", C.c_double), ("cand_nu_pre", C.c_int32 * 16), ("cand_nu_post", C.c_int32 * 16),
+                ("cand_cycles", C.c_int32 * 16), ("cand_ms", C.c_double * 16)]
+
+
+SMOOTH_TILES = 7
+
+
 class P3MZError(RuntimeError):
     def __init__(self, code: int, where: str, msg: str):
         super().__init__(f"{where}: status {code}: {msg}")
@@ -94,6 +104,8 @@ def _load() -> C.CDLL:
         "p3mz_kernel_bench": ([vp, C.c_int32, C.c_int32, vp, dp, dp], C.c_int),
         "p3mz_set_kernel_timer": ([vp, C.c_int32], C.c_int),
         "p3mz_get_kernel_timer": ([vp, dp, C.POINTER(C.c_int64), dp], C.c_int),
+        "p3mz_set_schedule": ([vp, C.c_int32, C.c_int32, C.c_int32], C.c_int),
+        "p3mz_autotune": ([vp, vp, C.c_int32, vp, C.POINTER(p3mz_tune_result)], C.c_int),
         "p3mz_destroy": ([vp], None),
         "p3mz_batch_create": ([C.c_int32, C.POINTER(p3mz_params), C.POINTER(C.c_int64), dp, C.POINTER(vp)], C.c_int),
         "p3mz_batch_compute": ([vp, vp, vp, vp, vp], C.c_int),
@@ -201,6 +213,17 @@ def p3mz_get_kernel_timer(ctx: int) -> tuple[float, int, float]:
     ms, n, b = C.c_double(), C.c_int64(), C.c_double()
     _check(lib.p3mz_get_kernel_timer(ctx, C.byref(ms), C.byref(n), C.byref(b)), "p3mz_get_kernel_timer")
     return ms.value, n.value, b.value
+
+
+def p3mz_set_schedule(ctx: int, nu_pre: int, nu_post: int, smooth_tile: int = 0) -> int:
+    return _check(lib.p3mz_set_schedule(ctx, nu_pre, nu_post, smooth_tile), "p3mz_set_schedule")
+
+
+def p3mz_autotune(ctx: int, frames_dev: int, n_frames: int, stream: int | None = None) -> p3mz_tune_result:
+    """frames_dev: device pointer to [n_frames][n_atoms][3] float64 positions."""
+    out = p3mz_tune_result()
+    _check(lib.p3mz_autotune(ctx, frames_dev, n_frames, stream, C.byref(out)), "p3mz_autotune")
+    return out
 
 
 def p3mz_destroy(ctx: int) -> None:
