@@ -107,12 +107,45 @@ def copy_ceiling_gbps(torch, nbytes=1 << 30, reps=10):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
-def run_mode(torch, P, w, system, precision, warmup, steps, kernel):
+def autotune_schedule(torch, P, w, system, precision, warmup, n_frames=8):
+    """Autotuner run: after `warmup` MD steps, the next `n_frames` MD
+    positions are the tuning frames; every candidate schedule restarts from
+    the history at the start of those frames."""
+    import numpy as np
+    dev = torch.device("cuda")
+    ctx = P.p3mz_create(make_params(P, w, precision), system.charges)
+    try:
+        pos = torch.from_numpy(np.ascontiguousarray(system.pos)).to(dev)
+        vel = torch.from_numpy(np.ascontiguousarray(system.vel)).to(dev)
+        mass = torch.from_numpy(np.ascontiguousarray(system.masses)).to(dev)
+        terms = md_terms(P, w.kind)
+        stream = torch.cuda.current_stream().cuda_stream
+        P.p3mz_md_run(ctx, pos.data_ptr(), vel.data_ptr(), mass.data_ptr(), terms, w.dt_fs, max(warmup, 4), None,
+                      None, stream)
+        blob = P.p3mz_save_state(ctx)
+        frames = torch.zeros((n_frames, system.n, 3), dtype=torch.float64, device=dev)
+        for k in range(n_frames):
+            P.p3mz_md_run(ctx, pos.data_ptr(), vel.data_ptr(), mass.data_ptr(), terms, w.dt_fs, 1, None, None,
+                          stream)
+            frames[k].copy_(pos)
+        P.p3mz_load_state(ctx, blob)
+        r = P.p3mz_autotune(ctx, frames.data_ptr(), n_frames, stream)
+        cands = [dict(nu_pre=r.cand_nu_pre[k], nu_post=r.cand_nu_post[k], ms=r.cand_ms[k],
+                      cycles=r.cand_cycles[k]) for k in range(r.n_candidates)]
+        return dict(nu_pre=r.nu_pre, nu_post=r.nu_post, smooth_tile=r.smooth_tile, ms_best=r.ms_best,
+                    ms_default=r.ms_default, ms_smooth=r.ms_smooth, frames=n_frames, candidates=cands)
+    finally:
+        P.p3mz_destroy(ctx)
+
+
+def run_mode(torch, P, w, system, precision, warmup, steps, kernel, schedule=None):
     """Warm up, pick the dominant kernel family, then time `steps` MD steps."""
     import numpy as np
     dev = torch.device("cuda")
     ctx = P.p3mz_create(make_params(P, w, precision), system.charges)
     try:
+        if schedule:
+            P.p3mz_set_schedule(ctx, schedule["nu_pre"], schedule["nu_post"], schedule["smooth_tile"])
         pos = torch.from_numpy(np.ascontiguousarray(system.pos)).to(dev)
         vel = torch.from_numpy(np.ascontiguousarray(system.vel)).to(dev)
         mass = torch.from_numpy(np.ascontiguousarray(system.masses)).to(dev)
@@ -182,20 +215,19 @@ def run_mode(torch, P, w, system, precision, warmup, steps, kernel):
             dominant_avg_launch_us=avg_launch_ms * 1e3, dominant_launches=int(klaunch),
             dominant_bytes_per_launch=bytes_per_launch,
             dominant_gbps=bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9 if klaunch else None,
+            schedule=dict(nu_pre=P.p3mz_get_stats(ctx).nu_pre, nu_post=P.p3mz_get_stats(ctx).nu_post,
+                          smooth_tile=schedule["smooth_tile"] if schedule else 0),
         )
         return out
     finally:
         P.p3mz_destroy(ctx)
 
 
-def parity_and_baseline(torch, P, w, system, sample_steps):
-    """Oracle on a bounded sample (cold solve + warm steps along the initial
-    velocities), the GPU modes on the same positions, and the oracle's time."""
+def oracle_sample(w, system, traj, nu_pre, nu_post):
     import numpy as np
     from oracle import oracle as O
-    traj = [system.pos + k * w.dt_fs * system.vel for k in range(sample_steps)]
     op = O.make_params(w.box, w.alpha, w.r_cut, w.mesh, w.order, tol=w.tol, predictor=w.predictor,
-                       coulomb_k=14.3996454784, nu_pre=2, nu_post=2, excl_group=w.excl_group)
+                       coulomb_k=14.3996454784, nu_pre=nu_pre, nu_post=nu_post, excl_group=w.excl_group)
     orc = O.Oracle(op, system.charges)
     ref, cyc_ref, t_mesh = [], [], []
     for k, x in enumerate(traj):
@@ -205,12 +237,32 @@ def parity_and_baseline(torch, P, w, system, sample_steps):
         cyc_ref.append(st.cycles)
         if k > 0:
             t_mesh.append(st.t_spread + st.t_solve + st.t_gather)
-        log(f"[oracle] step {k} cycles={st.cycles} mesh_s={st.t_spread + st.t_solve + st.t_gather:.3f}")
+        log(f"[oracle nu=({nu_pre},{nu_post})] step {k} cycles={st.cycles} "
+            f"mesh_s={st.t_spread + st.t_solve + st.t_gather:.3f}")
+    orc.close()
+    return ref, cyc_ref, t_mesh
+
+
+def parity_and_baseline(torch, P, w, system, sample_steps, schedules):
+    """Oracle on a bounded sample (cold solve + warm steps along the initial
+    velocities) with each mode's V-cycle schedule, the GPU modes on the same
+    positions, and the oracle's time (with the headline mode's schedule)."""
+    import numpy as np
+    traj = [system.pos + k * w.dt_fs * system.vel for k in range(sample_steps)]
+    runs = {}
     out = {}
     dev = torch.device("cuda")
     for precision, name in ((0, "fp64"), (1, "mixed")):
+        sch = schedules.get(name)
+        if sch is None:
+            continue
+        key = (sch["nu_pre"], sch["nu_post"])
+        if key not in runs:
+            runs[key] = oracle_sample(w, system, traj, *key)
+        ref, cyc_ref, t_mesh = runs[key]
         ctx = P.p3mz_create(make_params(P, w, precision), system.charges)
         try:
+            P.p3mz_set_schedule(ctx, sch["nu_pre"], sch["nu_post"], sch["smooth_tile"])
             pos = torch.zeros((system.n, 3), dtype=torch.float64, device=dev)
             frc = torch.zeros_like(pos)
             errs, cyc = [], []
@@ -222,15 +274,17 @@ def parity_and_baseline(torch, P, w, system, sample_steps):
                 errs.append(float(np.sqrt(((fg - ref[k]) ** 2).sum() / (ref[k] ** 2).sum())))
                 cyc.append(P.p3mz_get_stats(ctx).cycles)
             out[name] = dict(max_rel_rms_force_err=max(errs), vcycles_gpu=cyc, vcycles_oracle=cyc_ref,
-                             vcycles_equal=cyc == cyc_ref)
+                             vcycles_equal=cyc == cyc_ref, schedule=[sch["nu_pre"], sch["nu_post"]])
         finally:
             P.p3mz_destroy(ctx)
+    head = schedules.get("mixed") or schedules.get("fp64")
+    t_mesh = runs[(head["nu_pre"], head["nu_post"])][2]
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     mean_s = float(np.mean(t_mesh)) if t_mesh else float("nan")
     baseline = dict(value=mean_s * 1e9 / system.n, unit="ns/atom/step", cores=cores, kind="oracle",
                     sample=f"{sample_steps} mesh steps of {w.name} along the initial velocities "
-                           f"(dt {w.dt_fs} fs); cold first step excluded from the mean; "
-                           f"spread+smoothing+solve+gather only")
+                           f"(dt {w.dt_fs} fs), V-cycle schedule ({head['nu_pre']},{head['nu_post']}); "
+                           f"cold first step excluded from the mean; spread+smoothing+solve+gather only")
     return out, baseline
 
 
@@ -431,6 +485,7 @@ def main():
     ap.add_argument("--cpu-sample-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--modes", default="fp64,mixed", help="precision modes to run (the headline is mixed)")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default (2,2) V-cycle schedule")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -453,18 +508,27 @@ def main():
     log(f"atoms {system.n} box {system.box} mesh {w.mesh}^3 order {w.order} tol {w.tol}")
     ceiling = copy_ceiling_gbps(torch)
     log(f"device copy ceiling {ceiling:.0f} GB/s")
-    res = {}
+    res, tune, schedules = {}, {}, {}
     modes = args.modes.split(",")
+    if not args.no_tune and not os.environ.get("P3MZ_TUNE_CACHE"):
+        import tempfile
+        os.environ["P3MZ_TUNE_CACHE"] = os.path.join(tempfile.mkdtemp(prefix="p3mz_tune_"), "tune.json")
     for precision, name in ((0, "fp64"), (1, "mixed")):
         if name not in modes:
             continue
+        if args.no_tune:
+            schedules[name] = dict(nu_pre=2, nu_post=2, smooth_tile=0)
+        else:
+            tune[name] = autotune_schedule(torch, P, w, system, precision, args.warmup)
+            schedules[name] = {k: tune[name][k] for k in ("nu_pre", "nu_post", "smooth_tile")}
+            log(f"[{name}] autotune: {json.dumps({k: v for k, v in tune[name].items() if k != 'candidates'})}")
         log(f"[{name}] warmup {args.warmup}, timed {args.steps}")
-        res[name] = run_mode(torch, P, w, system, precision, args.warmup, args.steps, args.kernel)
+        res[name] = run_mode(torch, P, w, system, precision, args.warmup, args.steps, args.kernel, schedules[name])
         log(f"[{name}] {json.dumps({k: v for k, v in res[name].items() if k != 'kernel_ms_per_step'})}")
     parity, baseline = None, None
     if not args.no_cpu_baseline:
         sample = args.cpu_sample_steps or (8 if system.n <= 4000 else 3)
-        parity, baseline = parity_and_baseline(torch, P, w, system, sample)
+        parity, baseline = parity_and_baseline(torch, P, w, system, sample, schedules)
     m, f = res.get("mixed"), res.get("fp64")
     head = m if m is not None else f
     traffic, traffic_note = measured_traffic(head["dominant"], w.name, "mixed" if m is not None else "fp64")
@@ -480,7 +544,7 @@ def main():
         config=dict(workload=w.name, n_atoms=system.n, box=w.box, mesh=w.mesh, order=w.order,
                     alpha=w.alpha, r_cut=w.r_cut, tol=w.tol, predictor=w.predictor, dt_fs=w.dt_fs,
                     precision="mixed" if m is not None else "fp64"),
-        mixed=m, fp64=f,
+        mixed=m, fp64=f, autotune=tune or None,
         speedup_mixed_vs_fp64=(f["mesh_ms_per_step"] / m["mesh_ms_per_step"]) if (m and f) else None,
         roofline=roof, cpu_baseline=baseline, parity=parity,
     )
