@@ -216,8 +216,10 @@ p3mz_status p3mz_get_kernel_timer(const p3mz_ctx* ctx, double* total_ms, int64_t
 /* Back-to-back timing of one finest-level kernel on the context's current
  * buffers: `reps` launches between two HIP events on `stream`; *avg_ms is the
  * mean launch duration and *bytes_per_launch its algorithmic HBM traffic.
- * Families: HALFSWEEP, SWEEP0, RESTRICT, PROLONG, TAIL, SMOOTH (x axis).
- * Overwrites multigrid scratch only; the potential history is untouched.
+ * Families: HALFSWEEP, SWEEP0, RESTRICT, PROLONG, TAIL, SMOOTH (x axis),
+ * OUTER and SIGMA (without their one-workgroup finalize pass), SPREAD and
+ * GATHER (on the last step's binning, no forces written).  Overwrites
+ * scratch buffers only; the potential and multiplier history is untouched.
  * Synchronises the stream.  Errors: INVALID_ARG for other families or a mesh
  * without that kernel. */
 p3mz_status p3mz_kernel_bench(p3mz_ctx* ctx, int32_t kernel_id, int32_t reps, void* stream, double* avg_ms,

@@ -8,12 +8,14 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 
 import numpy as np
 
 from . import inputs
 
 K_E_EV_A = 14.3996454784   # Coulomb constant in eV*A/e^2
+INPUTS_VERSION = "v1"      # bump when a recipe changes (invalidates cached systems)
 
 
 @dataclasses.dataclass
@@ -34,12 +36,30 @@ class Workload:
     predictor: int = 3
     excl_group: int = 0     # 3 for water: O,H,H of one molecule are excluded pairs
 
-    def system(self) -> inputs.System:
+    def generate(self) -> inputs.System:
         if self.kind == "nacl":
             return inputs.nacl(self.n_atoms, self.box, self.temp_k, self.seed)
         if self.kind == "water":
             return inputs.water(self.n_atoms // 3, self.box, self.temp_k, self.seed)
         raise ValueError(self.kind)
+
+    def system(self) -> inputs.System:
+        """The seeded system; systems of a million atoms or more are kept in
+        an on-disk cache (directory P3MZ_INPUT_CACHE, default
+        ~/.cache/p3maze/inputs) so that several processes share one draw."""
+        if self.n_atoms < 1_000_000:
+            return self.generate()
+        d = os.environ.get("P3MZ_INPUT_CACHE") or os.path.join(os.path.expanduser("~"), ".cache", "p3maze", "inputs")
+        path = os.path.join(d, f"{self.name}-seed{self.seed}-{INPUTS_VERSION}.npz")
+        if os.path.exists(path):
+            z = np.load(path, allow_pickle=False)
+            return inputs.System(z["pos"], z["charges"], z["masses"], z["vel"], float(z["box"]), str(z["kind"]))
+        s = self.generate()
+        os.makedirs(d, exist_ok=True)
+        tmp = path + f".{os.getpid()}.tmp.npz"
+        np.savez(tmp, pos=s.pos, charges=s.charges, masses=s.masses, vel=s.vel, box=s.box, kind=s.kind)
+        os.replace(tmp, path)
+        return s
 
 
 def nacl_512() -> Workload:

@@ -157,6 +157,7 @@ struct p3mz_ctx {
   int nc = 1, ncells = 1;
   int *d_ckey = nullptr, *d_cslot = nullptr, *d_ccount = nullptr, *d_cstart = nullptr, *d_cperm_raw = nullptr,
       *d_cperm = nullptr;
+  double* d_spos = nullptr;   // cell-ordered {x, y, z, q} for the pair kernels
   double *d_q = nullptr, *d_qs = nullptr, *d_tmp = nullptr;
   double* d_sigma = nullptr;
   double* d_y[2] = {nullptr, nullptr};   // d_y[0]: multiplier; d_y[1]: FP64 outer residual
@@ -399,6 +400,7 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   P3MZ_TRY(c->alloc(&c->d_cslot, na));
   P3MZ_TRY(c->alloc(&c->d_cperm_raw, na));
   P3MZ_TRY(c->alloc(&c->d_cperm, na));
+  P3MZ_TRY(c->alloc(&c->d_spos, 4 * na));
   P3MZ_TRY(c->alloc(&c->d_ccount, c->ncells));
   P3MZ_TRY(c->alloc(&c->d_cstart, c->ncells + 1));
   P3MZ_HIP_TRY(hipMemset(c->d_ccount, 0, sizeof(int) * c->ncells));
@@ -545,10 +547,11 @@ p3mz_status enq_post2(p3mz_ctx* c, const double* pos, double* force, double* ene
   P3MZ_HIP_TRY(launch_scatter(na, c->d_ckey, c->d_cslot, c->d_cstart, c->d_cperm_raw, s));
   rec_key(6003);
   P3MZ_HIP_TRY(launch_sort_bins(c->ncells, c->d_cstart, c->d_cperm_raw, c->d_cperm, c->d_ctl, s));
+  P3MZ_HIP_TRY(launch_cell_pack(na, c->d_cperm, pos, c->d_qa, c->d_spos, s));
   rec_key(6004);
   kt_begin(KT_SR, 0, s);
   P3MZ_HIP_TRY(launch_sr(na, pos, c->d_qa, c->P.box, c->P.alpha, c->P.r_cut, c->P.coulomb_k, c->nc, c->P.excl_group,
-                         c->d_cstart, c->d_cperm, force, c->e_self, energy ? energy : c->d_energy,
+                         c->d_cstart, c->d_cperm, c->d_spos, force, c->e_self, energy ? energy : c->d_energy,
                          c->d_partial, c->d_ctl, s));
   kt_end(KT_SR, 0, (double)na * 56.0, s);
   rec_key(6005);
@@ -572,7 +575,7 @@ p3mz_status enq_md_post2(p3mz_ctx* c, const MdArgs& m, hipStream_t s) {
   // the cell list of the short-range pass is still valid for these positions
   rec_key(6100);
   P3MZ_HIP_TRY(launch_nonelec(na, m.pos, c->P.box, c->P.r_cut, m.model, m.p[0], m.p[1], m.p[2], m.p[3], m.p[4],
-                              m.p[5], c->nc, c->d_cstart, c->d_cperm, c->d_md_force, c->d_partial, c->d_e_other, s));
+                              m.p[5], c->nc, c->d_cstart, c->d_cperm, c->d_spos, c->d_md_force, c->d_partial, c->d_e_other, s));
   rec_key(6101);
   P3MZ_HIP_TRY(launch_kick_drift(na, m.pos, m.vel, c->d_md_force, m.mass, m.dt, m.f2a, 0, s));
   rec_key(6102);
@@ -1088,7 +1091,7 @@ p3mz_status batch_prepare_compute(p3mz_batch* b, const double* pos, double* forc
       p3mz_ctx* c = b->sys[r];
       rec_key(6100);
       P3MZ_HIP_TRY(launch_nonelec((int)c->n_atoms, X(r), c->P.box, c->P.r_cut, init->model, init->p[0], init->p[1],
-                                  init->p[2], init->p[3], init->p[4], init->p[5], c->nc, c->d_cstart, c->d_cperm,
+                                  init->p[2], init->p[3], init->p[4], init->p[5], c->nc, c->d_cstart, c->d_cperm, c->d_spos,
                                   c->d_md_force, c->d_partial, c->d_e_other, nullptr));
       return P3MZ_OK;
     }));
@@ -1334,7 +1337,7 @@ p3mz_status p3mz_md_run(p3mz_ctx* ctx, double* pos_dev, double* vel_dev, const d
                         (uint64_t)(uintptr_t)ctx->d_energy},
                        false, nullptr));
     P3MZ_HIP_TRY(launch_nonelec((int)ctx->n_atoms, pos_dev, ctx->P.box, ctx->P.r_cut, m.model, m.p[0], m.p[1], m.p[2],
-                                m.p[3], m.p[4], m.p[5], ctx->nc, ctx->d_cstart, ctx->d_cperm, ctx->d_md_force,
+                                m.p[3], m.p[4], m.p[5], ctx->nc, ctx->d_cstart, ctx->d_cperm, ctx->d_spos, ctx->d_md_force,
                                 ctx->d_partial, ctx->d_e_other, s));
     P3MZ_TRY(finish(ctx, s));
     ctx->md_have_force = true;
@@ -1405,10 +1408,33 @@ p3mz_status p3mz_kernel_bench(p3mz_ctx* ctx, int32_t kernel_id, int32_t reps, vo
   P3MZ_HIP_TRY(hipEventRecord(e0, s));
   for (int r = 0; r < reps && st == P3MZ_OK; r++) {
     hipError_t e;
+    const double N3 = (double)ctx->n3, na = (double)ctx->n_atoms, ts = (double)ctx->tsz;
+    const int p = ctx->pl.p, n = ctx->pl.n;
+    const LevelBufs& f = ctx->lv[0];
     if (kernel_id == KT_SMOOTH) {
       e = launch_smooth(true, ctx->pl.n, 0, ctx->smooth_tile, ctx->ntaps, ctx->half, ctx->d_taps, ctx->d_q, ctx->d_tmp,
                         s);
-      bytes = 16.0 * (double)ctx->n3;
+      bytes = 16.0 * N3;
+    } else if (kernel_id == KT_OUTER) {
+      // the cycle form without its finalize pass; y and the FP64 residual are
+      // scratch between steps (the multiplier is kept in the history slots)
+      e = launch_outer(ctx->fp64, n, 0, ctx->P.max_cycles, ctx->d_sigma, ctx->d_y[0], ctx->d_y[1], f.e0, f.e1, f.r0,
+                       f.r1, ctx->d_partial, ctx->d_ctl, s, false);
+      bytes = (32.0 + 2.0 * ts) * N3;
+    } else if (kernel_id == KT_SIGMA) {
+      e = launch_sigma(n, ctx->pl.h, ctx->d_qs, ctx->d_phi[0], ctx->d_phi[1], ctx->d_yh[0], ctx->d_yh[1], ctx->d_yh[2],
+                       ctx->d_sigma, ctx->d_y[0], ctx->P.tol, ctx->P.tol_mode, ctx->d_partial, ctx->d_ctl, s, false);
+      bytes = 64.0 * N3;
+    } else if (kernel_id == KT_SPREAD) {
+      e = launch_spread(true, n, p, kTile, ctx->ntx, ctx->d_start, ctx->d_perm, ctx->d_base, ctx->d_w, ctx->d_qa,
+                        ctx->d_tmp, s);
+      bytes = 8.0 * N3 + na * (24.0 * p + 24.0);
+    } else if (kernel_id == KT_GATHER) {
+      e = launch_gather(ctx->fp64, (int)ctx->n_atoms, n, p, ctx->pl.h, ctx->P.coulomb_k, ctx->d_perm, ctx->d_base,
+                        ctx->d_w, ctx->d_qa, ctx->d_phi[0], ctx->d_phi[1], ctx->d_phi32, nullptr, ctx->d_partial,
+                        ctx->d_ctl, s, false);
+      const double pe = p + 2.0;
+      bytes = na * (48.0 + 24.0 * p + pe * pe * pe * (ctx->fp64 ? 8.0 : 4.0));
     } else {
       e = launch_vcycle_kernel(ctx->fp64, kernel_id, ctx->lv, ctx->pl.levels, ctx->pl.tail, ctx->nu1, ctx->nu2,
                                ctx->d_green, ctx->d_ctl, s, &bytes);

@@ -41,15 +41,19 @@ hipError_t launch_spread(bool fp64, int n, int p, int tile, int ntx, const int* 
 // gradient of phi (precision of phi: fp64 or float).
 // phi: FP64 mode reads the new potential from phi0/phi1 (selected on the
 // device), mixed mode reads the FP32 copy phi32.
+// finalize = false launches the per-atom kernel only (back-to-back timing).
 hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, double h, double k_e, const int* perm,
                          const int* base, const void* w, const double* qa, const double* phi0,
                          const double* phi1, const float* phi32, double* force, double* partial, Ctl* ctl,
-                         hipStream_t s);
+                         hipStream_t s, bool finalize = true);
 // Short-range erfc pairs on the cell list, exclusion correction, energy
 // assembly into energy_out[4] (may be NULL).  force += F_sr.
+// spos[jj] = {x, y, z, q} of atom cperm[jj] (cell order), for the pair kernels.
+hipError_t launch_cell_pack(int n_atoms, const int* cperm, const double* pos, const double* qa, void* spos,
+                            hipStream_t s);
 hipError_t launch_sr(int n_atoms, const double* pos, const double* qa, double box, double alpha,
                      double r_cut, double k_e, int nc, int excl_group, const int* cstart,
-                     const int* cperm, double* force, double e_self, double* energy_out,
+                     const int* cperm, const void* spos, double* force, double e_self, double* energy_out,
                      double* partial, Ctl* ctl, hipStream_t s);
 
 // ---- mesh (mesh.hip) -----------------------------------------------------
@@ -66,13 +70,13 @@ void smooth_tile_shape(int tile, int* lines_per_workgroup, int* outputs_per_thre
 // are selected on the device from the control block.
 hipError_t launch_sigma(int n, double h, const double* qs, const double* phi0, const double* phi1,
                         const double* yb0, const double* yb1, const double* yb2, double* sigma, double* y,
-                        double tol, int tol_mode, double* partial, Ctl* ctl, hipStream_t s);
+                        double tol, int tol_mode, double* partial, Ctl* ctl, hipStream_t s, bool finalize = true);
 // Outer FP64 residual: cycle 0 (first) r = sigma - mean - M y; later cycles
 // y += e, r -= M e; r written colour-split in T for the next V-cycle; the
 // finalize pass records res_hist[c] and the stop decision.
 hipError_t launch_outer(bool fp64, int n, int first, int max_cycles, const double* sigma, double* y, double* r64,
                         const void* e0, const void* e1, void* r0, void* r1, double* partial, Ctl* ctl,
-                        hipStream_t s);
+                        hipStream_t s, bool finalize = true);
 struct LevelBufs {
   int n;
   void* e0; void* e1;   // colour-split correction
@@ -109,7 +113,7 @@ hipError_t launch_kick_drift(int n_atoms, double* pos, double* vel, const double
                              const double* mass, double dt, double f2a, int drift, hipStream_t s);
 hipError_t launch_nonelec(int n_atoms, const double* pos, double box, double r_cut, int model,
                           double p0, double p1, double p2, double p3, double p4, double p5,
-                          int nc, const int* cstart, const int* cperm, double* force,
+                          int nc, const int* cstart, const int* cperm, const void* spos, double* force,
                           double* partial, double* e_out, hipStream_t s);
 // Kinetic energy and one row (ctl->md_step, then advanced) of the logs.
 hipError_t launch_kinetic_log(int n_atoms, const double* vel, const double* mass, double mv2e,

@@ -4,6 +4,7 @@
 
 #include "kern.h"
 #include "launch.h"
+#include "pairs.h"
 
 namespace {
 
@@ -50,6 +51,7 @@ struct NonElec {
     double box, rc2, p0, p1, p2, p3, p4, p5;
     const double* pos;
     const int *cstart, *cperm;
+    const double4* spos;   // cell-ordered {x, y, z, q}
     double *force, *partial;
   };
   static constexpr int kThreads = kBlock;
@@ -64,26 +66,19 @@ __device__ void NonElec::run(const Args& A, Grid G) {
   double* __restrict__ force = A.force;
   double* __restrict__ partial = A.partial;
   __shared__ double sh[kBlock / 64];
+  __shared__ PairQueue queue[kBlock / 64];
   const int lane = threadIdx.x & 63;
   const int nwaves = G.g * (kBlock / 64);
+  PairQueue& Q = queue[threadIdx.x >> 6];
   double en = 0.0;
   for (int wave = (G.b * kBlock + threadIdx.x) >> 6; wave < n_atoms && model != 0; wave += nwaves) {
     double fx = 0.0, fy = 0.0, fz = 0.0;
     const int i = cperm[wave];
     const double inv_box = 1.0 / box;
-    const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
+    const double4 me = A.spos[wave];
+    const double xi = me.x, yi = me.y, zi = me.z;
     const bool pair_atom = model == 1 || (i % 3 == 0);
     if (pair_atom) {
-      int c[3];
-      const double xs[3] = {xi, yi, zi};
-      for (int d = 0; d < 3; d++) {
-        double s = xs[d] * inv_box;
-        s -= floor(s);
-        int ci = (int)(s * nc);
-        c[d] = ci >= nc ? nc - 1 : ci;
-      }
-      const int span = nc >= 3 ? 1 : 0;
-      const int lo = nc >= 3 ? -1 : 0, hi = nc >= 3 ? 1 : nc - 1;
       double shift;
       if (model == 1) {
         shift = p0 * exp(-sqrt(rc2) / p1);
@@ -91,37 +86,29 @@ __device__ void NonElec::run(const Args& A, Grid G) {
         const double s2 = p1 * p1 / rc2, s6 = s2 * s2 * s2;
         shift = 4.0 * p0 * (s6 * s6 - s6);
       }
-      for (int oz = lo; oz <= hi; oz++)
-        for (int oy = lo; oy <= hi; oy++)
-          for (int ox = lo; ox <= hi; ox++) {
-            const int cx = span ? (c[0] + ox + nc) % nc : ox;
-            const int cy = span ? (c[1] + oy + nc) % nc : oy;
-            const int cz = span ? (c[2] + oz + nc) % nc : oz;
-            const int cell = (cz * nc + cy) * nc + cx;
-            for (int jj = cstart[cell] + lane; jj < cstart[cell + 1]; jj += 64) {
-              const int j = cperm[jj];
-              if (j == i) continue;
-              if (model == 2 && (j % 3 != 0 || j / 3 == i / 3)) continue;
-              const double dx = mi(xi - pos[3 * j], box, inv_box);
-              const double dy = mi(yi - pos[3 * j + 1], box, inv_box);
-              const double dz = mi(zi - pos[3 * j + 2], box, inv_box);
-              const double r2 = dx * dx + dy * dy + dz * dz;
-              if (r2 >= rc2) continue;
-              double f;
-              if (model == 1) {
-                const double r = sqrt(r2);
-                const double v = p0 * exp(-r / p1);
-                f = v / p1 / r;
-                en += 0.5 * (v - shift);
-              } else {
-                const double sr2 = p1 * p1 / r2;
-                const double sr6 = sr2 * sr2 * sr2;
-                f = 24.0 * p0 * (2.0 * sr6 * sr6 - sr6) / r2;
-                en += 0.5 * (4.0 * p0 * (sr6 * sr6 - sr6) - shift);
-              }
-              fx += f * dx; fy += f * dy; fz += f * dz;
+      for_each_pair(
+          wave, xi, yi, zi, box, nc, cstart, A.spos, Q,
+          [&](int jj, double r2) {
+            if (!(r2 < rc2)) return false;
+            if (model == 1) return true;
+            const int j = cperm[jj];
+            return j % 3 == 0 && j / 3 != i / 3;
+          },
+          [&](double dx, double dy, double dz, double r2, double) {
+            double f;
+            if (model == 1) {
+              const double r = sqrt(r2);
+              const double v = p0 * exp(-r / p1);
+              f = v / p1 / r;
+              en += 0.5 * (v - shift);
+            } else {
+              const double sr2 = p1 * p1 / r2;
+              const double sr6 = sr2 * sr2 * sr2;
+              f = 24.0 * p0 * (2.0 * sr6 * sr6 - sr6) / r2;
+              en += 0.5 * (4.0 * p0 * (sr6 * sr6 - sr6) - shift);
             }
-          }
+            fx += f * dx; fy += f * dy; fz += f * dz;
+          });
     }
     if (model == 2 && lane == 0) {
       const int o = (i / 3) * 3;
@@ -249,10 +236,11 @@ hipError_t launch_kick_drift(int n_atoms, double* pos, double* vel, const double
 
 hipError_t launch_nonelec(int n_atoms, const double* pos, double box, double r_cut, int model, double p0,
                           double p1, double p2, double p3, double p4, double p5, int nc, const int* cstart,
-                          const int* cperm, double* force, double* partial, double* e_out, hipStream_t s) {
+                          const int* cperm, const void* spos, double* force, double* partial, double* e_out,
+                          hipStream_t s) {
   const int nb = std::min(blocks_for((int64_t)n_atoms * 64, kBlock), kPartialSlots);
   hipError_t e = go<NonElec>({n_atoms, model, nc, box, r_cut * r_cut, p0, p1, p2, p3, p4, p5, pos, cstart, cperm,
-                              force, partial}, nb, 0, s);
+                              (const double4*)spos, force, partial}, nb, 0, s);
   if (e != hipSuccess) return e;
   return go<FinOther>({nb, partial, e_out}, 1, 0, s);
 }

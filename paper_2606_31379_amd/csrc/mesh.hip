@@ -1176,15 +1176,16 @@ hipError_t smooth_configure(int n) {
 
 hipError_t launch_sigma(int n, double h, const double* qs, const double* phi0, const double* phi1,
                         const double* yb0, const double* yb1, const double* yb2, double* sigma, double* y,
-                        double tol, int tol_mode, double* partial, Ctl* ctl, hipStream_t s) {
+                        double tol, int tol_mode, double* partial, Ctl* ctl, hipStream_t s, bool finalize) {
   const int n3 = n * n * n, nb = red_blocks(n3);
   P3MZ_LAUNCH(go<Sigma<double>>({n, h, qs, phi0, phi1, yb0, yb1, yb2, sigma, y, partial, ctl}, nb, 0, s));
+  if (!finalize) return hipSuccess;
   return go<FinSigma>({nb, n3, tol_mode, tol, partial, ctl}, 1, 0, s);
 }
 
 hipError_t launch_outer(bool fp64, int n, int first, int max_cycles, const double* sigma, double* y, double* r64,
                         const void* e0, const void* e1, void* r0, void* r1, double* partial, Ctl* ctl,
-                        hipStream_t s) {
+                        hipStream_t s, bool finalize) {
   const int n3 = n * n * n, nb = red_blocks(n3);
   if (fp64)
     P3MZ_LAUNCH(go<Outer<double>>({n, first, sigma, y, r64, (const double*)e0, (const double*)e1, (double*)r0,
@@ -1192,6 +1193,7 @@ hipError_t launch_outer(bool fp64, int n, int first, int max_cycles, const doubl
   else
     P3MZ_LAUNCH(go<Outer<float>>({n, first, sigma, y, r64, (const float*)e0, (const float*)e1, (float*)r0,
                                   (float*)r1, partial, ctl}, nb, 0, s));
+  if (!finalize) return hipSuccess;
   return go<FinOuter>({first, max_cycles, nb, n3, partial, ctl}, 1, 0, s);
 }
 

@@ -4,6 +4,7 @@
 
 #include "kern.h"
 #include "launch.h"
+#include "pairs.h"
 
 namespace {
 
@@ -277,11 +278,13 @@ __device__ void SortBins::run(const Args& A, Grid G) {
 
 // Owner-computes spread.  One workgroup per TS^3 tile of the mesh; atoms are
 // keyed by the tile holding their first stencil index, so only the tile
-// itself and its lower neighbours (per axis) can reach it.  Each wave adds
-// whole atoms, one stencil point per lane, into its own LDS copy of the tile
-// (lanes of one atom touch distinct points), in the fixed order of the
-// sorted bins; the four wave copies are then summed in a fixed order.  No
-// global atomics, bitwise-reproducible.
+// itself and its lower neighbours (per axis) can reach it.  The candidate
+// atoms of those bins (fixed order: bins, then sorted atoms) are staged in
+// LDS in chunks, one atom record per thread (stencil origin, charge,
+// weights), so their global loads are independent.  Each wave then adds
+// whole atoms from LDS, one stencil point per lane, into its own LDS copy of
+// the tile (lanes of one atom touch distinct points); the four wave copies
+// are summed in a fixed order.  No global atomics, bitwise-reproducible.
 template <typename T, int TS>
 struct Spread {
   struct Args {
@@ -292,10 +295,12 @@ struct Spread {
     T* q;
   };
   static constexpr int kThreads = kBlock;
+  static constexpr int kChunk = 128;   // staged atoms per round
   __device__ static void run(const Args& A, Grid G);
 };
 template <typename T, int TS>
 __device__ void Spread<T, TS>::run(const Args& A, Grid G) {
+  constexpr int V = TS * TS * TS, CH = kChunk, MW = 3 * P3MZ_MAX_ORDER;
   const int n = A.n, p = A.p, ntx = A.ntx;
   const int* __restrict__ start = A.start;
   const int* __restrict__ perm = A.perm;
@@ -303,44 +308,118 @@ __device__ void Spread<T, TS>::run(const Args& A, Grid G) {
   const T* __restrict__ w = A.w;
   const double* __restrict__ qa = A.qa;
   T* __restrict__ q = A.q;
-  constexpr int V = TS * TS * TS;
   __shared__ T acc[kBlock / 64][V];
+  __shared__ T sw[CH][MW];       // weights x | y | z of each staged atom
+  __shared__ T sq[CH];
+  __shared__ int sb[CH][3];      // stencil origin
+  __shared__ int bin_lo[8], bin_off[9];
   const int t = G.b;
   const int tx = t % ntx, ty = (t / ntx) % ntx, tz = t / (ntx * ntx);
   const int ox = tx * TS, oy = ty * TS, oz = tz * TS;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int i = threadIdx.x; i < (kBlock / 64) * V; i += kBlock) (&acc[0][0])[i] = T(0);
+  if (threadIdx.x == 0) {
+    const int nd = ntx > 1 ? 2 : 1;
+    int off = 0, k = 0;
+    for (int dz = 0; dz < nd; dz++)
+      for (int dy = 0; dy < nd; dy++)
+        for (int dx = 0; dx < nd; dx++, k++) {
+          int sx = tx - dx, sy = ty - dy, sz = tz - dz;
+          sx += sx < 0 ? ntx : 0;
+          sy += sy < 0 ? ntx : 0;
+          sz += sz < 0 ? ntx : 0;
+          const int b = (sz * ntx + sy) * ntx + sx;
+          bin_lo[k] = start[b];
+          bin_off[k] = off;
+          off += start[b + 1] - start[b];
+        }
+    for (; k < 8; k++) {
+      bin_lo[k] = 0;
+      bin_off[k] = off;
+    }
+    bin_off[8] = off;
+  }
   __syncthreads();
-  const int nd = ntx > 1 ? 2 : 1;
+  const int total = bin_off[8];
   const int p2 = p * p, p3 = p2 * p;
-  for (int dz = 0; dz < nd; dz++)
-    for (int dy = 0; dy < nd; dy++)
-      for (int dx = 0; dx < nd; dx++) {
-        int sx = tx - dx, sy = ty - dy, sz = tz - dz;
-        sx += sx < 0 ? ntx : 0;
-        sy += sy < 0 ? ntx : 0;
-        sz += sz < 0 ? ntx : 0;
-        const int sb = (sz * ntx + sy) * ntx + sx;
-        const int a0 = start[sb], a1 = start[sb + 1];
-        for (int j = a0 + wv; j < a1; j += kBlock / 64) {
-          const int a = perm[j];
-          const int bx = base[3 * a], by = base[3 * a + 1], bz = base[3 * a + 2];
-          const T qv = (T)qa[a];
-          for (int l = lane; l < p3; l += 64) {
-            const int ax = l % p, ay = (l / p) % p, az = l / p2;
-            int gx = bx + ax, gy = by + ay, gz = bz + az;
-            gx -= gx >= n ? n : 0;
-            gy -= gy >= n ? n : 0;
-            gz -= gz >= n ? n : 0;
-            const int lx = gx - ox, ly = gy - oy, lz = gz - oz;
-            if ((unsigned)lx < (unsigned)TS && (unsigned)ly < (unsigned)TS && (unsigned)lz < (unsigned)TS) {
-              const T c = qv * w[(3 * a) * p + ax] * w[(3 * a + 1) * p + ay] * w[(3 * a + 2) * p + az];
-              acc[wv][(lz * TS + ly) * TS + lx] += c;
-            }
-          }
+  // this lane's stencil points of an atom, l = lane + 64 it (fixed for the
+  // whole kernel; p^3 <= 343 needs up to 6 per lane)
+  constexpr int kMaxIt = (P3MZ_MAX_ORDER * P3MZ_MAX_ORDER * P3MZ_MAX_ORDER + 63) / 64;
+  int sax[kMaxIt], say[kMaxIt], saz[kMaxIt];
+  const int n_it = (p3 + 63) / 64;
+#pragma unroll
+  for (int it = 0; it < kMaxIt; it++) {
+    const int l = lane + 64 * it;
+    sax[it] = l % p;
+    say[it] = (l / p) % p;
+    saz[it] = l / p2;
+  }
+  __shared__ int n_keep;
+  for (int c0 = 0; c0 < total; c0 += CH) {
+    const int m = min(CH, total - c0);
+    if (threadIdx.x == 0) n_keep = 0;
+    __syncthreads();
+    // stage the chunk's atoms whose stencil reaches this tile (the others sit
+    // in a lower neighbour bin too far from the shared face)
+    bool keep = false;
+    int a = 0, b3[3] = {0, 0, 0};
+    if ((int)threadIdx.x < m) {
+      const int c = c0 + threadIdx.x;
+      int k = 0;
+      while (c >= bin_off[k + 1]) k++;
+      a = perm[bin_lo[k] + (c - bin_off[k])];
+      b3[0] = base[3 * a];
+      b3[1] = base[3 * a + 1];
+      b3[2] = base[3 * a + 2];
+      const int o3[3] = {ox, oy, oz};
+      keep = true;
+      for (int d = 0; d < 3; d++) {
+        int rel = b3[d] - o3[d];              // stencil start relative to the tile, mod n
+        rel += rel < 0 ? n : 0;
+        // reaches the tile iff some point rel + t (t < p) lies in [0, TS) mod n
+        keep &= rel < TS || rel + p - 1 >= n;
+      }
+    }
+    // keep the chunk order: rank of this thread among the kept ones
+    const unsigned long long bal = __ballot(keep);
+    __shared__ int wave_cnt[kBlock / 64];
+    if (lane == 0) wave_cnt[wv] = __popcll(bal);
+    __syncthreads();
+    int slot = __popcll(bal & ((1ull << lane) - 1ull));
+    for (int k = 0; k < wv; k++) slot += wave_cnt[k];
+    if (keep) {
+      sb[slot][0] = b3[0];
+      sb[slot][1] = b3[1];
+      sb[slot][2] = b3[2];
+      sq[slot] = (T)qa[a];
+      for (int j = 0; j < 3 * p; j++) sw[slot][j] = w[3 * a * p + j];
+    }
+    if (threadIdx.x == 0) {
+      int tot = 0;
+      for (int k = 0; k < kBlock / 64; k++) tot += wave_cnt[k];
+      n_keep = tot;
+    }
+    __syncthreads();
+    const int mk = n_keep;
+    for (int i = wv; i < mk; i += kBlock / 64) {
+      const int bx = sb[i][0], by = sb[i][1], bz = sb[i][2];
+#pragma unroll
+      for (int it = 0; it < kMaxIt; it++) {
+        if (it >= n_it || lane + 64 * it >= p3) break;
+        const int ax = sax[it], ay = say[it], az = saz[it];
+        int gx = bx + ax, gy = by + ay, gz = bz + az;
+        gx -= gx >= n ? n : 0;
+        gy -= gy >= n ? n : 0;
+        gz -= gz >= n ? n : 0;
+        const int lx = gx - ox, ly = gy - oy, lz = gz - oz;
+        if ((unsigned)lx < (unsigned)TS && (unsigned)ly < (unsigned)TS && (unsigned)lz < (unsigned)TS) {
+          const T c = sq[i] * sw[i][ax] * sw[i][p + ay] * sw[i][2 * p + az];
+          acc[wv][(lz * TS + ly) * TS + lx] += c;
         }
       }
-  __syncthreads();
+    }
+    __syncthreads();
+  }
   for (int i = threadIdx.x; i < V; i += kBlock) {
     T s = acc[0][i];
     for (int k = 1; k < kBlock / 64; k++) s += acc[k][i];
@@ -481,6 +560,24 @@ __device__ void FinEnergy::run(const Args& A, Grid) {
   }
 }
 
+// Cell-ordered packed copy of the atoms, {x, y, z, q} per entry, for the
+// pair kernels' coalesced candidate loads.
+struct CellPack {
+  struct Args {
+    int n_atoms;
+    const int* cperm;
+    const double *pos, *qa;
+    double4* spos;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G) {
+    const int jj = G.b * kBlock + threadIdx.x;
+    if (jj >= A.n_atoms) return;
+    const int a = A.cperm[jj];
+    A.spos[jj] = make_double4(A.pos[3 * a], A.pos[3 * a + 1], A.pos[3 * a + 2], A.qa[a]);
+  }
+};
+
 // Short-range pairs (Eq. 20 force, Eq. 6 energy) over the cell list with the
 // minimum image; pairs inside one exclusion group instead get the Ewald
 // exclusion correction -k Q Q erf(alpha r)/r.  One wave per atom: lanes take
@@ -492,6 +589,7 @@ struct ShortRange {
     double box, alpha, rc2, k_e;
     const double *pos, *qa;
     const int *cstart, *cperm;
+    const double4* spos;   // cell-ordered {x, y, z, q}
     double *force, *partial;
   };
   static constexpr int kThreads = kBlock;
@@ -507,53 +605,32 @@ __device__ void ShortRange::run(const Args& A, Grid G) {
   double* __restrict__ force = A.force;
   double* __restrict__ partial = A.partial;
   __shared__ double sh[kBlock / 64];
+  __shared__ PairQueue queue[kBlock / 64];
   const int lane = threadIdx.x & 63;
   const int nwaves = G.g * (kBlock / 64);
+  PairQueue& Q = queue[threadIdx.x >> 6];
   double en = 0.0;
+  const double4* __restrict__ spos = A.spos;
   for (int wave = (G.b * kBlock + threadIdx.x) >> 6; wave < n_atoms; wave += nwaves) {
     double fx = 0.0, fy = 0.0, fz = 0.0;
     const int i = cperm[wave];
-    const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
-    const double qi = qa[i];
+    const double4 me = spos[wave];
+    const double xi = me.x, yi = me.y, zi = me.z;
+    const double qi = me.w;
     const double inv_box = 1.0 / box;
     const double tapi = 2.0 * alpha / sqrt(M_PI);
-    int c[3];
-    const double xs[3] = {xi, yi, zi};
-    for (int d = 0; d < 3; d++) {
-      double s = xs[d] * inv_box;
-      s -= floor(s);
-      int ci = (int)(s * nc);
-      c[d] = ci >= nc ? nc - 1 : ci;
-    }
     const int gi = excl_group > 0 ? i / excl_group : -1;
-    const int span = nc >= 3 ? 1 : 0;
-    const int lo = nc >= 3 ? -1 : 0, hi = nc >= 3 ? 1 : nc - 1;
-    for (int oz = lo; oz <= hi; oz++)
-      for (int oy = lo; oy <= hi; oy++)
-        for (int ox = lo; ox <= hi; ox++) {
-          const int cx = span ? (c[0] + ox + nc) % nc : ox;
-          const int cy = span ? (c[1] + oy + nc) % nc : oy;
-          const int cz = span ? (c[2] + oz + nc) % nc : oz;
-          const int cell = (cz * nc + cy) * nc + cx;
-          const int j0 = cstart[cell], j1 = cstart[cell + 1];
-          for (int jj = j0 + lane; jj < j1; jj += 64) {
-            const int j = cperm[jj];
-            if (j == i) continue;
-            if (gi >= 0 && j / excl_group == gi) continue;
-            double dx = xi - pos[3 * j], dy = yi - pos[3 * j + 1], dz = zi - pos[3 * j + 2];
-            dx -= box * rint(dx * inv_box);
-            dy -= box * rint(dy * inv_box);
-            dz -= box * rint(dz * inv_box);
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 >= rc2) continue;
-            const double r = sqrt(r2);
-            const double ec = erfc(alpha * r);
-            const double qq = k_e * qi * qa[j];
-            const double f = qq * (ec / (r2 * r) + tapi * exp(-alpha * alpha * r2) / r2);
-            fx += f * dx; fy += f * dy; fz += f * dz;
-            en += 0.5 * qq * ec / r;
-          }
-        }
+    for_each_pair(
+        wave, xi, yi, zi, box, nc, cstart, spos, Q,
+        [&](int jj, double r2) { return r2 < rc2 && !(gi >= 0 && cperm[jj] / excl_group == gi); },
+        [&](double dx, double dy, double dz, double r2, double qj) {
+          const double r = sqrt(r2);
+          const double ec = erfc(alpha * r);
+          const double qq = k_e * qi * qj;
+          const double f = qq * (ec / (r2 * r) + tapi * exp(-alpha * alpha * r2) / r2);
+          fx += f * dx; fy += f * dy; fz += f * dz;
+          en += 0.5 * qq * ec / r;
+        });
     if (gi >= 0 && lane < excl_group) {
       const int j = gi * excl_group + lane;
       if (j != i && j < n_atoms) {
@@ -642,7 +719,7 @@ hipError_t launch_spread(bool fp64, int n, int p, int tile, int ntx, const int* 
 hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, double h, double k_e, const int* perm,
                          const int* base, const void* w, const double* qa, const double* phi0,
                          const double* phi1, const float* phi32, double* force, double* partial, Ctl* ctl,
-                         hipStream_t s) {
+                         hipStream_t s, bool finalize) {
   const int nb = std::min(blocks_for(n_atoms, kBlock), kMaxRedBlocks);
   hipError_t e;
   if (fp64)
@@ -651,17 +728,22 @@ hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, double h, double 
   else
     e = go<Gather<float, float>>({n_atoms, n, p, h, k_e, perm, base, (const double*)w, qa, phi32, phi32, force,
                                   partial, ctl}, nb, 0, s);
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !finalize) return e;
   return go<FinSum>({nb, partial, &ctl->e_lr}, 1, 0, s);
+}
+
+hipError_t launch_cell_pack(int n_atoms, const int* cperm, const double* pos, const double* qa, void* spos,
+                            hipStream_t s) {
+  return go<CellPack>({n_atoms, cperm, pos, qa, (double4*)spos}, blocks_for(n_atoms, kBlock), 0, s);
 }
 
 hipError_t launch_sr(int n_atoms, const double* pos, const double* qa, double box, double alpha,
                      double r_cut, double k_e, int nc, int excl_group, const int* cstart,
-                     const int* cperm, double* force, double e_self, double* energy_out,
+                     const int* cperm, const void* spos, double* force, double e_self, double* energy_out,
                      double* partial, Ctl* ctl, hipStream_t s) {
   const int nb = std::min(blocks_for((int64_t)n_atoms * 64, kBlock), kPartialSlots);
   hipError_t e = go<ShortRange>({n_atoms, nc, excl_group, box, alpha, r_cut * r_cut, k_e, pos, qa, cstart, cperm,
-                                 force, partial}, nb, 0, s);
+                                 (const double4*)spos, force, partial}, nb, 0, s);
   if (e != hipSuccess) return e;
   return go<FinEnergy>({nb, e_self, partial, ctl, energy_out}, 1, 0, s);
 }

@@ -69,10 +69,13 @@ def hard_core_points(rng: np.random.Generator, n: int, box: float, dmin: float,
     candidates, drops those within ``dmin`` (minimum image) of a point
     accepted in an earlier round, and of every conflicting pair inside the
     batch keeps only the lower-indexed candidate.  Accepted points keep their
-    draw order.  One KD-tree is built per round over that round's points.
+    draw order.  The first test queries a KD-tree over most accepted points
+    (rebuilt now and then) and small trees over the latest rounds' points.
     """
     chunks: list[np.ndarray] = []
-    trees: list[cKDTree] = []
+    big, big_n = None, 0      # tree over the first big_n accepted points
+    recent: list[cKDTree] = []   # one small tree per later round
+    recent_n = 0
     have = 0
     for _ in range(max_rounds):
         need = n - have
@@ -82,7 +85,10 @@ def hard_core_points(rng: np.random.Generator, n: int, box: float, dmin: float,
         cand = rng.uniform(0.0, box, size=(m, 3))
         cand = np.minimum(cand, np.nextafter(box, 0.0))
         ok = np.ones(m, dtype=bool)
-        for tree in trees:
+        if big is not None:
+            d, _ = big.query(cand, k=1, distance_upper_bound=dmin, workers=-1)
+            ok[d < dmin] = False
+        for tree in recent:
             idx = np.nonzero(ok)[0]
             if idx.size == 0:
                 break
@@ -100,8 +106,13 @@ def hard_core_points(rng: np.random.Generator, n: int, box: float, dmin: float,
         new = cand[idx[:need]]
         if new.shape[0]:
             chunks.append(new)
-            trees.append(cKDTree(new, boxsize=box))
             have += new.shape[0]
+            recent_n += new.shape[0]
+            if big is None or recent_n > big_n // 4 or len(recent) >= 16:
+                big, big_n = cKDTree(np.concatenate(chunks, axis=0), boxsize=box), have
+                recent, recent_n = [], 0
+            else:
+                recent.append(cKDTree(new, boxsize=box))
     if have < n:
         raise RuntimeError(f"could not place {n} points with separation {dmin} in box {box}")
     return np.concatenate(chunks, axis=0)
@@ -167,16 +178,16 @@ def water(n_mol: int, box: float, temp_k: float, seed: int, r_oh: float = 1.0,
             pairs = pairs[mol_id[pairs[:, 0]] != mol_id[pairs[:, 1]]] if pairs.size else pairs
             bad = np.unique(mol_id[pairs.ravel()]) if pairs.size else np.zeros(0, dtype=int)
         else:
+            # contacts of the re-drawn molecules: the nearest atoms of each of
+            # their atoms (an atom has at most a handful within d_inter, its
+            # own molecule included, so 8 neighbours see every contact)
             atoms = (3 * check[:, None] + np.arange(3)[None, :]).ravel()
-            hits = tree.query_ball_point(flat[atoms], d_inter, return_sorted=False)
-            found = set()
-            for a, lst in zip(atoms, hits):
-                ma = mol_id[a]
-                for b in lst:
-                    if mol_id[b] != ma:
-                        found.add(int(ma))
-                        found.add(int(mol_id[b]))
-            bad = np.array(sorted(found), dtype=int)
+            d, nb = tree.query(flat[atoms], k=8, distance_upper_bound=d_inter, workers=-1)
+            hit = d < d_inter
+            nb = np.where(hit, nb, 0)
+            foreign = hit & (mol_id[nb] != mol_id[atoms][:, None])
+            rows, cols = np.nonzero(foreign)
+            bad = np.unique(np.concatenate([mol_id[atoms[rows]], mol_id[nb[rows, cols]]]))
         if bad.size == 0:
             break
         rot[bad] = _random_rotations(rng, bad.size)

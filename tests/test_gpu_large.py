@@ -1,0 +1,79 @@
+"""GPU parity at the full sizes of the linear-scaling water sweep (24,000 /
+192,000 / 1,536,000 atoms on 64^3 / 128^3 / 256^3) and of the large water
+system (7,999,998 atoms on 512^3, order 5), in the launch configuration the
+benchmark times (captured graphs).
+
+The oracle computes the whole mesh step (assignment, smoothing, the V-cycle
+solve, gather) for every atom, but the all-pairs short-range sum only for a
+seeded sample of atoms; forces are compared on that sample, V-cycle counts
+and the long-range energy on the whole system.  The 512^3 case needs several
+minutes of CPU time for the oracle and runs when P3MZ_FULL_SIZE=1.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2606_31379_amd import configs
+
+from .gpu_util import K_E, GpuCtx, params_pair, rel_rms
+
+pytestmark = pytest.mark.gpu
+
+FP64_BAR = 1e-10
+MIXED_BAR = 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no HIP device")
+    return _t
+
+
+def sampled_parity(torch, w, precisions, steps, sample=512):
+    s = w.system()
+    rng = np.random.Generator(np.random.PCG64(w.seed + 17))
+    targets = np.sort(rng.choice(s.n, size=sample, replace=False))
+    traj = [s.pos + k * w.dt_fs * s.vel for k in range(steps)]
+    _, op = params_pair(w.box, w.alpha, w.r_cut, w.mesh, w.order, tol=w.tol, k_e=K_E, excl_group=w.excl_group)
+    o = O.Oracle(op, s.charges)
+    o.set_sr_targets(targets)
+    ref = []
+    for x in traj:
+        f, e, _ = o.compute(x)
+        st = o.stats()
+        ref.append((f[targets], st.cycles, e[1]))
+        print(f"oracle {w.name}: cycles {st.cycles} solve {st.t_solve:.1f}s", flush=True)
+    o.close()
+    for precision in precisions:
+        gp, _ = params_pair(w.box, w.alpha, w.r_cut, w.mesh, w.order, tol=w.tol, precision=precision, k_e=K_E,
+                            excl_group=w.excl_group)
+        g = GpuCtx(gp, s.charges, torch)
+        bar = FP64_BAR if precision == 0 else MIXED_BAR
+        try:
+            for k, x in enumerate(traj):
+                fg, eg, _ = g.compute(x)
+                st = g.stats()
+                assert st.graphs == 1
+                fr, cyc, e_lr = ref[k]
+                err = rel_rms(fg[targets], fr)
+                print(f"gpu {w.name} precision {precision} step {k}: cycles {st.cycles} err {err:.2e}", flush=True)
+                assert err <= bar, (k, err)
+                assert st.cycles == cyc, (k, st.cycles, cyc)
+                assert abs(eg[1] - e_lr) <= bar * abs(e_lr), k
+        finally:
+            g.close()
+
+
+@pytest.mark.parametrize("i", [0, 1, 2])
+def test_water_sweep_full_size(torch, i):
+    sampled_parity(torch, configs.water_sweep(i), [0, 1] if i < 2 else [1, 0], steps=3)
+
+
+@pytest.mark.slow
+@pytest.mark.skipif(os.environ.get("P3MZ_FULL_SIZE") != "1", reason="minutes of oracle time; set P3MZ_FULL_SIZE=1")
+def test_large_water_512_full_size(torch):
+    sampled_parity(torch, configs.water_large(), [1], steps=2, sample=1000)
