@@ -519,7 +519,7 @@ def main():
         return main_batch(args, torch, P, configs.nacl_batch_64())
     w = configs.WORKLOADS[args.workload]()
     log(f"workload {w.name}: generating inputs")
-    system = w.system()
+    system = w.system(progress=lambda msg: log(f"[inputs] {msg}"))
     log(f"atoms {system.n} box {system.box} mesh {w.mesh}^3 order {w.order} tol {w.tol}")
     ceiling = copy_ceiling_gbps(torch)
     log(f"device copy ceiling {ceiling:.0f} GB/s")

@@ -63,7 +63,8 @@ typedef enum { P3MZ_PREC_FP64 = 0, P3MZ_PREC_MIXED = 1 } p3mz_precision;
 typedef struct {
   double box;          /* cubic edge L > 0                                             */
   double alpha;        /* Ewald splitting > 0; Gaussian width sigma = 1/(sqrt(2) alpha) */
-  double r_cut;        /* real-space cutoff R_c, 0 < R_c <= L/2 (minimum image)        */
+  double r_cut;        /* real-space cutoff R_c, 0 < R_c <= L/2 (minimum image),
+                          alpha * R_c <= 32                                            */
   int32_t mesh;        /* N points per edge, N = 4*2^m, 1 <= m <= 7 (8, 16, ..., 512)   */
   int32_t order;       /* B-spline order p, 2..7 (the paper uses cubic, p = 4)          */
   double tol;          /* residual tolerance > 0                                        */

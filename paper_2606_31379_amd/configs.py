@@ -36,14 +36,14 @@ class Workload:
     predictor: int = 3
     excl_group: int = 0     # 3 for water: O,H,H of one molecule are excluded pairs
 
-    def generate(self) -> inputs.System:
+    def generate(self, progress=None) -> inputs.System:
         if self.kind == "nacl":
             return inputs.nacl(self.n_atoms, self.box, self.temp_k, self.seed)
         if self.kind == "water":
-            return inputs.water(self.n_atoms // 3, self.box, self.temp_k, self.seed)
+            return inputs.water(self.n_atoms // 3, self.box, self.temp_k, self.seed, progress=progress)
         raise ValueError(self.kind)
 
-    def system(self) -> inputs.System:
+    def system(self, progress=None) -> inputs.System:
         """The seeded system; systems of a million atoms or more are kept in
         an on-disk cache (directory P3MZ_INPUT_CACHE, default
         ~/.cache/p3maze/inputs) so that several processes share one draw."""
@@ -54,7 +54,7 @@ class Workload:
         if os.path.exists(path):
             z = np.load(path, allow_pickle=False)
             return inputs.System(z["pos"], z["charges"], z["masses"], z["vel"], float(z["box"]), str(z["kind"]))
-        s = self.generate()
+        s = self.generate(progress)
         os.makedirs(d, exist_ok=True)
         tmp = path + f".{os.getpid()}.tmp.npz"
         np.savez(tmp, pos=s.pos, charges=s.charges, masses=s.masses, vel=s.vel, box=s.box, kind=s.kind)

@@ -46,6 +46,8 @@ struct Plan {
 p3mz_status make_plan(const p3mz_params& P, Plan* pl) {
   if (!(P.box > 0) || !(P.alpha > 0) || !(P.r_cut > 0) || P.r_cut > 0.5 * P.box)
     return fail(P3MZ_ERR_INVALID_ARG, "box, alpha and r_cut must be positive with r_cut <= box/2");
+  if (P.alpha * P.r_cut > 0.25 * kErfcMaxIntervals)
+    return fail(P3MZ_ERR_INVALID_ARG, "alpha * r_cut must be <= 32 (the real-space term would vanish)");
   if (P.order < 2 || P.order > P3MZ_MAX_ORDER) return fail(P3MZ_ERR_INVALID_ARG, "order must be in 2..7");
   if (!(P.tol > 0) || P.tol_mode < 0 || P.tol_mode > 1) return fail(P3MZ_ERR_INVALID_ARG, "bad tolerance");
   if (P.max_cycles < 0 || P.max_cycles > P3MZ_MAX_CYCLES) return fail(P3MZ_ERR_INVALID_ARG, "max_cycles must be in 0..64");
@@ -97,6 +99,37 @@ void smoothing_taps(int n, int K, double nu, std::vector<double>* taps, int* hal
     }
     *half = 0;
   }
+}
+
+// Piecewise Chebyshev interpolant of erfcx(x) = exp(x^2) erfc(x) on [0, X]
+// (intervals of width <= 1/4, degree kErfcDeg, values from long-double
+// erfcl/expl at the Chebyshev nodes); the pair kernel forms
+// erfc(x) = exp(-x^2) erfcx(x) from it.  Returns 0 intervals when X needs
+// more than the kernel's table holds (parameters are validated against that).
+int build_erfcx_table(double X, std::vector<double>* tab, double* scale) {
+  int n = std::max(1, (int)ceil(X / 0.25));
+  if (n > kErfcMaxIntervals) return 0;
+  const double w = X / n;
+  const int m = kErfcDeg + 1;
+  tab->assign((size_t)n * m, 0.0);
+  for (int i = 0; i < n; i++) {
+    const long double a = (long double)i * w, b = a + w;
+    long double f[kErfcDeg + 1];
+    for (int k = 0; k < m; k++) {
+      const long double th = (long double)M_PI * (k + 0.5L) / m;
+      const long double x = 0.5L * (a + b) + 0.5L * (b - a) * cosl(th);
+      f[k] = expl(x * x) * erfcl(x);
+    }
+    for (int j = 0; j < m; j++) {
+      long double c = 0.0L;
+      for (int k = 0; k < m; k++) c += f[k] * cosl((long double)M_PI * j * (k + 0.5L) / m);
+      c *= 2.0L / m;
+      if (j == 0) c *= 0.5L;
+      (*tab)[(size_t)i * m + j] = (double)c;
+    }
+  }
+  *scale = n / X;
+  return n;
 }
 
 // Periodic Green's function of M on the 4^3 mesh with the constant mode
@@ -158,6 +191,9 @@ struct p3mz_ctx {
   int *d_ckey = nullptr, *d_cslot = nullptr, *d_ccount = nullptr, *d_cstart = nullptr, *d_cperm_raw = nullptr,
       *d_cperm = nullptr;
   double* d_spos = nullptr;   // cell-ordered {x, y, z, q} for the pair kernels
+  double* d_erfc = nullptr;   // erfcx table of the pair kernel
+  int erfc_n = 0;
+  double erfc_scale = 0.0;
   double *d_q = nullptr, *d_qs = nullptr, *d_tmp = nullptr;
   double* d_sigma = nullptr;
   double* d_y[2] = {nullptr, nullptr};   // d_y[0]: multiplier; d_y[1]: FP64 outer residual
@@ -401,6 +437,12 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   P3MZ_TRY(c->alloc(&c->d_cperm_raw, na));
   P3MZ_TRY(c->alloc(&c->d_cperm, na));
   P3MZ_TRY(c->alloc(&c->d_spos, 4 * na));
+  {
+    std::vector<double> tab;
+    c->erfc_n = build_erfcx_table(c->P.alpha * c->P.r_cut, &tab, &c->erfc_scale);
+    P3MZ_TRY(c->alloc(&c->d_erfc, std::max<size_t>(tab.size(), 1)));
+    if (!tab.empty()) P3MZ_HIP_TRY(hipMemcpy(c->d_erfc, tab.data(), tab.size() * 8, hipMemcpyHostToDevice));
+  }
   P3MZ_TRY(c->alloc(&c->d_ccount, c->ncells));
   P3MZ_TRY(c->alloc(&c->d_cstart, c->ncells + 1));
   P3MZ_HIP_TRY(hipMemset(c->d_ccount, 0, sizeof(int) * c->ncells));
@@ -529,10 +571,12 @@ p3mz_status enq_post1(p3mz_ctx* c, double* force, hipStream_t s) {
   stage(c, 2, s);
   rec_key(5001);
   kt_begin(KT_GATHER, 0, s);
-  P3MZ_HIP_TRY(launch_gather(c->fp64, na, n, pl.p, pl.h, c->P.coulomb_k, c->d_perm, c->d_base, c->d_w, c->d_qa,
-                             c->d_phi[0], c->d_phi[1], c->d_phi32, force, c->d_partial, c->d_ctl, s));
-  const double pe = pl.p + 2.0;
-  kt_end(KT_GATHER, 0, (double)na * (48.0 + 24.0 * pl.p + pe * pe * pe * (c->fp64 ? 8.0 : 4.0)), s);
+  P3MZ_HIP_TRY(launch_gather(c->fp64, na, n, pl.p, kTile, c->ntx, pl.h, c->P.coulomb_k, c->d_start, c->d_perm,
+                             c->d_base, c->d_w, c->d_qa, c->d_phi[0], c->d_phi[1], c->d_phi32, force, c->d_partial,
+                             c->d_ctl, s));
+  // algorithmic bytes: the potential once, plus each atom's stencil record,
+  // charge and force (the (p+2)^3 neighbourhood reads are shared by atoms)
+  kt_end(KT_GATHER, 0, N3 * (c->fp64 ? 8.0 : 4.0) + (double)na * (48.0 + 24.0 * pl.p), s);
   return P3MZ_OK;
 }
 
@@ -551,7 +595,8 @@ p3mz_status enq_post2(p3mz_ctx* c, const double* pos, double* force, double* ene
   rec_key(6004);
   kt_begin(KT_SR, 0, s);
   P3MZ_HIP_TRY(launch_sr(na, pos, c->d_qa, c->P.box, c->P.alpha, c->P.r_cut, c->P.coulomb_k, c->nc, c->P.excl_group,
-                         c->d_cstart, c->d_cperm, c->d_spos, force, c->e_self, energy ? energy : c->d_energy,
+                         c->d_cstart, c->d_cperm, c->d_spos, c->d_erfc, c->erfc_n, c->erfc_scale, force, c->e_self,
+                         energy ? energy : c->d_energy,
                          c->d_partial, c->d_ctl, s));
   kt_end(KT_SR, 0, (double)na * 56.0, s);
   rec_key(6005);
@@ -1430,11 +1475,10 @@ p3mz_status p3mz_kernel_bench(p3mz_ctx* ctx, int32_t kernel_id, int32_t reps, vo
                         ctx->d_tmp, s);
       bytes = 8.0 * N3 + na * (24.0 * p + 24.0);
     } else if (kernel_id == KT_GATHER) {
-      e = launch_gather(ctx->fp64, (int)ctx->n_atoms, n, p, ctx->pl.h, ctx->P.coulomb_k, ctx->d_perm, ctx->d_base,
-                        ctx->d_w, ctx->d_qa, ctx->d_phi[0], ctx->d_phi[1], ctx->d_phi32, nullptr, ctx->d_partial,
-                        ctx->d_ctl, s, false);
-      const double pe = p + 2.0;
-      bytes = na * (48.0 + 24.0 * p + pe * pe * pe * (ctx->fp64 ? 8.0 : 4.0));
+      e = launch_gather(ctx->fp64, (int)ctx->n_atoms, n, p, kTile, ctx->ntx, ctx->pl.h, ctx->P.coulomb_k, ctx->d_start,
+                        ctx->d_perm, ctx->d_base, ctx->d_w, ctx->d_qa, ctx->d_phi[0], ctx->d_phi[1], ctx->d_phi32,
+                        nullptr, ctx->d_partial, ctx->d_ctl, s, false);
+      bytes = N3 * (ctx->fp64 ? 8.0 : 4.0) + na * (48.0 + 24.0 * p);
     } else {
       e = launch_vcycle_kernel(ctx->fp64, kernel_id, ctx->lv, ctx->pl.levels, ctx->pl.tail, ctx->nu1, ctx->nu2,
                                ctx->d_green, ctx->d_ctl, s, &bytes);

@@ -127,6 +127,29 @@ __device__ __forceinline__ void chunk_range(int64_t count, int* lo, int* hi) {
   *hi = (int)(l + per < count ? l + per : count);
 }
 
+// Piecewise Chebyshev table of erfcx(x) = exp(x^2) erfc(x) on [0, X]:
+// intervals of width X/n, degree kErfcDeg; coefficient j of interval k at
+// [k * (kErfcDeg + 1) + j], the constant term already halved.
+constexpr int kErfcDeg = 11;
+constexpr int kErfcMaxIntervals = 128;
+
+// erfcx(x) for 0 <= x < n / scale, from a table in LDS (Clenshaw).
+__device__ __forceinline__ double erfcx_table(const double* tab, int n, double scale, double x) {
+  const double u = x * scale;
+  int k = (int)u;
+  k = k < n - 1 ? k : n - 1;
+  const double t = 2.0 * (u - (double)k) - 1.0;
+  const double* c = tab + k * (kErfcDeg + 1);
+  double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+  for (int j = kErfcDeg; j >= 1; j--) {
+    const double b0 = fma(2.0 * t, b1, c[j] - b2);
+    b2 = b1;
+    b1 = b0;
+  }
+  return fma(t, b1, c[0] - b2);
+}
+
 // --- mesh indexing ---------------------------------------------------------
 // Natural layout: x fastest.  Colour-split layout: the points of colour
 // c = (i+j+k)&1 of each row (j,k) are packed, index ((k*n + j)*(n/2) + i/2).

@@ -42,19 +42,21 @@ hipError_t launch_spread(bool fp64, int n, int p, int tile, int ntx, const int* 
 // phi: FP64 mode reads the new potential from phi0/phi1 (selected on the
 // device), mixed mode reads the FP32 copy phi32.
 // finalize = false launches the per-atom kernel only (back-to-back timing).
-hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, double h, double k_e, const int* perm,
-                         const int* base, const void* w, const double* qa, const double* phi0,
-                         const double* phi1, const float* phi32, double* force, double* partial, Ctl* ctl,
-                         hipStream_t s, bool finalize = true);
+hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, int tile, int ntx, double h, double k_e,
+                         const int* start, const int* perm, const int* base, const void* w, const double* qa,
+                         const double* phi0, const double* phi1, const float* phi32, double* force, double* partial,
+                         Ctl* ctl, hipStream_t s, bool finalize = true);
 // Short-range erfc pairs on the cell list, exclusion correction, energy
 // assembly into energy_out[4] (may be NULL).  force += F_sr.
 // spos[jj] = {x, y, z, q} of atom cperm[jj] (cell order), for the pair kernels.
 hipError_t launch_cell_pack(int n_atoms, const int* cperm, const double* pos, const double* qa, void* spos,
                             hipStream_t s);
+// erfc_tab: erfcx table for alpha r in [0, alpha r_cut] (erfc_n intervals,
+// erfc_scale intervals per unit).
 hipError_t launch_sr(int n_atoms, const double* pos, const double* qa, double box, double alpha,
                      double r_cut, double k_e, int nc, int excl_group, const int* cstart,
-                     const int* cperm, const void* spos, double* force, double e_self, double* energy_out,
-                     double* partial, Ctl* ctl, hipStream_t s);
+                     const int* cperm, const void* spos, const double* erfc_tab, int erfc_n, double erfc_scale,
+                     double* force, double e_self, double* energy_out, double* partial, Ctl* ctl, hipStream_t s);
 
 // ---- mesh (mesh.hip) -----------------------------------------------------
 // Folded periodic smoothing filter along one axis: out = sum_m c[m] v[i+m-K],

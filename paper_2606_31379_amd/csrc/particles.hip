@@ -432,87 +432,130 @@ __device__ void Spread<T, TS>::run(const Args& A, Grid G) {
 // rewritten as derivative weights on a (p+2)^3 neighbourhood, and the
 // per-atom energy 1/2 k Q (W * phi)(r).  Row sums in precision T (the
 // weights are rounded to T), accumulation over rows in FP64.
-template <typename T, typename TP>
+//
+// A capped grid of workgroups walks the TS^3 tiles (the spread's bins).  For
+// each tile the potential on the tile plus its (p+1)-point halo is staged in
+// LDS once; the tile's atoms (its bin, sorted) are then evaluated from LDS,
+// one thread per (atom, z-plane of the neighbourhood); the plane partial sums
+// are added in a fixed order.
+template <typename T, typename TP, int TS>
 struct Gather {
   struct Args {
-    int n_atoms, n, p;
+    int n_atoms, n, p, ntx;
     double h, k_e;
-    const int *perm, *base;
+    const int *start, *perm, *base;
     const double *w, *qa;
     const TP *phi0, *phi1;
     double *force, *partial;
     const Ctl* ctl;
   };
   static constexpr int kThreads = kBlock;
+  static constexpr int kMaxE = TS + P3MZ_MAX_ORDER + 1;
   __device__ static void run(const Args& A, Grid G);
 };
-template <typename T, typename TP>
-__device__ void Gather<T, TP>::run(const Args& A, Grid G) {
-  const int n_atoms = A.n_atoms, n = A.n, p = A.p;
+template <typename T, typename TP, int TS>
+__device__ void Gather<T, TP, TS>::run(const Args& A, Grid G) {
+  const int n = A.n, p = A.p, ntx = A.ntx;
   const double h = A.h, k_e = A.k_e;
+  const int* __restrict__ start = A.start;
   const int* __restrict__ perm = A.perm;
   const int* __restrict__ base = A.base;
   const double* __restrict__ w = A.w;
   const double* __restrict__ qa = A.qa;
-  const TP* __restrict__ phi0 = A.phi0;
-  const TP* __restrict__ phi1 = A.phi1;
   double* __restrict__ force = A.force;
   double* __restrict__ partial = A.partial;
   const Ctl* ctl = A.ctl;
+  __shared__ T sphi[kMaxE * kMaxE * kMaxE];
+  __shared__ double part[kBlock][4];
   __shared__ double sh[kBlock / 64];
   // the new potential: written over phi^k on a cold solve, over phi^{k-1} otherwise
-  const TP* phi = (ctl->cold ? ctl->k_idx : 1 - ctl->k_idx) ? phi1 : phi0;
-  double e_atom = 0.0;
-  for (int t = G.b * kBlock + threadIdx.x; t < n_atoms; t += G.g * kBlock) {
-    const int a = perm[t];
-    const int pe = p + 2;
-    T wx[P3MZ_MAX_ORDER + 2], wy[P3MZ_MAX_ORDER + 2], wz[P3MZ_MAX_ORDER + 2];
-    T dx[P3MZ_MAX_ORDER + 2], dy[P3MZ_MAX_ORDER + 2], dz[P3MZ_MAX_ORDER + 2];
-    const T inv2h = (T)(0.5 / h);
-    for (int j = 0; j < pe; j++) {
-      wx[j] = (j >= 1 && j <= p) ? (T)w[(3 * a) * p + j - 1] : T(0);
-      wy[j] = (j >= 1 && j <= p) ? (T)w[(3 * a + 1) * p + j - 1] : T(0);
-      wz[j] = (j >= 1 && j <= p) ? (T)w[(3 * a + 2) * p + j - 1] : T(0);
+  const TP* __restrict__ phi = (ctl->cold ? ctl->k_idx : 1 - ctl->k_idx) ? A.phi1 : A.phi0;
+  const int pe = p + 2, E = TS + p + 1, E3 = E * E * E;
+  const int per_round = kBlock / pe;     // atoms evaluated per round
+  const T inv2h = (T)(0.5 / h);
+  double e_sum = 0.0;
+  const int ntiles = ntx * ntx * ntx;
+  for (int t = G.b; t < ntiles; t += G.g) {
+    const int tx = t % ntx, ty = (t / ntx) % ntx, tz = t / (ntx * ntx);
+    const int ox = tx * TS - 1, oy = ty * TS - 1, oz = tz * TS - 1;   // halo origin
+    __syncthreads();   // the previous tile's LDS reads are done
+    for (int e = threadIdx.x; e < E3; e += kBlock) {
+      const int lx = e % E, ly = (e / E) % E, lz = e / (E * E);
+      const int gx = ((ox + lx) % n + n) % n, gy = ((oy + ly) % n + n) % n, gz = ((oz + lz) % n + n) % n;
+      sphi[e] = (T)phi[((size_t)gz * n + gy) * n + gx];
     }
-    for (int j = 0; j < pe; j++) {
-      // extended index j <-> stencil offset j-1; d[j] = (w[j-1] - w[j+1]) / 2h
-      const T lo = j >= 1 ? wx[j - 1] : T(0), hi = j + 1 < pe ? wx[j + 1] : T(0);
-      dx[j] = (lo - hi) * inv2h;
-      const T loy = j >= 1 ? wy[j - 1] : T(0), hiy = j + 1 < pe ? wy[j + 1] : T(0);
-      dy[j] = (loy - hiy) * inv2h;
-      const T loz = j >= 1 ? wz[j - 1] : T(0), hiz = j + 1 < pe ? wz[j + 1] : T(0);
-      dz[j] = (loz - hiz) * inv2h;
-    }
-    const int bx = base[3 * a] - 1 + n, by = base[3 * a + 1] - 1 + n, bz = base[3 * a + 2] - 1 + n;
-    int ix[P3MZ_MAX_ORDER + 2];
-    for (int j = 0; j < pe; j++) ix[j] = (bx + j) % n;
-    double fx = 0, fy = 0, fz = 0, pot = 0;
-    for (int c = 0; c < pe; c++) {
-      const int iz = (bz + c) % n;
-      for (int b = 0; b < pe; b++) {
-        const int iy = (by + b) % n;
-        const TP* row = phi + (size_t)(iz * n + iy) * n;
-        T sx = T(0), s0 = T(0);
-        for (int j = 0; j < pe; j++) {
-          const T v = (T)row[ix[j]];
-          sx += dx[j] * v;
-          s0 += wx[j] * v;
+    __syncthreads();
+    const int a0 = start[t], na_t = start[t + 1] - a0;
+    for (int ag = 0; ag < na_t; ag += per_round) {
+      const int task = threadIdx.x;
+      const int ai = ag + task / pe, c = task % pe;
+      if (task < per_round * pe && ai < na_t) {
+        const int a = perm[a0 + ai];
+        T wx[P3MZ_MAX_ORDER + 2], wy[P3MZ_MAX_ORDER + 2], dx[P3MZ_MAX_ORDER + 2], dy[P3MZ_MAX_ORDER + 2];
+        T wz_c, dz_c;
+        {
+          T wz[P3MZ_MAX_ORDER + 2];
+          for (int j = 0; j < pe; j++) {
+            wx[j] = (j >= 1 && j <= p) ? (T)w[(3 * a) * p + j - 1] : T(0);
+            wy[j] = (j >= 1 && j <= p) ? (T)w[(3 * a + 1) * p + j - 1] : T(0);
+            wz[j] = (j >= 1 && j <= p) ? (T)w[(3 * a + 2) * p + j - 1] : T(0);
+          }
+          for (int j = 0; j < pe; j++) {
+            // extended index j <-> stencil offset j-1; d[j] = (w[j-1] - w[j+1]) / 2h
+            const T lo = j >= 1 ? wx[j - 1] : T(0), hi = j + 1 < pe ? wx[j + 1] : T(0);
+            dx[j] = (lo - hi) * inv2h;
+            const T loy = j >= 1 ? wy[j - 1] : T(0), hiy = j + 1 < pe ? wy[j + 1] : T(0);
+            dy[j] = (loy - hiy) * inv2h;
+          }
+          wz_c = wz[c];
+          const T loz = c >= 1 ? wz[c - 1] : T(0), hiz = c + 1 < pe ? wz[c + 1] : T(0);
+          dz_c = (loz - hiz) * inv2h;
         }
-        fx += (double)(wy[b] * wz[c]) * (double)sx;
-        fy += (double)(dy[b] * wz[c]) * (double)s0;
-        fz += (double)(wy[b] * dz[c]) * (double)s0;
-        pot += (double)(wy[b] * wz[c]) * (double)s0;
+        // neighbourhood origin in the halo tile: base - 1 - (tile origin - 1)
+        const int lx0 = base[3 * a] - (ox + 1), ly0 = base[3 * a + 1] - (oy + 1), lz0 = base[3 * a + 2] - (oz + 1);
+        double fx = 0, fy = 0, fz = 0, pot = 0;
+        const T* plane = sphi + (size_t)(lz0 + c) * E * E;
+        for (int b = 0; b < pe; b++) {
+          const T* row = plane + (ly0 + b) * E + lx0;
+          T sx = T(0), s0 = T(0);
+          for (int j = 0; j < pe; j++) {
+            const T v = row[j];
+            sx += dx[j] * v;
+            s0 += wx[j] * v;
+          }
+          fx += (double)(wy[b] * wz_c) * (double)sx;
+          fy += (double)(dy[b] * wz_c) * (double)s0;
+          fz += (double)(wy[b] * dz_c) * (double)s0;
+          pot += (double)(wy[b] * wz_c) * (double)s0;
+        }
+        part[task][0] = fx;
+        part[task][1] = fy;
+        part[task][2] = fz;
+        part[task][3] = pot;
       }
+      __syncthreads();
+      if ((int)threadIdx.x < per_round && ag + (int)threadIdx.x < na_t) {
+        const int k = threadIdx.x;
+        const int a = perm[a0 + ag + k];
+        double fx = 0, fy = 0, fz = 0, pot = 0;
+        for (int cc = 0; cc < pe; cc++) {
+          fx += part[k * pe + cc][0];
+          fy += part[k * pe + cc][1];
+          fz += part[k * pe + cc][2];
+          pot += part[k * pe + cc][3];
+        }
+        const double kq = k_e * qa[a];
+        if (force) {
+          force[3 * a] = -kq * fx;
+          force[3 * a + 1] = -kq * fy;
+          force[3 * a + 2] = -kq * fz;
+        }
+        e_sum += 0.5 * kq * pot;
+      }
+      __syncthreads();
     }
-    const double kq = k_e * qa[a];
-    if (force) {
-      force[3 * a] = -kq * fx;
-      force[3 * a + 1] = -kq * fy;
-      force[3 * a + 2] = -kq * fz;
-    }
-    e_atom += 0.5 * kq * pot;
   }
-  double bs = block_sum(e_atom, sh);
+  double bs = block_sum(e_sum, sh);
   if (threadIdx.x == 0) partial[G.b] = bs;
 }
 
@@ -591,6 +634,9 @@ struct ShortRange {
     const int *cstart, *cperm;
     const double4* spos;   // cell-ordered {x, y, z, q}
     double *force, *partial;
+    const double* erfc_tab;   // erfcx table on [0, alpha r_cut] (1..kErfcMaxIntervals intervals)
+    int erfc_n;
+    double erfc_scale;        // table intervals per unit of alpha r
   };
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G);
@@ -606,11 +652,16 @@ __device__ void ShortRange::run(const Args& A, Grid G) {
   double* __restrict__ partial = A.partial;
   __shared__ double sh[kBlock / 64];
   __shared__ PairQueue queue[kBlock / 64];
+  extern __shared__ double tab[];   // erfc_n * (kErfcDeg + 1) coefficients (dynamic LDS)
   const int lane = threadIdx.x & 63;
   const int nwaves = G.g * (kBlock / 64);
   PairQueue& Q = queue[threadIdx.x >> 6];
   double en = 0.0;
   const double4* __restrict__ spos = A.spos;
+  const int tab_n = A.erfc_n;
+  const double tab_scale = A.erfc_scale;
+  for (int k = threadIdx.x; k < tab_n * (kErfcDeg + 1); k += kBlock) tab[k] = A.erfc_tab[k];
+  __syncthreads();
   for (int wave = (G.b * kBlock + threadIdx.x) >> 6; wave < n_atoms; wave += nwaves) {
     double fx = 0.0, fy = 0.0, fz = 0.0;
     const int i = cperm[wave];
@@ -624,12 +675,16 @@ __device__ void ShortRange::run(const Args& A, Grid G) {
         wave, xi, yi, zi, box, nc, cstart, spos, Q,
         [&](int jj, double r2) { return r2 < rc2 && !(gi >= 0 && cperm[jj] / excl_group == gi); },
         [&](double dx, double dy, double dz, double r2, double qj) {
+          // erfc(a r) = exp(-a^2 r^2) erfcx(a r), erfcx from the table
           const double r = sqrt(r2);
-          const double ec = erfc(alpha * r);
+          const double inv_r = 1.0 / r;
+          const double x = alpha * r;
+          const double g = exp(-x * x);
+          const double ec = g * erfcx_table(tab, tab_n, tab_scale, x);
           const double qq = k_e * qi * qj;
-          const double f = qq * (ec / (r2 * r) + tapi * exp(-alpha * alpha * r2) / r2);
+          const double f = qq * inv_r * inv_r * (ec * inv_r + tapi * g);
           fx += f * dx; fy += f * dy; fz += f * dz;
-          en += 0.5 * qq * ec / r;
+          en += 0.5 * qq * ec * inv_r;
         });
     if (gi >= 0 && lane < excl_group) {
       const int j = gi * excl_group + lane;
@@ -640,7 +695,9 @@ __device__ void ShortRange::run(const Args& A, Grid G) {
         dz -= box * rint(dz * inv_box);
         const double r2 = dx * dx + dy * dy + dz * dz;
         const double r = sqrt(r2);
-        const double er = erf(alpha * r);
+        // erf = 1 - exp(-x^2) erfcx(x); intramolecular pairs lie well inside the table
+        const double xr = alpha * r;
+        const double er = 1.0 - exp(-xr * xr) * erfcx_table(tab, tab_n, tab_scale, xr);
         const double qq = k_e * qi * qa[j];
         const double f = qq * (tapi * exp(-alpha * alpha * r2) / r - er / r2) / r;
         fx += f * dx; fy += f * dy; fz += f * dz;
@@ -716,18 +773,19 @@ hipError_t launch_spread(bool fp64, int n, int p, int tile, int ntx, const int* 
   return go<Spread<float, 8>>({n, p, ntx, start, perm, base, (const float*)w, qa, (float*)q}, ntiles, 0, s);
 }
 
-hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, double h, double k_e, const int* perm,
-                         const int* base, const void* w, const double* qa, const double* phi0,
-                         const double* phi1, const float* phi32, double* force, double* partial, Ctl* ctl,
-                         hipStream_t s, bool finalize) {
-  const int nb = std::min(blocks_for(n_atoms, kBlock), kMaxRedBlocks);
+hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, int tile, int ntx, double h, double k_e,
+                         const int* start, const int* perm, const int* base, const void* w, const double* qa,
+                         const double* phi0, const double* phi1, const float* phi32, double* force, double* partial,
+                         Ctl* ctl, hipStream_t s, bool finalize) {
+  if (tile != 8) return hipErrorInvalidValue;
+  const int nb = std::min(ntx * ntx * ntx, kMaxRedBlocks);
   hipError_t e;
   if (fp64)
-    e = go<Gather<double, double>>({n_atoms, n, p, h, k_e, perm, base, (const double*)w, qa, phi0, phi1, force,
-                                    partial, ctl}, nb, 0, s);
+    e = go<Gather<double, double, 8>>({n_atoms, n, p, ntx, h, k_e, start, perm, base, (const double*)w, qa, phi0,
+                                       phi1, force, partial, ctl}, nb, 0, s);
   else
-    e = go<Gather<float, float>>({n_atoms, n, p, h, k_e, perm, base, (const double*)w, qa, phi32, phi32, force,
-                                  partial, ctl}, nb, 0, s);
+    e = go<Gather<float, float, 8>>({n_atoms, n, p, ntx, h, k_e, start, perm, base, (const double*)w, qa, phi32,
+                                     phi32, force, partial, ctl}, nb, 0, s);
   if (e != hipSuccess || !finalize) return e;
   return go<FinSum>({nb, partial, &ctl->e_lr}, 1, 0, s);
 }
@@ -739,11 +797,13 @@ hipError_t launch_cell_pack(int n_atoms, const int* cperm, const double* pos, co
 
 hipError_t launch_sr(int n_atoms, const double* pos, const double* qa, double box, double alpha,
                      double r_cut, double k_e, int nc, int excl_group, const int* cstart,
-                     const int* cperm, const void* spos, double* force, double e_self, double* energy_out,
-                     double* partial, Ctl* ctl, hipStream_t s) {
+                     const int* cperm, const void* spos, const double* erfc_tab, int erfc_n, double erfc_scale,
+                     double* force, double e_self, double* energy_out, double* partial, Ctl* ctl, hipStream_t s) {
+  if (erfc_n < 1 || erfc_n > kErfcMaxIntervals) return hipErrorInvalidValue;
   const int nb = std::min(blocks_for((int64_t)n_atoms * 64, kBlock), kPartialSlots);
+  const size_t lds = (size_t)erfc_n * (kErfcDeg + 1) * sizeof(double);
   hipError_t e = go<ShortRange>({n_atoms, nc, excl_group, box, alpha, r_cut * r_cut, k_e, pos, qa, cstart, cperm,
-                                 (const double4*)spos, force, partial}, nb, 0, s);
+                                 (const double4*)spos, force, partial, erfc_tab, erfc_n, erfc_scale}, nb, lds, s);
   if (e != hipSuccess) return e;
   return go<FinEnergy>({nb, e_self, partial, ctl, energy_out}, 1, 0, s);
 }

@@ -62,7 +62,7 @@ def _rng(seed: int) -> np.random.Generator:
 
 
 def hard_core_points(rng: np.random.Generator, n: int, box: float, dmin: float,
-                     max_rounds: int = 400) -> np.ndarray:
+                     max_rounds: int = 400, progress=None) -> np.ndarray:
     """Uniform random points in a periodic cube, no pair closer than ``dmin``.
 
     Batched random sequential addition: each round draws a batch of uniform
@@ -104,6 +104,8 @@ def hard_core_points(rng: np.random.Generator, n: int, box: float, dmin: float,
                 keep[drop] = False
                 idx = idx[keep]
         new = cand[idx[:need]]
+        if progress is not None and (len(chunks) % 20 == 0 or have + new.shape[0] == n):
+            progress(f"placed {have + new.shape[0]} of {n} points")
         if new.shape[0]:
             chunks.append(new)
             have += new.shape[0]
@@ -153,10 +155,11 @@ def _random_rotations(rng: np.random.Generator, k: int) -> np.ndarray:
 
 def water(n_mol: int, box: float, temp_k: float, seed: int, r_oh: float = 1.0,
           angle_deg: float = 109.47, d_oo: float = 2.4, d_inter: float = 1.2,
-          max_rounds: int = 200) -> System:
-    """Point-charge water; atoms ordered O, H, H per molecule."""
+          max_rounds: int = 200, progress=None) -> System:
+    """Point-charge water; atoms ordered O, H, H per molecule.  `progress`
+    (optional) receives a short text now and then."""
     rng = _rng(seed)
-    opos = hard_core_points(rng, n_mol, box, d_oo)
+    opos = hard_core_points(rng, n_mol, box, d_oo, progress=progress)
     half = math.radians(angle_deg) / 2.0
     tmpl = np.array([[0.0, 0.0, 0.0],
                      [r_oh * math.sin(half), 0.0, r_oh * math.cos(half)],
@@ -188,6 +191,8 @@ def water(n_mol: int, box: float, temp_k: float, seed: int, r_oh: float = 1.0,
             foreign = hit & (mol_id[nb] != mol_id[atoms][:, None])
             rows, cols = np.nonzero(foreign)
             bad = np.unique(np.concatenate([mol_id[atoms[rows]], mol_id[nb[rows, cols]]]))
+        if progress is not None:
+            progress(f"orientation pass: {bad.size} molecules with contacts")
         if bad.size == 0:
             break
         rot[bad] = _random_rotations(rng, bad.size)

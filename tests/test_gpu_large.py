@@ -34,7 +34,7 @@ def torch():
 
 
 def sampled_parity(torch, w, precisions, steps, sample=512):
-    s = w.system()
+    s = w.system(progress=lambda msg: print(f"[inputs] {msg}", flush=True))
     rng = np.random.Generator(np.random.PCG64(w.seed + 17))
     targets = np.sort(rng.choice(s.n, size=sample, replace=False))
     traj = [s.pos + k * w.dt_fs * s.vel for k in range(steps)]
