@@ -576,6 +576,24 @@ __device__ __forceinline__ T prolong_at(const T* __restrict__ c0, const T* __res
   return s;
 }
 
+// Prolongation fused with the first red half-sweep after it (levels where
+// launches, not bytes, dominate): each red point sums its six black
+// neighbours, each plus its trilinear coarse correction (the same value and
+// rounding prolongation would have stored there), in the order of cs_nbr6.
+// The black points keep their uncorrected values: the black half-sweep that
+// follows rewrites every one of them from the red points alone.
+template <typename T, int FIN>
+struct ProlongRed {
+  struct Args {
+    int n;
+    T* e0;
+    const T *e1, *r0, *ec0, *ec1;
+    const Ctl* ctl;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G);
+};
+
 // After prolongation the next red half-sweep overwrites every red value and
 // reads only black neighbours, so only the black points receive the
 // trilinear correction here; the red half-sweep follows.
@@ -605,6 +623,25 @@ __device__ void ProlongBlack<T, FIN>::run(const Args& A, Grid G) {
   cs_decode(g, t, &m, &j, &k);
   const int ib = 2 * m + ((1 + j + k) & 1);
   e1[t] += prolong_at(ec0, ec1, gc, ib, j, k);
+}
+
+template <typename T, int FIN>
+__device__ void ProlongRed<T, FIN>::run(const Args& A, Grid G) {
+  if (A.ctl->done) return;
+  const int n = A.n;
+  const CsGeo g(n), gc(n >> 1);
+  const int half = n * g.hn * n;
+  const int t = G.b * kBlock + threadIdx.x;
+  if (t >= half) return;
+  int m, j, k;
+  cs_decode(g, t, &m, &j, &k);
+  const int i = 2 * m + ((j + k) & 1);   // red point
+  const int msk = n - 1;
+  const T* __restrict__ e1 = A.e1;
+  auto V = [&](int x, int y, int z) { return e1[cs_index(g, x, y, z)] + prolong_at(A.ec0, A.ec1, gc, x, y, z); };
+  const T nb = ((V((i - 1) & msk, j, k) + V((i + 1) & msk, j, k)) + (V(i, (j - 1) & msk, k) + V(i, (j + 1) & msk, k))) +
+               (V(i, j, (k - 1) & msk) + V(i, j, (k + 1) & msk));
+  A.e0[t] = (nb - A.r0[t]) * T(1.0 / 6.0);
 }
 
 template <typename T>
@@ -738,17 +775,33 @@ __device__ void Tail<T>::run(const Args& A, Grid) {
     const int lc = l2 - 1, nc = n >> 1, nc3 = 1 << (3 * lc);
     T* e = E[q];
     const T* r = R[q];
-    for (int p = tid; p < n3; p += nt) e[p] = T(0);
-    __syncthreads();
-    for (int s = 0; s < nu1; s++) {
-      tail_rbgs(e, r, n, l2, 0);
+    if (nu1 >= 1) {
+      // first red half-sweep from e = 0: e = -r/6 at the red points
+      const int half = n3 >> 1;
+      for (int pp = tid; pp < half; pp += nt) {
+        const int m = pp & ((n >> 1) - 1), row = pp >> (l2 - 1);
+        const int j = row & (n - 1), k = row >> l2;
+        const int a = (row << l2) + 2 * m + ((j + k) & 1);
+        e[a] = (T(0) - r[a]) * T(1.0 / 6.0);
+      }
       __syncthreads();
       tail_rbgs(e, r, n, l2, 1);
       __syncthreads();
+      for (int s = 1; s < nu1; s++) {
+        tail_rbgs(e, r, n, l2, 0);
+        __syncthreads();
+        tail_rbgs(e, r, n, l2, 1);
+        __syncthreads();
+      }
+    } else {
+      for (int p = tid; p < n3; p += nt) e[p] = T(0);
+      __syncthreads();
     }
+    // residual; after a black half-sweep the black residuals vanish up to
+    // rounding and are taken as zero, as on the upper levels
     for (int p = tid; p < n3; p += nt) {
       const int i = p & msk, j = (p >> l2) & msk, k = p >> (2 * l2);
-      rho[p] = r[p] - (lds_nbr(e, n, l2, i, j, k) - T(6) * e[p]);
+      rho[p] = (nu1 >= 1 && ((i + j + k) & 1)) ? T(0) : r[p] - (lds_nbr(e, n, l2, i, j, k) - T(6) * e[p]);
     }
     __syncthreads();
     for (int p = tid; p < nc3; p += nt) {
@@ -768,16 +821,20 @@ __device__ void Tail<T>::run(const Args& A, Grid) {
     __syncthreads();
   }
   {
-    const int q = levels - 1;   // 4^3: e = G * r, FP64 accumulation
-    if (tid < 64) {
-      const int x = tid & 3, y = (tid >> 2) & 3, z = tid >> 4;
-      double s = 0.0;
-      for (int mm = 0; mm < 64; mm++) {
+    // 4^3: e = G * r with FP64 accumulation; 16 consecutive lanes share one
+    // output point, each summing 4 of the 64 terms, then a fixed shuffle tree
+    const int q = levels - 1;
+    const int o = tid >> 4, part = tid & 15;
+    double s = 0.0;
+    if (o < 64) {
+      const int x = o & 3, y = (o >> 2) & 3, z = o >> 4;
+      for (int mm = part * 4; mm < part * 4 + 4; mm++) {
         const int a = mm & 3, b = (mm >> 2) & 3, c = mm >> 4;
         s += G[(((z - c) & 3) * 4 + ((y - b) & 3)) * 4 + ((x - a) & 3)] * (double)R[q][mm];
       }
-      E[q][tid] = (T)s;
     }
+    for (int d = 8; d > 0; d >>= 1) s += __shfl_xor(s, d, 16);
+    if (o < 64 && part == 0) E[q][o] = (T)s;
     __syncthreads();
   }
   for (int q = levels - 2; q >= 0; q--) {
@@ -787,6 +844,9 @@ __device__ void Tail<T>::run(const Args& A, Grid) {
     const T* ec = E[q + 1];
     for (int p = tid; p < n3; p += nt) {
       const int x = p & msk, y = (p >> l2) & msk, z = p >> (2 * l2);
+      // the next red half-sweep overwrites every red point: only black points
+      // need the correction when post-smoothing follows
+      if (nu2 >= 1 && !((x + y + z) & 1)) continue;
       const int x0 = x >> 1, y0 = y >> 1, z0 = z >> 1;
       const int x1 = (x & 1) ? ((x0 + 1) & cm) : x0;
       const int y1 = (y & 1) ? ((y0 + 1) & cm) : y0;
@@ -970,6 +1030,11 @@ template <typename T, int FIN>
 hipError_t launch_prolong_black(int n, int nb, T* e1, const T* c0, const T* c1, Ctl* ctl, hipStream_t s) {
   return go<ProlongBlack<T, FIN>>({n, e1, c0, c1, ctl}, nb, 0, s);
 }
+template <typename T, int FIN>
+hipError_t launch_prolong_red(int n, int nb, T* e0, const T* e1, const T* r0, const T* c0, const T* c1, Ctl* ctl,
+                              hipStream_t s) {
+  return go<ProlongRed<T, FIN>>({n, e0, e1, r0, c0, c1, ctl}, nb, 0, s);
+}
 template <typename T>
 hipError_t launch_tail(const LevelBufs* lv, int levels, int tail, int nu1, int nu2, const double* green, Ctl* ctl,
                        hipStream_t s) {
@@ -988,8 +1053,11 @@ hipError_t launch_tail(const LevelBufs* lv, int levels, int tail, int nu1, int n
 // Sequence keys of the V-cycle launches (merge keys of batched systems):
 // level l from the finest going down, the tail, then the levels going up in
 // reverse, so systems with fewer levels keep their own order in a batch.
-// Sub-keys: 0..32 sweeps and prolongation, 62 zero fill, 63 restriction /
-// plain prolongation.
+// Sub-keys: 0..33 sweeps and prolongation (up: 0 black-point prolongation,
+// 1 prolongation fused with the first red sweep, then 2 + 2 it + colour),
+// 62 zero fill, 63 restriction / plain prolongation.  Levels up to this edge
+// use the fused prolongation.
+constexpr int kFuseProlongMax = 128;
 inline uint32_t key_down(int l, int sub) { return 1000u + 64u * (uint32_t)l + (uint32_t)sub; }
 inline uint32_t key_up(int l, int sub) { return 3000u + 64u * (uint32_t)(P3MZ_MAX_LEVELS - 1 - l) + (uint32_t)sub; }
 constexpr uint32_t kKeyTail = 2100u;
@@ -1043,17 +1111,29 @@ hipError_t vcycle_impl(const LevelBufs* lv, int levels, int tail, int nu1, int n
     T *e0 = (T*)lv[l].e0, *e1 = (T*)lv[l].e1, *r0 = (T*)lv[l].r0, *r1 = (T*)lv[l].r1;
     const T *c0 = (const T*)lv[l + 1].e0, *c1 = (const T*)lv[l + 1].e1;
     if (nu2 >= 1) {
-      rec_key(key_up(l, 0));
-      kt_begin(KT_PROLONG, l, s);
-      P3MZ_LAUNCH(l == 0 ? launch_prolong_black<T, 1>(n, nb, e1, c0, c1, ctl, s)
-                         : launch_prolong_black<T, 0>(n, nb, e1, c0, c1, ctl, s));
-      kt_end(KT_PROLONG, l, 1.125 * ts * n3, s);
+      // levels up to kFuseProlongMax: prolongation fused with the first red
+      // half-sweep; larger levels: black-point prolongation, then the sweep
+      const bool fuse = n <= kFuseProlongMax;
+      if (fuse) {
+        rec_key(key_up(l, 1));
+        kt_begin(KT_PROLONG, l, s);
+        P3MZ_LAUNCH(l == 0 ? launch_prolong_red<T, 1>(n, nb, e0, e1, r0, c0, c1, ctl, s)
+                           : launch_prolong_red<T, 0>(n, nb, e0, e1, r0, c0, c1, ctl, s));
+        kt_end(KT_PROLONG, l, 1.625 * ts * n3, s);
+      } else {
+        rec_key(key_up(l, 0));
+        kt_begin(KT_PROLONG, l, s);
+        P3MZ_LAUNCH(l == 0 ? launch_prolong_black<T, 1>(n, nb, e1, c0, c1, ctl, s)
+                           : launch_prolong_black<T, 0>(n, nb, e1, c0, c1, ctl, s));
+        kt_end(KT_PROLONG, l, 1.125 * ts * n3, s);
+      }
       for (int it = 0; it < nu2; it++) {
         for (int colour = 0; colour < 2; colour++) {
+          if (fuse && it == 0 && colour == 0) continue;   // done by the fused launch
           T* ec = colour ? e1 : e0;
           const T* eo = colour ? e0 : e1;
           const T* rc = colour ? r1 : r0;
-          rec_key(key_up(l, 1 + 2 * it + colour));
+          rec_key(key_up(l, 2 + 2 * it + colour));
           kt_begin(KT_HALFSWEEP, l, s);
           P3MZ_LAUNCH(l == 0 ? launch_half<T, 1>(n, colour, ec, eo, rc, ctl, s)
                              : launch_half<T, 0>(n, colour, ec, eo, rc, ctl, s));
@@ -1090,8 +1170,12 @@ hipError_t one_kernel(int kid, const LevelBufs* lv, int levels, int tail, int nu
       if (tail == 0) return hipErrorInvalidValue;
       *bytes = 2.125 * ts * n3;
       return launch_restrict<T, 1>(n, nu1 >= 1, e0, e1, r0, r1, (T*)lv[1].r0, (T*)lv[1].r1, ctl, s);
-    case KT_PROLONG:
+    case KT_PROLONG:   // the variant the V-cycle uses on this level
       if (tail == 0) return hipErrorInvalidValue;
+      if (n <= kFuseProlongMax) {
+        *bytes = 1.625 * ts * n3;
+        return launch_prolong_red<T, 1>(n, nb, e0, e1, r0, (const T*)lv[1].e0, (const T*)lv[1].e1, ctl, s);
+      }
       *bytes = 1.125 * ts * n3;
       return launch_prolong_black<T, 1>(n, nb, e1, (const T*)lv[1].e0, (const T*)lv[1].e1, ctl, s);
     case KT_TAIL:
