@@ -670,21 +670,27 @@ p3mz_status read_head(p3mz_ctx* c, hipStream_t s) {
   return P3MZ_OK;
 }
 
-// V-cycles: the expected number (the last step's count) is enqueued at
-// once, then the device flag is checked and cycles follow one at a time.
-// Returns the head of the control block after the solve.
-p3mz_status run_solve(p3mz_ctx* c, hipStream_t s) {
+// V-cycles, then the field update and gather (post1): the expected number
+// of cycles (the last step's count) is enqueued at once and post1 right
+// behind it, so a correct guess costs no host round trip inside the mesh
+// step; post1's kernels do nothing unless the solve has converged.  The
+// device flag is read after post1; if the solve is still open, cycles follow
+// one at a time, each followed by post1 again.  Returns with the head of the
+// control block read after the last post1.
+p3mz_status run_solve(p3mz_ctx* c, double* force, hipStream_t s) {
   int issued = 0;
   int batch = std::max(1, c->last_cycles);
   const std::vector<uint64_t> key = {1};
-  while (issued < c->P.max_cycles) {
+  for (;;) {
     for (int b = 0; b < batch && issued < c->P.max_cycles; b++, issued++)
       P3MZ_TRY(run_seq(c, c->g_cycle, key, s, [&](hipStream_t q) { return enq_cycle(c, q); }));
+    P3MZ_TRY(run_seq(c, c->g_post1, {(uint64_t)(uintptr_t)force, c->timing}, s,
+                     [&](hipStream_t q) { return enq_post1(c, force, q); }));
+    stage(c, 3, s);
     P3MZ_TRY(read_head(c, s));
-    if (c->h_ctl->done || c->h_ctl->nan_flag) return P3MZ_OK;
+    if (c->h_ctl->done || c->h_ctl->nan_flag || issued >= c->P.max_cycles) return P3MZ_OK;
     batch = 1;
   }
-  return read_head(c, s);
 }
 
 p3mz_status on_nan(p3mz_ctx* c) {
@@ -768,11 +774,8 @@ p3mz_status mesh_step(p3mz_ctx* c, const double* pos, double* force, double* ene
   c->ran_graphs = false;
   stage(c, 0, s);
   P3MZ_TRY(run_seq(c, c->g_pre, {(uint64_t)(uintptr_t)pos, tm}, s, [&](hipStream_t q) { return enq_pre(c, pos, q); }));
-  P3MZ_TRY(run_solve(c, s));
+  P3MZ_TRY(run_solve(c, force, s));
   if (c->h_ctl->nan_flag) return on_nan(c);
-  P3MZ_TRY(run_seq(c, c->g_post1, {(uint64_t)(uintptr_t)force, tm}, s,
-                   [&](hipStream_t q) { return enq_post1(c, force, q); }));
-  stage(c, 3, s);
   if (md)
     P3MZ_TRY(run_seq(c, c->g_md_post2, post2_key, s, [&](hipStream_t q) { return enq_md_post2(c, *m, q); }));
   else

@@ -77,6 +77,28 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
   return r;
 }
 
+// Max and sum of one value per thread in one pass (one pair of barriers);
+// `sh` needs 2 * blockDim.x/64 doubles.  Results valid in thread 0.
+__device__ __forceinline__ void block_max_sum(double* mx, double* sm, double* sh) {
+  const double m = wave_max(*mx), v = wave_sum(*sm);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (l == 0) {
+    sh[w] = m;
+    sh[nw + w] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < nw; i++) {
+      a = fmax(a, sh[i]);
+      b += sh[nw + i];
+    }
+    *mx = a;
+    *sm = b;
+  }
+}
+
 // Reductions are two-pass: every workgroup of a kernel stores its partial,
 // then a one-workgroup kernel reads them in index order (kernel boundaries
 // make the partials visible across XCDs without device-scope fences in the

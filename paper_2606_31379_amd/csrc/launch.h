@@ -41,7 +41,9 @@ hipError_t launch_spread(bool fp64, int n, int p, int tile, int ntx, const int* 
 // gradient of phi (precision of phi: fp64 or float).
 // phi: FP64 mode reads the new potential from phi0/phi1 (selected on the
 // device), mixed mode reads the FP32 copy phi32.
-// finalize = false launches the per-atom kernel only (back-to-back timing).
+// finalize = false launches the per-atom kernel only (back-to-back timing);
+// with finalize, both kernels do nothing unless ctl->done (the step's solve
+// has converged), so they may be enqueued before the host has checked it.
 hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, int tile, int ntx, double h, double k_e,
                          const int* start, const int* perm, const int* base, const void* w, const double* qa,
                          const double* phi0, const double* phi1, const float* phi32, double* force, double* partial,

@@ -314,24 +314,31 @@ __device__ void Outer<T>::run(const Args& A, Grid G) {
 }
 
 // One workgroup: residual of cycle c, running mean of y, stop decision.
+// The partials are read while the control block's flag is still in flight
+// (both reductions in one pass; fixed split and tree, so deterministic).
 struct FinOuter {
   struct Args {
     int first, max_cycles, nb, n3;
     const double* partial;
     Ctl* ctl;
   };
-  static constexpr int kThreads = kBlock;
+  static constexpr int kThreads = 1024;
   __device__ static void run(const Args& A, Grid G);
 };
 __device__ void FinOuter::run(const Args& A, Grid) {
   const int first = A.first, max_cycles = A.max_cycles, nb = A.nb, n3 = A.n3;
   const double* __restrict__ partial = A.partial;
   Ctl* ctl = A.ctl;
-  __shared__ double sh[kBlock / 64];
-  if (ctl->done) return;
+  __shared__ double sh[2 * kThreads / 64];
+  const int done = ctl->done;
+  double res = 0.0, ys = 0.0;
+  for (int i = threadIdx.x; i < nb; i += kThreads) {
+    res = fmax(res, partial[i]);
+    ys += partial[nb + i];
+  }
+  block_max_sum(&res, &ys, sh);
+  if (done) return;
   const int c = first ? 0 : ctl->cycles + 1;
-  const double res = reduce_partials_max(partial, nb, sh);
-  const double ys = reduce_partials_sum(partial + nb, nb, sh);
   if (threadIdx.x == 0) {
     ctl->res_hist[c] = res;
     ctl->mean_y = ys / (double)n3;
@@ -388,6 +395,20 @@ template <> __device__ __forceinline__ void vset<double>(double2& v, int q, doub
   if (q == 0) v.x = x; else v.y = x;
 }
 
+// Speculative start of the small V-cycle launches: the control block's stop
+// flag and the operands are loaded together and the flag is tested just
+// before the first store, so the two memory round trips of a launch that
+// moves little data overlap.  keep_issued() makes the computed value live
+// before that test (the compiler may not defer the loads past it).  Large
+// levels and batched launches test the flag first instead, so converged
+// systems read nothing.
+__device__ __forceinline__ void keep_issued(float v) { asm volatile("" ::"v"(v)); }
+__device__ __forceinline__ void keep_issued(double v) { asm volatile("" ::"v"(v)); }
+__device__ __forceinline__ void keep_issued(const float4& v) {
+  asm volatile("" ::"v"(v.x), "v"(v.y), "v"(v.z), "v"(v.w));
+}
+__device__ __forceinline__ void keep_issued(const double2& v) { asm volatile("" ::"v"(v.x), "v"(v.y)); }
+
 // cs_nbr6 for the W points t..t+W-1 of one row (same colour, same x-parity
 // s), each neighbour value passed through f first.  x-neighbours come from
 // the row's own vector plus one edge element, y/z neighbours from the vectors
@@ -419,7 +440,7 @@ __device__ __forceinline__ void cs_nbr6_vec(const T* __restrict__ o, const CsGeo
 
 // First pre-smoothing sweep from e = 0: red = -r/6, then black from those reds
 // (one thread per W consecutive points of a row).
-template <typename T, int FIN>
+template <typename T, int FIN, int SPEC>
 struct SweepZero {
   struct Args {
     int n;
@@ -430,14 +451,15 @@ struct SweepZero {
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G);
 };
-template <typename T, int FIN>
-__device__ void SweepZero<T, FIN>::run(const Args& A, Grid G) {
+template <typename T, int FIN, int SPEC>
+__device__ void SweepZero<T, FIN, SPEC>::run(const Args& A, Grid G) {
   const int n = A.n;
   const T* __restrict__ r0 = A.r0;
   const T* __restrict__ r1 = A.r1;
   T* __restrict__ e0 = A.e0;
   T* __restrict__ e1 = A.e1;
-  if (A.ctl->done) return;
+  const int done = A.ctl->done;
+  if (!SPEC && done) return;
   constexpr int W = Vec<T>::W;
   using V = typename Vec<T>::type;
   const CsGeo g(n);
@@ -451,7 +473,6 @@ __device__ void SweepZero<T, FIN>::run(const Args& A, Grid G) {
   V er;
 #pragma unroll
   for (int q = 0; q < W; q++) vset<T>(er, q, -vget<T>(rr, q) * sixth);
-  *reinterpret_cast<V*>(e0 + t) = er;
   // black points of the same row: their neighbours are the red values -r0/6
   T nb[W];
   cs_nbr6_vec(r0, g, t, m, j, k, (1 + j + k) & 1, [sixth](T x) { return -x * sixth; }, nb);
@@ -459,10 +480,15 @@ __device__ void SweepZero<T, FIN>::run(const Args& A, Grid G) {
   V eb;
 #pragma unroll
   for (int q = 0; q < W; q++) vset<T>(eb, q, (nb[q] - vget<T>(rb, q)) * sixth);
+  if (SPEC) {
+    keep_issued(eb);
+    if (done) return;
+  }
+  *reinterpret_cast<V*>(e0 + t) = er;
   *reinterpret_cast<V*>(e1 + t) = eb;
 }
 
-template <typename T, int FIN>
+template <typename T, int FIN, int SPEC>
 struct Halfsweep {
   struct Args {
     int n, colour;
@@ -473,13 +499,14 @@ struct Halfsweep {
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G);
 };
-template <typename T, int FIN>
-__device__ void Halfsweep<T, FIN>::run(const Args& A, Grid G) {
+template <typename T, int FIN, int SPEC>
+__device__ void Halfsweep<T, FIN, SPEC>::run(const Args& A, Grid G) {
   const int n = A.n, colour = A.colour;
   T* __restrict__ ec = A.ec;
   const T* __restrict__ eo = A.eo;
   const T* __restrict__ rc = A.rc;
-  if (A.ctl->done) return;
+  const int done = A.ctl->done;
+  if (!SPEC && done) return;
   constexpr int W = Vec<T>::W;
   using V = typename Vec<T>::type;
   const CsGeo g(n);
@@ -494,6 +521,10 @@ __device__ void Halfsweep<T, FIN>::run(const Args& A, Grid G) {
   V out;
 #pragma unroll
   for (int q = 0; q < W; q++) vset<T>(out, q, (nb[q] - vget<T>(r, q)) * T(1.0 / 6.0));
+  if (SPEC) {
+    keep_issued(out);
+    if (done) return;
+  }
   *reinterpret_cast<V*>(ec + t) = out;
 }
 
@@ -502,7 +533,7 @@ __device__ void Halfsweep<T, FIN>::run(const Args& A, Grid G) {
 // When the last pre-smoothing operation was a black half-sweep, the black
 // residuals are zero up to rounding (Gauss-Seidel just solved those rows), so
 // only the 13 red points of the 27-point stencil are evaluated (red_only).
-template <typename T, int FIN>
+template <typename T, int FIN, int SPEC>
 struct ResidRestrict {
   struct Args {
     int n, red_only;
@@ -510,11 +541,13 @@ struct ResidRestrict {
     T *rc0, *rc1;
     const Ctl* ctl;
   };
-  static constexpr int kThreads = kBlock;
+  // one thread per coarse point: small workgroups spread the few coarse
+  // points of the upper-middle levels over every compute unit
+  static constexpr int kThreads = 64;
   __device__ static void run(const Args& A, Grid G);
 };
-template <typename T, int FIN>
-__device__ void ResidRestrict<T, FIN>::run(const Args& A, Grid G) {
+template <typename T, int FIN, int SPEC>
+__device__ void ResidRestrict<T, FIN, SPEC>::run(const Args& A, Grid G) {
   const int n = A.n, red_only = A.red_only;
   const T* __restrict__ e0 = A.e0;
   const T* __restrict__ e1 = A.e1;
@@ -522,10 +555,11 @@ __device__ void ResidRestrict<T, FIN>::run(const Args& A, Grid G) {
   const T* __restrict__ r1 = A.r1;
   T* __restrict__ rc0 = A.rc0;
   T* __restrict__ rc1 = A.rc1;
-  if (A.ctl->done) return;
+  const int done = A.ctl->done;
+  if (!SPEC && done) return;
   const CsGeo g(n), gc(n >> 1);
   const int nc = gc.n;
-  const int t = G.b * kBlock + threadIdx.x;
+  const int t = G.b * kThreads + threadIdx.x;
   if (t >= nc * nc * nc) return;
   const int I = t & (nc - 1), J = (t >> gc.l2) & (nc - 1), K = t >> (2 * gc.l2);
   const T wt[3] = {T(0.25), T(0.5), T(0.25)};
@@ -549,8 +583,98 @@ __device__ void ResidRestrict<T, FIN>::run(const Args& A, Grid G) {
       s += wt[b + 1] * wt[c + 1] * row;
     }
   }
+  const T v = T(4) * s;
+  if (SPEC) {
+    keep_issued(v);
+    if (done) return;
+  }
   T* out = ((I + J + K) & 1) ? rc1 : rc0;
-  out[cs_index(gc, I, J, K)] = T(4) * s;
+  out[cs_index(gc, I, J, K)] = v;
+}
+
+// ResidRestrict for red_only, W = Vec<T>::W consecutive coarse points of a
+// coarse row per thread: the red residuals of each of the 9 fine rows are
+// formed as one row vector (the neighbour sums of a half-sweep) plus, in rows
+// whose red points sit at odd x, the one residual left of the vector; every
+// coarse point then sums its 13 red terms in the order of ResidRestrict, so
+// the results are those of the one-point-per-thread kernel.
+template <typename T, int FIN, int SPEC>
+struct RestrictRed {
+  using Args = typename ResidRestrict<T, FIN, SPEC>::Args;
+  static constexpr int kThreads = 64;
+  __device__ static void run(const Args& A, Grid G);
+};
+template <typename T, int FIN, int SPEC>
+__device__ void RestrictRed<T, FIN, SPEC>::run(const Args& A, Grid G) {
+  constexpr int W = Vec<T>::W;
+  using V = typename Vec<T>::type;
+  const int n = A.n;
+  const T* __restrict__ e0 = A.e0;
+  const T* __restrict__ e1 = A.e1;
+  const T* __restrict__ r0 = A.r0;
+  const int done = A.ctl->done;
+  if (!SPEC && done) return;
+  const CsGeo g(n), gc(n >> 1);
+  const int nc = gc.n;
+  const int t = (G.b * kThreads + threadIdx.x) * W;
+  if (t >= nc * nc * nc) return;
+  const int I0 = t & (nc - 1), J = (t >> gc.l2) & (nc - 1), K = t >> (2 * gc.l2);
+  const T wt[3] = {T(0.25), T(0.5), T(0.25)};
+  const int msk = n - 1;
+  T s[W];
+#pragma unroll
+  for (int q = 0; q < W; q++) s[q] = T(0);
+  for (int c = -1; c <= 1; c++) {
+    const int z = (2 * K + c) & msk;
+    for (int b = -1; b <= 1; b++) {
+      const int y = (2 * J + b) & msk;
+      const int par = (y + z) & 1;   // red points of this row sit at x = 2m + par
+      const int row0 = ((z << g.l2) + y) << (g.l2 - 1);
+      const int tv = row0 + I0;
+      T nb[W];
+      cs_nbr6_vec(e1, g, tv, I0, y, z, par, [](T x) { return x; }, nb);
+      const V ev = *reinterpret_cast<const V*>(e0 + tv);
+      const V rv = *reinterpret_cast<const V*>(r0 + tv);
+      T rho[W];
+#pragma unroll
+      for (int q = 0; q < W; q++) rho[q] = vget<T>(rv, q) - (nb[q] - T(6) * vget<T>(ev, q));
+      const T wbc = wt[b + 1] * wt[c + 1];
+      if (par == 0) {
+        // only x = 2I is red: m = I
+#pragma unroll
+        for (int q = 0; q < W; q++) {
+          T row = T(0);
+          row += wt[1] * rho[q];
+          s[q] += wbc * row;
+        }
+      } else {
+        // x = 2I - 1 (m = I - 1) and x = 2I + 1 (m = I)
+        const int me = (I0 - 1) & (nc - 1);
+        const int te = row0 + me;
+        const T rho_e = r0[te] - (cs_nbr6(e1, g, te, me, y, z, 1) - T(6) * e0[te]);
+#pragma unroll
+        for (int q = 0; q < W; q++) {
+          T row = T(0);
+          row += wt[0] * (q == 0 ? rho_e : rho[q - 1]);
+          row += wt[2] * rho[q];
+          s[q] += wbc * row;
+        }
+      }
+    }
+  }
+  T v[W];
+#pragma unroll
+  for (int q = 0; q < W; q++) v[q] = T(4) * s[q];
+  if (SPEC) {
+    keep_issued(v[W - 1]);
+    if (done) return;
+  }
+#pragma unroll
+  for (int q = 0; q < W; q++) {
+    const int I = I0 + q;
+    T* out = ((I + J + K) & 1) ? A.rc1 : A.rc0;
+    out[cs_index(gc, I, J, K)] = v[q];
+  }
 }
 
 // Trilinear interpolation of the coarse correction (colour-split, geometry
@@ -576,28 +700,60 @@ __device__ __forceinline__ T prolong_at(const T* __restrict__ c0, const T* __res
   return s;
 }
 
-// Prolongation fused with the first red half-sweep after it (levels where
-// launches, not bytes, dominate): each red point sums its six black
-// neighbours, each plus its trilinear coarse correction (the same value and
-// rounding prolongation would have stored there), in the order of cs_nbr6.
-// The black points keep their uncorrected values: the black half-sweep that
-// follows rewrites every one of them from the red points alone.
-template <typename T, int FIN>
-struct ProlongRed {
-  struct Args {
-    int n;
-    T* e0;
-    const T *e1, *r0, *ec0, *ec1;
-    const Ctl* ctl;
-  };
-  static constexpr int kThreads = kBlock;
-  __device__ static void run(const Args& A, Grid G);
-};
+// Black points x = 2m + sx, m = m0 .. m0+W-1, of the row (j,k) holding the
+// colour-split index t, plus their trilinear coarse correction: weights and
+// coarse indices as in prolong_at, summed in its order with exact zeros
+// interleaved (so the values equal e1[t+q] + prolong_at(...) exactly); the
+// coarse values of each coarse row are loaded once for the W points.
+template <typename T>
+__device__ __forceinline__ typename Vec<T>::type prolong_black_vec(const T* e1, const T* ec0, const T* ec1,
+                                                                  const CsGeo& g, const CsGeo& gc, int t) {
+  constexpr int W = Vec<T>::W;
+  using V = typename Vec<T>::type;
+  int m0, j, k;
+  cs_decode(g, t, &m0, &j, &k);
+  const int sx = (1 + j + k) & 1, cm = gc.n - 1;
+  const int y0 = j >> 1, z0 = k >> 1;
+  const int ys[2] = {y0, (j & 1) ? ((y0 + 1) & cm) : y0};
+  const int zs[2] = {z0, (k & 1) ? ((z0 + 1) & cm) : z0};
+  const T hx = sx ? T(0.5) : T(1), hy = (j & 1) ? T(0.5) : T(1), hz = (k & 1) ? T(0.5) : T(1);
+  // a coarse row that an even fine index does not use (second y or z entry)
+  // gets weight 0: it adds exact zeros, so all four rows can be loaded at once
+  const T wy[2] = {hy, (j & 1) ? hy : T(0)}, wz[2] = {hz, (k & 1) ? hz : T(0)};
+  const T wx1 = sx ? T(1) : T(0);
+  T acc[W];
+#pragma unroll
+  for (int q = 0; q < W; q++) acc[q] = T(0);
+#pragma unroll
+  for (int c = 0; c < 2; c++)
+#pragma unroll
+    for (int b = 0; b < 2; b++) {
+      const int Y = ys[b], Z = zs[c];
+      const int crow = ((Z << gc.l2) + Y) << (gc.l2 - 1);
+      const T w = hx * wy[b] * wz[c];
+      T cv[W + 1];   // coarse values at X = m0 .. m0+W (wrapped)
+#pragma unroll
+      for (int q = 0; q <= W; q++) {
+        const int X = (m0 + q) & cm;
+        cv[q] = (((X + Y + Z) & 1) ? ec1 : ec0)[crow + (X >> 1)];
+      }
+#pragma unroll
+      for (int q = 0; q < W; q++) {
+        acc[q] += w * cv[q];
+        acc[q] += (w * wx1) * cv[q + 1];
+      }
+    }
+  const V old = *reinterpret_cast<const V*>(e1 + t);
+  V out;
+#pragma unroll
+  for (int q = 0; q < W; q++) vset<T>(out, q, vget<T>(old, q) + acc[q]);
+  return out;
+}
 
 // After prolongation the next red half-sweep overwrites every red value and
 // reads only black neighbours, so only the black points receive the
 // trilinear correction here; the red half-sweep follows.
-template <typename T, int FIN>
+template <typename T, int FIN, int SPEC>
 struct ProlongBlack {
   struct Args {
     int n;
@@ -608,40 +764,26 @@ struct ProlongBlack {
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G);
 };
-template <typename T, int FIN>
-__device__ void ProlongBlack<T, FIN>::run(const Args& A, Grid G) {
+template <typename T, int FIN, int SPEC>
+__device__ void ProlongBlack<T, FIN, SPEC>::run(const Args& A, Grid G) {
+  constexpr int W = Vec<T>::W;
+  using V = typename Vec<T>::type;
   const int n = A.n;
   T* __restrict__ e1 = A.e1;
   const T* __restrict__ ec0 = A.ec0;
   const T* __restrict__ ec1 = A.ec1;
-  if (A.ctl->done) return;
+  const int done = A.ctl->done;
+  if (!SPEC && done) return;
   const CsGeo g(n), gc(n >> 1);
   const int half = n * g.hn * n;
-  const int t = G.b * kBlock + threadIdx.x;
+  const int t = (G.b * kBlock + threadIdx.x) * W;
   if (t >= half) return;
-  int m, j, k;
-  cs_decode(g, t, &m, &j, &k);
-  const int ib = 2 * m + ((1 + j + k) & 1);
-  e1[t] += prolong_at(ec0, ec1, gc, ib, j, k);
-}
-
-template <typename T, int FIN>
-__device__ void ProlongRed<T, FIN>::run(const Args& A, Grid G) {
-  if (A.ctl->done) return;
-  const int n = A.n;
-  const CsGeo g(n), gc(n >> 1);
-  const int half = n * g.hn * n;
-  const int t = G.b * kBlock + threadIdx.x;
-  if (t >= half) return;
-  int m, j, k;
-  cs_decode(g, t, &m, &j, &k);
-  const int i = 2 * m + ((j + k) & 1);   // red point
-  const int msk = n - 1;
-  const T* __restrict__ e1 = A.e1;
-  auto V = [&](int x, int y, int z) { return e1[cs_index(g, x, y, z)] + prolong_at(A.ec0, A.ec1, gc, x, y, z); };
-  const T nb = ((V((i - 1) & msk, j, k) + V((i + 1) & msk, j, k)) + (V(i, (j - 1) & msk, k) + V(i, (j + 1) & msk, k))) +
-               (V(i, j, (k - 1) & msk) + V(i, j, (k + 1) & msk));
-  A.e0[t] = (nb - A.r0[t]) * T(1.0 / 6.0);
+  const V out = prolong_black_vec(e1, ec0, ec1, g, gc, t);
+  if (SPEC) {
+    keep_issued(out);
+    if (done) return;
+  }
+  *reinterpret_cast<V*>(e1 + t) = out;
 }
 
 template <typename T>
@@ -694,31 +836,83 @@ struct FillZero {
 
 // ---------------------------------------------------------------------------
 // Tail of the V-cycle: all levels from n0 <= 16 down to 4^3 and back in one
-// workgroup, LDS-resident in natural layout, with the exact coarsest solve
-// e = G * r (G the periodic 4^3 Green's function of M, FP64 accumulation).
+// workgroup, LDS-resident in the same colour-split layout as the upper
+// levels, with the exact coarsest solve e = G * r (G the periodic 4^3
+// Green's function of M, FP64 accumulation).  Each phase performs the
+// operation of the corresponding multi-workgroup kernel above with the same
+// order of operations, so a level's result does not depend on where it runs;
+// sweeps, the first sweep from zero and the residual work on 16-byte row
+// vectors.  LDS per level q (edge n_q = n0 >> q): e0, e1, r0, r1 of
+// n_q^3/2 elements each, then the red residuals of the current level.
 // ---------------------------------------------------------------------------
+// Full weighting x 4 at the coarse points I0 .. I0+W-1 of coarse row (J,K)
+// from the red residuals rho (red colour array of the fine level; the black
+// residuals are zero), with the terms and their order of ResidRestrict.
 template <typename T>
-__device__ __forceinline__ T lds_nbr(const T* v, int n, int l2, int i, int j, int k) {
-  const int msk = n - 1;
-  const int row = (k << l2) + j;
-  const int rjm = (k << l2) + ((j - 1) & msk), rjp = (k << l2) + ((j + 1) & msk);
-  const int rkm = (((k - 1) & msk) << l2) + j, rkp = (((k + 1) & msk) << l2) + j;
-  return ((v[(row << l2) + ((i - 1) & msk)] + v[(row << l2) + ((i + 1) & msk)]) +
-          (v[(rjm << l2) + i] + v[(rjp << l2) + i])) +
-         (v[(rkm << l2) + i] + v[(rkp << l2) + i]);
+__device__ __forceinline__ void restrict_red_vec(const T* rho, const CsGeo& g, int I0, int J, int K, T* v) {
+  constexpr int W = Vec<T>::W;
+  using V = typename Vec<T>::type;
+  const T wt[3] = {T(0.25), T(0.5), T(0.25)};
+  const int msk = g.n - 1, hm = g.hn - 1;
+  T s[W];
+#pragma unroll
+  for (int q = 0; q < W; q++) s[q] = T(0);
+#pragma unroll
+  for (int c = -1; c <= 1; c++) {
+    const int z = (2 * K + c) & msk;
+#pragma unroll
+    for (int b = -1; b <= 1; b++) {
+      const int y = (2 * J + b) & msk;
+      const int row0 = ((z << g.l2) + y) << (g.l2 - 1);
+      const V rv = *reinterpret_cast<const V*>(rho + row0 + I0);
+      const T wbc = wt[b + 1] * wt[c + 1];
+      if (((b + c) & 1) == 0) {
+#pragma unroll
+        for (int q = 0; q < W; q++) {
+          T row = T(0);
+          row += wt[1] * vget<T>(rv, q);
+          s[q] += wbc * row;
+        }
+      } else {
+        const T re = rho[row0 + ((I0 - 1) & hm)];
+#pragma unroll
+        for (int q = 0; q < W; q++) {
+          T row = T(0);
+          row += wt[0] * (q == 0 ? re : vget<T>(rv, q - 1));
+          row += wt[2] * vget<T>(rv, q);
+          s[q] += wbc * row;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < W; q++) v[q] = T(4) * s[q];
 }
 
-// One red (colour 0) or black half-sweep over an LDS-resident level of edge
-// n = 2^l2, natural layout.
+__device__ __forceinline__ int tail_level_offset(int n0, int q) {
+  int off = 0;
+  for (int p = 0; p < q; p++) {
+    const int n = n0 >> p;
+    off += 2 * n * n * n;
+  }
+  return off;
+}
+
+// One half-sweep of colour `colour` (Halfsweep on LDS arrays).
 template <typename T>
-__device__ __forceinline__ void tail_rbgs(T* e, const T* r, int n, int l2, int colour) {
-  const int half = 1 << (3 * l2 - 1);
-  for (int p = threadIdx.x; p < half; p += blockDim.x) {
-    const int m = p & ((n >> 1) - 1), row = p >> (l2 - 1);
-    const int j = row & (n - 1), k = row >> l2;
-    const int i = 2 * m + ((colour + j + k) & 1);
-    const int a = (row << l2) + i;
-    e[a] = (lds_nbr(e, n, l2, i, j, k) - r[a]) * T(1.0 / 6.0);
+__device__ __forceinline__ void tail_half(T* ec, const T* eo, const T* rc, const CsGeo& g, int half, int colour) {
+  constexpr int W = Vec<T>::W;
+  using V = typename Vec<T>::type;
+  for (int t = threadIdx.x * W; t < half; t += blockDim.x * W) {
+    int m, j, k;
+    cs_decode(g, t, &m, &j, &k);
+    T nb[W];
+    cs_nbr6_vec(eo, g, t, m, j, k, (colour + j + k) & 1, [](T x) { return x; }, nb);
+    const V r = *reinterpret_cast<const V*>(rc + t);
+    V out;
+#pragma unroll
+    for (int q = 0; q < W; q++) vset<T>(out, q, (nb[q] - vget<T>(r, q)) * T(1.0 / 6.0));
+    *reinterpret_cast<V*>(ec + t) = out;
   }
 }
 
@@ -737,143 +931,192 @@ struct Tail {
 template <typename T>
 __device__ void Tail<T>::run(const Args& A, Grid) {
   const int n0 = A.n0, levels = A.levels, nu1 = A.nu1, nu2 = A.nu2;
-  const T* __restrict__ r0g = A.r0;
-  const T* __restrict__ r1g = A.r1;
-  T* __restrict__ e0g = A.e0;
-  T* __restrict__ e1g = A.e1;
-  const double* __restrict__ green = A.green;
   const Ctl* ctl = A.ctl;
-  if (ctl && ctl->done) return;
-  extern __shared__ unsigned char smem_raw[];
+  // the stop flag is tested after the first loads are in flight (as in the
+  // speculative upper-level launches); every wave reads the same flag
+  const int done = ctl ? ctl->done : 0;
+  constexpr int W = Vec<T>::W;
+  using V = typename Vec<T>::type;
+  extern __shared__ __align__(16) unsigned char tail_lds[];
   __shared__ double G[64];
-  T* base = reinterpret_cast<T*>(smem_raw);
-  T* E[P3MZ_MAX_LEVELS];
-  T* R[P3MZ_MAX_LEVELS];
-  int l20 = 0;
-  while ((1 << l20) < n0) l20++;
-  int off = 0;
-  for (int q = 0; q < levels; q++) {
-    const int c = 1 << (3 * (l20 - q));
-    E[q] = base + off; off += c;
-    R[q] = base + off; off += c;
-  }
-  T* rho = base + off;
+  T* const base = reinterpret_cast<T*>(tail_lds);
+  T* const rho = base + tail_level_offset(n0, levels);
   const int tid = threadIdx.x, nt = blockDim.x;
-  if (tid < 64) G[tid] = green[tid];
+  if (tid < 64) G[tid] = A.green[tid];
   {
-    const int n3 = 1 << (3 * l20), msk = n0 - 1;
-    for (int p = tid; p < n3; p += nt) {
-      const int i = p & msk, j = (p >> l20) & msk, k = p >> (2 * l20);
-      const T* src = ((i + j + k) & 1) ? r1g : r0g;
-      R[0][p] = src[cs_idx(n0, i, j, k)];
+    const int half = n0 * n0 * n0 / 2;
+    T* r0 = base + 2 * half;
+    T* r1 = r0 + half;
+    for (int t = tid; t < half; t += nt) {
+      r0[t] = A.r0[t];
+      r1[t] = A.r1[t];
     }
   }
+  if (done) return;
   __syncthreads();
   const T wt[3] = {T(0.25), T(0.5), T(0.25)};
   for (int q = 0; q + 1 < levels; q++) {
-    const int l2 = l20 - q, n = 1 << l2, n3 = 1 << (3 * l2), msk = n - 1;
-    const int lc = l2 - 1, nc = n >> 1, nc3 = 1 << (3 * lc);
-    T* e = E[q];
-    const T* r = R[q];
+    const int n = n0 >> q, half = n * n * n / 2;
+    T* e0 = base + tail_level_offset(n0, q);
+    T* e1 = e0 + half;
+    T* r0 = e1 + half;
+    T* r1 = r0 + half;
+    const CsGeo g(n);
     if (nu1 >= 1) {
-      // first red half-sweep from e = 0: e = -r/6 at the red points
-      const int half = n3 >> 1;
-      for (int pp = tid; pp < half; pp += nt) {
-        const int m = pp & ((n >> 1) - 1), row = pp >> (l2 - 1);
-        const int j = row & (n - 1), k = row >> l2;
-        const int a = (row << l2) + 2 * m + ((j + k) & 1);
-        e[a] = (T(0) - r[a]) * T(1.0 / 6.0);
+      // first sweep from e = 0 (SweepZero): red = -r/6, black from those reds
+      const T sixth = T(1.0 / 6.0);
+      for (int t = tid * W; t < half; t += nt * W) {
+        int m, j, k;
+        cs_decode(g, t, &m, &j, &k);
+        const V rr = *reinterpret_cast<const V*>(r0 + t);
+        V er;
+#pragma unroll
+        for (int c = 0; c < W; c++) vset<T>(er, c, -vget<T>(rr, c) * sixth);
+        *reinterpret_cast<V*>(e0 + t) = er;
+        T nb[W];
+        cs_nbr6_vec(r0, g, t, m, j, k, (1 + j + k) & 1, [sixth](T x) { return -x * sixth; }, nb);
+        const V rb = *reinterpret_cast<const V*>(r1 + t);
+        V eb;
+#pragma unroll
+        for (int c = 0; c < W; c++) vset<T>(eb, c, (nb[c] - vget<T>(rb, c)) * sixth);
+        *reinterpret_cast<V*>(e1 + t) = eb;
       }
       __syncthreads();
-      tail_rbgs(e, r, n, l2, 1);
-      __syncthreads();
-      for (int s = 1; s < nu1; s++) {
-        tail_rbgs(e, r, n, l2, 0);
+      for (int it = 1; it < nu1; it++) {
+        tail_half(e0, e1, r0, g, half, 0);
         __syncthreads();
-        tail_rbgs(e, r, n, l2, 1);
+        tail_half(e1, e0, r1, g, half, 1);
         __syncthreads();
+      }
+      // residual at the red points; after the black half-sweep the black
+      // residuals vanish up to rounding and are taken as zero (ResidRestrict)
+      for (int t = tid * W; t < half; t += nt * W) {
+        int m, j, k;
+        cs_decode(g, t, &m, &j, &k);
+        T nb[W];
+        cs_nbr6_vec(e1, g, t, m, j, k, (j + k) & 1, [](T x) { return x; }, nb);
+        const V ev = *reinterpret_cast<const V*>(e0 + t);
+        const V rv = *reinterpret_cast<const V*>(r0 + t);
+        V out;
+#pragma unroll
+        for (int c = 0; c < W; c++) vset<T>(out, c, vget<T>(rv, c) - (nb[c] - T(6) * vget<T>(ev, c)));
+        *reinterpret_cast<V*>(rho + t) = out;
       }
     } else {
-      for (int p = tid; p < n3; p += nt) e[p] = T(0);
-      __syncthreads();
-    }
-    // residual; after a black half-sweep the black residuals vanish up to
-    // rounding and are taken as zero, as on the upper levels
-    for (int p = tid; p < n3; p += nt) {
-      const int i = p & msk, j = (p >> l2) & msk, k = p >> (2 * l2);
-      rho[p] = (nu1 >= 1 && ((i + j + k) & 1)) ? T(0) : r[p] - (lds_nbr(e, n, l2, i, j, k) - T(6) * e[p]);
+      // no pre-smoothing: e = 0 and the residual is r itself
+      for (int t = tid; t < half; t += nt) {
+        e0[t] = T(0);
+        e1[t] = T(0);
+      }
     }
     __syncthreads();
-    for (int p = tid; p < nc3; p += nt) {
-      const int I = p & (nc - 1), J = (p >> lc) & (nc - 1), K = p >> (2 * lc);
-      T s = T(0);
-      for (int c = -1; c <= 1; c++) {
-        const int z = (2 * K + c) & msk;
-        for (int b = -1; b <= 1; b++) {
-          const int y = (2 * J + b) & msk;
-          const T* rowp = rho + (((z << l2) + y) << l2);
-          const T row = wt[0] * rowp[(2 * I - 1) & msk] + wt[1] * rowp[2 * I] + wt[2] * rowp[(2 * I + 1) & msk];
-          s += wt[b + 1] * wt[c + 1] * row;
+    {
+      // full weighting x 4 into the next level's right-hand side
+      const int nc = n >> 1, hc = nc * nc * nc / 2, msk = n - 1;
+      const CsGeo gc(nc);
+      T* rc0 = base + tail_level_offset(n0, q + 1) + 2 * hc;
+      T* rc1 = rc0 + hc;
+      if (nu1 >= 1) {
+        for (int p = tid * W; p < nc * nc * nc; p += nt * W) {
+          const int I0 = p & (nc - 1), J = (p >> gc.l2) & (nc - 1), K = p >> (2 * gc.l2);
+          T v[W];
+          restrict_red_vec(rho, g, I0, J, K, v);
+#pragma unroll
+          for (int q = 0; q < W; q++) {
+            const int I = I0 + q;
+            (((I + J + K) & 1) ? rc1 : rc0)[cs_index(gc, I, J, K)] = v[q];
+          }
+        }
+      } else {
+        // no pre-smoothing: the residual is r at every point
+        for (int p = tid; p < nc * nc * nc; p += nt) {
+          const int I = p & (nc - 1), J = (p >> gc.l2) & (nc - 1), K = p >> (2 * gc.l2);
+          T s = T(0);
+          for (int c = -1; c <= 1; c++) {
+            const int z = (2 * K + c) & msk;
+            for (int b = -1; b <= 1; b++) {
+              const int y = (2 * J + b) & msk;
+              T row = T(0);
+              for (int a = -1; a <= 1; a++) {
+                const int x = (2 * I + a) & msk;
+                const int odd = (x + y + z) & 1;
+                const int ti = cs_index(g, x, y, z);
+                row += wt[a + 1] * (odd ? r1[ti] : r0[ti]);
+              }
+              s += wt[b + 1] * wt[c + 1] * row;
+            }
+          }
+          T* out = ((I + J + K) & 1) ? rc1 : rc0;
+          out[cs_index(gc, I, J, K)] = T(4) * s;
         }
       }
-      R[q + 1][p] = T(4) * s;
     }
     __syncthreads();
   }
   {
     // 4^3: e = G * r with FP64 accumulation; 16 consecutive lanes share one
     // output point, each summing 4 of the 64 terms, then a fixed shuffle tree
-    const int q = levels - 1;
+    const int q = levels - 1, half = 32;
+    T* e0 = base + tail_level_offset(n0, q);
+    T* e1 = e0 + half;
+    const T* r0 = e1 + half;
+    const T* r1 = r0 + half;
+    const CsGeo g4(4);
     const int o = tid >> 4, part = tid & 15;
     double s = 0.0;
     if (o < 64) {
       const int x = o & 3, y = (o >> 2) & 3, z = o >> 4;
       for (int mm = part * 4; mm < part * 4 + 4; mm++) {
         const int a = mm & 3, b = (mm >> 2) & 3, c = mm >> 4;
-        s += G[(((z - c) & 3) * 4 + ((y - b) & 3)) * 4 + ((x - a) & 3)] * (double)R[q][mm];
+        const T rv = ((a + b + c) & 1) ? r1[cs_index(g4, a, b, c)] : r0[cs_index(g4, a, b, c)];
+        s += G[(((z - c) & 3) * 4 + ((y - b) & 3)) * 4 + ((x - a) & 3)] * (double)rv;
       }
     }
     for (int d = 8; d > 0; d >>= 1) s += __shfl_xor(s, d, 16);
-    if (o < 64 && part == 0) E[q][o] = (T)s;
+    if (o < 64 && part == 0) {
+      const int x = o & 3, y = (o >> 2) & 3, z = o >> 4;
+      (((x + y + z) & 1) ? e1 : e0)[cs_index(g4, x, y, z)] = (T)s;
+    }
     __syncthreads();
   }
   for (int q = levels - 2; q >= 0; q--) {
-    const int l2 = l20 - q, n = 1 << l2, n3 = 1 << (3 * l2), msk = n - 1;
-    const int lc = l2 - 1, nc = n >> 1, cm = nc - 1;
-    T* e = E[q];
-    const T* ec = E[q + 1];
-    for (int p = tid; p < n3; p += nt) {
-      const int x = p & msk, y = (p >> l2) & msk, z = p >> (2 * l2);
+    const int n = n0 >> q, half = n * n * n / 2, hc = half / 8;
+    T* e0 = base + tail_level_offset(n0, q);
+    T* e1 = e0 + half;
+    const T* r0 = e1 + half;
+    const T* r1 = r0 + half;
+    const T* c0 = base + tail_level_offset(n0, q + 1);
+    const T* c1 = c0 + hc;
+    const CsGeo g(n), gc(n >> 1);
+    if (nu2 >= 1) {
       // the next red half-sweep overwrites every red point: only black points
-      // need the correction when post-smoothing follows
-      if (nu2 >= 1 && !((x + y + z) & 1)) continue;
-      const int x0 = x >> 1, y0 = y >> 1, z0 = z >> 1;
-      const int x1 = (x & 1) ? ((x0 + 1) & cm) : x0;
-      const int y1 = (y & 1) ? ((y0 + 1) & cm) : y0;
-      const int z1 = (z & 1) ? ((z0 + 1) & cm) : z0;
-      const T hx = (x & 1) ? T(0.5) : T(1), hy = (y & 1) ? T(0.5) : T(1), hz = (z & 1) ? T(0.5) : T(1);
-      const int xs[2] = {x0, x1}, ys[2] = {y0, y1}, zs[2] = {z0, z1};
-      const int nx = (x & 1) ? 2 : 1, ny = (y & 1) ? 2 : 1, nz = (z & 1) ? 2 : 1;
-      T s = T(0);
-      for (int c = 0; c < nz; c++)
-        for (int b = 0; b < ny; b++)
-          for (int a = 0; a < nx; a++) s += hx * hy * hz * ec[(((zs[c] << lc) + ys[b]) << lc) + xs[a]];
-      e[p] += s;
-    }
-    __syncthreads();
-    for (int s = 0; s < nu2; s++) {
-      tail_rbgs(e, R[q], n, l2, 0);
+      // take the correction (ProlongBlack)
+      for (int t = tid * W; t < half; t += nt * W)
+        *reinterpret_cast<V*>(e1 + t) = prolong_black_vec(e1, c0, c1, g, gc, t);
       __syncthreads();
-      tail_rbgs(e, R[q], n, l2, 1);
+      for (int it = 0; it < nu2; it++) {
+        tail_half(e0, e1, r0, g, half, 0);
+        __syncthreads();
+        tail_half(e1, e0, r1, g, half, 1);
+        __syncthreads();
+      }
+    } else {
+      for (int t = tid; t < half; t += nt) {
+        int m, j, k;
+        cs_decode(g, t, &m, &j, &k);
+        e0[t] += prolong_at(c0, c1, gc, 2 * m + ((j + k) & 1), j, k);
+        e1[t] += prolong_at(c0, c1, gc, 2 * m + ((1 + j + k) & 1), j, k);
+      }
       __syncthreads();
     }
   }
   {
-    const int n3 = 1 << (3 * l20), msk = n0 - 1;
-    for (int p = tid; p < n3; p += nt) {
-      const int i = p & msk, j = (p >> l20) & msk, k = p >> (2 * l20);
-      T* dst = ((i + j + k) & 1) ? e1g : e0g;
-      dst[cs_idx(n0, i, j, k)] = E[0][p];
+    const int half = n0 * n0 * n0 / 2;
+    const T* e0 = base;
+    const T* e1 = base + half;
+    for (int t = tid * W; t < half; t += nt * W) {
+      *reinterpret_cast<V*>(A.e0 + t) = *reinterpret_cast<const V*>(e0 + t);
+      *reinterpret_cast<V*>(A.e1 + t) = *reinterpret_cast<const V*>(e1 + t);
     }
   }
 }
@@ -881,10 +1124,10 @@ __device__ void Tail<T>::run(const Args& A, Grid) {
 size_t tail_lds_bytes(int n0, int levels, size_t elem) {
   size_t tot = 0;
   for (int q = 0; q < levels; q++) {
-    size_t nq = (size_t)(n0 >> q);
-    tot += 2 * nq * nq * nq;
+    const size_t nq = (size_t)(n0 >> q);
+    tot += 2 * nq * nq * nq;   // e0, e1, r0, r1 of nq^3/2 each
   }
-  tot += (size_t)n0 * n0 * n0;
+  tot += (size_t)n0 * n0 * n0 / 2;   // red residuals
   return tot * elem;
 }
 
@@ -919,7 +1162,7 @@ __device__ void PhiUpdate::run(const Args& A, Grid G) {
   float* __restrict__ phi32 = A.phi32;
   const Ctl* ctl = A.ctl;
   const int t = G.b * kBlock + threadIdx.x;
-  if (t >= n3) return;
+  if (t >= n3 || !ctl->done) return;   // enqueued ahead of the convergence check
   const int cold = ctl->cold;
   double* pk = ctl->k_idx ? phi1 : phi0;
   double* pkm1 = ctl->k_idx ? phi0 : phi1;
@@ -1011,29 +1254,38 @@ template <typename T>
 int sweep_blocks(int n) {
   return blocks_for((int64_t)n * n * n / 2 / Vec<T>::W, kBlock);
 }
+// Levels up to this edge start speculatively (see keep_issued): a launch
+// there moves a few MB at most, so a launch after convergence costs little
+// more than its early return would.  Batched launches never speculate.
+constexpr int kSpeculateMax = 128;
+inline int speculate(int n) { return (n <= kSpeculateMax && g_recorder == nullptr) ? 1 : 0; }
 template <typename T, int FIN>
 hipError_t launch_sweep0(int n, T* r0, T* r1, T* e0, T* e1, Ctl* ctl, hipStream_t s) {
-  return go<SweepZero<T, FIN>>({n, r0, r1, e0, e1, ctl}, sweep_blocks<T>(n), 0, s);
+  if (speculate(n)) return go<SweepZero<T, FIN, 1>>({n, r0, r1, e0, e1, ctl}, sweep_blocks<T>(n), 0, s);
+  return go<SweepZero<T, FIN, 0>>({n, r0, r1, e0, e1, ctl}, sweep_blocks<T>(n), 0, s);
 }
 template <typename T, int FIN>
 hipError_t launch_half(int n, int colour, T* ec, const T* eo, const T* rc, Ctl* ctl, hipStream_t s) {
-  return go<Halfsweep<T, FIN>>({n, colour, ec, eo, rc, ctl}, sweep_blocks<T>(n), 0, s);
+  if (speculate(n)) return go<Halfsweep<T, FIN, 1>>({n, colour, ec, eo, rc, ctl}, sweep_blocks<T>(n), 0, s);
+  return go<Halfsweep<T, FIN, 0>>({n, colour, ec, eo, rc, ctl}, sweep_blocks<T>(n), 0, s);
 }
 template <typename T, int FIN>
 hipError_t launch_restrict(int n, int red_only, const T* e0, const T* e1, const T* r0, const T* r1, T* rc0, T* rc1,
                            Ctl* ctl, hipStream_t s) {
   const int nc = n / 2;
-  return go<ResidRestrict<T, FIN>>({n, red_only, e0, e1, r0, r1, rc0, rc1, ctl}, blocks_for(nc * nc * nc, kBlock), 0,
-                                   s);
+  const int nb = blocks_for(nc * nc * nc, ResidRestrict<T, FIN, 0>::kThreads);
+  if (red_only) {
+    const int nbv = blocks_for(nc * nc * nc / Vec<T>::W, RestrictRed<T, FIN, 0>::kThreads);
+    if (speculate(n)) return go<RestrictRed<T, FIN, 1>>({n, red_only, e0, e1, r0, r1, rc0, rc1, ctl}, nbv, 0, s);
+    return go<RestrictRed<T, FIN, 0>>({n, red_only, e0, e1, r0, r1, rc0, rc1, ctl}, nbv, 0, s);
+  }
+  if (speculate(n)) return go<ResidRestrict<T, FIN, 1>>({n, red_only, e0, e1, r0, r1, rc0, rc1, ctl}, nb, 0, s);
+  return go<ResidRestrict<T, FIN, 0>>({n, red_only, e0, e1, r0, r1, rc0, rc1, ctl}, nb, 0, s);
 }
 template <typename T, int FIN>
-hipError_t launch_prolong_black(int n, int nb, T* e1, const T* c0, const T* c1, Ctl* ctl, hipStream_t s) {
-  return go<ProlongBlack<T, FIN>>({n, e1, c0, c1, ctl}, nb, 0, s);
-}
-template <typename T, int FIN>
-hipError_t launch_prolong_red(int n, int nb, T* e0, const T* e1, const T* r0, const T* c0, const T* c1, Ctl* ctl,
-                              hipStream_t s) {
-  return go<ProlongRed<T, FIN>>({n, e0, e1, r0, c0, c1, ctl}, nb, 0, s);
+hipError_t launch_prolong_black(int n, T* e1, const T* c0, const T* c1, Ctl* ctl, hipStream_t s) {
+  if (speculate(n)) return go<ProlongBlack<T, FIN, 1>>({n, e1, c0, c1, ctl}, sweep_blocks<T>(n), 0, s);
+  return go<ProlongBlack<T, FIN, 0>>({n, e1, c0, c1, ctl}, sweep_blocks<T>(n), 0, s);
 }
 template <typename T>
 hipError_t launch_tail(const LevelBufs* lv, int levels, int tail, int nu1, int nu2, const double* green, Ctl* ctl,
@@ -1054,10 +1306,8 @@ hipError_t launch_tail(const LevelBufs* lv, int levels, int tail, int nu1, int n
 // level l from the finest going down, the tail, then the levels going up in
 // reverse, so systems with fewer levels keep their own order in a batch.
 // Sub-keys: 0..33 sweeps and prolongation (up: 0 black-point prolongation,
-// 1 prolongation fused with the first red sweep, then 2 + 2 it + colour),
-// 62 zero fill, 63 restriction / plain prolongation.  Levels up to this edge
-// use the fused prolongation.
-constexpr int kFuseProlongMax = 128;
+// then 2 + 2 it + colour), 62 zero fill, 63 restriction / plain
+// prolongation.
 inline uint32_t key_down(int l, int sub) { return 1000u + 64u * (uint32_t)l + (uint32_t)sub; }
 inline uint32_t key_up(int l, int sub) { return 3000u + 64u * (uint32_t)(P3MZ_MAX_LEVELS - 1 - l) + (uint32_t)sub; }
 constexpr uint32_t kKeyTail = 2100u;
@@ -1111,25 +1361,13 @@ hipError_t vcycle_impl(const LevelBufs* lv, int levels, int tail, int nu1, int n
     T *e0 = (T*)lv[l].e0, *e1 = (T*)lv[l].e1, *r0 = (T*)lv[l].r0, *r1 = (T*)lv[l].r1;
     const T *c0 = (const T*)lv[l + 1].e0, *c1 = (const T*)lv[l + 1].e1;
     if (nu2 >= 1) {
-      // levels up to kFuseProlongMax: prolongation fused with the first red
-      // half-sweep; larger levels: black-point prolongation, then the sweep
-      const bool fuse = n <= kFuseProlongMax;
-      if (fuse) {
-        rec_key(key_up(l, 1));
-        kt_begin(KT_PROLONG, l, s);
-        P3MZ_LAUNCH(l == 0 ? launch_prolong_red<T, 1>(n, nb, e0, e1, r0, c0, c1, ctl, s)
-                           : launch_prolong_red<T, 0>(n, nb, e0, e1, r0, c0, c1, ctl, s));
-        kt_end(KT_PROLONG, l, 1.625 * ts * n3, s);
-      } else {
-        rec_key(key_up(l, 0));
-        kt_begin(KT_PROLONG, l, s);
-        P3MZ_LAUNCH(l == 0 ? launch_prolong_black<T, 1>(n, nb, e1, c0, c1, ctl, s)
-                           : launch_prolong_black<T, 0>(n, nb, e1, c0, c1, ctl, s));
-        kt_end(KT_PROLONG, l, 1.125 * ts * n3, s);
-      }
+      rec_key(key_up(l, 0));
+      kt_begin(KT_PROLONG, l, s);
+      P3MZ_LAUNCH(l == 0 ? launch_prolong_black<T, 1>(n, e1, c0, c1, ctl, s)
+                         : launch_prolong_black<T, 0>(n, e1, c0, c1, ctl, s));
+      kt_end(KT_PROLONG, l, 1.125 * ts * n3, s);
       for (int it = 0; it < nu2; it++) {
         for (int colour = 0; colour < 2; colour++) {
-          if (fuse && it == 0 && colour == 0) continue;   // done by the fused launch
           T* ec = colour ? e1 : e0;
           const T* eo = colour ? e0 : e1;
           const T* rc = colour ? r1 : r0;
@@ -1170,14 +1408,10 @@ hipError_t one_kernel(int kid, const LevelBufs* lv, int levels, int tail, int nu
       if (tail == 0) return hipErrorInvalidValue;
       *bytes = 2.125 * ts * n3;
       return launch_restrict<T, 1>(n, nu1 >= 1, e0, e1, r0, r1, (T*)lv[1].r0, (T*)lv[1].r1, ctl, s);
-    case KT_PROLONG:   // the variant the V-cycle uses on this level
+    case KT_PROLONG:
       if (tail == 0) return hipErrorInvalidValue;
-      if (n <= kFuseProlongMax) {
-        *bytes = 1.625 * ts * n3;
-        return launch_prolong_red<T, 1>(n, nb, e0, e1, r0, (const T*)lv[1].e0, (const T*)lv[1].e1, ctl, s);
-      }
       *bytes = 1.125 * ts * n3;
-      return launch_prolong_black<T, 1>(n, nb, e1, (const T*)lv[1].e0, (const T*)lv[1].e1, ctl, s);
+      return launch_prolong_black<T, 1>(n, e1, (const T*)lv[1].e0, (const T*)lv[1].e1, ctl, s);
     case KT_TAIL:
       *bytes = 2.0 * ts * (double)lv[tail].n * lv[tail].n * lv[tail].n;
       return launch_tail<T>(lv, levels, tail, nu1, nu2, green, ctl, s);

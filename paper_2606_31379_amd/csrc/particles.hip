@@ -448,6 +448,7 @@ struct Gather {
     const TP *phi0, *phi1;
     double *force, *partial;
     const Ctl* ctl;
+    const Ctl* gate;   // non-null: do nothing unless gate->done (solve converged)
   };
   static constexpr int kThreads = kBlock;
   static constexpr int kMaxE = TS + P3MZ_MAX_ORDER + 1;
@@ -465,12 +466,13 @@ __device__ void Gather<T, TP, TS>::run(const Args& A, Grid G) {
   double* __restrict__ force = A.force;
   double* __restrict__ partial = A.partial;
   const Ctl* ctl = A.ctl;
+  if (A.gate && !A.gate->done) return;
   __shared__ T sphi[kMaxE * kMaxE * kMaxE];
   __shared__ double part[kBlock][4];
   __shared__ double sh[kBlock / 64];
   // the new potential: written over phi^k on a cold solve, over phi^{k-1} otherwise
   const TP* __restrict__ phi = (ctl->cold ? ctl->k_idx : 1 - ctl->k_idx) ? A.phi1 : A.phi0;
-  const int pe = p + 2, E = TS + p + 1, E3 = E * E * E;
+  const int pe = p + 2, E = TS + p + 1;
   const int per_round = kBlock / pe;     // atoms evaluated per round
   const T inv2h = (T)(0.5 / h);
   double e_sum = 0.0;
@@ -479,10 +481,17 @@ __device__ void Gather<T, TP, TS>::run(const Args& A, Grid G) {
     const int tx = t % ntx, ty = (t / ntx) % ntx, tz = t / (ntx * ntx);
     const int ox = tx * TS - 1, oy = ty * TS - 1, oz = tz * TS - 1;   // halo origin
     __syncthreads();   // the previous tile's LDS reads are done
-    for (int e = threadIdx.x; e < E3; e += kBlock) {
-      const int lx = e % E, ly = (e / E) % E, lz = e / (E * E);
-      const int gx = ((ox + lx) % n + n) % n, gy = ((oy + ly) % n + n) % n, gz = ((oz + lz) % n + n) % n;
-      sphi[e] = (T)phi[((size_t)gz * n + gy) * n + gx];
+    // halo tile: the threads cover (x, y) positions of a plane and walk z,
+    // so every thread issues its plane loads back to back (n is a power of
+    // two: periodic wrap by mask)
+    for (int e2 = threadIdx.x; e2 < E * E; e2 += kBlock) {
+      const int lx = e2 % E, ly = e2 / E;
+      const int gx = (ox + lx) & (n - 1), gy = (oy + ly) & (n - 1);
+      const TP* col = phi + (size_t)gy * n + gx;
+      for (int lz = 0; lz < E; lz++) {
+        const int gz = (oz + lz) & (n - 1);
+        sphi[lz * E * E + e2] = (T)col[(size_t)gz * n * n];
+      }
     }
     __syncthreads();
     const int a0 = start[t], na_t = start[t + 1] - a0;
@@ -565,9 +574,11 @@ struct FinSum {
     int nb;
     const double* partial;
     double* dst;
+    const Ctl* gate;   // non-null: do nothing unless gate->done
   };
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid) {
+    if (A.gate && !A.gate->done) return;
     __shared__ double sh[kBlock / 64];
     const double tot = reduce_partials_sum(A.partial, A.nb, sh);
     if (threadIdx.x == 0) *A.dst = tot;
@@ -780,14 +791,16 @@ hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, int tile, int ntx
   if (tile != 8) return hipErrorInvalidValue;
   const int nb = std::min(ntx * ntx * ntx, kMaxRedBlocks);
   hipError_t e;
+  // the step's gather (finalize) waits for a converged solve
+  const Ctl* gate = finalize ? ctl : nullptr;
   if (fp64)
     e = go<Gather<double, double, 8>>({n_atoms, n, p, ntx, h, k_e, start, perm, base, (const double*)w, qa, phi0,
-                                       phi1, force, partial, ctl}, nb, 0, s);
+                                       phi1, force, partial, ctl, gate}, nb, 0, s);
   else
     e = go<Gather<float, float, 8>>({n_atoms, n, p, ntx, h, k_e, start, perm, base, (const double*)w, qa, phi32,
-                                     phi32, force, partial, ctl}, nb, 0, s);
+                                     phi32, force, partial, ctl, gate}, nb, 0, s);
   if (e != hipSuccess || !finalize) return e;
-  return go<FinSum>({nb, partial, &ctl->e_lr}, 1, 0, s);
+  return go<FinSum>({nb, partial, &ctl->e_lr, gate}, 1, 0, s);
 }
 
 hipError_t launch_cell_pack(int n_atoms, const int* cperm, const double* pos, const double* qa, void* spos,
