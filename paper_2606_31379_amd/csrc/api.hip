@@ -394,8 +394,6 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   const bool have_tune = tune_lookup(tune_key(pl.n, pl.p, c->P.precision), &tuned);
   c->nu1 = c->P.nu_pre >= 0 ? c->P.nu_pre : (have_tune ? tuned.nu_pre : 2);
   c->nu2 = c->P.nu_post >= 0 ? c->P.nu_post : (have_tune ? tuned.nu_post : 2);
-  // the tile shape never changes results, so a tuned one is always taken
-  c->smooth_tile = have_tune && smooth_tile_ok(tuned.smooth_tile, n) ? tuned.smooth_tile : 0;
   if (c->nu1 + c->nu2 < 1) return fail(P3MZ_ERR_INVALID_ARG, "nu_pre + nu_post must be >= 1");
   P3MZ_HIP_TRY(hipGetDevice(&c->dev));
   P3MZ_HIP_TRY(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
@@ -410,6 +408,12 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   std::vector<double> taps;
   smoothing_taps(n, pl.K, pl.nu_s, &taps, &c->half);
   c->ntaps = (int)taps.size();
+  // the launch shape never changes results, so a tuned one is always taken;
+  // otherwise the first shape (in preference order) that fits the mesh
+  c->smooth_tile = have_tune && smooth_tile_ok(tuned.smooth_tile, n, c->ntaps) ? tuned.smooth_tile : -1;
+  for (int t = 0; c->smooth_tile < 0 && t < smooth_tile_count(); t++)
+    if (smooth_tile_ok(t, n, c->ntaps)) c->smooth_tile = t;
+  if (c->smooth_tile < 0) return fail(P3MZ_ERR_MESH_SHAPE, "no smoothing launch shape fits this mesh");
   P3MZ_TRY(c->allocb(&c->d_taps, taps.size() * 8));
   P3MZ_HIP_TRY(hipMemcpy(c->d_taps, taps.data(), taps.size() * 8, hipMemcpyHostToDevice));
   double g[64];
@@ -419,8 +423,8 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   const int64_t na = c->n_atoms;
   c->ntx = n / kTile;
   c->nbins = c->ntx * c->ntx * c->ntx;
-  P3MZ_TRY(c->alloc(&c->d_base, 3 * na));
-  P3MZ_TRY(c->allocb(&c->d_w, (size_t)3 * na * pl.p * 8));
+  P3MZ_TRY(c->alloc(&c->d_base, 4 * na));                                 // int4 records in bin order
+  P3MZ_TRY(c->allocb(&c->d_w, (size_t)na * (1 + 3 * pl.p) * 8));          // charge + weights in bin order
   P3MZ_TRY(c->alloc(&c->d_key, na));
   P3MZ_TRY(c->alloc(&c->d_slot, na));
   P3MZ_TRY(c->alloc(&c->d_perm_raw, na));
@@ -485,7 +489,7 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   P3MZ_TRY(c->alloc(&c->d_e_other, 1));
   size_t lds = 0;
   P3MZ_HIP_TRY(tail_configure(c->fp64, n >> pl.tail, pl.levels - pl.tail, &lds));
-  P3MZ_HIP_TRY(smooth_configure(n));
+  P3MZ_HIP_TRY(smooth_configure());
   P3MZ_HIP_TRY(hipDeviceSynchronize());
   return P3MZ_OK;
 }
@@ -509,17 +513,19 @@ p3mz_status enq_pre(p3mz_ctx* c, const double* pos, hipStream_t s) {
   const int n = pl.n, na = (int)c->n_atoms;
   const double N3 = (double)c->n3, ts = (double)c->tsz;
   rec_key(100);
-  P3MZ_HIP_TRY(launch_bin_stencil(true, na, pos, c->P.box, n, pl.p, kTile, c->ntx, c->d_base, c->d_w, c->d_key,
-                                  c->d_slot, c->d_count, c->d_ctl, s));
+  P3MZ_HIP_TRY(launch_bin_tiles(na, pos, c->P.box, n, pl.p, kTile, c->ntx, c->d_key, c->d_slot, c->d_count, c->d_ctl,
+                                s));
   rec_key(101);
   P3MZ_HIP_TRY(launch_scan(c->nbins, c->d_count, c->d_start, c->d_bsum, s));
   rec_key(102);
   P3MZ_HIP_TRY(launch_scatter(na, c->d_key, c->d_slot, c->d_start, c->d_perm_raw, s));
   rec_key(103);
   P3MZ_HIP_TRY(launch_sort_bins(c->nbins, c->d_start, c->d_perm_raw, c->d_perm, c->d_ctl, s));
+  P3MZ_HIP_TRY(launch_pack_atoms(na, pos, c->d_qa, c->P.box, n, pl.p, c->d_perm, c->d_base, (double*)c->d_w, s));
   rec_key(104);
   kt_begin(KT_SPREAD, 0, s);
-  P3MZ_HIP_TRY(launch_spread(true, n, pl.p, kTile, c->ntx, c->d_start, c->d_perm, c->d_base, c->d_w, c->d_qa, c->d_q, s));
+  P3MZ_HIP_TRY(launch_spread(true, na, n, pl.p, kTile, c->ntx, c->d_start, c->d_base, (const double*)c->d_w, c->d_q,
+                             s));
   kt_end(KT_SPREAD, 0, 8.0 * N3 + (double)na * (24.0 * pl.p + 24.0), s);
   double* src[3] = {c->d_q, c->d_qs, c->d_tmp};
   double* dst[3] = {c->d_qs, c->d_tmp, c->d_qs};
@@ -571,8 +577,8 @@ p3mz_status enq_post1(p3mz_ctx* c, double* force, hipStream_t s) {
   stage(c, 2, s);
   rec_key(5001);
   kt_begin(KT_GATHER, 0, s);
-  P3MZ_HIP_TRY(launch_gather(c->fp64, na, n, pl.p, kTile, c->ntx, pl.h, c->P.coulomb_k, c->d_start, c->d_perm,
-                             c->d_base, c->d_w, c->d_qa, c->d_phi[0], c->d_phi[1], c->d_phi32, force, c->d_partial,
+  P3MZ_HIP_TRY(launch_gather(c->fp64, na, n, pl.p, kTile, c->ntx, pl.h, c->P.coulomb_k, c->d_start, c->d_base,
+                             (const double*)c->d_w, c->d_phi[0], c->d_phi[1], c->d_phi32, force, c->d_partial,
                              c->d_ctl, s));
   // algorithmic bytes: the potential once, plus each atom's stencil record,
   // charge and force (the (p+2)^3 neighbourhood reads are shared by atoms)
@@ -1474,13 +1480,13 @@ p3mz_status p3mz_kernel_bench(p3mz_ctx* ctx, int32_t kernel_id, int32_t reps, vo
                        ctx->d_sigma, ctx->d_y[0], ctx->P.tol, ctx->P.tol_mode, ctx->d_partial, ctx->d_ctl, s, false);
       bytes = 64.0 * N3;
     } else if (kernel_id == KT_SPREAD) {
-      e = launch_spread(true, n, p, kTile, ctx->ntx, ctx->d_start, ctx->d_perm, ctx->d_base, ctx->d_w, ctx->d_qa,
+      e = launch_spread(true, (int)ctx->n_atoms, n, p, kTile, ctx->ntx, ctx->d_start, ctx->d_base, (const double*)ctx->d_w,
                         ctx->d_tmp, s);
       bytes = 8.0 * N3 + na * (24.0 * p + 24.0);
     } else if (kernel_id == KT_GATHER) {
       e = launch_gather(ctx->fp64, (int)ctx->n_atoms, n, p, kTile, ctx->ntx, ctx->pl.h, ctx->P.coulomb_k, ctx->d_start,
-                        ctx->d_perm, ctx->d_base, ctx->d_w, ctx->d_qa, ctx->d_phi[0], ctx->d_phi[1], ctx->d_phi32,
-                        nullptr, ctx->d_partial, ctx->d_ctl, s, false);
+                        ctx->d_base, (const double*)ctx->d_w, ctx->d_phi[0], ctx->d_phi[1], ctx->d_phi32, nullptr,
+                        ctx->d_partial, ctx->d_ctl, s, false);
       bytes = N3 * (ctx->fp64 ? 8.0 : 4.0) + na * (48.0 + 24.0 * p);
     } else {
       e = launch_vcycle_kernel(ctx->fp64, kernel_id, ctx->lv, ctx->pl.levels, ctx->pl.tail, ctx->nu1, ctx->nu2,
@@ -1504,7 +1510,7 @@ p3mz_status p3mz_set_schedule(p3mz_ctx* ctx, int32_t nu_pre, int32_t nu_post, in
   if (!ctx) return fail(P3MZ_ERR_INVALID_ARG, "ctx is NULL");
   if (nu_pre < 0 || nu_post < 0 || nu_pre > 16 || nu_post > 16 || nu_pre + nu_post < 1)
     return fail(P3MZ_ERR_INVALID_ARG, "sweep counts must be in 0..16 with nu_pre + nu_post >= 1");
-  if (!smooth_tile_ok(smooth_tile, ctx->pl.n)) return fail(P3MZ_ERR_INVALID_ARG, "smoothing tile not valid on this mesh");
+  if (!smooth_tile_ok(smooth_tile, ctx->pl.n, ctx->ntaps)) return fail(P3MZ_ERR_INVALID_ARG, "smoothing tile not valid on this mesh");
   P3MZ_HIP_TRY(hipDeviceSynchronize());
   ctx->drop_graphs();
   ctx->nu1 = nu_pre;
@@ -1527,7 +1533,7 @@ p3mz_status p3mz_autotune(p3mz_ctx* ctx, const double* frames_dev, int32_t n_fra
   int best_tile = ctx->smooth_tile;
   double best_tile_ms = 1e300;
   for (int t = 0; t < smooth_tile_count(); t++) {
-    if (!smooth_tile_ok(t, n)) continue;
+    if (!smooth_tile_ok(t, n, ctx->ntaps)) continue;
     double ms_min = 1e300;
     for (int rep = 0; rep < 4; rep++) {
       P3MZ_HIP_TRY(hipEventRecord(e0, s));

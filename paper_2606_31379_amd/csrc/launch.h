@@ -16,11 +16,15 @@ void kt_begin(int id, int level, hipStream_t s);
 void kt_end(int id, int level, double bytes, hipStream_t s);
 
 // ---- particles (particles.hip) ------------------------------------------
-// Per-atom stencil base, B-spline weights (precision T) and tile key for
-// the spread; slot = arrival rank inside the key's bin.
-hipError_t launch_bin_stencil(bool fp64, int n_atoms, const double* pos, double box, int n, int p,
-                              int tile, int ntx, int* base, void* w, int* key, int* slot, int* count,
-                              Ctl* ctl, hipStream_t s);
+// Tile key of each atom (the tile holding its first stencil index); slot =
+// arrival rank inside the key's bin.
+hipError_t launch_bin_tiles(int n_atoms, const double* pos, double box, int n, int p, int tile, int ntx, int* key,
+                           int* slot, int* count, Ctl* ctl, hipStream_t s);
+// Atom records in bin order (position i holds atom perm[i]): rb[i] = {stencil
+// origin x, y, z, atom index} (int4); rw[c * n_atoms + i] = component c of
+// {charge, FP64 B-spline weights x | y | z}.
+hipError_t launch_pack_atoms(int n_atoms, const double* pos, const double* qa, double box, int n, int p,
+                             const int* perm, void* rb, double* rw, hipStream_t s);
 // Cell key of each atom for the short-range cell list (nc cells per edge).
 hipError_t launch_bin_cells(int n_atoms, const double* pos, double box, int nc, int* key, int* slot,
                             int* count, Ctl* ctl, hipStream_t s);
@@ -35,8 +39,8 @@ hipError_t launch_scatter(int n_atoms, const int* key, const int* slot, const in
 hipError_t launch_sort_bins(int nbins, const int* start, const int* perm_raw, int* perm, Ctl* ctl,
                             hipStream_t s);
 // Owner-computes spread: q (natural layout, precision T) from the binned atoms.
-hipError_t launch_spread(bool fp64, int n, int p, int tile, int ntx, const int* start, const int* perm,
-                         const int* base, const void* w, const double* qa, void* q, hipStream_t s);
+hipError_t launch_spread(bool fp64, int n_atoms, int n, int p, int tile, int ntx, const int* start, const void* rb,
+                         const double* rw, void* q, hipStream_t s);
 // Long-range force and energy by interpolating the central-difference
 // gradient of phi (precision of phi: fp64 or float).
 // phi: FP64 mode reads the new potential from phi0/phi1 (selected on the
@@ -45,9 +49,9 @@ hipError_t launch_spread(bool fp64, int n, int p, int tile, int ntx, const int* 
 // with finalize, both kernels do nothing unless ctl->done (the step's solve
 // has converged), so they may be enqueued before the host has checked it.
 hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, int tile, int ntx, double h, double k_e,
-                         const int* start, const int* perm, const int* base, const void* w, const double* qa,
-                         const double* phi0, const double* phi1, const float* phi32, double* force, double* partial,
-                         Ctl* ctl, hipStream_t s, bool finalize = true);
+                         const int* start, const void* rb, const double* rw, const double* phi0, const double* phi1,
+                         const float* phi32, double* force, double* partial, Ctl* ctl, hipStream_t s,
+                         bool finalize = true);
 // Short-range erfc pairs on the cell list, exclusion correction, energy
 // assembly into energy_out[4] (may be NULL).  force += F_sr.
 // spos[jj] = {x, y, z, q} of atom cperm[jj] (cell order), for the pair kernels.
@@ -66,7 +70,7 @@ hipError_t launch_sr(int n_atoms, const double* pos, const double* qa, double bo
 hipError_t launch_smooth(bool fp64, int n, int axis, int tile, int ntaps, int half, const void* taps,
                          const void* in, void* out, hipStream_t s);
 int smooth_tile_count();
-bool smooth_tile_ok(int tile, int n);
+bool smooth_tile_ok(int tile, int n, int ntaps);
 void smooth_tile_shape(int tile, int* lines_per_workgroup, int* outputs_per_thread);
 // sigma_p = (h/4pi) M (2 phi^k - phi^{k-1}) + q^s (cold: q^s) and the
 // multiplier predictor into y; a one-workgroup pass then forms the mean of
@@ -110,7 +114,7 @@ hipError_t launch_set_ctl_open(Ctl* ctl, hipStream_t s);
 hipError_t launch_sub_scalar(int64_t count, const double* in, double* out, const double* sub, hipStream_t s);
 hipError_t tail_configure(bool fp64, int n_tail, int levels_tail, size_t* lds_bytes);
 // Allows the smoothing kernels the LDS they need on an n^3 mesh.
-hipError_t smooth_configure(int n);
+hipError_t smooth_configure();
 
 // ---- molecular dynamics (md.hip) ----------------------------------------
 hipError_t launch_kick_drift(int n_atoms, double* pos, double* vel, const double* force,

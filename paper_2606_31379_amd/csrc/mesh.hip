@@ -33,83 +33,117 @@ __device__ __forceinline__ int cs_index(const CsGeo& g, int i, int j, int k) {
 // ---------------------------------------------------------------------------
 // Smoothing: one periodic line filter along `AXIS` (0 = x, 1 = y, 2 = z).
 // The K-fold diffusion step [nu, 1-2nu, nu] is applied as its (2K+1)-tap
-// convolution, folded onto the periodic line when 2K+1 > n.  A workgroup
-// stages W whole lines in LDS; each thread produces R consecutive outputs of
-// one line from a sliding window (ntaps+R-1 LDS reads for R outputs); the
-// taps sit in LDS and every lane reads the same one (broadcast).  y/z lines are W consecutive x columns
-// (coalesced), staged position-major; x lines are W rows, staged row-major
-// and written back through a second LDS buffer so global stores stay
-// coalesced.  Both layouts carry one element of padding per row/position to
-// spread the sliding-window reads over the LDS banks.
+// convolution, folded onto the periodic line when 2K+1 > n:
+// out[i] = sum_m taps[m] v[(i + m - half) mod n], m ascending.
+// A workgroup owns W lines and a segment of S consecutive outputs of each
+// (S divides n; whole lines when they fit in LDS).  It stages the segment
+// extended by the filter reach, ext[k] = v[(i_seg + k - half) mod n] for
+// k < S + kt + R, so no index wraps inside the filter loop; kt is ntaps
+// rounded up to a multiple of R with zero taps (they add exact zeros).
+// Each thread produces R consecutive outputs of one line: taps are taken R
+// at a time with a window of 2R line values in registers, and every output
+// sums its terms in ascending tap order.  y/z lines are W consecutive x
+// columns (coalesced loads and stores), staged position-major; x lines are
+// staged row-major and written back through a second LDS buffer so the
+// global stores stay coalesced.
 // ---------------------------------------------------------------------------
 template <typename T, int AXIS, int W, int R>
 struct Smooth {
   struct Args {
-    int n, ntaps, half;
+    int n, ntaps, half, seg;
     const T *taps, *in;
     T* out;
   };
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G);
 };
+
+// LDS layout of one smoothing workgroup (elements): the padded taps, the
+// staged extended lines and, for x lines, the output rows.
+struct SmoothLds {
+  int kt, L, ld, ldo, taps_off, buf_off, obuf_off, total;
+  __host__ __device__ SmoothLds(int axis, int W, int R, int ntaps, int seg) {
+    kt = (ntaps + R - 1) / R * R;
+    L = seg + kt + R;
+    ld = axis == 0 ? ((L + 15) & ~15) + 2 : W + 1;   // 16-byte rows, staggered over the banks
+    ldo = seg + 2;
+    taps_off = 0;
+    buf_off = (kt + 1) & ~1;
+    obuf_off = buf_off + (axis == 0 ? W * ld : L * ld);
+    total = obuf_off + (axis == 0 ? W * ldo : 0);
+  }
+};
+
 template <typename T, int AXIS, int W, int R>
 __device__ void Smooth<T, AXIS, W, R>::run(const Args& A, Grid G) {
-  const int n = A.n, ntaps = A.ntaps, half = A.half;
-  const T* __restrict__ taps_g = A.taps;
+  static_assert((W & (W - 1)) == 0 && R % 2 == 0, "W a power of two, R even");
+  const int n = A.n, ntaps = A.ntaps, half = A.half, S = A.seg, msk = n - 1;
   const T* __restrict__ in = A.in;
   T* __restrict__ out = A.out;
-  extern __shared__ unsigned char smem_raw[];
-  T* taps = reinterpret_cast<T*>(smem_raw);          // [ntaps], broadcast reads
-  T* buf = taps + ((ntaps + 1) & ~1);
-  const int g = G.b;
+  const SmoothLds lay(AXIS, W, R, ntaps, S);
+  extern __shared__ __align__(16) unsigned char smooth_lds[];
+  T* const lds = reinterpret_cast<T*>(smooth_lds);
+  T* const taps = lds + lay.taps_off;
+  T* const buf = lds + lay.buf_off;
+  const int kt = lay.kt, L = lay.L, ld = lay.ld;
   const int tid = threadIdx.x;
-  for (int i = tid; i < ntaps; i += kBlock) taps[i] = taps_g[i];
-  const int ld = AXIS == 0 ? n + 1 : W + 1;         // padded LDS stride between rows / positions
+  for (int i = tid; i < kt; i += kBlock) taps[i] = i < ntaps ? A.taps[i] : T(0);
+  // workgroup -> (line group, segment)
+  const int nseg = n / S;
+  const int seg = G.b % nseg, grp = G.b / nseg;
+  const int i_seg = seg * S;
   size_t row0 = 0;
   int x0 = 0, o = 0;
   if (AXIS == 0) {
-    row0 = (size_t)g * W;
-    for (int e = tid; e < W * n; e += kBlock) {
-      const int r = e / n, i = e - r * n;
-      buf[r * ld + i] = in[(row0 + r) * n + i];
-    }
+    row0 = (size_t)grp * W;
+    for (int r = 0; r < W; r++)
+      for (int k = tid; k < L; k += kBlock) buf[r * ld + k] = in[(row0 + r) * n + ((i_seg + k - half) & msk)];
   } else {
     const int ncol = n / W;
-    x0 = (g % ncol) * W;
-    o = g / ncol;
-    for (int e = tid; e < W * n; e += kBlock) {
-      const int t = e / W, c = e - t * W;
+    x0 = (grp % ncol) * W;
+    o = grp / ncol;
+    for (int e = tid; e < L * W; e += kBlock) {
+      const int k = e / W, c = e & (W - 1);
+      const int t = (i_seg + k - half) & msk;
       const size_t a = AXIS == 1 ? ((size_t)o * n + t) * n + x0 + c : ((size_t)t * n + o) * n + x0 + c;
-      buf[t * ld + c] = in[a];
+      buf[k * ld + c] = in[a];
     }
   }
   __syncthreads();
-  T* obuf = buf + (AXIS == 0 ? W * ld : 0);
-  const int groups = n / R;
-  for (int task = tid; task < W * groups; task += kBlock) {
-    const int c = task % W, i0 = (task / W) * R;
+  T* const obuf = lds + lay.obuf_off;
+  for (int task = tid; task < W * (S / R); task += kBlock) {
+    const int c = task & (W - 1), i0 = (task / W) * R;
     T acc[R];
 #pragma unroll
     for (int r = 0; r < R; r++) acc[r] = T(0);
-    int src = i0 - half;
-    src += src < 0 ? n : 0;
-    const int span = ntaps + R - 1;
-    for (int mm = 0; mm < span; mm++) {
-      const T v = AXIS == 0 ? buf[c * ld + src] : buf[src * ld + c];
-      src = (src + 1 == n) ? 0 : src + 1;
+    for (int m0 = 0; m0 < kt; m0 += R) {
+      T v[2 * R], tp[R];
+      if (AXIS == 0) {
+        const double2* p = reinterpret_cast<const double2*>(buf + c * ld + i0 + m0);
 #pragma unroll
-      for (int r = 0; r < R; r++) {
-        const int tap = mm - r;
-        if (tap >= 0 && tap < ntaps) acc[r] += taps[tap] * v;
+        for (int q = 0; q < R; q++) {
+          const double2 d = p[q];
+          v[2 * q] = d.x;
+          v[2 * q + 1] = d.y;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 2 * R; q++) v[q] = buf[(i0 + m0 + q) * ld + c];
       }
+#pragma unroll
+      for (int j = 0; j < R; j++) tp[j] = taps[m0 + j];
+#pragma unroll
+      for (int j = 0; j < R; j++)
+#pragma unroll
+        for (int r = 0; r < R; r++) acc[r] += tp[j] * v[r + j];
     }
     if (AXIS == 0) {
 #pragma unroll
-      for (int r = 0; r < R; r++) obuf[c * ld + i0 + r] = acc[r];
+      for (int r = 0; r < R; r++) obuf[c * lay.ldo + i0 + r] = acc[r];
     } else {
 #pragma unroll
       for (int r = 0; r < R; r++) {
-        const int t = i0 + r;
+        const int t = i_seg + i0 + r;
         const size_t a = AXIS == 1 ? ((size_t)o * n + t) * n + x0 + c : ((size_t)t * n + o) * n + x0 + c;
         out[a] = acc[r];
       }
@@ -117,16 +151,9 @@ __device__ void Smooth<T, AXIS, W, R>::run(const Args& A, Grid G) {
   }
   if (AXIS == 0) {
     __syncthreads();
-    for (int e = tid; e < W * n; e += kBlock) {
-      const int r = e / n, i = e - r * n;
-      out[(row0 + r) * n + i] = obuf[r * ld + i];
-    }
+    for (int r = 0; r < W; r++)
+      for (int i = tid; i < S; i += kBlock) out[(row0 + r) * n + i_seg + i] = obuf[r * lay.ldo + i];
   }
-}
-
-size_t smooth_lds_bytes(int n, int axis, int W, int ntaps, size_t elem) {
-  const size_t tp = (size_t)((ntaps + 1) & ~1);
-  return (tp + (axis == 0 ? (size_t)2 * W * (n + 1) : (size_t)(W + 1) * n)) * elem;
 }
 
 // ---------------------------------------------------------------------------
@@ -1422,36 +1449,51 @@ hipError_t one_kernel(int kid, const LevelBufs* lv, int levels, int tail, int nu
 
 }  // namespace
 
-// smoothing launch shape: W lines per workgroup, R outputs per thread
 // Smoothing launch shapes (W lines per workgroup, R outputs per thread);
 // variant 0 is the default, the others are candidates for the autotuner.
-constexpr int kSmoothTiles[][2] = {{4, 4}, {2, 4}, {8, 4}, {4, 2}, {4, 8}, {8, 2}, {2, 8}};
+constexpr int kSmoothTiles[][2] = {{16, 8}, {32, 8}, {8, 8}, {32, 4}, {16, 4}, {8, 4}, {4, 8}};
 constexpr int kSmoothTileCount = (int)(sizeof(kSmoothTiles) / sizeof(kSmoothTiles[0]));
+// dynamic LDS of one smoothing workgroup (two fit on a compute unit)
+constexpr size_t kSmoothLdsCap = 80 * 1024;
 
 namespace {
-template <int W, int R>
-hipError_t smooth_wr(int n, int axis, int ntaps, int half, const double* tp, const double* ip, double* op,
-                     hipStream_t s) {
-  const int grid = axis == 0 ? (int)((size_t)n * n / W) : (n / W) * n;
-  const size_t lds = smooth_lds_bytes(n, axis, W, ntaps, 8);
-  if (axis == 0) return go<Smooth<double, 0, W, R>>({n, ntaps, half, tp, ip, op}, grid, lds, s);
-  if (axis == 1) return go<Smooth<double, 1, W, R>>({n, ntaps, half, tp, ip, op}, grid, lds, s);
-  return go<Smooth<double, 2, W, R>>({n, ntaps, half, tp, ip, op}, grid, lds, s);
+// Segment length: the longest power-of-two piece of a line (whole lines
+// first) whose workgroup fits in kSmoothLdsCap on every axis; 0 if none.
+int smooth_segment(int n, int W, int R, int ntaps) {
+  for (int S = n; S >= R; S >>= 1) {
+    const SmoothLds a0(0, W, R, ntaps, S), a1(1, W, R, ntaps, S);
+    if ((size_t)std::max(a0.total, a1.total) * sizeof(double) <= kSmoothLdsCap) return S;
+  }
+  return 0;
 }
 
 template <int W, int R>
-hipError_t smooth_allow(int n) {
-  const int bytes = (int)smooth_lds_bytes(n, 0, W, n, 8);   // the x axis needs the most
-  P3MZ_LAUNCH(allow_lds<Smooth<double, 0, W, R>>(bytes));
-  P3MZ_LAUNCH(allow_lds<Smooth<double, 1, W, R>>(bytes));
-  return allow_lds<Smooth<double, 2, W, R>>(bytes);
+hipError_t smooth_wr(int n, int axis, int ntaps, int half, const double* tp, const double* ip, double* op,
+                     hipStream_t s) {
+  const int S = smooth_segment(n, W, R, ntaps);
+  if (S == 0) return hipErrorInvalidValue;
+  const int nseg = n / S;
+  const int grid = (axis == 0 ? (int)((size_t)n * n / W) : (n / W) * n) * nseg;
+  const size_t lds = (size_t)SmoothLds(axis, W, R, ntaps, S).total * sizeof(double);
+  if (axis == 0) return go<Smooth<double, 0, W, R>>({n, ntaps, half, S, tp, ip, op}, grid, lds, s);
+  if (axis == 1) return go<Smooth<double, 1, W, R>>({n, ntaps, half, S, tp, ip, op}, grid, lds, s);
+  return go<Smooth<double, 2, W, R>>({n, ntaps, half, S, tp, ip, op}, grid, lds, s);
+}
+
+template <int W, int R>
+hipError_t smooth_allow() {
+  P3MZ_LAUNCH(allow_lds<Smooth<double, 0, W, R>>((int)kSmoothLdsCap));
+  P3MZ_LAUNCH(allow_lds<Smooth<double, 1, W, R>>((int)kSmoothLdsCap));
+  return allow_lds<Smooth<double, 2, W, R>>((int)kSmoothLdsCap);
 }
 }  // namespace
 
 int smooth_tile_count() { return kSmoothTileCount; }
 
-bool smooth_tile_ok(int tile, int n) {
-  return tile >= 0 && tile < kSmoothTileCount && n % kSmoothTiles[tile][0] == 0 && n % kSmoothTiles[tile][1] == 0;
+bool smooth_tile_ok(int tile, int n, int ntaps) {
+  if (tile < 0 || tile >= kSmoothTileCount) return false;
+  const int W = kSmoothTiles[tile][0], R = kSmoothTiles[tile][1];
+  return n % W == 0 && n % R == 0 && smooth_segment(n, W, R, ntaps) > 0;
 }
 
 void smooth_tile_shape(int tile, int* w, int* r) {
@@ -1462,33 +1504,32 @@ void smooth_tile_shape(int tile, int* w, int* r) {
 hipError_t launch_smooth(bool fp64, int n, int axis, int tile, int ntaps, int half, const void* taps, const void* in,
                          void* out, hipStream_t s) {
   if (!fp64) return hipErrorInvalidValue;   // the charge source is FP64 in both modes
-  if (!smooth_tile_ok(tile, n)) return hipErrorInvalidValue;
+  if (!smooth_tile_ok(tile, n, ntaps)) return hipErrorInvalidValue;
   const double *tp = (const double*)taps, *ip = (const double*)in;
   double* op = (double*)out;
   switch (tile) {
-    case 0: return smooth_wr<4, 4>(n, axis, ntaps, half, tp, ip, op, s);
-    case 1: return smooth_wr<2, 4>(n, axis, ntaps, half, tp, ip, op, s);
-    case 2: return smooth_wr<8, 4>(n, axis, ntaps, half, tp, ip, op, s);
-    case 3: return smooth_wr<4, 2>(n, axis, ntaps, half, tp, ip, op, s);
-    case 4: return smooth_wr<4, 8>(n, axis, ntaps, half, tp, ip, op, s);
-    case 5: return smooth_wr<8, 2>(n, axis, ntaps, half, tp, ip, op, s);
-    default: return smooth_wr<2, 8>(n, axis, ntaps, half, tp, ip, op, s);
+    case 0: return smooth_wr<16, 8>(n, axis, ntaps, half, tp, ip, op, s);
+    case 1: return smooth_wr<32, 8>(n, axis, ntaps, half, tp, ip, op, s);
+    case 2: return smooth_wr<8, 8>(n, axis, ntaps, half, tp, ip, op, s);
+    case 3: return smooth_wr<32, 4>(n, axis, ntaps, half, tp, ip, op, s);
+    case 4: return smooth_wr<16, 4>(n, axis, ntaps, half, tp, ip, op, s);
+    case 5: return smooth_wr<8, 4>(n, axis, ntaps, half, tp, ip, op, s);
+    default: return smooth_wr<4, 8>(n, axis, ntaps, half, tp, ip, op, s);
   }
 }
 
-// Dynamic-LDS limits only ever grow, so contexts of different mesh sizes can
-// coexist in one process.
-hipError_t smooth_configure(int n) {
-  static int granted = 0;
-  if (n <= granted) return hipSuccess;
-  P3MZ_LAUNCH(smooth_allow<4, 4>(n));
-  P3MZ_LAUNCH(smooth_allow<2, 4>(n));
-  P3MZ_LAUNCH(smooth_allow<8, 4>(n));
-  P3MZ_LAUNCH(smooth_allow<4, 2>(n));
-  P3MZ_LAUNCH(smooth_allow<4, 8>(n));
-  P3MZ_LAUNCH(smooth_allow<8, 2>(n));
-  P3MZ_LAUNCH(smooth_allow<2, 8>(n));
-  granted = n;
+// Every smoothing kernel may use up to kSmoothLdsCap of dynamic LDS.
+hipError_t smooth_configure() {
+  static bool granted = false;
+  if (granted) return hipSuccess;
+  P3MZ_LAUNCH(smooth_allow<16, 8>());
+  P3MZ_LAUNCH(smooth_allow<32, 8>());
+  P3MZ_LAUNCH(smooth_allow<8, 8>());
+  P3MZ_LAUNCH(smooth_allow<32, 4>());
+  P3MZ_LAUNCH(smooth_allow<16, 4>());
+  P3MZ_LAUNCH(smooth_allow<8, 4>());
+  P3MZ_LAUNCH(smooth_allow<4, 8>());
+  granted = true;
   return hipSuccess;
 }
 

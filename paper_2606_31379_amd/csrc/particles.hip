@@ -31,53 +31,82 @@ __device__ __forceinline__ void stencil_origin(double x, double box, int n, int 
   if (*tau < 0.0) *tau = 0.0;
 }
 
-template <typename T>
-struct BinStencil {
+// Tile key of every atom (the 8^3 tile holding its first stencil index) and
+// its slot in the tile's count; a non-finite coordinate raises the NaN flag.
+struct BinTiles {
   struct Args {
     int n_atoms, n, p, tile, ntx;
     double box;
     const double* pos;
-    int *base, *key, *slot, *count;
-    T* w;
+    int *key, *slot, *count;
     Ctl* ctl;
   };
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G);
 };
-template <typename T>
-__device__ void BinStencil<T>::run(const Args& A, Grid G) {
+__device__ void BinTiles::run(const Args& A, Grid G) {
   const int n_atoms = A.n_atoms, n = A.n, p = A.p, tile = A.tile, ntx = A.ntx;
-  const double box = A.box;
-  const double* __restrict__ pos = A.pos;
-  int* __restrict__ base = A.base;
-  T* __restrict__ w = A.w;
-  int* __restrict__ key = A.key;
-  int* __restrict__ slot = A.slot;
-  int* __restrict__ count = A.count;
-  Ctl* ctl = A.ctl;
-  int a = G.b * kBlock + threadIdx.x;
+  const int a = G.b * kBlock + threadIdx.x;
   if (a >= n_atoms) return;
   int tk[3];
   for (int d = 0; d < 3; d++) {
-    double x = pos[3 * a + d];
+    double x = A.pos[3 * a + d];
     if (!isfinite(x)) {
-      ctl->nan_flag = 1;
+      A.ctl->nan_flag = 1;
       x = 0.0;
     }
     int first;
     double tau;
-    stencil_origin(x, box, n, p, &first, &tau);
+    stencil_origin(x, A.box, n, p, &first, &tau);
     int f = first % n;
     if (f < 0) f += n;
-    base[3 * a + d] = f;
-    T wl[P3MZ_MAX_ORDER];
-    bspline_weights<T>(p, (T)tau, wl);
-    for (int j = 0; j < p; j++) w[(3 * a + d) * p + j] = wl[j];
     tk[d] = f / tile;
   }
-  int k = (tk[2] * ntx + tk[1]) * ntx + tk[0];
-  key[a] = k;
-  slot[a] = atomicAdd(&count[k], 1);
+  const int k = (tk[2] * ntx + tk[1]) * ntx + tk[0];
+  A.key[a] = k;
+  A.slot[a] = atomicAdd(&A.count[k], 1);
+}
+
+// Atom records in bin order, written after the bin sort: stencil origin and
+// atom index (rb), then charge and the 3p FP64 weights x | y | z (rw, one
+// row of n_atoms values per component: rw[c * n_atoms + i]), so the tile
+// kernels read their atoms' records coalesced instead of gathering them by
+// atom index.
+struct PackAtoms {
+  struct Args {
+    int n_atoms, n, p;
+    double box;
+    const double *pos, *qa;
+    const int* perm;
+    int4* rb;
+    double* rw;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G);
+};
+__device__ void PackAtoms::run(const Args& A, Grid G) {
+  const int n = A.n, p = A.p;
+  const int i = G.b * kBlock + threadIdx.x;
+  if (i >= A.n_atoms) return;
+  const int a = A.perm[i];
+  const size_t na = (size_t)A.n_atoms;
+  double* rec = A.rw + i;
+  rec[0] = A.qa[a];
+  int f3[3];
+  for (int d = 0; d < 3; d++) {
+    double x = A.pos[3 * a + d];
+    if (!isfinite(x)) x = 0.0;
+    int first;
+    double tau;
+    stencil_origin(x, A.box, n, p, &first, &tau);
+    int f = first % n;
+    if (f < 0) f += n;
+    f3[d] = f;
+    double wl[P3MZ_MAX_ORDER];
+    bspline_weights<double>(p, tau, wl);
+    for (int j = 0; j < p; j++) rec[(1 + d * p + j) * na] = wl[j];
+  }
+  A.rb[i] = make_int4(f3[0], f3[1], f3[2], a);
 }
 
 struct BinCells {
@@ -288,10 +317,10 @@ __device__ void SortBins::run(const Args& A, Grid G) {
 template <typename T, int TS>
 struct Spread {
   struct Args {
-    int n, p, ntx;
-    const int *start, *perm, *base;
-    const T* w;
-    const double* qa;
+    int n, p, ntx, n_atoms;
+    const int* start;
+    const int4* rb;
+    const double* rw;
     T* q;
   };
   static constexpr int kThreads = kBlock;
@@ -303,39 +332,46 @@ __device__ void Spread<T, TS>::run(const Args& A, Grid G) {
   constexpr int V = TS * TS * TS, CH = kChunk, MW = 3 * P3MZ_MAX_ORDER;
   const int n = A.n, p = A.p, ntx = A.ntx;
   const int* __restrict__ start = A.start;
-  const int* __restrict__ perm = A.perm;
-  const int* __restrict__ base = A.base;
-  const T* __restrict__ w = A.w;
-  const double* __restrict__ qa = A.qa;
+  const int4* __restrict__ rb = A.rb;
+  const double* __restrict__ rw = A.rw;
   T* __restrict__ q = A.q;
+  const size_t na = (size_t)A.n_atoms;   // row length of rw
   __shared__ T acc[kBlock / 64][V];
   __shared__ T sw[CH][MW];       // weights x | y | z of each staged atom
   __shared__ T sq[CH];
-  __shared__ int sb[CH][3];      // stencil origin
-  __shared__ int bin_lo[8], bin_off[9];
+  __shared__ int sb[CH][3];      // stencil start relative to the tile
+  __shared__ int kidx[CH];       // staged atoms that reach the tile, in chunk order
+  __shared__ int bin_lo[8], bin_cnt[8], bin_off[9];
+  __shared__ int wave_cnt[kBlock / 64];
   const int t = G.b;
   const int tx = t % ntx, ty = (t / ntx) % ntx, tz = t / (ntx * ntx);
   const int ox = tx * TS, oy = ty * TS, oz = tz * TS;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int i = threadIdx.x; i < (kBlock / 64) * V; i += kBlock) (&acc[0][0])[i] = T(0);
+  // candidate bins: this tile and its lower neighbours, one thread each
+  const int nd = ntx > 1 ? 2 : 1, nbin = nd * nd * nd;
+  if ((int)threadIdx.x < 8) {
+    const int k = threadIdx.x;
+    int lo = 0, cnt = 0;
+    if (k < nbin) {
+      const int dx = k % nd, dy = (k / nd) % nd, dz = k / (nd * nd);
+      int sx = tx - dx, sy = ty - dy, sz = tz - dz;
+      sx += sx < 0 ? ntx : 0;
+      sy += sy < 0 ? ntx : 0;
+      sz += sz < 0 ? ntx : 0;
+      const int b = (sz * ntx + sy) * ntx + sx;
+      lo = start[b];
+      cnt = start[b + 1] - lo;
+    }
+    bin_lo[k] = lo;
+    bin_cnt[k] = cnt;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    const int nd = ntx > 1 ? 2 : 1;
-    int off = 0, k = 0;
-    for (int dz = 0; dz < nd; dz++)
-      for (int dy = 0; dy < nd; dy++)
-        for (int dx = 0; dx < nd; dx++, k++) {
-          int sx = tx - dx, sy = ty - dy, sz = tz - dz;
-          sx += sx < 0 ? ntx : 0;
-          sy += sy < 0 ? ntx : 0;
-          sz += sz < 0 ? ntx : 0;
-          const int b = (sz * ntx + sy) * ntx + sx;
-          bin_lo[k] = start[b];
-          bin_off[k] = off;
-          off += start[b + 1] - start[b];
-        }
-    for (; k < 8; k++) {
-      bin_lo[k] = 0;
+    int off = 0;
+    for (int k = 0; k < 8; k++) {
       bin_off[k] = off;
+      off += bin_cnt[k];
     }
     bin_off[8] = off;
   }
@@ -343,78 +379,78 @@ __device__ void Spread<T, TS>::run(const Args& A, Grid G) {
   const int total = bin_off[8];
   const int p2 = p * p, p3 = p2 * p;
   // this lane's stencil points of an atom, l = lane + 64 it (fixed for the
-  // whole kernel; p^3 <= 343 needs up to 6 per lane)
+  // whole kernel; p^3 <= 343 needs up to 6 per lane); invalid slots get an
+  // offset that fails the in-tile test
   constexpr int kMaxIt = (P3MZ_MAX_ORDER * P3MZ_MAX_ORDER * P3MZ_MAX_ORDER + 63) / 64;
   int sax[kMaxIt], say[kMaxIt], saz[kMaxIt];
   const int n_it = (p3 + 63) / 64;
 #pragma unroll
   for (int it = 0; it < kMaxIt; it++) {
     const int l = lane + 64 * it;
-    sax[it] = l % p;
-    say[it] = (l / p) % p;
-    saz[it] = l / p2;
+    const bool ok = l < p3;
+    sax[it] = ok ? l % p : 0;
+    say[it] = ok ? (l / p) % p : 0;
+    saz[it] = ok ? l / p2 : 1 << 20;
   }
-  __shared__ int n_keep;
   for (int c0 = 0; c0 < total; c0 += CH) {
     const int m = min(CH, total - c0);
-    if (threadIdx.x == 0) n_keep = 0;
-    __syncthreads();
-    // stage the chunk's atoms whose stencil reaches this tile (the others sit
-    // in a lower neighbour bin too far from the shared face)
+    // stage the chunk's atoms, one per thread, with the record loaded
+    // together with the origin (one memory round trip); the ones whose
+    // stencil reaches this tile are listed in chunk order (the others sit in
+    // a lower neighbour bin too far from the shared face)
     bool keep = false;
-    int a = 0, b3[3] = {0, 0, 0};
     if ((int)threadIdx.x < m) {
       const int c = c0 + threadIdx.x;
       int k = 0;
       while (c >= bin_off[k + 1]) k++;
-      a = perm[bin_lo[k] + (c - bin_off[k])];
-      b3[0] = base[3 * a];
-      b3[1] = base[3 * a + 1];
-      b3[2] = base[3 * a + 2];
-      const int o3[3] = {ox, oy, oz};
+      const int ps = bin_lo[k] + (c - bin_off[k]);   // position in bin order
+      const int4 r = rb[ps];
+      const double* rec = rw + ps;
+      sq[threadIdx.x] = (T)rec[0];
+      for (int j = 0; j < 3 * p; j++) sw[threadIdx.x][j] = (T)rec[(1 + j) * na];
+      const int b3[3] = {r.x, r.y, r.z}, o3[3] = {ox, oy, oz};
       keep = true;
       for (int d = 0; d < 3; d++) {
         int rel = b3[d] - o3[d];              // stencil start relative to the tile, mod n
         rel += rel < 0 ? n : 0;
         // reaches the tile iff some point rel + t (t < p) lies in [0, TS) mod n
         keep &= rel < TS || rel + p - 1 >= n;
+        sb[threadIdx.x][d] = rel < TS ? rel : rel - n;   // in [-(p-1), TS) for a kept atom
       }
     }
     // keep the chunk order: rank of this thread among the kept ones
     const unsigned long long bal = __ballot(keep);
-    __shared__ int wave_cnt[kBlock / 64];
     if (lane == 0) wave_cnt[wv] = __popcll(bal);
     __syncthreads();
     int slot = __popcll(bal & ((1ull << lane) - 1ull));
-    for (int k = 0; k < wv; k++) slot += wave_cnt[k];
-    if (keep) {
-      sb[slot][0] = b3[0];
-      sb[slot][1] = b3[1];
-      sb[slot][2] = b3[2];
-      sq[slot] = (T)qa[a];
-      for (int j = 0; j < 3 * p; j++) sw[slot][j] = w[3 * a * p + j];
+    int mk = 0;
+    for (int k = 0; k < kBlock / 64; k++) {
+      slot += k < wv ? wave_cnt[k] : 0;
+      mk += wave_cnt[k];
     }
-    if (threadIdx.x == 0) {
-      int tot = 0;
-      for (int k = 0; k < kBlock / 64; k++) tot += wave_cnt[k];
-      n_keep = tot;
-    }
+    if (keep) kidx[slot] = threadIdx.x;
     __syncthreads();
-    const int mk = n_keep;
-    for (int i = wv; i < mk; i += kBlock / 64) {
-      const int bx = sb[i][0], by = sb[i][1], bz = sb[i][2];
+    // kept atoms round-robin over the waves, in chunk order per wave
+    for (int ii = wv; ii < mk; ii += kBlock / 64) {
+      const int i = kidx[ii];
+      const int rx = sb[i][0], ry = sb[i][1], rz = sb[i][2];
 #pragma unroll
       for (int it = 0; it < kMaxIt; it++) {
-        if (it >= n_it || lane + 64 * it >= p3) break;
+        if (it >= n_it) break;
         const int ax = sax[it], ay = say[it], az = saz[it];
-        int gx = bx + ax, gy = by + ay, gz = bz + az;
-        gx -= gx >= n ? n : 0;
-        gy -= gy >= n ? n : 0;
-        gz -= gz >= n ? n : 0;
-        const int lx = gx - ox, ly = gy - oy, lz = gz - oz;
+        int lx = rx + ax, ly = ry + ay, lz = rz + az;
+        if (ntx == 1) {   // the tile is the whole periodic mesh: stencils wrap onto it
+          lx &= n - 1;
+          ly &= n - 1;
+          lz = az < p ? lz & (n - 1) : lz;
+        }
         if ((unsigned)lx < (unsigned)TS && (unsigned)ly < (unsigned)TS && (unsigned)lz < (unsigned)TS) {
           const T c = sq[i] * sw[i][ax] * sw[i][p + ay] * sw[i][2 * p + az];
-          acc[wv][(lz * TS + ly) * TS + lx] += c;
+          // lanes of one atom hit distinct points and a wave's adds to one
+          // point execute in program order, so the sums stay deterministic;
+          // the no-return LDS add lets consecutive atoms overlap
+          __hip_atomic_fetch_add(&acc[wv][(lz * TS + ly) * TS + lx], c, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_WORKGROUP);
         }
       }
     }
@@ -443,8 +479,9 @@ struct Gather {
   struct Args {
     int n_atoms, n, p, ntx;
     double h, k_e;
-    const int *start, *perm, *base;
-    const double *w, *qa;
+    const int* start;
+    const int4* rb;
+    const double* rw;
     const TP *phi0, *phi1;
     double *force, *partial;
     const Ctl* ctl;
@@ -459,10 +496,9 @@ __device__ void Gather<T, TP, TS>::run(const Args& A, Grid G) {
   const int n = A.n, p = A.p, ntx = A.ntx;
   const double h = A.h, k_e = A.k_e;
   const int* __restrict__ start = A.start;
-  const int* __restrict__ perm = A.perm;
-  const int* __restrict__ base = A.base;
-  const double* __restrict__ w = A.w;
-  const double* __restrict__ qa = A.qa;
+  const int4* __restrict__ rb = A.rb;
+  const double* __restrict__ rw = A.rw;
+  const size_t na = (size_t)A.n_atoms;   // row length of rw
   double* __restrict__ force = A.force;
   double* __restrict__ partial = A.partial;
   const Ctl* ctl = A.ctl;
@@ -499,15 +535,16 @@ __device__ void Gather<T, TP, TS>::run(const Args& A, Grid G) {
       const int task = threadIdx.x;
       const int ai = ag + task / pe, c = task % pe;
       if (task < per_round * pe && ai < na_t) {
-        const int a = perm[a0 + ai];
+        const int ps = a0 + ai;   // position in bin order
+        const double* w = rw + na + ps;   // weight j of this atom: w[j * na]
         T wx[P3MZ_MAX_ORDER + 2], wy[P3MZ_MAX_ORDER + 2], dx[P3MZ_MAX_ORDER + 2], dy[P3MZ_MAX_ORDER + 2];
         T wz_c, dz_c;
         {
           T wz[P3MZ_MAX_ORDER + 2];
           for (int j = 0; j < pe; j++) {
-            wx[j] = (j >= 1 && j <= p) ? (T)w[(3 * a) * p + j - 1] : T(0);
-            wy[j] = (j >= 1 && j <= p) ? (T)w[(3 * a + 1) * p + j - 1] : T(0);
-            wz[j] = (j >= 1 && j <= p) ? (T)w[(3 * a + 2) * p + j - 1] : T(0);
+            wx[j] = (j >= 1 && j <= p) ? (T)w[(j - 1) * na] : T(0);
+            wy[j] = (j >= 1 && j <= p) ? (T)w[(p + j - 1) * na] : T(0);
+            wz[j] = (j >= 1 && j <= p) ? (T)w[(2 * p + j - 1) * na] : T(0);
           }
           for (int j = 0; j < pe; j++) {
             // extended index j <-> stencil offset j-1; d[j] = (w[j-1] - w[j+1]) / 2h
@@ -521,7 +558,8 @@ __device__ void Gather<T, TP, TS>::run(const Args& A, Grid G) {
           dz_c = (loz - hiz) * inv2h;
         }
         // neighbourhood origin in the halo tile: base - 1 - (tile origin - 1)
-        const int lx0 = base[3 * a] - (ox + 1), ly0 = base[3 * a + 1] - (oy + 1), lz0 = base[3 * a + 2] - (oz + 1);
+        const int4 r = rb[ps];
+        const int lx0 = r.x - (ox + 1), ly0 = r.y - (oy + 1), lz0 = r.z - (oz + 1);
         double fx = 0, fy = 0, fz = 0, pot = 0;
         const T* plane = sphi + (size_t)(lz0 + c) * E * E;
         for (int b = 0; b < pe; b++) {
@@ -545,7 +583,8 @@ __device__ void Gather<T, TP, TS>::run(const Args& A, Grid G) {
       __syncthreads();
       if ((int)threadIdx.x < per_round && ag + (int)threadIdx.x < na_t) {
         const int k = threadIdx.x;
-        const int a = perm[a0 + ag + k];
+        const int ps = a0 + ag + k;
+        const int a = rb[ps].w;
         double fx = 0, fy = 0, fz = 0, pot = 0;
         for (int cc = 0; cc < pe; cc++) {
           fx += part[k * pe + cc][0];
@@ -553,7 +592,7 @@ __device__ void Gather<T, TP, TS>::run(const Args& A, Grid G) {
           fz += part[k * pe + cc][2];
           pot += part[k * pe + cc][3];
         }
-        const double kq = k_e * qa[a];
+        const double kq = k_e * rw[ps];
         if (force) {
           force[3 * a] = -kq * fx;
           force[3 * a + 1] = -kq * fy;
@@ -738,15 +777,14 @@ inline int blocks_for(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
 }  // namespace
 
-hipError_t launch_bin_stencil(bool fp64, int n_atoms, const double* pos, double box, int n, int p,
-                              int tile, int ntx, int* base, void* w, int* key, int* slot, int* count,
-                              Ctl* ctl, hipStream_t s) {
-  const int nb = blocks_for(n_atoms, kBlock);
-  if (fp64)
-    return go<BinStencil<double>>({n_atoms, n, p, tile, ntx, box, pos, base, key, slot, count, (double*)w, ctl}, nb,
-                                  0, s);
-  return go<BinStencil<float>>({n_atoms, n, p, tile, ntx, box, pos, base, key, slot, count, (float*)w, ctl}, nb, 0,
-                               s);
+hipError_t launch_bin_tiles(int n_atoms, const double* pos, double box, int n, int p, int tile, int ntx, int* key,
+                           int* slot, int* count, Ctl* ctl, hipStream_t s) {
+  return go<BinTiles>({n_atoms, n, p, tile, ntx, box, pos, key, slot, count, ctl}, blocks_for(n_atoms, kBlock), 0, s);
+}
+
+hipError_t launch_pack_atoms(int n_atoms, const double* pos, const double* qa, double box, int n, int p,
+                             const int* perm, void* rb, double* rw, hipStream_t s) {
+  return go<PackAtoms>({n_atoms, n, p, box, pos, qa, perm, (int4*)rb, rw}, blocks_for(n_atoms, kBlock), 0, s);
 }
 
 hipError_t launch_bin_cells(int n_atoms, const double* pos, double box, int nc, int* key, int* slot,
@@ -775,30 +813,29 @@ hipError_t launch_sort_bins(int nbins, const int* start, const int* perm_raw, in
   return go<SortBins>({nbins, start, perm_raw, perm}, blocks_for((int64_t)nbins * 64, kBlock), 0, s);
 }
 
-hipError_t launch_spread(bool fp64, int n, int p, int tile, int ntx, const int* start, const int* perm,
-                         const int* base, const void* w, const double* qa, void* q, hipStream_t s) {
+hipError_t launch_spread(bool fp64, int n_atoms, int n, int p, int tile, int ntx, const int* start, const void* rb,
+                         const double* rw, void* q, hipStream_t s) {
   const int ntiles = ntx * ntx * ntx;
   if (tile != 8) return hipErrorInvalidValue;
   if (fp64)
-    return go<Spread<double, 8>>({n, p, ntx, start, perm, base, (const double*)w, qa, (double*)q}, ntiles, 0, s);
-  return go<Spread<float, 8>>({n, p, ntx, start, perm, base, (const float*)w, qa, (float*)q}, ntiles, 0, s);
+    return go<Spread<double, 8>>({n, p, ntx, n_atoms, start, (const int4*)rb, rw, (double*)q}, ntiles, 0, s);
+  return go<Spread<float, 8>>({n, p, ntx, n_atoms, start, (const int4*)rb, rw, (float*)q}, ntiles, 0, s);
 }
 
 hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, int tile, int ntx, double h, double k_e,
-                         const int* start, const int* perm, const int* base, const void* w, const double* qa,
-                         const double* phi0, const double* phi1, const float* phi32, double* force, double* partial,
-                         Ctl* ctl, hipStream_t s, bool finalize) {
+                         const int* start, const void* rb, const double* rw, const double* phi0, const double* phi1,
+                         const float* phi32, double* force, double* partial, Ctl* ctl, hipStream_t s, bool finalize) {
   if (tile != 8) return hipErrorInvalidValue;
   const int nb = std::min(ntx * ntx * ntx, kMaxRedBlocks);
   hipError_t e;
   // the step's gather (finalize) waits for a converged solve
   const Ctl* gate = finalize ? ctl : nullptr;
   if (fp64)
-    e = go<Gather<double, double, 8>>({n_atoms, n, p, ntx, h, k_e, start, perm, base, (const double*)w, qa, phi0,
-                                       phi1, force, partial, ctl, gate}, nb, 0, s);
+    e = go<Gather<double, double, 8>>({n_atoms, n, p, ntx, h, k_e, start, (const int4*)rb, rw, phi0, phi1, force,
+                                       partial, ctl, gate}, nb, 0, s);
   else
-    e = go<Gather<float, float, 8>>({n_atoms, n, p, ntx, h, k_e, start, perm, base, (const double*)w, qa, phi32,
-                                     phi32, force, partial, ctl, gate}, nb, 0, s);
+    e = go<Gather<float, float, 8>>({n_atoms, n, p, ntx, h, k_e, start, (const int4*)rb, rw, phi32, phi32, force,
+                                     partial, ctl, gate}, nb, 0, s);
   if (e != hipSuccess || !finalize) return e;
   return go<FinSum>({nb, partial, &ctl->e_lr, gate}, 1, 0, s);
 }
