@@ -945,9 +945,12 @@ p3mz_status batch_record(p3mz_batch* b, BatchSet* set, int part, std::vector<uns
       } else if (L.many != x.many || elem != x.args.size()) {
         return fail(P3MZ_ERR_STATE, "systems of one batch need the same precision and sweep structure");
       }
+      const size_t at = args->size();
       args->insert(args->end(), x.args.begin(), x.args.end());
+      const int first = L.gx;   // this system's workgroups follow the previous ones
+      memcpy(args->data() + at + x.off_field, &first, sizeof first);
       L.count++;
-      L.gx = std::max(L.gx, x.grid);
+      L.gx += x.grid;
       L.lds = std::max(L.lds, x.lds);
     }
     // round the grid up to a multiple of 8 so the XCD renumbering applies

@@ -8,10 +8,11 @@
 // where Grid is the logical workgroup index and the number of workgroups the
 // system's launch has.  k_one<K> launches it for one system (arguments by
 // value); k_many<K> launches it for many independent systems at once: the
-// grid is (max workgroups, systems), blockIdx.y picks the system's packed
-// arguments in device memory and workgroups beyond that system's own count
-// return at once.  The same run() therefore gives bitwise the same result
-// for a system whether it runs alone or inside a batch.
+// systems' workgroups are laid end to end in one grid (no idle workgroups
+// for the smaller systems), each workgroup finds its system by a binary
+// search over the packed arguments in device memory.  The same run()
+// therefore gives bitwise the same result for a system whether it runs alone
+// or inside a batch.
 //
 // Launch sites call go<K>(args, grid, lds, stream).  Normally that launches
 // k_one<K>.  While a Recorder is installed (batch set-up) it appends the
@@ -19,6 +20,7 @@
 // so the batch can merge the launch sequences of all its systems by key.
 #pragma once
 
+#include <cstddef>
 #include <cstring>
 #include <vector>
 
@@ -42,7 +44,8 @@ __device__ __forceinline__ void chunk_range(const Grid& G, int64_t count, int* l
 template <class K>
 struct Packed {
   typename K::Args a;
-  int grid;
+  int grid;   // workgroups of this system's launch
+  int off;    // first workgroup of this system in the batched grid
 };
 
 template <class K>
@@ -50,20 +53,29 @@ __global__ void __launch_bounds__(K::kThreads) k_one(typename K::Args a) {
   K::run(a, Grid{xcd_block(), (int)gridDim.x});
 }
 
+// The XCD renumbering runs over the whole batched grid, so each system's
+// workgroups stay on few XCDs, in logical order.
 template <class K>
-__global__ void __launch_bounds__(K::kThreads) k_many(const Packed<K>* __restrict__ p) {
-  const int b = xcd_block();
-  const int g = p[blockIdx.y].grid;
-  if (b >= g) return;
-  const typename K::Args a = p[blockIdx.y].a;   // uniform: scalar loads
+__global__ void __launch_bounds__(K::kThreads) k_many(const Packed<K>* __restrict__ p, int count) {
+  const int lam = xcd_block();
+  int lo = 0, hi = count - 1;   // last system whose first workgroup is <= lam (uniform)
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (p[mid].off <= lam) lo = mid;
+    else hi = mid - 1;
+  }
+  const int b = lam - p[lo].off, g = p[lo].grid;
+  if (b >= g) return;   // padding of the grid to a multiple of 8
+  const typename K::Args a = p[lo].a;   // uniform: scalar loads
   K::run(a, Grid{b, g});
 }
 
-// Launches k_many<K> over `count` packed argument sets at `dev`.
+// Launches k_many<K> over `count` packed argument sets at `dev` with `gx`
+// workgroups in all.
 using ManyFn = hipError_t (*)(const void* dev, int count, int gx, size_t lds, hipStream_t s);
 template <class K>
 hipError_t launch_many(const void* dev, int count, int gx, size_t lds, hipStream_t s) {
-  hipLaunchKernelGGL(k_many<K>, dim3(gx, count), dim3(K::kThreads), lds, s, (const Packed<K>*)dev);
+  hipLaunchKernelGGL(k_many<K>, dim3(gx), dim3(K::kThreads), lds, s, (const Packed<K>*)dev, count);
   return hipGetLastError();
 }
 
@@ -73,6 +85,7 @@ struct LaunchRec {
   ManyFn many;                      // batched launcher of the kernel
   int grid;                         // workgroups of this system's launch
   size_t lds;                       // dynamic LDS bytes
+  size_t off_field;                 // byte offset of Packed<K>::off
   std::vector<unsigned char> args;  // Packed<K> bytes
 };
 
@@ -95,12 +108,13 @@ inline void rec_key(uint32_t base) {
 template <class K>
 hipError_t go(const typename K::Args& a, int grid, size_t lds, hipStream_t s) {
   if (g_recorder) {
-    Packed<K> p{a, grid};
+    Packed<K> p{a, grid, 0};
     LaunchRec r;
     r.key = g_recorder->base * 64u + g_recorder->seq++;
     r.many = &launch_many<K>;
     r.grid = grid;
     r.lds = lds;
+    r.off_field = offsetof(Packed<K>, off);
     r.args.resize(sizeof p);
     memcpy(r.args.data(), &p, sizeof p);
     g_recorder->recs.push_back(std::move(r));

@@ -330,14 +330,15 @@ struct Spread {
 template <typename T, int TS>
 __device__ void Spread<T, TS>::run(const Args& A, Grid G) {
   constexpr int V = TS * TS * TS, CH = kChunk, MW = 3 * P3MZ_MAX_ORDER;
-  const int n = A.n, p = A.p, ntx = A.ntx;
+  const int n = A.n, p = A.p, ntx = A.ntx, pw = 3 * p;
   const int* __restrict__ start = A.start;
   const int4* __restrict__ rb = A.rb;
   const double* __restrict__ rw = A.rw;
   T* __restrict__ q = A.q;
   const size_t na = (size_t)A.n_atoms;   // row length of rw
   __shared__ T acc[kBlock / 64][V];
-  __shared__ T sw[CH][MW];       // weights x | y | z of each staged atom
+  extern __shared__ __align__(16) unsigned char spread_lds[];
+  T* const sw = reinterpret_cast<T*>(spread_lds);   // [CH][3p] weights x | y | z (dynamic LDS)
   __shared__ T sq[CH];
   __shared__ int sb[CH][3];      // stencil start relative to the tile
   __shared__ int kidx[CH];       // staged atoms that reach the tile, in chunk order
@@ -392,23 +393,38 @@ __device__ void Spread<T, TS>::run(const Args& A, Grid G) {
     say[it] = ok ? (l / p) % p : 0;
     saz[it] = ok ? l / p2 : 1 << 20;
   }
-  for (int c0 = 0; c0 < total; c0 += CH) {
-    const int m = min(CH, total - c0);
-    // stage the chunk's atoms, one per thread, with the record loaded
-    // together with the origin (one memory round trip); the ones whose
-    // stencil reaches this tile are listed in chunk order (the others sit in
-    // a lower neighbour bin too far from the shared face)
-    bool keep = false;
-    if ((int)threadIdx.x < m) {
+  // Candidate atoms are staged CH at a time, one per thread.  The records of
+  // the next chunk are loaded into registers while the current chunk is
+  // being added, so only the first chunk waits for memory.
+  int4 nr = make_int4(0, 0, 0, 0);
+  double nq = 0.0, nwv[MW];
+  auto fetch = [&](int c0) {
+    if ((int)threadIdx.x < min(CH, total - c0)) {
       const int c = c0 + threadIdx.x;
       int k = 0;
       while (c >= bin_off[k + 1]) k++;
       const int ps = bin_lo[k] + (c - bin_off[k]);   // position in bin order
-      const int4 r = rb[ps];
+      nr = rb[ps];
       const double* rec = rw + ps;
-      sq[threadIdx.x] = (T)rec[0];
-      for (int j = 0; j < 3 * p; j++) sw[threadIdx.x][j] = (T)rec[(1 + j) * na];
-      const int b3[3] = {r.x, r.y, r.z}, o3[3] = {ox, oy, oz};
+      nq = rec[0];
+#pragma unroll
+      for (int j = 0; j < MW; j++)   // fixed trip count: all loads in flight at once
+        if (j < pw) nwv[j] = rec[(1 + j) * na];
+    }
+  };
+  fetch(0);
+  for (int c0 = 0; c0 < total; c0 += CH) {
+    const int m = min(CH, total - c0);
+    // the chunk's atoms whose stencil reaches this tile are listed in chunk
+    // order (the others sit in a lower neighbour bin too far from the shared
+    // face)
+    bool keep = false;
+    if ((int)threadIdx.x < m) {
+      sq[threadIdx.x] = (T)nq;
+#pragma unroll
+      for (int j = 0; j < MW; j++)
+        if (j < pw) sw[threadIdx.x * pw + j] = (T)nwv[j];
+      const int b3[3] = {nr.x, nr.y, nr.z}, o3[3] = {ox, oy, oz};
       keep = true;
       for (int d = 0; d < 3; d++) {
         int rel = b3[d] - o3[d];              // stencil start relative to the tile, mod n
@@ -418,7 +434,6 @@ __device__ void Spread<T, TS>::run(const Args& A, Grid G) {
         sb[threadIdx.x][d] = rel < TS ? rel : rel - n;   // in [-(p-1), TS) for a kept atom
       }
     }
-    // keep the chunk order: rank of this thread among the kept ones
     const unsigned long long bal = __ballot(keep);
     if (lane == 0) wave_cnt[wv] = __popcll(bal);
     __syncthreads();
@@ -430,10 +445,12 @@ __device__ void Spread<T, TS>::run(const Args& A, Grid G) {
     }
     if (keep) kidx[slot] = threadIdx.x;
     __syncthreads();
+    if (c0 + CH < total) fetch(c0 + CH);
     // kept atoms round-robin over the waves, in chunk order per wave
     for (int ii = wv; ii < mk; ii += kBlock / 64) {
       const int i = kidx[ii];
       const int rx = sb[i][0], ry = sb[i][1], rz = sb[i][2];
+      const T* wi = sw + i * pw;
 #pragma unroll
       for (int it = 0; it < kMaxIt; it++) {
         if (it >= n_it) break;
@@ -445,7 +462,7 @@ __device__ void Spread<T, TS>::run(const Args& A, Grid G) {
           lz = az < p ? lz & (n - 1) : lz;
         }
         if ((unsigned)lx < (unsigned)TS && (unsigned)ly < (unsigned)TS && (unsigned)lz < (unsigned)TS) {
-          const T c = sq[i] * sw[i][ax] * sw[i][p + ay] * sw[i][2 * p + az];
+          const T c = sq[i] * wi[ax] * wi[p + ay] * wi[2 * p + az];
           // lanes of one atom hit distinct points and a wave's adds to one
           // point execute in program order, so the sums stay deterministic;
           // the no-return LDS add lets consecutive atoms overlap
@@ -524,9 +541,12 @@ __device__ void Gather<T, TP, TS>::run(const Args& A, Grid G) {
       const int lx = e2 % E, ly = e2 / E;
       const int gx = (ox + lx) & (n - 1), gy = (oy + ly) & (n - 1);
       const TP* col = phi + (size_t)gy * n + gx;
-      for (int lz = 0; lz < E; lz++) {
-        const int gz = (oz + lz) & (n - 1);
-        sphi[lz * E * E + e2] = (T)col[(size_t)gz * n * n];
+#pragma unroll
+      for (int lz = 0; lz < kMaxE; lz++) {   // fixed trip count: all loads in flight at once
+        if (lz < E) {
+          const int gz = (oz + lz) & (n - 1);
+          sphi[lz * E * E + e2] = (T)col[(size_t)gz * n * n];
+        }
       }
     }
     __syncthreads();
@@ -817,9 +837,10 @@ hipError_t launch_spread(bool fp64, int n_atoms, int n, int p, int tile, int ntx
                          const double* rw, void* q, hipStream_t s) {
   const int ntiles = ntx * ntx * ntx;
   if (tile != 8) return hipErrorInvalidValue;
+  const size_t lds = (size_t)Spread<double, 8>::kChunk * 3 * p * (fp64 ? sizeof(double) : sizeof(float));
   if (fp64)
-    return go<Spread<double, 8>>({n, p, ntx, n_atoms, start, (const int4*)rb, rw, (double*)q}, ntiles, 0, s);
-  return go<Spread<float, 8>>({n, p, ntx, n_atoms, start, (const int4*)rb, rw, (float*)q}, ntiles, 0, s);
+    return go<Spread<double, 8>>({n, p, ntx, n_atoms, start, (const int4*)rb, rw, (double*)q}, ntiles, lds, s);
+  return go<Spread<float, 8>>({n, p, ntx, n_atoms, start, (const int4*)rb, rw, (float*)q}, ntiles, lds, s);
 }
 
 hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, int tile, int ntx, double h, double k_e,
