@@ -314,7 +314,7 @@ __device__ void SortBins::run(const Args& A, Grid G) {
 // whole atoms from LDS, one stencil point per lane, into its own LDS copy of
 // the tile (lanes of one atom touch distinct points); the four wave copies
 // are summed in a fixed order.  No global atomics, bitwise-reproducible.
-template <typename T, int TS>
+template <typename T, int TS, int P>
 struct Spread {
   struct Args {
     int n, p, ntx, n_atoms;
@@ -327,10 +327,11 @@ struct Spread {
   static constexpr int kChunk = 128;   // staged atoms per round
   __device__ static void run(const Args& A, Grid G);
 };
-template <typename T, int TS>
-__device__ void Spread<T, TS>::run(const Args& A, Grid G) {
-  constexpr int V = TS * TS * TS, CH = kChunk, MW = 3 * P3MZ_MAX_ORDER;
-  const int n = A.n, p = A.p, ntx = A.ntx, pw = 3 * p;
+template <typename T, int TS, int P>
+__device__ void Spread<T, TS, P>::run(const Args& A, Grid G) {
+  // the assignment order is a template parameter: register arrays sized exactly
+  constexpr int V = TS * TS * TS, CH = kChunk, MW = 3 * P, p = P, pw = 3 * P;
+  const int n = A.n, ntx = A.ntx;
   const int* __restrict__ start = A.start;
   const int4* __restrict__ rb = A.rb;
   const double* __restrict__ rw = A.rw;
@@ -382,7 +383,7 @@ __device__ void Spread<T, TS>::run(const Args& A, Grid G) {
   // this lane's stencil points of an atom, l = lane + 64 it (fixed for the
   // whole kernel; p^3 <= 343 needs up to 6 per lane); invalid slots get an
   // offset that fails the in-tile test
-  constexpr int kMaxIt = (P3MZ_MAX_ORDER * P3MZ_MAX_ORDER * P3MZ_MAX_ORDER + 63) / 64;
+  constexpr int kMaxIt = (P * P * P + 63) / 64;
   int sax[kMaxIt], say[kMaxIt], saz[kMaxIt];
   const int n_it = (p3 + 63) / 64;
 #pragma unroll
@@ -446,13 +447,21 @@ __device__ void Spread<T, TS>::run(const Args& A, Grid G) {
     if (keep) kidx[slot] = threadIdx.x;
     __syncthreads();
     if (c0 + CH < total) fetch(c0 + CH);
-    // kept atoms round-robin over the waves, in chunk order per wave
-    for (int ii = wv; ii < mk; ii += kBlock / 64) {
-      const int i = kidx[ii];
+    // kept atoms round-robin over the waves, in chunk order per wave: this
+    // wave's j-th atom is kidx[wv + 4 j], its index held in lane j of one
+    // register.  Two atoms are prepared at a time and added in order, so the
+    // loads of the second overlap the first; lanes of one atom hit distinct
+    // points and a wave's adds to one point execute in program order, so the
+    // sums stay deterministic (no-return LDS adds).
+    const int nmine = (mk - wv + kBlock / 64 - 1) / (kBlock / 64);
+    const int kv = lane < nmine ? kidx[wv + (kBlock / 64) * lane] : 0;
+    auto prep = [&](int i, T* c, int* at) {
       const int rx = sb[i][0], ry = sb[i][1], rz = sb[i][2];
       const T* wi = sw + i * pw;
+      const T qi = sq[i];
 #pragma unroll
       for (int it = 0; it < kMaxIt; it++) {
+        at[it] = -1;
         if (it >= n_it) break;
         const int ax = sax[it], ay = say[it], az = saz[it];
         int lx = rx + ax, ly = ry + ay, lz = rz + az;
@@ -462,14 +471,25 @@ __device__ void Spread<T, TS>::run(const Args& A, Grid G) {
           lz = az < p ? lz & (n - 1) : lz;
         }
         if ((unsigned)lx < (unsigned)TS && (unsigned)ly < (unsigned)TS && (unsigned)lz < (unsigned)TS) {
-          const T c = sq[i] * wi[ax] * wi[p + ay] * wi[2 * p + az];
-          // lanes of one atom hit distinct points and a wave's adds to one
-          // point execute in program order, so the sums stay deterministic;
-          // the no-return LDS add lets consecutive atoms overlap
-          __hip_atomic_fetch_add(&acc[wv][(lz * TS + ly) * TS + lx], c, __ATOMIC_RELAXED,
-                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+          c[it] = qi * wi[ax] * wi[p + ay] * wi[2 * p + az];
+          at[it] = (lz * TS + ly) * TS + lx;
         }
       }
+    };
+    auto add = [&](const T* c, const int* at) {
+#pragma unroll
+      for (int it = 0; it < kMaxIt; it++)
+        if (at[it] >= 0)
+          __hip_atomic_fetch_add(&acc[wv][at[it]], c[it], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+    for (int j = 0; j < nmine; j += 2) {
+      T c0[kMaxIt], c1[kMaxIt];
+      int at0[kMaxIt], at1[kMaxIt];
+      prep(__builtin_amdgcn_readlane(kv, j), c0, at0);
+      const bool two = j + 1 < nmine;
+      if (two) prep(__builtin_amdgcn_readlane(kv, j + 1), c1, at1);
+      add(c0, at0);
+      if (two) add(c1, at1);
     }
     __syncthreads();
   }
@@ -833,14 +853,34 @@ hipError_t launch_sort_bins(int nbins, const int* start, const int* perm_raw, in
   return go<SortBins>({nbins, start, perm_raw, perm}, blocks_for((int64_t)nbins * 64, kBlock), 0, s);
 }
 
+namespace {
+template <int P>
+hipError_t spread_p(bool fp64, int n_atoms, int n, int ntx, const int* start, const void* rb, const double* rw,
+                    void* q, hipStream_t s) {
+  const int ntiles = ntx * ntx * ntx;
+  if (fp64) {
+    using K = Spread<double, 8, P>;
+    return go<K>({n, P, ntx, n_atoms, start, (const int4*)rb, rw, (double*)q}, ntiles,
+                 (size_t)K::kChunk * 3 * P * sizeof(double), s);
+  }
+  using K = Spread<float, 8, P>;
+  return go<K>({n, P, ntx, n_atoms, start, (const int4*)rb, rw, (float*)q}, ntiles,
+               (size_t)K::kChunk * 3 * P * sizeof(float), s);
+}
+}  // namespace
+
 hipError_t launch_spread(bool fp64, int n_atoms, int n, int p, int tile, int ntx, const int* start, const void* rb,
                          const double* rw, void* q, hipStream_t s) {
-  const int ntiles = ntx * ntx * ntx;
   if (tile != 8) return hipErrorInvalidValue;
-  const size_t lds = (size_t)Spread<double, 8>::kChunk * 3 * p * (fp64 ? sizeof(double) : sizeof(float));
-  if (fp64)
-    return go<Spread<double, 8>>({n, p, ntx, n_atoms, start, (const int4*)rb, rw, (double*)q}, ntiles, lds, s);
-  return go<Spread<float, 8>>({n, p, ntx, n_atoms, start, (const int4*)rb, rw, (float*)q}, ntiles, lds, s);
+  switch (p) {
+    case 2: return spread_p<2>(fp64, n_atoms, n, ntx, start, rb, rw, q, s);
+    case 3: return spread_p<3>(fp64, n_atoms, n, ntx, start, rb, rw, q, s);
+    case 4: return spread_p<4>(fp64, n_atoms, n, ntx, start, rb, rw, q, s);
+    case 5: return spread_p<5>(fp64, n_atoms, n, ntx, start, rb, rw, q, s);
+    case 6: return spread_p<6>(fp64, n_atoms, n, ntx, start, rb, rw, q, s);
+    case 7: return spread_p<7>(fp64, n_atoms, n, ntx, start, rb, rw, q, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, int tile, int ntx, double h, double k_e,
