@@ -511,7 +511,7 @@ __device__ void Spread<T, TS, P>::run(const Args& A, Grid G) {
 // LDS once; the tile's atoms (its bin, sorted) are then evaluated from LDS,
 // one thread per (atom, z-plane of the neighbourhood); the plane partial sums
 // are added in a fixed order.
-template <typename T, typename TP, int TS>
+template <typename T, typename TP, int TS, int P>
 struct Gather {
   struct Args {
     int n_atoms, n, p, ntx;
@@ -525,12 +525,14 @@ struct Gather {
     const Ctl* gate;   // non-null: do nothing unless gate->done (solve converged)
   };
   static constexpr int kThreads = kBlock;
-  static constexpr int kMaxE = TS + P3MZ_MAX_ORDER + 1;
+  static constexpr int E = TS + P + 1;   // halo tile edge
+  static constexpr int PE = P + 2;       // neighbourhood edge (stencil plus the difference)
   __device__ static void run(const Args& A, Grid G);
 };
-template <typename T, typename TP, int TS>
-__device__ void Gather<T, TP, TS>::run(const Args& A, Grid G) {
-  const int n = A.n, p = A.p, ntx = A.ntx;
+template <typename T, typename TP, int TS, int P>
+__device__ void Gather<T, TP, TS, P>::run(const Args& A, Grid G) {
+  static_assert(E * E <= kBlock, "one halo column per thread");
+  const int n = A.n, ntx = A.ntx;
   const double h = A.h, k_e = A.k_e;
   const int* __restrict__ start = A.start;
   const int4* __restrict__ rb = A.rb;
@@ -540,72 +542,108 @@ __device__ void Gather<T, TP, TS>::run(const Args& A, Grid G) {
   double* __restrict__ partial = A.partial;
   const Ctl* ctl = A.ctl;
   if (A.gate && !A.gate->done) return;
-  __shared__ T sphi[kMaxE * kMaxE * kMaxE];
+  __shared__ T sphi[E * E * E];
   __shared__ double part[kBlock][4];
   __shared__ double sh[kBlock / 64];
   // the new potential: written over phi^k on a cold solve, over phi^{k-1} otherwise
   const TP* __restrict__ phi = (ctl->cold ? ctl->k_idx : 1 - ctl->k_idx) ? A.phi1 : A.phi0;
-  const int pe = p + 2, E = TS + p + 1;
-  const int per_round = kBlock / pe;     // atoms evaluated per round
+  constexpr int per_round = kBlock / PE;   // atoms evaluated per round
   const T inv2h = (T)(0.5 / h);
+  const int tid = threadIdx.x;
   double e_sum = 0.0;
   const int ntiles = ntx * ntx * ntx;
+  // The next tile's halo column (this thread's (x, y) position, all z) and
+  // atom range are loaded into registers while the current tile is being
+  // evaluated, so a tile waits for memory only once.
+  TP hv[E];
+  int nlo = 0, nhi = 0;
+  auto fetch = [&](int t) {
+    const int tx = t % ntx, ty = (t / ntx) % ntx, tz = t / (ntx * ntx);
+    const int ox = tx * TS - 1, oy = ty * TS - 1, oz = tz * TS - 1;   // halo origin
+    if (tid < E * E) {
+      const int lx = tid % E, ly = tid / E;
+      const TP* col = phi + (size_t)((oy + ly) & (n - 1)) * n + ((ox + lx) & (n - 1));
+#pragma unroll
+      for (int lz = 0; lz < E; lz++) hv[lz] = col[(size_t)((oz + lz) & (n - 1)) * n * n];
+    }
+    nlo = start[t];
+    nhi = start[t + 1];
+  };
+  // One round: thread task = (atom ai, z-plane c of its neighbourhood); its
+  // weights and stencil origin are loaded ahead of the evaluation.  Threads
+  // k < per_round also hold atom k's index and charge for the final sums.
+  T rwx[P], rwy[P], rwz[P];
+  int4 rorg = make_int4(0, 0, 0, 0);
+  int ka = 0;
+  double kq = 0.0;
+  auto load_round = [&](int a0, int na_t, int ag) {
+    const int ai = ag + tid / PE;
+    if (tid < per_round * PE && ai < na_t) {
+      const int ps = a0 + ai;
+      const double* w = rw + na + ps;   // weight j of this atom: w[j * na]
+#pragma unroll
+      for (int j = 0; j < P; j++) {
+        rwx[j] = (T)w[j * na];
+        rwy[j] = (T)w[(P + j) * na];
+        rwz[j] = (T)w[(2 * P + j) * na];
+      }
+      rorg = rb[ps];
+    }
+    if (tid < per_round && ag + tid < na_t) {
+      const int ps = a0 + ag + tid;
+      ka = rb[ps].w;
+      kq = k_e * rw[ps];
+    }
+  };
+  if (G.b < ntiles) fetch(G.b);
   for (int t = G.b; t < ntiles; t += G.g) {
     const int tx = t % ntx, ty = (t / ntx) % ntx, tz = t / (ntx * ntx);
     const int ox = tx * TS - 1, oy = ty * TS - 1, oz = tz * TS - 1;   // halo origin
+    const int a0 = nlo, na_t = nhi - nlo;
+    load_round(a0, na_t, 0);
     __syncthreads();   // the previous tile's LDS reads are done
-    // halo tile: the threads cover (x, y) positions of a plane and walk z,
-    // so every thread issues its plane loads back to back (n is a power of
-    // two: periodic wrap by mask)
-    for (int e2 = threadIdx.x; e2 < E * E; e2 += kBlock) {
-      const int lx = e2 % E, ly = e2 / E;
-      const int gx = (ox + lx) & (n - 1), gy = (oy + ly) & (n - 1);
-      const TP* col = phi + (size_t)gy * n + gx;
+    if (tid < E * E) {
 #pragma unroll
-      for (int lz = 0; lz < kMaxE; lz++) {   // fixed trip count: all loads in flight at once
-        if (lz < E) {
-          const int gz = (oz + lz) & (n - 1);
-          sphi[lz * E * E + e2] = (T)col[(size_t)gz * n * n];
-        }
-      }
+      for (int lz = 0; lz < E; lz++) sphi[lz * E * E + tid] = (T)hv[lz];
     }
+    if (t + G.g < ntiles) fetch(t + G.g);
     __syncthreads();
-    const int a0 = start[t], na_t = start[t + 1] - a0;
     for (int ag = 0; ag < na_t; ag += per_round) {
-      const int task = threadIdx.x;
-      const int ai = ag + task / pe, c = task % pe;
-      if (task < per_round * pe && ai < na_t) {
-        const int ps = a0 + ai;   // position in bin order
-        const double* w = rw + na + ps;   // weight j of this atom: w[j * na]
-        T wx[P3MZ_MAX_ORDER + 2], wy[P3MZ_MAX_ORDER + 2], dx[P3MZ_MAX_ORDER + 2], dy[P3MZ_MAX_ORDER + 2];
-        T wz_c, dz_c;
-        {
-          T wz[P3MZ_MAX_ORDER + 2];
-          for (int j = 0; j < pe; j++) {
-            wx[j] = (j >= 1 && j <= p) ? (T)w[(j - 1) * na] : T(0);
-            wy[j] = (j >= 1 && j <= p) ? (T)w[(p + j - 1) * na] : T(0);
-            wz[j] = (j >= 1 && j <= p) ? (T)w[(2 * p + j - 1) * na] : T(0);
-          }
-          for (int j = 0; j < pe; j++) {
-            // extended index j <-> stencil offset j-1; d[j] = (w[j-1] - w[j+1]) / 2h
-            const T lo = j >= 1 ? wx[j - 1] : T(0), hi = j + 1 < pe ? wx[j + 1] : T(0);
-            dx[j] = (lo - hi) * inv2h;
-            const T loy = j >= 1 ? wy[j - 1] : T(0), hiy = j + 1 < pe ? wy[j + 1] : T(0);
-            dy[j] = (loy - hiy) * inv2h;
-          }
-          wz_c = wz[c];
-          const T loz = c >= 1 ? wz[c - 1] : T(0), hiz = c + 1 < pe ? wz[c + 1] : T(0);
-          dz_c = (loz - hiz) * inv2h;
+      const int ai = ag + tid / PE, c = tid % PE;
+      if (tid < per_round * PE && ai < na_t) {
+        // extended index j <-> stencil offset j-1; d[j] = (w[j-1] - w[j+1]) / 2h
+        T wx[PE], wy[PE], dx[PE], dy[PE], wz[PE];
+#pragma unroll
+        for (int j = 0; j < PE; j++) {
+          wx[j] = (j >= 1 && j <= P) ? rwx[j - 1] : T(0);
+          wy[j] = (j >= 1 && j <= P) ? rwy[j - 1] : T(0);
+          wz[j] = (j >= 1 && j <= P) ? rwz[j - 1] : T(0);
         }
+#pragma unroll
+        for (int j = 0; j < PE; j++) {
+          const T lo = j >= 1 ? wx[j - 1] : T(0), hi = j + 1 < PE ? wx[j + 1] : T(0);
+          dx[j] = (lo - hi) * inv2h;
+          const T loy = j >= 1 ? wy[j - 1] : T(0), hiy = j + 1 < PE ? wy[j + 1] : T(0);
+          dy[j] = (loy - hiy) * inv2h;
+        }
+        T wz_c = T(0), dz_c = T(0);
+#pragma unroll
+        for (int j = 0; j < PE; j++)
+          if (j == c) {
+            wz_c = wz[j];
+            const T loz = j >= 1 ? wz[j - 1] : T(0), hiz = j + 1 < PE ? wz[j + 1] : T(0);
+            dz_c = (loz - hiz) * inv2h;
+          }
         // neighbourhood origin in the halo tile: base - 1 - (tile origin - 1)
-        const int4 r = rb[ps];
-        const int lx0 = r.x - (ox + 1), ly0 = r.y - (oy + 1), lz0 = r.z - (oz + 1);
+        const int lx0 = rorg.x - (ox + 1), ly0 = rorg.y - (oy + 1), lz0 = rorg.z - (oz + 1);
         double fx = 0, fy = 0, fz = 0, pot = 0;
-        const T* plane = sphi + (size_t)(lz0 + c) * E * E;
-        for (int b = 0; b < pe; b++) {
+        const T* plane = sphi + (lz0 + c) * E * E;
+#pragma unroll
+        for (int b = 0; b < PE; b++) {
           const T* row = plane + (ly0 + b) * E + lx0;
           T sx = T(0), s0 = T(0);
-          for (int j = 0; j < pe; j++) {
+#pragma unroll
+          for (int j = 0; j < PE; j++) {
             const T v = row[j];
             sx += dx[j] * v;
             s0 += wx[j] * v;
@@ -615,31 +653,28 @@ __device__ void Gather<T, TP, TS>::run(const Args& A, Grid G) {
           fz += (double)(wy[b] * dz_c) * (double)s0;
           pot += (double)(wy[b] * wz_c) * (double)s0;
         }
-        part[task][0] = fx;
-        part[task][1] = fy;
-        part[task][2] = fz;
-        part[task][3] = pot;
+        part[tid][0] = fx;
+        part[tid][1] = fy;
+        part[tid][2] = fz;
+        part[tid][3] = pot;
       }
       __syncthreads();
-      if ((int)threadIdx.x < per_round && ag + (int)threadIdx.x < na_t) {
-        const int k = threadIdx.x;
-        const int ps = a0 + ag + k;
-        const int a = rb[ps].w;
+      if (tid < per_round && ag + tid < na_t) {
         double fx = 0, fy = 0, fz = 0, pot = 0;
-        for (int cc = 0; cc < pe; cc++) {
-          fx += part[k * pe + cc][0];
-          fy += part[k * pe + cc][1];
-          fz += part[k * pe + cc][2];
-          pot += part[k * pe + cc][3];
+        for (int cc = 0; cc < PE; cc++) {
+          fx += part[tid * PE + cc][0];
+          fy += part[tid * PE + cc][1];
+          fz += part[tid * PE + cc][2];
+          pot += part[tid * PE + cc][3];
         }
-        const double kq = k_e * rw[ps];
         if (force) {
-          force[3 * a] = -kq * fx;
-          force[3 * a + 1] = -kq * fy;
-          force[3 * a + 2] = -kq * fz;
+          force[3 * ka] = -kq * fx;
+          force[3 * ka + 1] = -kq * fy;
+          force[3 * ka + 2] = -kq * fz;
         }
         e_sum += 0.5 * kq * pot;
       }
+      if (ag + per_round < na_t) load_round(a0, na_t, ag + per_round);
       __syncthreads();
     }
   }
@@ -883,20 +918,36 @@ hipError_t launch_spread(bool fp64, int n_atoms, int n, int p, int tile, int ntx
   }
 }
 
+namespace {
+template <int P>
+hipError_t gather_p(bool fp64, int n_atoms, int n, int ntx, double h, double k_e, const int* start, const void* rb,
+                    const double* rw, const double* phi0, const double* phi1, const float* phi32, double* force,
+                    double* partial, Ctl* ctl, const Ctl* gate, int nb, hipStream_t s) {
+  if (fp64)
+    return go<Gather<double, double, 8, P>>({n_atoms, n, P, ntx, h, k_e, start, (const int4*)rb, rw, phi0, phi1, force,
+                                             partial, ctl, gate}, nb, 0, s);
+  return go<Gather<float, float, 8, P>>({n_atoms, n, P, ntx, h, k_e, start, (const int4*)rb, rw, phi32, phi32, force,
+                                         partial, ctl, gate}, nb, 0, s);
+}
+}  // namespace
+
 hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, int tile, int ntx, double h, double k_e,
                          const int* start, const void* rb, const double* rw, const double* phi0, const double* phi1,
                          const float* phi32, double* force, double* partial, Ctl* ctl, hipStream_t s, bool finalize) {
   if (tile != 8) return hipErrorInvalidValue;
   const int nb = std::min(ntx * ntx * ntx, kMaxRedBlocks);
-  hipError_t e;
   // the step's gather (finalize) waits for a converged solve
   const Ctl* gate = finalize ? ctl : nullptr;
-  if (fp64)
-    e = go<Gather<double, double, 8>>({n_atoms, n, p, ntx, h, k_e, start, (const int4*)rb, rw, phi0, phi1, force,
-                                       partial, ctl, gate}, nb, 0, s);
-  else
-    e = go<Gather<float, float, 8>>({n_atoms, n, p, ntx, h, k_e, start, (const int4*)rb, rw, phi32, phi32, force,
-                                     partial, ctl, gate}, nb, 0, s);
+  hipError_t e;
+  switch (p) {
+    case 2: e = gather_p<2>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rw, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
+    case 3: e = gather_p<3>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rw, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
+    case 4: e = gather_p<4>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rw, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
+    case 5: e = gather_p<5>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rw, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
+    case 6: e = gather_p<6>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rw, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
+    case 7: e = gather_p<7>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rw, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
+    default: return hipErrorInvalidValue;
+  }
   if (e != hipSuccess || !finalize) return e;
   return go<FinSum>({nb, partial, &ctl->e_lr, gate}, 1, 0, s);
 }
