@@ -161,6 +161,20 @@ __device__ void Smooth<T, AXIS, W, R>::run(const Args& A, Grid G) {
 // Reduction kernels run on a capped grid (each workgroup walks one contiguous
 // chunk), so their one-workgroup finalize pass reads few partials.
 // ---------------------------------------------------------------------------
+// Four consecutive FP64 values of a natural-layout array (t a multiple of 4:
+// 32-byte aligned, one row of the mesh).
+struct D4 {
+  double v[4];
+};
+__device__ __forceinline__ D4 ld4(const double* __restrict__ a, int t) {
+  const double2 lo = *reinterpret_cast<const double2*>(a + t), hi = *reinterpret_cast<const double2*>(a + t + 2);
+  return D4{{lo.x, lo.y, hi.x, hi.y}};
+}
+__device__ __forceinline__ void st4(double* __restrict__ a, int t, const double* v) {
+  *reinterpret_cast<double2*>(a + t) = make_double2(v[0], v[1]);
+  *reinterpret_cast<double2*>(a + t + 2) = make_double2(v[2], v[3]);
+}
+
 template <typename TQ>
 struct Sigma {
   struct Args {
@@ -176,6 +190,7 @@ struct Sigma {
 };
 template <typename TQ>
 __device__ void Sigma<TQ>::run(const Args& A, Grid G) {
+  static_assert(sizeof(TQ) == sizeof(double), "the charge source is FP64");
   const int n = A.n;
   const double h = A.h;
   const TQ* __restrict__ qs = A.qs;
@@ -201,28 +216,57 @@ __device__ void Sigma<TQ>::run(const Args& A, Grid G) {
   const double* y2 = yb[ctl->yh2];
   double sv = 0.0, qmax = 0.0;
   const int l2 = __builtin_ctz(n), msk = n - 1;
-  for (int t = lo + threadIdx.x; t < hi; t += kBlock) {
-    const int i = t & msk, j = (t >> l2) & msk, k = t >> (2 * l2);
-    const double q = (double)qs[t];
-    double s = q;
+  // four consecutive points of one row per thread (chunks are multiples of 4)
+  for (int t = lo + 4 * threadIdx.x; t < hi; t += 4 * kBlock) {
+    const int i0 = t & msk, j = (t >> l2) & msk, k = t >> (2 * l2);
+    const D4 q4 = ld4(qs, t);
+    double sg[4];
+#pragma unroll
+    for (int c = 0; c < 4; c++) sg[c] = q4.v[c];
     if (!cold) {
-      const int im = (i - 1) & msk, ip = (i + 1) & msk, jm = (j - 1) & msk, jp = (j + 1) & msk;
-      const int km = (k - 1) & msk, kp = (k + 1) & msk;
-      auto P = [&](int a) { return 2.0 * pk[a] - pkm1[a]; };
-      const double nb = ((P(nat_idx(n, im, j, k)) + P(nat_idx(n, ip, j, k))) +
-                         (P(nat_idx(n, i, jm, k)) + P(nat_idx(n, i, jp, k)))) +
-                        (P(nat_idx(n, i, j, km)) + P(nat_idx(n, i, j, kp)));
-      const double mphi = nb - 6.0 * P(t);
-      s = h / (4.0 * kPi) * mphi + q;
+      // Verlet-predicted potential P = 2 phi^k - phi^{k-1} on the row and its
+      // four neighbour rows, plus the two x neighbours beyond the vector
+      const int row = t - i0;
+      const int rym = nat_idx(n, 0, (j - 1) & msk, k), ryp = nat_idx(n, 0, (j + 1) & msk, k);
+      const int rzm = nat_idx(n, 0, j, (k - 1) & msk), rzp = nat_idx(n, 0, j, (k + 1) & msk);
+      auto P4 = [&](int a) {
+        const D4 u = ld4(pk, a), w = ld4(pkm1, a);
+        D4 r;
+#pragma unroll
+        for (int c = 0; c < 4; c++) r.v[c] = 2.0 * u.v[c] - w.v[c];
+        return r;
+      };
+      auto P1 = [&](int a) { return 2.0 * pk[a] - pkm1[a]; };
+      const D4 own = P4(t), ym = P4(rym + i0), yp = P4(ryp + i0), zm = P4(rzm + i0), zp = P4(rzp + i0);
+      const double xl = P1(row + ((i0 - 1) & msk)), xr = P1(row + ((i0 + 4) & msk));
+#pragma unroll
+      for (int c = 0; c < 4; c++) {
+        const double xm = c == 0 ? xl : own.v[c - 1], xp = c == 3 ? xr : own.v[c + 1];
+        const double nb = ((xm + xp) + (ym.v[c] + yp.v[c])) + (zm.v[c] + zp.v[c]);
+        const double mphi = nb - 6.0 * own.v[c];
+        sg[c] = h / (4.0 * kPi) * mphi + q4.v[c];
+      }
     }
-    sigma[t] = s;
-    double yv = 0.0;
-    if (m_eff == 1) yv = y0[t];
-    else if (m_eff == 2) yv = 2.0 * y0[t] - y1[t];
-    else if (m_eff == 3) yv = 3.0 * y0[t] - 3.0 * y1[t] + y2[t];
-    y[t] = yv;
-    sv += s;
-    qmax = fmax(qmax, fabs(q));
+    st4(sigma, t, sg);
+    double yv[4] = {0.0, 0.0, 0.0, 0.0};
+    if (m_eff >= 1) {
+      const D4 a0 = ld4(y0, t);
+      D4 a1 = a0, a2 = a0;
+      if (m_eff >= 2) a1 = ld4(y1, t);
+      if (m_eff >= 3) a2 = ld4(y2, t);
+#pragma unroll
+      for (int c = 0; c < 4; c++) {
+        if (m_eff == 1) yv[c] = a0.v[c];
+        else if (m_eff == 2) yv[c] = 2.0 * a0.v[c] - a1.v[c];
+        else yv[c] = 3.0 * a0.v[c] - 3.0 * a1.v[c] + a2.v[c];
+      }
+    }
+    st4(y, t, yv);
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+      sv += sg[c];
+      qmax = fmax(qmax, fabs(q4.v[c]));
+    }
   }
   double bs = block_sum(sv, sh);
   double bm = block_max(qmax, sh);
@@ -305,32 +349,78 @@ __device__ void Outer<T>::run(const Args& A, Grid G) {
   chunk_range(G, n3, &lo, &hi);
   const double mean_sigma = ctl->mean_sigma;
   double rmax = 0.0, ysum = 0.0;
-  for (int t = lo + threadIdx.x; t < hi; t += kBlock) {
-    const int i = t & msk, j = (t >> g.l2) & msk, k = t >> (2 * g.l2);
-    const int im = (i - 1) & msk, ip = (i + 1) & msk, jm = (j - 1) & msk, jp = (j + 1) & msk;
-    const int km = (k - 1) & msk, kp = (k + 1) & msk;
-    double r, yv;
+  // Correction e at four consecutive points x = i0 .. i0+3 of row (j, k):
+  // their colours alternate, so each colour array holds two of them side
+  // by side (x = i0, i0+2 in the array of colour par, x = i0+1, i0+3 in the
+  // other).
+  auto E4 = [&](int j, int k, int i0, D4* out) {
+    const int par = (i0 + j + k) & 1;
+    const int idx = cs_index(g, i0, j, k);
+    const T* a = par ? e1 : e0;
+    const T* b = par ? e0 : e1;
+    const T a0 = a[idx], a1 = a[idx + 1], b0 = b[idx], b1 = b[idx + 1];
+    out->v[0] = (double)a0;
+    out->v[1] = (double)b0;
+    out->v[2] = (double)a1;
+    out->v[3] = (double)b1;
+  };
+  auto E1 = [&](int x, int j, int k) -> double {
+    return (double)(((x + j + k) & 1) ? e1 : e0)[cs_index(g, x, j, k)];
+  };
+  // four consecutive points of one row per thread (chunks are multiples of 4)
+  for (int t = lo + 4 * threadIdx.x; t < hi; t += 4 * kBlock) {
+    const int i0 = t & msk, j = (t >> g.l2) & msk, k = t >> (2 * g.l2);
+    const int jm = (j - 1) & msk, jp = (j + 1) & msk, km = (k - 1) & msk, kp = (k + 1) & msk;
+    double r[4], yv[4];
     if (c == 0) {
-      auto Y = [&](int a, int b, int d) { return y[(((d << g.l2) + b) << g.l2) + a]; };
-      yv = y[t];
-      const double nb = ((Y(im, j, k) + Y(ip, j, k)) + (Y(i, jm, k) + Y(i, jp, k))) + (Y(i, j, km) + Y(i, j, kp));
-      r = (sigma[t] - mean_sigma) - (nb - 6.0 * yv);
+      const int row = t - i0;
+      const D4 own = ld4(y, t), ym = ld4(y, nat_idx(n, i0, jm, k)), yp = ld4(y, nat_idx(n, i0, jp, k));
+      const D4 zm = ld4(y, nat_idx(n, i0, j, km)), zp = ld4(y, nat_idx(n, i0, j, kp));
+      const double xl = y[row + ((i0 - 1) & msk)], xr = y[row + ((i0 + 4) & msk)];
+      const D4 sg = ld4(sigma, t);
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const double xm = q == 0 ? xl : own.v[q - 1], xp = q == 3 ? xr : own.v[q + 1];
+        const double nb = ((xm + xp) + (ym.v[q] + yp.v[q])) + (zm.v[q] + zp.v[q]);
+        yv[q] = own.v[q];
+        r[q] = (sg.v[q] - mean_sigma) - (nb - 6.0 * own.v[q]);
+      }
     } else {
-      auto E = [&](int a, int b, int d) -> double {
-        const T* ec = ((a + b + d) & 1) ? e1 : e0;
-        return (double)ec[cs_index(g, a, b, d)];
-      };
-      const double ev = E(i, j, k);
-      const double nb = ((E(im, j, k) + E(ip, j, k)) + (E(i, jm, k) + E(i, jp, k))) + (E(i, j, km) + E(i, j, kp));
-      yv = y[t] + ev;
-      y[t] = yv;
-      r = r64[t] - (nb - 6.0 * ev);
+      D4 own, ym, yp, zm, zp;
+      E4(j, k, i0, &own);
+      E4(jm, k, i0, &ym);
+      E4(jp, k, i0, &yp);
+      E4(j, km, i0, &zm);
+      E4(j, kp, i0, &zp);
+      const double xl = E1((i0 - 1) & msk, j, k), xr = E1((i0 + 4) & msk, j, k);
+      const D4 y4 = ld4(y, t), r4 = ld4(r64, t);
+#pragma unroll
+      for (int q = 0; q < 4; q++) {
+        const double xm = q == 0 ? xl : own.v[q - 1], xp = q == 3 ? xr : own.v[q + 1];
+        const double ev = own.v[q];
+        const double nb = ((xm + xp) + (ym.v[q] + yp.v[q])) + (zm.v[q] + zp.v[q]);
+        yv[q] = y4.v[q] + ev;
+        r[q] = r4.v[q] - (nb - 6.0 * ev);
+      }
+      st4(y, t, yv);
     }
-    r64[t] = r;
-    T* rc = ((i + j + k) & 1) ? r1 : r0;
-    rc[cs_index(g, i, j, k)] = (T)r;
-    rmax = fmax(rmax, fabs(r));
-    ysum += yv;
+    st4(r64, t, r);
+    {
+      // r in precision T, colour-split, in the pattern of E4
+      const int par = (i0 + j + k) & 1;
+      const int idx = cs_index(g, i0, j, k);
+      T* a = par ? r1 : r0;
+      T* b = par ? r0 : r1;
+      a[idx] = (T)r[0];
+      b[idx] = (T)r[1];
+      a[idx + 1] = (T)r[2];
+      b[idx + 1] = (T)r[3];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      rmax = fmax(rmax, fabs(r[q]));
+      ysum += yv[q];
+    }
   }
   double bm = block_max(rmax, sh);
   double bs = block_sum(ysum, sh);
@@ -1453,24 +1543,23 @@ hipError_t one_kernel(int kid, const LevelBufs* lv, int levels, int tail, int nu
 // variant 0 is the default, the others are candidates for the autotuner.
 constexpr int kSmoothTiles[][2] = {{16, 8}, {32, 8}, {8, 8}, {32, 4}, {16, 4}, {8, 4}, {4, 8}};
 constexpr int kSmoothTileCount = (int)(sizeof(kSmoothTiles) / sizeof(kSmoothTiles[0]));
-// dynamic LDS of one smoothing workgroup (two fit on a compute unit)
-constexpr size_t kSmoothLdsCap = 80 * 1024;
+// dynamic LDS of one smoothing workgroup: four fit on a compute unit, so
+// enough waves are in flight to cover the memory latency
+constexpr size_t kSmoothLdsCap = 40 * 1024;
 
 namespace {
-// Segment length: the longest power-of-two piece of a line (whole lines
-// first) whose workgroup fits in kSmoothLdsCap on every axis; 0 if none.
-int smooth_segment(int n, int W, int R, int ntaps) {
-  for (int S = n; S >= R; S >>= 1) {
-    const SmoothLds a0(0, W, R, ntaps, S), a1(1, W, R, ntaps, S);
-    if ((size_t)std::max(a0.total, a1.total) * sizeof(double) <= kSmoothLdsCap) return S;
-  }
+// Segment length of one axis' pass: the longest power-of-two piece of a
+// line (whole lines first) whose workgroup fits in kSmoothLdsCap; 0 if none.
+int smooth_segment(int n, int W, int R, int ntaps, int axis) {
+  for (int S = n; S >= R; S >>= 1)
+    if ((size_t)SmoothLds(axis, W, R, ntaps, S).total * sizeof(double) <= kSmoothLdsCap) return S;
   return 0;
 }
 
 template <int W, int R>
 hipError_t smooth_wr(int n, int axis, int ntaps, int half, const double* tp, const double* ip, double* op,
                      hipStream_t s) {
-  const int S = smooth_segment(n, W, R, ntaps);
+  const int S = smooth_segment(n, W, R, ntaps, axis);
   if (S == 0) return hipErrorInvalidValue;
   const int nseg = n / S;
   const int grid = (axis == 0 ? (int)((size_t)n * n / W) : (n / W) * n) * nseg;
@@ -1493,7 +1582,7 @@ int smooth_tile_count() { return kSmoothTileCount; }
 bool smooth_tile_ok(int tile, int n, int ntaps) {
   if (tile < 0 || tile >= kSmoothTileCount) return false;
   const int W = kSmoothTiles[tile][0], R = kSmoothTiles[tile][1];
-  return n % W == 0 && n % R == 0 && smooth_segment(n, W, R, ntaps) > 0;
+  return n % W == 0 && n % R == 0 && smooth_segment(n, W, R, ntaps, 0) > 0 && smooth_segment(n, W, R, ntaps, 1) > 0;
 }
 
 void smooth_tile_shape(int tile, int* w, int* r) {
@@ -1536,7 +1625,7 @@ hipError_t smooth_configure() {
 hipError_t launch_sigma(int n, double h, const double* qs, const double* phi0, const double* phi1,
                         const double* yb0, const double* yb1, const double* yb2, double* sigma, double* y,
                         double tol, int tol_mode, double* partial, Ctl* ctl, hipStream_t s, bool finalize) {
-  const int n3 = n * n * n, nb = red_blocks(n3);
+  const int n3 = n * n * n, nb = red_blocks(n3 / 4);   // four points per thread
   P3MZ_LAUNCH(go<Sigma<double>>({n, h, qs, phi0, phi1, yb0, yb1, yb2, sigma, y, partial, ctl}, nb, 0, s));
   if (!finalize) return hipSuccess;
   return go<FinSigma>({nb, n3, tol_mode, tol, partial, ctl}, 1, 0, s);
@@ -1545,7 +1634,7 @@ hipError_t launch_sigma(int n, double h, const double* qs, const double* phi0, c
 hipError_t launch_outer(bool fp64, int n, int first, int max_cycles, const double* sigma, double* y, double* r64,
                         const void* e0, const void* e1, void* r0, void* r1, double* partial, Ctl* ctl,
                         hipStream_t s, bool finalize) {
-  const int n3 = n * n * n, nb = red_blocks(n3);
+  const int n3 = n * n * n, nb = red_blocks(n3 / 4);   // four points per thread
   if (fp64)
     P3MZ_LAUNCH(go<Outer<double>>({n, first, sigma, y, r64, (const double*)e0, (const double*)e1, (double*)r0,
                                    (double*)r1, partial, ctl}, nb, 0, s));
