@@ -469,10 +469,11 @@ def main_batch(args, torch, P, w):
         parity, baseline = batch_parity_and_baseline(torch, P, w, systems)
     m, f = res.get("mixed"), res.get("fp64")
     head = m if m is not None else f
+    traffic, traffic_note = measured_traffic("halfsweep", w.name, "mixed" if m is not None else "fp64")
     roof = dict(bound="hbm", kernel="halfsweep (one batched launch over every replica's finest level)",
                 achieved=head["dominant_gbps"], peak=HBM_PEAK_GBPS, unit="GB/s",
-                frac=head["dominant_gbps"] / HBM_PEAK_GBPS, traffic=None,
-                traffic_source="no counter summary for the batched launch",
+                frac=head["dominant_gbps"] / HBM_PEAK_GBPS, traffic=traffic,
+                traffic_source=traffic_note,
                 avg_launch_us=head["dominant_avg_launch_us"], alg_bytes_per_launch=head["dominant_bytes_per_launch"],
                 launches=head["dominant_launches"], copy_ceiling_GBps=ceiling)
     line = dict(
