@@ -200,7 +200,7 @@ enum {
   P3MZ_KERNEL_RESTRICT = 3,   /* fused residual + full-weighting restriction      */
   P3MZ_KERNEL_PROLONG = 4,    /* trilinear correction of the black points         */
   P3MZ_KERNEL_SWEEP0 = 5,     /* first sweep from a zero correction               */
-  P3MZ_KERNEL_TAIL = 6,       /* LDS-resident coarse levels (<= 16^3) + 4^3 solve */
+  P3MZ_KERNEL_TAIL = 6,       /* one-workgroup coarse levels (<= 16^3; 32^3 in batches) + 4^3 solve */
   P3MZ_KERNEL_SPREAD = 7, P3MZ_KERNEL_GATHER = 8, P3MZ_KERNEL_SR = 9,
   P3MZ_KERNEL_SIGMA = 10, P3MZ_KERNEL_PHI = 11
 };

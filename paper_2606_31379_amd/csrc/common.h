@@ -8,6 +8,7 @@
 #define P3MZ_MAX_LEVELS 16
 #define P3MZ_MAX_ORDER 7
 #define P3MZ_TAIL_MAX 16        // levels of at most 16^3 run in one LDS-resident workgroup
+#define P3MZ_TAIL_MAX_BATCH 32  // batched systems: the 32^3 level joins that workgroup (in global memory)
 #define P3MZ_WAVE 64
 
 // Device-side control block.  Kernels of the V-cycle read `done` first and

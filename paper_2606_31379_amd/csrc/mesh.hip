@@ -709,40 +709,25 @@ __device__ void ResidRestrict<T, FIN, SPEC>::run(const Args& A, Grid G) {
   out[cs_index(gc, I, J, K)] = v;
 }
 
-// ResidRestrict for red_only, W = Vec<T>::W consecutive coarse points of a
-// coarse row per thread: the red residuals of each of the 9 fine rows are
-// formed as one row vector (the neighbour sums of a half-sweep) plus, in rows
-// whose red points sit at odd x, the one residual left of the vector; every
-// coarse point then sums its 13 red terms in the order of ResidRestrict, so
-// the results are those of the one-point-per-thread kernel.
-template <typename T, int FIN, int SPEC>
-struct RestrictRed {
-  using Args = typename ResidRestrict<T, FIN, SPEC>::Args;
-  static constexpr int kThreads = 64;
-  __device__ static void run(const Args& A, Grid G);
-};
-template <typename T, int FIN, int SPEC>
-__device__ void RestrictRed<T, FIN, SPEC>::run(const Args& A, Grid G) {
+// Full weighting x 4 at the coarse points I0 .. I0+W-1 of coarse row (J,K),
+// the red residuals r - M e of the 9 fine rows formed on the fly (the black
+// ones vanish after a black half-sweep), in the order of ResidRestrict.
+// ROWS_UNROLL: how far the 3 x 3 row loop is unrolled (3 for the separate
+// launch; 1 inside the tail, whose 1024-thread workgroup has fewer registers).
+template <typename T, int ROWS_UNROLL>
+__device__ __forceinline__ void restrict_red_recompute(const T* e0, const T* e1, const T* r0, const CsGeo& g, int I0,
+                                                       int J, int K, T* v) {
   constexpr int W = Vec<T>::W;
   using V = typename Vec<T>::type;
-  const int n = A.n;
-  const T* __restrict__ e0 = A.e0;
-  const T* __restrict__ e1 = A.e1;
-  const T* __restrict__ r0 = A.r0;
-  const int done = A.ctl->done;
-  if (!SPEC && done) return;
-  const CsGeo g(n), gc(n >> 1);
-  const int nc = gc.n;
-  const int t = (G.b * kThreads + threadIdx.x) * W;
-  if (t >= nc * nc * nc) return;
-  const int I0 = t & (nc - 1), J = (t >> gc.l2) & (nc - 1), K = t >> (2 * gc.l2);
   const T wt[3] = {T(0.25), T(0.5), T(0.25)};
-  const int msk = n - 1;
+  const int msk = g.n - 1, nc = g.hn;
   T s[W];
 #pragma unroll
   for (int q = 0; q < W; q++) s[q] = T(0);
+#pragma unroll ROWS_UNROLL
   for (int c = -1; c <= 1; c++) {
     const int z = (2 * K + c) & msk;
+#pragma unroll ROWS_UNROLL
     for (int b = -1; b <= 1; b++) {
       const int y = (2 * J + b) & msk;
       const int par = (y + z) & 1;   // red points of this row sit at x = 2m + par
@@ -779,9 +764,38 @@ __device__ void RestrictRed<T, FIN, SPEC>::run(const Args& A, Grid G) {
       }
     }
   }
-  T v[W];
 #pragma unroll
   for (int q = 0; q < W; q++) v[q] = T(4) * s[q];
+}
+
+// ResidRestrict for red_only, W = Vec<T>::W consecutive coarse points of a
+// coarse row per thread: the red residuals of each of the 9 fine rows are
+// formed as one row vector (the neighbour sums of a half-sweep) plus, in rows
+// whose red points sit at odd x, the one residual left of the vector; every
+// coarse point then sums its 13 red terms in the order of ResidRestrict, so
+// the results are those of the one-point-per-thread kernel.
+template <typename T, int FIN, int SPEC>
+struct RestrictRed {
+  using Args = typename ResidRestrict<T, FIN, SPEC>::Args;
+  static constexpr int kThreads = 64;
+  __device__ static void run(const Args& A, Grid G);
+};
+template <typename T, int FIN, int SPEC>
+__device__ void RestrictRed<T, FIN, SPEC>::run(const Args& A, Grid G) {
+  constexpr int W = Vec<T>::W;
+  const int n = A.n;
+  const T* __restrict__ e0 = A.e0;
+  const T* __restrict__ e1 = A.e1;
+  const T* __restrict__ r0 = A.r0;
+  const int done = A.ctl->done;
+  if (!SPEC && done) return;
+  const CsGeo g(n), gc(n >> 1);
+  const int nc = gc.n;
+  const int t = (G.b * kThreads + threadIdx.x) * W;
+  if (t >= nc * nc * nc) return;
+  const int I0 = t & (nc - 1), J = (t >> gc.l2) & (nc - 1), K = t >> (2 * gc.l2);
+  T v[W];
+  restrict_red_recompute<T, 3>(e0, e1, r0, g, I0, J, K, v);
   if (SPEC) {
     keep_issued(v[W - 1]);
     if (done) return;
@@ -952,14 +966,15 @@ struct FillZero {
 };
 
 // ---------------------------------------------------------------------------
-// Tail of the V-cycle: all levels from n0 <= 16 down to 4^3 and back in one
-// workgroup, LDS-resident in the same colour-split layout as the upper
-// levels, with the exact coarsest solve e = G * r (G the periodic 4^3
-// Green's function of M, FP64 accumulation).  Each phase performs the
-// operation of the corresponding multi-workgroup kernel above with the same
-// order of operations, so a level's result does not depend on where it runs;
-// sweeps, the first sweep from zero and the residual work on 16-byte row
-// vectors.  LDS per level q (edge n_q = n0 >> q): e0, e1, r0, r1 of
+// Tail of the V-cycle: all levels from n0 down to 4^3 and back in one
+// workgroup, with the exact coarsest solve e = G * r (G the periodic 4^3
+// Green's function of M, FP64 accumulation).  Levels up to 16^3 are
+// LDS-resident in the same colour-split layout as the upper levels; a top
+// level of 32^3 (batched systems) stays in global memory.  Each phase
+// performs the operation of the corresponding multi-workgroup kernel above
+// with the same order of operations, so a level's result does not depend on
+// where it runs; sweeps, the first sweep from zero and the residual work on
+// 16-byte row vectors.  LDS per level q (edge n_q): e0, e1, r0, r1 of
 // n_q^3/2 elements each, then the red residuals of the current level.
 // ---------------------------------------------------------------------------
 // Full weighting x 4 at the coarse points I0 .. I0+W-1 of coarse row (J,K)
@@ -1015,7 +1030,7 @@ __device__ __forceinline__ int tail_level_offset(int n0, int q) {
   return off;
 }
 
-// One half-sweep of colour `colour` (Halfsweep on LDS arrays).
+// One half-sweep of colour `colour` (Halfsweep on LDS or global arrays).
 template <typename T>
 __device__ __forceinline__ void tail_half(T* ec, const T* eo, const T* rc, const CsGeo& g, int half, int colour) {
   constexpr int W = Vec<T>::W;
@@ -1032,6 +1047,11 @@ __device__ __forceinline__ void tail_half(T* ec, const T* eo, const T* rc, const
     *reinterpret_cast<V*>(ec + t) = out;
   }
 }
+
+// Levels of the tail up to this edge live in LDS; a tail whose top level is
+// larger keeps that one level in global memory (same workgroup, so its
+// phases are ordered by the same barriers) and the rest in LDS.
+constexpr int kTailLdsMax = 16;
 
 template <typename T>
 struct Tail {
@@ -1057,13 +1077,29 @@ __device__ void Tail<T>::run(const Args& A, Grid) {
   extern __shared__ __align__(16) unsigned char tail_lds[];
   __shared__ double G[64];
   T* const base = reinterpret_cast<T*>(tail_lds);
-  T* const rho = base + tail_level_offset(n0, levels);
+  // level q has edge n0 >> q; with a global top level, LDS starts at q = 1
+  const int q0 = n0 > kTailLdsMax ? 1 : 0, nl = n0 >> q0;
+  T* const rho = base + tail_level_offset(nl, levels - q0);   // red residuals of an LDS level
+  auto E0 = [&](int q) -> T* { return q < q0 ? A.e0 : base + tail_level_offset(nl, q - q0); };
+  auto E1 = [&](int q) -> T* {
+    const int n = n0 >> q;
+    return q < q0 ? A.e1 : E0(q) + n * n * n / 2;
+  };
+  auto R0 = [&](int q) -> T* {
+    const int n = n0 >> q;
+    return q < q0 ? const_cast<T*>(A.r0) : E0(q) + n * n * n;
+  };
+  auto R1 = [&](int q) -> T* {
+    const int n = n0 >> q;
+    return q < q0 ? const_cast<T*>(A.r1) : E0(q) + 3 * (n * n * n / 2);
+  };
   const int tid = threadIdx.x, nt = blockDim.x;
   if (tid < 64) G[tid] = A.green[tid];
-  {
+  if (q0 == 0) {
+    // the top level is in LDS: its right-hand side comes from global memory
     const int half = n0 * n0 * n0 / 2;
-    T* r0 = base + 2 * half;
-    T* r1 = r0 + half;
+    T* r0 = R0(0);
+    T* r1 = R1(0);
     for (int t = tid; t < half; t += nt) {
       r0[t] = A.r0[t];
       r1[t] = A.r1[t];
@@ -1074,11 +1110,15 @@ __device__ void Tail<T>::run(const Args& A, Grid) {
   const T wt[3] = {T(0.25), T(0.5), T(0.25)};
   for (int q = 0; q + 1 < levels; q++) {
     const int n = n0 >> q, half = n * n * n / 2;
-    T* e0 = base + tail_level_offset(n0, q);
-    T* e1 = e0 + half;
-    T* r0 = e1 + half;
-    T* r1 = r0 + half;
+    T* e0 = E0(q);
+    T* e1 = E1(q);
+    const T* r0 = R0(q);
+    const T* r1 = R1(q);
     const CsGeo g(n);
+    const int nc = n >> 1;
+    const CsGeo gc(nc);
+    T* rc0 = R0(q + 1);
+    T* rc1 = R1(q + 1);
     if (nu1 >= 1) {
       // first sweep from e = 0 (SweepZero): red = -r/6, black from those reds
       const T sixth = T(1.0 / 6.0);
@@ -1105,6 +1145,22 @@ __device__ void Tail<T>::run(const Args& A, Grid) {
         tail_half(e1, e0, r1, g, half, 1);
         __syncthreads();
       }
+      if (q < q0) {
+        // global level: the red residuals are formed inside the restriction
+        // (RestrictRed), W coarse points per task
+        for (int p = tid * W; p < nc * nc * nc; p += nt * W) {
+          const int I0 = p & (nc - 1), J = (p >> gc.l2) & (nc - 1), K = p >> (2 * gc.l2);
+          T v[W];
+          restrict_red_recompute<T, 1>(e0, e1, r0, g, I0, J, K, v);
+#pragma unroll
+          for (int c = 0; c < W; c++) {
+            const int I = I0 + c;
+            (((I + J + K) & 1) ? rc1 : rc0)[cs_index(gc, I, J, K)] = v[c];
+          }
+        }
+        __syncthreads();
+        continue;
+      }
       // residual at the red points; after the black half-sweep the black
       // residuals vanish up to rounding and are taken as zero (ResidRestrict)
       for (int t = tid * W; t < half; t += nt * W) {
@@ -1129,19 +1185,16 @@ __device__ void Tail<T>::run(const Args& A, Grid) {
     __syncthreads();
     {
       // full weighting x 4 into the next level's right-hand side
-      const int nc = n >> 1, hc = nc * nc * nc / 2, msk = n - 1;
-      const CsGeo gc(nc);
-      T* rc0 = base + tail_level_offset(n0, q + 1) + 2 * hc;
-      T* rc1 = rc0 + hc;
+      const int msk = n - 1;
       if (nu1 >= 1) {
         for (int p = tid * W; p < nc * nc * nc; p += nt * W) {
           const int I0 = p & (nc - 1), J = (p >> gc.l2) & (nc - 1), K = p >> (2 * gc.l2);
           T v[W];
           restrict_red_vec(rho, g, I0, J, K, v);
 #pragma unroll
-          for (int q = 0; q < W; q++) {
-            const int I = I0 + q;
-            (((I + J + K) & 1) ? rc1 : rc0)[cs_index(gc, I, J, K)] = v[q];
+          for (int c = 0; c < W; c++) {
+            const int I = I0 + c;
+            (((I + J + K) & 1) ? rc1 : rc0)[cs_index(gc, I, J, K)] = v[c];
           }
         }
       } else {
@@ -1173,11 +1226,11 @@ __device__ void Tail<T>::run(const Args& A, Grid) {
   {
     // 4^3: e = G * r with FP64 accumulation; 16 consecutive lanes share one
     // output point, each summing 4 of the 64 terms, then a fixed shuffle tree
-    const int q = levels - 1, half = 32;
-    T* e0 = base + tail_level_offset(n0, q);
-    T* e1 = e0 + half;
-    const T* r0 = e1 + half;
-    const T* r1 = r0 + half;
+    const int q = levels - 1;
+    T* e0 = E0(q);
+    T* e1 = E1(q);
+    const T* r0 = R0(q);
+    const T* r1 = R1(q);
     const CsGeo g4(4);
     const int o = tid >> 4, part = tid & 15;
     double s = 0.0;
@@ -1197,13 +1250,13 @@ __device__ void Tail<T>::run(const Args& A, Grid) {
     __syncthreads();
   }
   for (int q = levels - 2; q >= 0; q--) {
-    const int n = n0 >> q, half = n * n * n / 2, hc = half / 8;
-    T* e0 = base + tail_level_offset(n0, q);
-    T* e1 = e0 + half;
-    const T* r0 = e1 + half;
-    const T* r1 = r0 + half;
-    const T* c0 = base + tail_level_offset(n0, q + 1);
-    const T* c1 = c0 + hc;
+    const int n = n0 >> q, half = n * n * n / 2;
+    T* e0 = E0(q);
+    T* e1 = E1(q);
+    const T* r0 = R0(q);
+    const T* r1 = R1(q);
+    const T* c0 = E0(q + 1);
+    const T* c1 = E1(q + 1);
     const CsGeo g(n), gc(n >> 1);
     if (nu2 >= 1) {
       // the next red half-sweep overwrites every red point: only black points
@@ -1227,10 +1280,11 @@ __device__ void Tail<T>::run(const Args& A, Grid) {
       __syncthreads();
     }
   }
-  {
+  if (q0 == 0) {
+    // LDS top level: the correction goes back to global memory
     const int half = n0 * n0 * n0 / 2;
-    const T* e0 = base;
-    const T* e1 = base + half;
+    const T* e0 = E0(0);
+    const T* e1 = E1(0);
     for (int t = tid * W; t < half; t += nt * W) {
       *reinterpret_cast<V*>(A.e0 + t) = *reinterpret_cast<const V*>(e0 + t);
       *reinterpret_cast<V*>(A.e1 + t) = *reinterpret_cast<const V*>(e1 + t);
@@ -1239,6 +1293,10 @@ __device__ void Tail<T>::run(const Args& A, Grid) {
 }
 
 size_t tail_lds_bytes(int n0, int levels, size_t elem) {
+  if (n0 > kTailLdsMax) {   // the top level stays in global memory
+    n0 >>= 1;
+    levels -= 1;
+  }
   size_t tot = 0;
   for (int q = 0; q < levels; q++) {
     const size_t nq = (size_t)(n0 >> q);
