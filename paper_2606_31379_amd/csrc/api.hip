@@ -220,7 +220,10 @@ struct p3mz_ctx {
   bool sub_events = false;       // the sub-stage events were recorded this step
   bool ran_graphs = false;       // the last step was launched from graphs
   hipStream_t cap = nullptr;
-  GraphSlot g_pre, g_cycle, g_post1, g_post2, g_md_post2;
+  GraphSlot g_pre, g_post1, g_post2, g_md_post2;
+  // g_cycles[k]: k consecutive V-cycles (each with its outer residual) in one graph
+  static constexpr int kCycleGraphMax = 16;
+  GraphSlot g_cycles[kCycleGraphMax + 1];
   // optional timing: stage events and one kernel family's per-launch events
   bool timing = false;
   hipEvent_t stage_ev[5] = {};
@@ -250,7 +253,7 @@ struct p3mz_ctx {
   }
   void drop_graphs() {
     g_pre.reset();
-    g_cycle.reset();
+    for (GraphSlot& g : g_cycles) g.reset();
     g_post1.reset();
     g_post2.reset();
     g_md_post2.reset();
@@ -686,10 +689,17 @@ p3mz_status read_head(p3mz_ctx* c, hipStream_t s) {
 p3mz_status run_solve(p3mz_ctx* c, double* force, hipStream_t s) {
   int issued = 0;
   int batch = std::max(1, c->last_cycles);
-  const std::vector<uint64_t> key = {1};
   for (;;) {
-    for (int b = 0; b < batch && issued < c->P.max_cycles; b++, issued++)
-      P3MZ_TRY(run_seq(c, c->g_cycle, key, s, [&](hipStream_t q) { return enq_cycle(c, q); }));
+    // the cycles of a batch go out as few graph launches as possible
+    for (int left = std::min(batch, c->P.max_cycles - issued); left > 0;) {
+      const int k = std::min(left, p3mz_ctx::kCycleGraphMax);
+      P3MZ_TRY(run_seq(c, c->g_cycles[k], {(uint64_t)k}, s, [&](hipStream_t q) {
+        for (int i = 0; i < k; i++) P3MZ_TRY(enq_cycle(c, q));
+        return P3MZ_OK;
+      }));
+      left -= k;
+      issued += k;
+    }
     P3MZ_TRY(run_seq(c, c->g_post1, {(uint64_t)(uintptr_t)force, c->timing}, s,
                      [&](hipStream_t q) { return enq_post1(c, force, q); }));
     stage(c, 3, s);
