@@ -136,6 +136,21 @@ def test_water_3000_steps(torch, precision, bar):
     check_steps(res, bar)
 
 
+@pytest.mark.parametrize("order", [2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("mesh", [8, 32])
+@pytest.mark.parametrize("precision,bar", [(0, FP64_BAR), (1, MIXED_BAR)])
+def test_forces_every_order(torch, order, mesh, precision, bar):
+    # every assignment order of the spread and gather kernels, on a one-tile
+    # mesh (stencils wrap onto the same tile) and on a 4^3-tile mesh; 300
+    # atoms in a 12 A box put more atoms in some tiles than one gather round
+    # holds at the high orders
+    s = inputs.random_neutral(300, 12.0, seed=100 + 10 * order + mesh, dmin=0.7)
+    alpha = 0.25 if mesh == 8 else 0.45
+    gp, op = params_pair(12.0, alpha, 5.0, mesh, order, tol=1e-9, precision=precision)
+    res = run_pair(torch, s, gp, op, steps=2)
+    check_steps(res, bar)
+
+
 @pytest.mark.parametrize("pred", [0, 1, 2])
 def test_predictor_ramp_and_counts(torch, pred):
     s = inputs.nacl(128, 25.2 * (128 / 512) ** (1 / 3), 1300.0, seed=77)
