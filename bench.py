@@ -198,7 +198,8 @@ def run_mode(torch, P, w, system, precision, warmup, steps, kernel, schedule=Non
         # library's stream.  (Events around every single in-step launch add a
         # few microseconds of event overhead to a ~3 us kernel; back-to-back
         # launches agree with the profiler's per-dispatch durations.)
-        burst_ok = dominant in ("halfsweep", "sweep0", "restrict", "prolong", "tail", "smooth", "outer", "sigma",
+        burst_ok = dominant in ("halfsweep", "sweep0", "restrict", "prolong", "tail", "fused_down", "fused_up",
+                                "smooth", "outer", "sigma",
                                 "spread", "gather")
         reps = 200
         kms, kbytes = P.p3mz_kernel_bench(ctx, P.KERNELS[dominant], reps, stream) if burst_ok else (float("nan"), 0.0)

@@ -202,7 +202,9 @@ enum {
   P3MZ_KERNEL_SWEEP0 = 5,     /* first sweep from a zero correction               */
   P3MZ_KERNEL_TAIL = 6,       /* one-workgroup coarse levels (<= 16^3; 32^3 in batches) + 4^3 solve */
   P3MZ_KERNEL_SPREAD = 7, P3MZ_KERNEL_GATHER = 8, P3MZ_KERNEL_SR = 9,
-  P3MZ_KERNEL_SIGMA = 10, P3MZ_KERNEL_PHI = 11
+  P3MZ_KERNEL_SIGMA = 10, P3MZ_KERNEL_PHI = 11,
+  P3MZ_KERNEL_FUSED_DOWN = 12, /* fused down leg of a small level (first sweep + pairs) */
+  P3MZ_KERNEL_FUSED_UP = 13    /* fused up leg of a small level (correction + pairs)    */
 };
 /* Start timing one kernel family (kernel_id as above, -1 = off) and zero the
  * totals.  Up to 2048 launches per compute are timed.  While a family is timed
@@ -217,7 +219,8 @@ p3mz_status p3mz_get_kernel_timer(const p3mz_ctx* ctx, double* total_ms, int64_t
 /* Back-to-back timing of one finest-level kernel on the context's current
  * buffers: `reps` launches between two HIP events on `stream`; *avg_ms is the
  * mean launch duration and *bytes_per_launch its algorithmic HBM traffic.
- * Families: HALFSWEEP, SWEEP0, RESTRICT, PROLONG, TAIL, SMOOTH (x axis),
+ * Families: HALFSWEEP, SWEEP0, RESTRICT, PROLONG, TAIL, FUSED_DOWN and
+ * FUSED_UP (finest level fused), SMOOTH (x axis),
  * OUTER and SIGMA (without their one-workgroup finalize pass), SPREAD and
  * GATHER (on the last step's binning, no forces written).  Overwrites
  * scratch buffers only; the potential and multiplier history is untouched.
@@ -232,6 +235,17 @@ p3mz_status p3mz_kernel_bench(p3mz_ctx* ctx, int32_t kernel_id, int32_t reps, vo
  * identical results).  Synchronises the device; graphs are recaptured. */
 #define P3MZ_SMOOTH_TILES 7
 p3mz_status p3mz_set_schedule(p3mz_ctx* ctx, int32_t nu_pre, int32_t nu_post, int32_t smooth_tile);
+
+/* Multigrid levels above the one-workgroup tail whose edge is at most
+ * max_edge (levels of 16^3 .. 64^3 qualify; 0 = none) run each leg of the
+ * V-cycle (the pre-smoothing sweeps, and the correction plus post-smoothing
+ * sweeps) as one launch: each workgroup keeps a tile of grid rows with a halo
+ * of one row per sweep in LDS and recomputes the halo instead of exchanging
+ * it (temporal blocking).  Needs nu_pre, nu_post >= 1 and the halo box within
+ * 160 KiB of LDS; other levels and schedules keep one launch per sweep.
+ * Results are bitwise identical either way.  Default 64.  Synchronises the
+ * device; graphs are recaptured.  Errors: INVALID_ARG for max_edge < 0. */
+p3mz_status p3mz_set_fused_levels(p3mz_ctx* ctx, int32_t max_edge);
 
 typedef struct {
   int32_t nu_pre, nu_post;   /* chosen schedule                                        */

@@ -475,6 +475,11 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
     P3MZ_TRY(c->allocb(&b.e1, half * c->tsz));
     P3MZ_TRY(c->allocb(&b.r0, half * c->tsz));
     P3MZ_TRY(c->allocb(&b.r1, half * c->tsz));
+    if (l < pl.tail && nl <= kFusedEdgeMax && nl >= 16) {
+      P3MZ_TRY(c->allocb(&b.d0, half * c->tsz));
+      P3MZ_TRY(c->allocb(&b.d1, half * c->tsz));
+      b.fty = b.ftz = fused_tile(nl);
+    }
   }
   // every reduction grid is capped, so one fixed-size partial buffer fits all
   P3MZ_TRY(c->alloc(&c->d_partial, kPartialSlots));
@@ -493,6 +498,7 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   size_t lds = 0;
   P3MZ_HIP_TRY(tail_configure(c->fp64, n >> pl.tail, pl.levels - pl.tail, &lds));
   P3MZ_HIP_TRY(smooth_configure());
+  P3MZ_HIP_TRY(fused_configure());
   P3MZ_HIP_TRY(hipDeviceSynchronize());
   return P3MZ_OK;
 }
@@ -1532,6 +1538,18 @@ p3mz_status p3mz_set_schedule(p3mz_ctx* ctx, int32_t nu_pre, int32_t nu_post, in
   return P3MZ_OK;
 }
 
+p3mz_status p3mz_set_fused_levels(p3mz_ctx* ctx, int32_t max_edge) {
+  if (!ctx) return fail(P3MZ_ERR_INVALID_ARG, "ctx is NULL");
+  if (max_edge < 0) return fail(P3MZ_ERR_INVALID_ARG, "max_edge must be >= 0");
+  P3MZ_HIP_TRY(hipDeviceSynchronize());
+  ctx->drop_graphs();
+  for (int l = 0; l < ctx->pl.levels; l++) {
+    LevelBufs& b = ctx->lv[l];
+    b.fty = b.ftz = (b.d0 && b.n <= max_edge) ? fused_tile(b.n) : 0;
+  }
+  return P3MZ_OK;
+}
+
 p3mz_status p3mz_autotune(p3mz_ctx* ctx, const double* frames_dev, int32_t n_frames, void* stream,
                           p3mz_tune_result* out) {
   if (!ctx || !frames_dev || n_frames < 1 || n_frames > 64 || !out)
@@ -1677,10 +1695,14 @@ p3mz_status p3mz_batch_create(int32_t n_sys, const p3mz_params* per_sys, const i
   // worth moving into the single-workgroup tail: it saves five launches per
   // V-cycle.  The tail performs the same operations in the same order as
   // the separate launches, so results are unchanged.
+  // The fused legs of the small levels trade redundant halo work for fewer
+  // launches; side by side with other systems' launches a batch is bound by
+  // throughput instead, so batched systems keep one launch per sweep.
   for (p3mz_ctx* c : b->sys) {
     Plan& pl = c->pl;
     pl.tail = 0;
     while ((pl.n >> pl.tail) > P3MZ_TAIL_MAX_BATCH) pl.tail++;
+    for (int l = 0; l < pl.levels; l++) c->lv[l].fty = c->lv[l].ftz = 0;
     size_t lds = 0;
     const hipError_t e = tail_configure(c->fp64, pl.n >> pl.tail, pl.levels - pl.tail, &lds);
     if (e != hipSuccess) {

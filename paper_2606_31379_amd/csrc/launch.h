@@ -7,7 +7,8 @@
 // Kernel families that can be timed individually with HIP events.
 enum KernelId {
   KT_HALFSWEEP = 0, KT_OUTER = 1, KT_SMOOTH = 2, KT_RESTRICT = 3, KT_PROLONG = 4, KT_SWEEP0 = 5,
-  KT_TAIL = 6, KT_SPREAD = 7, KT_GATHER = 8, KT_SR = 9, KT_SIGMA = 10, KT_PHI = 11, KT_COUNT = 12
+  KT_TAIL = 6, KT_SPREAD = 7, KT_GATHER = 8, KT_SR = 9, KT_SIGMA = 10, KT_PHI = 11, KT_FUSED_DOWN = 12,
+  KT_FUSED_UP = 13, KT_COUNT = 14
 };
 // Bracket one launch of kernel family `id` on multigrid level `level` with
 // events when that family/level is being timed (no-ops otherwise).
@@ -89,9 +90,18 @@ struct LevelBufs {
   int n;
   void* e0; void* e1;   // colour-split correction
   void* r0; void* r1;   // colour-split right-hand side
+  // fused legs (fty > 0): tiles of fty x ftz rows; the down leg writes d0/d1,
+  // the up leg reads d1 and writes e0/e1
+  void* d0 = nullptr; void* d1 = nullptr;
+  int fty = 0, ftz = 0;
 };
+// Largest level edge that gets the fused-leg buffers.
+constexpr int kFusedEdgeMax = 64;
+// Tile rows of a fused level of edge n (0: the level is not fused).
+int fused_tile(int n);
 // One V-cycle on the colour-split level hierarchy lv[0..levels-1]; the
-// levels from `tail` on run in one LDS-resident workgroup.
+// levels from `tail` on run in one LDS-resident workgroup; levels with
+// fty > 0 run each leg as one fused launch when its LDS box fits.
 hipError_t launch_vcycle(bool fp64, const LevelBufs* lv, int levels, int tail, int nu1, int nu2,
                          const double* green, Ctl* ctl, hipStream_t s);
 // One finest-level launch of a V-cycle kernel family (KT_HALFSWEEP, KT_SWEEP0,
@@ -115,6 +125,8 @@ hipError_t launch_sub_scalar(int64_t count, const double* in, double* out, const
 hipError_t tail_configure(bool fp64, int n_tail, int levels_tail, size_t* lds_bytes);
 // Allows the smoothing kernels the LDS they need on an n^3 mesh.
 hipError_t smooth_configure();
+// Allows the fused-leg kernels their LDS.
+hipError_t fused_configure();
 
 // ---- molecular dynamics (md.hip) ----------------------------------------
 hipError_t launch_kick_drift(int n_atoms, double* pos, double* vel, const double* force,

@@ -512,6 +512,16 @@ template <> __device__ __forceinline__ void vset<double>(double2& v, int q, doub
   if (q == 0) v.x = x; else v.y = x;
 }
 
+// -x/6 rounded on its own.  The first sweep from e = 0 sums red values -r/6
+// that it computes on the fly; without contraction they are exactly the
+// values a stored red array would hold, so the sweep's black result does not
+// depend on whether the reds come from memory or are recomputed.
+template <typename T>
+__device__ __forceinline__ T neg_sixth(T x) {
+#pragma clang fp contract(off)
+  return -x * T(1.0 / 6.0);
+}
+
 // Speculative start of the small V-cycle launches: the control block's stop
 // flag and the operands are loaded together and the flag is tested just
 // before the first store, so the two memory round trips of a launch that
@@ -589,10 +599,10 @@ __device__ void SweepZero<T, FIN, SPEC>::run(const Args& A, Grid G) {
   const V rr = *reinterpret_cast<const V*>(r0 + t);
   V er;
 #pragma unroll
-  for (int q = 0; q < W; q++) vset<T>(er, q, -vget<T>(rr, q) * sixth);
+  for (int q = 0; q < W; q++) vset<T>(er, q, neg_sixth(vget<T>(rr, q)));
   // black points of the same row: their neighbours are the red values -r0/6
   T nb[W];
-  cs_nbr6_vec(r0, g, t, m, j, k, (1 + j + k) & 1, [sixth](T x) { return -x * sixth; }, nb);
+  cs_nbr6_vec(r0, g, t, m, j, k, (1 + j + k) & 1, [](T x) { return neg_sixth(x); }, nb);
   const V rb = *reinterpret_cast<const V*>(r1 + t);
   V eb;
 #pragma unroll
@@ -966,6 +976,136 @@ struct FillZero {
 };
 
 // ---------------------------------------------------------------------------
+// Fused smoothing of a small level (temporal blocking).  On levels whose
+// kernels are bound by launch and memory latency rather than bandwidth, one
+// launch runs a whole leg's chain of half-sweeps: a workgroup owns a tile of
+// TY x TZ full x-rows and holds, in LDS, a box of rows around it with a halo
+// of S rows in y and z (S = number of neighbour-dependent half-sweeps).  The
+// first operation is pointwise and fills the box; half-sweep s then updates
+// the box shrunk to halo S-1-s, so the last one produces the tile itself.
+// Every point value is computed with the arithmetic, operand order and
+// neighbour order of the unfused kernels (SweepZero, ProlongBlack,
+// Halfsweep), so the level's result is bitwise that of the unfused chain;
+// halo values are recomputed redundantly by neighbouring tiles.
+//   down leg (UP = 0): red = -r/6 everywhere (first sweep from e = 0), then
+//     black, red, ... (S = 2 nu1 - 1 half-sweeps); out = down-leg buffers.
+//   up leg (UP = 1): black += trilinear correction (ProlongBlack), then red,
+//     black, ... (S = 2 nu2 half-sweeps).  The black input (the down leg's
+//     result) and the output are different buffers: a tile reads its halo
+//     rows while neighbouring tiles write their own rows.
+// LDS: e of both colours on the box (halo S), r of both colours on the box
+// shrunk by one (halo S-1), rows of n/2 elements per colour.
+// ---------------------------------------------------------------------------
+struct FusedBox {
+  int by, bz, ry, rz;   // rows of the e box (halo S) and of the r box (halo S-1)
+  size_t elems;         // LDS elements of e0, e1, r0, r1
+  FusedBox(int n, int ty, int tz, int S)
+      : by(ty + 2 * S), bz(tz + 2 * S), ry(ty + 2 * S - 2), rz(tz + 2 * S - 2),
+        elems((size_t)(n / 2) * (2 * (size_t)(ty + 2 * S) * (tz + 2 * S) + 2 * (size_t)(ty + 2 * S - 2) * (tz + 2 * S - 2))) {}
+};
+
+template <typename T, int UP, int FIN>
+struct Fused {
+  struct Args {
+    int n, ty, tz, steps;
+    const T *r0, *r1;
+    const T* src1;          // up leg: black values of the down leg
+    const T *ec0, *ec1;     // up leg: coarse correction (colour-split, edge n/2)
+    T *out0, *out1;
+    const Ctl* ctl;
+  };
+  // one workgroup per compute unit on a 64^3 level: every phase of the
+  // halo box is one pass of the workgroup, so the global loads of the first
+  // operation are issued at once
+  static constexpr int kThreads = 1024;
+  __device__ static void run(const Args& A, Grid G);
+};
+template <typename T, int UP, int FIN>
+__device__ void Fused<T, UP, FIN>::run(const Args& A, Grid G) {
+  constexpr int W = Vec<T>::W;
+  using V = typename Vec<T>::type;
+  const int done = A.ctl->done;
+  const int n = A.n, hn = n >> 1, msk = n - 1, S = A.steps, TY = A.ty, TZ = A.tz;
+  const int BY = TY + 2 * S, BZ = TZ + 2 * S, RY = BY - 2, RZ = BZ - 2;
+  const int nty = n / TY;
+  const int y0 = (G.b % nty) * TY, z0 = (G.b / nty) * TZ;
+  const int vl2 = __builtin_ctz(hn / W), vmsk = hn / W - 1;   // vectors per colour row
+  extern __shared__ __align__(16) unsigned char fused_lds[];
+  T* const E0 = reinterpret_cast<T*>(fused_lds);
+  T* const E1 = E0 + (size_t)BY * BZ * hn;
+  T* const R0 = E1 + (size_t)BY * BZ * hn;
+  T* const R1 = R0 + (size_t)RY * RZ * hn;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const CsGeo g(n), gc(n >> 1);
+  const T sixth = T(1.0 / 6.0);
+  // pointwise first operation on the whole box; r of both colours into the
+  // inner box
+  const int cinit = UP ? 1 : 0;
+  T* const Ei = UP ? E1 : E0;
+  for (int task = tid; task < BY * BZ * (hn / W); task += nt) {
+    const int row = task >> vl2, m = (task & vmsk) * W;
+    const int ey = row % BY, ez = row / BY;   // box coordinates
+    const int j = (y0 + ey - S) & msk, k = (z0 + ez - S) & msk;
+    const int t = ((k << g.l2) + j) * hn + m;
+    V v;
+    if (UP) {
+      v = prolong_black_vec(A.src1, A.ec0, A.ec1, g, gc, t);
+    } else {
+      const V rr = *reinterpret_cast<const V*>(A.r0 + t);
+#pragma unroll
+      for (int q = 0; q < W; q++) vset<T>(v, q, neg_sixth(vget<T>(rr, q)));
+    }
+    *reinterpret_cast<V*>(Ei + row * hn + m) = v;
+    if (ey >= 1 && ey <= RY && ez >= 1 && ez <= RZ) {
+      const int rrow = (ez - 1) * RY + (ey - 1);
+      *reinterpret_cast<V*>(R0 + rrow * hn + m) = *reinterpret_cast<const V*>(A.r0 + t);
+      *reinterpret_cast<V*>(R1 + rrow * hn + m) = *reinterpret_cast<const V*>(A.r1 + t);
+    }
+  }
+  if (done) return;   // uniform: nothing has been written to global memory
+  __syncthreads();
+  for (int st = 0; st < S; st++) {
+    const int c = (cinit + 1 + st) & 1, h = S - 1 - st;   // colour and halo of this half-sweep
+    const int HY = TY + 2 * h, HZ = TZ + 2 * h;
+    T* const Ec = c ? E1 : E0;
+    const T* const Eo = c ? E0 : E1;
+    const T* const Rc = c ? R1 : R0;
+    const bool last = st == S - 1;
+    for (int task = tid; task < HY * HZ * (hn / W); task += nt) {
+      const int hrow = task >> vl2, m = (task & vmsk) * W;
+      const int dy = hrow % HY + (S - h), dz = hrow / HY + (S - h);   // box coordinates
+      const int j = (y0 + dy - S) & msk, k = (z0 + dz - S) & msk;
+      const int row = dz * BY + dy;
+      const int sp = (c + j + k) & 1;   // x-parity of this colour in the row
+      const T* o = Eo + row * hn;
+      const V own = *reinterpret_cast<const V*>(o + m);
+      const T edge = sp ? o[m + W == hn ? 0 : m + W] : o[m == 0 ? hn - 1 : m - 1];
+      const V vym = *reinterpret_cast<const V*>(o - hn + m), vyp = *reinterpret_cast<const V*>(o + hn + m);
+      const V vzm = *reinterpret_cast<const V*>(o - BY * hn + m), vzp = *reinterpret_cast<const V*>(o + BY * hn + m);
+      const V rv = *reinterpret_cast<const V*>(Rc + ((dz - 1) * RY + (dy - 1)) * hn + m);
+      V out;
+#pragma unroll
+      for (int q = 0; q < W; q++) {
+        const T xm = sp ? vget<T>(own, q) : (q == 0 ? edge : vget<T>(own, q - 1));
+        const T xp = sp ? (q == W - 1 ? edge : vget<T>(own, q + 1)) : vget<T>(own, q);
+        const T nb = ((xm + xp) + (vget<T>(vym, q) + vget<T>(vyp, q))) + (vget<T>(vzm, q) + vget<T>(vzp, q));
+        vset<T>(out, q, (nb - vget<T>(rv, q)) * sixth);
+      }
+      if (last) {
+        // the tile: this colour from the last half-sweep, the other colour
+        // from the one before (or the first operation)
+        const int t = ((k << g.l2) + j) * hn + m;
+        *reinterpret_cast<V*>((c ? A.out1 : A.out0) + t) = out;
+        *reinterpret_cast<V*>((c ? A.out0 : A.out1) + t) = own;
+      } else {
+        *reinterpret_cast<V*>(Ec + row * hn + m) = out;
+      }
+    }
+    if (!last) __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Tail of the V-cycle: all levels from n0 down to 4^3 and back in one
 // workgroup, with the exact coarsest solve e = G * r (G the periodic 4^3
 // Green's function of M, FP64 accumulation).  Levels up to 16^3 are
@@ -1065,37 +1205,185 @@ struct Tail {
   static constexpr int kThreads = 1024;
   __device__ static void run(const Args& A, Grid G);
 };
+// One level of the descending leg on level arrays of edge n (the pointers
+// may be global or LDS; the functions are inlined per call site so each
+// access keeps its own address space): nu1 sweeps, the first from e = 0,
+// then the restricted residual into the next level's right-hand side rc.
+// GL: a level in global memory forms the red residuals inside the
+// restriction (RestrictRed); an LDS level writes them to rho first
+// (ResidRestrict).
+template <typename T, bool GL>
+__device__ __forceinline__ void tail_down(T* e0, T* e1, const T* r0, const T* r1, T* rc0, T* rc1, T* rho, int n,
+                                          int nu1) {
+  constexpr int W = Vec<T>::W;
+  using V = typename Vec<T>::type;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int half = n * n * n / 2;
+  const CsGeo g(n);
+  const int nc = n >> 1;
+  const CsGeo gc(nc);
+  const T wt[3] = {T(0.25), T(0.5), T(0.25)};
+  if (nu1 >= 1) {
+    // first sweep from e = 0 (SweepZero): red = -r/6, black from those reds
+    const T sixth = T(1.0 / 6.0);
+    for (int t = tid * W; t < half; t += nt * W) {
+      int m, j, k;
+      cs_decode(g, t, &m, &j, &k);
+      const V rr = *reinterpret_cast<const V*>(r0 + t);
+      V er;
+#pragma unroll
+      for (int c = 0; c < W; c++) vset<T>(er, c, neg_sixth(vget<T>(rr, c)));
+      *reinterpret_cast<V*>(e0 + t) = er;
+      T nb[W];
+      cs_nbr6_vec(r0, g, t, m, j, k, (1 + j + k) & 1, [](T x) { return neg_sixth(x); }, nb);
+      const V rb = *reinterpret_cast<const V*>(r1 + t);
+      V eb;
+#pragma unroll
+      for (int c = 0; c < W; c++) vset<T>(eb, c, (nb[c] - vget<T>(rb, c)) * sixth);
+      *reinterpret_cast<V*>(e1 + t) = eb;
+    }
+    __syncthreads();
+    for (int it = 1; it < nu1; it++) {
+      tail_half(e0, e1, r0, g, half, 0);
+      __syncthreads();
+      tail_half(e1, e0, r1, g, half, 1);
+      __syncthreads();
+    }
+    if (GL) {
+      for (int p = tid * W; p < nc * nc * nc; p += nt * W) {
+        const int I0 = p & (nc - 1), J = (p >> gc.l2) & (nc - 1), K = p >> (2 * gc.l2);
+        T v[W];
+        restrict_red_recompute<T, 1>(e0, e1, r0, g, I0, J, K, v);
+#pragma unroll
+        for (int c = 0; c < W; c++) {
+          const int I = I0 + c;
+          (((I + J + K) & 1) ? rc1 : rc0)[cs_index(gc, I, J, K)] = v[c];
+        }
+      }
+      __syncthreads();
+      return;
+    }
+    // residual at the red points; after the black half-sweep the black
+    // residuals vanish up to rounding and are taken as zero
+    for (int t = tid * W; t < half; t += nt * W) {
+      int m, j, k;
+      cs_decode(g, t, &m, &j, &k);
+      T nb[W];
+      cs_nbr6_vec(e1, g, t, m, j, k, (j + k) & 1, [](T x) { return x; }, nb);
+      const V ev = *reinterpret_cast<const V*>(e0 + t);
+      const V rv = *reinterpret_cast<const V*>(r0 + t);
+      V out;
+#pragma unroll
+      for (int c = 0; c < W; c++) vset<T>(out, c, vget<T>(rv, c) - (nb[c] - T(6) * vget<T>(ev, c)));
+      *reinterpret_cast<V*>(rho + t) = out;
+    }
+    __syncthreads();
+    // full weighting x 4 into the next level's right-hand side
+    for (int p = tid * W; p < nc * nc * nc; p += nt * W) {
+      const int I0 = p & (nc - 1), J = (p >> gc.l2) & (nc - 1), K = p >> (2 * gc.l2);
+      T v[W];
+      restrict_red_vec(rho, g, I0, J, K, v);
+#pragma unroll
+      for (int c = 0; c < W; c++) {
+        const int I = I0 + c;
+        (((I + J + K) & 1) ? rc1 : rc0)[cs_index(gc, I, J, K)] = v[c];
+      }
+    }
+    __syncthreads();
+    return;
+  }
+  // no pre-smoothing: e = 0 and the residual is r itself at every point
+  for (int t = tid; t < half; t += nt) {
+    e0[t] = T(0);
+    e1[t] = T(0);
+  }
+  __syncthreads();
+  const int msk = n - 1;
+  for (int p = tid; p < nc * nc * nc; p += nt) {
+    const int I = p & (nc - 1), J = (p >> gc.l2) & (nc - 1), K = p >> (2 * gc.l2);
+    T s = T(0);
+    for (int c = -1; c <= 1; c++) {
+      const int z = (2 * K + c) & msk;
+      for (int b = -1; b <= 1; b++) {
+        const int y = (2 * J + b) & msk;
+        T row = T(0);
+        for (int a = -1; a <= 1; a++) {
+          const int x = (2 * I + a) & msk;
+          const int odd = (x + y + z) & 1;
+          const int ti = cs_index(g, x, y, z);
+          row += wt[a + 1] * (odd ? r1[ti] : r0[ti]);
+        }
+        s += wt[b + 1] * wt[c + 1] * row;
+      }
+    }
+    T* out = ((I + J + K) & 1) ? rc1 : rc0;
+    out[cs_index(gc, I, J, K)] = T(4) * s;
+  }
+  __syncthreads();
+}
+
+// One level of the ascending leg: trilinear correction from the coarse
+// level (c0, c1), then nu2 sweeps.
 template <typename T>
-__device__ void Tail<T>::run(const Args& A, Grid) {
+__device__ __forceinline__ void tail_up(T* e0, T* e1, const T* r0, const T* r1, const T* c0, const T* c1, int n,
+                                        int nu2) {
+  constexpr int W = Vec<T>::W;
+  using V = typename Vec<T>::type;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int half = n * n * n / 2;
+  const CsGeo g(n), gc(n >> 1);
+  if (nu2 >= 1) {
+    // the next red half-sweep overwrites every red point: only black points
+    // take the correction (ProlongBlack)
+    for (int t = tid * W; t < half; t += nt * W)
+      *reinterpret_cast<V*>(e1 + t) = prolong_black_vec(e1, c0, c1, g, gc, t);
+    __syncthreads();
+    for (int it = 0; it < nu2; it++) {
+      tail_half(e0, e1, r0, g, half, 0);
+      __syncthreads();
+      tail_half(e1, e0, r1, g, half, 1);
+      __syncthreads();
+    }
+  } else {
+    for (int t = tid; t < half; t += nt) {
+      int m, j, k;
+      cs_decode(g, t, &m, &j, &k);
+      e0[t] += prolong_at(c0, c1, gc, 2 * m + ((j + k) & 1), j, k);
+      e1[t] += prolong_at(c0, c1, gc, 2 * m + ((1 + j + k) & 1), j, k);
+    }
+    __syncthreads();
+  }
+}
+
+// GTOP: the top level (edge n0 > kTailLdsMax) stays in global memory and
+// the LDS holds the levels below it.
+template <typename T, bool GTOP>
+__device__ __forceinline__ void tail_run(const typename Tail<T>::Args& A, int done) {
   const int n0 = A.n0, levels = A.levels, nu1 = A.nu1, nu2 = A.nu2;
-  const Ctl* ctl = A.ctl;
-  // the stop flag is tested after the first loads are in flight (as in the
-  // speculative upper-level launches); every wave reads the same flag
-  const int done = ctl ? ctl->done : 0;
   constexpr int W = Vec<T>::W;
   using V = typename Vec<T>::type;
   extern __shared__ __align__(16) unsigned char tail_lds[];
   __shared__ double G[64];
   T* const base = reinterpret_cast<T*>(tail_lds);
-  // level q has edge n0 >> q; with a global top level, LDS starts at q = 1
-  const int q0 = n0 > kTailLdsMax ? 1 : 0, nl = n0 >> q0;
-  T* const rho = base + tail_level_offset(nl, levels - q0);   // red residuals of an LDS level
-  auto E0 = [&](int q) -> T* { return q < q0 ? A.e0 : base + tail_level_offset(nl, q - q0); };
+  // LDS level q has edge nl >> q
+  const int nl = GTOP ? n0 >> 1 : n0, ll = GTOP ? levels - 1 : levels;
+  T* const rho = base + tail_level_offset(nl, ll);   // red residuals of an LDS level
+  auto E0 = [&](int q) -> T* { return base + tail_level_offset(nl, q); };
   auto E1 = [&](int q) -> T* {
-    const int n = n0 >> q;
-    return q < q0 ? A.e1 : E0(q) + n * n * n / 2;
+    const int n = nl >> q;
+    return E0(q) + n * n * n / 2;
   };
   auto R0 = [&](int q) -> T* {
-    const int n = n0 >> q;
-    return q < q0 ? const_cast<T*>(A.r0) : E0(q) + n * n * n;
+    const int n = nl >> q;
+    return E0(q) + n * n * n;
   };
   auto R1 = [&](int q) -> T* {
-    const int n = n0 >> q;
-    return q < q0 ? const_cast<T*>(A.r1) : E0(q) + 3 * (n * n * n / 2);
+    const int n = nl >> q;
+    return E0(q) + 3 * (n * n * n / 2);
   };
   const int tid = threadIdx.x, nt = blockDim.x;
   if (tid < 64) G[tid] = A.green[tid];
-  if (q0 == 0) {
+  if (!GTOP) {
     // the top level is in LDS: its right-hand side comes from global memory
     const int half = n0 * n0 * n0 / 2;
     T* r0 = R0(0);
@@ -1107,126 +1395,13 @@ __device__ void Tail<T>::run(const Args& A, Grid) {
   }
   if (done) return;
   __syncthreads();
-  const T wt[3] = {T(0.25), T(0.5), T(0.25)};
-  for (int q = 0; q + 1 < levels; q++) {
-    const int n = n0 >> q, half = n * n * n / 2;
-    T* e0 = E0(q);
-    T* e1 = E1(q);
-    const T* r0 = R0(q);
-    const T* r1 = R1(q);
-    const CsGeo g(n);
-    const int nc = n >> 1;
-    const CsGeo gc(nc);
-    T* rc0 = R0(q + 1);
-    T* rc1 = R1(q + 1);
-    if (nu1 >= 1) {
-      // first sweep from e = 0 (SweepZero): red = -r/6, black from those reds
-      const T sixth = T(1.0 / 6.0);
-      for (int t = tid * W; t < half; t += nt * W) {
-        int m, j, k;
-        cs_decode(g, t, &m, &j, &k);
-        const V rr = *reinterpret_cast<const V*>(r0 + t);
-        V er;
-#pragma unroll
-        for (int c = 0; c < W; c++) vset<T>(er, c, -vget<T>(rr, c) * sixth);
-        *reinterpret_cast<V*>(e0 + t) = er;
-        T nb[W];
-        cs_nbr6_vec(r0, g, t, m, j, k, (1 + j + k) & 1, [sixth](T x) { return -x * sixth; }, nb);
-        const V rb = *reinterpret_cast<const V*>(r1 + t);
-        V eb;
-#pragma unroll
-        for (int c = 0; c < W; c++) vset<T>(eb, c, (nb[c] - vget<T>(rb, c)) * sixth);
-        *reinterpret_cast<V*>(e1 + t) = eb;
-      }
-      __syncthreads();
-      for (int it = 1; it < nu1; it++) {
-        tail_half(e0, e1, r0, g, half, 0);
-        __syncthreads();
-        tail_half(e1, e0, r1, g, half, 1);
-        __syncthreads();
-      }
-      if (q < q0) {
-        // global level: the red residuals are formed inside the restriction
-        // (RestrictRed), W coarse points per task
-        for (int p = tid * W; p < nc * nc * nc; p += nt * W) {
-          const int I0 = p & (nc - 1), J = (p >> gc.l2) & (nc - 1), K = p >> (2 * gc.l2);
-          T v[W];
-          restrict_red_recompute<T, 1>(e0, e1, r0, g, I0, J, K, v);
-#pragma unroll
-          for (int c = 0; c < W; c++) {
-            const int I = I0 + c;
-            (((I + J + K) & 1) ? rc1 : rc0)[cs_index(gc, I, J, K)] = v[c];
-          }
-        }
-        __syncthreads();
-        continue;
-      }
-      // residual at the red points; after the black half-sweep the black
-      // residuals vanish up to rounding and are taken as zero (ResidRestrict)
-      for (int t = tid * W; t < half; t += nt * W) {
-        int m, j, k;
-        cs_decode(g, t, &m, &j, &k);
-        T nb[W];
-        cs_nbr6_vec(e1, g, t, m, j, k, (j + k) & 1, [](T x) { return x; }, nb);
-        const V ev = *reinterpret_cast<const V*>(e0 + t);
-        const V rv = *reinterpret_cast<const V*>(r0 + t);
-        V out;
-#pragma unroll
-        for (int c = 0; c < W; c++) vset<T>(out, c, vget<T>(rv, c) - (nb[c] - T(6) * vget<T>(ev, c)));
-        *reinterpret_cast<V*>(rho + t) = out;
-      }
-    } else {
-      // no pre-smoothing: e = 0 and the residual is r itself
-      for (int t = tid; t < half; t += nt) {
-        e0[t] = T(0);
-        e1[t] = T(0);
-      }
-    }
-    __syncthreads();
-    {
-      // full weighting x 4 into the next level's right-hand side
-      const int msk = n - 1;
-      if (nu1 >= 1) {
-        for (int p = tid * W; p < nc * nc * nc; p += nt * W) {
-          const int I0 = p & (nc - 1), J = (p >> gc.l2) & (nc - 1), K = p >> (2 * gc.l2);
-          T v[W];
-          restrict_red_vec(rho, g, I0, J, K, v);
-#pragma unroll
-          for (int c = 0; c < W; c++) {
-            const int I = I0 + c;
-            (((I + J + K) & 1) ? rc1 : rc0)[cs_index(gc, I, J, K)] = v[c];
-          }
-        }
-      } else {
-        // no pre-smoothing: the residual is r at every point
-        for (int p = tid; p < nc * nc * nc; p += nt) {
-          const int I = p & (nc - 1), J = (p >> gc.l2) & (nc - 1), K = p >> (2 * gc.l2);
-          T s = T(0);
-          for (int c = -1; c <= 1; c++) {
-            const int z = (2 * K + c) & msk;
-            for (int b = -1; b <= 1; b++) {
-              const int y = (2 * J + b) & msk;
-              T row = T(0);
-              for (int a = -1; a <= 1; a++) {
-                const int x = (2 * I + a) & msk;
-                const int odd = (x + y + z) & 1;
-                const int ti = cs_index(g, x, y, z);
-                row += wt[a + 1] * (odd ? r1[ti] : r0[ti]);
-              }
-              s += wt[b + 1] * wt[c + 1] * row;
-            }
-          }
-          T* out = ((I + J + K) & 1) ? rc1 : rc0;
-          out[cs_index(gc, I, J, K)] = T(4) * s;
-        }
-      }
-    }
-    __syncthreads();
-  }
+  if (GTOP) tail_down<T, true>(A.e0, A.e1, A.r0, A.r1, R0(0), R1(0), rho, n0, nu1);
+  for (int q = 0; q + 1 < ll; q++)
+    tail_down<T, false>(E0(q), E1(q), R0(q), R1(q), R0(q + 1), R1(q + 1), rho, nl >> q, nu1);
   {
     // 4^3: e = G * r with FP64 accumulation; 16 consecutive lanes share one
     // output point, each summing 4 of the 64 terms, then a fixed shuffle tree
-    const int q = levels - 1;
+    const int q = ll - 1;
     T* e0 = E0(q);
     T* e1 = E1(q);
     const T* r0 = R0(q);
@@ -1249,38 +1424,10 @@ __device__ void Tail<T>::run(const Args& A, Grid) {
     }
     __syncthreads();
   }
-  for (int q = levels - 2; q >= 0; q--) {
-    const int n = n0 >> q, half = n * n * n / 2;
-    T* e0 = E0(q);
-    T* e1 = E1(q);
-    const T* r0 = R0(q);
-    const T* r1 = R1(q);
-    const T* c0 = E0(q + 1);
-    const T* c1 = E1(q + 1);
-    const CsGeo g(n), gc(n >> 1);
-    if (nu2 >= 1) {
-      // the next red half-sweep overwrites every red point: only black points
-      // take the correction (ProlongBlack)
-      for (int t = tid * W; t < half; t += nt * W)
-        *reinterpret_cast<V*>(e1 + t) = prolong_black_vec(e1, c0, c1, g, gc, t);
-      __syncthreads();
-      for (int it = 0; it < nu2; it++) {
-        tail_half(e0, e1, r0, g, half, 0);
-        __syncthreads();
-        tail_half(e1, e0, r1, g, half, 1);
-        __syncthreads();
-      }
-    } else {
-      for (int t = tid; t < half; t += nt) {
-        int m, j, k;
-        cs_decode(g, t, &m, &j, &k);
-        e0[t] += prolong_at(c0, c1, gc, 2 * m + ((j + k) & 1), j, k);
-        e1[t] += prolong_at(c0, c1, gc, 2 * m + ((1 + j + k) & 1), j, k);
-      }
-      __syncthreads();
-    }
-  }
-  if (q0 == 0) {
+  for (int q = ll - 2; q >= 0; q--) tail_up(E0(q), E1(q), R0(q), R1(q), E0(q + 1), E1(q + 1), nl >> q, nu2);
+  if (GTOP) {
+    tail_up(A.e0, A.e1, A.r0, A.r1, E0(0), E1(0), n0, nu2);
+  } else {
     // LDS top level: the correction goes back to global memory
     const int half = n0 * n0 * n0 / 2;
     const T* e0 = E0(0);
@@ -1290,6 +1437,17 @@ __device__ void Tail<T>::run(const Args& A, Grid) {
       *reinterpret_cast<V*>(A.e1 + t) = *reinterpret_cast<const V*>(e1 + t);
     }
   }
+}
+
+template <typename T>
+__device__ void Tail<T>::run(const Args& A, Grid) {
+  // the stop flag is tested after the first loads are in flight (as in the
+  // speculative upper-level launches); every wave reads the same flag
+  const int done = A.ctl ? A.ctl->done : 0;
+  if (A.n0 > kTailLdsMax)
+    tail_run<T, true>(A, done);
+  else
+    tail_run<T, false>(A, done);
 }
 
 size_t tail_lds_bytes(int n0, int levels, size_t elem) {
@@ -1471,6 +1629,47 @@ hipError_t launch_tail(const LevelBufs* lv, int levels, int tail, int nu1, int n
                      1, tail_lds_bytes(lv[tail].n, lt, sizeof(T)), s);
 }
 
+// Fused legs: LDS of one workgroup within the compute unit's 160 KiB.
+constexpr size_t kFusedLdsCap = 160 * 1024;
+constexpr int kFusedStepsMax = 8;
+
+template <typename T>
+bool fused_fits(int n, int ty, int tz, int S) {
+  return ty > 0 && tz > 0 && n % ty == 0 && n % tz == 0 && (n / 2) % Vec<T>::W == 0 && S >= 1 &&
+         S <= kFusedStepsMax && FusedBox(n, ty, tz, S).elems * sizeof(T) <= kFusedLdsCap;
+}
+
+// Both legs of level L fused (the down leg writes the buffers the up leg
+// reads, so the two go together).
+template <typename T>
+bool fused_level(const LevelBufs& L, int nu1, int nu2) {
+  return L.fty > 0 && L.d0 && L.d1 && nu1 >= 1 && nu2 >= 1 && fused_fits<T>(L.n, L.fty, L.ftz, 2 * nu1 - 1) &&
+         fused_fits<T>(L.n, L.fty, L.ftz, 2 * nu2);
+}
+
+template <typename T, int UP, int FIN>
+hipError_t launch_fused_t(int n, int ty, int tz, int S, const T* r0, const T* r1, const T* src1, const T* ec0,
+                          const T* ec1, T* out0, T* out1, Ctl* ctl, hipStream_t s) {
+  if (!fused_fits<T>(n, ty, tz, S)) return hipErrorInvalidValue;
+  const int grid = (n / ty) * (n / tz);
+  const size_t lds = FusedBox(n, ty, tz, S).elems * sizeof(T);
+  return go<Fused<T, UP, FIN>>({n, ty, tz, S, r0, r1, src1, ec0, ec1, out0, out1, ctl}, grid, lds, s);
+}
+
+// Down leg of level L: first sweep from zero and nu1 - 1 pairs into d0/d1.
+template <typename T, int FIN>
+hipError_t launch_fused_down(const LevelBufs& L, int nu1, Ctl* ctl, hipStream_t s) {
+  return launch_fused_t<T, 0, FIN>(L.n, L.fty, L.ftz, 2 * nu1 - 1, (const T*)L.r0, (const T*)L.r1, nullptr, nullptr,
+                                   nullptr, (T*)L.d0, (T*)L.d1, ctl, s);
+}
+// Up leg of level L: black-point correction from the coarse level C, then
+// nu2 pairs, from d1 into e0/e1.
+template <typename T, int FIN>
+hipError_t launch_fused_up(const LevelBufs& L, const LevelBufs& C, int nu2, Ctl* ctl, hipStream_t s) {
+  return launch_fused_t<T, 1, FIN>(L.n, L.fty, L.ftz, 2 * nu2, (const T*)L.r0, (const T*)L.r1, (const T*)L.d1,
+                                   (const T*)C.e0, (const T*)C.e1, (T*)L.e0, (T*)L.e1, ctl, s);
+}
+
 #define P3MZ_LAUNCH(...)             \
   do {                               \
     hipError_t e_ = (__VA_ARGS__);   \
@@ -1481,8 +1680,8 @@ hipError_t launch_tail(const LevelBufs* lv, int levels, int tail, int nu1, int n
 // level l from the finest going down, the tail, then the levels going up in
 // reverse, so systems with fewer levels keep their own order in a batch.
 // Sub-keys: 0..33 sweeps and prolongation (up: 0 black-point prolongation,
-// then 2 + 2 it + colour), 62 zero fill, 63 restriction / plain
-// prolongation.
+// then 2 + 2 it + colour), 60 fused leg, 62 zero fill, 63 restriction /
+// plain prolongation.
 inline uint32_t key_down(int l, int sub) { return 1000u + 64u * (uint32_t)l + (uint32_t)sub; }
 inline uint32_t key_up(int l, int sub) { return 3000u + 64u * (uint32_t)(P3MZ_MAX_LEVELS - 1 - l) + (uint32_t)sub; }
 constexpr uint32_t kKeyTail = 2100u;
@@ -1495,7 +1694,15 @@ hipError_t vcycle_impl(const LevelBufs* lv, int levels, int tail, int nu1, int n
     const int n = lv[l].n, half = n * n * n / 2;
     const double n3 = (double)n * n * n;
     T *e0 = (T*)lv[l].e0, *e1 = (T*)lv[l].e1, *r0 = (T*)lv[l].r0, *r1 = (T*)lv[l].r1;
-    if (nu1 >= 1) {
+    if (fused_level<T>(lv[l], nu1, nu2)) {
+      rec_key(key_down(l, 60));
+      kt_begin(KT_FUSED_DOWN, l, s);
+      P3MZ_LAUNCH(l == 0 ? launch_fused_down<T, 1>(lv[l], nu1, ctl, s) : launch_fused_down<T, 0>(lv[l], nu1, ctl, s));
+      kt_end(KT_FUSED_DOWN, l, 2.0 * ts * n3, s);
+      // the restriction reads the down leg's result
+      e0 = (T*)lv[l].d0;
+      e1 = (T*)lv[l].d1;
+    } else if (nu1 >= 1) {
       rec_key(key_down(l, 0));
       kt_begin(KT_SWEEP0, l, s);
       P3MZ_LAUNCH(l == 0 ? launch_sweep0<T, 1>(n, r0, r1, e0, e1, ctl, s) : launch_sweep0<T, 0>(n, r0, r1, e0, e1, ctl, s));
@@ -1535,7 +1742,13 @@ hipError_t vcycle_impl(const LevelBufs* lv, int levels, int tail, int nu1, int n
     const double n3 = (double)n * n * n;
     T *e0 = (T*)lv[l].e0, *e1 = (T*)lv[l].e1, *r0 = (T*)lv[l].r0, *r1 = (T*)lv[l].r1;
     const T *c0 = (const T*)lv[l + 1].e0, *c1 = (const T*)lv[l + 1].e1;
-    if (nu2 >= 1) {
+    if (fused_level<T>(lv[l], nu1, nu2)) {
+      rec_key(key_up(l, 60));
+      kt_begin(KT_FUSED_UP, l, s);
+      P3MZ_LAUNCH(l == 0 ? launch_fused_up<T, 1>(lv[l], lv[l + 1], nu2, ctl, s)
+                         : launch_fused_up<T, 0>(lv[l], lv[l + 1], nu2, ctl, s));
+      kt_end(KT_FUSED_UP, l, 2.625 * ts * n3, s);
+    } else if (nu2 >= 1) {
       rec_key(key_up(l, 0));
       kt_begin(KT_PROLONG, l, s);
       P3MZ_LAUNCH(l == 0 ? launch_prolong_black<T, 1>(n, e1, c0, c1, ctl, s)
@@ -1587,6 +1800,14 @@ hipError_t one_kernel(int kid, const LevelBufs* lv, int levels, int tail, int nu
       if (tail == 0) return hipErrorInvalidValue;
       *bytes = 1.125 * ts * n3;
       return launch_prolong_black<T, 1>(n, e1, (const T*)lv[1].e0, (const T*)lv[1].e1, ctl, s);
+    case KT_FUSED_DOWN:
+      if (tail == 0 || !fused_level<T>(lv[0], nu1, nu2)) return hipErrorInvalidValue;
+      *bytes = 2.0 * ts * n3;
+      return launch_fused_down<T, 1>(lv[0], nu1, ctl, s);
+    case KT_FUSED_UP:
+      if (tail == 0 || !fused_level<T>(lv[0], nu1, nu2)) return hipErrorInvalidValue;
+      *bytes = 2.625 * ts * n3;
+      return launch_fused_up<T, 1>(lv[0], lv[1], nu2, ctl, s);
     case KT_TAIL:
       *bytes = 2.0 * ts * (double)lv[tail].n * lv[tail].n * lv[tail].n;
       return launch_tail<T>(lv, levels, tail, nu1, nu2, green, ctl, s);
@@ -1722,6 +1943,27 @@ hipError_t tail_configure(bool fp64, int n_tail, int levels_tail, size_t* lds_by
   if ((int)b <= granted[fp64]) return hipSuccess;
   P3MZ_LAUNCH(fp64 ? allow_lds<Tail<double>>((int)b) : allow_lds<Tail<float>>((int)b));
   granted[fp64] = (int)b;
+  return hipSuccess;
+}
+
+int fused_tile(int n) { return n >= 64 ? 4 : 2; }
+
+namespace {
+template <typename T, int UP>
+hipError_t fused_allow() {
+  P3MZ_LAUNCH(allow_lds<Fused<T, UP, 0>>((int)kFusedLdsCap));
+  return allow_lds<Fused<T, UP, 1>>((int)kFusedLdsCap);
+}
+}  // namespace
+
+hipError_t fused_configure() {
+  static bool done = false;
+  if (done) return hipSuccess;
+  P3MZ_LAUNCH(fused_allow<float, 0>());
+  P3MZ_LAUNCH(fused_allow<float, 1>());
+  P3MZ_LAUNCH(fused_allow<double, 0>());
+  P3MZ_LAUNCH(fused_allow<double, 1>());
+  done = true;
   return hipSuccess;
 }
 

@@ -32,12 +32,13 @@ MESH_Q, MESH_QS, MESH_SIGMA_P, MESH_Y, MESH_PHI, MESH_PHI_PREV = range(6)
 EXPORTS = ["p3mz_create", "p3mz_compute", "p3mz_get_mesh", "p3mz_vcycle", "p3mz_get_stats",
            "p3mz_reset_history", "p3mz_save_state", "p3mz_load_state", "p3mz_md_run",
            "p3mz_set_graphs", "p3mz_set_timing", "p3mz_set_kernel_timer", "p3mz_get_kernel_timer",
-           "p3mz_kernel_bench", "p3mz_set_schedule", "p3mz_autotune",
+           "p3mz_kernel_bench", "p3mz_set_schedule", "p3mz_set_fused_levels", "p3mz_autotune",
            "p3mz_destroy", "p3mz_batch_create", "p3mz_batch_compute", "p3mz_batch_md_run",
            "p3mz_batch_get_stats", "p3mz_batch_set_timing", "p3mz_batch_get_timing", "p3mz_batch_set_graphs",
            "p3mz_batch_kernel_bench", "p3mz_batch_destroy", "p3mz_status_string", "p3mz_last_error", "p3mz_version"]
 KERNELS = {"halfsweep": 0, "outer": 1, "smooth": 2, "restrict": 3, "prolong": 4, "sweep0": 5,
-           "tail": 6, "spread": 7, "gather": 8, "sr": 9, "sigma": 10, "phi": 11}
+           "tail": 6, "spread": 7, "gather": 8, "sr": 9, "sigma": 10, "phi": 11, "fused_down": 12,
+           "fused_up": 13}
 
 
 class p3mz_params(C.Structure):
@@ -105,6 +106,7 @@ def _load() -> C.CDLL:
         "p3mz_set_kernel_timer": ([vp, C.c_int32], C.c_int),
         "p3mz_get_kernel_timer": ([vp, dp, C.POINTER(C.c_int64), dp], C.c_int),
         "p3mz_set_schedule": ([vp, C.c_int32, C.c_int32, C.c_int32], C.c_int),
+        "p3mz_set_fused_levels": ([vp, C.c_int32], C.c_int),
         "p3mz_autotune": ([vp, vp, C.c_int32, vp, C.POINTER(p3mz_tune_result)], C.c_int),
         "p3mz_destroy": ([vp], None),
         "p3mz_batch_create": ([C.c_int32, C.POINTER(p3mz_params), C.POINTER(C.c_int64), dp, C.POINTER(vp)], C.c_int),
@@ -217,6 +219,10 @@ def p3mz_get_kernel_timer(ctx: int) -> tuple[float, int, float]:
 
 def p3mz_set_schedule(ctx: int, nu_pre: int, nu_post: int, smooth_tile: int = 0) -> int:
     return _check(lib.p3mz_set_schedule(ctx, nu_pre, nu_post, smooth_tile), "p3mz_set_schedule")
+
+
+def p3mz_set_fused_levels(ctx: int, max_edge: int) -> int:
+    return _check(lib.p3mz_set_fused_levels(ctx, max_edge), "p3mz_set_fused_levels")
 
 
 def p3mz_autotune(ctx: int, frames_dev: int, n_frames: int, stream: int | None = None) -> p3mz_tune_result:

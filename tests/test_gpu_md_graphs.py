@@ -99,18 +99,22 @@ def test_kernel_timers(torch):
     try:
         traj = trajectory(s, 3)
         P.p3mz_set_timing(g.h, True)
-        P.p3mz_set_kernel_timer(g.h, P.KERNELS["halfsweep"])
+        # the 64^3 level runs its legs fused (one launch per leg)
+        P.p3mz_set_kernel_timer(g.h, P.KERNELS["fused_up"])
         for x in traj:
             g.compute(x)
         ms, n, b = P.p3mz_get_kernel_timer(g.h)
-        assert n > 0 and ms > 0 and math.isclose(b / n, 1.5 * 4 * 64 ** 3)
+        assert n > 0 and ms > 0 and math.isclose(b / n, 2.625 * 4 * 64 ** 3)
+        P.p3mz_set_kernel_timer(g.h, P.KERNELS["halfsweep"])
+        g.compute(traj[-1])
+        assert P.p3mz_get_kernel_timer(g.h)[1] == 0
         st = g.stats()
         # the kernel timer forces direct launches, so the sub-stages are timed too
         assert st.graphs == 0 and st.ms_mesh > 0 and st.ms_short_range > 0
         assert st.ms_spread > 0 and st.ms_solve > 0 and st.ms_gather > 0
         assert abs(st.ms_spread + st.ms_solve + st.ms_gather - st.ms_mesh) < 1e-3 * st.ms_mesh + 1e-3
         P.p3mz_set_kernel_timer(g.h, -1)
-        for name in ("halfsweep", "sweep0", "restrict", "prolong", "tail", "smooth"):
+        for name in ("halfsweep", "sweep0", "restrict", "prolong", "tail", "smooth", "fused_down", "fused_up"):
             ms, b = P.p3mz_kernel_bench(g.h, P.KERNELS[name], 5, g.stream())
             assert ms > 0 and b > 0, name
         with pytest.raises(P.P3MZError):

@@ -246,6 +246,58 @@ def test_bitwise_reproducible(torch, precision):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("nu", [(1, 1), (2, 2), (1, 2), (2, 1), (3, 3)])
+def test_fused_levels_bitwise(torch, precision, nu):
+    """Each V-cycle leg of the 64^3 and 32^3 levels as one temporally blocked
+    launch gives bitwise the result of one launch per sweep ((3, 3) in FP64
+    needs more LDS than a compute unit has and falls back on 64^3)."""
+    from paper_2606_31379_amd import p3maze as P
+    rng = np.random.default_rng(11 + nu[0])
+    r = rng.normal(size=(64,) * 3)
+    r -= r.mean()
+    gp, op = params_pair(20.0, 0.3, 9.0, 64, 4, precision=precision, nu_pre=nu[0], nu_post=nu[1])
+    g = GpuCtx(gp, np.array([1.0, -1.0]), torch)
+    try:
+        fused = g.vcycle(r)
+        P.p3mz_set_fused_levels(g.h, 0)
+        plain = g.vcycle(r)
+        P.p3mz_set_fused_levels(g.h, 32)
+        partial = g.vcycle(r)
+    finally:
+        g.close()
+    assert np.array_equal(fused, plain)
+    assert np.array_equal(partial, plain)
+    eo = O.Oracle(op, np.array([1.0, -1.0])).vcycle(r)
+    assert np.max(np.abs(fused - eo)) <= (1e-12 if precision == 0 else 2e-5) * np.max(np.abs(eo))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_fused_levels_whole_steps_bitwise(torch, precision):
+    """Whole MD-trajectory steps of water-3000 (64^3 mesh): forces, energies
+    and V-cycle counts are bitwise the same with and without fused legs."""
+    from paper_2606_31379_amd import p3maze as P
+    w = configs.water_3000()
+    s = w.system()
+    gp, _ = params_pair(w.box, w.alpha, w.r_cut, w.mesh, w.order, tol=w.tol, precision=precision, k_e=K_E,
+                        excl_group=w.excl_group)
+    runs = []
+    for max_edge in (64, 0):
+        g = GpuCtx(gp, s.charges, torch)
+        try:
+            P.p3mz_set_fused_levels(g.h, max_edge)
+            out = []
+            for p in trajectory(s, 4):
+                f, e, _ = g.compute(p)
+                out.append((f, e, g.stats().cycles))
+            runs.append(out)
+        finally:
+            g.close()
+    for (fa, ea, ca), (fb, eb, cb) in zip(*runs):
+        assert ca == cb
+        assert np.array_equal(fa, fb) and np.array_equal(ea, eb)
+
+
 def test_save_load_continues_bitwise(torch):
     w = configs.nacl_512()
     s = w.system()
