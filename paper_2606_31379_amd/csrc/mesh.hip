@@ -997,14 +997,19 @@ struct FillZero {
 // shrunk by one (halo S-1), rows of n/2 elements per colour.
 // ---------------------------------------------------------------------------
 struct FusedBox {
-  int by, bz, ry, rz;   // rows of the e box (halo S) and of the r box (halo S-1)
+  int by, bz, ry, rz;   // rows of the e box (halo S + hb) and of the r box (one less)
   size_t elems;         // LDS elements of e0, e1, r0, r1
-  FusedBox(int n, int ty, int tz, int S)
-      : by(ty + 2 * S), bz(tz + 2 * S), ry(ty + 2 * S - 2), rz(tz + 2 * S - 2),
-        elems((size_t)(n / 2) * (2 * (size_t)(ty + 2 * S) * (tz + 2 * S) + 2 * (size_t)(ty + 2 * S - 2) * (tz + 2 * S - 2))) {}
+  FusedBox(int n, int ty, int tz, int S, int hb)
+      : by(ty + 2 * (S + hb)), bz(tz + 2 * (S + hb)), ry(by - 2), rz(bz - 2),
+        elems((size_t)(n / 2) * (2 * (size_t)by * bz + 2 * (size_t)ry * rz)) {}
 };
 
-template <typename T, int UP, int FIN>
+// RST (down leg only): the launch also forms the restricted red residual of
+// its tile's coarse points (RestrictRed's arithmetic, in its order) into the
+// coarse right-hand side rc0/rc1.  That needs the final black values two rows
+// and the final red values one row around the tile, so every half-sweep runs
+// on a box two rows wider (hb = 2).
+template <typename T, int UP, int FIN, int RST>
 struct Fused {
   struct Args {
     int n, ty, tz, steps;
@@ -1012,6 +1017,7 @@ struct Fused {
     const T* src1;          // up leg: black values of the down leg
     const T *ec0, *ec1;     // up leg: coarse correction (colour-split, edge n/2)
     T *out0, *out1;
+    T *rc0, *rc1;           // RST: coarse right-hand side (colour-split, edge n/2)
     const Ctl* ctl;
   };
   // one workgroup per compute unit on a 64^3 level: every phase of the
@@ -1020,13 +1026,15 @@ struct Fused {
   static constexpr int kThreads = 1024;
   __device__ static void run(const Args& A, Grid G);
 };
-template <typename T, int UP, int FIN>
-__device__ void Fused<T, UP, FIN>::run(const Args& A, Grid G) {
+template <typename T, int UP, int FIN, int RST>
+__device__ void Fused<T, UP, FIN, RST>::run(const Args& A, Grid G) {
   constexpr int W = Vec<T>::W;
   using V = typename Vec<T>::type;
+  constexpr int HB = RST ? 2 : 0;
   const int done = A.ctl->done;
   const int n = A.n, hn = n >> 1, msk = n - 1, S = A.steps, TY = A.ty, TZ = A.tz;
-  const int BY = TY + 2 * S, BZ = TZ + 2 * S, RY = BY - 2, RZ = BZ - 2;
+  const int SB = S + HB;   // halo of the e box
+  const int BY = TY + 2 * SB, BZ = TZ + 2 * SB, RY = BY - 2, RZ = BZ - 2;
   const int nty = n / TY;
   const int y0 = (G.b % nty) * TY, z0 = (G.b / nty) * TZ;
   const int vl2 = __builtin_ctz(hn / W), vmsk = hn / W - 1;   // vectors per colour row
@@ -1045,7 +1053,7 @@ __device__ void Fused<T, UP, FIN>::run(const Args& A, Grid G) {
   for (int task = tid; task < BY * BZ * (hn / W); task += nt) {
     const int row = task >> vl2, m = (task & vmsk) * W;
     const int ey = row % BY, ez = row / BY;   // box coordinates
-    const int j = (y0 + ey - S) & msk, k = (z0 + ez - S) & msk;
+    const int j = (y0 + ey - SB) & msk, k = (z0 + ez - SB) & msk;
     const int t = ((k << g.l2) + j) * hn + m;
     V v;
     if (UP) {
@@ -1065,16 +1073,16 @@ __device__ void Fused<T, UP, FIN>::run(const Args& A, Grid G) {
   if (done) return;   // uniform: nothing has been written to global memory
   __syncthreads();
   for (int st = 0; st < S; st++) {
-    const int c = (cinit + 1 + st) & 1, h = S - 1 - st;   // colour and halo of this half-sweep
+    const int c = (cinit + 1 + st) & 1, h = S - 1 - st + HB;   // colour and halo of this half-sweep
     const int HY = TY + 2 * h, HZ = TZ + 2 * h;
     T* const Ec = c ? E1 : E0;
     const T* const Eo = c ? E0 : E1;
     const T* const Rc = c ? R1 : R0;
-    const bool last = st == S - 1;
+    const bool out_now = !RST && st == S - 1;   // the last half-sweep writes the tile to global memory
     for (int task = tid; task < HY * HZ * (hn / W); task += nt) {
       const int hrow = task >> vl2, m = (task & vmsk) * W;
-      const int dy = hrow % HY + (S - h), dz = hrow / HY + (S - h);   // box coordinates
-      const int j = (y0 + dy - S) & msk, k = (z0 + dz - S) & msk;
+      const int dy = hrow % HY + (SB - h), dz = hrow / HY + (SB - h);   // box coordinates
+      const int j = (y0 + dy - SB) & msk, k = (z0 + dz - SB) & msk;
       const int row = dz * BY + dy;
       const int sp = (c + j + k) & 1;   // x-parity of this colour in the row
       const T* o = Eo + row * hn;
@@ -1091,7 +1099,7 @@ __device__ void Fused<T, UP, FIN>::run(const Args& A, Grid G) {
         const T nb = ((xm + xp) + (vget<T>(vym, q) + vget<T>(vyp, q))) + (vget<T>(vzm, q) + vget<T>(vzp, q));
         vset<T>(out, q, (nb - vget<T>(rv, q)) * sixth);
       }
-      if (last) {
+      if (out_now) {
         // the tile: this colour from the last half-sweep, the other colour
         // from the one before (or the first operation)
         const int t = ((k << g.l2) + j) * hn + m;
@@ -1101,7 +1109,86 @@ __device__ void Fused<T, UP, FIN>::run(const Args& A, Grid G) {
         *reinterpret_cast<V*>(Ec + row * hn + m) = out;
       }
     }
-    if (!last) __syncthreads();
+    if (!out_now) __syncthreads();
+  }
+  if (!RST) return;
+  // the tile's rows of both colours
+  for (int task = tid; task < TY * TZ * (hn / W); task += nt) {
+    const int trow = task >> vl2, m = (task & vmsk) * W;
+    const int dy = trow % TY + SB, dz = trow / TY + SB;
+    const int j = (y0 + dy - SB) & msk, k = (z0 + dz - SB) & msk;
+    const int row = dz * BY + dy;
+    const int t = ((k << g.l2) + j) * hn + m;
+    *reinterpret_cast<V*>(A.out0 + t) = *reinterpret_cast<const V*>(E0 + row * hn + m);
+    *reinterpret_cast<V*>(A.out1 + t) = *reinterpret_cast<const V*>(E1 + row * hn + m);
+  }
+  // restricted red residual at the tile's coarse points: coarse rows
+  // J = y0/2 .. (y0+TY)/2 - 1 (likewise K), W coarse points per task
+  const int cty = TY >> 1, ctz = TZ >> 1, nc = hn, cvl2 = __builtin_ctz(nc / W);
+  const T wt[3] = {T(0.25), T(0.5), T(0.25)};
+  for (int task = tid; task < cty * ctz * (nc / W); task += nt) {
+    const int crow = task >> cvl2, I0 = (task & (nc / W - 1)) * W;
+    const int J = (y0 >> 1) + crow % cty, K = (z0 >> 1) + crow / cty;
+    T sacc[W];
+#pragma unroll
+    for (int q = 0; q < W; q++) sacc[q] = T(0);
+    // three rows at a time (all nine unrolled spill)
+#pragma unroll 1
+    for (int cz = -1; cz <= 1; cz++) {
+      const int dz = 2 * K + cz - z0 + SB;   // box row of fine z = 2K + cz
+      const int z = (2 * K + cz) & msk;
+#pragma unroll
+      for (int by = -1; by <= 1; by++) {
+        const int dy = 2 * J + by - y0 + SB;
+        const int y = (2 * J + by) & msk;
+        const int par = (y + z) & 1;   // red points of this row sit at x = 2m + par
+        const int row = dz * BY + dy;
+        const T* o = E1 + row * hn;
+        const V own = *reinterpret_cast<const V*>(o + I0);
+        const T edge = par ? o[I0 + W == hn ? 0 : I0 + W] : o[I0 == 0 ? hn - 1 : I0 - 1];
+        const V vym = *reinterpret_cast<const V*>(o - hn + I0), vyp = *reinterpret_cast<const V*>(o + hn + I0);
+        const V vzm = *reinterpret_cast<const V*>(o - BY * hn + I0), vzp = *reinterpret_cast<const V*>(o + BY * hn + I0);
+        const V ev = *reinterpret_cast<const V*>(E0 + row * hn + I0);
+        const T* rr = R0 + ((dz - 1) * RY + (dy - 1)) * hn;
+        const V rv = *reinterpret_cast<const V*>(rr + I0);
+        T rho[W];
+#pragma unroll
+        for (int q = 0; q < W; q++) {
+          const T xm = par ? vget<T>(own, q) : (q == 0 ? edge : vget<T>(own, q - 1));
+          const T xp = par ? (q == W - 1 ? edge : vget<T>(own, q + 1)) : vget<T>(own, q);
+          const T nb = ((xm + xp) + (vget<T>(vym, q) + vget<T>(vyp, q))) + (vget<T>(vzm, q) + vget<T>(vzp, q));
+          rho[q] = vget<T>(rv, q) - (nb - T(6) * vget<T>(ev, q));
+        }
+        const T wbc = wt[by + 1] * wt[cz + 1];
+        if (par == 0) {
+          // only x = 2I is red: m = I
+#pragma unroll
+          for (int q = 0; q < W; q++) {
+            T rowsum = T(0);
+            rowsum += wt[1] * rho[q];
+            sacc[q] += wbc * rowsum;
+          }
+        } else {
+          // x = 2I - 1 (m = I - 1) and x = 2I + 1 (m = I)
+          const int me = (I0 - 1) & (hn - 1);
+          const T xm = o[me], xp = o[me + 1 == hn ? 0 : me + 1];
+          const T nbe = ((xm + xp) + (o[me - hn] + o[me + hn])) + (o[me - BY * hn] + o[me + BY * hn]);
+          const T rho_e = rr[me] - (nbe - T(6) * E0[row * hn + me]);
+#pragma unroll
+          for (int q = 0; q < W; q++) {
+            T rowsum = T(0);
+            rowsum += wt[0] * (q == 0 ? rho_e : rho[q - 1]);
+            rowsum += wt[2] * rho[q];
+            sacc[q] += wbc * rowsum;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < W; q++) {
+      const int I = I0 + q;
+      (((I + J + K) & 1) ? A.rc1 : A.rc0)[cs_index(gc, I, J, K)] = T(4) * sacc[q];
+    }
   }
 }
 
@@ -1634,40 +1721,49 @@ constexpr size_t kFusedLdsCap = 160 * 1024;
 constexpr int kFusedStepsMax = 8;
 
 template <typename T>
-bool fused_fits(int n, int ty, int tz, int S) {
-  return ty > 0 && tz > 0 && n % ty == 0 && n % tz == 0 && (n / 2) % Vec<T>::W == 0 && S >= 1 &&
-         S <= kFusedStepsMax && FusedBox(n, ty, tz, S).elems * sizeof(T) <= kFusedLdsCap;
+bool fused_fits(int n, int ty, int tz, int S, int hb) {
+  return ty > 0 && tz > 0 && n % ty == 0 && n % tz == 0 && (ty & 1) == 0 && (tz & 1) == 0 &&
+         (n / 2) % Vec<T>::W == 0 && S >= 1 && S <= kFusedStepsMax &&
+         FusedBox(n, ty, tz, S, hb).elems * sizeof(T) <= kFusedLdsCap;
 }
 
 // Both legs of level L fused (the down leg writes the buffers the up leg
 // reads, so the two go together).
 template <typename T>
 bool fused_level(const LevelBufs& L, int nu1, int nu2) {
-  return L.fty > 0 && L.d0 && L.d1 && nu1 >= 1 && nu2 >= 1 && fused_fits<T>(L.n, L.fty, L.ftz, 2 * nu1 - 1) &&
-         fused_fits<T>(L.n, L.fty, L.ftz, 2 * nu2);
+  return L.fty > 0 && L.d0 && L.d1 && nu1 >= 1 && nu2 >= 1 && fused_fits<T>(L.n, L.fty, L.ftz, 2 * nu1 - 1, 0) &&
+         fused_fits<T>(L.n, L.fty, L.ftz, 2 * nu2, 0);
+}
+// The fused down leg of L also restricts (its wider box fits in LDS).
+template <typename T>
+bool fused_restricts(const LevelBufs& L, int nu1, int nu2) {
+  return fused_level<T>(L, nu1, nu2) && fused_fits<T>(L.n, L.fty, L.ftz, 2 * nu1 - 1, 2);
 }
 
-template <typename T, int UP, int FIN>
+template <typename T, int UP, int FIN, int RST>
 hipError_t launch_fused_t(int n, int ty, int tz, int S, const T* r0, const T* r1, const T* src1, const T* ec0,
-                          const T* ec1, T* out0, T* out1, Ctl* ctl, hipStream_t s) {
-  if (!fused_fits<T>(n, ty, tz, S)) return hipErrorInvalidValue;
+                          const T* ec1, T* out0, T* out1, T* rc0, T* rc1, Ctl* ctl, hipStream_t s) {
+  const int hb = RST ? 2 : 0;
+  if (!fused_fits<T>(n, ty, tz, S, hb)) return hipErrorInvalidValue;
   const int grid = (n / ty) * (n / tz);
-  const size_t lds = FusedBox(n, ty, tz, S).elems * sizeof(T);
-  return go<Fused<T, UP, FIN>>({n, ty, tz, S, r0, r1, src1, ec0, ec1, out0, out1, ctl}, grid, lds, s);
+  const size_t lds = FusedBox(n, ty, tz, S, hb).elems * sizeof(T);
+  return go<Fused<T, UP, FIN, RST>>({n, ty, tz, S, r0, r1, src1, ec0, ec1, out0, out1, rc0, rc1, ctl}, grid, lds, s);
 }
 
-// Down leg of level L: first sweep from zero and nu1 - 1 pairs into d0/d1.
-template <typename T, int FIN>
-hipError_t launch_fused_down(const LevelBufs& L, int nu1, Ctl* ctl, hipStream_t s) {
-  return launch_fused_t<T, 0, FIN>(L.n, L.fty, L.ftz, 2 * nu1 - 1, (const T*)L.r0, (const T*)L.r1, nullptr, nullptr,
-                                   nullptr, (T*)L.d0, (T*)L.d1, ctl, s);
+// Down leg of level L: first sweep from zero and nu1 - 1 pairs into d0/d1;
+// with RST also the restricted residual into the coarse level C's rhs.
+template <typename T, int FIN, int RST>
+hipError_t launch_fused_down(const LevelBufs& L, const LevelBufs& C, int nu1, Ctl* ctl, hipStream_t s) {
+  return launch_fused_t<T, 0, FIN, RST>(L.n, L.fty, L.ftz, 2 * nu1 - 1, (const T*)L.r0, (const T*)L.r1, nullptr,
+                                        nullptr, nullptr, (T*)L.d0, (T*)L.d1, RST ? (T*)C.r0 : nullptr,
+                                        RST ? (T*)C.r1 : nullptr, ctl, s);
 }
 // Up leg of level L: black-point correction from the coarse level C, then
 // nu2 pairs, from d1 into e0/e1.
 template <typename T, int FIN>
 hipError_t launch_fused_up(const LevelBufs& L, const LevelBufs& C, int nu2, Ctl* ctl, hipStream_t s) {
-  return launch_fused_t<T, 1, FIN>(L.n, L.fty, L.ftz, 2 * nu2, (const T*)L.r0, (const T*)L.r1, (const T*)L.d1,
-                                   (const T*)C.e0, (const T*)C.e1, (T*)L.e0, (T*)L.e1, ctl, s);
+  return launch_fused_t<T, 1, FIN, 0>(L.n, L.fty, L.ftz, 2 * nu2, (const T*)L.r0, (const T*)L.r1, (const T*)L.d1,
+                                      (const T*)C.e0, (const T*)C.e1, (T*)L.e0, (T*)L.e1, nullptr, nullptr, ctl, s);
 }
 
 #define P3MZ_LAUNCH(...)             \
@@ -1694,10 +1790,19 @@ hipError_t vcycle_impl(const LevelBufs* lv, int levels, int tail, int nu1, int n
     const int n = lv[l].n, half = n * n * n / 2;
     const double n3 = (double)n * n * n;
     T *e0 = (T*)lv[l].e0, *e1 = (T*)lv[l].e1, *r0 = (T*)lv[l].r0, *r1 = (T*)lv[l].r1;
+    if (fused_restricts<T>(lv[l], nu1, nu2)) {
+      rec_key(key_down(l, 61));
+      kt_begin(KT_FUSED_DOWN, l, s);
+      P3MZ_LAUNCH(l == 0 ? launch_fused_down<T, 1, 1>(lv[l], lv[l + 1], nu1, ctl, s)
+                         : launch_fused_down<T, 0, 1>(lv[l], lv[l + 1], nu1, ctl, s));
+      kt_end(KT_FUSED_DOWN, l, 2.125 * ts * n3, s);
+      continue;   // restricted in the same launch
+    }
     if (fused_level<T>(lv[l], nu1, nu2)) {
       rec_key(key_down(l, 60));
       kt_begin(KT_FUSED_DOWN, l, s);
-      P3MZ_LAUNCH(l == 0 ? launch_fused_down<T, 1>(lv[l], nu1, ctl, s) : launch_fused_down<T, 0>(lv[l], nu1, ctl, s));
+      P3MZ_LAUNCH(l == 0 ? launch_fused_down<T, 1, 0>(lv[l], lv[l + 1], nu1, ctl, s)
+                         : launch_fused_down<T, 0, 0>(lv[l], lv[l + 1], nu1, ctl, s));
       kt_end(KT_FUSED_DOWN, l, 2.0 * ts * n3, s);
       // the restriction reads the down leg's result
       e0 = (T*)lv[l].d0;
@@ -1802,8 +1907,12 @@ hipError_t one_kernel(int kid, const LevelBufs* lv, int levels, int tail, int nu
       return launch_prolong_black<T, 1>(n, e1, (const T*)lv[1].e0, (const T*)lv[1].e1, ctl, s);
     case KT_FUSED_DOWN:
       if (tail == 0 || !fused_level<T>(lv[0], nu1, nu2)) return hipErrorInvalidValue;
+      if (fused_restricts<T>(lv[0], nu1, nu2)) {
+        *bytes = 2.125 * ts * n3;
+        return launch_fused_down<T, 1, 1>(lv[0], lv[1], nu1, ctl, s);
+      }
       *bytes = 2.0 * ts * n3;
-      return launch_fused_down<T, 1>(lv[0], nu1, ctl, s);
+      return launch_fused_down<T, 1, 0>(lv[0], lv[1], nu1, ctl, s);
     case KT_FUSED_UP:
       if (tail == 0 || !fused_level<T>(lv[0], nu1, nu2)) return hipErrorInvalidValue;
       *bytes = 2.625 * ts * n3;
@@ -1949,20 +2058,22 @@ hipError_t tail_configure(bool fp64, int n_tail, int levels_tail, size_t* lds_by
 int fused_tile(int n) { return n >= 64 ? 4 : 2; }
 
 namespace {
-template <typename T, int UP>
+template <typename T, int UP, int RST>
 hipError_t fused_allow() {
-  P3MZ_LAUNCH(allow_lds<Fused<T, UP, 0>>((int)kFusedLdsCap));
-  return allow_lds<Fused<T, UP, 1>>((int)kFusedLdsCap);
+  P3MZ_LAUNCH(allow_lds<Fused<T, UP, 0, RST>>((int)kFusedLdsCap));
+  return allow_lds<Fused<T, UP, 1, RST>>((int)kFusedLdsCap);
 }
 }  // namespace
 
 hipError_t fused_configure() {
   static bool done = false;
   if (done) return hipSuccess;
-  P3MZ_LAUNCH(fused_allow<float, 0>());
-  P3MZ_LAUNCH(fused_allow<float, 1>());
-  P3MZ_LAUNCH(fused_allow<double, 0>());
-  P3MZ_LAUNCH(fused_allow<double, 1>());
+  P3MZ_LAUNCH((fused_allow<float, 0, 0>()));
+  P3MZ_LAUNCH((fused_allow<float, 0, 1>()));
+  P3MZ_LAUNCH((fused_allow<float, 1, 0>()));
+  P3MZ_LAUNCH((fused_allow<double, 0, 0>()));
+  P3MZ_LAUNCH((fused_allow<double, 0, 1>()));
+  P3MZ_LAUNCH((fused_allow<double, 1, 0>()));
   done = true;
   return hipSuccess;
 }
