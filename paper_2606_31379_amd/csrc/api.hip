@@ -196,7 +196,7 @@ struct p3mz_ctx {
   double erfc_scale = 0.0;
   double *d_q = nullptr, *d_qs = nullptr, *d_tmp = nullptr;
   double* d_sigma = nullptr;
-  double* d_y[2] = {nullptr, nullptr};   // d_y[0]: multiplier; d_y[1]: FP64 outer residual
+  double* d_y[2] = {nullptr, nullptr};   // multiplier ping-pong (the control block's final_buf names the last)
   double* d_phi[2] = {nullptr, nullptr};
   double* d_yh[3] = {nullptr, nullptr, nullptr};
   float* d_phi32 = nullptr;
@@ -555,7 +555,7 @@ p3mz_status enq_pre(p3mz_ctx* c, const double* pos, hipStream_t s) {
   kt_begin(KT_OUTER, 0, s);
   P3MZ_HIP_TRY(launch_outer(c->fp64, n, 1, c->P.max_cycles, c->d_sigma, c->d_y[0], c->d_y[1], f.e0, f.e1, f.r0, f.r1,
                             c->d_partial, c->d_ctl, s));
-  kt_end(KT_OUTER, 0, (24.0 + ts) * N3, s);
+  kt_end(KT_OUTER, 0, (16.0 + ts) * N3, s);
   return P3MZ_OK;
 }
 
@@ -569,7 +569,7 @@ p3mz_status enq_cycle(p3mz_ctx* c, hipStream_t s) {
   kt_begin(KT_OUTER, 0, s);
   P3MZ_HIP_TRY(launch_outer(c->fp64, pl.n, 0, c->P.max_cycles, c->d_sigma, c->d_y[0], c->d_y[1], f.e0, f.e1, f.r0,
                             f.r1, c->d_partial, c->d_ctl, s));
-  kt_end(KT_OUTER, 0, (32.0 + 2.0 * ts) * N3, s);
+  kt_end(KT_OUTER, 0, (24.0 + 2.0 * ts) * N3, s);
   return P3MZ_OK;
 }
 
@@ -1489,11 +1489,11 @@ p3mz_status p3mz_kernel_bench(p3mz_ctx* ctx, int32_t kernel_id, int32_t reps, vo
                         s);
       bytes = 16.0 * N3;
     } else if (kernel_id == KT_OUTER) {
-      // the cycle form without its finalize pass; y and the FP64 residual are
-      // scratch between steps (the multiplier is kept in the history slots)
+      // the cycle form without its finalize pass; both multiplier buffers
+      // are scratch between steps (the multiplier is kept in the history slots)
       e = launch_outer(ctx->fp64, n, 0, ctx->P.max_cycles, ctx->d_sigma, ctx->d_y[0], ctx->d_y[1], f.e0, f.e1, f.r0,
                        f.r1, ctx->d_partial, ctx->d_ctl, s, false);
-      bytes = (32.0 + 2.0 * ts) * N3;
+      bytes = (24.0 + 2.0 * ts) * N3;
     } else if (kernel_id == KT_SIGMA) {
       e = launch_sigma(n, ctx->pl.h, ctx->d_qs, ctx->d_phi[0], ctx->d_phi[1], ctx->d_yh[0], ctx->d_yh[1], ctx->d_yh[2],
                        ctx->d_sigma, ctx->d_y[0], ctx->P.tol, ctx->P.tol_mode, ctx->d_partial, ctx->d_ctl, s, false);

@@ -80,10 +80,12 @@ void smooth_tile_shape(int tile, int* lines_per_workgroup, int* outputs_per_thre
 hipError_t launch_sigma(int n, double h, const double* qs, const double* phi0, const double* phi1,
                         const double* yb0, const double* yb1, const double* yb2, double* sigma, double* y,
                         double tol, int tol_mode, double* partial, Ctl* ctl, hipStream_t s, bool finalize = true);
-// Outer FP64 residual: cycle 0 (first) r = sigma - mean - M y; later cycles
-// y += e, r -= M e; r written colour-split in T for the next V-cycle; the
-// finalize pass records res_hist[c] and the stop decision.
-hipError_t launch_outer(bool fp64, int n, int first, int max_cycles, const double* sigma, double* y, double* r64,
+// Outer FP64 residual r = sigma - mean - M y: cycle 0 (first) on the
+// predicted y in y0; cycle c > 0 on y + e, the previous cycle's y (y0 or y1
+// by parity) plus this cycle's correction, written to the other buffer; r
+// written colour-split in T for the next V-cycle; the finalize pass records
+// res_hist[c], the stop decision and which buffer holds y.
+hipError_t launch_outer(bool fp64, int n, int first, int max_cycles, const double* sigma, double* y0, double* y1,
                         const void* e0, const void* e1, void* r0, void* r1, double* partial, Ctl* ctl,
                         hipStream_t s, bool finalize = true);
 struct LevelBufs {

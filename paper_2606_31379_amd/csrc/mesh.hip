@@ -307,19 +307,22 @@ __device__ void FinSigma::run(const Args& A, Grid) {
 }
 
 // ---------------------------------------------------------------------------
-// Outer residual in FP64 (Eq. 26) for M y = sigma_p.  Cycle 0 forms
-// r = (sigma_p - mean) - M y0 from the predicted multiplier; cycle c > 0
-// applies the V-cycle correction e in FP64, y += e and r -= M e, which equals
-// sigma_p - M y up to FP64 rounding and needs no FP64 stencil.  r goes to the
-// next V-cycle in precision T, colour-split; the finalize pass records the
-// residual, the running mean of y and the stop decision.
+// Outer residual in FP64 (Eq. 26) for M y = sigma_p, recomputed from y
+// every cycle: cycle 0 forms r = (sigma_p - mean) - M y from the predicted
+// multiplier; cycle c > 0 first applies the V-cycle correction, y += e in
+// FP64, and forms the same residual from the new y.  The multiplier
+// ping-pongs between y0 (cycles 0, 2, ...) and y1 (cycles 1, 3, ...), since
+// every point reads its neighbours' old values; the control block's
+// final_buf names the buffer of the last cycle.  r goes to the next V-cycle
+// in precision T, colour-split; the finalize pass records the residual, the
+// running mean of y and the stop decision.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct Outer {
   struct Args {
     int n, first;
     const double* sigma;
-    double *y, *r64;
+    double *y0, *y1;
     const T *e0, *e1;
     T *r0, *r1;
     double* partial;
@@ -332,8 +335,6 @@ template <typename T>
 __device__ void Outer<T>::run(const Args& A, Grid G) {
   const int n = A.n, first = A.first;
   const double* __restrict__ sigma = A.sigma;
-  double* __restrict__ y = A.y;
-  double* __restrict__ r64 = A.r64;
   const T* __restrict__ e0 = A.e0;
   const T* __restrict__ e1 = A.e1;
   T* __restrict__ r0 = A.r0;
@@ -372,39 +373,42 @@ __device__ void Outer<T>::run(const Args& A, Grid G) {
     const int i0 = t & msk, j = (t >> g.l2) & msk, k = t >> (2 * g.l2);
     const int jm = (j - 1) & msk, jp = (j + 1) & msk, km = (k - 1) & msk, kp = (k + 1) & msk;
     double r[4], yv[4];
-    if (c == 0) {
-      const int row = t - i0;
-      const D4 own = ld4(y, t), ym = ld4(y, nat_idx(n, i0, jm, k)), yp = ld4(y, nat_idx(n, i0, jp, k));
-      const D4 zm = ld4(y, nat_idx(n, i0, j, km)), zp = ld4(y, nat_idx(n, i0, j, kp));
-      const double xl = y[row + ((i0 - 1) & msk)], xr = y[row + ((i0 + 4) & msk)];
-      const D4 sg = ld4(sigma, t);
+    const int row = t - i0;
+    // y of cycle c at the point, its four-point row neighbours and the two
+    // x-edge points: the stored y (cycle 0), or the previous cycle's y plus
+    // this cycle's correction
+    const double* yo = (c & 1) ? A.y0 : A.y1;   // cycle c - 1 (cycle 0: the predictor in y0)
+    const double* ys = c == 0 ? A.y0 : yo;
+    D4 own = ld4(ys, t), ym = ld4(ys, nat_idx(n, i0, jm, k)), yp = ld4(ys, nat_idx(n, i0, jp, k));
+    D4 zm = ld4(ys, nat_idx(n, i0, j, km)), zp = ld4(ys, nat_idx(n, i0, j, kp));
+    double xl = ys[row + ((i0 - 1) & msk)], xr = ys[row + ((i0 + 4) & msk)];
+    if (c > 0) {
+      D4 eo, eym, eyp, ezm, ezp;
+      E4(j, k, i0, &eo);
+      E4(jm, k, i0, &eym);
+      E4(jp, k, i0, &eyp);
+      E4(j, km, i0, &ezm);
+      E4(j, kp, i0, &ezp);
+      xl += E1((i0 - 1) & msk, j, k);
+      xr += E1((i0 + 4) & msk, j, k);
 #pragma unroll
       for (int q = 0; q < 4; q++) {
-        const double xm = q == 0 ? xl : own.v[q - 1], xp = q == 3 ? xr : own.v[q + 1];
-        const double nb = ((xm + xp) + (ym.v[q] + yp.v[q])) + (zm.v[q] + zp.v[q]);
-        yv[q] = own.v[q];
-        r[q] = (sg.v[q] - mean_sigma) - (nb - 6.0 * own.v[q]);
+        own.v[q] += eo.v[q];
+        ym.v[q] += eym.v[q];
+        yp.v[q] += eyp.v[q];
+        zm.v[q] += ezm.v[q];
+        zp.v[q] += ezp.v[q];
       }
-    } else {
-      D4 own, ym, yp, zm, zp;
-      E4(j, k, i0, &own);
-      E4(jm, k, i0, &ym);
-      E4(jp, k, i0, &yp);
-      E4(j, km, i0, &zm);
-      E4(j, kp, i0, &zp);
-      const double xl = E1((i0 - 1) & msk, j, k), xr = E1((i0 + 4) & msk, j, k);
-      const D4 y4 = ld4(y, t), r4 = ld4(r64, t);
-#pragma unroll
-      for (int q = 0; q < 4; q++) {
-        const double xm = q == 0 ? xl : own.v[q - 1], xp = q == 3 ? xr : own.v[q + 1];
-        const double ev = own.v[q];
-        const double nb = ((xm + xp) + (ym.v[q] + yp.v[q])) + (zm.v[q] + zp.v[q]);
-        yv[q] = y4.v[q] + ev;
-        r[q] = r4.v[q] - (nb - 6.0 * ev);
-      }
-      st4(y, t, yv);
     }
-    st4(r64, t, r);
+    const D4 sg = ld4(sigma, t);
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const double xm = q == 0 ? xl : own.v[q - 1], xp = q == 3 ? xr : own.v[q + 1];
+      const double nb = ((xm + xp) + (ym.v[q] + yp.v[q])) + (zm.v[q] + zp.v[q]);
+      yv[q] = own.v[q];
+      r[q] = (sg.v[q] - mean_sigma) - (nb - 6.0 * own.v[q]);
+    }
+    if (c > 0) st4((c & 1) ? A.y1 : A.y0, t, yv);
     {
       // r in precision T, colour-split, in the pattern of E4
       const int par = (i0 + j + k) & 1;
@@ -460,7 +464,7 @@ __device__ void FinOuter::run(const Args& A, Grid) {
     ctl->res_hist[c] = res;
     ctl->mean_y = ys / (double)n3;
     ctl->cycles = c;
-    ctl->final_buf = 0;
+    ctl->final_buf = c & 1;
     if (res <= ctl->thresh) {
       ctl->done = 1;
     } else if (c >= max_cycles) {
@@ -2019,15 +2023,15 @@ hipError_t launch_sigma(int n, double h, const double* qs, const double* phi0, c
   return go<FinSigma>({nb, n3, tol_mode, tol, partial, ctl}, 1, 0, s);
 }
 
-hipError_t launch_outer(bool fp64, int n, int first, int max_cycles, const double* sigma, double* y, double* r64,
+hipError_t launch_outer(bool fp64, int n, int first, int max_cycles, const double* sigma, double* y0, double* y1,
                         const void* e0, const void* e1, void* r0, void* r1, double* partial, Ctl* ctl,
                         hipStream_t s, bool finalize) {
   const int n3 = n * n * n, nb = red_blocks(n3 / 4);   // four points per thread
   if (fp64)
-    P3MZ_LAUNCH(go<Outer<double>>({n, first, sigma, y, r64, (const double*)e0, (const double*)e1, (double*)r0,
+    P3MZ_LAUNCH(go<Outer<double>>({n, first, sigma, y0, y1, (const double*)e0, (const double*)e1, (double*)r0,
                                    (double*)r1, partial, ctl}, nb, 0, s));
   else
-    P3MZ_LAUNCH(go<Outer<float>>({n, first, sigma, y, r64, (const float*)e0, (const float*)e1, (float*)r0,
+    P3MZ_LAUNCH(go<Outer<float>>({n, first, sigma, y0, y1, (const float*)e0, (const float*)e1, (float*)r0,
                                   (float*)r1, partial, ctl}, nb, 0, s));
   if (!finalize) return hipSuccess;
   return go<FinOuter>({first, max_cycles, nb, n3, partial, ctl}, 1, 0, s);
