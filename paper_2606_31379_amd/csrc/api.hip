@@ -183,7 +183,7 @@ struct p3mz_ctx {
   void* d_taps = nullptr;
   double* d_green = nullptr;
   double* d_qa = nullptr;
-  int *d_base = nullptr, *d_key = nullptr, *d_slot = nullptr, *d_perm_raw = nullptr, *d_perm = nullptr;
+  int *d_base = nullptr, *d_key = nullptr, *d_slot = nullptr, *d_perm_raw = nullptr;
   void* d_w = nullptr;
   int ntx = 0, nbins = 0;
   int *d_count = nullptr, *d_start = nullptr, *d_bsum = nullptr;
@@ -431,7 +431,6 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   P3MZ_TRY(c->alloc(&c->d_key, na));
   P3MZ_TRY(c->alloc(&c->d_slot, na));
   P3MZ_TRY(c->alloc(&c->d_perm_raw, na));
-  P3MZ_TRY(c->alloc(&c->d_perm, na));
   P3MZ_TRY(c->alloc(&c->d_count, c->nbins));
   P3MZ_TRY(c->alloc(&c->d_start, c->nbins + 1));
   P3MZ_HIP_TRY(hipMemset(c->d_count, 0, sizeof(int) * c->nbins));
@@ -529,8 +528,8 @@ p3mz_status enq_pre(p3mz_ctx* c, const double* pos, hipStream_t s) {
   rec_key(102);
   P3MZ_HIP_TRY(launch_scatter(na, c->d_key, c->d_slot, c->d_start, c->d_perm_raw, s));
   rec_key(103);
-  P3MZ_HIP_TRY(launch_sort_bins(c->nbins, c->d_start, c->d_perm_raw, c->d_perm, c->d_ctl, s));
-  P3MZ_HIP_TRY(launch_pack_atoms(na, pos, c->d_qa, c->P.box, n, pl.p, c->d_perm, c->d_base, (double*)c->d_w, s));
+  P3MZ_HIP_TRY(launch_sort_pack(c->nbins, c->d_start, c->d_perm_raw, na, pos, c->d_qa, c->P.box, n, pl.p, c->d_base,
+                                (double*)c->d_w, s));
   rec_key(104);
   kt_begin(KT_SPREAD, 0, s);
   P3MZ_HIP_TRY(launch_spread(true, na, n, pl.p, kTile, c->ntx, c->d_start, c->d_base, (const double*)c->d_w, c->d_q,

@@ -39,6 +39,11 @@ hipError_t launch_scatter(int n_atoms, const int* key, const int* slot, const in
 // Sort every bin's atom list by atom index (makes all later sums deterministic).
 hipError_t launch_sort_bins(int nbins, const int* start, const int* perm_raw, int* perm, Ctl* ctl,
                             hipStream_t s);
+// SortBins and PackAtoms in one launch: each bin's atoms in ascending index,
+// their records (rb, rw as in launch_pack_atoms) written at the sorted
+// positions.
+hipError_t launch_sort_pack(int nbins, const int* start, const int* perm_raw, int n_atoms, const double* pos,
+                            const double* qa, double box, int n, int p, void* rb, double* rw, hipStream_t s);
 // Owner-computes spread: q (natural layout, precision T) from the binned atoms.
 hipError_t launch_spread(bool fp64, int n_atoms, int n, int p, int tile, int ntx, const int* start, const void* rb,
                          const double* rw, void* q, hipStream_t s);

@@ -84,21 +84,19 @@ struct PackAtoms {
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G);
 };
-__device__ void PackAtoms::run(const Args& A, Grid G) {
-  const int n = A.n, p = A.p;
-  const int i = G.b * kBlock + threadIdx.x;
-  if (i >= A.n_atoms) return;
-  const int a = A.perm[i];
-  const size_t na = (size_t)A.n_atoms;
-  double* rec = A.rw + i;
-  rec[0] = A.qa[a];
+// The records of atom a at bin-order position i.
+__device__ __forceinline__ void pack_atom(int i, int a, int n_atoms, int n, int p, double box, const double* pos,
+                                          const double* qa, int4* rb, double* rw) {
+  const size_t na = (size_t)n_atoms;
+  double* rec = rw + i;
+  rec[0] = qa[a];
   int f3[3];
   for (int d = 0; d < 3; d++) {
-    double x = A.pos[3 * a + d];
+    double x = pos[3 * a + d];
     if (!isfinite(x)) x = 0.0;
     int first;
     double tau;
-    stencil_origin(x, A.box, n, p, &first, &tau);
+    stencil_origin(x, box, n, p, &first, &tau);
     int f = first % n;
     if (f < 0) f += n;
     f3[d] = f;
@@ -106,7 +104,12 @@ __device__ void PackAtoms::run(const Args& A, Grid G) {
     bspline_weights<double>(p, tau, wl);
     for (int j = 0; j < p; j++) rec[(1 + d * p + j) * na] = wl[j];
   }
-  A.rb[i] = make_int4(f3[0], f3[1], f3[2], a);
+  rb[i] = make_int4(f3[0], f3[1], f3[2], a);
+}
+__device__ void PackAtoms::run(const Args& A, Grid G) {
+  const int i = G.b * kBlock + threadIdx.x;
+  if (i >= A.n_atoms) return;
+  pack_atom(i, A.perm[i], A.n_atoms, A.n, A.p, A.box, A.pos, A.qa, A.rb, A.rw);
 }
 
 struct BinCells {
@@ -223,6 +226,8 @@ struct ScanFill {
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G);
 };
+// With bsum null (one workgroup covers every count) the offsets start at 0
+// and the total comes from this workgroup's own scan.
 __device__ void ScanFill::run(const Args& A, Grid G) {
   const int nbins = A.nbins, nb = A.nb;
   int* __restrict__ count = A.count;
@@ -244,7 +249,7 @@ __device__ void ScanFill::run(const Args& A, Grid G) {
     sh[threadIdx.x] += u;
     __syncthreads();
   }
-  int acc = bsum[G.b] + sh[threadIdx.x] - s;
+  int acc = (bsum ? bsum[G.b] : 0) + sh[threadIdx.x] - s;
   for (int q = 0; q < kScanPer; q++) {
     if (base + q < nbins) {
       start[base + q] = acc;
@@ -252,7 +257,7 @@ __device__ void ScanFill::run(const Args& A, Grid G) {
     }
     acc += v[q];
   }
-  if (G.b == 0 && threadIdx.x == 0) start[nbins] = bsum[nb];
+  if (G.b == 0 && threadIdx.x == 0) start[nbins] = bsum ? bsum[nb] : sh[kBlock - 1];
 }
 
 struct Scatter {
@@ -271,11 +276,18 @@ struct Scatter {
 
 // One wave per bin: rank of each entry = number of smaller atom indices in
 // the bin (indices are distinct), so perm[start + rank] is the sorted list.
+// With rb set, the sorted entry is not stored: the atom's records are
+// written at its sorted position instead (PackAtoms in the same launch).
 struct SortBins {
   struct Args {
     int nbins;
     const int *start, *perm_raw;
     int* perm;
+    int n_atoms, n, p;
+    double box;
+    const double *pos, *qa;
+    int4* rb;
+    double* rw;
   };
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G);
@@ -301,7 +313,12 @@ __device__ void SortBins::run(const Args& A, Grid G) {
         rank += (vj < v);
       }
     }
-    if (i < cnt) perm[s0 + rank] = v;
+    if (i < cnt) {
+      if (A.rb)
+        pack_atom(s0 + rank, v, A.n_atoms, A.n, A.p, A.box, A.pos, A.qa, A.rb, A.rw);
+      else
+        perm[s0 + rank] = v;
+    }
   }
 }
 
@@ -871,6 +888,13 @@ int scan_partials(int nbins) { return (nbins + kScanChunk - 1) / kScanChunk + 1;
 
 hipError_t launch_scan(int nbins, int* count, int* start, int* bsum, hipStream_t s) {
   const int nb = (nbins + kScanChunk - 1) / kScanChunk;
+  if (nb == 1) {
+    // one workgroup scans all; in a batch recording it takes the sequence
+    // position of the multi-workgroup ScanFill, so it merges with the other
+    // systems' ScanFill launches
+    if (g_recorder) g_recorder->seq += 2;
+    return go<ScanFill>({nbins, 1, count, start, nullptr}, 1, 0, s);
+  }
   hipError_t e = go<ScanSums>({nbins, count, bsum}, nb, 0, s);
   if (e != hipSuccess) return e;
   e = go<ScanTop>({nb, bsum}, 1, 0, s);
@@ -885,7 +909,14 @@ hipError_t launch_scatter(int n_atoms, const int* key, const int* slot, const in
 
 hipError_t launch_sort_bins(int nbins, const int* start, const int* perm_raw, int* perm, Ctl*,
                             hipStream_t s) {
-  return go<SortBins>({nbins, start, perm_raw, perm}, blocks_for((int64_t)nbins * 64, kBlock), 0, s);
+  return go<SortBins>({nbins, start, perm_raw, perm, 0, 0, 0, 0.0, nullptr, nullptr, nullptr, nullptr},
+                      blocks_for((int64_t)nbins * 64, kBlock), 0, s);
+}
+
+hipError_t launch_sort_pack(int nbins, const int* start, const int* perm_raw, int n_atoms, const double* pos,
+                            const double* qa, double box, int n, int p, void* rb, double* rw, hipStream_t s) {
+  return go<SortBins>({nbins, start, perm_raw, nullptr, n_atoms, n, p, box, pos, qa, (int4*)rb, rw},
+                      blocks_for((int64_t)nbins * 64, kBlock), 0, s);
 }
 
 namespace {
