@@ -563,11 +563,20 @@ p3mz_status enq_cycle(p3mz_ctx* c, hipStream_t s) {
   const Plan& pl = c->pl;
   const LevelBufs& f = c->lv[0];
   const double N3 = (double)c->n3, ts = (double)c->tsz;
-  P3MZ_HIP_TRY(launch_vcycle(c->fp64, c->lv, pl.levels, pl.tail, c->nu1, c->nu2, c->d_green, c->d_ctl, s));
+  // A single system: the tail makes the stop decision of the previous outer
+  // residual, and this cycle's is made by the next cycle's tail or ahead of
+  // the field update (one launch less per cycle).  A batch decides right
+  // after each residual: its systems converge at different cycles, and a
+  // deferred decision would let the converged ones run the next cycle's
+  // upper levels.
+  const bool defer = !g_recorder;
+  const Decide d{c->d_partial, red_blocks((int64_t)c->n3 / 4), (int)c->n3, c->P.max_cycles};
+  P3MZ_HIP_TRY(launch_vcycle(c->fp64, c->lv, pl.levels, pl.tail, c->nu1, c->nu2, c->d_green, c->d_ctl, s,
+                             defer ? &d : nullptr));
   rec_key(4100);
   kt_begin(KT_OUTER, 0, s);
   P3MZ_HIP_TRY(launch_outer(c->fp64, pl.n, 0, c->P.max_cycles, c->d_sigma, c->d_y[0], c->d_y[1], f.e0, f.e1, f.r0,
-                            f.r1, c->d_partial, c->d_ctl, s));
+                            f.r1, c->d_partial, c->d_ctl, s, !defer));
   kt_end(KT_OUTER, 0, (24.0 + 2.0 * ts) * N3, s);
   return P3MZ_OK;
 }
@@ -577,6 +586,7 @@ p3mz_status enq_post1(p3mz_ctx* c, double* force, hipStream_t s) {
   const Plan& pl = c->pl;
   const int n = pl.n, na = (int)c->n_atoms;
   const double N3 = (double)c->n3;
+  if (!g_recorder) P3MZ_HIP_TRY(launch_outer_decide(n, c->P.max_cycles, c->d_partial, c->d_ctl, s));
   rec_key(5000);
   kt_begin(KT_PHI, 0, s);
   P3MZ_HIP_TRY(launch_phi_update(n, pl.h, c->d_phi[0], c->d_phi[1], c->d_y[0], c->d_y[1], c->d_yh[0], c->d_yh[1],

@@ -31,7 +31,8 @@ struct Ctl {
   int yh0, yh1, yh2;     // multiplier buffers, newest first
   int predictor;         // requested predictor order
   int md_step;           // row of the MD energy log
-  int pad0, pad1;
+  int pending;           // 1 + cycle of an outer residual whose stop decision is still to be made (0: none)
+  int pad1;
   long long steps;       // completed steps
   double thresh;         // residual threshold
   double norm_qs;        // max |q^s|

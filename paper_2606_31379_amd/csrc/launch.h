@@ -88,11 +88,22 @@ hipError_t launch_sigma(int n, double h, const double* qs, const double* phi0, c
 // Outer FP64 residual r = sigma - mean - M y: cycle 0 (first) on the
 // predicted y in y0; cycle c > 0 on y + e, the previous cycle's y (y0 or y1
 // by parity) plus this cycle's correction, written to the other buffer; r
-// written colour-split in T for the next V-cycle; the finalize pass records
-// res_hist[c], the stop decision and which buffer holds y.
+// written colour-split in T for the next V-cycle; it marks its stop decision
+// pending, and with finalize a one-workgroup pass makes it right away
+// (res_hist[c], done/status and which buffer holds y).
 hipError_t launch_outer(bool fp64, int n, int first, int max_cycles, const double* sigma, double* y0, double* y1,
                         const void* e0, const void* e1, void* r0, void* r1, double* partial, Ctl* ctl,
                         hipStream_t s, bool finalize = true);
+// The stop decision of an outer residual: its partials (nb workgroups,
+// max then sum) on a fine mesh of n3 points, with the cycle cap.
+struct Decide {
+  const double* partial;
+  int nb, n3, max_cycles;
+};
+// The stop decision alone (one workgroup): records res_hist, the mean of y,
+// the cycle count and done/status for the outer residual marked pending in
+// the control block; nothing if none is.
+hipError_t launch_outer_decide(int n, int max_cycles, const double* partial, Ctl* ctl, hipStream_t s);
 struct LevelBufs {
   int n;
   void* e0; void* e1;   // colour-split correction
@@ -108,9 +119,12 @@ constexpr int kFusedEdgeMax = 64;
 int fused_tile(int n);
 // One V-cycle on the colour-split level hierarchy lv[0..levels-1]; the
 // levels from `tail` on run in one LDS-resident workgroup; levels with
-// fty > 0 run each leg as one fused launch when its LDS box fits.
+// fty > 0 run each leg as one fused launch when its LDS box fits.  With
+// `decide`, the tail first makes the pending stop decision of the previous
+// outer residual (the launches before it may run on a system that has just
+// converged: they only write scratch levels).
 hipError_t launch_vcycle(bool fp64, const LevelBufs* lv, int levels, int tail, int nu1, int nu2,
-                         const double* green, Ctl* ctl, hipStream_t s);
+                         const double* green, Ctl* ctl, hipStream_t s, const Decide* decide = nullptr);
 // One finest-level launch of a V-cycle kernel family (KT_HALFSWEEP, KT_SWEEP0,
 // KT_RESTRICT, KT_PROLONG, KT_TAIL) on the current buffers; *bytes = its
 // algorithmic traffic.

@@ -303,6 +303,7 @@ __device__ void FinSigma::run(const Args& A, Grid) {
     ctl->cycles = 0;
     ctl->status = 0;
     ctl->final_buf = 0;
+    ctl->pending = 0;
   }
 }
 
@@ -326,7 +327,7 @@ struct Outer {
     const T *e0, *e1;
     T *r0, *r1;
     double* partial;
-    const Ctl* ctl;
+    Ctl* ctl;
   };
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G);
@@ -340,7 +341,7 @@ __device__ void Outer<T>::run(const Args& A, Grid G) {
   T* __restrict__ r0 = A.r0;
   T* __restrict__ r1 = A.r1;
   double* __restrict__ partial = A.partial;
-  const Ctl* ctl = A.ctl;
+  Ctl* ctl = A.ctl;
   __shared__ double sh[kBlock / 64];
   if (ctl->done) return;
   const int c = first ? 0 : ctl->cycles + 1;
@@ -431,15 +432,53 @@ __device__ void Outer<T>::run(const Args& A, Grid G) {
   if (threadIdx.x == 0) {
     partial[G.b] = bm;
     partial[G.g + G.b] = bs;
+    if (G.b == 0) ctl->pending = c + 1;
   }
 }
 
-// One workgroup: residual of cycle c, running mean of y, stop decision.
-// The partials are read while the control block's flag is still in flight
-// (both reductions in one pass; fixed split and tree, so deterministic).
+// The stop decision of the pending outer residual, by one whole workgroup
+// (1024 threads): residual of cycle c (max norm), running mean of y, cycle
+// count, which buffer holds y, done/status.  The partials are read while the
+// pending mark is still in flight (both reductions in one pass; fixed split
+// and tree, so deterministic).  Returns, in every thread, whether the solve
+// is done after it.  sh: 2 * blockDim.x / 64 doubles; flag: one int.
+__device__ __forceinline__ int outer_decide(Ctl* ctl, const double* __restrict__ partial, int nb, int n3,
+                                            int max_cycles, double* sh, int* flag) {
+  const int pend = ctl->pending;
+  double res = 0.0, ys = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    res = fmax(res, partial[i]);
+    ys += partial[nb + i];
+  }
+  block_max_sum(&res, &ys, sh);
+  if (threadIdx.x == 0) {
+    int done = ctl->done;
+    if (pend) {
+      const int c = pend - 1;
+      ctl->res_hist[c] = res;
+      ctl->mean_y = ys / (double)n3;
+      ctl->cycles = c;
+      ctl->final_buf = c & 1;
+      if (res <= ctl->thresh) {
+        done = 1;
+      } else if (c >= max_cycles) {
+        done = 1;
+        ctl->status = 1;
+      }
+      ctl->done = done;
+      ctl->pending = 0;
+    }
+    *flag = done;
+  }
+  __syncthreads();
+  return *flag;
+}
+
+// The stop decision as a launch of its own (after the first residual, and
+// ahead of the field update for the last cycle's residual).
 struct FinOuter {
   struct Args {
-    int first, max_cycles, nb, n3;
+    int max_cycles, nb, n3;
     const double* partial;
     Ctl* ctl;
   };
@@ -447,31 +486,9 @@ struct FinOuter {
   __device__ static void run(const Args& A, Grid G);
 };
 __device__ void FinOuter::run(const Args& A, Grid) {
-  const int first = A.first, max_cycles = A.max_cycles, nb = A.nb, n3 = A.n3;
-  const double* __restrict__ partial = A.partial;
-  Ctl* ctl = A.ctl;
   __shared__ double sh[2 * kThreads / 64];
-  const int done = ctl->done;
-  double res = 0.0, ys = 0.0;
-  for (int i = threadIdx.x; i < nb; i += kThreads) {
-    res = fmax(res, partial[i]);
-    ys += partial[nb + i];
-  }
-  block_max_sum(&res, &ys, sh);
-  if (done) return;
-  const int c = first ? 0 : ctl->cycles + 1;
-  if (threadIdx.x == 0) {
-    ctl->res_hist[c] = res;
-    ctl->mean_y = ys / (double)n3;
-    ctl->cycles = c;
-    ctl->final_buf = c & 1;
-    if (res <= ctl->thresh) {
-      ctl->done = 1;
-    } else if (c >= max_cycles) {
-      ctl->done = 1;
-      ctl->status = 1;
-    }
-  }
+  __shared__ int flag;
+  (void)outer_decide(A.ctl, A.partial, A.nb, A.n3, A.max_cycles, sh, &flag);
 }
 
 // ---------------------------------------------------------------------------
@@ -1291,7 +1308,11 @@ struct Tail {
     const T *r0, *r1;
     T *e0, *e1;
     const double* green;
-    const Ctl* ctl;
+    Ctl* ctl;
+    // the pending stop decision of the previous outer residual (partial
+    // null: none is made here)
+    const double* partial;
+    int nb, n3, max_cycles;
   };
   static constexpr int kThreads = 1024;
   __device__ static void run(const Args& A, Grid G);
@@ -1450,6 +1471,8 @@ __device__ __forceinline__ void tail_up(T* e0, T* e1, const T* r0, const T* r1, 
 // the LDS holds the levels below it.
 template <typename T, bool GTOP>
 __device__ __forceinline__ void tail_run(const typename Tail<T>::Args& A, int done) {
+  // (done: the control block's flag, replaced by the pending stop decision
+  // when this launch makes it)
   const int n0 = A.n0, levels = A.levels, nu1 = A.nu1, nu2 = A.nu2;
   constexpr int W = Vec<T>::W;
   using V = typename Vec<T>::type;
@@ -1483,6 +1506,12 @@ __device__ __forceinline__ void tail_run(const typename Tail<T>::Args& A, int do
       r0[t] = A.r0[t];
       r1[t] = A.r1[t];
     }
+  }
+  if (A.partial) {
+    // the pending stop decision, its partials loaded alongside the level data
+    __shared__ double sh[2 * Tail<T>::kThreads / 64];
+    __shared__ int flag;
+    done = outer_decide(A.ctl, A.partial, A.nb, A.n3, A.max_cycles, sh, &flag);
   }
   if (done) return;
   __syncthreads();
@@ -1671,6 +1700,7 @@ __global__ void k_set_open(Ctl* ctl) {
   ctl->done = 0;
   ctl->cycles = 0;
   ctl->status = 0;
+  ctl->pending = 0;
 }
 
 // Vectorized sweeps: one thread per Vec<T>::W points, so half / W threads.
@@ -1713,10 +1743,11 @@ hipError_t launch_prolong_black(int n, T* e1, const T* c0, const T* c1, Ctl* ctl
 }
 template <typename T>
 hipError_t launch_tail(const LevelBufs* lv, int levels, int tail, int nu1, int nu2, const double* green, Ctl* ctl,
-                       hipStream_t s) {
+                       hipStream_t s, const Decide* d = nullptr) {
   const int lt = levels - tail;
   return go<Tail<T>>({lv[tail].n, lt, nu1, nu2, (const T*)lv[tail].r0, (const T*)lv[tail].r1, (T*)lv[tail].e0,
-                      (T*)lv[tail].e1, green, ctl},
+                      (T*)lv[tail].e1, green, ctl, d ? d->partial : nullptr, d ? d->nb : 0, d ? d->n3 : 0,
+                      d ? d->max_cycles : 0},
                      1, tail_lds_bytes(lv[tail].n, lt, sizeof(T)), s);
 }
 
@@ -1788,7 +1819,7 @@ constexpr uint32_t kKeyTail = 2100u;
 
 template <typename T>
 hipError_t vcycle_impl(const LevelBufs* lv, int levels, int tail, int nu1, int nu2, const double* green,
-                       Ctl* ctl, hipStream_t s) {
+                       Ctl* ctl, hipStream_t s, const Decide* decide) {
   const double ts = sizeof(T);
   for (int l = 0; l < tail; l++) {
     const int n = lv[l].n, half = n * n * n / 2;
@@ -1843,7 +1874,7 @@ hipError_t vcycle_impl(const LevelBufs* lv, int levels, int tail, int nu1, int n
     const double nt3 = (double)lv[tail].n * lv[tail].n * lv[tail].n;
     rec_key(kKeyTail);
     kt_begin(KT_TAIL, 0, s);
-    P3MZ_LAUNCH(launch_tail<T>(lv, levels, tail, nu1, nu2, green, ctl, s));
+    P3MZ_LAUNCH(launch_tail<T>(lv, levels, tail, nu1, nu2, green, ctl, s, decide));
     kt_end(KT_TAIL, 0, 2.0 * ts * nt3, s);
   }
   for (int l = tail - 1; l >= 0; l--) {
@@ -2034,13 +2065,18 @@ hipError_t launch_outer(bool fp64, int n, int first, int max_cycles, const doubl
     P3MZ_LAUNCH(go<Outer<float>>({n, first, sigma, y0, y1, (const float*)e0, (const float*)e1, (float*)r0,
                                   (float*)r1, partial, ctl}, nb, 0, s));
   if (!finalize) return hipSuccess;
-  return go<FinOuter>({first, max_cycles, nb, n3, partial, ctl}, 1, 0, s);
+  return go<FinOuter>({max_cycles, nb, n3, partial, ctl}, 1, 0, s);
+}
+
+hipError_t launch_outer_decide(int n, int max_cycles, const double* partial, Ctl* ctl, hipStream_t s) {
+  const int n3 = n * n * n, nb = red_blocks(n3 / 4);
+  return go<FinOuter>({max_cycles, nb, n3, partial, ctl}, 1, 0, s);
 }
 
 hipError_t launch_vcycle(bool fp64, const LevelBufs* lv, int levels, int tail, int nu1, int nu2,
-                         const double* green, Ctl* ctl, hipStream_t s) {
-  return fp64 ? vcycle_impl<double>(lv, levels, tail, nu1, nu2, green, ctl, s)
-              : vcycle_impl<float>(lv, levels, tail, nu1, nu2, green, ctl, s);
+                         const double* green, Ctl* ctl, hipStream_t s, const Decide* decide) {
+  return fp64 ? vcycle_impl<double>(lv, levels, tail, nu1, nu2, green, ctl, s, decide)
+              : vcycle_impl<float>(lv, levels, tail, nu1, nu2, green, ctl, s, decide);
 }
 
 hipError_t launch_vcycle_kernel(bool fp64, int kid, const LevelBufs* lv, int levels, int tail, int nu1, int nu2,
