@@ -228,33 +228,33 @@ def run_mode(torch, P, w, system, precision, warmup, steps, kernel, schedule=Non
         P.p3mz_destroy(ctx)
 
 
-def oracle_sample(w, system, traj, nu_pre, nu_post, targets, min_time_s=0.0, max_steps=400):
-    """Oracle forces and cycle counts on `traj`; with min_time_s the oracle
-    keeps stepping along the same straight-line motion (timing only) until
-    its warm mesh steps add up to that many seconds."""
+def oracle_sample(w, system, traj, nu_pre, nu_post, targets, min_time_s=0.0, max_reps=50):
+    """Oracle forces and cycle counts on `traj` (a cold step, then warm
+    steps); with min_time_s the sequence is run again from a cold start
+    (timing only) until the warm mesh steps add up to that many seconds, so
+    the timed steps keep the sample's mix of V-cycle counts."""
     import numpy as np
     from oracle import oracle as O
     op = O.make_params(w.box, w.alpha, w.r_cut, w.mesh, w.order, tol=w.tol, predictor=w.predictor,
                        coulomb_k=14.3996454784, nu_pre=nu_pre, nu_post=nu_post, excl_group=w.excl_group)
-    orc = O.Oracle(op, system.charges)
-    if targets is not None:
-        orc.set_sr_targets(targets)
     ref, cyc_ref, t_mesh = [], [], []
-    k = 0
-    while k < len(traj) or (sum(t_mesh) < min_time_s and k < max_steps):
-        x = traj[k] if k < len(traj) else system.pos + k * w.dt_fs * system.vel
-        f, e, _ = orc.compute(x)
-        st = orc.stats()
-        if k < len(traj):
-            ref.append(f if targets is None else f[targets])
-            cyc_ref.append(st.cycles)
-        if k > 0:
-            t_mesh.append(st.t_spread + st.t_solve + st.t_gather)
-        if k < len(traj) or k % 20 == 0:
-            log(f"[oracle nu=({nu_pre},{nu_post})] step {k} cycles={st.cycles} "
-                f"mesh_s={st.t_spread + st.t_solve + st.t_gather:.3f}")
-        k += 1
-    orc.close()
+    rep = 0
+    while rep == 0 or (sum(t_mesh) < min_time_s and rep < max_reps):
+        orc = O.Oracle(op, system.charges)
+        if targets is not None:
+            orc.set_sr_targets(targets)
+        for k, x in enumerate(traj):
+            f, e, _ = orc.compute(x)
+            st = orc.stats()
+            if rep == 0:
+                ref.append(f if targets is None else f[targets])
+                cyc_ref.append(st.cycles)
+                log(f"[oracle nu=({nu_pre},{nu_post})] step {k} cycles={st.cycles} "
+                    f"mesh_s={st.t_spread + st.t_solve + st.t_gather:.3f}")
+            if k > 0:
+                t_mesh.append(st.t_spread + st.t_solve + st.t_gather)
+        orc.close()
+        rep += 1
     return ref, cyc_ref, t_mesh
 
 
@@ -309,8 +309,9 @@ def parity_and_baseline(torch, P, w, system, sample_steps, schedules):
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     mean_s = float(np.mean(t_mesh)) if t_mesh else float("nan")
     baseline = dict(value=mean_s * 1e9 / system.n, unit="ns/atom/step", cores=cores, kind="oracle",
-                    sample=f"{len(t_mesh)} warm mesh steps of {w.name} ({sum(t_mesh):.1f} s of oracle time) along "
-                           f"the initial velocities (dt {w.dt_fs} fs) after one cold step, V-cycle schedule "
+                    sample=f"{len(t_mesh)} warm mesh steps of {w.name} ({sum(t_mesh):.1f} s of oracle time): "
+                           f"{sample_steps}-step runs along the initial velocities (dt {w.dt_fs} fs), each from a "
+                           f"cold step that is not timed, repeated to at least 10 s, V-cycle schedule "
                            f"({head['nu_pre']},{head['nu_post']}); spread+smoothing+solve+gather only")
     return out, baseline
 
