@@ -175,6 +175,34 @@ __device__ __forceinline__ void st4(double* __restrict__ a, int t, const double*
   *reinterpret_cast<double2*>(a + t + 2) = make_double2(v[2], v[3]);
 }
 
+// Visits the n^3 points of a natural-layout mesh four at a time (x-vectors
+// of one row), calling f(t) with the index of the first point.  From 64^3 up
+// a workgroup walks a column: JB consecutive rows (the 1024 points of one
+// pass of 256 threads) of a band of z-planes, plane after plane, so a 7-point
+// stencil's z-neighbour rows are those the workgroup read one pass before or
+// reads one pass later; the workgroups of one XCD (consecutive logical
+// indices) cover every column of the same z-band, so y-neighbour rows are
+// shared through that XCD's L2.  The grid is red_blocks(n^3 / 4), which for
+// n >= 64 is (n / JB) columns times a whole number of z-bands.  Smaller
+// meshes take contiguous chunks.
+template <typename F>
+__device__ __forceinline__ void march4(const Grid& G, int n, F f) {
+  const int l2 = __builtin_ctz(n), msk = n - 1;
+  if (n >= 64) {
+    const int JB = (4 * kBlock) >> l2, nj = n / JB, nz = G.g / nj, KB = n / nz;
+    const int jb = G.b % nj, zr = G.b / nj;
+    const int j = jb * JB + ((4 * (int)threadIdx.x) >> l2), x = (4 * (int)threadIdx.x) & msk;
+    for (int kk = 0; kk < KB; kk++) {
+      const int k = zr * KB + kk;
+      f(((k << l2) + j) * n + x);
+    }
+  } else {
+    int lo, hi;
+    chunk_range(G, n * n * n, &lo, &hi);
+    for (int t = lo + 4 * threadIdx.x; t < hi; t += 4 * kBlock) f(t);
+  }
+}
+
 template <typename TQ>
 struct Sigma {
   struct Args {
@@ -204,9 +232,6 @@ __device__ void Sigma<TQ>::run(const Args& A, Grid G) {
   double* __restrict__ partial = A.partial;
   const Ctl* ctl = A.ctl;
   __shared__ double sh[kBlock / 64];
-  const int n3 = n * n * n;
-  int lo, hi;
-  chunk_range(G, n3, &lo, &hi);
   const int cold = ctl->cold, m_eff = ctl->m_eff;
   const double* pk = ctl->k_idx ? phi1 : phi0;
   const double* pkm1 = ctl->k_idx ? phi0 : phi1;
@@ -216,8 +241,8 @@ __device__ void Sigma<TQ>::run(const Args& A, Grid G) {
   const double* y2 = yb[ctl->yh2];
   double sv = 0.0, qmax = 0.0;
   const int l2 = __builtin_ctz(n), msk = n - 1;
-  // four consecutive points of one row per thread (chunks are multiples of 4)
-  for (int t = lo + 4 * threadIdx.x; t < hi; t += 4 * kBlock) {
+  // four consecutive points of one row per thread
+  march4(G, n, [&](int t) {
     const int i0 = t & msk, j = (t >> l2) & msk, k = t >> (2 * l2);
     const D4 q4 = ld4(qs, t);
     double sg[4];
@@ -267,7 +292,7 @@ __device__ void Sigma<TQ>::run(const Args& A, Grid G) {
       sv += sg[c];
       qmax = fmax(qmax, fabs(q4.v[c]));
     }
-  }
+  });
   double bs = block_sum(sv, sh);
   double bm = block_max(qmax, sh);
   if (threadIdx.x == 0) {
@@ -347,8 +372,6 @@ __device__ void Outer<T>::run(const Args& A, Grid G) {
   const int c = first ? 0 : ctl->cycles + 1;
   const CsGeo g(n);
   const int n3 = n * n * n, msk = n - 1;
-  int lo, hi;
-  chunk_range(G, n3, &lo, &hi);
   const double mean_sigma = ctl->mean_sigma;
   double rmax = 0.0, ysum = 0.0;
   // Correction e at four consecutive points x = i0 .. i0+3 of row (j, k):
@@ -369,8 +392,8 @@ __device__ void Outer<T>::run(const Args& A, Grid G) {
   auto E1 = [&](int x, int j, int k) -> double {
     return (double)(((x + j + k) & 1) ? e1 : e0)[cs_index(g, x, j, k)];
   };
-  // four consecutive points of one row per thread (chunks are multiples of 4)
-  for (int t = lo + 4 * threadIdx.x; t < hi; t += 4 * kBlock) {
+  // four consecutive points of one row per thread
+  march4(G, n, [&](int t) {
     const int i0 = t & msk, j = (t >> g.l2) & msk, k = t >> (2 * g.l2);
     const int jm = (j - 1) & msk, jp = (j + 1) & msk, km = (k - 1) & msk, kp = (k + 1) & msk;
     double r[4], yv[4];
@@ -426,7 +449,7 @@ __device__ void Outer<T>::run(const Args& A, Grid G) {
       rmax = fmax(rmax, fabs(r[q]));
       ysum += yv[q];
     }
-  }
+  });
   double bm = block_max(rmax, sh);
   double bs = block_sum(ysum, sh);
   if (threadIdx.x == 0) {
