@@ -228,7 +228,7 @@ def run_mode(torch, P, w, system, precision, warmup, steps, kernel, schedule=Non
         P.p3mz_destroy(ctx)
 
 
-def oracle_sample(w, system, traj, nu_pre, nu_post, targets, min_time_s=0.0, max_reps=50):
+def oracle_sample(w, system, traj, nu_pre, nu_post, targets, min_time_s=0.0, max_reps=200):
     """Oracle forces and cycle counts on `traj` (a cold step, then warm
     steps); with min_time_s the sequence is run again from a cold start
     (timing only) until the warm mesh steps add up to that many seconds, so
