@@ -237,13 +237,15 @@ p3mz_status p3mz_kernel_bench(p3mz_ctx* ctx, int32_t kernel_id, int32_t reps, vo
 p3mz_status p3mz_set_schedule(p3mz_ctx* ctx, int32_t nu_pre, int32_t nu_post, int32_t smooth_tile);
 
 /* Multigrid levels above the one-workgroup tail whose edge is at most
- * max_edge (levels of 16^3 .. 64^3 qualify; 0 = none) run each leg of the
+ * max_edge (the 32^3 and 64^3 levels qualify; 0 = none) run each leg of the
  * V-cycle (the pre-smoothing sweeps, and the correction plus post-smoothing
  * sweeps) as one launch: each workgroup keeps a tile of grid rows with a halo
  * of one row per sweep in LDS and recomputes the halo instead of exchanging
- * it (temporal blocking).  Needs nu_pre, nu_post >= 1 and the halo box within
- * 160 KiB of LDS; other levels and schedules keep one launch per sweep.
- * Results are bitwise identical either way.  Default 64.  Synchronises the
+ * it (temporal blocking).  The down leg also forms the restricted residual of
+ * its tile when a box two rows wider fits.  Needs nu_pre, nu_post >= 1 and
+ * the halo box within 160 KiB of LDS; other levels and schedules keep one
+ * launch per sweep.  Results are bitwise identical either way.  Default 64;
+ * systems of a batch always keep one launch per sweep.  Synchronises the
  * device; graphs are recaptured.  Errors: INVALID_ARG for max_edge < 0. */
 p3mz_status p3mz_set_fused_levels(p3mz_ctx* ctx, int32_t max_edge);
 

@@ -264,6 +264,9 @@ def test_fused_levels_bitwise(torch, precision, nu):
         plain = g.vcycle(r)
         P.p3mz_set_fused_levels(g.h, 32)
         partial = g.vcycle(r)
+        with pytest.raises(P.P3MZError) as ei:
+            P.p3mz_set_fused_levels(g.h, -1)
+        assert ei.value.code == P.P3MZ_ERR_INVALID_ARG
     finally:
         g.close()
     assert np.array_equal(fused, plain)
