@@ -202,6 +202,7 @@ struct p3mz_ctx {
   float* d_phi32 = nullptr;
   LevelBufs lv[P3MZ_MAX_LEVELS];
   double* d_partial = nullptr;
+  double* d_spart = nullptr;     // sigma's partials when the first outer residual reduces them
   Ctl* d_ctl = nullptr;
   Ctl* h_ctl = nullptr;         // pinned mirror
   double* d_energy = nullptr;   // internal energy4 when the caller passes none
@@ -482,6 +483,7 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   }
   // every reduction grid is capped, so one fixed-size partial buffer fits all
   P3MZ_TRY(c->alloc(&c->d_partial, kPartialSlots));
+  P3MZ_TRY(c->alloc(&c->d_spart, kPartialSlots));
   P3MZ_TRY(c->alloc(&c->d_ctl, 1));
   P3MZ_HIP_TRY(hipHostMalloc((void**)&c->h_ctl, sizeof(Ctl), hipHostMallocDefault));
   memset(&c->mirror, 0, sizeof(Ctl));
@@ -546,14 +548,21 @@ p3mz_status enq_pre(p3mz_ctx* c, const double* pos, hipStream_t s) {
   stage(c, 1, s);
   rec_key(110);
   kt_begin(KT_SIGMA, 0, s);
+  // A single system folds the sigma pass's reduction into the first outer
+  // residual (every workgroup reduces sigma's partials, kept in a buffer of
+  // their own) and leaves that residual's stop decision to the first
+  // cycle's tail: two launches less per step.  A batch keeps both passes.
+  const bool fold = !g_recorder;
   P3MZ_HIP_TRY(launch_sigma(n, pl.h, c->d_qs, c->d_phi[0], c->d_phi[1], c->d_yh[0], c->d_yh[1], c->d_yh[2],
-                            c->d_sigma, c->d_y[0], c->P.tol, c->P.tol_mode, c->d_partial, c->d_ctl, s));
+                            c->d_sigma, c->d_y[0], c->P.tol, c->P.tol_mode, fold ? c->d_spart : c->d_partial,
+                            c->d_ctl, s, !fold));
   kt_end(KT_SIGMA, 0, 64.0 * N3, s);
   const LevelBufs& f = c->lv[0];
   rec_key(111);
   kt_begin(KT_OUTER, 0, s);
   P3MZ_HIP_TRY(launch_outer(c->fp64, n, 1, c->P.max_cycles, c->d_sigma, c->d_y[0], c->d_y[1], f.e0, f.e1, f.r0, f.r1,
-                            c->d_partial, c->d_ctl, s));
+                            c->d_partial, c->d_ctl, s, !fold, fold ? c->d_spart : nullptr, c->P.tol,
+                            c->P.tol_mode));
   kt_end(KT_OUTER, 0, (16.0 + ts) * N3, s);
   return P3MZ_OK;
 }

@@ -91,9 +91,12 @@ hipError_t launch_sigma(int n, double h, const double* qs, const double* phi0, c
 // written colour-split in T for the next V-cycle; it marks its stop decision
 // pending, and with finalize a one-workgroup pass makes it right away
 // (res_hist[c], done/status and which buffer holds y).
+// spart (first residual only): sigma's partials, reduced by every workgroup
+// in place of the separate FinSigma pass (tol, tol_mode: the threshold).
 hipError_t launch_outer(bool fp64, int n, int first, int max_cycles, const double* sigma, double* y0, double* y1,
                         const void* e0, const void* e1, void* r0, void* r1, double* partial, Ctl* ctl,
-                        hipStream_t s, bool finalize = true);
+                        hipStream_t s, bool finalize = true, const double* spart = nullptr, double tol = 0.0,
+                        int tol_mode = 0);
 // The stop decision of an outer residual: its partials (nb workgroups,
 // max then sum) on a fine mesh of n3 points, with the cycle cap.
 struct Decide {

@@ -353,6 +353,11 @@ struct Outer {
     T *r0, *r1;
     double* partial;
     Ctl* ctl;
+    // first residual of a single system: sigma's partials (null: the
+    // control block already holds the step's mean, FinSigma)
+    const double* spart;
+    int tol_mode;
+    double tol;
   };
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G);
@@ -368,11 +373,36 @@ __device__ void Outer<T>::run(const Args& A, Grid G) {
   double* __restrict__ partial = A.partial;
   Ctl* ctl = A.ctl;
   __shared__ double sh[kBlock / 64];
-  if (ctl->done) return;
-  const int c = first ? 0 : ctl->cycles + 1;
+  __shared__ double s_mean;
   const CsGeo g(n);
   const int n3 = n * n * n, msk = n - 1;
-  const double mean_sigma = ctl->mean_sigma;
+  double mean_sigma;
+  if (first && A.spart) {
+    // FinSigma's reduction in every workgroup (same split and tree, so the
+    // same mean); the first workgroup opens the step's solve in the control
+    // block
+    const int snb = G.g;
+    const double tot = reduce_partials_sum(A.spart, snb, sh);
+    const double mx = reduce_partials_max(A.spart + snb, snb, sh);
+    if (threadIdx.x == 0) {
+      s_mean = tot / (double)n3;
+      if (G.b == 0) {
+        ctl->mean_sigma = s_mean;
+        ctl->norm_qs = mx;
+        ctl->thresh = A.tol_mode == 0 ? A.tol * mx : A.tol;
+        ctl->done = 0;
+        ctl->cycles = 0;
+        ctl->status = 0;
+        ctl->final_buf = 0;
+      }
+    }
+    __syncthreads();
+    mean_sigma = s_mean;
+  } else {
+    if (ctl->done) return;
+    mean_sigma = ctl->mean_sigma;
+  }
+  const int c = first ? 0 : ctl->cycles + 1;
   double rmax = 0.0, ysum = 0.0;
   // Correction e at four consecutive points x = i0 .. i0+3 of row (j, k):
   // their colours alternate, so each colour array holds two of them side
@@ -2079,14 +2109,15 @@ hipError_t launch_sigma(int n, double h, const double* qs, const double* phi0, c
 
 hipError_t launch_outer(bool fp64, int n, int first, int max_cycles, const double* sigma, double* y0, double* y1,
                         const void* e0, const void* e1, void* r0, void* r1, double* partial, Ctl* ctl,
-                        hipStream_t s, bool finalize) {
-  const int n3 = n * n * n, nb = red_blocks(n3 / 4);   // four points per thread
+                        hipStream_t s, bool finalize, const double* spart, double tol, int tol_mode) {
+  const int n3 = n * n * n, nb = red_blocks(n3 / 4);   // four points per thread (sigma's grid too)
+  if (!first) spart = nullptr;
   if (fp64)
     P3MZ_LAUNCH(go<Outer<double>>({n, first, sigma, y0, y1, (const double*)e0, (const double*)e1, (double*)r0,
-                                   (double*)r1, partial, ctl}, nb, 0, s));
+                                   (double*)r1, partial, ctl, spart, tol_mode, tol}, nb, 0, s));
   else
     P3MZ_LAUNCH(go<Outer<float>>({n, first, sigma, y0, y1, (const float*)e0, (const float*)e1, (float*)r0,
-                                  (float*)r1, partial, ctl}, nb, 0, s));
+                                  (float*)r1, partial, ctl, spart, tol_mode, tol}, nb, 0, s));
   if (!finalize) return hipSuccess;
   return go<FinOuter>({max_cycles, nb, n3, partial, ctl}, 1, 0, s);
 }
