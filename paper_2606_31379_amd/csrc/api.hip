@@ -595,11 +595,13 @@ p3mz_status enq_post1(p3mz_ctx* c, double* force, hipStream_t s) {
   const Plan& pl = c->pl;
   const int n = pl.n, na = (int)c->n_atoms;
   const double N3 = (double)c->n3;
-  if (!g_recorder) P3MZ_HIP_TRY(launch_outer_decide(n, c->P.max_cycles, c->d_partial, c->d_ctl, s));
+  // a single system's last stop decision is made by every workgroup of the
+  // field update (a batch made it right after the residual)
+  const Decide d{c->d_partial, red_blocks((int64_t)c->n3 / 4), (int)c->n3, c->P.max_cycles};
   rec_key(5000);
   kt_begin(KT_PHI, 0, s);
   P3MZ_HIP_TRY(launch_phi_update(n, pl.h, c->d_phi[0], c->d_phi[1], c->d_y[0], c->d_y[1], c->d_yh[0], c->d_yh[1],
-                                 c->d_yh[2], c->d_phi32, c->d_ctl, s));
+                                 c->d_yh[2], c->d_phi32, c->d_ctl, s, g_recorder ? nullptr : &d));
   kt_end(KT_PHI, 0, 40.0 * N3 + (c->fp64 ? 0.0 : 4.0 * N3), s);
   stage(c, 2, s);
   rec_key(5001);

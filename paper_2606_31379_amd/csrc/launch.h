@@ -134,9 +134,11 @@ hipError_t launch_vcycle(bool fp64, const LevelBufs* lv, int levels, int tail, i
 hipError_t launch_vcycle_kernel(bool fp64, int kid, const LevelBufs* lv, int levels, int tail, int nu1, int nu2,
                                 const double* green, Ctl* ctl, hipStream_t s, double* bytes);
 // phi update and history push: phi^{k+1} = phi_p - (4pi/h)(y - mean y);
-// buffers selected on the device.
+// buffers selected on the device.  With `decide`, every workgroup first makes
+// the pending stop decision of the last outer residual (the first records it).
 hipError_t launch_phi_update(int n, double h, double* phi0, double* phi1, const double* ya, const double* yb,
-                             double* yh0, double* yh1, double* yh2, float* phi32, Ctl* ctl, hipStream_t s);
+                             double* yh0, double* yh1, double* yh2, float* phi32, Ctl* ctl, hipStream_t s,
+                             const Decide* decide = nullptr);
 // End-of-step rotation of the history on the device.
 hipError_t launch_advance(Ctl* ctl, hipStream_t s);
 // Layout conversions for inspection and the stand-alone V-cycle.

@@ -489,42 +489,91 @@ __device__ void Outer<T>::run(const Args& A, Grid G) {
   }
 }
 
-// The stop decision of the pending outer residual, by one whole workgroup
-// (1024 threads): residual of cycle c (max norm), running mean of y, cycle
-// count, which buffer holds y, done/status.  The partials are read while the
-// pending mark is still in flight (both reductions in one pass; fixed split
-// and tree, so deterministic).  Returns, in every thread, whether the solve
-// is done after it.  sh: 2 * blockDim.x / 64 doubles; flag: one int.
-__device__ __forceinline__ int outer_decide(Ctl* ctl, const double* __restrict__ partial, int nb, int n3,
-                                            int max_cycles, double* sh, int* flag) {
+// The stop decision's two reductions over the outer residual's partials
+// (max of the first nb, sum of the next nb) with the split and tree of a
+// 1024-thread workgroup: virtual thread v folds partials v, v + 1024, ...,
+// each 64-lane group reduces by butterfly, and the 16 group results are
+// combined in order.  Any workgroup of a power-of-two multiple of 64 threads
+// computes it, so every place the decision is made gives the same bits.
+// sh: 32 doubles.  Results valid in thread 0.
+__device__ __forceinline__ void decide_reduce(const double* __restrict__ partial, int nb, double* sh, double* res,
+                                              double* ys) {
+  constexpr int kV = 1024;
+  const int nt = blockDim.x, lane = threadIdx.x & 63;
+  for (int v0 = 0; v0 < kV; v0 += nt) {
+    const int v = v0 + threadIdx.x;
+    double m = 0.0, s = 0.0;
+    for (int i = v; i < nb; i += kV) {
+      m = fmax(m, partial[i]);
+      s += partial[nb + i];
+    }
+    m = wave_max(m);
+    s = wave_sum(s);
+    if (lane == 0) {
+      sh[v >> 6] = m;
+      sh[16 + (v >> 6)] = s;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < 16; i++) {
+      a = fmax(a, sh[i]);
+      b += sh[16 + i];
+    }
+    *res = a;
+    *ys = b;
+  }
+}
+
+// The state the field update needs from the stop decision.
+struct DecideOut {
+  int done, final_buf;
+  double mean_y;
+};
+
+// The stop decision of the pending outer residual: residual of cycle c (max
+// norm), running mean of y, cycle count, which buffer holds y, done/status.
+// The partials are read while the pending mark is still in flight.  Every
+// thread of the workgroup gets the outcome in *out (shared); only a writer
+// workgroup records it in the control block, and clears the pending mark if
+// `clear`.  A launch whose workgroups all decide (the field update) must not
+// clear it: a workgroup that started later would see no decision pending and
+// take fields the writer may not have stored yet; the decision is idempotent,
+// so a later decision point may repeat it.  With nothing pending the outcome
+// is the control block's current state.
+__device__ __forceinline__ void outer_decide(Ctl* ctl, const double* __restrict__ partial, int nb, int n3,
+                                             int max_cycles, bool writer, bool clear, double* sh, DecideOut* out) {
   const int pend = ctl->pending;
   double res = 0.0, ys = 0.0;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-    res = fmax(res, partial[i]);
-    ys += partial[nb + i];
-  }
-  block_max_sum(&res, &ys, sh);
+  decide_reduce(partial, nb, sh, &res, &ys);
   if (threadIdx.x == 0) {
-    int done = ctl->done;
     if (pend) {
       const int c = pend - 1;
-      ctl->res_hist[c] = res;
-      ctl->mean_y = ys / (double)n3;
-      ctl->cycles = c;
-      ctl->final_buf = c & 1;
+      int done = ctl->done;
+      const double mean_y = ys / (double)n3;
+      int status = 0;
       if (res <= ctl->thresh) {
         done = 1;
       } else if (c >= max_cycles) {
         done = 1;
-        ctl->status = 1;
+        status = 1;
       }
-      ctl->done = done;
-      ctl->pending = 0;
+      if (writer) {
+        ctl->res_hist[c] = res;
+        ctl->mean_y = mean_y;
+        ctl->cycles = c;
+        ctl->final_buf = c & 1;
+        if (status) ctl->status = 1;
+        ctl->done = done;
+        if (clear) ctl->pending = 0;
+      }
+      *out = DecideOut{done, c & 1, mean_y};
+    } else {
+      *out = DecideOut{ctl->done, ctl->final_buf, ctl->mean_y};
     }
-    *flag = done;
   }
   __syncthreads();
-  return *flag;
 }
 
 // The stop decision as a launch of its own (after the first residual, and
@@ -539,9 +588,9 @@ struct FinOuter {
   __device__ static void run(const Args& A, Grid G);
 };
 __device__ void FinOuter::run(const Args& A, Grid) {
-  __shared__ double sh[2 * kThreads / 64];
-  __shared__ int flag;
-  (void)outer_decide(A.ctl, A.partial, A.nb, A.n3, A.max_cycles, sh, &flag);
+  __shared__ double sh[32];
+  __shared__ DecideOut out;
+  outer_decide(A.ctl, A.partial, A.nb, A.n3, A.max_cycles, true, true, sh, &out);
 }
 
 // ---------------------------------------------------------------------------
@@ -1562,9 +1611,10 @@ __device__ __forceinline__ void tail_run(const typename Tail<T>::Args& A, int do
   }
   if (A.partial) {
     // the pending stop decision, its partials loaded alongside the level data
-    __shared__ double sh[2 * Tail<T>::kThreads / 64];
-    __shared__ int flag;
-    done = outer_decide(A.ctl, A.partial, A.nb, A.n3, A.max_cycles, sh, &flag);
+    __shared__ double sh[32];
+    __shared__ DecideOut out;
+    outer_decide(A.ctl, A.partial, A.nb, A.n3, A.max_cycles, true, true, sh, &out);
+    done = out.done;
   }
   if (done) return;
   __syncthreads();
@@ -1650,7 +1700,11 @@ struct PhiUpdate {
     const double *ya, *yb;
     double *yh0, *yh1, *yh2;
     float* phi32;
-    const Ctl* ctl;
+    Ctl* ctl;
+    // the pending stop decision of the last outer residual, made by every
+    // workgroup (the first records it); null: already made
+    const double* dpart;
+    int dnb, dn3, max_cycles;
   };
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G);
@@ -1666,14 +1720,28 @@ __device__ void PhiUpdate::run(const Args& A, Grid G) {
   double* __restrict__ yh1 = A.yh1;
   double* __restrict__ yh2 = A.yh2;
   float* __restrict__ phi32 = A.phi32;
-  const Ctl* ctl = A.ctl;
+  Ctl* ctl = A.ctl;
   const int t = G.b * kBlock + threadIdx.x;
-  if (t >= n3 || !ctl->done) return;   // enqueued ahead of the convergence check
+  int done, final_buf;
+  double mean_y;
+  if (A.dpart) {
+    __shared__ double sh[32];
+    __shared__ DecideOut out;
+    outer_decide(ctl, A.dpart, A.dnb, A.dn3, A.max_cycles, G.b == 0, false, sh, &out);
+    done = out.done;
+    final_buf = out.final_buf;
+    mean_y = out.mean_y;
+  } else {
+    done = ctl->done;
+    final_buf = ctl->final_buf;
+    mean_y = ctl->mean_y;
+  }
+  if (t >= n3 || !done) return;   // enqueued ahead of the convergence check
   const int cold = ctl->cold;
   double* pk = ctl->k_idx ? phi1 : phi0;
   double* pkm1 = ctl->k_idx ? phi0 : phi1;
-  const double* ysrc = ctl->final_buf ? yb : ya;
-  const double y = ysrc[t] - ctl->mean_y;
+  const double* ysrc = final_buf ? yb : ya;
+  const double y = ysrc[t] - mean_y;
   const double phi_p = cold ? 0.0 : 2.0 * pk[t] - pkm1[t];
   const double phi = phi_p - 4.0 * kPi / h * y;
   if (cold) {
@@ -2173,9 +2241,12 @@ hipError_t fused_configure() {
 }
 
 hipError_t launch_phi_update(int n, double h, double* phi0, double* phi1, const double* ya, const double* yb,
-                             double* yh0, double* yh1, double* yh2, float* phi32, Ctl* ctl, hipStream_t s) {
+                             double* yh0, double* yh1, double* yh2, float* phi32, Ctl* ctl, hipStream_t s,
+                             const Decide* d) {
   const int n3 = n * n * n;
-  return go<PhiUpdate>({n3, h, phi0, phi1, ya, yb, yh0, yh1, yh2, phi32, ctl}, blocks_for(n3, kBlock), 0, s);
+  return go<PhiUpdate>({n3, h, phi0, phi1, ya, yb, yh0, yh1, yh2, phi32, ctl, d ? d->partial : nullptr,
+                        d ? d->nb : 0, d ? d->n3 : 0, d ? d->max_cycles : 0},
+                       blocks_for(n3, kBlock), 0, s);
 }
 
 hipError_t launch_advance(Ctl* ctl, hipStream_t s) { return go<Advance>({ctl}, 1, 0, s); }
