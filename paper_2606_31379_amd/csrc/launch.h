@@ -21,11 +21,6 @@ void kt_end(int id, int level, double bytes, hipStream_t s);
 // arrival rank inside the key's bin.
 hipError_t launch_bin_tiles(int n_atoms, const double* pos, double box, int n, int p, int tile, int ntx, int* key,
                            int* slot, int* count, Ctl* ctl, hipStream_t s);
-// Atom records in bin order (position i holds atom perm[i]): rb[i] = {stencil
-// origin x, y, z, atom index} (int4); rw[c * n_atoms + i] = component c of
-// {charge, FP64 B-spline weights x | y | z}.
-hipError_t launch_pack_atoms(int n_atoms, const double* pos, const double* qa, double box, int n, int p,
-                             const int* perm, void* rb, double* rw, hipStream_t s);
 // Cell key of each atom for the short-range cell list (nc cells per edge).
 hipError_t launch_bin_cells(int n_atoms, const double* pos, double box, int nc, int* key, int* slot,
                             int* count, Ctl* ctl, hipStream_t s);
@@ -39,9 +34,10 @@ hipError_t launch_scatter(int n_atoms, const int* key, const int* slot, const in
 // Sort every bin's atom list by atom index (makes all later sums deterministic).
 hipError_t launch_sort_bins(int nbins, const int* start, const int* perm_raw, int* perm, Ctl* ctl,
                             hipStream_t s);
-// SortBins and PackAtoms in one launch: each bin's atoms in ascending index,
-// their records (rb, rw as in launch_pack_atoms) written at the sorted
-// positions.
+// Sort every bin's atom list by atom index and write each atom's records at
+// its sorted position i: rb[i] = {stencil origin x, y, z, atom index} (int4);
+// rw[c * n_atoms + i] = component c of {charge, FP64 B-spline weights
+// x | y | z}.
 hipError_t launch_sort_pack(int nbins, const int* start, const int* perm_raw, int n_atoms, const double* pos,
                             const double* qa, double box, int n, int p, void* rb, double* rw, hipStream_t s);
 // Owner-computes spread: q (natural layout, precision T) from the binned atoms.
@@ -103,10 +99,6 @@ struct Decide {
   const double* partial;
   int nb, n3, max_cycles;
 };
-// The stop decision alone (one workgroup): records res_hist, the mean of y,
-// the cycle count and done/status for the outer residual marked pending in
-// the control block; nothing if none is.
-hipError_t launch_outer_decide(int n, int max_cycles, const double* partial, Ctl* ctl, hipStream_t s);
 struct LevelBufs {
   int n;
   void* e0; void* e1;   // colour-split correction

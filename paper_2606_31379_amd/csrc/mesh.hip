@@ -576,8 +576,8 @@ __device__ __forceinline__ void outer_decide(Ctl* ctl, const double* __restrict_
   __syncthreads();
 }
 
-// The stop decision as a launch of its own (after the first residual, and
-// ahead of the field update for the last cycle's residual).
+// The stop decision as a launch of its own (batched systems decide right
+// after every residual).
 struct FinOuter {
   struct Args {
     int max_cycles, nb, n3;
@@ -2187,11 +2187,6 @@ hipError_t launch_outer(bool fp64, int n, int first, int max_cycles, const doubl
     P3MZ_LAUNCH(go<Outer<float>>({n, first, sigma, y0, y1, (const float*)e0, (const float*)e1, (float*)r0,
                                   (float*)r1, partial, ctl, spart, tol_mode, tol}, nb, 0, s));
   if (!finalize) return hipSuccess;
-  return go<FinOuter>({max_cycles, nb, n3, partial, ctl}, 1, 0, s);
-}
-
-hipError_t launch_outer_decide(int n, int max_cycles, const double* partial, Ctl* ctl, hipStream_t s) {
-  const int n3 = n * n * n, nb = red_blocks(n3 / 4);
   return go<FinOuter>({max_cycles, nb, n3, partial, ctl}, 1, 0, s);
 }
 

@@ -67,23 +67,11 @@ __device__ void BinTiles::run(const Args& A, Grid G) {
   A.slot[a] = atomicAdd(&A.count[k], 1);
 }
 
-// Atom records in bin order, written after the bin sort: stencil origin and
+// Atom records in bin order, written by the bin sort: stencil origin and
 // atom index (rb), then charge and the 3p FP64 weights x | y | z (rw, one
 // row of n_atoms values per component: rw[c * n_atoms + i]), so the tile
 // kernels read their atoms' records coalesced instead of gathering them by
 // atom index.
-struct PackAtoms {
-  struct Args {
-    int n_atoms, n, p;
-    double box;
-    const double *pos, *qa;
-    const int* perm;
-    int4* rb;
-    double* rw;
-  };
-  static constexpr int kThreads = kBlock;
-  __device__ static void run(const Args& A, Grid G);
-};
 // The records of atom a at bin-order position i.
 __device__ __forceinline__ void pack_atom(int i, int a, int n_atoms, int n, int p, double box, const double* pos,
                                           const double* qa, int4* rb, double* rw) {
@@ -105,11 +93,6 @@ __device__ __forceinline__ void pack_atom(int i, int a, int n_atoms, int n, int 
     for (int j = 0; j < p; j++) rec[(1 + d * p + j) * na] = wl[j];
   }
   rb[i] = make_int4(f3[0], f3[1], f3[2], a);
-}
-__device__ void PackAtoms::run(const Args& A, Grid G) {
-  const int i = G.b * kBlock + threadIdx.x;
-  if (i >= A.n_atoms) return;
-  pack_atom(i, A.perm[i], A.n_atoms, A.n, A.p, A.box, A.pos, A.qa, A.rb, A.rw);
 }
 
 struct BinCells {
@@ -277,7 +260,7 @@ struct Scatter {
 // One wave per bin: rank of each entry = number of smaller atom indices in
 // the bin (indices are distinct), so perm[start + rank] is the sorted list.
 // With rb set, the sorted entry is not stored: the atom's records are
-// written at its sorted position instead (PackAtoms in the same launch).
+// written at its sorted position instead (the records described above).
 struct SortBins {
   struct Args {
     int nbins;
@@ -872,11 +855,6 @@ inline int blocks_for(int64_t n, int b) { return (int)((n + b - 1) / b); }
 hipError_t launch_bin_tiles(int n_atoms, const double* pos, double box, int n, int p, int tile, int ntx, int* key,
                            int* slot, int* count, Ctl* ctl, hipStream_t s) {
   return go<BinTiles>({n_atoms, n, p, tile, ntx, box, pos, key, slot, count, ctl}, blocks_for(n_atoms, kBlock), 0, s);
-}
-
-hipError_t launch_pack_atoms(int n_atoms, const double* pos, const double* qa, double box, int n, int p,
-                             const int* perm, void* rb, double* rw, hipStream_t s) {
-  return go<PackAtoms>({n_atoms, n, p, box, pos, qa, perm, (int4*)rb, rw}, blocks_for(n_atoms, kBlock), 0, s);
 }
 
 hipError_t launch_bin_cells(int n_atoms, const double* pos, double box, int nc, int* key, int* slot,
