@@ -517,7 +517,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default (2,2) V-cycle schedule")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(domain decomposition is design-only); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
