@@ -515,6 +515,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--modes", default="fp64,mixed", help="precision modes to run (the headline is mixed)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default (2,2) V-cycle schedule")
+    ap.add_argument("--predictor", type=int, default=None,
+                    help="multiplier predictor order 0..3 (0: no warm start, the plain real-space P3M solve; "
+                         "default: the workload's)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -532,6 +535,9 @@ def main():
     if args.workload == "nacl-batch64":
         return main_batch(args, torch, P, configs.nacl_batch_64())
     w = configs.WORKLOADS[args.workload]()
+    if args.predictor is not None:
+        import dataclasses
+        w = dataclasses.replace(w, predictor=args.predictor)
     log(f"workload {w.name}: generating inputs")
     system = w.system(progress=lambda msg: log(f"[inputs] {msg}"))
     log(f"atoms {system.n} box {system.box} mesh {w.mesh}^3 order {w.order} tol {w.tol}")
