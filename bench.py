@@ -138,12 +138,14 @@ def autotune_schedule(torch, P, w, system, precision, warmup, n_frames=8):
         P.p3mz_destroy(ctx)
 
 
-def run_mode(torch, P, w, system, precision, warmup, steps, kernel, schedule=None):
+def run_mode(torch, P, w, system, precision, warmup, steps, kernel, schedule=None, skin=None):
     """Warm up, pick the dominant kernel family, then time `steps` MD steps."""
     import numpy as np
     dev = torch.device("cuda")
     ctx = P.p3mz_create(make_params(P, w, precision), system.charges)
     try:
+        if skin is not None:
+            P.p3mz_set_neighbor_list(ctx, skin)
         if schedule:
             P.p3mz_set_schedule(ctx, schedule["nu_pre"], schedule["nu_post"], schedule["smooth_tile"])
         pos = torch.from_numpy(np.ascontiguousarray(system.pos)).to(dev)
@@ -181,6 +183,7 @@ def run_mode(torch, P, w, system, precision, warmup, steps, kernel, schedule=Non
             + ", ".join(f"{k}={v:.4f}" for k, v in sorted(shares.items(), key=lambda x: -x[1])))
         P.p3mz_set_kernel_timer(ctx, -1)      # the headline region runs with captured graphs
         mesh_ms_tot, sr_ms_tot, graphs = 0.0, 0.0, 1
+        builds0 = P.p3mz_get_neighbor_stats(ctx)[0]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(steps):
@@ -191,6 +194,7 @@ def run_mode(torch, P, w, system, precision, warmup, steps, kernel, schedule=Non
             graphs &= st.graphs
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        builds, over, cap = P.p3mz_get_neighbor_stats(ctx)
         cycles = clog.cpu().numpy()[:steps]
         energies = elog.cpu().numpy()[:steps]
         # Roofline: the dominant family's finest-level kernel launched back to
@@ -213,6 +217,7 @@ def run_mode(torch, P, w, system, precision, warmup, steps, kernel, schedule=Non
             mesh_ms_per_step=mesh_ms,
             md_ms_per_step=wall * 1e3 / steps,
             short_range_ms_per_step=sr_ms_tot / steps, graphs=bool(graphs),
+            neighbor_lists=dict(capacity=cap, builds_per_step=(builds - builds0) / steps, over_capacity_atoms=over),
             vcycles_per_step=float(cycles.mean()), vcycles_min=int(cycles.min()), vcycles_max=int(cycles.max()),
             energy_drift_per_step=float(np.polyfit(np.arange(steps), energies[:, 5], 1)[0]) if steps > 2 else None,
             kernel_ms_per_step=shares, dominant=dominant,
@@ -515,6 +520,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--modes", default="fp64,mixed", help="precision modes to run (the headline is mixed)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default (2,2) V-cycle schedule")
+    ap.add_argument("--skin", type=float, default=None,
+                    help="neighbour-list skin in box units (0: scan the cells every step; default: 0.1 r_cut)")
     ap.add_argument("--predictor", type=int, default=None,
                     help="multiplier predictor order 0..3 (0: no warm start, the plain real-space P3M solve; "
                          "default: the workload's)")
@@ -558,7 +565,8 @@ def main():
             schedules[name] = {k: tune[name][k] for k in ("nu_pre", "nu_post", "smooth_tile")}
             log(f"[{name}] autotune: {json.dumps({k: v for k, v in tune[name].items() if k != 'candidates'})}")
         log(f"[{name}] warmup {args.warmup}, timed {args.steps}")
-        res[name] = run_mode(torch, P, w, system, precision, args.warmup, args.steps, args.kernel, schedules[name])
+        res[name] = run_mode(torch, P, w, system, precision, args.warmup, args.steps, args.kernel, schedules[name],
+                             args.skin)
         log(f"[{name}] {json.dumps({k: v for k, v in res[name].items() if k != 'kernel_ms_per_step'})}")
     parity, baseline = None, None
     if not args.no_cpu_baseline:

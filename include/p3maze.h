@@ -249,6 +249,28 @@ p3mz_status p3mz_set_schedule(p3mz_ctx* ctx, int32_t nu_pre, int32_t nu_post, in
  * device; graphs are recaptured.  Errors: INVALID_ARG for max_edge < 0. */
 p3mz_status p3mz_set_fused_levels(p3mz_ctx* ctx, int32_t max_edge);
 
+/* Short-range pair sums (Eq. (6) with the exclusion correction of Eq. (20),
+ * and the MD pair terms) over Verlet neighbour lists with a skin: each list
+ * holds every atom within r_cut + skin at its build; a build is triggered on
+ * the device when some atom has moved more than skin/2 (minimum image) since
+ * the last one, so every pair within r_cut is always in the lists and the
+ * results equal those of a fresh cell scan up to summation order.  The cell
+ * list is then made of cells at least r_cut + skin wide.  skin in [0, r_cut]
+ * (0: no lists, the cells are scanned every step); capacity = entries per
+ * atom, 0 for 30 % above the count expected at the mean density plus 64
+ * (rounded up to 64; an atom with more neighbours falls back to the cell
+ * scan).  The lists take n_atoms * capacity * 4 bytes of device memory.
+ * Default: skin 0.1 r_cut, automatic capacity; systems of a batch scan the
+ * cells.  Synchronises the device; graphs are recaptured; the next step
+ * builds the lists.  Errors: INVALID_ARG for skin outside [0, r_cut] or
+ * capacity < 0; OUT_OF_MEMORY. */
+p3mz_status p3mz_set_neighbor_list(p3mz_ctx* ctx, double skin, int32_t capacity);
+
+/* Neighbour-list builds so far, atoms found over capacity summed over those
+ * builds, and the capacity (0: no lists), as of the last completed step. */
+p3mz_status p3mz_get_neighbor_stats(const p3mz_ctx* ctx, int64_t* builds, int64_t* over_capacity,
+                                    int32_t* capacity);
+
 typedef struct {
   int32_t nu_pre, nu_post;   /* chosen schedule                                        */
   int32_t smooth_tile;       /* chosen smoothing launch shape                          */

@@ -188,6 +188,13 @@ struct p3mz_ctx {
   int ntx = 0, nbins = 0;
   int *d_count = nullptr, *d_start = nullptr, *d_bsum = nullptr;
   int nc = 1, ncells = 1;
+  int ncells_max = 1;     // cell arrays are sized for the cells of edge r_cut
+  // neighbour lists (skin 0: none, the pair kernels scan the cells every step)
+  double nbr_skin = 0.0;
+  int nbr_cap = 0;
+  int* d_nbr = nullptr;     // [n_atoms][nbr_cap] entries
+  int* d_nlist = nullptr;   // entries per atom
+  double* d_ref = nullptr;  // {x, y, z, q} of each atom at the last build (cell order)
   int *d_ckey = nullptr, *d_cslot = nullptr, *d_ccount = nullptr, *d_cstart = nullptr, *d_cperm_raw = nullptr,
       *d_cperm = nullptr;
   double* d_spos = nullptr;   // cell-ordered {x, y, z, q} for the pair kernels
@@ -251,6 +258,15 @@ struct p3mz_ctx {
     allocs.push_back(v);
     *p = v;
     return P3MZ_OK;
+  }
+  void release(void* p) {
+    if (!p) return;
+    for (size_t k = 0; k < allocs.size(); k++)
+      if (allocs[k] == p) {
+        (void)hipFree(p);
+        allocs.erase(allocs.begin() + (long)k);
+        return;
+      }
   }
   void drop_graphs() {
     g_pre.reset();
@@ -388,6 +404,53 @@ p3mz_status tune_store(const std::string& key, const TuneEntry& t) {
   return P3MZ_OK;
 }
 
+// Cells per box edge for a cell list of cells at least `width` wide (fewer
+// than 3: one cell, every pair is a candidate).
+int cells_per_edge(double box, double width) {
+  int nc = (int)floor(box / width);
+  if (nc < 3) nc = 1;
+  if (nc > 256) nc = 256;
+  return nc;
+}
+
+// Default skin of the neighbour lists, as a fraction of r_cut.
+constexpr double kSkinFraction = 0.1;
+
+// Neighbour lists of skin `skin` (0: none) and `cap` entries per atom (0:
+// from the mean density, 30 % above the expected count plus 64).  The cell
+// list is rebuilt for cells at least r_cut + skin wide; the first step
+// after this builds the lists.
+p3mz_status nbr_configure(p3mz_ctx* c, double skin, int cap) {
+  c->release(c->d_nbr);
+  c->release(c->d_nlist);
+  c->release(c->d_ref);
+  c->d_nbr = c->d_nlist = nullptr;
+  c->d_ref = nullptr;
+  c->nbr_skin = skin;
+  c->nbr_cap = 0;
+  c->drop_graphs();
+  const double rl = c->P.r_cut + skin;
+  c->nc = cells_per_edge(c->P.box, rl);
+  c->ncells = c->nc * c->nc * c->nc;
+  if (c->ncells > c->ncells_max) return fail(P3MZ_ERR_STATE, "cell list larger than allocated");
+  if (skin <= 0.0) return P3MZ_OK;
+  const int64_t na = c->n_atoms;
+  if (cap <= 0) {
+    const double expect = 4.0 / 3.0 * kPi * rl * rl * rl * (double)na / (c->P.box * c->P.box * c->P.box);
+    cap = (int)std::min<double>(1.3 * expect + 64.0, (double)(1 << 24));
+  }
+  cap = (int)std::min<int64_t>((cap + 63) / 64 * 64, (std::max<int64_t>(na - 1, 1) + 63) / 64 * 64);
+  c->nbr_cap = cap;
+  P3MZ_TRY(c->alloc(&c->d_nbr, (size_t)na * cap));
+  P3MZ_TRY(c->alloc(&c->d_nlist, (size_t)na));
+  P3MZ_TRY(c->alloc(&c->d_ref, 4 * (size_t)na));
+  // NaN reference positions: the first check flags a build
+  P3MZ_HIP_TRY(hipMemset(c->d_ref, 0xff, sizeof(double) * 4 * (size_t)na));
+  const int one = 1;
+  P3MZ_HIP_TRY(hipMemcpy(&c->d_ctl->nbr_stale, &one, sizeof(int), hipMemcpyHostToDevice));
+  return P3MZ_OK;
+}
+
 p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   const Plan& pl = c->pl;
   const int n = pl.n;
@@ -435,14 +498,19 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   P3MZ_TRY(c->alloc(&c->d_count, c->nbins));
   P3MZ_TRY(c->alloc(&c->d_start, c->nbins + 1));
   P3MZ_HIP_TRY(hipMemset(c->d_count, 0, sizeof(int) * c->nbins));
-  c->nc = (int)floor(c->P.box / c->P.r_cut);
-  if (c->nc < 3) c->nc = 1;
-  if (c->nc > 256) c->nc = 256;
-  c->ncells = c->nc * c->nc * c->nc;
+  c->nc = cells_per_edge(c->P.box, c->P.r_cut);
+  c->ncells = c->ncells_max = c->nc * c->nc * c->nc;
   P3MZ_TRY(c->alloc(&c->d_ckey, na));
   P3MZ_TRY(c->alloc(&c->d_cslot, na));
   P3MZ_TRY(c->alloc(&c->d_cperm_raw, na));
   P3MZ_TRY(c->alloc(&c->d_cperm, na));
+  {
+    // a valid permutation before the first cell sort (the neighbour check
+    // reads the order of the last build)
+    std::vector<int> id((size_t)na);
+    for (int64_t a = 0; a < na; a++) id[(size_t)a] = (int)a;
+    P3MZ_HIP_TRY(hipMemcpy(c->d_cperm, id.data(), sizeof(int) * (size_t)na, hipMemcpyHostToDevice));
+  }
   P3MZ_TRY(c->alloc(&c->d_spos, 4 * na));
   {
     std::vector<double> tab;
@@ -500,6 +568,7 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   P3MZ_HIP_TRY(tail_configure(c->fp64, n >> pl.tail, pl.levels - pl.tail, &lds));
   P3MZ_HIP_TRY(smooth_configure());
   P3MZ_HIP_TRY(fused_configure());
+  P3MZ_TRY(nbr_configure(c, kSkinFraction * c->P.r_cut, 0));
   P3MZ_HIP_TRY(hipDeviceSynchronize());
   return P3MZ_OK;
 }
@@ -616,23 +685,33 @@ p3mz_status enq_post1(p3mz_ctx* c, double* force, hipStream_t s) {
 }
 
 // short-range pairs on a fresh cell list, energies, history rotation
+// With neighbour lists the cell list and the lists are rebuilt only on the
+// steps the check flags (the rebuild launches test the flag on the device).
 p3mz_status enq_post2(p3mz_ctx* c, const double* pos, double* force, double* energy, hipStream_t s) {
   const int na = (int)c->n_atoms;
+  const bool nbr = c->d_nbr != nullptr;
+  const int* gate = nbr ? &c->d_ctl->nbr_stale : nullptr;
+  if (nbr)
+    P3MZ_HIP_TRY(launch_nbr_check(na, c->P.box, c->nbr_skin, c->d_cperm, pos, c->d_qa, c->d_spos, c->d_ref, c->d_ctl,
+                                  s));
   rec_key(6000);
-  P3MZ_HIP_TRY(launch_bin_cells(na, pos, c->P.box, c->nc, c->d_ckey, c->d_cslot, c->d_ccount, c->d_ctl, s));
+  P3MZ_HIP_TRY(launch_bin_cells(na, pos, c->P.box, c->nc, c->d_ckey, c->d_cslot, c->d_ccount, c->d_ctl, s, gate));
   rec_key(6001);
-  P3MZ_HIP_TRY(launch_scan(c->ncells, c->d_ccount, c->d_cstart, c->d_bsum, s));
+  P3MZ_HIP_TRY(launch_scan(c->ncells, c->d_ccount, c->d_cstart, c->d_bsum, s, gate));
   rec_key(6002);
-  P3MZ_HIP_TRY(launch_scatter(na, c->d_ckey, c->d_cslot, c->d_cstart, c->d_cperm_raw, s));
+  P3MZ_HIP_TRY(launch_scatter(na, c->d_ckey, c->d_cslot, c->d_cstart, c->d_cperm_raw, s, gate));
   rec_key(6003);
-  P3MZ_HIP_TRY(launch_sort_bins(c->ncells, c->d_cstart, c->d_cperm_raw, c->d_cperm, c->d_ctl, s));
-  P3MZ_HIP_TRY(launch_cell_pack(na, c->d_cperm, pos, c->d_qa, c->d_spos, s));
+  P3MZ_HIP_TRY(launch_sort_bins(c->ncells, c->d_cstart, c->d_cperm_raw, c->d_cperm, c->d_ctl, s, gate));
+  P3MZ_HIP_TRY(launch_cell_pack(na, c->d_cperm, pos, c->d_qa, c->d_spos, s, gate));
+  if (nbr)
+    P3MZ_HIP_TRY(launch_nbr_build(na, c->P.box, c->P.r_cut + c->nbr_skin, c->nc, c->P.excl_group, c->nbr_cap,
+                                  c->d_cstart, c->d_cperm, c->d_spos, c->d_ref, c->d_nbr, c->d_nlist, c->d_ctl, s));
   rec_key(6004);
   kt_begin(KT_SR, 0, s);
   P3MZ_HIP_TRY(launch_sr(na, pos, c->d_qa, c->P.box, c->P.alpha, c->P.r_cut, c->P.coulomb_k, c->nc, c->P.excl_group,
                          c->d_cstart, c->d_cperm, c->d_spos, c->d_erfc, c->erfc_n, c->erfc_scale, force, c->e_self,
                          energy ? energy : c->d_energy,
-                         c->d_partial, c->d_ctl, s));
+                         c->d_partial, c->d_ctl, s, c->d_nbr, c->d_nlist, c->nbr_cap));
   kt_end(KT_SR, 0, (double)na * 56.0, s);
   rec_key(6005);
   P3MZ_HIP_TRY(launch_advance(c->d_ctl, s));
@@ -655,7 +734,8 @@ p3mz_status enq_md_post2(p3mz_ctx* c, const MdArgs& m, hipStream_t s) {
   // the cell list of the short-range pass is still valid for these positions
   rec_key(6100);
   P3MZ_HIP_TRY(launch_nonelec(na, m.pos, c->P.box, c->P.r_cut, m.model, m.p[0], m.p[1], m.p[2], m.p[3], m.p[4],
-                              m.p[5], c->nc, c->d_cstart, c->d_cperm, c->d_spos, c->d_md_force, c->d_partial, c->d_e_other, s));
+                              m.p[5], c->nc, c->d_cstart, c->d_cperm, c->d_spos, c->d_md_force, c->d_partial, c->d_e_other, s,
+                              c->d_nbr, c->d_nlist, c->nbr_cap));
   rec_key(6101);
   P3MZ_HIP_TRY(launch_kick_drift(na, m.pos, m.vel, c->d_md_force, m.mass, m.dt, m.f2a, 0, s));
   rec_key(6102);
@@ -1431,7 +1511,7 @@ p3mz_status p3mz_md_run(p3mz_ctx* ctx, double* pos_dev, double* vel_dev, const d
                        false, nullptr));
     P3MZ_HIP_TRY(launch_nonelec((int)ctx->n_atoms, pos_dev, ctx->P.box, ctx->P.r_cut, m.model, m.p[0], m.p[1], m.p[2],
                                 m.p[3], m.p[4], m.p[5], ctx->nc, ctx->d_cstart, ctx->d_cperm, ctx->d_spos, ctx->d_md_force,
-                                ctx->d_partial, ctx->d_e_other, s));
+                                ctx->d_partial, ctx->d_e_other, s, ctx->d_nbr, ctx->d_nlist, ctx->nbr_cap));
     P3MZ_TRY(finish(ctx, s));
     ctx->md_have_force = true;
   }
@@ -1567,6 +1647,23 @@ p3mz_status p3mz_set_fused_levels(p3mz_ctx* ctx, int32_t max_edge) {
     LevelBufs& b = ctx->lv[l];
     b.fty = b.ftz = (b.d0 && b.n <= max_edge) ? fused_tile(b.n) : 0;
   }
+  return P3MZ_OK;
+}
+
+p3mz_status p3mz_set_neighbor_list(p3mz_ctx* ctx, double skin, int32_t capacity) {
+  if (!ctx) return fail(P3MZ_ERR_INVALID_ARG, "ctx is NULL");
+  if (!(skin >= 0.0) || !(skin <= ctx->P.r_cut) || capacity < 0)
+    return fail(P3MZ_ERR_INVALID_ARG, "skin must be in [0, r_cut] and capacity >= 0");
+  P3MZ_HIP_TRY(hipDeviceSynchronize());
+  return nbr_configure(ctx, skin, capacity);
+}
+
+p3mz_status p3mz_get_neighbor_stats(const p3mz_ctx* ctx, int64_t* builds, int64_t* over_capacity,
+                                    int32_t* capacity) {
+  if (!ctx || !builds || !over_capacity || !capacity) return fail(P3MZ_ERR_INVALID_ARG, "NULL argument");
+  *builds = ctx->mirror.nbr_builds;
+  *over_capacity = ctx->mirror.nbr_over;
+  *capacity = ctx->nbr_cap;
   return P3MZ_OK;
 }
 
@@ -1719,6 +1816,12 @@ p3mz_status p3mz_batch_create(int32_t n_sys, const p3mz_params* per_sys, const i
   // launches; side by side with other systems' launches a batch is bound by
   // throughput instead, so batched systems keep one launch per sweep.
   for (p3mz_ctx* c : b->sys) {
+    // batched systems scan the cells every step (no neighbour lists)
+    const p3mz_status st = nbr_configure(c, 0.0, 0);
+    if (st != P3MZ_OK) {
+      delete b;
+      return st;
+    }
     Plan& pl = c->pl;
     pl.tail = 0;
     while ((pl.n >> pl.tail) > P3MZ_TAIL_MAX_BATCH) pl.tail++;

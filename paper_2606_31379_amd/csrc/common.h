@@ -32,7 +32,7 @@ struct Ctl {
   int predictor;         // requested predictor order
   int md_step;           // row of the MD energy log
   int pending;           // 1 + cycle of an outer residual whose stop decision is still to be made (0: none)
-  int pad1;
+  int nbr_stale;         // 1: the short-range neighbour list must be rebuilt this step
   long long steps;       // completed steps
   double thresh;         // residual threshold
   double norm_qs;        // max |q^s|
@@ -40,6 +40,9 @@ struct Ctl {
   double mean_y;         // mean of the current multiplier
   double e_lr, e_sr;
   double res_hist[P3MZ_MAX_CYCLES + 1];
+  long long nbr_builds;  // neighbour-list builds so far
+  int nbr_over;          // atoms whose neighbours exceeded the list capacity at the last build
+  int pad2;
 };
 
 // --- wave / block reductions (wave64) ------------------------------------

@@ -22,18 +22,20 @@ void kt_end(int id, int level, double bytes, hipStream_t s);
 hipError_t launch_bin_tiles(int n_atoms, const double* pos, double box, int n, int p, int tile, int ntx, int* key,
                            int* slot, int* count, Ctl* ctl, hipStream_t s);
 // Cell key of each atom for the short-range cell list (nc cells per edge).
+// gate (here and in the scan, scatter, sort and pack below): non-null makes
+// the launch do nothing unless *gate (the neighbour-list rebuild flag).
 hipError_t launch_bin_cells(int n_atoms, const double* pos, double box, int nc, int* key, int* slot,
-                            int* count, Ctl* ctl, hipStream_t s);
+                            int* count, Ctl* ctl, hipStream_t s, const int* gate = nullptr);
 // Exclusive scan of count[0..nbins) into start[0..nbins], zeroing count;
 // bsum needs scan_partials(nbins) ints.
 int scan_partials(int nbins);
-hipError_t launch_scan(int nbins, int* count, int* start, int* bsum, hipStream_t s);
+hipError_t launch_scan(int nbins, int* count, int* start, int* bsum, hipStream_t s, const int* gate = nullptr);
 // perm_raw[start[key[a]] + slot[a]] = a.
 hipError_t launch_scatter(int n_atoms, const int* key, const int* slot, const int* start, int* perm_raw,
-                          hipStream_t s);
+                          hipStream_t s, const int* gate = nullptr);
 // Sort every bin's atom list by atom index (makes all later sums deterministic).
 hipError_t launch_sort_bins(int nbins, const int* start, const int* perm_raw, int* perm, Ctl* ctl,
-                            hipStream_t s);
+                            hipStream_t s, const int* gate = nullptr);
 // Sort every bin's atom list by atom index and write each atom's records at
 // its sorted position i: rb[i] = {stencil origin x, y, z, atom index} (int4);
 // rw[c * n_atoms + i] = component c of {charge, FP64 B-spline weights
@@ -54,17 +56,31 @@ hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, int tile, int ntx
                          const int* start, const void* rb, const double* rw, const double* phi0, const double* phi1,
                          const float* phi32, double* force, double* partial, Ctl* ctl, hipStream_t s,
                          bool finalize = true);
-// Short-range erfc pairs on the cell list, exclusion correction, energy
+// Short-range erfc pairs (neighbour lists or the cell list), exclusion correction, energy
 // assembly into energy_out[4] (may be NULL).  force += F_sr.
 // spos[jj] = {x, y, z, q} of atom cperm[jj] (cell order), for the pair kernels.
 hipError_t launch_cell_pack(int n_atoms, const int* cperm, const double* pos, const double* qa, void* spos,
-                            hipStream_t s);
+                            hipStream_t s, const int* gate = nullptr);
+// Neighbour lists with a skin.  Check (every step): spos[jj] = the atom
+// cperm[jj] now (the order of the last build), and ctl->nbr_stale = 1 when
+// some atom has moved more than skin/2 from ref[jj] (double4).  Build (does
+// nothing unless ctl->nbr_stale): on a cell list of cells at least r_list
+// wide, list[wi * cap ..] = entries (cell-order index | flag bits) of every
+// atom within r_list of atom wi, nlist[wi] = their number (may exceed cap:
+// then the pair kernels scan the cells for wi), ref = spos.
+hipError_t launch_nbr_check(int n_atoms, double box, double skin, const int* cperm, const double* pos,
+                            const double* qa, void* spos, const void* ref, Ctl* ctl, hipStream_t s);
+hipError_t launch_nbr_build(int n_atoms, double box, double r_list, int nc, int excl_group, int cap,
+                            const int* cstart, const int* cperm, const void* spos, void* ref, int* list, int* nlist,
+                            Ctl* ctl, hipStream_t s);
 // erfc_tab: erfcx table for alpha r in [0, alpha r_cut] (erfc_n intervals,
-// erfc_scale intervals per unit).
+// erfc_scale intervals per unit).  list/nlist/cap: neighbour lists as built
+// by launch_nbr_build (null: every atom scans the cells).
 hipError_t launch_sr(int n_atoms, const double* pos, const double* qa, double box, double alpha,
                      double r_cut, double k_e, int nc, int excl_group, const int* cstart,
                      const int* cperm, const void* spos, const double* erfc_tab, int erfc_n, double erfc_scale,
-                     double* force, double e_self, double* energy_out, double* partial, Ctl* ctl, hipStream_t s);
+                     double* force, double e_self, double* energy_out, double* partial, Ctl* ctl, hipStream_t s,
+                     const int* list = nullptr, const int* nlist = nullptr, int cap = 0);
 
 // ---- mesh (mesh.hip) -----------------------------------------------------
 // Folded periodic smoothing filter along one axis: out = sum_m c[m] v[i+m-K],
@@ -152,7 +168,8 @@ hipError_t launch_kick_drift(int n_atoms, double* pos, double* vel, const double
 hipError_t launch_nonelec(int n_atoms, const double* pos, double box, double r_cut, int model,
                           double p0, double p1, double p2, double p3, double p4, double p5,
                           int nc, const int* cstart, const int* cperm, const void* spos, double* force,
-                          double* partial, double* e_out, hipStream_t s);
+                          double* partial, double* e_out, hipStream_t s, const int* list = nullptr,
+                          const int* nlist = nullptr, int cap = 0);
 // Kinetic energy and one row (ctl->md_step, then advanced) of the logs.
 hipError_t launch_kinetic_log(int n_atoms, const double* vel, const double* mass, double mv2e,
                               const double* energy4, const double* e_other, double* log_base,

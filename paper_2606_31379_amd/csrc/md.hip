@@ -41,111 +41,100 @@ __device__ __forceinline__ double mi(double d, double box, double inv_box) { ret
 
 // model 1: stand-in Born-Mayer repulsion between all pairs (shifted at r_cut);
 // model 2: flexible three-site water -- intermolecular O-O Lennard-Jones
-// (shifted at r_cut) plus harmonic O-H bonds and H-O-H angle.  One wave per
-// atom: lanes stride the neighbour cells' lists, lane 0 adds the bonded
-// terms of the atom's molecule that act on it (each atom's wave recomputes
-// them; no atomics), a fixed shuffle tree sums the lanes.  force += F_other.
+// (shifted at r_cut) plus harmonic O-H bonds and H-O-H angle.
+//
+// Pair terms: each wave takes `span` (1..64) consecutive cell-order
+// positions, finds the atoms with pair terms among them (all atoms in model
+// 1, the O atoms in model 2) by ballot, and runs them one after another:
+// lanes stride the atom's neighbour list (or its neighbour cells), a fixed
+// shuffle tree sums the lanes.  force += F_pair.  Large systems take 64
+// positions per wave, so no wave is spent on an H atom; small ones fewer,
+// so there are still enough waves to fill the chip.
 struct NonElec {
   struct Args {
-    int n_atoms, model, nc;
-    double box, rc2, p0, p1, p2, p3, p4, p5;
-    const double* pos;
+    int n_atoms, model, nc, span;
+    double box, rc2, p0, p1;
     const int *cstart, *cperm;
     const double4* spos;   // cell-ordered {x, y, z, q}
     double *force, *partial;
+    const int *list, *nlist;   // neighbour lists as in the short-range kernel (null: scan the cells)
+    int cap;
   };
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G);
 };
 __device__ void NonElec::run(const Args& A, Grid G) {
   const int n_atoms = A.n_atoms, model = A.model, nc = A.nc;
-  const double box = A.box, rc2 = A.rc2, p0 = A.p0, p1 = A.p1, p2 = A.p2, p3 = A.p3, p4 = A.p4, p5 = A.p5;
-  const double* __restrict__ pos = A.pos;
+  const double box = A.box, rc2 = A.rc2, p0 = A.p0, p1 = A.p1;
   const int* __restrict__ cstart = A.cstart;
   const int* __restrict__ cperm = A.cperm;
   double* __restrict__ force = A.force;
-  double* __restrict__ partial = A.partial;
   __shared__ double sh[kBlock / 64];
   __shared__ PairQueue queue[kBlock / 64];
   const int lane = threadIdx.x & 63;
   const int nwaves = G.g * (kBlock / 64);
   PairQueue& Q = queue[threadIdx.x >> 6];
   double en = 0.0;
-  for (int wave = (G.b * kBlock + threadIdx.x) >> 6; wave < n_atoms && model != 0; wave += nwaves) {
-    double fx = 0.0, fy = 0.0, fz = 0.0;
-    const int i = cperm[wave];
-    const double inv_box = 1.0 / box;
-    const double4 me = A.spos[wave];
-    const double xi = me.x, yi = me.y, zi = me.z;
-    const bool pair_atom = model == 1 || (i % 3 == 0);
-    if (pair_atom) {
-      double shift;
-      if (model == 1) {
-        shift = p0 * exp(-sqrt(rc2) / p1);
-      } else {
-        const double s2 = p1 * p1 / rc2, s6 = s2 * s2 * s2;
-        shift = 4.0 * p0 * (s6 * s6 - s6);
+  double shift;
+  if (model == 1) {
+    shift = p0 * exp(-sqrt(rc2) / p1);
+  } else {
+    const double s2 = p1 * p1 / rc2, s6 = s2 * s2 * s2;
+    shift = 4.0 * p0 * (s6 * s6 - s6);
+  }
+  const int span = A.span;
+  for (int chunk = (G.b * kBlock + threadIdx.x) >> 6; chunk * span < n_atoms && model != 0; chunk += nwaves) {
+    const int mine = chunk * span + lane;
+    const bool in = lane < span && mine < n_atoms;
+    const int ai = in ? cperm[mine] : 0;
+    unsigned long long todo = __ballot(in && (model == 1 || ai % 3 == 0));
+    while (todo) {
+      const int l = __ffsll((unsigned long long)todo) - 1;   // wave-uniform
+      todo &= todo - 1;
+      const int wave = chunk * span + l;
+      const int i = __shfl(ai, l, 64);
+      const double4 me = A.spos[wave];
+      const double xi = me.x, yi = me.y, zi = me.z;
+      double fx = 0.0, fy = 0.0, fz = 0.0;
+      auto pair = [&](double dx, double dy, double dz, double r2, double) {
+        double f;
+        if (model == 1) {
+          const double r = sqrt(r2);
+          const double v = p0 * exp(-r / p1);
+          f = v / p1 / r;
+          en += 0.5 * (v - shift);
+        } else {
+          const double sr2 = p1 * p1 / r2;
+          const double sr6 = sr2 * sr2 * sr2;
+          f = 24.0 * p0 * (2.0 * sr6 * sr6 - sr6) / r2;
+          en += 0.5 * (4.0 * p0 * (sr6 * sr6 - sr6) - shift);
+        }
+        fx += f * dx; fy += f * dy; fz += f * dz;
+      };
+      const int nl = A.list ? A.nlist[wave] : 0;
+      if (A.list && nl <= A.cap)
+        // model 2: the list's site flag marks O atoms; the O of the atom's
+        // own molecule is the atom itself, which no list holds
+        for_each_listed(A.list + (size_t)wave * A.cap, nl, xi, yi, zi, box, A.spos,
+                        [&](unsigned e, double r2) { return r2 < rc2 && (model == 1 || (e & kNbrSite)); }, pair);
+      else
+        for_each_pair(
+            wave, xi, yi, zi, box, nc, cstart, A.spos, Q,
+            [&](int jj, double r2) {
+              if (!(r2 < rc2)) return false;
+              if (model == 1) return true;
+              const int j = cperm[jj];
+              return j % 3 == 0 && j / 3 != i / 3;
+            },
+            pair);
+      fx = wave_sum(fx);
+      fy = wave_sum(fy);
+      fz = wave_sum(fz);
+      if (lane == 0) {
+        force[3 * i] += fx;
+        force[3 * i + 1] += fy;
+        force[3 * i + 2] += fz;
       }
-      for_each_pair(
-          wave, xi, yi, zi, box, nc, cstart, A.spos, Q,
-          [&](int jj, double r2) {
-            if (!(r2 < rc2)) return false;
-            if (model == 1) return true;
-            const int j = cperm[jj];
-            return j % 3 == 0 && j / 3 != i / 3;
-          },
-          [&](double dx, double dy, double dz, double r2, double) {
-            double f;
-            if (model == 1) {
-              const double r = sqrt(r2);
-              const double v = p0 * exp(-r / p1);
-              f = v / p1 / r;
-              en += 0.5 * (v - shift);
-            } else {
-              const double sr2 = p1 * p1 / r2;
-              const double sr6 = sr2 * sr2 * sr2;
-              f = 24.0 * p0 * (2.0 * sr6 * sr6 - sr6) / r2;
-              en += 0.5 * (4.0 * p0 * (sr6 * sr6 - sr6) - shift);
-            }
-            fx += f * dx; fy += f * dy; fz += f * dz;
-          });
-    }
-    if (model == 2 && lane == 0) {
-      const int o = (i / 3) * 3;
-      double a[3], b[3];
-      for (int d = 0; d < 3; d++) {
-        a[d] = mi(pos[3 * (o + 1) + d] - pos[3 * o + d], box, inv_box);
-        b[d] = mi(pos[3 * (o + 2) + d] - pos[3 * o + d], box, inv_box);
-      }
-      const double la = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
-      const double lb = sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
-      const double fa = -p2 * (la - p3) / la, fb = -p2 * (lb - p3) / lb;
-      double cth = (a[0] * b[0] + a[1] * b[1] + a[2] * b[2]) / (la * lb);
-      cth = fmin(1.0, fmax(-1.0, cth));
-      const double th = acos(cth);
-      const double sth = fmax(sqrt(1.0 - cth * cth), 1e-12);
-      const double g = p4 * (th - p5) / sth;
-      double f1[3], f2[3];
-      for (int d = 0; d < 3; d++) {
-        f1[d] = fa * a[d] + g * (b[d] / (la * lb) - cth * a[d] / (la * la));
-        f2[d] = fb * b[d] + g * (a[d] / (la * lb) - cth * b[d] / (lb * lb));
-      }
-      const int role = i - o;
-      if (role == 0) {
-        fx -= f1[0] + f2[0]; fy -= f1[1] + f2[1]; fz -= f1[2] + f2[2];
-        en += 0.5 * p2 * ((la - p3) * (la - p3) + (lb - p3) * (lb - p3)) + 0.5 * p4 * (th - p5) * (th - p5);
-      } else {
-        const double* fr = role == 1 ? f1 : f2;
-        fx += fr[0]; fy += fr[1]; fz += fr[2];
-      }
-    }
-    fx = wave_sum(fx);
-    fy = wave_sum(fy);
-    fz = wave_sum(fz);
-    if (lane == 0) {
-      force[3 * i] += fx;
-      force[3 * i + 1] += fy;
-      force[3 * i + 2] += fz;
     }
   }
   en = wave_sum(en);
@@ -154,8 +143,64 @@ __device__ void NonElec::run(const Args& A, Grid G) {
   if (threadIdx.x == 0) {
     double s = 0.0;
     for (int k = 0; k < kBlock / 64; k++) s += sh[k];
-    partial[G.b] = s;
+    A.partial[G.b] = s;
   }
+}
+
+// Bonded terms of model 2, one thread per atom: the harmonic O-H bonds and
+// H-O-H angle of the atom's molecule that act on it (each atom recomputes
+// its molecule's geometry; no atomics); the molecule's energy is counted at
+// its O.  force += F_bonded.
+struct Bonded {
+  struct Args {
+    int n_atoms;
+    double box, k_bond, r0, k_angle, theta0;
+    const double* pos;
+    double *force, *partial;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G);
+};
+__device__ void Bonded::run(const Args& A, Grid G) {
+  const double box = A.box, inv_box = 1.0 / box, p2 = A.k_bond, p3 = A.r0, p4 = A.k_angle, p5 = A.theta0;
+  const double* __restrict__ pos = A.pos;
+  __shared__ double sh[kBlock / 64];
+  double en = 0.0;
+  for (int i = G.b * kBlock + threadIdx.x; i < A.n_atoms; i += G.g * kBlock) {
+    const int o = (i / 3) * 3;
+    double a[3], b[3];
+    for (int d = 0; d < 3; d++) {
+      a[d] = mi(pos[3 * (o + 1) + d] - pos[3 * o + d], box, inv_box);
+      b[d] = mi(pos[3 * (o + 2) + d] - pos[3 * o + d], box, inv_box);
+    }
+    const double la = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    const double lb = sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+    const double fa = -p2 * (la - p3) / la, fb = -p2 * (lb - p3) / lb;
+    double cth = (a[0] * b[0] + a[1] * b[1] + a[2] * b[2]) / (la * lb);
+    cth = fmin(1.0, fmax(-1.0, cth));
+    const double th = acos(cth);
+    const double sth = fmax(sqrt(1.0 - cth * cth), 1e-12);
+    const double g = p4 * (th - p5) / sth;
+    double f1[3], f2[3];
+    for (int d = 0; d < 3; d++) {
+      f1[d] = fa * a[d] + g * (b[d] / (la * lb) - cth * a[d] / (la * la));
+      f2[d] = fb * b[d] + g * (a[d] / (la * lb) - cth * b[d] / (lb * lb));
+    }
+    const int role = i - o;
+    double fx, fy, fz;
+    if (role == 0) {
+      fx = -(f1[0] + f2[0]); fy = -(f1[1] + f2[1]); fz = -(f1[2] + f2[2]);
+      en += 0.5 * p2 * ((la - p3) * (la - p3) + (lb - p3) * (lb - p3)) + 0.5 * p4 * (th - p5) * (th - p5);
+    } else {
+      const double* fr = role == 1 ? f1 : f2;
+      fx = fr[0]; fy = fr[1]; fz = fr[2];
+    }
+    A.force[3 * i] += fx;
+    A.force[3 * i + 1] += fy;
+    A.force[3 * i + 2] += fz;
+  }
+  const double bs = block_sum(en, sh);
+  if (threadIdx.x == 0) A.partial[G.b] = bs;
 }
 
 struct FinOther {
@@ -237,12 +282,23 @@ hipError_t launch_kick_drift(int n_atoms, double* pos, double* vel, const double
 hipError_t launch_nonelec(int n_atoms, const double* pos, double box, double r_cut, int model, double p0,
                           double p1, double p2, double p3, double p4, double p5, int nc, const int* cstart,
                           const int* cperm, const void* spos, double* force, double* partial, double* e_out,
-                          hipStream_t s) {
-  const int nb = std::min(blocks_for((int64_t)n_atoms * 64, kBlock), kPartialSlots);
-  hipError_t e = go<NonElec>({n_atoms, model, nc, box, r_cut * r_cut, p0, p1, p2, p3, p4, p5, pos, cstart, cperm,
-                              (const double4*)spos, force, partial}, nb, 0, s);
+                          hipStream_t s, const int* list, const int* nlist, int cap) {
+  // positions per wave: 64, halved while that leaves fewer than 8192 waves
+  int span = 64;
+  while (span > 1 && (n_atoms + span - 1) / span < 8192) span >>= 1;
+  const int64_t waves = (n_atoms + span - 1) / span;
+  // partials: the pair kernel's first, then the bonded kernel's
+  const int nb = std::min(blocks_for(waves * 64, kBlock), kPartialSlots - kMaxRedBlocks);
+  hipError_t e = go<NonElec>({n_atoms, model, nc, span, box, r_cut * r_cut, p0, p1, cstart, cperm,
+                              (const double4*)spos, force, partial, list, nlist, cap}, nb, 0, s);
   if (e != hipSuccess) return e;
-  return go<FinOther>({nb, partial, e_out}, 1, 0, s);
+  int nbb = 0;
+  if (model == 2) {
+    nbb = std::min(blocks_for(n_atoms, kBlock), kMaxRedBlocks);
+    e = go<Bonded>({n_atoms, box, p2, p3, p4, p5, pos, force, partial + nb}, nbb, 0, s);
+    if (e != hipSuccess) return e;
+  }
+  return go<FinOther>({nb + nbb, partial, e_out}, 1, 0, s);
 }
 
 hipError_t launch_kinetic_log(int n_atoms, const double* vel, const double* mass, double mv2e,

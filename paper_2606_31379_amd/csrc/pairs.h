@@ -16,6 +16,11 @@
 
 constexpr int kPairQueue = 128;   // entries per wave: one full batch + one batch's overflow
 
+// Neighbour-list entry: cell-order position in the low 30 bits, flags above.
+constexpr unsigned kNbrSameGroup = 0x80000000u;   // partner in the atom's exclusion group
+constexpr unsigned kNbrSite = 0x40000000u;        // partner's atom index is divisible by 3
+constexpr unsigned kNbrIndex = 0x3fffffffu;
+
 struct PairQueue {
   double dx[kPairQueue], dy[kPairQueue], dz[kPairQueue], r2[kPairQueue], q[kPairQueue];
 };
@@ -73,6 +78,27 @@ __device__ __forceinline__ bool candidate_range(int r, const int* c, int nc, con
   return true;
 }
 
+// Evaluates the first min(count, 64) queued pairs, one per lane, moves the
+// rest to the front of the queue and returns how many remain.
+template <class Pair>
+__device__ __forceinline__ int queue_flush(PairQueue& Q, int count, int lane, Pair& pair) {
+  const int nproc = count < 64 ? count : 64;
+  wave_sync_lds();
+  if (lane < nproc) pair(Q.dx[lane], Q.dy[lane], Q.dz[lane], Q.r2[lane], Q.q[lane]);
+  const int rest = count - nproc;
+  double v0 = 0, v1 = 0, v2 = 0, v3 = 0, v4 = 0;
+  if (lane < rest) {
+    v0 = Q.dx[nproc + lane]; v1 = Q.dy[nproc + lane]; v2 = Q.dz[nproc + lane];
+    v3 = Q.r2[nproc + lane]; v4 = Q.q[nproc + lane];
+  }
+  wave_sync_lds();
+  if (lane < rest) {
+    Q.dx[lane] = v0; Q.dy[lane] = v1; Q.dz[lane] = v2; Q.r2[lane] = v3; Q.q[lane] = v4;
+  }
+  wave_sync_lds();
+  return rest;
+}
+
 // Pairs (i, j) of the atom at cell-order position wi, for every j within
 // the neighbour cells with accept(jj, r2) true (jj = j's cell-order
 // position; the caller maps it to an atom index when it needs one).
@@ -93,21 +119,7 @@ __device__ __forceinline__ void for_each_pair(int wi, double xi, double yi, doub
   while (more && b0 >= hi) more = candidate_range(++r, c, nc, cstart, &b0, &hi);
   for (;;) {
     if (count >= 64 || (!more && count > 0)) {
-      const int nproc = count < 64 ? count : 64;
-      wave_sync_lds();
-      if (lane < nproc) pair(Q.dx[lane], Q.dy[lane], Q.dz[lane], Q.r2[lane], Q.q[lane]);
-      const int rest = count - nproc;
-      double v0 = 0, v1 = 0, v2 = 0, v3 = 0, v4 = 0;
-      if (lane < rest) {
-        v0 = Q.dx[nproc + lane]; v1 = Q.dy[nproc + lane]; v2 = Q.dz[nproc + lane];
-        v3 = Q.r2[nproc + lane]; v4 = Q.q[nproc + lane];
-      }
-      wave_sync_lds();
-      if (lane < rest) {
-        Q.dx[lane] = v0; Q.dy[lane] = v1; Q.dz[lane] = v2; Q.r2[lane] = v3; Q.q[lane] = v4;
-      }
-      wave_sync_lds();
-      count = rest;
+      count = queue_flush(Q, count, lane, pair);
       continue;
     }
     if (!more) break;
@@ -131,5 +143,25 @@ __device__ __forceinline__ void for_each_pair(int wi, double xi, double yi, doub
     count += __popcll(m);
     b0 += 64;
     while (more && b0 >= hi) more = candidate_range(++r, c, nc, cstart, &b0, &hi);
+  }
+}
+
+// The pairs of the cnt entries of one atom's neighbour list `ent`, for every
+// entry with accept(entry, r2) true (accept sees the entry's flag bits).
+// Most entries of a list lie within the cutoff, so each lane evaluates its
+// own entries (k = lane, lane + 64, ...) in place, without the queue.
+template <class Accept, class Pair>
+__device__ __forceinline__ void for_each_listed(const int* __restrict__ ent, int cnt, double xi, double yi, double zi,
+                                                double box, const double4* __restrict__ spos, Accept accept,
+                                                Pair pair) {
+  const double inv_box = 1.0 / box;
+  for (int k = threadIdx.x & 63; k < cnt; k += 64) {
+    const unsigned e = (unsigned)ent[k];
+    const double4 a = spos[e & kNbrIndex];
+    const double dx = min_img(xi - a.x, box, inv_box);
+    const double dy = min_img(yi - a.y, box, inv_box);
+    const double dz = min_img(zi - a.z, box, inv_box);
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    if (accept(e, r2)) pair(dx, dy, dz, r2, a.w);
   }
 }

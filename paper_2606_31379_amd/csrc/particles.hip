@@ -102,11 +102,13 @@ struct BinCells {
     const double* pos;
     int *key, *slot, *count;
     Ctl* ctl;
+    const int* gate;   // non-null: do nothing unless *gate (rebuild of the neighbour list)
   };
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G);
 };
 __device__ void BinCells::run(const Args& A, Grid G) {
+  if (A.gate && !*A.gate) return;
   const int n_atoms = A.n_atoms, nc = A.nc;
   const double box = A.box;
   const double* __restrict__ pos = A.pos;
@@ -145,11 +147,13 @@ struct ScanSums {
     int nbins;
     const int* count;
     int* bsum;
+    const int* gate;
   };
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G);
 };
 __device__ void ScanSums::run(const Args& A, Grid G) {
+  if (A.gate && !*A.gate) return;
   const int nbins = A.nbins;
   const int* __restrict__ count = A.count;
   int* __restrict__ bsum = A.bsum;
@@ -170,11 +174,13 @@ struct ScanTop {
   struct Args {
     int nb;
     int* bsum;
+    const int* gate;
   };
   static constexpr int kThreads = 1024;
   __device__ static void run(const Args& A, Grid G);
 };
 __device__ void ScanTop::run(const Args& A, Grid) {
+  if (A.gate && !*A.gate) return;
   const int nb = A.nb;
   int* __restrict__ bsum = A.bsum;
   __shared__ int sh[1024];
@@ -205,6 +211,7 @@ struct ScanFill {
     int nbins, nb;
     int *count, *start;
     const int* bsum;
+    const int* gate;
   };
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G);
@@ -212,6 +219,7 @@ struct ScanFill {
 // With bsum null (one workgroup covers every count) the offsets start at 0
 // and the total comes from this workgroup's own scan.
 __device__ void ScanFill::run(const Args& A, Grid G) {
+  if (A.gate && !*A.gate) return;
   const int nbins = A.nbins, nb = A.nb;
   int* __restrict__ count = A.count;
   int* __restrict__ start = A.start;
@@ -248,9 +256,11 @@ struct Scatter {
     int n_atoms;
     const int *key, *slot, *start;
     int* perm_raw;
+    const int* gate;
   };
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G) {
+    if (A.gate && !*A.gate) return;
     int a = G.b * kBlock + threadIdx.x;
     if (a >= A.n_atoms) return;
     A.perm_raw[A.start[A.key[a]] + A.slot[a]] = a;
@@ -271,11 +281,13 @@ struct SortBins {
     const double *pos, *qa;
     int4* rb;
     double* rw;
+    const int* gate;
   };
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G);
 };
 __device__ void SortBins::run(const Args& A, Grid G) {
+  if (A.gate && !*A.gate) return;
   const int nbins = A.nbins;
   const int* __restrict__ start = A.start;
   const int* __restrict__ perm_raw = A.perm_raw;
@@ -707,6 +719,7 @@ struct FinEnergy {
     const double* partial;
     Ctl* ctl;
     double* energy_out;
+    int nbr;   // 1: the step used neighbour lists; a flagged rebuild is now done
   };
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid);
@@ -718,6 +731,10 @@ __device__ void FinEnergy::run(const Args& A, Grid) {
   __shared__ double sh[kBlock / 64];
   const double tot = reduce_partials_sum(A.partial, A.nb, sh);
   if (threadIdx.x == 0) {
+    if (A.nbr && ctl->nbr_stale) {
+      ctl->nbr_builds++;
+      ctl->nbr_stale = 0;
+    }
     ctl->e_sr = tot;
     if (energy_out) {
       energy_out[0] = tot;
@@ -736,15 +753,121 @@ struct CellPack {
     const int* cperm;
     const double *pos, *qa;
     double4* spos;
+    const int* gate;   // non-null: do nothing unless *gate
   };
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G) {
+    if (A.gate && !*A.gate) return;
     const int jj = G.b * kBlock + threadIdx.x;
     if (jj >= A.n_atoms) return;
     const int a = A.cperm[jj];
     A.spos[jj] = make_double4(A.pos[3 * a], A.pos[3 * a + 1], A.pos[3 * a + 2], A.qa[a]);
   }
 };
+
+// Verlet neighbour list with a skin (Verlet's buffered list): the list of
+// the atom at cell-order position wi holds every other atom within
+// r_l = r_cut + skin at the last build.  While no atom has moved more than
+// skin/2 (minimum image) since then, every pair within r_cut is in it, so
+// the pair sums over the list equal those over the cell neighbourhood.
+//
+// Every step: refresh the cell-ordered copy in the build's order and flag a
+// rebuild when some atom has moved too far (a non-finite position, or the
+// NaN reference positions of a list never built, also flag it).
+struct NbrCheck {
+  struct Args {
+    int n_atoms;
+    double box, half_skin2;
+    const int* cperm;
+    const double *pos, *qa;
+    double4* spos;
+    const double4* ref;
+    Ctl* ctl;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G) {
+    const int jj = G.b * kBlock + threadIdx.x;
+    if (jj >= A.n_atoms) return;
+    const int a = A.cperm[jj];
+    const double x = A.pos[3 * a], y = A.pos[3 * a + 1], z = A.pos[3 * a + 2];
+    A.spos[jj] = make_double4(x, y, z, A.qa[a]);
+    const double4 r = A.ref[jj];
+    const double inv_box = 1.0 / A.box;
+    const double dx = min_img(x - r.x, A.box, inv_box), dy = min_img(y - r.y, A.box, inv_box),
+                 dz = min_img(z - r.z, A.box, inv_box);
+    if (!(dx * dx + dy * dy + dz * dz <= A.half_skin2)) A.ctl->nbr_stale = 1;
+  }
+};
+
+// The list build (only when flagged): one wave per atom scans the 27 cells
+// (cells at least r_l wide) around it.  Entries are cell-order positions
+// jj in candidate order, so the sums over a list are deterministic, with
+// two flag bits: kNbrSameGroup (an exclusion-group partner) and kNbrSite
+// (atom index divisible by 3: the O of an O,H,H triple).  Entries past the
+// capacity are dropped and the count keeps the true number: such an atom's
+// pair kernels fall back to the cell scan.
+struct NbrBuild {
+  struct Args {
+    int n_atoms, nc, excl_group, cap;
+    double box, rl2;
+    const int *cstart, *cperm;
+    const double4* spos;
+    double4* ref;
+    int *list, *cnt;
+    Ctl* ctl;
+  };
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G);
+};
+__device__ void NbrBuild::run(const Args& A, Grid G) {
+  if (!A.ctl->nbr_stale) return;
+  const int n_atoms = A.n_atoms, nc = A.nc, g = A.excl_group, cap = A.cap;
+  const double box = A.box, rl2 = A.rl2, inv_box = 1.0 / box;
+  const int* __restrict__ cstart = A.cstart;
+  const int* __restrict__ cperm = A.cperm;
+  const double4* __restrict__ spos = A.spos;
+  const int lane = threadIdx.x & 63;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  const int nwaves = G.g * (kBlock / 64);
+  for (int wave = (G.b * kBlock + threadIdx.x) >> 6; wave < n_atoms; wave += nwaves) {
+    const double4 me = spos[wave];
+    const int i = cperm[wave];
+    const int gi = g > 0 ? i / g : -1;
+    int* __restrict__ out = A.list + (size_t)wave * cap;
+    int c[3];
+    cell_of(me.x, me.y, me.z, box, nc, c);
+    int count = 0;
+    int lo = 0, hi = 0;
+    for (int r = 0; candidate_range(r, c, nc, cstart, &lo, &hi); r++) {
+      for (int b0 = lo; b0 < hi; b0 += 64) {
+        const int jj = b0 + lane;
+        bool ok = false;
+        unsigned e = 0;
+        if (jj < hi && jj != wave) {
+          const double4 a = spos[jj];
+          const double dx = min_img(me.x - a.x, box, inv_box), dy = min_img(me.y - a.y, box, inv_box),
+                       dz = min_img(me.z - a.z, box, inv_box);
+          if (dx * dx + dy * dy + dz * dz < rl2) {
+            const int j = cperm[jj];
+            ok = true;
+            e = (unsigned)jj | (gi >= 0 && j / g == gi ? kNbrSameGroup : 0u) | (j % 3 == 0 ? kNbrSite : 0u);
+          }
+        }
+        const unsigned long long m = __ballot(ok);
+        if (ok) {
+          const int slot = count + __popcll(m & below);
+          if (slot < cap) out[slot] = (int)e;
+        }
+        count += __popcll(m);
+      }
+    }
+    if (lane == 0) {
+      A.cnt[wave] = count;
+      A.ref[wave] = me;
+      if (count > cap) atomicAdd(&A.ctl->nbr_over, 1);
+    }
+  }
+}
 
 // Short-range pairs (Eq. 20 force, Eq. 6 energy) over the cell list with the
 // minimum image; pairs inside one exclusion group instead get the Ewald
@@ -762,6 +885,10 @@ struct ShortRange {
     const double* erfc_tab;   // erfcx table on [0, alpha r_cut] (1..kErfcMaxIntervals intervals)
     int erfc_n;
     double erfc_scale;        // table intervals per unit of alpha r
+    // neighbour lists (null: scan the cells): entries of cell-order atom wi
+    // at list + wi * cap, nlist[wi] of them (more than cap: scan the cells)
+    const int *list, *nlist;
+    int cap;
   };
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G);
@@ -796,21 +923,25 @@ __device__ void ShortRange::run(const Args& A, Grid G) {
     const double inv_box = 1.0 / box;
     const double tapi = 2.0 * alpha / sqrt(M_PI);
     const int gi = excl_group > 0 ? i / excl_group : -1;
-    for_each_pair(
-        wave, xi, yi, zi, box, nc, cstart, spos, Q,
-        [&](int jj, double r2) { return r2 < rc2 && !(gi >= 0 && cperm[jj] / excl_group == gi); },
-        [&](double dx, double dy, double dz, double r2, double qj) {
-          // erfc(a r) = exp(-a^2 r^2) erfcx(a r), erfcx from the table
-          const double r = sqrt(r2);
-          const double inv_r = 1.0 / r;
-          const double x = alpha * r;
-          const double g = exp(-x * x);
-          const double ec = g * erfcx_table(tab, tab_n, tab_scale, x);
-          const double qq = k_e * qi * qj;
-          const double f = qq * inv_r * inv_r * (ec * inv_r + tapi * g);
-          fx += f * dx; fy += f * dy; fz += f * dz;
-          en += 0.5 * qq * ec * inv_r;
-        });
+    auto pair = [&](double dx, double dy, double dz, double r2, double qj) {
+      // erfc(a r) = exp(-a^2 r^2) erfcx(a r), erfcx from the table
+      const double r = sqrt(r2);
+      const double inv_r = 1.0 / r;
+      const double x = alpha * r;
+      const double g = exp(-x * x);
+      const double ec = g * erfcx_table(tab, tab_n, tab_scale, x);
+      const double qq = k_e * qi * qj;
+      const double f = qq * inv_r * inv_r * (ec * inv_r + tapi * g);
+      fx += f * dx; fy += f * dy; fz += f * dz;
+      en += 0.5 * qq * ec * inv_r;
+    };
+    const int nl = A.list ? A.nlist[wave] : 0;
+    if (A.list && nl <= A.cap)
+      for_each_listed(A.list + (size_t)wave * A.cap, nl, xi, yi, zi, box, spos,
+                      [&](unsigned e, double r2) { return r2 < rc2 && !(e & kNbrSameGroup); }, pair);
+    else
+      for_each_pair(wave, xi, yi, zi, box, nc, cstart, spos, Q,
+                    [&](int jj, double r2) { return r2 < rc2 && !(gi >= 0 && cperm[jj] / excl_group == gi); }, pair);
     if (gi >= 0 && lane < excl_group) {
       const int j = gi * excl_group + lane;
       if (j != i && j < n_atoms) {
@@ -858,36 +989,36 @@ hipError_t launch_bin_tiles(int n_atoms, const double* pos, double box, int n, i
 }
 
 hipError_t launch_bin_cells(int n_atoms, const double* pos, double box, int nc, int* key, int* slot,
-                            int* count, Ctl* ctl, hipStream_t s) {
-  return go<BinCells>({n_atoms, nc, box, pos, key, slot, count, ctl}, blocks_for(n_atoms, kBlock), 0, s);
+                            int* count, Ctl* ctl, hipStream_t s, const int* gate) {
+  return go<BinCells>({n_atoms, nc, box, pos, key, slot, count, ctl, gate}, blocks_for(n_atoms, kBlock), 0, s);
 }
 
 int scan_partials(int nbins) { return (nbins + kScanChunk - 1) / kScanChunk + 1; }
 
-hipError_t launch_scan(int nbins, int* count, int* start, int* bsum, hipStream_t s) {
+hipError_t launch_scan(int nbins, int* count, int* start, int* bsum, hipStream_t s, const int* gate) {
   const int nb = (nbins + kScanChunk - 1) / kScanChunk;
   if (nb == 1) {
     // one workgroup scans all; in a batch recording it takes the sequence
     // position of the multi-workgroup ScanFill, so it merges with the other
     // systems' ScanFill launches
     if (g_recorder) g_recorder->seq += 2;
-    return go<ScanFill>({nbins, 1, count, start, nullptr}, 1, 0, s);
+    return go<ScanFill>({nbins, 1, count, start, nullptr, gate}, 1, 0, s);
   }
-  hipError_t e = go<ScanSums>({nbins, count, bsum}, nb, 0, s);
+  hipError_t e = go<ScanSums>({nbins, count, bsum, gate}, nb, 0, s);
   if (e != hipSuccess) return e;
-  e = go<ScanTop>({nb, bsum}, 1, 0, s);
+  e = go<ScanTop>({nb, bsum, gate}, 1, 0, s);
   if (e != hipSuccess) return e;
-  return go<ScanFill>({nbins, nb, count, start, bsum}, nb, 0, s);
+  return go<ScanFill>({nbins, nb, count, start, bsum, gate}, nb, 0, s);
 }
 
 hipError_t launch_scatter(int n_atoms, const int* key, const int* slot, const int* start, int* perm_raw,
-                          hipStream_t s) {
-  return go<Scatter>({n_atoms, key, slot, start, perm_raw}, blocks_for(n_atoms, kBlock), 0, s);
+                          hipStream_t s, const int* gate) {
+  return go<Scatter>({n_atoms, key, slot, start, perm_raw, gate}, blocks_for(n_atoms, kBlock), 0, s);
 }
 
 hipError_t launch_sort_bins(int nbins, const int* start, const int* perm_raw, int* perm, Ctl*,
-                            hipStream_t s) {
-  return go<SortBins>({nbins, start, perm_raw, perm, 0, 0, 0, 0.0, nullptr, nullptr, nullptr, nullptr},
+                            hipStream_t s, const int* gate) {
+  return go<SortBins>({nbins, start, perm_raw, perm, 0, 0, 0, 0.0, nullptr, nullptr, nullptr, nullptr, gate},
                       blocks_for((int64_t)nbins * 64, kBlock), 0, s);
 }
 
@@ -962,19 +1093,37 @@ hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, int tile, int ntx
 }
 
 hipError_t launch_cell_pack(int n_atoms, const int* cperm, const double* pos, const double* qa, void* spos,
-                            hipStream_t s) {
-  return go<CellPack>({n_atoms, cperm, pos, qa, (double4*)spos}, blocks_for(n_atoms, kBlock), 0, s);
+                            hipStream_t s, const int* gate) {
+  return go<CellPack>({n_atoms, cperm, pos, qa, (double4*)spos, gate}, blocks_for(n_atoms, kBlock), 0, s);
+}
+
+hipError_t launch_nbr_check(int n_atoms, double box, double skin, const int* cperm, const double* pos,
+                            const double* qa, void* spos, const void* ref, Ctl* ctl, hipStream_t s) {
+  const double h = 0.5 * skin;
+  return go<NbrCheck>({n_atoms, box, h * h, cperm, pos, qa, (double4*)spos, (const double4*)ref, ctl},
+                      blocks_for(n_atoms, kBlock), 0, s);
+}
+
+hipError_t launch_nbr_build(int n_atoms, double box, double r_list, int nc, int excl_group, int cap,
+                            const int* cstart, const int* cperm, const void* spos, void* ref, int* list, int* nlist,
+                            Ctl* ctl, hipStream_t s) {
+  if (cap < 1 || (unsigned)(n_atoms - 1) > kNbrIndex) return hipErrorInvalidValue;
+  const int nb = std::min(blocks_for((int64_t)n_atoms * 64, kBlock), kPartialSlots);
+  return go<NbrBuild>({n_atoms, nc, excl_group, cap, box, r_list * r_list, cstart, cperm, (const double4*)spos,
+                       (double4*)ref, list, nlist, ctl}, nb, 0, s);
 }
 
 hipError_t launch_sr(int n_atoms, const double* pos, const double* qa, double box, double alpha,
                      double r_cut, double k_e, int nc, int excl_group, const int* cstart,
                      const int* cperm, const void* spos, const double* erfc_tab, int erfc_n, double erfc_scale,
-                     double* force, double e_self, double* energy_out, double* partial, Ctl* ctl, hipStream_t s) {
+                     double* force, double e_self, double* energy_out, double* partial, Ctl* ctl, hipStream_t s,
+                     const int* list, const int* nlist, int cap) {
   if (erfc_n < 1 || erfc_n > kErfcMaxIntervals) return hipErrorInvalidValue;
   const int nb = std::min(blocks_for((int64_t)n_atoms * 64, kBlock), kPartialSlots);
   const size_t lds = (size_t)erfc_n * (kErfcDeg + 1) * sizeof(double);
   hipError_t e = go<ShortRange>({n_atoms, nc, excl_group, box, alpha, r_cut * r_cut, k_e, pos, qa, cstart, cperm,
-                                 (const double4*)spos, force, partial, erfc_tab, erfc_n, erfc_scale}, nb, lds, s);
+                                 (const double4*)spos, force, partial, erfc_tab, erfc_n, erfc_scale, list, nlist, cap},
+                                nb, lds, s);
   if (e != hipSuccess) return e;
-  return go<FinEnergy>({nb, e_self, partial, ctl, energy_out}, 1, 0, s);
+  return go<FinEnergy>({nb, e_self, partial, ctl, energy_out, list ? 1 : 0}, 1, 0, s);
 }

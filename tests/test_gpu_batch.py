@@ -71,6 +71,9 @@ def test_batch_compute_equals_single(torch, precision, graphs):
     q = packed([s.charges for s in systems])
     b = P.p3mz_batch_create([sys_params(P, r, precision) for r in reps], n, q)
     singles = [P.p3mz_create(sys_params(P, r, precision), s.charges) for r, s in zip(reps, systems)]
+    for h in singles:
+        # batched systems scan the cells for their pairs: so does the reference
+        P.p3mz_set_neighbor_list(h, 0.0)
     stream = torch.cuda.current_stream().cuda_stream
     try:
         P.p3mz_batch_set_graphs(b, graphs)
@@ -131,6 +134,7 @@ def test_batch_md_equals_single(torch, precision):
         for i, (r, s) in enumerate(zip(reps, systems)):
             h = P.p3mz_create(sys_params(P, r, precision), s.charges)
             try:
+                P.p3mz_set_neighbor_list(h, 0.0)
                 p1 = torch.from_numpy(s.pos.copy()).to(dev)
                 v1 = torch.from_numpy(s.vel.copy()).to(dev)
                 m1 = torch.from_numpy(s.masses.copy()).to(dev)
