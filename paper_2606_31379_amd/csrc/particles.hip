@@ -799,27 +799,32 @@ struct NbrCheck {
   }
 };
 
-// The list build (only when flagged): one wave per atom scans the 27 cells
-// (cells at least r_l wide) around it.  Entries are cell-order positions
-// jj in candidate order, so the sums over a list are deterministic, with
-// two flag bits: kNbrSameGroup (an exclusion-group partner) and kNbrSite
-// (atom index divisible by 3: the O of an O,H,H triple).  Entries past the
-// capacity are dropped and the count keeps the true number: such an atom's
-// pair kernels fall back to the cell scan.
-struct NbrBuild {
-  struct Args {
-    int n_atoms, nc, excl_group, cap;
-    double box, rl2;
-    const int *cstart, *cperm;
-    const double4* spos;
-    double4* ref;
-    int *list, *cnt;
-    Ctl* ctl;
-  };
+// The list build (only when flagged), on cells at least r_l wide.  Entries
+// are cell-order positions jj in candidate order (the 27-cell neighbourhood
+// in the order of candidate_range), so the sums over a list are
+// deterministic, with two flag bits: kNbrSameGroup (an exclusion-group partner) and kNbrSite (atom index
+// divisible by 3: the O of an O,H,H triple).  Entries past the capacity are
+// dropped and the count keeps the true number: such an atom's pair kernels
+// fall back to the cell scan.
+struct NbrArgs {
+  int n_atoms, nc, excl_group, cap;
+  double box, rl2;
+  const int *cstart, *cperm;
+  const double4* spos;
+  double4* ref;
+  int *list, *cnt;
+  Ctl* ctl;
+};
+
+// One wave per atom: lanes test 64 consecutive candidates at a time.  Every
+// atom loads its whole neighbourhood, so this suits small systems (few
+// cells, where a wave per cell would leave the chip idle).
+struct NbrBuildAtom {
+  using Args = NbrArgs;
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G);
 };
-__device__ void NbrBuild::run(const Args& A, Grid G) {
+__device__ void NbrBuildAtom::run(const Args& A, Grid G) {
   if (!A.ctl->nbr_stale) return;
   const int n_atoms = A.n_atoms, nc = A.nc, g = A.excl_group, cap = A.cap;
   const double box = A.box, rl2 = A.rl2, inv_box = 1.0 / box;
@@ -869,14 +874,84 @@ __device__ void NbrBuild::run(const Args& A, Grid G) {
   }
 }
 
-// Short-range pairs (Eq. 20 force, Eq. 6 energy) over the cell list with the
-// minimum image; pairs inside one exclusion group instead get the Ewald
-// exclusion correction -k Q Q erf(alpha r)/r.  One wave per atom: lanes take
-// fixed strides of each neighbour cell's list, then a fixed shuffle tree
+// One single-wave workgroup per cell: a lane per atom of the cell (64 at a
+// time), the candidates of the cell's neighbourhood streamed through LDS 64
+// at a time and tested by every lane against its atom, so each candidate is
+// loaded once per 64 atoms instead of once per atom.
+struct NbrBuildCell {
+  using Args = NbrArgs;
+  static constexpr int kThreads = 64;
+  __device__ static void run(const Args& A, Grid G);
+};
+__device__ void NbrBuildCell::run(const Args& A, Grid G) {
+  if (!A.ctl->nbr_stale) return;
+  const int nc = A.nc, g = A.excl_group, cap = A.cap, ncells = nc * nc * nc;
+  const double box = A.box, rl2 = A.rl2, inv_box = 1.0 / box;
+  const int* __restrict__ cstart = A.cstart;
+  const int* __restrict__ cperm = A.cperm;
+  const double4* __restrict__ spos = A.spos;
+  __shared__ double4 cand[64];
+  __shared__ int cidx[64];
+  const int lane = threadIdx.x;
+  for (int cell = G.b; cell < ncells; cell += G.g) {
+    const int c[3] = {cell % nc, (cell / nc) % nc, cell / (nc * nc)};
+    const int s0 = cstart[cell], s1 = cstart[cell + 1];
+    for (int b = s0; b < s1; b += 64) {
+      const int wi = b + lane;
+      const bool act = wi < s1;
+      const double4 me = act ? spos[wi] : make_double4(0.0, 0.0, 0.0, 0.0);
+      const int i = act ? cperm[wi] : 0;
+      const int gi = g > 0 ? i / g : -1;
+      int* __restrict__ out = A.list + (size_t)(act ? wi : 0) * cap;
+      int count = 0;
+      int lo = 0, hi = 0;
+      for (int r = 0; candidate_range(r, c, nc, cstart, &lo, &hi); r++) {
+        for (int c0 = lo; c0 < hi; c0 += 64) {
+          const int m = min(64, hi - c0);
+          if (lane < m) {
+            cand[lane] = spos[c0 + lane];
+            cidx[lane] = cperm[c0 + lane];
+          }
+          wave_sync_lds();
+          if (act) {
+            for (int t = 0; t < m; t++) {
+              const double4 a = cand[t];
+              const double dx = min_img(me.x - a.x, box, inv_box), dy = min_img(me.y - a.y, box, inv_box),
+                           dz = min_img(me.z - a.z, box, inv_box);
+              const int jj = c0 + t;
+              if (dx * dx + dy * dy + dz * dz < rl2 && jj != wi) {
+                const int j = cidx[t];
+                const unsigned e =
+                    (unsigned)jj | (gi >= 0 && j / g == gi ? kNbrSameGroup : 0u) | (j % 3 == 0 ? kNbrSite : 0u);
+                if (count < cap) out[count] = (int)e;
+                count++;
+              }
+            }
+          }
+          wave_sync_lds();
+        }
+      }
+      if (act) {
+        A.cnt[wi] = count;
+        A.ref[wi] = me;
+        if (count > cap) atomicAdd(&A.ctl->nbr_over, 1);
+      }
+    }
+  }
+}
+
+// Short-range pairs (Eq. 20 force, Eq. 6 energy) with the minimum image;
+// pairs inside one exclusion group instead get the Ewald exclusion
+// correction -k Q Q erf(alpha r)/r.  One wave per atom; a fixed shuffle tree
 // adds the lane sums (deterministic).  force += F_sr.
+// LIST: over each atom's neighbour list (atoms over the list capacity are
+// skipped); otherwise the cell scan, for every atom (no lists, span 1: one
+// atom per wave) or for the atoms over capacity (span 64: each wave picks
+// them from 64 consecutive positions by ballot).
+template <bool LIST>
 struct ShortRange {
   struct Args {
-    int n_atoms, nc, excl_group;
+    int n_atoms, nc, excl_group, span;
     double box, alpha, rc2, k_e;
     const double *pos, *qa;
     const int *cstart, *cperm;
@@ -885,88 +960,110 @@ struct ShortRange {
     const double* erfc_tab;   // erfcx table on [0, alpha r_cut] (1..kErfcMaxIntervals intervals)
     int erfc_n;
     double erfc_scale;        // table intervals per unit of alpha r
-    // neighbour lists (null: scan the cells): entries of cell-order atom wi
-    // at list + wi * cap, nlist[wi] of them (more than cap: scan the cells)
+    // neighbour lists (null: none): entries of cell-order atom wi at
+    // list + wi * cap, nlist[wi] of them
     const int *list, *nlist;
     int cap;
   };
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G);
 };
-__device__ void ShortRange::run(const Args& A, Grid G) {
-  const int n_atoms = A.n_atoms, nc = A.nc, excl_group = A.excl_group;
+
+// The short-range force on the atom at cell-order position `wave` (lanes
+// split its pairs, a fixed shuffle tree sums them) and its pair energy,
+// accumulated into each lane's en.
+template <bool LIST>
+__device__ __forceinline__ void sr_atom(const typename ShortRange<LIST>::Args& A, int wave, const double* tab,
+                                        PairQueue* Q, double& en) {
+  const int n_atoms = A.n_atoms, excl_group = A.excl_group;
   const double box = A.box, alpha = A.alpha, rc2 = A.rc2, k_e = A.k_e;
   const double* __restrict__ pos = A.pos;
   const double* __restrict__ qa = A.qa;
-  const int* __restrict__ cstart = A.cstart;
   const int* __restrict__ cperm = A.cperm;
-  double* __restrict__ force = A.force;
-  double* __restrict__ partial = A.partial;
-  __shared__ double sh[kBlock / 64];
-  __shared__ PairQueue queue[kBlock / 64];
-  extern __shared__ double tab[];   // erfc_n * (kErfcDeg + 1) coefficients (dynamic LDS)
-  const int lane = threadIdx.x & 63;
-  const int nwaves = G.g * (kBlock / 64);
-  PairQueue& Q = queue[threadIdx.x >> 6];
-  double en = 0.0;
   const double4* __restrict__ spos = A.spos;
   const int tab_n = A.erfc_n;
   const double tab_scale = A.erfc_scale;
-  for (int k = threadIdx.x; k < tab_n * (kErfcDeg + 1); k += kBlock) tab[k] = A.erfc_tab[k];
-  __syncthreads();
-  for (int wave = (G.b * kBlock + threadIdx.x) >> 6; wave < n_atoms; wave += nwaves) {
-    double fx = 0.0, fy = 0.0, fz = 0.0;
-    const int i = cperm[wave];
-    const double4 me = spos[wave];
-    const double xi = me.x, yi = me.y, zi = me.z;
-    const double qi = me.w;
-    const double inv_box = 1.0 / box;
-    const double tapi = 2.0 * alpha / sqrt(M_PI);
-    const int gi = excl_group > 0 ? i / excl_group : -1;
-    auto pair = [&](double dx, double dy, double dz, double r2, double qj) {
-      // erfc(a r) = exp(-a^2 r^2) erfcx(a r), erfcx from the table
+  const int lane = threadIdx.x & 63;
+  double fx = 0.0, fy = 0.0, fz = 0.0;
+  const int i = cperm[wave];
+  const double4 me = spos[wave];
+  const double xi = me.x, yi = me.y, zi = me.z;
+  const double qi = me.w;
+  const double inv_box = 1.0 / box;
+  const double tapi = 2.0 * alpha / sqrt(M_PI);
+  const int gi = excl_group > 0 ? i / excl_group : -1;
+  auto pair = [&](double dx, double dy, double dz, double r2, double qj) {
+    // erfc(a r) = exp(-a^2 r^2) erfcx(a r), erfcx from the table
+    const double r = sqrt(r2);
+    const double inv_r = 1.0 / r;
+    const double x = alpha * r;
+    const double g = exp(-x * x);
+    const double ec = g * erfcx_table(tab, tab_n, tab_scale, x);
+    const double qq = k_e * qi * qj;
+    const double f = qq * inv_r * inv_r * (ec * inv_r + tapi * g);
+    fx += f * dx; fy += f * dy; fz += f * dz;
+    en += 0.5 * qq * ec * inv_r;
+  };
+  if constexpr (LIST)
+    for_each_listed(A.list + (size_t)wave * A.cap, A.nlist[wave], xi, yi, zi, box, spos,
+                    [&](unsigned e, double r2) { return r2 < rc2 && !(e & kNbrSameGroup); }, pair);
+  else
+    for_each_pair(wave, xi, yi, zi, box, A.nc, A.cstart, spos, *Q,
+                  [&](int jj, double r2) { return r2 < rc2 && !(gi >= 0 && cperm[jj] / excl_group == gi); }, pair);
+  if (gi >= 0 && lane < excl_group) {
+    const int j = gi * excl_group + lane;
+    if (j != i && j < n_atoms) {
+      double dx = xi - pos[3 * j], dy = yi - pos[3 * j + 1], dz = zi - pos[3 * j + 2];
+      dx -= box * rint(dx * inv_box);
+      dy -= box * rint(dy * inv_box);
+      dz -= box * rint(dz * inv_box);
+      const double r2 = dx * dx + dy * dy + dz * dz;
       const double r = sqrt(r2);
-      const double inv_r = 1.0 / r;
-      const double x = alpha * r;
-      const double g = exp(-x * x);
-      const double ec = g * erfcx_table(tab, tab_n, tab_scale, x);
-      const double qq = k_e * qi * qj;
-      const double f = qq * inv_r * inv_r * (ec * inv_r + tapi * g);
+      // erf = 1 - exp(-x^2) erfcx(x); intramolecular pairs lie well inside the table
+      const double xr = alpha * r;
+      const double er = 1.0 - exp(-xr * xr) * erfcx_table(tab, tab_n, tab_scale, xr);
+      const double qq = k_e * qi * qa[j];
+      const double f = qq * (tapi * exp(-alpha * alpha * r2) / r - er / r2) / r;
       fx += f * dx; fy += f * dy; fz += f * dz;
-      en += 0.5 * qq * ec * inv_r;
-    };
-    const int nl = A.list ? A.nlist[wave] : 0;
-    if (A.list && nl <= A.cap)
-      for_each_listed(A.list + (size_t)wave * A.cap, nl, xi, yi, zi, box, spos,
-                      [&](unsigned e, double r2) { return r2 < rc2 && !(e & kNbrSameGroup); }, pair);
-    else
-      for_each_pair(wave, xi, yi, zi, box, nc, cstart, spos, Q,
-                    [&](int jj, double r2) { return r2 < rc2 && !(gi >= 0 && cperm[jj] / excl_group == gi); }, pair);
-    if (gi >= 0 && lane < excl_group) {
-      const int j = gi * excl_group + lane;
-      if (j != i && j < n_atoms) {
-        double dx = xi - pos[3 * j], dy = yi - pos[3 * j + 1], dz = zi - pos[3 * j + 2];
-        dx -= box * rint(dx * inv_box);
-        dy -= box * rint(dy * inv_box);
-        dz -= box * rint(dz * inv_box);
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        const double r = sqrt(r2);
-        // erf = 1 - exp(-x^2) erfcx(x); intramolecular pairs lie well inside the table
-        const double xr = alpha * r;
-        const double er = 1.0 - exp(-xr * xr) * erfcx_table(tab, tab_n, tab_scale, xr);
-        const double qq = k_e * qi * qa[j];
-        const double f = qq * (tapi * exp(-alpha * alpha * r2) / r - er / r2) / r;
-        fx += f * dx; fy += f * dy; fz += f * dz;
-        en += -0.5 * qq * er / r;
-      }
+      en += -0.5 * qq * er / r;
     }
-    fx = wave_sum(fx);
-    fy = wave_sum(fy);
-    fz = wave_sum(fz);
-    if (lane == 0 && force) {
-      force[3 * i] += fx;
-      force[3 * i + 1] += fy;
-      force[3 * i + 2] += fz;
+  }
+  fx = wave_sum(fx);
+  fy = wave_sum(fy);
+  fz = wave_sum(fz);
+  if (lane == 0 && A.force) {
+    A.force[3 * i] += fx;
+    A.force[3 * i + 1] += fy;
+    A.force[3 * i + 2] += fz;
+  }
+}
+
+template <bool LIST>
+__device__ void ShortRange<LIST>::run(const Args& A, Grid G) {
+  const int n_atoms = A.n_atoms;
+  __shared__ double sh[kBlock / 64];
+  __shared__ PairQueue queue[LIST ? 1 : kBlock / 64];
+  extern __shared__ double tab[];   // erfc_n * (kErfcDeg + 1) coefficients (dynamic LDS)
+  const int lane = threadIdx.x & 63;
+  const int nwaves = G.g * (kBlock / 64);
+  double en = 0.0;
+  for (int k = threadIdx.x; k < A.erfc_n * (kErfcDeg + 1); k += kBlock) tab[k] = A.erfc_tab[k];
+  __syncthreads();
+  if constexpr (LIST) {
+    for (int wave = (G.b * kBlock + threadIdx.x) >> 6; wave < n_atoms; wave += nwaves)
+      if (A.nlist[wave] <= A.cap) sr_atom<true>(A, wave, tab, nullptr, en);
+  } else {
+    PairQueue* Q = &queue[threadIdx.x >> 6];
+    const int span = A.span;
+    for (int chunk = (G.b * kBlock + threadIdx.x) >> 6; chunk * span < n_atoms; chunk += nwaves) {
+      const int mine = chunk * span + lane;
+      const bool in = lane < span && mine < n_atoms;
+      unsigned long long todo = __ballot(in && (!A.list || A.nlist[mine] > A.cap));
+      while (todo) {
+        const int l = __ffsll((unsigned long long)todo) - 1;   // wave-uniform
+        todo &= todo - 1;
+        sr_atom<false>(A, chunk * span + l, tab, Q, en);
+      }
     }
   }
   en = wave_sum(en);
@@ -975,7 +1072,7 @@ __device__ void ShortRange::run(const Args& A, Grid G) {
   if (threadIdx.x == 0) {
     double s = 0.0;
     for (int k = 0; k < kBlock / 64; k++) s += sh[k];
-    partial[G.b] = s;
+    A.partial[G.b] = s;
   }
 }
 
@@ -1108,9 +1205,15 @@ hipError_t launch_nbr_build(int n_atoms, double box, double r_list, int nc, int 
                             const int* cstart, const int* cperm, const void* spos, void* ref, int* list, int* nlist,
                             Ctl* ctl, hipStream_t s) {
   if (cap < 1 || (unsigned)(n_atoms - 1) > kNbrIndex) return hipErrorInvalidValue;
-  const int nb = std::min(blocks_for((int64_t)n_atoms * 64, kBlock), kPartialSlots);
-  return go<NbrBuild>({n_atoms, nc, excl_group, cap, box, r_list * r_list, cstart, cperm, (const double4*)spos,
-                       (double4*)ref, list, nlist, ctl}, nb, 0, s);
+  const NbrArgs a{n_atoms, nc, excl_group, cap, box, r_list * r_list, cstart, cperm, (const double4*)spos,
+                  (double4*)ref, list, nlist, ctl};
+  // a wave per cell once that gives enough waves (each takes its cell's
+  // atoms 64 at a time); fewer, fuller cells: a wave per atom
+  const int64_t ncells = (int64_t)nc * nc * nc;
+  const int64_t per_cell = (n_atoms + ncells - 1) / ncells;
+  if (ncells * ((per_cell + 63) / 64) >= 8192)
+    return go<NbrBuildCell>(a, (int)std::min<int64_t>(ncells, 65536), 0, s);
+  return go<NbrBuildAtom>(a, std::min(blocks_for((int64_t)n_atoms * 64, kBlock), kPartialSlots), 0, s);
 }
 
 hipError_t launch_sr(int n_atoms, const double* pos, const double* qa, double box, double alpha,
@@ -1119,11 +1222,27 @@ hipError_t launch_sr(int n_atoms, const double* pos, const double* qa, double bo
                      double* force, double e_self, double* energy_out, double* partial, Ctl* ctl, hipStream_t s,
                      const int* list, const int* nlist, int cap) {
   if (erfc_n < 1 || erfc_n > kErfcMaxIntervals) return hipErrorInvalidValue;
-  const int nb = std::min(blocks_for((int64_t)n_atoms * 64, kBlock), kPartialSlots);
   const size_t lds = (size_t)erfc_n * (kErfcDeg + 1) * sizeof(double);
-  hipError_t e = go<ShortRange>({n_atoms, nc, excl_group, box, alpha, r_cut * r_cut, k_e, pos, qa, cstart, cperm,
-                                 (const double4*)spos, force, partial, erfc_tab, erfc_n, erfc_scale, list, nlist, cap},
-                                nb, lds, s);
+  const double rc2 = r_cut * r_cut;
+  if (!list) {
+    const int nb = std::min(blocks_for((int64_t)n_atoms * 64, kBlock), kPartialSlots);
+    hipError_t e = go<ShortRange<false>>({n_atoms, nc, excl_group, 1, box, alpha, rc2, k_e, pos, qa, cstart, cperm,
+                                          (const double4*)spos, force, partial, erfc_tab, erfc_n, erfc_scale,
+                                          nullptr, nullptr, 0}, nb, lds, s);
+    if (e != hipSuccess) return e;
+    return go<FinEnergy>({nb, e_self, partial, ctl, energy_out, 0}, 1, 0, s);
+  }
+  // the lists, then the cell scan for the atoms over capacity; partials of
+  // the first kernel, then of the second
+  const int nb = std::min(blocks_for((int64_t)n_atoms * 64, kBlock), kPartialSlots / 2);
+  hipError_t e = go<ShortRange<true>>({n_atoms, nc, excl_group, 1, box, alpha, rc2, k_e, pos, qa, cstart, cperm,
+                                       (const double4*)spos, force, partial, erfc_tab, erfc_n, erfc_scale, list,
+                                       nlist, cap}, nb, lds, s);
   if (e != hipSuccess) return e;
-  return go<FinEnergy>({nb, e_self, partial, ctl, energy_out, list ? 1 : 0}, 1, 0, s);
+  const int nb2 = std::min(blocks_for((int64_t)(n_atoms + 63) / 64 * 64, kBlock), kPartialSlots / 2);
+  e = go<ShortRange<false>>({n_atoms, nc, excl_group, 64, box, alpha, rc2, k_e, pos, qa, cstart, cperm,
+                             (const double4*)spos, force, partial + nb, erfc_tab, erfc_n, erfc_scale, list, nlist,
+                             cap}, nb2, lds, s);
+  if (e != hipSuccess) return e;
+  return go<FinEnergy>({nb + nb2, e_self, partial, ctl, energy_out, 1}, 1, 0, s);
 }
