@@ -179,6 +179,21 @@ p3mz_status p3mz_md_run(p3mz_ctx* ctx, double* pos_dev, double* vel_dev, const d
                         const p3mz_mdterms* terms, double dt, int32_t n_steps,
                         double* energy_log_dev, int32_t* cycles_log_dev, void* stream);
 
+/* Langevin thermostat for p3mz_md_run, in the OVRVO splitting: each step
+ * starts with v <- a v + b sqrt(kT / (m * mv2_to_energy)) z (a = exp(-gamma
+ * dt / 2), b = sqrt(1 - a^2), z independent standard normals per component),
+ * then the half kick, the drift, the forces and the half kick, and ends with
+ * the same velocity update with new normals (Sivak, Chodera and Crooks' OVRVO
+ * scheme, the Langevin integrator of the paper's equilibration runs).  gamma
+ * is the friction in inverse time units of dt (0: no thermostat, plain
+ * velocity Verlet, the default); kT in energy units.  The normals come from
+ * Philox4x32-10 with key = seed and counter {atom, step (64 bits), end of the
+ * step (0, 1)}, uniforms (x + 1/2) 2^-32, then Box-Muller: (x0, x1) give the
+ * x and y normals, (x2, x3) the z normal.  The step counter restarts at 0 with
+ * every call; batched MD runs without a thermostat.  Synchronises the device.
+ * Errors: INVALID_ARG for negative or non-finite gamma or kT. */
+p3mz_status p3mz_set_thermostat(p3mz_ctx* ctx, double gamma, double kT, uint64_t seed);
+
 /* Launch mode.  By default (on = 1) each step is enqueued as three captured
  * HIP graphs -- before the solve, one V-cycle (replayed once per cycle), after
  * the solve -- captured on a private stream at first use and re-captured only

@@ -139,6 +139,12 @@ def lib() -> C.CDLL:
                                  C.c_int32, dp, ip]
         L.orc_nonelectrostatic.argtypes = [C.POINTER(MdTerms), C.c_int64, dp, C.c_double,
                                            C.c_double, dp, dp]
+        u32p = C.POINTER(C.c_uint32)
+        L.orc_set_thermostat.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_uint64]
+        L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.orc_philox4x32_10.restype = None
+        L.orc_thermo_normals.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.c_int, dp]
+        L.orc_thermo_normals.restype = None
         _lib = L
     return _lib
 
@@ -355,6 +361,12 @@ class Oracle:
         if rc:
             raise OracleError(rc)
 
+    def set_thermostat(self, gamma: float, kt: float, seed: int = 0):
+        """OVRVO Langevin thermostat for md_run (gamma 0: none); restarts its step counter."""
+        rc = lib().orc_set_thermostat(self._h, gamma, kt, seed)
+        if rc:
+            raise OracleError(rc)
+
     def md_run(self, pos, vel, mass, terms: MdTerms, dt, n_steps):
         pos = np.array(pos, dtype=np.float64, order="C", copy=True)
         vel = np.array(vel, dtype=np.float64, order="C", copy=True)
@@ -366,3 +378,19 @@ class Oracle:
         if rc < 0:
             raise OracleError(rc)
         return pos, vel, elog, clog, rc
+
+
+def philox4x32_10(counter, key):
+    """The oracle's Philox4x32-10: four 32-bit counter words, two key words -> four words."""
+    c = (C.c_uint32 * 4)(*counter)
+    k = (C.c_uint32 * 2)(*key)
+    out = (C.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, out)
+    return [int(v) for v in out]
+
+
+def thermo_normals(seed: int, atom: int, step: int, half: int) -> np.ndarray:
+    """The thermostat's three standard normals for (atom, step, end of the step)."""
+    z = np.zeros(3)
+    lib().orc_thermo_normals(seed, atom, step, half, _dp(z))
+    return z

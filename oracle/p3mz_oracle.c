@@ -75,6 +75,11 @@ struct orc_state {
   /* per-level multigrid work arrays */
   double *rho[ORC_MAX_LEVELS], *rl[ORC_MAX_LEVELS], *el[ORC_MAX_LEVELS];
   orc_stats st;
+  /* Langevin thermostat of the OVRVO scheme (gamma 0: none) and its step
+   * counter */
+  double th_gamma, th_kt;
+  uint64_t th_seed;
+  int64_t th_step;
 };
 
 /* ------------------------------------------------------------------------ */
@@ -869,8 +874,77 @@ int orc_nonelectrostatic(const orc_mdterms* t, int64_t n_atoms, const double* po
   return ORC_OK;
 }
 
+/* Philox4x32-10 as defined by Salmon, Moraes, Dror and Shaw (SC 2011):
+ * a round maps the counter (c0, c1, c2, c3) with key (k0, k1) to
+ * (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)) with
+ * M0 = 0xD2511F53, M1 = 0xCD9E8D57; the key grows by the Weyl increments
+ * (0x9E3779B9, 0xBB67AE85) after each of the ten rounds. */
+void orc_philox4x32_10(const uint32_t counter[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c[4] = {counter[0], counter[1], counter[2], counter[3]};
+  uint32_t k[2] = {key[0], key[1]};
+  const uint64_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  for (int round = 0; round < 10; round++) {
+    uint64_t prod0 = M0 * (uint64_t)c[0];
+    uint64_t prod1 = M1 * (uint64_t)c[2];
+    uint32_t n0 = (uint32_t)(prod1 >> 32) ^ c[1] ^ k[0];
+    uint32_t n1 = (uint32_t)(prod1 & 0xffffffffu);
+    uint32_t n2 = (uint32_t)(prod0 >> 32) ^ c[3] ^ k[1];
+    uint32_t n3 = (uint32_t)(prod0 & 0xffffffffu);
+    c[0] = n0; c[1] = n1; c[2] = n2; c[3] = n3;
+    k[0] = k[0] + 0x9E3779B9u;
+    k[1] = k[1] + 0xBB67AE85u;
+  }
+  for (int i = 0; i < 4; i++) out[i] = c[i];
+}
+
+/* The thermostat's three standard normals of atom a at step `step`, end
+ * `half` of the step: Philox with counter {a, low and high words of step,
+ * half} and key {low, high word of the seed}; the four words become
+ * uniforms (w + 1/2) / 2^32 in (0, 1); Box-Muller (Box and Muller 1958):
+ * z = sqrt(-2 ln u) (cos, sin)(2 pi v) for (u, v) = (u0, u1) gives the x and
+ * y normals, the cosine branch of (u2, u3) the z normal. */
+void orc_thermo_normals(uint64_t seed, int64_t a, int64_t step, int half, double z[3]) {
+  const uint32_t ctr[4] = {(uint32_t)a, (uint32_t)((uint64_t)step & 0xffffffffu), (uint32_t)((uint64_t)step >> 32),
+                           (uint32_t)half};
+  const uint32_t key[2] = {(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32)};
+  uint32_t w[4];
+  orc_philox4x32_10(ctr, key, w);
+  double u[4];
+  for (int i = 0; i < 4; i++) u[i] = ((double)w[i] + 0.5) / 4294967296.0;
+  const double two_pi = 2.0 * 3.14159265358979323846;
+  z[0] = sqrt(-2.0 * log(u[0])) * cos(two_pi * u[1]);
+  z[1] = sqrt(-2.0 * log(u[0])) * sin(two_pi * u[1]);
+  z[2] = sqrt(-2.0 * log(u[2])) * cos(two_pi * u[3]);
+}
+
+int orc_set_thermostat(orc_state* s, double gamma, double kt, uint64_t seed) {
+  if (!s || !(gamma >= 0.0) || !(kt >= 0.0) || !isfinite(gamma) || !isfinite(kt)) return ORC_ERR_INVALID_ARG;
+  s->th_gamma = gamma;
+  s->th_kt = kt;
+  s->th_seed = seed;
+  s->th_step = 0;
+  return ORC_OK;
+}
+
+/* The O part of the OVRVO splitting (Sivak, Chodera and Crooks 2014): an
+ * exact Ornstein-Uhlenbeck update of the velocities over dt/2,
+ * v <- c v + sqrt(1 - c^2) sqrt(kT / m') z with c = exp(-gamma dt / 2) and
+ * m' the mass in the units where the kinetic energy is m' v^2 / 2. */
+static void orc_thermo_half(const orc_state* s, double* vel, const double* mass, const orc_mdterms* t, double dt,
+                            int half) {
+  const double c = exp(-0.5 * s->th_gamma * dt);
+  const double sc = sqrt(1.0 - c * c);
+  for (int64_t a = 0; a < s->n; a++) {
+    double z[3];
+    orc_thermo_normals(s->th_seed, a, s->th_step, half, z);
+    const double sd = sqrt(s->th_kt / (mass[a] * t->mv2_to_energy));
+    for (int d = 0; d < 3; d++) vel[3 * a + d] = c * vel[3 * a + d] + sc * sd * z[d];
+  }
+}
+
 /* Velocity Verlet for the particles (Theory, numerical integration; the
- * mesh potential follows the Verlet/constraint update inside each compute). */
+ * mesh potential follows the Verlet/constraint update inside each compute),
+ * within the OVRVO scheme when a thermostat is set. */
 int orc_md_run(orc_state* s, double* pos, double* vel, const double* mass, const orc_mdterms* t,
                double dt, int32_t n_steps, double* energy_log, int32_t* cycles_log) {
   if (!s || !pos || !vel || !mass || !t || n_steps < 0) return ORC_ERR_INVALID_ARG;
@@ -886,6 +960,7 @@ int orc_md_run(orc_state* s, double* pos, double* vel, const double* mass, const
   if (rc < 0) { free(f); free(fo); return rc; }
   for (size_t k = 0; k < n3a; k++) f[k] += fo[k];
   for (int32_t step = 0; step < n_steps; step++) {
+    if (s->th_gamma > 0.0) orc_thermo_half(s, vel, mass, t, dt, 0);
     for (int64_t a = 0; a < s->n; a++)
       for (int d = 0; d < 3; d++) {
         vel[3 * a + d] += 0.5 * dt * f[3 * a + d] / mass[a] * t->force_to_acc;
@@ -897,13 +972,13 @@ int orc_md_run(orc_state* s, double* pos, double* vel, const double* mass, const
     rc = orc_nonelectrostatic(t, s->n, pos, s->P.box, s->P.r_cut, fo, &eo);
     if (rc < 0) { free(f); free(fo); return rc; }
     for (size_t k = 0; k < n3a; k++) f[k] += fo[k];
+    for (int64_t a = 0; a < s->n; a++)
+      for (int d = 0; d < 3; d++) vel[3 * a + d] += 0.5 * dt * f[3 * a + d] / mass[a] * t->force_to_acc;
+    if (s->th_gamma > 0.0) orc_thermo_half(s, vel, mass, t, dt, 1);
+    s->th_step++;
     double ekin = 0.0;
-    for (int64_t a = 0; a < s->n; a++) {
-      for (int d = 0; d < 3; d++) {
-        vel[3 * a + d] += 0.5 * dt * f[3 * a + d] / mass[a] * t->force_to_acc;
-        ekin += 0.5 * mass[a] * vel[3 * a + d] * vel[3 * a + d] * t->mv2_to_energy;
-      }
-    }
+    for (int64_t a = 0; a < s->n; a++)
+      for (int d = 0; d < 3; d++) ekin += 0.5 * mass[a] * vel[3 * a + d] * vel[3 * a + d] * t->mv2_to_energy;
     if (energy_log) {
       double* L = energy_log + 6 * (size_t)step;
       L[0] = e4[0]; L[1] = e4[1]; L[2] = e4[2]; L[3] = eo; L[4] = ekin;

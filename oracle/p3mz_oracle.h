@@ -130,6 +130,11 @@ int  orc_load_state(orc_state* s, const void* buf, size_t bytes);
 int  orc_md_run(orc_state* s, double* pos, double* vel, const double* mass,
                 const orc_mdterms* t, double dt, int32_t n_steps,
                 double* energy_log /* [n_steps][6] */, int32_t* cycles_log);
+/* OVRVO Langevin thermostat for orc_md_run (gamma 0: none); resets its step
+ * counter.  The generator and the normals are exported for their pins. */
+int  orc_set_thermostat(orc_state* s, double gamma, double kt, uint64_t seed);
+void orc_philox4x32_10(const uint32_t counter[4], const uint32_t key[2], uint32_t out[4]);
+void orc_thermo_normals(uint64_t seed, int64_t a, int64_t step, int half, double z[3]);
 int  orc_nonelectrostatic(const orc_mdterms* t, int64_t n_atoms, const double* pos,
                           double box, double r_cut, double* force, double* energy);
 

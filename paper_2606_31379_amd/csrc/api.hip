@@ -214,6 +214,8 @@ struct p3mz_ctx {
   Ctl* h_ctl = nullptr;         // pinned mirror
   double* d_energy = nullptr;   // internal energy4 when the caller passes none
   // md
+  double th_gamma = 0.0, th_kt = 0.0;   // OVRVO thermostat (gamma 0: none)
+  uint64_t th_seed = 0;
   double* d_md_force = nullptr;
   double* d_e_other = nullptr;
   bool md_have_force = false;
@@ -724,6 +726,7 @@ struct MdArgs {
   int* clog;
   double dt, f2a, mv2e, p[6];
   int model;
+  Thermostat th;
 };
 
 // the rest of an MD step after the mesh step: pairs, non-electrostatic
@@ -737,7 +740,7 @@ p3mz_status enq_md_post2(p3mz_ctx* c, const MdArgs& m, hipStream_t s) {
                               m.p[5], c->nc, c->d_cstart, c->d_cperm, c->d_spos, c->d_md_force, c->d_partial, c->d_e_other, s,
                               c->d_nbr, c->d_nlist, c->nbr_cap));
   rec_key(6101);
-  P3MZ_HIP_TRY(launch_kick_drift(na, m.pos, m.vel, c->d_md_force, m.mass, m.dt, m.f2a, 0, s));
+  P3MZ_HIP_TRY(launch_kick_drift(na, m.pos, m.vel, c->d_md_force, m.mass, m.dt, m.f2a, 0, s, &m.th));
   rec_key(6102);
   P3MZ_HIP_TRY(launch_kinetic_log(na, m.vel, m.mass, m.mv2e, c->d_energy, c->d_e_other, m.elog, m.clog, c->d_ctl,
                                   c->d_partial, s));
@@ -1490,6 +1493,12 @@ p3mz_status p3mz_md_run(p3mz_ctx* ctx, double* pos_dev, double* vel_dev, const d
   m.f2a = terms->force_to_acc;
   m.mv2e = terms->mv2_to_energy;
   m.model = terms->model;
+  m.th = Thermostat{0, 1.0, 0.0, 0.0, 1.0, 0u, 0u, nullptr};
+  if (ctx->th_gamma > 0.0) {
+    const double a = exp(-0.5 * ctx->th_gamma * dt);
+    m.th = Thermostat{1, a, sqrt(1.0 - a * a), ctx->th_kt, m.mv2e, (unsigned)ctx->th_seed,
+                      (unsigned)(ctx->th_seed >> 32), ctx->d_ctl};
+  }
   if (terms->model == 1) {
     m.p[0] = terms->bm_a;
     m.p[1] = terms->bm_rho;
@@ -1502,6 +1511,9 @@ p3mz_status p3mz_md_run(p3mz_ctx* ctx, double* pos_dev, double* vel_dev, const d
                                      (uint64_t)(uintptr_t)energy_log_dev, (uint64_t)(uintptr_t)cycles_log_dev,
                                      (uint64_t)m.model, bits(m.mv2e)};
   for (double v : m.p) key_post2.push_back(bits(v));
+  for (double v : {m.th.a, m.th.b, m.th.kt}) key_post2.push_back(bits(v));
+  key_post2.push_back(ctx->th_seed);
+  key_post2.push_back((uint64_t)m.th.on);
   P3MZ_HIP_TRY(hipMemsetAsync(&ctx->d_ctl->md_step, 0, sizeof(int), s));   // eager, never captured
   if (!ctx->md_have_force) {
     // forces at the initial positions (a cold solve on first use); no log row
@@ -1517,7 +1529,8 @@ p3mz_status p3mz_md_run(p3mz_ctx* ctx, double* pos_dev, double* vel_dev, const d
   }
   p3mz_status worst = P3MZ_OK;
   for (int step = 0; step < n_steps; step++) {
-    P3MZ_HIP_TRY(launch_kick_drift((int)ctx->n_atoms, pos_dev, vel_dev, ctx->d_md_force, mass_dev, dt, m.f2a, 1, s));
+    P3MZ_HIP_TRY(launch_kick_drift((int)ctx->n_atoms, pos_dev, vel_dev, ctx->d_md_force, mass_dev, dt, m.f2a, 1, s,
+                                   &m.th));
     P3MZ_TRY(mesh_step(ctx, pos_dev, ctx->d_md_force, ctx->d_energy, s, key_post2, true, &m));
     if (ctx->h_ctl->status) worst = P3MZ_WARN_NOT_CONVERGED;
     ctx->last_cycles = ctx->h_ctl->cycles;
@@ -1656,6 +1669,19 @@ p3mz_status p3mz_set_neighbor_list(p3mz_ctx* ctx, double skin, int32_t capacity)
     return fail(P3MZ_ERR_INVALID_ARG, "skin must be in [0, r_cut] and capacity >= 0");
   P3MZ_HIP_TRY(hipDeviceSynchronize());
   return nbr_configure(ctx, skin, capacity);
+}
+
+p3mz_status p3mz_set_thermostat(p3mz_ctx* ctx, double gamma, double kt, uint64_t seed) {
+  if (!ctx) return fail(P3MZ_ERR_INVALID_ARG, "ctx is NULL");
+  if (!(gamma >= 0.0) || !(kt >= 0.0) || !isfinite(gamma) || !isfinite(kt))
+    return fail(P3MZ_ERR_INVALID_ARG, "gamma and kT must be finite and >= 0");
+  P3MZ_HIP_TRY(hipDeviceSynchronize());
+  ctx->th_gamma = gamma;
+  ctx->th_kt = kt;
+  ctx->th_seed = seed;
+  const long long zero = 0;
+  P3MZ_HIP_TRY(hipMemcpy(&ctx->d_ctl->therm_step, &zero, sizeof zero, hipMemcpyHostToDevice));
+  return P3MZ_OK;
 }
 
 p3mz_status p3mz_get_neighbor_stats(const p3mz_ctx* ctx, int64_t* builds, int64_t* over_capacity,

@@ -43,6 +43,17 @@ struct Ctl {
   long long nbr_builds;  // neighbour-list builds so far
   int nbr_over;          // atoms whose neighbours exceeded the list capacity at the last build
   int pad2;
+  long long therm_step;  // MD steps since the thermostat was set (counter of its random numbers)
+};
+
+// Langevin thermostat of the OVRVO splitting: v <- a v + b sqrt(kT / (m e)) z
+// at both ends of a step (e = the mass-velocity-to-energy factor), z standard
+// normals from the counter-based generator keyed by seed.
+struct Thermostat {
+  int on;
+  double a, b, kt, mv2e;
+  unsigned seed0, seed1;
+  const Ctl* ctl;   // therm_step
 };
 
 // --- wave / block reductions (wave64) ------------------------------------

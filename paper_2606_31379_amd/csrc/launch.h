@@ -163,8 +163,10 @@ hipError_t smooth_configure();
 hipError_t fused_configure();
 
 // ---- molecular dynamics (md.hip) ----------------------------------------
+// th (null: none): the OVRVO thermostat halves at the two ends of the step.
 hipError_t launch_kick_drift(int n_atoms, double* pos, double* vel, const double* force,
-                             const double* mass, double dt, double f2a, int drift, hipStream_t s);
+                             const double* mass, double dt, double f2a, int drift, hipStream_t s,
+                             const Thermostat* th = nullptr);
 hipError_t launch_nonelec(int n_atoms, const double* pos, double box, double r_cut, int model,
                           double p0, double p1, double p2, double p3, double p4, double p5,
                           int nc, const int* cstart, const int* cperm, const void* spos, double* force,

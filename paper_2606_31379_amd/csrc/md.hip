@@ -12,12 +12,47 @@ constexpr int kBlock = 256;
 
 inline int blocks_for(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, "Parallel random numbers:
+// as easy as 1, 2, 3", SC 2011): ten rounds of two 32x32->64-bit multiplies
+// on the 128-bit counter, the 64-bit key bumped by the Weyl constants
+// between rounds.
+__device__ __forceinline__ void philox4x32_10(unsigned x[4], unsigned k0, unsigned k1) {
+#pragma unroll
+  for (int r = 0; r < 10; r++) {
+    const unsigned long long p0 = 0xD2511F53ull * x[0], p1 = 0xCD9E8D57ull * x[2];
+    const unsigned y0 = (unsigned)(p1 >> 32) ^ x[1] ^ k0, y1 = (unsigned)p1;
+    const unsigned y2 = (unsigned)(p0 >> 32) ^ x[3] ^ k1, y3 = (unsigned)p0;
+    x[0] = y0; x[1] = y1; x[2] = y2; x[3] = y3;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+}
+
+// Standard normal number d (0..2) of atom a at thermostat step `step`, end
+// `half` of the step: counter {a, step low, step high, half}, key = seed;
+// uniforms (x + 1/2) 2^-32, then the Box-Muller transform of the pairs
+// (u0, u1) -> normals 0, 1 and (u2, u3) -> normal 2.
+__device__ __forceinline__ double thermo_normal(const Thermostat& T, int a, long long step, int half, int d) {
+  unsigned x[4] = {(unsigned)a, (unsigned)(unsigned long long)step, (unsigned)((unsigned long long)step >> 32),
+                   (unsigned)half};
+  philox4x32_10(x, T.seed0, T.seed1);
+  const double s = 1.0 / 4294967296.0;
+  const unsigned ur = d < 2 ? x[0] : x[2], ua = d < 2 ? x[1] : x[3];
+  const double r = sqrt(-2.0 * log(((double)ur + 0.5) * s));
+  const double ang = 2.0 * M_PI * (((double)ua + 0.5) * s);
+  return d == 1 ? r * sin(ang) : r * cos(ang);
+}
+
+// One thread per velocity component.  drift: the start of a step (the
+// thermostat's first half, the half kick, the drift); otherwise its end
+// (the half kick, the thermostat's second half).
 struct KickDrift {
   struct Args {
     int n_atoms, drift;
     double dt, f2a;
     double *pos, *vel;
     const double *f, *mass;
+    Thermostat th;
   };
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G);
@@ -32,7 +67,13 @@ __device__ void KickDrift::run(const Args& A, Grid G) {
   const int t = G.b * kBlock + threadIdx.x;
   if (t >= 3 * n_atoms) return;
   const int a = t / 3;
-  double v = vel[t] + 0.5 * dt * f[t] / mass[a] * f2a;
+  const Thermostat& T = A.th;
+  double v = vel[t];
+  if (drift && T.on)
+    v = T.a * v + T.b * sqrt(T.kt / (mass[a] * T.mv2e)) * thermo_normal(T, a, T.ctl->therm_step, 0, t - 3 * a);
+  v += 0.5 * dt * f[t] / mass[a] * f2a;
+  if (!drift && T.on)
+    v = T.a * v + T.b * sqrt(T.kt / (mass[a] * T.mv2e)) * thermo_normal(T, a, T.ctl->therm_step, 1, t - 3 * a);
   vel[t] = v;
   if (drift) pos[t] += dt * v;
 }
@@ -268,15 +309,17 @@ __device__ void FinLog::run(const Args& A, Grid) {
     }
     if (clog_base) clog_base[k] = ctl->cycles;
     ctl->md_step = k + 1;
+    ctl->therm_step++;
   }
 }
 
 }  // namespace
 
 hipError_t launch_kick_drift(int n_atoms, double* pos, double* vel, const double* force, const double* mass,
-                             double dt, double f2a, int drift, hipStream_t s) {
-  return go<KickDrift>({n_atoms, drift, dt, f2a, pos, vel, force, mass}, blocks_for(3 * (int64_t)n_atoms, kBlock), 0,
-                       s);
+                             double dt, double f2a, int drift, hipStream_t s, const Thermostat* th) {
+  const Thermostat off{0, 1.0, 0.0, 0.0, 1.0, 0u, 0u, nullptr};
+  return go<KickDrift>({n_atoms, drift, dt, f2a, pos, vel, force, mass, th ? *th : off},
+                       blocks_for(3 * (int64_t)n_atoms, kBlock), 0, s);
 }
 
 hipError_t launch_nonelec(int n_atoms, const double* pos, double box, double r_cut, int model, double p0,

@@ -33,7 +33,7 @@ EXPORTS = ["p3mz_create", "p3mz_compute", "p3mz_get_mesh", "p3mz_vcycle", "p3mz_
            "p3mz_reset_history", "p3mz_save_state", "p3mz_load_state", "p3mz_md_run",
            "p3mz_set_graphs", "p3mz_set_timing", "p3mz_set_kernel_timer", "p3mz_get_kernel_timer",
            "p3mz_kernel_bench", "p3mz_set_schedule", "p3mz_set_fused_levels",
-           "p3mz_set_neighbor_list", "p3mz_get_neighbor_stats", "p3mz_autotune",
+           "p3mz_set_neighbor_list", "p3mz_get_neighbor_stats", "p3mz_set_thermostat", "p3mz_autotune",
            "p3mz_destroy", "p3mz_batch_create", "p3mz_batch_compute", "p3mz_batch_md_run",
            "p3mz_batch_get_stats", "p3mz_batch_set_timing", "p3mz_batch_get_timing", "p3mz_batch_set_graphs",
            "p3mz_batch_kernel_bench", "p3mz_batch_destroy", "p3mz_status_string", "p3mz_last_error", "p3mz_version"]
@@ -109,6 +109,7 @@ def _load() -> C.CDLL:
         "p3mz_set_schedule": ([vp, C.c_int32, C.c_int32, C.c_int32], C.c_int),
         "p3mz_set_fused_levels": ([vp, C.c_int32], C.c_int),
         "p3mz_set_neighbor_list": ([vp, C.c_double, C.c_int32], C.c_int),
+        "p3mz_set_thermostat": ([vp, C.c_double, C.c_double, C.c_uint64], C.c_int),
         "p3mz_get_neighbor_stats": ([vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int32)], C.c_int),
         "p3mz_autotune": ([vp, vp, C.c_int32, vp, C.POINTER(p3mz_tune_result)], C.c_int),
         "p3mz_destroy": ([vp], None),
@@ -230,6 +231,10 @@ def p3mz_set_fused_levels(ctx: int, max_edge: int) -> int:
 
 def p3mz_set_neighbor_list(ctx: int, skin: float, capacity: int = 0) -> int:
     return _check(lib.p3mz_set_neighbor_list(ctx, skin, capacity), "p3mz_set_neighbor_list")
+
+
+def p3mz_set_thermostat(ctx: int, gamma: float, kt: float, seed: int = 0) -> int:
+    return _check(lib.p3mz_set_thermostat(ctx, gamma, kt, seed), "p3mz_set_thermostat")
 
 
 def p3mz_get_neighbor_stats(ctx: int) -> tuple[int, int, int]:
