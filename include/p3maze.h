@@ -278,7 +278,8 @@ p3mz_status p3mz_set_fused_levels(p3mz_ctx* ctx, int32_t max_edge);
  * Default: skin 0.1 r_cut, automatic capacity; systems of a batch scan the
  * cells.  Synchronises the device; graphs are recaptured; the next step
  * builds the lists.  Errors: INVALID_ARG for skin outside [0, r_cut] or
- * capacity < 0; OUT_OF_MEMORY. */
+ * capacity < 0 (the lists stay as they were); OUT_OF_MEMORY or HIP (the
+ * context is left without lists, scanning the cells). */
 p3mz_status p3mz_set_neighbor_list(p3mz_ctx* ctx, double skin, int32_t capacity);
 
 /* Neighbour-list builds so far, atoms found over capacity summed over those

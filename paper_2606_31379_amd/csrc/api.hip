@@ -428,28 +428,44 @@ p3mz_status nbr_configure(p3mz_ctx* c, double skin, int cap) {
   c->release(c->d_ref);
   c->d_nbr = c->d_nlist = nullptr;
   c->d_ref = nullptr;
-  c->nbr_skin = skin;
+  c->nbr_skin = 0.0;
   c->nbr_cap = 0;
   c->drop_graphs();
-  const double rl = c->P.r_cut + skin;
-  c->nc = cells_per_edge(c->P.box, rl);
+  // without lists until the new ones are in place: a failure below leaves
+  // the context scanning cells of edge r_cut
+  c->nc = cells_per_edge(c->P.box, c->P.r_cut);
   c->ncells = c->nc * c->nc * c->nc;
-  if (c->ncells > c->ncells_max) return fail(P3MZ_ERR_STATE, "cell list larger than allocated");
   if (skin <= 0.0) return P3MZ_OK;
+  const double rl = c->P.r_cut + skin;
   const int64_t na = c->n_atoms;
   if (cap <= 0) {
     const double expect = 4.0 / 3.0 * kPi * rl * rl * rl * (double)na / (c->P.box * c->P.box * c->P.box);
     cap = (int)std::min<double>(1.3 * expect + 64.0, (double)(1 << 24));
   }
   cap = (int)std::min<int64_t>((cap + 63) / 64 * 64, (std::max<int64_t>(na - 1, 1) + 63) / 64 * 64);
-  c->nbr_cap = cap;
-  P3MZ_TRY(c->alloc(&c->d_nbr, (size_t)na * cap));
-  P3MZ_TRY(c->alloc(&c->d_nlist, (size_t)na));
-  P3MZ_TRY(c->alloc(&c->d_ref, 4 * (size_t)na));
-  // NaN reference positions: the first check flags a build
-  P3MZ_HIP_TRY(hipMemset(c->d_ref, 0xff, sizeof(double) * 4 * (size_t)na));
+  int *nbr = nullptr, *nlist = nullptr;
+  double* ref = nullptr;
+  p3mz_status st = c->alloc(&nbr, (size_t)na * cap);
+  if (st == P3MZ_OK) st = c->alloc(&nlist, (size_t)na);
+  if (st == P3MZ_OK) st = c->alloc(&ref, 4 * (size_t)na);
+  hipError_t e = hipSuccess;
   const int one = 1;
-  P3MZ_HIP_TRY(hipMemcpy(&c->d_ctl->nbr_stale, &one, sizeof(int), hipMemcpyHostToDevice));
+  // NaN reference positions: the first check flags a build
+  if (st == P3MZ_OK) e = hipMemset(ref, 0xff, sizeof(double) * 4 * (size_t)na);
+  if (st == P3MZ_OK && e == hipSuccess) e = hipMemcpy(&c->d_ctl->nbr_stale, &one, sizeof(int), hipMemcpyHostToDevice);
+  if (st != P3MZ_OK || e != hipSuccess) {
+    c->release(nbr);
+    c->release(nlist);
+    c->release(ref);
+    return st != P3MZ_OK ? st : hip_fail(e, "neighbour-list set-up", __FILE__, __LINE__);
+  }
+  c->nc = cells_per_edge(c->P.box, rl);
+  c->ncells = c->nc * c->nc * c->nc;
+  c->d_nbr = nbr;
+  c->d_nlist = nlist;
+  c->d_ref = ref;
+  c->nbr_skin = skin;
+  c->nbr_cap = cap;
   return P3MZ_OK;
 }
 
