@@ -138,7 +138,10 @@ def autotune_schedule(torch, P, w, system, precision, warmup, n_frames=8):
         P.p3mz_destroy(ctx)
 
 
-def run_mode(torch, P, w, system, precision, warmup, steps, kernel, schedule=None, skin=None):
+K_B_EV = 8.617333262e-5   # Boltzmann constant, eV/K
+
+
+def run_mode(torch, P, w, system, precision, warmup, steps, kernel, schedule=None, skin=None, gamma=None):
     """Warm up, pick the dominant kernel family, then time `steps` MD steps."""
     import numpy as np
     dev = torch.device("cuda")
@@ -146,6 +149,8 @@ def run_mode(torch, P, w, system, precision, warmup, steps, kernel, schedule=Non
     try:
         if skin is not None:
             P.p3mz_set_neighbor_list(ctx, skin)
+        if gamma:
+            P.p3mz_set_thermostat(ctx, gamma, K_B_EV * w.temp_k, w.seed)
         if schedule:
             P.p3mz_set_schedule(ctx, schedule["nu_pre"], schedule["nu_post"], schedule["smooth_tile"])
         pos = torch.from_numpy(np.ascontiguousarray(system.pos)).to(dev)
@@ -218,6 +223,9 @@ def run_mode(torch, P, w, system, precision, warmup, steps, kernel, schedule=Non
             md_ms_per_step=wall * 1e3 / steps,
             short_range_ms_per_step=sr_ms_tot / steps, graphs=bool(graphs),
             neighbor_lists=dict(capacity=cap, builds_per_step=(builds - builds0) / steps, over_capacity_atoms=over),
+            kinetic_temperature_k=[float(2.0 * e / (3.0 * system.n * K_B_EV)) for e in
+                                   (energies[0, 4], energies[-1, 4])] if steps > 0 else None,
+            thermostat=dict(gamma_per_fs=gamma, kt_ev=K_B_EV * w.temp_k) if gamma else None,
             vcycles_per_step=float(cycles.mean()), vcycles_min=int(cycles.min()), vcycles_max=int(cycles.max()),
             energy_drift_per_step=float(np.polyfit(np.arange(steps), energies[:, 5], 1)[0]) if steps > 2 else None,
             kernel_ms_per_step=shares, dominant=dominant,
@@ -520,6 +528,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--modes", default="fp64,mixed", help="precision modes to run (the headline is mixed)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default (2,2) V-cycle schedule")
+    ap.add_argument("--gamma", type=float, default=None,
+                    help="OVRVO thermostat friction in 1/fs at the workload's temperature (default: none)")
     ap.add_argument("--skin", type=float, default=None,
                     help="neighbour-list skin in box units (0: scan the cells every step; default: 0.1 r_cut)")
     ap.add_argument("--predictor", type=int, default=None,
@@ -566,7 +576,7 @@ def main():
             log(f"[{name}] autotune: {json.dumps({k: v for k, v in tune[name].items() if k != 'candidates'})}")
         log(f"[{name}] warmup {args.warmup}, timed {args.steps}")
         res[name] = run_mode(torch, P, w, system, precision, args.warmup, args.steps, args.kernel, schedules[name],
-                             args.skin)
+                             args.skin, args.gamma)
         log(f"[{name}] {json.dumps({k: v for k, v in res[name].items() if k != 'kernel_ms_per_step'})}")
     parity, baseline = None, None
     if not args.no_cpu_baseline:
