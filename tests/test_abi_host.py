@@ -72,3 +72,15 @@ def test_product_package_never_uses_the_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert not pat.search(txt), f
+
+
+def test_null_context_rejected_by_the_md_and_pair_options():
+    """The neighbour-list and thermostat entry points check their arguments
+    before any device call (no GPU needed)."""
+    import ctypes as C
+    from paper_2606_31379_amd import p3maze as P
+    L = P.lib
+    assert L.p3mz_set_neighbor_list(None, 0.5, 0) == P.P3MZ_ERR_INVALID_ARG
+    assert L.p3mz_set_thermostat(None, 0.1, 0.025, 1) == P.P3MZ_ERR_INVALID_ARG
+    b, o, c = C.c_int64(), C.c_int64(), C.c_int32()
+    assert L.p3mz_get_neighbor_stats(None, C.byref(b), C.byref(o), C.byref(c)) == P.P3MZ_ERR_INVALID_ARG
