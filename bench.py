@@ -36,8 +36,16 @@ HBM_PEAK_GBPS = 8000.0
 METRIC = "mesh-step ns/atom (spread+MG+gather) & HBM GB/s vs roofline, mixed vs FP64"
 
 
+T0 = time.perf_counter()
+PHASES = {}   # wall seconds of each part of the run, for the time budget
+
+
 def log(*a):
-    print(*a, file=sys.stderr, flush=True)
+    print(f"[{time.perf_counter() - T0:7.1f}s]", *a, file=sys.stderr, flush=True)
+
+
+def phase(name, t_start):
+    PHASES[name] = round(PHASES.get(name, 0.0) + time.perf_counter() - t_start, 2)
 
 
 def md_terms(P, kind):
@@ -89,6 +97,19 @@ def measured_traffic(kernel, workload, mode):
     if vals.get("source_sha256") != source_digest():
         return None, f"{os.path.relpath(path, ROOT)} predates the current kernels"
     return float(vals["hbm_bytes_per_launch"]), os.path.relpath(path, ROOT)
+
+
+def mg_sweep_roofline(fam):
+    """Bandwidth of the finest-level multigrid sweep kernels together
+    (red-black half-sweeps, the first sweep from zero, fused legs)."""
+    ms = sum(fam[k]["avg_active_launch_us"] * fam[k]["active_launches"] for k in
+             ("halfsweep", "sweep0", "fused_down", "fused_up") if fam.get(k) and fam[k]["active_launches"])
+    by = sum(fam[k]["bytes_per_active_launch"] * fam[k]["active_launches"] for k in
+             ("halfsweep", "sweep0", "fused_down", "fused_up") if fam.get(k) and fam[k]["active_launches"])
+    if ms <= 0:
+        return None
+    gbps = by / (ms * 1e-6) / 1e9
+    return dict(achieved=gbps, frac=gbps / HBM_PEAK_GBPS, kernels="halfsweep+sweep0+fused legs, finest level")
 
 
 def copy_ceiling_gbps(torch, nbytes=1 << 30, reps=10):
@@ -169,20 +190,33 @@ def run_mode(torch, P, w, system, precision, warmup, steps, kernel, schedule=Non
                               clog[offset + k].data_ptr() if with_logs else None, stream)
 
         md(warmup)
-        # which kernel family takes the most time per step
-        shares = {}
+        # Per-family kernel time: `probe` MD steps launched kernel by kernel
+        # with HIP events around every finest-level launch of one family (on
+        # the library's stream).  Launches that found the solve converged (a
+        # speculative cycle beyond the step's count, a field update enqueued
+        # before the last cycle) return at once; they are counted apart as
+        # idle (below a quarter of the family's longest launch).
+        shares, fam = {}, {}
         P.p3mz_set_timing(ctx, True)
         probe = max(2, min(5, steps))
         for name, kid in P.KERNELS.items():
             P.p3mz_set_kernel_timer(ctx, kid)
             md(probe)
-            ms, n, _ = P.p3mz_get_kernel_timer(ctx)
-            shares[name] = ms / probe
-        # the roofline is taken for the mesh step (the short-range pair kernel is
-        # outside the measured metric) and for HBM-bound kernels: the tail runs
-        # the coarse levels in one workgroup, bound by its own latency, and is
-        # reported as a share instead
-        mesh_shares = {k: v for k, v in shares.items() if k not in ("sr", "tail")}
+            ms_l, by_l = P.p3mz_get_kernel_launches(ctx)
+            shares[name] = sum(ms_l) / probe
+            top = max(ms_l) if ms_l else 0.0
+            act = [(m, b) for m, b in zip(ms_l, by_l) if m >= 0.25 * top and m > 0]
+            a_ms = sum(m for m, _ in act)
+            a_by = sum(b for _, b in act)
+            fam[name] = dict(ms_per_step=shares[name], launches=len(ms_l), active_launches=len(act),
+                             avg_active_launch_us=1e3 * a_ms / len(act) if act else None,
+                             bytes_per_active_launch=a_by / len(act) if act else None,
+                             active_bytes_per_step=a_by / probe,
+                             gbps=a_by / (a_ms * 1e-3) / 1e9 if a_ms > 0 else None)
+        P.p3mz_set_kernel_timer(ctx, -1)
+        # the dominant family of the mesh step (the short-range pair kernel is
+        # outside the measured metric), by its share of the step
+        mesh_shares = {k: v for k, v in shares.items() if k != "sr"}
         dominant = kernel if kernel != "auto" else max(mesh_shares, key=mesh_shares.get)
         log(f"[{'fp64' if precision == 0 else 'mixed'}] kernel ms/step: "
             + ", ".join(f"{k}={v:.4f}" for k, v in sorted(shares.items(), key=lambda x: -x[1])))
@@ -202,21 +236,17 @@ def run_mode(torch, P, w, system, precision, warmup, steps, kernel, schedule=Non
         builds, over, cap = P.p3mz_get_neighbor_stats(ctx)
         cycles = clog.cpu().numpy()[:steps]
         energies = elog.cpu().numpy()[:steps]
-        # Roofline: the dominant family's finest-level kernel launched back to
-        # back on the live buffers of the last timed step, HIP events on the
-        # library's stream.  (Events around every single in-step launch add a
-        # few microseconds of event overhead to a ~3 us kernel; back-to-back
-        # launches agree with the profiler's per-dispatch durations.)
+        # Back-to-back launches of the dominant family's finest-level kernel
+        # on the live buffers of the last timed step (a cross-check of the
+        # in-step durations above).
         burst_ok = dominant in ("halfsweep", "sweep0", "restrict", "prolong", "tail", "fused_down", "fused_up",
                                 "smooth", "outer", "sigma",
                                 "spread", "gather")
-        reps = 200
-        kms, kbytes = P.p3mz_kernel_bench(ctx, P.KERNELS[dominant], reps, stream) if burst_ok else (float("nan"), 0.0)
-        klaunch = reps if burst_ok else 0
-        kms, kbytes = kms * klaunch, kbytes * klaunch
+        reps = 20 if system.n > 1_000_000 else 200
+        bms, _ = P.p3mz_kernel_bench(ctx, P.KERNELS[dominant], reps, stream) if burst_ok else (float("nan"), 0.0)
         mesh_ms = mesh_ms_tot / steps
-        avg_launch_ms = kms / max(klaunch, 1)
-        bytes_per_launch = kbytes / max(klaunch, 1)
+        d = fam[dominant]
+        step_bytes = sum(f["active_bytes_per_step"] for k, f in fam.items() if k != "sr")
         out = dict(
             ns_per_atom=mesh_ms * 1e6 / system.n,
             mesh_ms_per_step=mesh_ms,
@@ -228,11 +258,17 @@ def run_mode(torch, P, w, system, precision, warmup, steps, kernel, schedule=Non
             thermostat=dict(gamma_per_fs=gamma, kt_ev=K_B_EV * w.temp_k) if gamma else None,
             vcycles_per_step=float(cycles.mean()), vcycles_min=int(cycles.min()), vcycles_max=int(cycles.max()),
             energy_drift_per_step=float(np.polyfit(np.arange(steps), energies[:, 5], 1)[0]) if steps > 2 else None,
-            kernel_ms_per_step=shares, dominant=dominant,
-            latency_bound_tail_share=shares.get("tail", 0.0) / max(sum(v for k, v in shares.items() if k != "sr"), 1e-12),
-            dominant_avg_launch_us=avg_launch_ms * 1e3, dominant_launches=int(klaunch),
-            dominant_bytes_per_launch=bytes_per_launch,
-            dominant_gbps=bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9 if klaunch else None,
+            kernel_ms_per_step=shares, kernel_families=fam, dominant=dominant,
+            dominant_share=shares[dominant] / max(sum(mesh_shares.values()), 1e-12),
+            dominant_avg_launch_us=d["avg_active_launch_us"], dominant_launches=d["active_launches"],
+            dominant_idle_launches=d["launches"] - d["active_launches"],
+            dominant_bytes_per_launch=d["bytes_per_active_launch"], dominant_gbps=d["gbps"],
+            dominant_burst_avg_launch_us=bms * 1e3 if burst_ok else None,
+            # finest-level algorithmic bytes of every mesh kernel per step over
+            # the mesh-step time (coarse levels add at most 1/7 of the V-cycle's)
+            whole_step=dict(finest_level_bytes=step_bytes, mesh_ms=mesh_ms,
+                            gbps=step_bytes / (mesh_ms * 1e-3) / 1e9,
+                            frac=step_bytes / (mesh_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS),
             schedule=dict(nu_pre=P.p3mz_get_stats(ctx).nu_pre, nu_post=P.p3mz_get_stats(ctx).nu_post,
                           smooth_tile=schedule["smooth_tile"] if schedule else 0),
         )
@@ -282,7 +318,7 @@ def parity_and_baseline(torch, P, w, system, sample_steps, schedules):
     targets = None
     if system.n > 20000:
         rng = np.random.Generator(np.random.PCG64(w.seed + 17))
-        targets = np.sort(rng.choice(system.n, size=512, replace=False))
+        targets = np.sort(rng.choice(system.n, size=1000 if system.n > 2_000_000 else 512, replace=False))
     runs = {}
     out = {}
     dev = torch.device("cuda")
@@ -522,7 +558,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="water-3000")
+    ap.add_argument("--workload", default="water-7999998")
     ap.add_argument("--kernel", default="auto", help="kernel family for the roofline (default: dominant)")
     ap.add_argument("--cpu-sample-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -555,8 +591,11 @@ def main():
     if args.predictor is not None:
         import dataclasses
         w = dataclasses.replace(w, predictor=args.predictor)
+    PHASES["startup"] = round(time.perf_counter() - T0, 2)
     log(f"workload {w.name}: generating inputs")
+    t = time.perf_counter()
     system = w.system(progress=lambda msg: log(f"[inputs] {msg}"))
+    phase("inputs", t)
     log(f"atoms {system.n} box {system.box} mesh {w.mesh}^3 order {w.order} tol {w.tol}")
     ceiling = copy_ceiling_gbps(torch)
     log(f"device copy ceiling {ceiling:.0f} GB/s")
@@ -571,17 +610,23 @@ def main():
         if args.no_tune:
             schedules[name] = dict(nu_pre=2, nu_post=2, smooth_tile=0)
         else:
+            t = time.perf_counter()
             tune[name] = autotune_schedule(torch, P, w, system, precision, args.warmup)
+            phase("autotune", t)
             schedules[name] = {k: tune[name][k] for k in ("nu_pre", "nu_post", "smooth_tile")}
             log(f"[{name}] autotune: {json.dumps({k: v for k, v in tune[name].items() if k != 'candidates'})}")
         log(f"[{name}] warmup {args.warmup}, timed {args.steps}")
+        t = time.perf_counter()
         res[name] = run_mode(torch, P, w, system, precision, args.warmup, args.steps, args.kernel, schedules[name],
                              args.skin, args.gamma)
-        log(f"[{name}] {json.dumps({k: v for k, v in res[name].items() if k != 'kernel_ms_per_step'})}")
+        phase("gpu_runs", t)
+        log(f"[{name}] {json.dumps({k: v for k, v in res[name].items() if k not in ('kernel_ms_per_step', 'kernel_families')})}")
     parity, baseline = None, None
     if not args.no_cpu_baseline:
         sample = args.cpu_sample_steps or (8 if system.n <= 4000 else 3 if system.n <= 2_000_000 else 2)
+        t = time.perf_counter()
         parity, baseline = parity_and_baseline(torch, P, w, system, sample, schedules)
+        phase("oracle_parity_and_baseline", t)
     m, f = res.get("mixed"), res.get("fp64")
     head = m if m is not None else f
     traffic, traffic_note = measured_traffic(head["dominant"], w.name, "mixed" if m is not None else "fp64")
@@ -589,6 +634,10 @@ def main():
                 unit="GB/s", frac=(head["dominant_gbps"] / HBM_PEAK_GBPS) if head["dominant_gbps"] else None,
                 traffic=traffic, traffic_source=traffic_note, avg_launch_us=head["dominant_avg_launch_us"],
                 alg_bytes_per_launch=head["dominant_bytes_per_launch"], launches=head["dominant_launches"],
+                idle_launches=head["dominant_idle_launches"], share_of_mesh_step=head["dominant_share"],
+                burst_avg_launch_us=head["dominant_burst_avg_launch_us"],
+                whole_step_frac=head["whole_step"]["frac"],
+                mg_sweeps=mg_sweep_roofline(head["kernel_families"]),
                 copy_ceiling_GBps=ceiling)
     line = dict(
         metric=METRIC, value=head["ns_per_atom"], unit="ns/atom/step", n_gpus=1, steps=args.steps,
@@ -601,6 +650,8 @@ def main():
         speedup_mixed_vs_fp64=(f["mesh_ms_per_step"] / m["mesh_ms_per_step"]) if (m and f) else None,
         roofline=roof, cpu_baseline=baseline, parity=parity,
     )
+    PHASES["total"] = round(time.perf_counter() - T0, 2)
+    line["phase_s"] = PHASES
     print(json.dumps(line), flush=True)
 
 

@@ -108,6 +108,12 @@ typedef struct {
    * mesh step into spread+smoothing / solve+update / gather only when the
    * step was launched kernel by kernel (else -1). */
   double ms_mesh, ms_short_range, ms_spread, ms_solve, ms_gather;
+  /* sum over all atoms of the electrostatic force (short range + mesh) the
+   * last compute wrote: zero up to rounding for the pair part, and to the
+   * solver tolerance for the mesh part (the central-difference gradient is
+   * antisymmetric; Eq. 21 and the momentum paragraph after it).  NaN when
+   * the call wrote no forces. */
+  double net_force[3];
 } p3mz_stats;
 
 typedef struct p3mz_ctx p3mz_ctx;
@@ -135,6 +141,13 @@ p3mz_status p3mz_compute(p3mz_ctx* ctx, const double* pos_dev, double* force_dev
  * (zero-mean), 3 multiplier y, 4 potential phi^{k+1}, 5 previous potential.
  * FP32 meshes of the mixed mode are widened exactly. */
 p3mz_status p3mz_get_mesh(p3mz_ctx* ctx, int32_t which, double* out_dev, void* stream);
+
+/* The mesh potential phi^{k+1} of the last compute (the field the forces
+ * were interpolated from; Eq. 21 and the field update of the Supporting
+ * Information) into phi_dev ([N][N][N] doubles, x fastest, zero mean, the
+ * potential of the smoothed charges in coulomb_k = 1 units).  Same as
+ * p3mz_get_mesh(ctx, 4, ...).  Enqueued on stream.  Errors: INVALID_ARG. */
+p3mz_status p3mz_get_potential(p3mz_ctx* ctx, double* phi_dev, void* stream);
 
 /* One V-cycle of the context's schedule for M e = r on the finest mesh:
  * r_dev, e_dev [N][N][N] doubles (e is overwritten).  In mixed mode r is
@@ -173,8 +186,12 @@ typedef struct {
  * mass_dev [n].  energy_log_dev [n_steps][6] = {E_sr, E_lr, E_self,
  * E_other, E_kin, E_total}; cycles_log_dev [n_steps] V-cycles per step
  * (either may be NULL).  The first call computes the forces at the initial
- * positions (a cold solve) before the first step.  Synchronises once per
- * step.  Errors as p3mz_compute. */
+ * positions before the first step (a cold solve on first use); a later call
+ * continues the trajectory from the forces the last one left, provided it
+ * passes the same pos/vel/mass buffers and terms and nothing else (a
+ * p3mz_compute, a state load or reset) ran in between; otherwise it
+ * recomputes the forces at the given positions first.  Synchronises once
+ * per step.  Errors as p3mz_compute. */
 p3mz_status p3mz_md_run(p3mz_ctx* ctx, double* pos_dev, double* vel_dev, const double* mass_dev,
                         const p3mz_mdterms* terms, double dt, int32_t n_steps,
                         double* energy_log_dev, int32_t* cycles_log_dev, void* stream);
@@ -230,6 +247,13 @@ p3mz_status p3mz_set_kernel_timer(p3mz_ctx* ctx, int32_t kernel_id);
  * (the bytes the method must move per launch, independent of caching). */
 p3mz_status p3mz_get_kernel_timer(const p3mz_ctx* ctx, double* total_ms, int64_t* launches,
                                   double* total_bytes);
+/* The same launches one by one, in launch order: ms_host[i] (event
+ * milliseconds) and bytes_host[i] (algorithmic bytes) for the first
+ * min(max, launches) of them (up to 65536 are kept); *count = the number
+ * written.  Launches that found the solve already converged return at once
+ * and show as short durations.  Errors: INVALID_ARG for NULL pointers. */
+p3mz_status p3mz_get_kernel_launches(const p3mz_ctx* ctx, int32_t max, float* ms_host, double* bytes_host,
+                                     int32_t* count);
 
 /* Back-to-back timing of one finest-level kernel on the context's current
  * buffers: `reps` launches between two HIP events on `stream`; *avg_ms is the
@@ -353,6 +377,15 @@ p3mz_status p3mz_batch_compute(p3mz_batch* b, const double* pos_dev, double* for
 p3mz_status p3mz_batch_md_run(p3mz_batch* b, double* pos_dev, double* vel_dev, const double* mass_dev,
                               const p3mz_mdterms* terms, double dt, int32_t n_steps, double* energy_log_dev,
                               int32_t* cycles_log_dev, void* stream);
+/* One velocity-Verlet MD step of every system (p3mz_batch_md_run with
+ * n_steps = 1), returning what the step computed: force_dev packed [atom][3]
+ * (the total force the closing half kick used: electrostatic plus the
+ * non-electrostatic terms), energies_dev [n_sys][4] = {E_sr, E_lr, E_self,
+ * E_total} (electrostatic) and cycles_dev [n_sys] V-cycles of the step's
+ * solve; each of the three may be NULL.  Errors as p3mz_batch_md_run. */
+p3mz_status p3mz_batch_step(p3mz_batch* b, double* pos_dev, double* vel_dev, const double* mass_dev,
+                            const p3mz_mdterms* terms, double dt, double* force_dev, double* energies_dev,
+                            int32_t* cycles_dev, void* stream);
 /* Statistics of system `sys` after the last batched step. */
 p3mz_status p3mz_batch_get_stats(const p3mz_batch* b, int32_t sys, p3mz_stats* out);
 /* Events around the mesh part (spread .. gather) and the pair part of every

@@ -210,6 +210,7 @@ struct p3mz_ctx {
   LevelBufs lv[P3MZ_MAX_LEVELS];
   double* d_partial = nullptr;
   double* d_spart = nullptr;     // sigma's partials when the first outer residual reduces them
+  double* d_nfpart = nullptr;    // net-force partials of the pair kernels
   Ctl* d_ctl = nullptr;
   Ctl* h_ctl = nullptr;         // pinned mirror
   double* d_energy = nullptr;   // internal energy4 when the caller passes none
@@ -219,6 +220,7 @@ struct p3mz_ctx {
   double* d_md_force = nullptr;
   double* d_e_other = nullptr;
   bool md_have_force = false;
+  std::vector<uint64_t> md_force_key;   // buffers and terms d_md_force was computed with
   // host mirror of the device history state (refreshed after every step)
   Ctl mirror{};
   int last_cycles = 0;
@@ -243,6 +245,9 @@ struct p3mz_ctx {
   int kt_used = 0;
   double kt_total_ms = 0.0, kt_total_bytes = 0.0;
   int64_t kt_launches = 0;
+  static constexpr size_t kKtKeep = 65536;   // per-launch records kept for p3mz_get_kernel_launches
+  std::vector<float> kt_hist_ms;
+  std::vector<double> kt_hist_bytes;
 
   template <typename T>
   p3mz_status alloc(T** p, size_t count) {
@@ -570,6 +575,7 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   // every reduction grid is capped, so one fixed-size partial buffer fits all
   P3MZ_TRY(c->alloc(&c->d_partial, kPartialSlots));
   P3MZ_TRY(c->alloc(&c->d_spart, kPartialSlots));
+  P3MZ_TRY(c->alloc(&c->d_nfpart, 3 * kPartialSlots));
   P3MZ_TRY(c->alloc(&c->d_ctl, 1));
   P3MZ_HIP_TRY(hipHostMalloc((void**)&c->h_ctl, sizeof(Ctl), hipHostMallocDefault));
   memset(&c->mirror, 0, sizeof(Ctl));
@@ -729,7 +735,7 @@ p3mz_status enq_post2(p3mz_ctx* c, const double* pos, double* force, double* ene
   P3MZ_HIP_TRY(launch_sr(na, pos, c->d_qa, c->P.box, c->P.alpha, c->P.r_cut, c->P.coulomb_k, c->nc, c->P.excl_group,
                          c->d_cstart, c->d_cperm, c->d_spos, c->d_erfc, c->erfc_n, c->erfc_scale, force, c->e_self,
                          energy ? energy : c->d_energy,
-                         c->d_partial, c->d_ctl, s, c->d_nbr, c->d_nlist, c->nbr_cap));
+                         c->d_partial, c->d_nfpart, c->d_ctl, s, c->d_nbr, c->d_nlist, c->nbr_cap));
   kt_end(KT_SR, 0, (double)na * 56.0, s);
   rec_key(6005);
   P3MZ_HIP_TRY(launch_advance(c->d_ctl, s));
@@ -874,6 +880,7 @@ p3mz_status finish(p3mz_ctx* c, hipStream_t s) {
   st.e_total = h.e_sr + h.e_lr + c->e_self;
   st.steps = h.steps;
   st.graphs = c->ran_graphs;
+  for (int k = 0; k < 3; k++) st.net_force[k] = h.net_force[k];
   if (c->timing) {
     float ms = 0.f;
     P3MZ_HIP_TRY(hipEventElapsedTime(&ms, c->stage_ev[0], c->stage_ev[3]));
@@ -896,6 +903,10 @@ p3mz_status finish(p3mz_ctx* c, hipStream_t s) {
     c->kt_total_ms += ms;
     c->kt_total_bytes += c->kt_bytes[i / 2];
     c->kt_launches++;
+    if (c->kt_hist_ms.size() < p3mz_ctx::kKtKeep) {
+      c->kt_hist_ms.push_back(ms);
+      c->kt_hist_bytes.push_back(c->kt_bytes[i / 2]);
+    }
   }
   c->kt_used = 0;
   return P3MZ_OK;
@@ -1017,6 +1028,7 @@ struct p3mz_batch {
   BatchSet compute, md;
   bool use_graphs = true;
   bool md_have_force = false;
+  std::vector<uint64_t> md_force_key;   // buffers and terms the systems' forces were computed with
   int last_cycles = 0;
   hipStream_t cap = nullptr;
   bool timing = false;
@@ -1180,6 +1192,7 @@ p3mz_status batch_finish(p3mz_batch* b, hipStream_t s) {
     st.e_total = h.e_sr + h.e_lr + c->e_self;
     st.steps = h.steps;
     st.graphs = b->ran_graphs;
+    for (int k = 0; k < 3; k++) st.net_force[k] = h.net_force[k];
     st.ms_mesh = st.ms_short_range = st.ms_spread = st.ms_solve = st.ms_gather = -1.0;
   }
   b->last_cycles = cmax;
@@ -1393,6 +1406,10 @@ p3mz_status p3mz_get_mesh(p3mz_ctx* ctx, int32_t which, double* out_dev, void* s
   return P3MZ_OK;
 }
 
+p3mz_status p3mz_get_potential(p3mz_ctx* ctx, double* phi_dev, void* stream) {
+  return p3mz_get_mesh(ctx, 4, phi_dev, stream);
+}
+
 p3mz_status p3mz_vcycle(p3mz_ctx* ctx, const double* r_dev, double* e_dev, void* stream) {
   if (!ctx || !r_dev || !e_dev) return fail(P3MZ_ERR_INVALID_ARG, "NULL argument");
   hipStream_t s = (hipStream_t)stream;
@@ -1531,6 +1548,11 @@ p3mz_status p3mz_md_run(p3mz_ctx* ctx, double* pos_dev, double* vel_dev, const d
   key_post2.push_back(ctx->th_seed);
   key_post2.push_back((uint64_t)m.th.on);
   P3MZ_HIP_TRY(hipMemsetAsync(&ctx->d_ctl->md_step, 0, sizeof(int), s));   // eager, never captured
+  // the stored forces continue a trajectory only for the same buffers and terms
+  std::vector<uint64_t> force_key = {(uint64_t)(uintptr_t)pos_dev, (uint64_t)(uintptr_t)vel_dev,
+                                     (uint64_t)(uintptr_t)mass_dev, (uint64_t)m.model};
+  for (double v : m.p) force_key.push_back(bits(v));
+  if (ctx->md_have_force && ctx->md_force_key != force_key) ctx->md_have_force = false;
   if (!ctx->md_have_force) {
     // forces at the initial positions (a cold solve on first use); no log row
     P3MZ_TRY(mesh_step(ctx, pos_dev, ctx->d_md_force, ctx->d_energy, s,
@@ -1542,6 +1564,7 @@ p3mz_status p3mz_md_run(p3mz_ctx* ctx, double* pos_dev, double* vel_dev, const d
                                 ctx->d_partial, ctx->d_e_other, s, ctx->d_nbr, ctx->d_nlist, ctx->nbr_cap));
     P3MZ_TRY(finish(ctx, s));
     ctx->md_have_force = true;
+    ctx->md_force_key = force_key;
   }
   p3mz_status worst = P3MZ_OK;
   for (int step = 0; step < n_steps; step++) {
@@ -1586,6 +1609,20 @@ p3mz_status p3mz_set_kernel_timer(p3mz_ctx* ctx, int32_t kernel_id) {
   ctx->kt_total_ms = 0.0;
   ctx->kt_total_bytes = 0.0;
   ctx->kt_launches = 0;
+  ctx->kt_hist_ms.clear();
+  ctx->kt_hist_bytes.clear();
+  return P3MZ_OK;
+}
+
+p3mz_status p3mz_get_kernel_launches(const p3mz_ctx* ctx, int32_t max, float* ms_host, double* bytes_host,
+                                     int32_t* count) {
+  if (!ctx || !ms_host || !bytes_host || !count || max < 0) return fail(P3MZ_ERR_INVALID_ARG, "NULL argument");
+  const int32_t n = (int32_t)std::min<size_t>((size_t)max, ctx->kt_hist_ms.size());
+  for (int32_t i = 0; i < n; i++) {
+    ms_host[i] = ctx->kt_hist_ms[(size_t)i];
+    bytes_host[i] = ctx->kt_hist_bytes[(size_t)i];
+  }
+  *count = n;
   return P3MZ_OK;
 }
 
@@ -1922,10 +1959,15 @@ p3mz_status p3mz_batch_md_run(p3mz_batch* b, double* pos_dev, double* vel_dev, c
   hipStream_t s = (hipStream_t)stream;
   const MdArgs m0 = md_args_for(terms, dt);
   bool nc = false;
+  std::vector<uint64_t> force_key = {(uint64_t)(uintptr_t)pos_dev, (uint64_t)(uintptr_t)vel_dev,
+                                     (uint64_t)(uintptr_t)mass_dev, (uint64_t)m0.model};
+  for (double v : m0.p) force_key.push_back(bits(v));
+  if (b->md_have_force && b->md_force_key != force_key) b->md_have_force = false;
   if (!b->md_have_force) {
     P3MZ_TRY(batch_prepare_compute(b, pos_dev, nullptr, nullptr, &m0));
     P3MZ_TRY(batch_step(b, &b->compute, s, false, true, &nc));
     b->md_have_force = true;
+    b->md_force_key = force_key;
   }
   P3MZ_TRY(batch_prepare_md(b, pos_dev, vel_dev, mass_dev, m0, energy_log_dev, cycles_log_dev, n_steps));
   hipLaunchKernelGGL(k_batch_md_reset, dim3((b->sys.size() + 255) / 256), dim3(256), 0, s, b->d_ctls,
@@ -1938,6 +1980,24 @@ p3mz_status p3mz_batch_md_run(p3mz_batch* b, double* pos_dev, double* vel_dev, c
   }
   if (worst) return fail(P3MZ_WARN_NOT_CONVERGED, "V-cycle cap reached before the tolerance in a batched system");
   return P3MZ_OK;
+}
+
+p3mz_status p3mz_batch_step(p3mz_batch* b, double* pos_dev, double* vel_dev, const double* mass_dev,
+                            const p3mz_mdterms* terms, double dt, double* force_dev, double* energies_dev,
+                            int32_t* cycles_dev, void* stream) {
+  if (!b) return fail(P3MZ_ERR_INVALID_ARG, "batch is NULL");
+  const p3mz_status st = p3mz_batch_md_run(b, pos_dev, vel_dev, mass_dev, terms, dt, 1, nullptr, cycles_dev, stream);
+  if (st < 0) return st;
+  hipStream_t s = (hipStream_t)stream;
+  for (size_t r = 0; r < b->sys.size(); r++) {
+    const p3mz_ctx* c = b->sys[r];
+    if (force_dev)
+      P3MZ_HIP_TRY(hipMemcpyAsync(force_dev + 3 * b->off[r], c->d_md_force, sizeof(double) * 3 * (size_t)c->n_atoms,
+                                  hipMemcpyDeviceToDevice, s));
+    if (energies_dev)
+      P3MZ_HIP_TRY(hipMemcpyAsync(energies_dev + 4 * r, c->d_energy, 4 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  return st;
 }
 
 p3mz_status p3mz_batch_get_stats(const p3mz_batch* b, int32_t sys, p3mz_stats* out) {

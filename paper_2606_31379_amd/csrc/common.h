@@ -44,6 +44,7 @@ struct Ctl {
   int nbr_over;          // atoms whose neighbours exceeded the list capacity at the last build
   int pad2;
   long long therm_step;  // MD steps since the thermostat was set (counter of its random numbers)
+  double net_force[3];   // sum of the step's electrostatic forces (NaN when no force was written)
 };
 
 // Langevin thermostat of the OVRVO splitting: v <- a v + b sqrt(kT / (m e)) z

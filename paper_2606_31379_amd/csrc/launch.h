@@ -57,7 +57,8 @@ hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, int tile, int ntx
                          const float* phi32, double* force, double* partial, Ctl* ctl, hipStream_t s,
                          bool finalize = true);
 // Short-range erfc pairs (neighbour lists or the cell list), exclusion correction, energy
-// assembly into energy_out[4] (may be NULL).  force += F_sr.
+// assembly into energy_out[4] (may be NULL).  force += F_sr; the sum of the
+// final forces goes to ctl->net_force (nfpart: 3 * kPartialSlots doubles).
 // spos[jj] = {x, y, z, q} of atom cperm[jj] (cell order), for the pair kernels.
 hipError_t launch_cell_pack(int n_atoms, const int* cperm, const double* pos, const double* qa, void* spos,
                             hipStream_t s, const int* gate = nullptr);
@@ -79,8 +80,8 @@ hipError_t launch_nbr_build(int n_atoms, double box, double r_list, int nc, int 
 hipError_t launch_sr(int n_atoms, const double* pos, const double* qa, double box, double alpha,
                      double r_cut, double k_e, int nc, int excl_group, const int* cstart,
                      const int* cperm, const void* spos, const double* erfc_tab, int erfc_n, double erfc_scale,
-                     double* force, double e_self, double* energy_out, double* partial, Ctl* ctl, hipStream_t s,
-                     const int* list = nullptr, const int* nlist = nullptr, int cap = 0);
+                     double* force, double e_self, double* energy_out, double* partial, double* nfpart, Ctl* ctl,
+                     hipStream_t s, const int* list = nullptr, const int* nlist = nullptr, int cap = 0);
 
 // ---- mesh (mesh.hip) -----------------------------------------------------
 // Folded periodic smoothing filter along one axis: out = sum_m c[m] v[i+m-K],

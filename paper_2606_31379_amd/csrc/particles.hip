@@ -717,6 +717,8 @@ struct FinEnergy {
     int nb;
     double e_self;
     const double* partial;
+    const double* nfpart;   // 3 per workgroup of the pair kernels
+    int has_force;          // 0: no force output this step (net force unknown)
     Ctl* ctl;
     double* energy_out;
     int nbr;   // 1: the step used neighbour lists; a flagged rebuild is now done
@@ -730,7 +732,14 @@ __device__ void FinEnergy::run(const Args& A, Grid) {
   double* energy_out = A.energy_out;
   __shared__ double sh[kBlock / 64];
   const double tot = reduce_partials_sum(A.partial, A.nb, sh);
+  double nf[3];
+  for (int c = 0; c < 3; c++) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < A.nb; i += blockDim.x) acc += A.nfpart[3 * i + c];
+    nf[c] = block_sum(acc, sh);
+  }
   if (threadIdx.x == 0) {
+    for (int c = 0; c < 3; c++) ctl->net_force[c] = A.has_force ? nf[c] : __builtin_nan("");
     if (A.nbr && ctl->nbr_stale) {
       ctl->nbr_builds++;
       ctl->nbr_stale = 0;
@@ -957,6 +966,7 @@ struct ShortRange {
     const int *cstart, *cperm;
     const double4* spos;   // cell-ordered {x, y, z, q}
     double *force, *partial;
+    double* nfpart;           // 3 per workgroup: sum of the atoms' final forces (net force)
     const double* erfc_tab;   // erfcx table on [0, alpha r_cut] (1..kErfcMaxIntervals intervals)
     int erfc_n;
     double erfc_scale;        // table intervals per unit of alpha r
@@ -974,7 +984,7 @@ struct ShortRange {
 // accumulated into each lane's en.
 template <bool LIST>
 __device__ __forceinline__ void sr_atom(const typename ShortRange<LIST>::Args& A, int wave, const double* tab,
-                                        PairQueue* Q, double& en) {
+                                        PairQueue* Q, double& en, double* nf) {
   const int n_atoms = A.n_atoms, excl_group = A.excl_group;
   const double box = A.box, alpha = A.alpha, rc2 = A.rc2, k_e = A.k_e;
   const double* __restrict__ pos = A.pos;
@@ -1032,9 +1042,14 @@ __device__ __forceinline__ void sr_atom(const typename ShortRange<LIST>::Args& A
   fy = wave_sum(fy);
   fz = wave_sum(fz);
   if (lane == 0 && A.force) {
-    A.force[3 * i] += fx;
-    A.force[3 * i + 1] += fy;
-    A.force[3 * i + 2] += fz;
+    // the atom's final electrostatic force (the gather wrote the mesh part)
+    const double gx = A.force[3 * i] + fx, gy = A.force[3 * i + 1] + fy, gz = A.force[3 * i + 2] + fz;
+    A.force[3 * i] = gx;
+    A.force[3 * i + 1] = gy;
+    A.force[3 * i + 2] = gz;
+    nf[0] += gx;
+    nf[1] += gy;
+    nf[2] += gz;
   }
 }
 
@@ -1044,14 +1059,16 @@ __device__ void ShortRange<LIST>::run(const Args& A, Grid G) {
   __shared__ double sh[kBlock / 64];
   __shared__ PairQueue queue[LIST ? 1 : kBlock / 64];
   extern __shared__ double tab[];   // erfc_n * (kErfcDeg + 1) coefficients (dynamic LDS)
+  __shared__ double shf[3 * (kBlock / 64)];
   const int lane = threadIdx.x & 63;
   const int nwaves = G.g * (kBlock / 64);
   double en = 0.0;
+  double nf[3] = {0.0, 0.0, 0.0};   // lane 0: net force of the wave's atoms
   for (int k = threadIdx.x; k < A.erfc_n * (kErfcDeg + 1); k += kBlock) tab[k] = A.erfc_tab[k];
   __syncthreads();
   if constexpr (LIST) {
     for (int wave = (G.b * kBlock + threadIdx.x) >> 6; wave < n_atoms; wave += nwaves)
-      if (A.nlist[wave] <= A.cap) sr_atom<true>(A, wave, tab, nullptr, en);
+      if (A.nlist[wave] <= A.cap) sr_atom<true>(A, wave, tab, nullptr, en, nf);
   } else {
     PairQueue* Q = &queue[threadIdx.x >> 6];
     const int span = A.span;
@@ -1062,17 +1079,24 @@ __device__ void ShortRange<LIST>::run(const Args& A, Grid G) {
       while (todo) {
         const int l = __ffsll((unsigned long long)todo) - 1;   // wave-uniform
         todo &= todo - 1;
-        sr_atom<false>(A, chunk * span + l, tab, Q, en);
+        sr_atom<false>(A, chunk * span + l, tab, Q, en, nf);
       }
     }
   }
   en = wave_sum(en);
-  if (lane == 0) sh[threadIdx.x >> 6] = en;
+  if (lane == 0) {
+    sh[threadIdx.x >> 6] = en;
+    for (int c = 0; c < 3; c++) shf[3 * (threadIdx.x >> 6) + c] = nf[c];
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int k = 0; k < kBlock / 64; k++) s += sh[k];
+    double s = 0.0, f[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < kBlock / 64; k++) {
+      s += sh[k];
+      for (int c = 0; c < 3; c++) f[c] += shf[3 * k + c];
+    }
     A.partial[G.b] = s;
+    for (int c = 0; c < 3; c++) A.nfpart[3 * G.b + c] = f[c];
   }
 }
 
@@ -1219,30 +1243,30 @@ hipError_t launch_nbr_build(int n_atoms, double box, double r_list, int nc, int 
 hipError_t launch_sr(int n_atoms, const double* pos, const double* qa, double box, double alpha,
                      double r_cut, double k_e, int nc, int excl_group, const int* cstart,
                      const int* cperm, const void* spos, const double* erfc_tab, int erfc_n, double erfc_scale,
-                     double* force, double e_self, double* energy_out, double* partial, Ctl* ctl, hipStream_t s,
-                     const int* list, const int* nlist, int cap) {
+                     double* force, double e_self, double* energy_out, double* partial, double* nfpart, Ctl* ctl,
+                     hipStream_t s, const int* list, const int* nlist, int cap) {
   if (erfc_n < 1 || erfc_n > kErfcMaxIntervals) return hipErrorInvalidValue;
   const size_t lds = (size_t)erfc_n * (kErfcDeg + 1) * sizeof(double);
   const double rc2 = r_cut * r_cut;
   if (!list) {
     const int nb = std::min(blocks_for((int64_t)n_atoms * 64, kBlock), kPartialSlots);
     hipError_t e = go<ShortRange<false>>({n_atoms, nc, excl_group, 1, box, alpha, rc2, k_e, pos, qa, cstart, cperm,
-                                          (const double4*)spos, force, partial, erfc_tab, erfc_n, erfc_scale,
-                                          nullptr, nullptr, 0}, nb, lds, s);
+                                          (const double4*)spos, force, partial, nfpart, erfc_tab, erfc_n,
+                                          erfc_scale, nullptr, nullptr, 0}, nb, lds, s);
     if (e != hipSuccess) return e;
-    return go<FinEnergy>({nb, e_self, partial, ctl, energy_out, 0}, 1, 0, s);
+    return go<FinEnergy>({nb, e_self, partial, nfpart, force != nullptr, ctl, energy_out, 0}, 1, 0, s);
   }
   // the lists, then the cell scan for the atoms over capacity; partials of
   // the first kernel, then of the second
   const int nb = std::min(blocks_for((int64_t)n_atoms * 64, kBlock), kPartialSlots / 2);
   hipError_t e = go<ShortRange<true>>({n_atoms, nc, excl_group, 1, box, alpha, rc2, k_e, pos, qa, cstart, cperm,
-                                       (const double4*)spos, force, partial, erfc_tab, erfc_n, erfc_scale, list,
-                                       nlist, cap}, nb, lds, s);
+                                       (const double4*)spos, force, partial, nfpart, erfc_tab, erfc_n, erfc_scale,
+                                       list, nlist, cap}, nb, lds, s);
   if (e != hipSuccess) return e;
   const int nb2 = std::min(blocks_for((int64_t)(n_atoms + 63) / 64 * 64, kBlock), kPartialSlots / 2);
   e = go<ShortRange<false>>({n_atoms, nc, excl_group, 64, box, alpha, rc2, k_e, pos, qa, cstart, cperm,
-                             (const double4*)spos, force, partial + nb, erfc_tab, erfc_n, erfc_scale, list, nlist,
-                             cap}, nb2, lds, s);
+                             (const double4*)spos, force, partial + nb, nfpart + 3 * nb, erfc_tab, erfc_n,
+                             erfc_scale, list, nlist, cap}, nb2, lds, s);
   if (e != hipSuccess) return e;
-  return go<FinEnergy>({nb + nb2, e_self, partial, ctl, energy_out, 1}, 1, 0, s);
+  return go<FinEnergy>({nb + nb2, e_self, partial, nfpart, force != nullptr, ctl, energy_out, 1}, 1, 0, s);
 }

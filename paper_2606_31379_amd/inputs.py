@@ -171,33 +171,59 @@ def water(n_mol: int, box: float, temp_k: float, seed: int, r_oh: float = 1.0,
         return opos[:, None, :] + np.einsum("mij,aj->mai", rmats, tmpl)
 
     pos = build(rot)
-    check = np.arange(n_mol)          # molecules whose contacts must be (re)checked
+
+    def wrapped(p):
+        f = np.mod(p.reshape(-1, 3), box)
+        return np.minimum(f, np.nextafter(box, 0.0))
+
+    def foreign_contacts(tree, tree_atoms, stale, atoms, pts):
+        """(molecule, molecule) pairs of every intermolecular contact closer
+        than d_inter between query atoms and the tree's atoms whose molecule
+        is not stale.  Exact: an atom whose 8 nearest tree atoms all lie
+        within d_inter is queried again by radius."""
+        d, nb = tree.query(pts, k=8, distance_upper_bound=d_inter, workers=-1)
+        hit = d < d_inter
+        ja = tree_atoms[np.where(hit, nb, 0)]
+        keep = hit & ~stale[mol_id[ja]] & (mol_id[ja] != mol_id[atoms][:, None])
+        rows, cols = np.nonzero(keep)
+        pa, pb = [mol_id[atoms[rows]]], [mol_id[ja[rows, cols]]]
+        for i in np.nonzero(d[:, -1] < d_inter)[0]:
+            js = tree_atoms[np.asarray(tree.query_ball_point(pts[i], d_inter), dtype=int)]
+            js = js[~stale[mol_id[js]] & (mol_id[js] != mol_id[atoms[i]])]
+            pa.append(np.full(js.size, mol_id[atoms[i]]))
+            pb.append(mol_id[js])
+        return np.concatenate(pa), np.concatenate(pb)
+
+    # Contacts are found with a tree over the wrapped atoms as they were at
+    # its build plus a small tree over the molecules re-drawn since then; the
+    # big tree's entries of re-drawn molecules are stale and skipped.  Only
+    # the molecules re-drawn in the last pass can have new contacts.
+    flat = wrapped(pos)
+    all_atoms = np.arange(3 * n_mol)
+    static = cKDTree(flat, boxsize=box)
+    moved = np.zeros(n_mol, dtype=bool)
+    check = np.arange(n_mol)
     for _ in range(max_rounds):
-        flat = np.mod(pos.reshape(-1, 3), box)
-        flat = np.minimum(flat, np.nextafter(box, 0.0))
-        tree = cKDTree(flat, boxsize=box)
-        if check.size == n_mol:
-            pairs = tree.query_pairs(d_inter, output_type="ndarray")
-            pairs = pairs[mol_id[pairs[:, 0]] != mol_id[pairs[:, 1]]] if pairs.size else pairs
-            bad = np.unique(mol_id[pairs.ravel()]) if pairs.size else np.zeros(0, dtype=int)
-        else:
-            # contacts of the re-drawn molecules: the nearest atoms of each of
-            # their atoms (an atom has at most a handful within d_inter, its
-            # own molecule included, so 8 neighbours see every contact)
-            atoms = (3 * check[:, None] + np.arange(3)[None, :]).ravel()
-            d, nb = tree.query(flat[atoms], k=8, distance_upper_bound=d_inter, workers=-1)
-            hit = d < d_inter
-            nb = np.where(hit, nb, 0)
-            foreign = hit & (mol_id[nb] != mol_id[atoms][:, None])
-            rows, cols = np.nonzero(foreign)
-            bad = np.unique(np.concatenate([mol_id[atoms[rows]], mol_id[nb[rows, cols]]]))
+        atoms = (3 * check[:, None] + np.arange(3)[None, :]).ravel()
+        pa, pb = foreign_contacts(static, all_atoms, moved, atoms, flat[atoms])
+        if moved.any():
+            mv_atoms = np.nonzero(np.repeat(moved, 3))[0]
+            qa, qb = foreign_contacts(cKDTree(flat[mv_atoms], boxsize=box), mv_atoms,
+                                      np.zeros(n_mol, dtype=bool), atoms, flat[atoms])
+            pa, pb = np.concatenate([pa, qa]), np.concatenate([pb, qb])
+        bad = np.unique(np.concatenate([pa, pb]))
         if progress is not None:
             progress(f"orientation pass: {bad.size} molecules with contacts")
         if bad.size == 0:
             break
         rot[bad] = _random_rotations(rng, bad.size)
-        pos = build(rot)
+        pos[bad] = opos[bad, None, :] + np.einsum("mij,aj->mai", rot[bad], tmpl)
+        flat.reshape(n_mol, 3, 3)[bad] = wrapped(pos[bad]).reshape(-1, 3, 3)
+        moved[bad] = True
         check = bad
+        if moved.sum() > n_mol // 4:
+            static = cKDTree(flat, boxsize=box)
+            moved[:] = False
     else:
         raise RuntimeError("could not orient water molecules without overlaps")
     pos = pos.reshape(-1, 3)

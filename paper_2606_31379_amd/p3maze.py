@@ -29,12 +29,13 @@ P3MZ_PREC_MIXED = 1
 MESH_Q, MESH_QS, MESH_SIGMA_P, MESH_Y, MESH_PHI, MESH_PHI_PREV = range(6)
 
 # every symbol include/p3maze.h declares
-EXPORTS = ["p3mz_create", "p3mz_compute", "p3mz_get_mesh", "p3mz_vcycle", "p3mz_get_stats",
+EXPORTS = ["p3mz_create", "p3mz_compute", "p3mz_get_mesh", "p3mz_get_potential", "p3mz_vcycle", "p3mz_get_stats",
            "p3mz_reset_history", "p3mz_save_state", "p3mz_load_state", "p3mz_md_run",
            "p3mz_set_graphs", "p3mz_set_timing", "p3mz_set_kernel_timer", "p3mz_get_kernel_timer",
+           "p3mz_get_kernel_launches",
            "p3mz_kernel_bench", "p3mz_set_schedule", "p3mz_set_fused_levels",
            "p3mz_set_neighbor_list", "p3mz_get_neighbor_stats", "p3mz_set_thermostat", "p3mz_autotune",
-           "p3mz_destroy", "p3mz_batch_create", "p3mz_batch_compute", "p3mz_batch_md_run",
+           "p3mz_destroy", "p3mz_batch_create", "p3mz_batch_compute", "p3mz_batch_md_run", "p3mz_batch_step",
            "p3mz_batch_get_stats", "p3mz_batch_set_timing", "p3mz_batch_get_timing", "p3mz_batch_set_graphs",
            "p3mz_batch_kernel_bench", "p3mz_batch_destroy", "p3mz_status_string", "p3mz_last_error", "p3mz_version"]
 KERNELS = {"halfsweep": 0, "outer": 1, "smooth": 2, "restrict": 3, "prolong": 4, "sweep0": 5,
@@ -58,7 +59,7 @@ class p3mz_stats(C.Structure):
                 ("e_sr", C.c_double), ("e_lr", C.c_double), ("e_self", C.c_double),
                 ("e_total", C.c_double), ("steps", C.c_int64), ("graphs", C.c_int32),
                 ("ms_mesh", C.c_double), ("ms_short_range", C.c_double), ("ms_spread", C.c_double),
-                ("ms_solve", C.c_double), ("ms_gather", C.c_double)]
+                ("ms_solve", C.c_double), ("ms_gather", C.c_double), ("net_force", C.c_double * 3)]
 
 
 class p3mz_mdterms(C.Structure):
@@ -94,6 +95,7 @@ def _load() -> C.CDLL:
         "p3mz_create": ([C.POINTER(p3mz_params), C.c_int64, dp, C.POINTER(vp)], C.c_int),
         "p3mz_compute": ([vp, vp, vp, vp, vp], C.c_int),
         "p3mz_get_mesh": ([vp, C.c_int32, vp, vp], C.c_int),
+        "p3mz_get_potential": ([vp, vp, vp], C.c_int),
         "p3mz_vcycle": ([vp, vp, vp, vp], C.c_int),
         "p3mz_get_stats": ([vp, C.POINTER(p3mz_stats)], C.c_int),
         "p3mz_reset_history": ([vp], C.c_int),
@@ -106,6 +108,7 @@ def _load() -> C.CDLL:
         "p3mz_kernel_bench": ([vp, C.c_int32, C.c_int32, vp, dp, dp], C.c_int),
         "p3mz_set_kernel_timer": ([vp, C.c_int32], C.c_int),
         "p3mz_get_kernel_timer": ([vp, dp, C.POINTER(C.c_int64), dp], C.c_int),
+        "p3mz_get_kernel_launches": ([vp, C.c_int32, C.POINTER(C.c_float), dp, ip], C.c_int),
         "p3mz_set_schedule": ([vp, C.c_int32, C.c_int32, C.c_int32], C.c_int),
         "p3mz_set_fused_levels": ([vp, C.c_int32], C.c_int),
         "p3mz_set_neighbor_list": ([vp, C.c_double, C.c_int32], C.c_int),
@@ -117,6 +120,7 @@ def _load() -> C.CDLL:
         "p3mz_batch_compute": ([vp, vp, vp, vp, vp], C.c_int),
         "p3mz_batch_md_run": ([vp, vp, vp, vp, C.POINTER(p3mz_mdterms), C.c_double, C.c_int32, vp, vp, vp],
                               C.c_int),
+        "p3mz_batch_step": ([vp, vp, vp, vp, C.POINTER(p3mz_mdterms), C.c_double, vp, vp, vp, vp], C.c_int),
         "p3mz_batch_get_stats": ([vp, C.c_int32, C.POINTER(p3mz_stats)], C.c_int),
         "p3mz_batch_set_timing": ([vp, C.c_int32], C.c_int),
         "p3mz_batch_get_timing": ([vp, dp, dp, C.POINTER(C.c_int32)], C.c_int),
@@ -160,6 +164,10 @@ def p3mz_compute(ctx: int, pos_dev: int, force_dev: int | None, energy_dev: int 
 
 def p3mz_get_mesh(ctx: int, which: int, out_dev: int, stream: int | None = None) -> int:
     return _check(lib.p3mz_get_mesh(ctx, which, out_dev, stream), "p3mz_get_mesh")
+
+
+def p3mz_get_potential(ctx: int, phi_dev: int, stream: int | None = None) -> int:
+    return _check(lib.p3mz_get_potential(ctx, phi_dev, stream), "p3mz_get_potential")
 
 
 def p3mz_vcycle(ctx: int, r_dev: int, e_dev: int, stream: int | None = None) -> int:
@@ -221,6 +229,15 @@ def p3mz_get_kernel_timer(ctx: int) -> tuple[float, int, float]:
     return ms.value, n.value, b.value
 
 
+def p3mz_get_kernel_launches(ctx: int, max_launches: int = 65536) -> tuple[list[float], list[float]]:
+    """Per-launch (event milliseconds, algorithmic bytes) of the timed family, in launch order."""
+    ms = (C.c_float * max_launches)()
+    by = (C.c_double * max_launches)()
+    n = C.c_int32()
+    _check(lib.p3mz_get_kernel_launches(ctx, max_launches, ms, by, C.byref(n)), "p3mz_get_kernel_launches")
+    return list(ms[:n.value]), list(by[:n.value])
+
+
 def p3mz_set_schedule(ctx: int, nu_pre: int, nu_post: int, smooth_tile: int = 0) -> int:
     return _check(lib.p3mz_set_schedule(ctx, nu_pre, nu_post, smooth_tile), "p3mz_set_schedule")
 
@@ -276,6 +293,13 @@ def p3mz_batch_md_run(b: int, pos_dev: int, vel_dev: int, mass_dev: int, terms: 
                       stream: int | None = None) -> int:
     return _check(lib.p3mz_batch_md_run(b, pos_dev, vel_dev, mass_dev, C.byref(terms), dt, n_steps, energy_log_dev,
                                         cycles_log_dev, stream), "p3mz_batch_md_run")
+
+
+def p3mz_batch_step(b: int, pos_dev: int, vel_dev: int, mass_dev: int, terms: p3mz_mdterms, dt: float,
+                    force_dev: int | None, energies_dev: int | None, cycles_dev: int | None,
+                    stream: int | None = None) -> int:
+    return _check(lib.p3mz_batch_step(b, pos_dev, vel_dev, mass_dev, C.byref(terms), dt, force_dev, energies_dev,
+                                      cycles_dev, stream), "p3mz_batch_step")
 
 
 def p3mz_batch_get_stats(b: int, sys: int) -> p3mz_stats:

@@ -198,3 +198,54 @@ def test_batch_errors(torch):
         P.p3mz_batch_create([sys_params(P, reps[0], 1), sys_params(P, reps[1], 1)], n, bad)
     b = P.p3mz_batch_create([sys_params(P, reps[0], 1)], n[:1], q[: n[0]])   # a batch of one
     P.p3mz_batch_destroy(b)
+
+
+def test_full_64_replica_batch_against_oracle(torch):
+    """The whole batched workload: 64 NaCl replicas of 512-32,768 ions on
+    16^3-64^3 meshes (632,472 ions), mixed precision, captured graphs.  A
+    cold solve and one warm step along the velocities; on every replica the
+    V-cycle counts equal the FP64 oracle's, and the forces on 64 seeded ions
+    per replica are within the mixed-mode bar."""
+    from paper_2606_31379_amd import p3maze as P
+    w = configs.nacl_batch_64()
+    systems = w.systems()
+    n = [s.n for s in systems]
+    assert len(n) == 64 and sum(n) == 632472
+    rng = np.random.Generator(np.random.PCG64(77))
+    targets = [np.sort(rng.choice(s.n, size=64, replace=False)) for s in systems]
+    trajs = [[s.pos, s.pos + w.dt_fs * s.vel] for s in systems]
+    ref = []
+    for r, s, tr, tg in zip(w.replicas, systems, trajs, targets):
+        o = O.Oracle(O.make_params(r.box, w.alpha, w.r_cut, r.mesh, w.order, tol=w.tol, predictor=w.predictor,
+                                   coulomb_k=K_E), s.charges)
+        o.set_sr_targets(tg)
+        rows = []
+        for x in tr:
+            f, _, _ = o.compute(x)
+            rows.append((f[tg], o.stats().cycles))
+        o.close()
+        ref.append(rows)
+    print(f"oracle done for {len(systems)} replicas", flush=True)
+    dev = torch.device("cuda")
+    b = P.p3mz_batch_create([sys_params(P, r, 1) for r in w.replicas], n, packed([s.charges for s in systems]))
+    try:
+        pos = torch.zeros((sum(n), 3), dtype=torch.float64, device=dev)
+        frc = torch.zeros_like(pos)
+        for k in range(2):
+            pos.copy_(torch.from_numpy(packed([tr[k] for tr in trajs])))
+            P.p3mz_batch_compute(b, pos.data_ptr(), frc.data_ptr(), None, torch.cuda.current_stream().cuda_stream)
+            torch.cuda.synchronize()
+            fg = frc.cpu().numpy()
+            off, worst = 0, 0.0
+            for i, s in enumerate(systems):
+                fr, cyc = ref[i][k]
+                st = P.p3mz_batch_get_stats(b, i)
+                assert st.graphs == 1
+                assert st.cycles == cyc, (k, i, st.cycles, cyc)
+                err = rel_rms(fg[off:off + s.n][targets[i]], fr)
+                worst = max(worst, err)
+                assert err <= 1e-5, (k, i, err)
+                off += s.n
+            print(f"step {k}: worst replica rel-RMS force error {worst:.2e}", flush=True)
+    finally:
+        P.p3mz_batch_destroy(b)

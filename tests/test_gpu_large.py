@@ -6,10 +6,8 @@ benchmark times (captured graphs).
 The oracle computes the whole mesh step (assignment, smoothing, the V-cycle
 solve, gather) for every atom, but the all-pairs short-range sum only for a
 seeded sample of atoms; forces are compared on that sample, V-cycle counts
-and the long-range energy on the whole system.  The 512^3 case needs several
-minutes of CPU time for the oracle and runs when P3MZ_FULL_SIZE=1.
+and the long-range energy on the whole system.
 """
-import os
 
 import numpy as np
 import pytest
@@ -73,7 +71,9 @@ def test_water_sweep_full_size(torch, i):
     sampled_parity(torch, configs.water_sweep(i), [0, 1] if i < 2 else [1, 0], steps=3)
 
 
-@pytest.mark.slow
-@pytest.mark.skipif(os.environ.get("P3MZ_FULL_SIZE") != "1", reason="minutes of oracle time; set P3MZ_FULL_SIZE=1")
 def test_large_water_512_full_size(torch):
-    sampled_parity(torch, configs.water_large(), [1], steps=2, sample=1000)
+    """The large water system (7,999,998 atoms, 512^3, order 5, tolerance
+    1e-6): two mesh steps (cold solve, then a warm step) in both precisions,
+    forces on 1,000 seeded atoms, V-cycle counts and the long-range energy of
+    the whole system."""
+    sampled_parity(torch, configs.water_large(), [1, 0], steps=2, sample=1000)
