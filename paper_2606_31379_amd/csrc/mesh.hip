@@ -1692,6 +1692,9 @@ size_t tail_lds_bytes(int n0, int levels, size_t elem) {
 // phi^{k+1} = phi_p - (4 pi / h) y*, with y* projected to zero mean; the
 // multiplier is pushed into the history on warm steps.
 // ---------------------------------------------------------------------------
+// Workgroups of the field update: 2,048 (eight per compute unit) keep every
+// channel busy while the stop decision is made at most that many times.
+constexpr int kPhiBlocks = 2048;
 struct PhiUpdate {
   struct Args {
     int n3;
@@ -1710,7 +1713,7 @@ struct PhiUpdate {
   __device__ static void run(const Args& A, Grid G);
 };
 __device__ void PhiUpdate::run(const Args& A, Grid G) {
-  const int n3 = A.n3;
+  const int n4 = A.n3 >> 2;
   const double h = A.h;
   double* __restrict__ phi0 = A.phi0;
   double* __restrict__ phi1 = A.phi1;
@@ -1721,7 +1724,6 @@ __device__ void PhiUpdate::run(const Args& A, Grid G) {
   double* __restrict__ yh2 = A.yh2;
   float* __restrict__ phi32 = A.phi32;
   Ctl* ctl = A.ctl;
-  const int t = G.b * kBlock + threadIdx.x;
   int done, final_buf;
   double mean_y;
   if (A.dpart) {
@@ -1736,23 +1738,37 @@ __device__ void PhiUpdate::run(const Args& A, Grid G) {
     final_buf = ctl->final_buf;
     mean_y = ctl->mean_y;
   }
-  if (t >= n3 || !done) return;   // enqueued ahead of the convergence check
+  if (!done) return;   // enqueued ahead of the convergence check
   const int cold = ctl->cold;
   double* pk = ctl->k_idx ? phi1 : phi0;
   double* pkm1 = ctl->k_idx ? phi0 : phi1;
   const double* ysrc = final_buf ? yb : ya;
-  const double y = ysrc[t] - mean_y;
-  const double phi_p = cold ? 0.0 : 2.0 * pk[t] - pkm1[t];
-  const double phi = phi_p - 4.0 * kPi / h * y;
-  if (cold) {
-    pk[t] = phi;
-    pkm1[t] = phi;
-  } else {
-    pkm1[t] = phi;   // becomes phi^k after the rotation
-    double* const yh[3] = {yh0, yh1, yh2};
-    yh[ctl->yh2][t] = y;   // the oldest slot becomes the newest multiplier
+  double* const yh[3] = {yh0, yh1, yh2};
+  double* ynew = yh[ctl->yh2];   // the oldest slot becomes the newest multiplier
+  const double c4 = 4.0 * kPi / h;
+  // four consecutive points per thread (two 16-byte loads per array)
+  for (int g = G.b * kBlock + threadIdx.x; g < n4; g += G.g * kBlock) {
+    const int t = 4 * g;
+    const double2 y01 = *(const double2*)(ysrc + t), y23 = *(const double2*)(ysrc + t + 2);
+    const double y[4] = {y01.x - mean_y, y01.y - mean_y, y23.x - mean_y, y23.y - mean_y};
+    double phi[4];
+    if (cold) {
+      for (int i = 0; i < 4; i++) phi[i] = 0.0 - c4 * y[i];
+      *(double2*)(pk + t) = make_double2(phi[0], phi[1]);
+      *(double2*)(pk + t + 2) = make_double2(phi[2], phi[3]);
+    } else {
+      const double2 a01 = *(const double2*)(pk + t), a23 = *(const double2*)(pk + t + 2);
+      const double2 b01 = *(const double2*)(pkm1 + t), b23 = *(const double2*)(pkm1 + t + 2);
+      const double a[4] = {a01.x, a01.y, a23.x, a23.y}, b[4] = {b01.x, b01.y, b23.x, b23.y};
+      for (int i = 0; i < 4; i++) phi[i] = (2.0 * a[i] - b[i]) - c4 * y[i];
+      *(double2*)(ynew + t) = make_double2(y[0], y[1]);
+      *(double2*)(ynew + t + 2) = make_double2(y[2], y[3]);
+    }
+    // pkm1 becomes phi^k after the rotation (a cold solve sets both)
+    *(double2*)(pkm1 + t) = make_double2(phi[0], phi[1]);
+    *(double2*)(pkm1 + t + 2) = make_double2(phi[2], phi[3]);
+    if (phi32) *(float4*)(phi32 + t) = make_float4((float)phi[0], (float)phi[1], (float)phi[2], (float)phi[3]);
   }
-  if (phi32) phi32[t] = (float)phi;
 }
 
 // End of a step: rotate the potential and multiplier history (cold solves
@@ -2239,9 +2255,12 @@ hipError_t launch_phi_update(int n, double h, double* phi0, double* phi1, const 
                              double* yh0, double* yh1, double* yh2, float* phi32, Ctl* ctl, hipStream_t s,
                              const Decide* d) {
   const int n3 = n * n * n;
+  // a capped grid: every workgroup makes the stop decision once (reading
+  // the outer residual's partials), then streams four points per thread
+  const int nb = std::max(1, std::min(blocks_for(n3 / 4, kBlock), kPhiBlocks));
   return go<PhiUpdate>({n3, h, phi0, phi1, ya, yb, yh0, yh1, yh2, phi32, ctl, d ? d->partial : nullptr,
                         d ? d->nb : 0, d ? d->n3 : 0, d ? d->max_cycles : 0},
-                       blocks_for(n3, kBlock), 0, s);
+                       nb, 0, s);
 }
 
 hipError_t launch_advance(Ctl* ctl, hipStream_t s) { return go<Advance>({ctl}, 1, 0, s); }
