@@ -155,6 +155,23 @@ p3mz_status p3mz_get_potential(p3mz_ctx* ctx, double* phi_dev, void* stream);
  * Leaves the potential history untouched. */
 p3mz_status p3mz_vcycle(p3mz_ctx* ctx, const double* r_dev, double* e_dev, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * V-cycle of p3mz_vcycle without a context.  One V-cycle with the schedule
+ * (nu_pre, nu_post) for M e = r on an N^3 mesh, r_dev and e_dev [N][N][N]
+ * doubles (x fastest, e overwritten; mixed precision rounds r to FP32 and
+ * runs the cycle in the mixed precision of a step).  The result equals
+ * p3mz_vcycle of a context with the same mesh, precision and schedule.
+ * The level hierarchy, the coarsest-level Green's function and the control
+ * block live in a fixed device array of 8 MiB per GPU, held until the
+ * process ends, so N <= 64.  The call allocates nothing; its first call on
+ * a device locates that device's array and synchronises the device.  All
+ * calls on one GPU share the array: calls that overlap in time on one GPU
+ * (other streams, other threads) race.  Errors: INVALID_ARG for NULL
+ * pointers, N not 4*2^m in 8..64, a bad precision or schedule; HIP. */
+p3mz_status p3mz_vcycle_noalloc(int32_t mesh, int32_t precision, int32_t nu_pre, int32_t nu_post,
+                                const double* r_dev, double* e_dev, void* stream);
+
 /* Statistics of the last compute (host struct). */
 p3mz_status p3mz_get_stats(const p3mz_ctx* ctx, p3mz_stats* out);
 

@@ -8,6 +8,7 @@
 #include <sys/stat.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1839,6 +1840,124 @@ void p3mz_destroy(p3mz_ctx* ctx) {
   if (!ctx) return;
   (void)hipDeviceSynchronize();
   delete ctx;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free V-cycle.  The level hierarchy, the 4^3 Green's function and
+// a control block of one V-cycle on a mesh of at most kNoallocMaxMesh points
+// per edge live in a fixed device array.  Host code never uses the array's
+// name as a device address: each device's copy is located once with
+// hipGetSymbolAddress and that address is passed to the kernels.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kNoallocMaxMesh = 64;
+constexpr size_t kNoallocBytes = 8u << 20;
+constexpr int kNoallocMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+struct NoallocDevice {
+  unsigned char* base = nullptr;   // this device's copy of `scratch`
+};
+std::mutex g_noalloc_mu;
+NoallocDevice g_noalloc[kNoallocMaxDevices];
+
+// Carves the level hierarchy of an n^3 mesh out of the scratch array (the
+// same buffers a context allocates for p3mz_vcycle).  Returns the bytes used.
+size_t noalloc_layout(unsigned char* base, int n, size_t ts, int levels, int tail, LevelBufs* lv, Ctl** ctl,
+                      double** green) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    unsigned char* p = base + off;
+    off += (bytes + 255) & ~(size_t)255;
+    return (void*)p;
+  };
+  *ctl = (Ctl*)take(sizeof(Ctl));
+  *green = (double*)take(64 * sizeof(double));
+  for (int l = 0; l < levels; l++) {
+    const int nl = n >> l;
+    const size_t half = (size_t)nl * nl * nl / 2;
+    LevelBufs& b = lv[l];
+    b = LevelBufs{};
+    b.n = nl;
+    b.e0 = take(half * ts);
+    b.e1 = take(half * ts);
+    b.r0 = take(half * ts);
+    b.r1 = take(half * ts);
+    if (l < tail && nl <= kFusedEdgeMax && nl >= 16) {
+      b.d0 = take(half * ts);
+      b.d1 = take(half * ts);
+      b.fty = b.ftz = fused_tile(nl);
+    }
+  }
+  return off;
+}
+
+// First call on the current device: locate its copy of the scratch array,
+// store the Green's function there and allow the kernels their LDS.
+p3mz_status noalloc_device(unsigned char** base) {
+  int dev = 0;
+  P3MZ_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoallocMaxDevices) return fail(P3MZ_ERR_INVALID_ARG, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  NoallocDevice& d = g_noalloc[dev];
+  if (!d.base) {
+    void* ptr = nullptr;
+    P3MZ_HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    LevelBufs lv[P3MZ_MAX_LEVELS];
+    Ctl* ctl = nullptr;
+    double* green = nullptr;
+    noalloc_layout((unsigned char*)ptr, 8, 8, 2, 0, lv, &ctl, &green);
+    double g[64];
+    coarse_green(g);
+    P3MZ_HIP_TRY(hipMemcpy(green, g, sizeof g, hipMemcpyHostToDevice));
+    size_t lds = 0;
+    for (int fp64 = 0; fp64 < 2; fp64++) {
+      P3MZ_HIP_TRY(tail_configure(fp64 != 0, 8, 2, &lds));
+      P3MZ_HIP_TRY(tail_configure(fp64 != 0, 16, 3, &lds));
+    }
+    P3MZ_HIP_TRY(fused_configure());
+    P3MZ_HIP_TRY(hipDeviceSynchronize());
+    d.base = (unsigned char*)ptr;
+  }
+  *base = d.base;
+  return P3MZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+p3mz_status p3mz_vcycle_noalloc(int32_t mesh, int32_t precision, int32_t nu_pre, int32_t nu_post, const double* r_dev,
+                                double* e_dev, void* stream) {
+  if (!r_dev || !e_dev) return fail(P3MZ_ERR_INVALID_ARG, "NULL argument");
+  int m = mesh;
+  while (m > 4 && (m & 1) == 0) m >>= 1;
+  if (mesh < 8 || m != 4 || mesh > kNoallocMaxMesh)
+    return fail(P3MZ_ERR_INVALID_ARG, "mesh must be 4*2^m points per edge, 8..64");
+  if (precision != P3MZ_PREC_FP64 && precision != P3MZ_PREC_MIXED) return fail(P3MZ_ERR_INVALID_ARG, "bad precision");
+  if (nu_pre < 0 || nu_post < 0 || nu_pre > 16 || nu_post > 16 || nu_pre + nu_post < 1)
+    return fail(P3MZ_ERR_INVALID_ARG, "bad sweep counts");
+  unsigned char* base = nullptr;
+  P3MZ_TRY(noalloc_device(&base));
+  const bool fp64 = precision == P3MZ_PREC_FP64;
+  int levels = 0, tail = 0;
+  for (int q = mesh; q >= 4; q >>= 1) levels++;
+  while ((mesh >> tail) > P3MZ_TAIL_MAX) tail++;
+  LevelBufs lv[P3MZ_MAX_LEVELS];
+  Ctl* ctl = nullptr;
+  double* green = nullptr;
+  if (noalloc_layout(base, mesh, fp64 ? 8 : 4, levels, tail, lv, &ctl, &green) > kNoallocBytes)
+    return fail(P3MZ_ERR_INVALID_ARG, "mesh too large for the scratch array");
+  hipStream_t s = (hipStream_t)stream;
+  P3MZ_HIP_TRY(launch_set_ctl_open(ctl, s));
+  P3MZ_HIP_TRY(launch_nat_to_cs(fp64, mesh, r_dev, lv[0].r0, lv[0].r1, s));
+  P3MZ_HIP_TRY(launch_vcycle(fp64, lv, levels, tail, nu_pre, nu_post, green, ctl, s));
+  P3MZ_HIP_TRY(launch_cs_to_nat(fp64, mesh, lv[0].e0, lv[0].e1, e_dev, s));
+  return P3MZ_OK;
 }
 
 const char* p3mz_status_string(p3mz_status s) {

@@ -29,7 +29,8 @@ P3MZ_PREC_MIXED = 1
 MESH_Q, MESH_QS, MESH_SIGMA_P, MESH_Y, MESH_PHI, MESH_PHI_PREV = range(6)
 
 # every symbol include/p3maze.h declares
-EXPORTS = ["p3mz_create", "p3mz_compute", "p3mz_get_mesh", "p3mz_get_potential", "p3mz_vcycle", "p3mz_get_stats",
+EXPORTS = ["p3mz_create", "p3mz_compute", "p3mz_get_mesh", "p3mz_get_potential", "p3mz_vcycle",
+           "p3mz_vcycle_noalloc", "p3mz_get_stats",
            "p3mz_reset_history", "p3mz_save_state", "p3mz_load_state", "p3mz_md_run",
            "p3mz_set_graphs", "p3mz_set_timing", "p3mz_set_kernel_timer", "p3mz_get_kernel_timer",
            "p3mz_get_kernel_launches",
@@ -97,6 +98,7 @@ def _load() -> C.CDLL:
         "p3mz_get_mesh": ([vp, C.c_int32, vp, vp], C.c_int),
         "p3mz_get_potential": ([vp, vp, vp], C.c_int),
         "p3mz_vcycle": ([vp, vp, vp, vp], C.c_int),
+        "p3mz_vcycle_noalloc": ([C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp], C.c_int),
         "p3mz_get_stats": ([vp, C.POINTER(p3mz_stats)], C.c_int),
         "p3mz_reset_history": ([vp], C.c_int),
         "p3mz_save_state": ([vp, vp, C.POINTER(C.c_size_t)], C.c_int),
@@ -172,6 +174,12 @@ def p3mz_get_potential(ctx: int, phi_dev: int, stream: int | None = None) -> int
 
 def p3mz_vcycle(ctx: int, r_dev: int, e_dev: int, stream: int | None = None) -> int:
     return _check(lib.p3mz_vcycle(ctx, r_dev, e_dev, stream), "p3mz_vcycle")
+
+
+def p3mz_vcycle_noalloc(mesh: int, precision: int, nu_pre: int, nu_post: int, r_dev: int, e_dev: int,
+                        stream: int | None = None) -> int:
+    return _check(lib.p3mz_vcycle_noalloc(mesh, precision, nu_pre, nu_post, r_dev, e_dev, stream),
+                  "p3mz_vcycle_noalloc")
 
 
 def p3mz_get_stats(ctx: int) -> p3mz_stats:
