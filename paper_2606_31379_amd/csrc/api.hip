@@ -184,8 +184,10 @@ struct p3mz_ctx {
   void* d_taps = nullptr;
   double* d_green = nullptr;
   double* d_qa = nullptr;
-  int *d_base = nullptr, *d_key = nullptr, *d_slot = nullptr, *d_perm_raw = nullptr;
-  void* d_w = nullptr;
+  int *d_key = nullptr, *d_slot = nullptr, *d_perm_raw = nullptr;
+  void* d_rb = nullptr;   // int2 records in bin order: stencil origin, atom index
+  void* d_rq = nullptr;   // double4 records in bin order: charge, fractional offsets
+  int* d_cls = nullptr;   // first position of each crossing class in each bin (8 per bin)
   int ntx = 0, nbins = 0;
   int *d_count = nullptr, *d_start = nullptr, *d_bsum = nullptr;
   int nc = 1, ncells = 1;
@@ -514,13 +516,14 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   const int64_t na = c->n_atoms;
   c->ntx = n / kTile;
   c->nbins = c->ntx * c->ntx * c->ntx;
-  P3MZ_TRY(c->alloc(&c->d_base, 4 * na));                                 // int4 records in bin order
-  P3MZ_TRY(c->allocb(&c->d_w, (size_t)na * (1 + 3 * pl.p) * 8));          // charge + weights in bin order
+  P3MZ_TRY(c->allocb(&c->d_rb, (size_t)na * 8));
+  P3MZ_TRY(c->allocb(&c->d_rq, (size_t)na * 32));
   P3MZ_TRY(c->alloc(&c->d_key, na));
   P3MZ_TRY(c->alloc(&c->d_slot, na));
   P3MZ_TRY(c->alloc(&c->d_perm_raw, na));
   P3MZ_TRY(c->alloc(&c->d_count, c->nbins));
   P3MZ_TRY(c->alloc(&c->d_start, c->nbins + 1));
+  P3MZ_TRY(c->alloc(&c->d_cls, 8 * (size_t)c->nbins));
   P3MZ_HIP_TRY(hipMemset(c->d_count, 0, sizeof(int) * c->nbins));
   c->nc = cells_per_edge(c->P.box, c->P.r_cut);
   c->ncells = c->ncells_max = c->nc * c->nc * c->nc;
@@ -624,13 +627,14 @@ p3mz_status enq_pre(p3mz_ctx* c, const double* pos, hipStream_t s) {
   rec_key(102);
   P3MZ_HIP_TRY(launch_scatter(na, c->d_key, c->d_slot, c->d_start, c->d_perm_raw, s));
   rec_key(103);
-  P3MZ_HIP_TRY(launch_sort_pack(c->nbins, c->d_start, c->d_perm_raw, na, pos, c->d_qa, c->P.box, n, pl.p, c->d_base,
-                                (double*)c->d_w, s));
+  P3MZ_HIP_TRY(launch_sort_pack(c->nbins, c->d_start, c->d_perm_raw, na, pos, c->d_qa, c->P.box, n, pl.p, kTile,
+                                c->d_rb, c->d_rq, c->d_cls, s));
   rec_key(104);
   kt_begin(KT_SPREAD, 0, s);
-  P3MZ_HIP_TRY(launch_spread(true, na, n, pl.p, kTile, c->ntx, c->d_start, c->d_base, (const double*)c->d_w, c->d_q,
+  P3MZ_HIP_TRY(launch_spread(true, n, pl.p, kTile, c->ntx, c->P.box, c->d_start, c->d_cls, c->d_rb, c->d_rq, c->d_q,
                              s));
-  kt_end(KT_SPREAD, 0, 8.0 * N3 + (double)na * (24.0 * pl.p + 24.0), s);
+  // algorithmic bytes: the mesh written once, each atom's 40-byte record read once
+  kt_end(KT_SPREAD, 0, 8.0 * N3 + 40.0 * (double)na, s);
   double* src[3] = {c->d_q, c->d_qs, c->d_tmp};
   double* dst[3] = {c->d_qs, c->d_tmp, c->d_qs};
   for (int axis = 0; axis < 3; axis++) {
@@ -700,12 +704,11 @@ p3mz_status enq_post1(p3mz_ctx* c, double* force, hipStream_t s) {
   stage(c, 2, s);
   rec_key(5001);
   kt_begin(KT_GATHER, 0, s);
-  P3MZ_HIP_TRY(launch_gather(c->fp64, na, n, pl.p, kTile, c->ntx, pl.h, c->P.coulomb_k, c->d_start, c->d_base,
-                             (const double*)c->d_w, c->d_phi[0], c->d_phi[1], c->d_phi32, force, c->d_partial,
-                             c->d_ctl, s));
-  // algorithmic bytes: the potential once, plus each atom's stencil record,
-  // charge and force (the (p+2)^3 neighbourhood reads are shared by atoms)
-  kt_end(KT_GATHER, 0, N3 * (c->fp64 ? 8.0 : 4.0) + (double)na * (48.0 + 24.0 * pl.p), s);
+  P3MZ_HIP_TRY(launch_gather(c->fp64, na, n, pl.p, kTile, c->ntx, pl.h, c->P.coulomb_k, c->d_start, c->d_rb, c->d_rq,
+                             c->d_phi[0], c->d_phi[1], c->d_phi32, force, c->d_partial, c->d_ctl, s));
+  // algorithmic bytes: the potential once, plus each atom's 40-byte record
+  // and its force (the (p+2)^3 neighbourhood reads are shared by atoms)
+  kt_end(KT_GATHER, 0, N3 * (c->fp64 ? 8.0 : 4.0) + (double)na * 64.0, s);
   return P3MZ_OK;
 }
 
@@ -1666,14 +1669,14 @@ p3mz_status p3mz_kernel_bench(p3mz_ctx* ctx, int32_t kernel_id, int32_t reps, vo
                        ctx->d_sigma, ctx->d_y[0], ctx->P.tol, ctx->P.tol_mode, ctx->d_partial, ctx->d_ctl, s, false);
       bytes = 64.0 * N3;
     } else if (kernel_id == KT_SPREAD) {
-      e = launch_spread(true, (int)ctx->n_atoms, n, p, kTile, ctx->ntx, ctx->d_start, ctx->d_base, (const double*)ctx->d_w,
+      e = launch_spread(true, n, p, kTile, ctx->ntx, ctx->P.box, ctx->d_start, ctx->d_cls, ctx->d_rb, ctx->d_rq,
                         ctx->d_tmp, s);
-      bytes = 8.0 * N3 + na * (24.0 * p + 24.0);
+      bytes = 8.0 * N3 + 40.0 * na;
     } else if (kernel_id == KT_GATHER) {
       e = launch_gather(ctx->fp64, (int)ctx->n_atoms, n, p, kTile, ctx->ntx, ctx->pl.h, ctx->P.coulomb_k, ctx->d_start,
-                        ctx->d_base, (const double*)ctx->d_w, ctx->d_phi[0], ctx->d_phi[1], ctx->d_phi32, nullptr,
+                        ctx->d_rb, ctx->d_rq, ctx->d_phi[0], ctx->d_phi[1], ctx->d_phi32, nullptr,
                         ctx->d_partial, ctx->d_ctl, s, false);
-      bytes = N3 * (ctx->fp64 ? 8.0 : 4.0) + na * (48.0 + 24.0 * p);
+      bytes = N3 * (ctx->fp64 ? 8.0 : 4.0) + 64.0 * na;
     } else {
       e = launch_vcycle_kernel(ctx->fp64, kernel_id, ctx->lv, ctx->pl.levels, ctx->pl.tail, ctx->nu1, ctx->nu2,
                                ctx->d_green, ctx->d_ctl, s, &bytes);

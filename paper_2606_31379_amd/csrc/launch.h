@@ -36,15 +36,17 @@ hipError_t launch_scatter(int n_atoms, const int* key, const int* slot, const in
 // Sort every bin's atom list by atom index (makes all later sums deterministic).
 hipError_t launch_sort_bins(int nbins, const int* start, const int* perm_raw, int* perm, Ctl* ctl,
                             hipStream_t s, const int* gate = nullptr);
-// Sort every bin's atom list by atom index and write each atom's records at
-// its sorted position i: rb[i] = {stencil origin x, y, z, atom index} (int4);
-// rw[c * n_atoms + i] = component c of {charge, FP64 B-spline weights
-// x | y | z}.
+// Sort every bin's atom list by (class, atom index) and write each atom's
+// records at its sorted position i: rb[i] = {stencil origin x | y << 10 |
+// z << 20, atom index} (int2), rq[i] = {charge, tau_x, tau_y, tau_z}
+// (double4); cls[8 b + c] = first position of class c (the faces of its tile
+// the atom's stencil crosses: bit d for axis d) in bin b.
 hipError_t launch_sort_pack(int nbins, const int* start, const int* perm_raw, int n_atoms, const double* pos,
-                            const double* qa, double box, int n, int p, void* rb, double* rw, hipStream_t s);
-// Owner-computes spread: q (natural layout, precision T) from the binned atoms.
-hipError_t launch_spread(bool fp64, int n_atoms, int n, int p, int tile, int ntx, const int* start, const void* rb,
-                         const double* rw, void* q, hipStream_t s);
+                            const double* qa, double box, int n, int p, int tile, void* rb, void* rq, int* cls,
+                            hipStream_t s);
+// Owner-computes spread: q (natural layout, FP64 or FP32) from the binned atoms.
+hipError_t launch_spread(bool fp64, int n, int p, int tile, int ntx, double box, const int* start, const int* cls,
+                         const void* rb, const void* rq, void* q, hipStream_t s);
 // Long-range force and energy by interpolating the central-difference
 // gradient of phi (precision of phi: fp64 or float).
 // phi: FP64 mode reads the new potential from phi0/phi1 (selected on the
@@ -53,7 +55,7 @@ hipError_t launch_spread(bool fp64, int n_atoms, int n, int p, int tile, int ntx
 // with finalize, both kernels do nothing unless ctl->done (the step's solve
 // has converged), so they may be enqueued before the host has checked it.
 hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, int tile, int ntx, double h, double k_e,
-                         const int* start, const void* rb, const double* rw, const double* phi0, const double* phi1,
+                         const int* start, const void* rb, const void* rq, const double* phi0, const double* phi1,
                          const float* phi32, double* force, double* partial, Ctl* ctl, hipStream_t s,
                          bool finalize = true);
 // Short-range erfc pairs (neighbour lists or the cell list), exclusion correction, energy

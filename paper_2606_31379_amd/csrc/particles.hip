@@ -67,32 +67,38 @@ __device__ void BinTiles::run(const Args& A, Grid G) {
   A.slot[a] = atomicAdd(&A.count[k], 1);
 }
 
-// Atom records in bin order, written by the bin sort: stencil origin and
-// atom index (rb), then charge and the 3p FP64 weights x | y | z (rw, one
-// row of n_atoms values per component: rw[c * n_atoms + i]), so the tile
-// kernels read their atoms' records coalesced instead of gathering them by
-// atom index.
-// The records of atom a at bin-order position i.
-__device__ __forceinline__ void pack_atom(int i, int a, int n_atoms, int n, int p, double box, const double* pos,
-                                          const double* qa, int4* rb, double* rw) {
-  const size_t na = (size_t)n_atoms;
-  double* rec = rw + i;
-  rec[0] = qa[a];
-  int f3[3];
+// Atom records in bin order, written by the bin sort: rb[i] = {stencil
+// origin x | y << 10 | z << 20, atom index} and rq[i] = {charge, tau_x,
+// tau_y, tau_z} (the fractional offsets the B-spline weights are computed
+// from), so the tile kernels read their atoms' 40 bytes coalesced instead of
+// gathering them by atom index, and form the weights themselves.
+__device__ __forceinline__ int org_pack(int x, int y, int z) { return x | (y << 10) | (z << 20); }
+__device__ __forceinline__ int org_x(int o) { return o & 1023; }
+__device__ __forceinline__ int org_y(int o) { return (o >> 10) & 1023; }
+__device__ __forceinline__ int org_z(int o) { return o >> 20; }
+
+// Stencil origin (wrapped into [0, n)) and fractional offset of atom a.
+__device__ __forceinline__ void atom_origin(int a, int n, int p, double box, const double* pos, int f3[3],
+                                            double tau3[3]) {
   for (int d = 0; d < 3; d++) {
     double x = pos[3 * a + d];
     if (!isfinite(x)) x = 0.0;
     int first;
-    double tau;
-    stencil_origin(x, box, n, p, &first, &tau);
+    stencil_origin(x, box, n, p, &first, &tau3[d]);
     int f = first % n;
     if (f < 0) f += n;
     f3[d] = f;
-    double wl[P3MZ_MAX_ORDER];
-    bspline_weights<double>(p, tau, wl);
-    for (int j = 0; j < p; j++) rec[(1 + d * p + j) * na] = wl[j];
   }
-  rb[i] = make_int4(f3[0], f3[1], f3[2], a);
+}
+
+// Class of an atom within its tile's bin: bit d set when its stencil crosses
+// the upper face of the tile along axis d (so it also reaches the next tile
+// along d).  A tile's spread needs, from the bin of the tile d below it, only
+// the classes that contain every bit of d.
+__device__ __forceinline__ int cross_class(const int f3[3], int tile, int p) {
+  int c = 0;
+  for (int d = 0; d < 3; d++) c |= ((f3[d] % tile) + p - 1 >= tile) << d;
+  return c;
 }
 
 struct BinCells {
@@ -267,20 +273,23 @@ struct Scatter {
   }
 };
 
-// One wave per bin: rank of each entry = number of smaller atom indices in
-// the bin (indices are distinct), so perm[start + rank] is the sorted list.
-// With rb set, the sorted entry is not stored: the atom's records are
-// written at its sorted position instead (the records described above).
+// One wave per bin: rank of each entry = number of smaller keys in the bin
+// (keys are distinct), so perm[start + rank] is the sorted list.  The key is
+// the atom index; for the mesh bins (rb set) it is (class, atom index), the
+// sorted entry is not stored, the atom's records are written at its sorted
+// position instead (the records described above) and cls[8 b + c] receives
+// the first position of class c in bin b.
 struct SortBins {
   struct Args {
     int nbins;
     const int *start, *perm_raw;
     int* perm;
-    int n_atoms, n, p;
+    int n_atoms, n, p, tile;
     double box;
     const double *pos, *qa;
-    int4* rb;
-    double* rw;
+    int2* rb;
+    double4* rq;
+    int* cls;
     const int* gate;
   };
   static constexpr int kThreads = kBlock;
@@ -291,48 +300,77 @@ __device__ void SortBins::run(const Args& A, Grid G) {
   const int nbins = A.nbins;
   const int* __restrict__ start = A.start;
   const int* __restrict__ perm_raw = A.perm_raw;
-  int* __restrict__ perm = A.perm;
   const int wave = (G.b * kBlock + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (wave >= nbins) return;
   const int s0 = start[wave], cnt = start[wave + 1] - s0;
+  const bool mesh = A.rb != nullptr;
+  // key of entry i: (class << 32) | atom index (class 0 for the cell bins)
+  auto key_of = [&](int i, int* f3, double* tau3) -> long long {
+    if (i >= cnt) return 0x7fffffffffffffffLL;
+    const int a = perm_raw[s0 + i];
+    if (!mesh) return a;
+    atom_origin(a, A.n, A.p, A.box, A.pos, f3, tau3);
+    return ((long long)cross_class(f3, A.tile, A.p) << 32) | (long long)a;
+  };
+  int ncls[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int i0 = 0; i0 < cnt; i0 += 64) {
     const int i = i0 + lane;
-    const int v = (i < cnt) ? perm_raw[s0 + i] : 0x7fffffff;
+    int f3[3];
+    double tau3[3];
+    const long long v = key_of(i, f3, tau3);
     int rank = 0;
     for (int j0 = 0; j0 < cnt; j0 += 64) {
-      const int vj_own = (j0 + lane < cnt) ? perm_raw[s0 + j0 + lane] : 0x7fffffff;
+      int g3[3];
+      double t3[3];
+      const long long vj_own = j0 == i0 ? v : key_of(j0 + lane, g3, t3);
       const int lim = min(64, cnt - j0);
       for (int jj = 0; jj < lim; jj++) {
-        int vj = __shfl(vj_own, jj, 64);
+        const long long vj = __shfl(vj_own, jj, 64);
         rank += (vj < v);
       }
     }
     if (i < cnt) {
-      if (A.rb)
-        pack_atom(s0 + rank, v, A.n_atoms, A.n, A.p, A.box, A.pos, A.qa, A.rb, A.rw);
-      else
-        perm[s0 + rank] = v;
+      const int a = (int)(v & 0xffffffffLL);
+      if (mesh) {
+        A.rb[s0 + rank] = make_int2(org_pack(f3[0], f3[1], f3[2]), a);
+        A.rq[s0 + rank] = make_double4(A.qa[a], tau3[0], tau3[1], tau3[2]);
+      } else {
+        A.perm[s0 + rank] = a;
+      }
+    }
+    if (mesh)
+      for (int c = 0; c < 8; c++) ncls[c] += __popcll(__ballot(i < cnt && (int)(v >> 32) == c));
+  }
+  if (mesh && lane == 0) {
+    int off = s0;
+    for (int c = 0; c < 8; c++) {
+      A.cls[8 * wave + c] = off;
+      off += ncls[c];
     }
   }
 }
 
 // Owner-computes spread.  One workgroup per TS^3 tile of the mesh; atoms are
-// keyed by the tile holding their first stencil index, so only the tile
-// itself and its lower neighbours (per axis) can reach it.  The candidate
-// atoms of those bins (fixed order: bins, then sorted atoms) are staged in
-// LDS in chunks, one atom record per thread (stencil origin, charge,
-// weights), so their global loads are independent.  Each wave then adds
-// whole atoms from LDS, one stencil point per lane, into its own LDS copy of
-// the tile (lanes of one atom touch distinct points); the four wave copies
-// are summed in a fixed order.  No global atomics, bitwise-reproducible.
+// keyed by the tile holding their first stencil index (p <= TS, so a
+// stencil reaches at most the next tile along each axis).  The atoms that
+// reach the tile are those of its own bin and, from the bin of the tile d
+// below it (d in {0,1}^3), those whose class (the faces their stencil
+// crosses) contains d: at most 27 contiguous ranges of class-sorted bins,
+// staged in LDS in chunks in a fixed order (ranges, then positions), one
+// atom per thread, which also forms the atom's B-spline weights.  Each wave
+// then adds whole atoms from LDS, one stencil point per lane, into its own
+// LDS copy of the tile (lanes of one atom touch distinct points); the four
+// wave copies are summed in a fixed order.  No global atomics,
+// bitwise-reproducible.
 template <typename T, int TS, int P>
 struct Spread {
   struct Args {
-    int n, p, ntx, n_atoms;
-    const int* start;
-    const int4* rb;
-    const double* rw;
+    int n, ntx;
+    double box;
+    const int *start, *cls;
+    const int2* rb;
+    const double4* rq;
     T* q;
   };
   static constexpr int kThreads = kBlock;
@@ -342,55 +380,53 @@ struct Spread {
 template <typename T, int TS, int P>
 __device__ void Spread<T, TS, P>::run(const Args& A, Grid G) {
   // the assignment order is a template parameter: register arrays sized exactly
-  constexpr int V = TS * TS * TS, CH = kChunk, MW = 3 * P, p = P, pw = 3 * P;
+  constexpr int V = TS * TS * TS, CH = kChunk, p = P, pw = 3 * P;
   const int n = A.n, ntx = A.ntx;
   const int* __restrict__ start = A.start;
-  const int4* __restrict__ rb = A.rb;
-  const double* __restrict__ rw = A.rw;
+  const int* __restrict__ cls = A.cls;
+  const int2* __restrict__ rb = A.rb;
+  const double4* __restrict__ rq = A.rq;
   T* __restrict__ q = A.q;
-  const size_t na = (size_t)A.n_atoms;   // row length of rw
   __shared__ T acc[kBlock / 64][V];
-  extern __shared__ __align__(16) unsigned char spread_lds[];
-  T* const sw = reinterpret_cast<T*>(spread_lds);   // [CH][3p] weights x | y | z (dynamic LDS)
+  __shared__ T sw[CH * pw];      // [CH][3p] weights x | y | z
   __shared__ T sq[CH];
   __shared__ int sb[CH][3];      // stencil start relative to the tile
-  __shared__ int kidx[CH];       // staged atoms that reach the tile, in chunk order
-  __shared__ int bin_lo[8], bin_cnt[8], bin_off[9];
-  __shared__ int wave_cnt[kBlock / 64];
+  __shared__ int r_lo[64], r_off[65];   // staged ranges: first position, prefix of lengths
   const int t = G.b;
   const int tx = t % ntx, ty = (t / ntx) % ntx, tz = t / (ntx * ntx);
   const int ox = tx * TS, oy = ty * TS, oz = tz * TS;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int i = threadIdx.x; i < (kBlock / 64) * V; i += kBlock) (&acc[0][0])[i] = T(0);
-  // candidate bins: this tile and its lower neighbours, one thread each
-  const int nd = ntx > 1 ? 2 : 1, nbin = nd * nd * nd;
-  if ((int)threadIdx.x < 8) {
-    const int k = threadIdx.x;
-    int lo = 0, cnt = 0;
-    if (k < nbin) {
-      const int dx = k % nd, dy = (k / nd) % nd, dz = k / (nd * nd);
+  // the ranges: lane k = (d, c) of the first wave, d = k >> 3 the lower
+  // neighbour, c = k & 7 the class; used when c contains d (all classes of
+  // the tile's own bin; with one tile per axis, only the own bin)
+  if (wv == 0) {
+    const int nd = ntx > 1 ? 2 : 1;
+    const int d = lane >> 3, c = lane & 7;
+    const int dx = d & 1, dy = (d >> 1) & 1, dz = d >> 2;
+    int lo = 0, len = 0;
+    if ((c & d) == d && dx < nd && dy < nd && dz < nd) {
       int sx = tx - dx, sy = ty - dy, sz = tz - dz;
       sx += sx < 0 ? ntx : 0;
       sy += sy < 0 ? ntx : 0;
       sz += sz < 0 ? ntx : 0;
       const int b = (sz * ntx + sy) * ntx + sx;
-      lo = start[b];
-      cnt = start[b + 1] - lo;
+      lo = cls[8 * b + c];
+      len = (c < 7 ? cls[8 * b + c + 1] : start[b + 1]) - lo;
     }
-    bin_lo[k] = lo;
-    bin_cnt[k] = cnt;
+    // inclusive scan of the lengths over the wave
+    int incl = len;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int u = __shfl_up(incl, o, 64);
+      incl += lane >= o ? u : 0;
+    }
+    r_lo[lane] = lo;
+    r_off[lane + 1] = incl;
+    if (lane == 0) r_off[0] = 0;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int off = 0;
-    for (int k = 0; k < 8; k++) {
-      bin_off[k] = off;
-      off += bin_cnt[k];
-    }
-    bin_off[8] = off;
-  }
-  __syncthreads();
-  const int total = bin_off[8];
+  const int total = r_off[64];
   const int p2 = p * p, p3 = p2 * p;
   // this lane's stencil points of an atom, l = lane + 64 it (fixed for the
   // whole kernel; p^3 <= 343 needs up to 6 per lane); invalid slots get an
@@ -406,67 +442,51 @@ __device__ void Spread<T, TS, P>::run(const Args& A, Grid G) {
     say[it] = ok ? (l / p) % p : 0;
     saz[it] = ok ? l / p2 : 1 << 20;
   }
-  // Candidate atoms are staged CH at a time, one per thread.  The records of
-  // the next chunk are loaded into registers while the current chunk is
-  // being added, so only the first chunk waits for memory.
-  int4 nr = make_int4(0, 0, 0, 0);
-  double nq = 0.0, nwv[MW];
+  // Staged atoms CH at a time, one per thread.  The records of the next
+  // chunk are loaded into registers while the current chunk is being added,
+  // so only the first chunk waits for memory.
+  int2 nr = make_int2(0, 0);
+  double4 nq = make_double4(0.0, 0.0, 0.0, 0.0);
   auto fetch = [&](int c0) {
     if ((int)threadIdx.x < min(CH, total - c0)) {
       const int c = c0 + threadIdx.x;
-      int k = 0;
-      while (c >= bin_off[k + 1]) k++;
-      const int ps = bin_lo[k] + (c - bin_off[k]);   // position in bin order
+      int lo = 0, hi = 63;   // last range whose offset is <= c
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (r_off[mid] <= c) lo = mid;
+        else hi = mid - 1;
+      }
+      const int ps = r_lo[lo] + (c - r_off[lo]);   // position in bin order
       nr = rb[ps];
-      const double* rec = rw + ps;
-      nq = rec[0];
-#pragma unroll
-      for (int j = 0; j < MW; j++)   // fixed trip count: all loads in flight at once
-        if (j < pw) nwv[j] = rec[(1 + j) * na];
+      nq = rq[ps];
     }
   };
   fetch(0);
   for (int c0 = 0; c0 < total; c0 += CH) {
     const int m = min(CH, total - c0);
-    // the chunk's atoms whose stencil reaches this tile are listed in chunk
-    // order (the others sit in a lower neighbour bin too far from the shared
-    // face)
-    bool keep = false;
     if ((int)threadIdx.x < m) {
-      sq[threadIdx.x] = (T)nq;
-#pragma unroll
-      for (int j = 0; j < MW; j++)
-        if (j < pw) sw[threadIdx.x * pw + j] = (T)nwv[j];
-      const int b3[3] = {nr.x, nr.y, nr.z}, o3[3] = {ox, oy, oz};
-      keep = true;
+      const int i = threadIdx.x;
+      sq[i] = (T)nq.x;
+      const double tau3[3] = {nq.y, nq.z, nq.w};
+      const int b3[3] = {org_x(nr.x), org_y(nr.x), org_z(nr.x)}, o3[3] = {ox, oy, oz};
       for (int d = 0; d < 3; d++) {
+        double wl[P];
+        bspline_weights<double>(p, tau3[d], wl);
+#pragma unroll
+        for (int j = 0; j < P; j++) sw[i * pw + d * p + j] = (T)wl[j];
         int rel = b3[d] - o3[d];              // stencil start relative to the tile, mod n
         rel += rel < 0 ? n : 0;
-        // reaches the tile iff some point rel + t (t < p) lies in [0, TS) mod n
-        keep &= rel < TS || rel + p - 1 >= n;
-        sb[threadIdx.x][d] = rel < TS ? rel : rel - n;   // in [-(p-1), TS) for a kept atom
+        sb[i][d] = rel < TS ? rel : rel - n;   // in [-(p-1), TS)
       }
     }
-    const unsigned long long bal = __ballot(keep);
-    if (lane == 0) wave_cnt[wv] = __popcll(bal);
-    __syncthreads();
-    int slot = __popcll(bal & ((1ull << lane) - 1ull));
-    int mk = 0;
-    for (int k = 0; k < kBlock / 64; k++) {
-      slot += k < wv ? wave_cnt[k] : 0;
-      mk += wave_cnt[k];
-    }
-    if (keep) kidx[slot] = threadIdx.x;
     __syncthreads();
     if (c0 + CH < total) fetch(c0 + CH);
-    // kept atoms round-robin over the waves, in chunk order per wave: this
-    // wave's j-th atom is kidx[wv + 4 j], its index held in lane j of one
-    // register.  Two atoms are prepared at a time and added in order, so the
-    // loads of the second overlap the first; lanes of one atom hit distinct
-    // points and a wave's adds to one point execute in program order, so the
-    // sums stay deterministic (no-return LDS adds).
-    const int nmine = (mk - wv + kBlock / 64 - 1) / (kBlock / 64);
-    const int kv = lane < nmine ? kidx[wv + (kBlock / 64) * lane] : 0;
+    // staged atoms round-robin over the waves, in chunk order per wave: this
+    // wave's j-th atom is wv + 4 j.  Two atoms are prepared at a time and
+    // added in order, so the loads of the second overlap the first; lanes
+    // of one atom hit distinct points and a wave's adds to one point execute
+    // in program order, so the sums stay deterministic (no-return LDS adds).
+    const int nmine = (m - wv + kBlock / 64 - 1) / (kBlock / 64);
     auto prep = [&](int i, T* c, int* at) {
       const int rx = sb[i][0], ry = sb[i][1], rz = sb[i][2];
       const T* wi = sw + i * pw;
@@ -495,13 +515,13 @@ __device__ void Spread<T, TS, P>::run(const Args& A, Grid G) {
           __hip_atomic_fetch_add(&acc[wv][at[it]], c[it], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     };
     for (int j = 0; j < nmine; j += 2) {
-      T c0[kMaxIt], c1[kMaxIt];
+      T c0v[kMaxIt], c1v[kMaxIt];
       int at0[kMaxIt], at1[kMaxIt];
-      prep(__builtin_amdgcn_readlane(kv, j), c0, at0);
+      prep(wv + (kBlock / 64) * j, c0v, at0);
       const bool two = j + 1 < nmine;
-      if (two) prep(__builtin_amdgcn_readlane(kv, j + 1), c1, at1);
-      add(c0, at0);
-      if (two) add(c1, at1);
+      if (two) prep(wv + (kBlock / 64) * (j + 1), c1v, at1);
+      add(c0v, at0);
+      if (two) add(c1v, at1);
     }
     __syncthreads();
   }
@@ -529,8 +549,8 @@ struct Gather {
     int n_atoms, n, p, ntx;
     double h, k_e;
     const int* start;
-    const int4* rb;
-    const double* rw;
+    const int2* rb;
+    const double4* rq;
     const TP *phi0, *phi1;
     double *force, *partial;
     const Ctl* ctl;
@@ -547,9 +567,8 @@ __device__ void Gather<T, TP, TS, P>::run(const Args& A, Grid G) {
   const int n = A.n, ntx = A.ntx;
   const double h = A.h, k_e = A.k_e;
   const int* __restrict__ start = A.start;
-  const int4* __restrict__ rb = A.rb;
-  const double* __restrict__ rw = A.rw;
-  const size_t na = (size_t)A.n_atoms;   // row length of rw
+  const int2* __restrict__ rb = A.rb;
+  const double4* __restrict__ rq = A.rq;
   double* __restrict__ force = A.force;
   double* __restrict__ partial = A.partial;
   const Ctl* ctl = A.ctl;
@@ -585,27 +604,36 @@ __device__ void Gather<T, TP, TS, P>::run(const Args& A, Grid G) {
   // weights and stencil origin are loaded ahead of the evaluation.  Threads
   // k < per_round also hold atom k's index and charge for the final sums.
   T rwx[P], rwy[P], rwz[P];
-  int4 rorg = make_int4(0, 0, 0, 0);
+  int rorg = 0;
   int ka = 0;
   double kq = 0.0;
+  double4 rtau = make_double4(0.0, 0.0, 0.0, 0.0);
+  // the round's records are loaded ahead; the weights are formed from the
+  // fractional offsets (FP64, then rounded to T) right before the round
   auto load_round = [&](int a0, int na_t, int ag) {
     const int ai = ag + tid / PE;
     if (tid < per_round * PE && ai < na_t) {
       const int ps = a0 + ai;
-      const double* w = rw + na + ps;   // weight j of this atom: w[j * na]
-#pragma unroll
-      for (int j = 0; j < P; j++) {
-        rwx[j] = (T)w[j * na];
-        rwy[j] = (T)w[(P + j) * na];
-        rwz[j] = (T)w[(2 * P + j) * na];
-      }
-      rorg = rb[ps];
+      rtau = rq[ps];
+      rorg = rb[ps].x;
     }
     if (tid < per_round && ag + tid < na_t) {
       const int ps = a0 + ag + tid;
-      ka = rb[ps].w;
-      kq = k_e * rw[ps];
+      ka = rb[ps].y;
+      kq = k_e * rq[ps].x;
     }
+  };
+  auto form_weights = [&]() {
+    double wl[P];
+    bspline_weights<double>(P, rtau.y, wl);
+#pragma unroll
+    for (int j = 0; j < P; j++) rwx[j] = (T)wl[j];
+    bspline_weights<double>(P, rtau.z, wl);
+#pragma unroll
+    for (int j = 0; j < P; j++) rwy[j] = (T)wl[j];
+    bspline_weights<double>(P, rtau.w, wl);
+#pragma unroll
+    for (int j = 0; j < P; j++) rwz[j] = (T)wl[j];
   };
   if (G.b < ntiles) fetch(G.b);
   for (int t = G.b; t < ntiles; t += G.g) {
@@ -623,6 +651,7 @@ __device__ void Gather<T, TP, TS, P>::run(const Args& A, Grid G) {
     for (int ag = 0; ag < na_t; ag += per_round) {
       const int ai = ag + tid / PE, c = tid % PE;
       if (tid < per_round * PE && ai < na_t) {
+        form_weights();
         // extended index j <-> stencil offset j-1; d[j] = (w[j-1] - w[j+1]) / 2h
         T wx[PE], wy[PE], dx[PE], dy[PE], wz[PE];
 #pragma unroll
@@ -647,7 +676,7 @@ __device__ void Gather<T, TP, TS, P>::run(const Args& A, Grid G) {
             dz_c = (loz - hiz) * inv2h;
           }
         // neighbourhood origin in the halo tile: base - 1 - (tile origin - 1)
-        const int lx0 = rorg.x - (ox + 1), ly0 = rorg.y - (oy + 1), lz0 = rorg.z - (oz + 1);
+        const int lx0 = org_x(rorg) - (ox + 1), ly0 = org_y(rorg) - (oy + 1), lz0 = org_z(rorg) - (oz + 1);
         double fx = 0, fy = 0, fz = 0, pot = 0;
         const T* plane = sphi + (lz0 + c) * E * E;
 #pragma unroll
@@ -1139,42 +1168,42 @@ hipError_t launch_scatter(int n_atoms, const int* key, const int* slot, const in
 
 hipError_t launch_sort_bins(int nbins, const int* start, const int* perm_raw, int* perm, Ctl*,
                             hipStream_t s, const int* gate) {
-  return go<SortBins>({nbins, start, perm_raw, perm, 0, 0, 0, 0.0, nullptr, nullptr, nullptr, nullptr, gate},
+  return go<SortBins>({nbins, start, perm_raw, perm, 0, 0, 0, 0, 0.0, nullptr, nullptr, nullptr, nullptr, nullptr,
+                       gate},
                       blocks_for((int64_t)nbins * 64, kBlock), 0, s);
 }
 
 hipError_t launch_sort_pack(int nbins, const int* start, const int* perm_raw, int n_atoms, const double* pos,
-                            const double* qa, double box, int n, int p, void* rb, double* rw, hipStream_t s) {
-  return go<SortBins>({nbins, start, perm_raw, nullptr, n_atoms, n, p, box, pos, qa, (int4*)rb, rw},
+                            const double* qa, double box, int n, int p, int tile, void* rb, void* rq, int* cls,
+                            hipStream_t s) {
+  return go<SortBins>({nbins, start, perm_raw, nullptr, n_atoms, n, p, tile, box, pos, qa, (int2*)rb, (double4*)rq,
+                       cls, nullptr},
                       blocks_for((int64_t)nbins * 64, kBlock), 0, s);
 }
 
 namespace {
 template <int P>
-hipError_t spread_p(bool fp64, int n_atoms, int n, int ntx, const int* start, const void* rb, const double* rw,
-                    void* q, hipStream_t s) {
+hipError_t spread_p(bool fp64, int n, int ntx, double box, const int* start, const int* cls, const void* rb,
+                    const void* rq, void* q, hipStream_t s) {
   const int ntiles = ntx * ntx * ntx;
-  if (fp64) {
-    using K = Spread<double, 8, P>;
-    return go<K>({n, P, ntx, n_atoms, start, (const int4*)rb, rw, (double*)q}, ntiles,
-                 (size_t)K::kChunk * 3 * P * sizeof(double), s);
-  }
-  using K = Spread<float, 8, P>;
-  return go<K>({n, P, ntx, n_atoms, start, (const int4*)rb, rw, (float*)q}, ntiles,
-               (size_t)K::kChunk * 3 * P * sizeof(float), s);
+  if (fp64)
+    return go<Spread<double, 8, P>>({n, ntx, box, start, cls, (const int2*)rb, (const double4*)rq, (double*)q}, ntiles,
+                                    0, s);
+  return go<Spread<float, 8, P>>({n, ntx, box, start, cls, (const int2*)rb, (const double4*)rq, (float*)q}, ntiles, 0,
+                                 s);
 }
 }  // namespace
 
-hipError_t launch_spread(bool fp64, int n_atoms, int n, int p, int tile, int ntx, const int* start, const void* rb,
-                         const double* rw, void* q, hipStream_t s) {
+hipError_t launch_spread(bool fp64, int n, int p, int tile, int ntx, double box, const int* start, const int* cls,
+                         const void* rb, const void* rq, void* q, hipStream_t s) {
   if (tile != 8) return hipErrorInvalidValue;
   switch (p) {
-    case 2: return spread_p<2>(fp64, n_atoms, n, ntx, start, rb, rw, q, s);
-    case 3: return spread_p<3>(fp64, n_atoms, n, ntx, start, rb, rw, q, s);
-    case 4: return spread_p<4>(fp64, n_atoms, n, ntx, start, rb, rw, q, s);
-    case 5: return spread_p<5>(fp64, n_atoms, n, ntx, start, rb, rw, q, s);
-    case 6: return spread_p<6>(fp64, n_atoms, n, ntx, start, rb, rw, q, s);
-    case 7: return spread_p<7>(fp64, n_atoms, n, ntx, start, rb, rw, q, s);
+    case 2: return spread_p<2>(fp64, n, ntx, box, start, cls, rb, rq, q, s);
+    case 3: return spread_p<3>(fp64, n, ntx, box, start, cls, rb, rq, q, s);
+    case 4: return spread_p<4>(fp64, n, ntx, box, start, cls, rb, rq, q, s);
+    case 5: return spread_p<5>(fp64, n, ntx, box, start, cls, rb, rq, q, s);
+    case 6: return spread_p<6>(fp64, n, ntx, box, start, cls, rb, rq, q, s);
+    case 7: return spread_p<7>(fp64, n, ntx, box, start, cls, rb, rq, q, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1182,18 +1211,20 @@ hipError_t launch_spread(bool fp64, int n_atoms, int n, int p, int tile, int ntx
 namespace {
 template <int P>
 hipError_t gather_p(bool fp64, int n_atoms, int n, int ntx, double h, double k_e, const int* start, const void* rb,
-                    const double* rw, const double* phi0, const double* phi1, const float* phi32, double* force,
+                    const void* rq, const double* phi0, const double* phi1, const float* phi32, double* force,
                     double* partial, Ctl* ctl, const Ctl* gate, int nb, hipStream_t s) {
   if (fp64)
-    return go<Gather<double, double, 8, P>>({n_atoms, n, P, ntx, h, k_e, start, (const int4*)rb, rw, phi0, phi1, force,
+    return go<Gather<double, double, 8, P>>({n_atoms, n, P, ntx, h, k_e, start, (const int2*)rb, (const double4*)rq,
+                                             phi0, phi1, force,
                                              partial, ctl, gate}, nb, 0, s);
-  return go<Gather<float, float, 8, P>>({n_atoms, n, P, ntx, h, k_e, start, (const int4*)rb, rw, phi32, phi32, force,
+  return go<Gather<float, float, 8, P>>({n_atoms, n, P, ntx, h, k_e, start, (const int2*)rb, (const double4*)rq,
+                                         phi32, phi32, force,
                                          partial, ctl, gate}, nb, 0, s);
 }
 }  // namespace
 
 hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, int tile, int ntx, double h, double k_e,
-                         const int* start, const void* rb, const double* rw, const double* phi0, const double* phi1,
+                         const int* start, const void* rb, const void* rq, const double* phi0, const double* phi1,
                          const float* phi32, double* force, double* partial, Ctl* ctl, hipStream_t s, bool finalize) {
   if (tile != 8) return hipErrorInvalidValue;
   const int nb = std::min(ntx * ntx * ntx, kMaxRedBlocks);
@@ -1201,12 +1232,12 @@ hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, int tile, int ntx
   const Ctl* gate = finalize ? ctl : nullptr;
   hipError_t e;
   switch (p) {
-    case 2: e = gather_p<2>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rw, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
-    case 3: e = gather_p<3>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rw, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
-    case 4: e = gather_p<4>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rw, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
-    case 5: e = gather_p<5>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rw, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
-    case 6: e = gather_p<6>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rw, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
-    case 7: e = gather_p<7>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rw, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
+    case 2: e = gather_p<2>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rq, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
+    case 3: e = gather_p<3>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rq, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
+    case 4: e = gather_p<4>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rq, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
+    case 5: e = gather_p<5>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rq, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
+    case 6: e = gather_p<6>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rq, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
+    case 7: e = gather_p<7>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rq, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess || !finalize) return e;
