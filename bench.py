@@ -324,7 +324,7 @@ def parity_and_baseline(torch, P, w, system, sample_steps, schedules):
     dev = torch.device("cuda")
     head = schedules.get("mixed") or schedules.get("fp64")
     head_key = (head["nu_pre"], head["nu_post"])
-    for precision, name in ((0, "fp64"), (1, "mixed")):
+    for precision, name in ((0, "fp64"), (1, "mixed"), (2, "mixed32")):
         sch = schedules.get(name)
         if sch is None:
             continue
@@ -562,7 +562,9 @@ def main():
     ap.add_argument("--kernel", default="auto", help="kernel family for the roofline (default: dominant)")
     ap.add_argument("--cpu-sample-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--modes", default="fp64,mixed", help="precision modes to run (the headline is mixed)")
+    ap.add_argument("--modes", default="fp64,mixed,mixed32",
+                    help="precision modes to run: fp64, mixed (FP32 V-cycle and gather), mixed32 (also an FP32 "
+                         "charge source)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default (2,2) V-cycle schedule")
     ap.add_argument("--gamma", type=float, default=None,
                     help="OVRVO thermostat friction in 1/fs at the workload's temperature (default: none)")
@@ -604,7 +606,7 @@ def main():
     if not args.no_tune and not os.environ.get("P3MZ_TUNE_CACHE"):
         import tempfile
         os.environ["P3MZ_TUNE_CACHE"] = os.path.join(tempfile.mkdtemp(prefix="p3mz_tune_"), "tune.json")
-    for precision, name in ((0, "fp64"), (1, "mixed")):
+    for precision, name in ((0, "fp64"), (1, "mixed"), (2, "mixed32")):
         if name not in modes:
             continue
         if args.no_tune:

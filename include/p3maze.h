@@ -56,7 +56,16 @@ typedef enum {
   P3MZ_ERR_DENSITY = -8          /* too many atoms in one spatial bin for the deterministic sort */
 } p3mz_status;
 
-typedef enum { P3MZ_PREC_FP64 = 0, P3MZ_PREC_MIXED = 1 } p3mz_precision;
+/* FP64: every stage in FP64.  MIXED: the V-cycle and the gather in FP32,
+ * the charge source, sigma_p, the outer residual, projections, coarsest
+ * solve and updates in FP64.  MIXED32: as MIXED with an FP32 charge
+ * source: the assigned charges (summed in FP64) are stored and smoothed in
+ * FP32; sigma_p is still formed in FP64 from the widened FP32 charges.  The
+ * rounding noise (~1e-7 of max|q^s|, new every step and amplified by the
+ * multiplier extrapolation) perturbs the residual sequence; at tolerances
+ * of 1e-6 and above the V-cycle counts match an FP64 reference, at 1e-8 it
+ * costs extra V-cycles.  Meant for tol >= 1e-6. */
+typedef enum { P3MZ_PREC_FP64 = 0, P3MZ_PREC_MIXED = 1, P3MZ_PREC_MIXED32 = 2 } p3mz_precision;
 
 /* Control parameters of the problem statement (Theory; protocol paragraphs
  * of the molten-salt and water results). */
@@ -77,7 +86,9 @@ typedef struct {
                           prolongation, and the force gather in FP32; charge
                           assignment, smoothing, sigma_p, the outer residual,
                           zero-mean projections, coarsest solve and the
-                          multiplier/potential updates in FP64                */
+                          multiplier/potential updates in FP64.  MIXED32:
+                          assigned charges stored and smoothed in FP32 as
+                          well (for tol >= 1e-6)                           */
   double coulomb_k;    /* Coulomb constant k_e (1 for Gaussian units)                   */
   int32_t nu_pre;      /* red-black Gauss-Seidel sweeps before restriction, >= 0;
                           -1: the autotuned or default (2) value                       */

@@ -53,7 +53,8 @@ p3mz_status make_plan(const p3mz_params& P, Plan* pl) {
   if (!(P.tol > 0) || P.tol_mode < 0 || P.tol_mode > 1) return fail(P3MZ_ERR_INVALID_ARG, "bad tolerance");
   if (P.max_cycles < 0 || P.max_cycles > P3MZ_MAX_CYCLES) return fail(P3MZ_ERR_INVALID_ARG, "max_cycles must be in 0..64");
   if (P.predictor < 0 || P.predictor > 3) return fail(P3MZ_ERR_INVALID_ARG, "predictor must be in 0..3");
-  if (P.precision != P3MZ_PREC_FP64 && P.precision != P3MZ_PREC_MIXED) return fail(P3MZ_ERR_INVALID_ARG, "bad precision");
+  if (P.precision != P3MZ_PREC_FP64 && P.precision != P3MZ_PREC_MIXED && P.precision != P3MZ_PREC_MIXED32)
+    return fail(P3MZ_ERR_INVALID_ARG, "bad precision");
   if (P.nu_pre < -1 || P.nu_post < -1 || P.nu_pre > 16 || P.nu_post > 16) return fail(P3MZ_ERR_INVALID_ARG, "bad sweep counts");
   if (P.excl_group < 0) return fail(P3MZ_ERR_INVALID_ARG, "excl_group must be >= 0");
   const int n = P.mesh;
@@ -173,6 +174,7 @@ struct p3mz_ctx {
   Plan pl;
   int dev = 0;
   bool fp64 = true;
+  bool src32 = false;      // charge assignment and smoothing in FP32
   size_t tsz = 8;
   int nu1 = 2, nu2 = 2;
   int smooth_tile = 0;     // smoothing launch shape (autotuned)
@@ -354,7 +356,8 @@ std::string tune_key(int n, int p, int precision) {
   for (char& ch : arch)
     if (ch == '"' || ch == ' ') ch = '_';
   char buf[256];
-  snprintf(buf, sizeof buf, "%s/n%d/p%d/%s", arch.c_str(), n, p, precision == P3MZ_PREC_FP64 ? "fp64" : "mixed");
+  snprintf(buf, sizeof buf, "%s/n%d/p%d/%s", arch.c_str(), n, p,
+           precision == P3MZ_PREC_FP64 ? "fp64" : precision == P3MZ_PREC_MIXED ? "mixed" : "mixed32");
   return buf;
 }
 
@@ -482,6 +485,7 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   const int n = pl.n;
   c->n3 = (int64_t)n * n * n;
   c->fp64 = c->P.precision == P3MZ_PREC_FP64;
+  c->src32 = c->P.precision == P3MZ_PREC_MIXED32;
   c->tsz = c->fp64 ? 8 : 4;
   TuneEntry tuned;
   const bool have_tune = tune_lookup(tune_key(pl.n, pl.p, c->P.precision), &tuned);
@@ -495,9 +499,8 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   c->e_self = e_self;
   P3MZ_TRY(c->alloc(&c->d_qa, c->n_atoms));
   P3MZ_HIP_TRY(hipMemcpy(c->d_qa, charges_host, sizeof(double) * c->n_atoms, hipMemcpyHostToDevice));
-  // The charge source (weights, spread, smoothing, sigma_p) is FP64 in both
-  // modes: FP32 rounding of q^s (~1e-7 relative) would exceed the residual
-  // tolerance and change the V-cycle counts of the warm-started solve.
+  // The charge source (spread, smoothing) is FP64 in the FP64 and MIXED
+  // modes and FP32 in MIXED32; sigma_p is formed in FP64 in every mode.
   std::vector<double> taps;
   smoothing_taps(n, pl.K, pl.nu_s, &taps, &c->half);
   c->ntaps = (int)taps.size();
@@ -508,7 +511,12 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
     if (smooth_tile_ok(t, n, c->ntaps)) c->smooth_tile = t;
   if (c->smooth_tile < 0) return fail(P3MZ_ERR_MESH_SHAPE, "no smoothing launch shape fits this mesh");
   P3MZ_TRY(c->allocb(&c->d_taps, taps.size() * 8));
-  P3MZ_HIP_TRY(hipMemcpy(c->d_taps, taps.data(), taps.size() * 8, hipMemcpyHostToDevice));
+  if (c->src32) {
+    std::vector<float> t32(taps.begin(), taps.end());
+    P3MZ_HIP_TRY(hipMemcpy(c->d_taps, t32.data(), t32.size() * 4, hipMemcpyHostToDevice));
+  } else {
+    P3MZ_HIP_TRY(hipMemcpy(c->d_taps, taps.data(), taps.size() * 8, hipMemcpyHostToDevice));
+  }
   double g[64];
   coarse_green(g);
   P3MZ_TRY(c->alloc(&c->d_green, 64));
@@ -631,17 +639,19 @@ p3mz_status enq_pre(p3mz_ctx* c, const double* pos, hipStream_t s) {
                                 c->d_rb, c->d_rq, c->d_cls, s));
   rec_key(104);
   kt_begin(KT_SPREAD, 0, s);
-  P3MZ_HIP_TRY(launch_spread(true, n, pl.p, kTile, c->ntx, c->P.box, c->d_start, c->d_cls, c->d_rb, c->d_rq, c->d_q,
-                             s));
+  const double qsz = c->src32 ? 4.0 : 8.0;   // bytes per point of the charge source
+  P3MZ_HIP_TRY(launch_spread(!c->src32, n, pl.p, kTile, c->ntx, c->P.box, c->d_start, c->d_cls, c->d_rb, c->d_rq,
+                             c->d_q, s));
   // algorithmic bytes: the mesh written once, each atom's 40-byte record read once
-  kt_end(KT_SPREAD, 0, 8.0 * N3 + 40.0 * (double)na, s);
+  kt_end(KT_SPREAD, 0, qsz * N3 + 40.0 * (double)na, s);
   double* src[3] = {c->d_q, c->d_qs, c->d_tmp};
   double* dst[3] = {c->d_qs, c->d_tmp, c->d_qs};
   for (int axis = 0; axis < 3; axis++) {
     rec_key(105 + axis);
     kt_begin(KT_SMOOTH, 0, s);
-    P3MZ_HIP_TRY(launch_smooth(true, n, axis, c->smooth_tile, c->ntaps, c->half, c->d_taps, src[axis], dst[axis], s));
-    kt_end(KT_SMOOTH, 0, 16.0 * N3, s);
+    P3MZ_HIP_TRY(launch_smooth(!c->src32, n, axis, c->smooth_tile, c->ntaps, c->half, c->d_taps, src[axis], dst[axis],
+                               s));
+    kt_end(KT_SMOOTH, 0, 2.0 * qsz * N3, s);
   }
   stage(c, 1, s);
   rec_key(110);
@@ -651,10 +661,10 @@ p3mz_status enq_pre(p3mz_ctx* c, const double* pos, hipStream_t s) {
   // their own) and leaves that residual's stop decision to the first
   // cycle's tail: two launches less per step.  A batch keeps both passes.
   const bool fold = !g_recorder;
-  P3MZ_HIP_TRY(launch_sigma(n, pl.h, c->d_qs, c->d_phi[0], c->d_phi[1], c->d_yh[0], c->d_yh[1], c->d_yh[2],
+  P3MZ_HIP_TRY(launch_sigma(n, pl.h, c->src32, c->d_qs, c->d_phi[0], c->d_phi[1], c->d_yh[0], c->d_yh[1], c->d_yh[2],
                             c->d_sigma, c->d_y[0], c->P.tol, c->P.tol_mode, fold ? c->d_spart : c->d_partial,
                             c->d_ctl, s, !fold));
-  kt_end(KT_SIGMA, 0, 64.0 * N3, s);
+  kt_end(KT_SIGMA, 0, (56.0 + qsz) * N3, s);
   const LevelBufs& f = c->lv[0];
   rec_key(111);
   kt_begin(KT_OUTER, 0, s);
@@ -1392,8 +1402,8 @@ p3mz_status p3mz_get_mesh(p3mz_ctx* ctx, int32_t which, double* out_dev, void* s
   const size_t n3 = (size_t)ctx->n3;
   const Ctl& m = ctx->mirror;
   switch (which) {
-    case 0: P3MZ_HIP_TRY(hipMemcpyAsync(out_dev, ctx->d_q, n3 * 8, hipMemcpyDeviceToDevice, s)); break;
-    case 1: P3MZ_HIP_TRY(hipMemcpyAsync(out_dev, ctx->d_qs, n3 * 8, hipMemcpyDeviceToDevice, s)); break;
+    case 0: P3MZ_HIP_TRY(launch_widen(!ctx->src32, (int64_t)n3, ctx->d_q, out_dev, s)); break;
+    case 1: P3MZ_HIP_TRY(launch_widen(!ctx->src32, (int64_t)n3, ctx->d_qs, out_dev, s)); break;
     case 2: P3MZ_HIP_TRY(launch_sub_scalar(n3, ctx->d_sigma, out_dev, &ctx->d_ctl->mean_sigma, s)); break;
     case 3: {
       // the final multiplier after the zero-mean projection is the newest
@@ -1655,9 +1665,9 @@ p3mz_status p3mz_kernel_bench(p3mz_ctx* ctx, int32_t kernel_id, int32_t reps, vo
     const int p = ctx->pl.p, n = ctx->pl.n;
     const LevelBufs& f = ctx->lv[0];
     if (kernel_id == KT_SMOOTH) {
-      e = launch_smooth(true, ctx->pl.n, 0, ctx->smooth_tile, ctx->ntaps, ctx->half, ctx->d_taps, ctx->d_q, ctx->d_tmp,
-                        s);
-      bytes = 16.0 * N3;
+      e = launch_smooth(!ctx->src32, ctx->pl.n, 0, ctx->smooth_tile, ctx->ntaps, ctx->half, ctx->d_taps, ctx->d_q,
+                        ctx->d_tmp, s);
+      bytes = (ctx->src32 ? 8.0 : 16.0) * N3;
     } else if (kernel_id == KT_OUTER) {
       // the cycle form without its finalize pass; both multiplier buffers
       // are scratch between steps (the multiplier is kept in the history slots)
@@ -1665,13 +1675,14 @@ p3mz_status p3mz_kernel_bench(p3mz_ctx* ctx, int32_t kernel_id, int32_t reps, vo
                        f.r1, ctx->d_partial, ctx->d_ctl, s, false);
       bytes = (24.0 + 2.0 * ts) * N3;
     } else if (kernel_id == KT_SIGMA) {
-      e = launch_sigma(n, ctx->pl.h, ctx->d_qs, ctx->d_phi[0], ctx->d_phi[1], ctx->d_yh[0], ctx->d_yh[1], ctx->d_yh[2],
-                       ctx->d_sigma, ctx->d_y[0], ctx->P.tol, ctx->P.tol_mode, ctx->d_partial, ctx->d_ctl, s, false);
-      bytes = 64.0 * N3;
+      e = launch_sigma(n, ctx->pl.h, ctx->src32, ctx->d_qs, ctx->d_phi[0], ctx->d_phi[1], ctx->d_yh[0], ctx->d_yh[1],
+                       ctx->d_yh[2], ctx->d_sigma, ctx->d_y[0], ctx->P.tol, ctx->P.tol_mode, ctx->d_partial, ctx->d_ctl,
+                       s, false);
+      bytes = (ctx->src32 ? 60.0 : 64.0) * N3;
     } else if (kernel_id == KT_SPREAD) {
-      e = launch_spread(true, n, p, kTile, ctx->ntx, ctx->P.box, ctx->d_start, ctx->d_cls, ctx->d_rb, ctx->d_rq,
+      e = launch_spread(!ctx->src32, n, p, kTile, ctx->ntx, ctx->P.box, ctx->d_start, ctx->d_cls, ctx->d_rb, ctx->d_rq,
                         ctx->d_tmp, s);
-      bytes = 8.0 * N3 + 40.0 * na;
+      bytes = (ctx->src32 ? 4.0 : 8.0) * N3 + 40.0 * na;
     } else if (kernel_id == KT_GATHER) {
       e = launch_gather(ctx->fp64, (int)ctx->n_atoms, n, p, kTile, ctx->ntx, ctx->pl.h, ctx->P.coulomb_k, ctx->d_start,
                         ctx->d_rb, ctx->d_rq, ctx->d_phi[0], ctx->d_phi[1], ctx->d_phi32, nullptr,
@@ -1771,7 +1782,8 @@ p3mz_status p3mz_autotune(p3mz_ctx* ctx, const double* frames_dev, int32_t n_fra
       double* src[3] = {ctx->d_q, ctx->d_tmp, ctx->d_qs};
       double* dst[3] = {ctx->d_tmp, ctx->d_qs, ctx->d_tmp};
       for (int axis = 0; axis < 3; axis++)
-        P3MZ_HIP_TRY(launch_smooth(true, n, axis, t, ctx->ntaps, ctx->half, ctx->d_taps, src[axis], dst[axis], s));
+        P3MZ_HIP_TRY(launch_smooth(!ctx->src32, n, axis, t, ctx->ntaps, ctx->half, ctx->d_taps, src[axis], dst[axis],
+                                   s));
       P3MZ_HIP_TRY(hipEventRecord(e1, s));
       P3MZ_HIP_TRY(hipEventSynchronize(e1));
       float ms = 0.f;

@@ -87,7 +87,8 @@ hipError_t launch_sr(int n_atoms, const double* pos, const double* qa, double bo
 
 // ---- mesh (mesh.hip) -----------------------------------------------------
 // Folded periodic smoothing filter along one axis: out = sum_m c[m] v[i+m-K],
-// launch shape `tile` (see smooth_tile_shape; 0 = default).
+// launch shape `tile` (see smooth_tile_shape; 0 = default); taps, in and
+// out in FP64 or FP32.
 hipError_t launch_smooth(bool fp64, int n, int axis, int tile, int ntaps, int half, const void* taps,
                          const void* in, void* out, hipStream_t s);
 int smooth_tile_count();
@@ -97,7 +98,8 @@ void smooth_tile_shape(int tile, int* lines_per_workgroup, int* outputs_per_thre
 // multiplier predictor into y; a one-workgroup pass then forms the mean of
 // sigma_p, max|q^s| and the threshold and opens the solve.  History buffers
 // are selected on the device from the control block.
-hipError_t launch_sigma(int n, double h, const double* qs, const double* phi0, const double* phi1,
+// qs: the smoothed charges in FP32 (qs32) or FP64.
+hipError_t launch_sigma(int n, double h, bool qs32, const void* qs, const double* phi0, const double* phi1,
                         const double* yb0, const double* yb1, const double* yb2, double* sigma, double* y,
                         double tol, int tol_mode, double* partial, Ctl* ctl, hipStream_t s, bool finalize = true);
 // Outer FP64 residual r = sigma - mean - M y: cycle 0 (first) on the

@@ -62,13 +62,14 @@ struct Smooth {
 // staged extended lines and, for x lines, the output rows.
 struct SmoothLds {
   int kt, L, ld, ldo, taps_off, buf_off, obuf_off, total;
-  __host__ __device__ SmoothLds(int axis, int W, int R, int ntaps, int seg) {
+  // vw: elements per 16 bytes (2 for FP64, 4 for FP32)
+  __host__ __device__ SmoothLds(int axis, int W, int R, int ntaps, int seg, int vw = 2) {
     kt = (ntaps + R - 1) / R * R;
     L = seg + kt + R;
-    ld = axis == 0 ? ((L + 15) & ~15) + 2 : W + 1;   // 16-byte rows, staggered over the banks
+    ld = axis == 0 ? ((L + 15) & ~15) + vw : W + 1;   // 16-byte rows, staggered over the banks
     ldo = seg + 2;
     taps_off = 0;
-    buf_off = (kt + 1) & ~1;
+    buf_off = (kt + vw - 1) / vw * vw;
     obuf_off = buf_off + (axis == 0 ? W * ld : L * ld);
     total = obuf_off + (axis == 0 ? W * ldo : 0);
   }
@@ -80,7 +81,7 @@ __device__ void Smooth<T, AXIS, W, R>::run(const Args& A, Grid G) {
   const int n = A.n, ntaps = A.ntaps, half = A.half, S = A.seg, msk = n - 1;
   const T* __restrict__ in = A.in;
   T* __restrict__ out = A.out;
-  const SmoothLds lay(AXIS, W, R, ntaps, S);
+  const SmoothLds lay(AXIS, W, R, ntaps, S, 16 / (int)sizeof(T));
   extern __shared__ __align__(16) unsigned char smooth_lds[];
   T* const lds = reinterpret_cast<T*>(smooth_lds);
   T* const taps = lds + lay.taps_off;
@@ -119,12 +120,24 @@ __device__ void Smooth<T, AXIS, W, R>::run(const Args& A, Grid G) {
     for (int m0 = 0; m0 < kt; m0 += R) {
       T v[2 * R], tp[R];
       if (AXIS == 0) {
-        const double2* p = reinterpret_cast<const double2*>(buf + c * ld + i0 + m0);
+        if constexpr (sizeof(T) == 8) {
+          const double2* p = reinterpret_cast<const double2*>(buf + c * ld + i0 + m0);
 #pragma unroll
-        for (int q = 0; q < R; q++) {
-          const double2 d = p[q];
-          v[2 * q] = d.x;
-          v[2 * q + 1] = d.y;
+          for (int q = 0; q < R; q++) {
+            const double2 d = p[q];
+            v[2 * q] = d.x;
+            v[2 * q + 1] = d.y;
+          }
+        } else {
+          const float4* p = reinterpret_cast<const float4*>(buf + c * ld + i0 + m0);
+#pragma unroll
+          for (int q = 0; q < R / 2; q++) {
+            const float4 d = p[q];
+            v[4 * q] = d.x;
+            v[4 * q + 1] = d.y;
+            v[4 * q + 2] = d.z;
+            v[4 * q + 3] = d.w;
+          }
         }
       } else {
 #pragma unroll
@@ -216,9 +229,15 @@ struct Sigma {
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G);
 };
+// Four consecutive values of the smoothed charges, widened to FP64.
+__device__ __forceinline__ D4 ld4q(const double* __restrict__ a, int t) { return ld4(a, t); }
+__device__ __forceinline__ D4 ld4q(const float* __restrict__ a, int t) {
+  const float4 v = *reinterpret_cast<const float4*>(a + t);
+  return D4{{(double)v.x, (double)v.y, (double)v.z, (double)v.w}};
+}
+
 template <typename TQ>
 __device__ void Sigma<TQ>::run(const Args& A, Grid G) {
-  static_assert(sizeof(TQ) == sizeof(double), "the charge source is FP64");
   const int n = A.n;
   const double h = A.h;
   const TQ* __restrict__ qs = A.qs;
@@ -244,7 +263,7 @@ __device__ void Sigma<TQ>::run(const Args& A, Grid G) {
   // four consecutive points of one row per thread
   march4(G, n, [&](int t) {
     const int i0 = t & msk, j = (t >> l2) & msk, k = t >> (2 * l2);
-    const D4 q4 = ld4(qs, t);
+    const D4 q4 = ld4q(qs, t);
     double sg[4];
 #pragma unroll
     for (int c = 0; c < 4; c++) sg[c] = q4.v[c];
@@ -2116,24 +2135,43 @@ int smooth_segment(int n, int W, int R, int ntaps, int axis) {
   return 0;
 }
 
-template <int W, int R>
-hipError_t smooth_wr(int n, int axis, int ntaps, int half, const double* tp, const double* ip, double* op,
-                     hipStream_t s) {
+// (The segment is sized for FP64 elements; an FP32 pass uses the same
+// segment in half the LDS.)
+template <typename T, int W, int R>
+hipError_t smooth_wr(int n, int axis, int ntaps, int half, const T* tp, const T* ip, T* op, hipStream_t s) {
   const int S = smooth_segment(n, W, R, ntaps, axis);
   if (S == 0) return hipErrorInvalidValue;
   const int nseg = n / S;
   const int grid = (axis == 0 ? (int)((size_t)n * n / W) : (n / W) * n) * nseg;
-  const size_t lds = (size_t)SmoothLds(axis, W, R, ntaps, S).total * sizeof(double);
-  if (axis == 0) return go<Smooth<double, 0, W, R>>({n, ntaps, half, S, tp, ip, op}, grid, lds, s);
-  if (axis == 1) return go<Smooth<double, 1, W, R>>({n, ntaps, half, S, tp, ip, op}, grid, lds, s);
-  return go<Smooth<double, 2, W, R>>({n, ntaps, half, S, tp, ip, op}, grid, lds, s);
+  const size_t lds = (size_t)SmoothLds(axis, W, R, ntaps, S, 16 / (int)sizeof(T)).total * sizeof(T);
+  if (axis == 0) return go<Smooth<T, 0, W, R>>({n, ntaps, half, S, tp, ip, op}, grid, lds, s);
+  if (axis == 1) return go<Smooth<T, 1, W, R>>({n, ntaps, half, S, tp, ip, op}, grid, lds, s);
+  return go<Smooth<T, 2, W, R>>({n, ntaps, half, S, tp, ip, op}, grid, lds, s);
 }
 
+template <typename T, int W, int R>
+hipError_t smooth_allow_t() {
+  P3MZ_LAUNCH(allow_lds<Smooth<T, 0, W, R>>((int)kSmoothLdsCap));
+  P3MZ_LAUNCH(allow_lds<Smooth<T, 1, W, R>>((int)kSmoothLdsCap));
+  return allow_lds<Smooth<T, 2, W, R>>((int)kSmoothLdsCap);
+}
 template <int W, int R>
 hipError_t smooth_allow() {
-  P3MZ_LAUNCH(allow_lds<Smooth<double, 0, W, R>>((int)kSmoothLdsCap));
-  P3MZ_LAUNCH(allow_lds<Smooth<double, 1, W, R>>((int)kSmoothLdsCap));
-  return allow_lds<Smooth<double, 2, W, R>>((int)kSmoothLdsCap);
+  P3MZ_LAUNCH((smooth_allow_t<double, W, R>()));
+  return smooth_allow_t<float, W, R>();
+}
+
+template <typename T>
+hipError_t smooth_t(int n, int axis, int tile, int ntaps, int half, const T* tp, const T* ip, T* op, hipStream_t s) {
+  switch (tile) {
+    case 0: return smooth_wr<T, 16, 8>(n, axis, ntaps, half, tp, ip, op, s);
+    case 1: return smooth_wr<T, 32, 8>(n, axis, ntaps, half, tp, ip, op, s);
+    case 2: return smooth_wr<T, 8, 8>(n, axis, ntaps, half, tp, ip, op, s);
+    case 3: return smooth_wr<T, 32, 4>(n, axis, ntaps, half, tp, ip, op, s);
+    case 4: return smooth_wr<T, 16, 4>(n, axis, ntaps, half, tp, ip, op, s);
+    case 5: return smooth_wr<T, 8, 4>(n, axis, ntaps, half, tp, ip, op, s);
+    default: return smooth_wr<T, 4, 8>(n, axis, ntaps, half, tp, ip, op, s);
+  }
 }
 }  // namespace
 
@@ -2152,19 +2190,10 @@ void smooth_tile_shape(int tile, int* w, int* r) {
 
 hipError_t launch_smooth(bool fp64, int n, int axis, int tile, int ntaps, int half, const void* taps, const void* in,
                          void* out, hipStream_t s) {
-  if (!fp64) return hipErrorInvalidValue;   // the charge source is FP64 in both modes
   if (!smooth_tile_ok(tile, n, ntaps)) return hipErrorInvalidValue;
-  const double *tp = (const double*)taps, *ip = (const double*)in;
-  double* op = (double*)out;
-  switch (tile) {
-    case 0: return smooth_wr<16, 8>(n, axis, ntaps, half, tp, ip, op, s);
-    case 1: return smooth_wr<32, 8>(n, axis, ntaps, half, tp, ip, op, s);
-    case 2: return smooth_wr<8, 8>(n, axis, ntaps, half, tp, ip, op, s);
-    case 3: return smooth_wr<32, 4>(n, axis, ntaps, half, tp, ip, op, s);
-    case 4: return smooth_wr<16, 4>(n, axis, ntaps, half, tp, ip, op, s);
-    case 5: return smooth_wr<8, 4>(n, axis, ntaps, half, tp, ip, op, s);
-    default: return smooth_wr<4, 8>(n, axis, ntaps, half, tp, ip, op, s);
-  }
+  if (fp64)
+    return smooth_t<double>(n, axis, tile, ntaps, half, (const double*)taps, (const double*)in, (double*)out, s);
+  return smooth_t<float>(n, axis, tile, ntaps, half, (const float*)taps, (const float*)in, (float*)out, s);
 }
 
 // Every smoothing kernel may use up to kSmoothLdsCap of dynamic LDS.
@@ -2182,11 +2211,15 @@ hipError_t smooth_configure() {
   return hipSuccess;
 }
 
-hipError_t launch_sigma(int n, double h, const double* qs, const double* phi0, const double* phi1,
+hipError_t launch_sigma(int n, double h, bool qs32, const void* qs, const double* phi0, const double* phi1,
                         const double* yb0, const double* yb1, const double* yb2, double* sigma, double* y,
                         double tol, int tol_mode, double* partial, Ctl* ctl, hipStream_t s, bool finalize) {
   const int n3 = n * n * n, nb = red_blocks(n3 / 4);   // four points per thread
-  P3MZ_LAUNCH(go<Sigma<double>>({n, h, qs, phi0, phi1, yb0, yb1, yb2, sigma, y, partial, ctl}, nb, 0, s));
+  if (qs32)
+    P3MZ_LAUNCH(go<Sigma<float>>({n, h, (const float*)qs, phi0, phi1, yb0, yb1, yb2, sigma, y, partial, ctl}, nb, 0, s));
+  else
+    P3MZ_LAUNCH(go<Sigma<double>>({n, h, (const double*)qs, phi0, phi1, yb0, yb1, yb2, sigma, y, partial, ctl}, nb, 0,
+                                  s));
   if (!finalize) return hipSuccess;
   return go<FinSigma>({nb, n3, tol_mode, tol, partial, ctl}, 1, 0, s);
 }

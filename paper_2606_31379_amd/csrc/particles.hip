@@ -362,23 +362,25 @@ __device__ void SortBins::run(const Args& A, Grid G) {
 // then adds whole atoms from LDS, one stencil point per lane, into its own
 // LDS copy of the tile (lanes of one atom touch distinct points); the four
 // wave copies are summed in a fixed order.  No global atomics,
-// bitwise-reproducible.
-template <typename T, int TS, int P>
+// bitwise-reproducible.  The sums are formed in FP64; TO is the stored
+// precision of q (FP64, or FP32 for the FP32 charge source).
+template <typename TO, int TS, int P>
 struct Spread {
+  using T = double;
   struct Args {
     int n, ntx;
     double box;
     const int *start, *cls;
     const int2* rb;
     const double4* rq;
-    T* q;
+    TO* q;
   };
   static constexpr int kThreads = kBlock;
   static constexpr int kChunk = 128;   // staged atoms per round
   __device__ static void run(const Args& A, Grid G);
 };
-template <typename T, int TS, int P>
-__device__ void Spread<T, TS, P>::run(const Args& A, Grid G) {
+template <typename TO, int TS, int P>
+__device__ void Spread<TO, TS, P>::run(const Args& A, Grid G) {
   // the assignment order is a template parameter: register arrays sized exactly
   constexpr int V = TS * TS * TS, CH = kChunk, p = P, pw = 3 * P;
   const int n = A.n, ntx = A.ntx;
@@ -386,7 +388,7 @@ __device__ void Spread<T, TS, P>::run(const Args& A, Grid G) {
   const int* __restrict__ cls = A.cls;
   const int2* __restrict__ rb = A.rb;
   const double4* __restrict__ rq = A.rq;
-  T* __restrict__ q = A.q;
+  TO* __restrict__ q = A.q;
   __shared__ T acc[kBlock / 64][V];
   __shared__ T sw[CH * pw];      // [CH][3p] weights x | y | z
   __shared__ T sq[CH];
@@ -529,7 +531,7 @@ __device__ void Spread<T, TS, P>::run(const Args& A, Grid G) {
     T s = acc[0][i];
     for (int k = 1; k < kBlock / 64; k++) s += acc[k][i];
     const int lx = i % TS, ly = (i / TS) % TS, lz = i / (TS * TS);
-    q[nat_idx(n, ox + lx, oy + ly, oz + lz)] = s;
+    q[nat_idx(n, ox + lx, oy + ly, oz + lz)] = (TO)s;
   }
 }
 

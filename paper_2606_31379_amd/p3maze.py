@@ -26,6 +26,7 @@ P3MZ_ERR_STATE = -7
 P3MZ_ERR_DENSITY = -8
 P3MZ_PREC_FP64 = 0
 P3MZ_PREC_MIXED = 1
+P3MZ_PREC_MIXED32 = 2
 MESH_Q, MESH_QS, MESH_SIGMA_P, MESH_Y, MESH_PHI, MESH_PHI_PREV = range(6)
 
 # every symbol include/p3maze.h declares

@@ -32,6 +32,9 @@ def torch():
 
 
 def sampled_parity(torch, w, precisions, steps, sample=512):
+    """V-cycle counts must be equal in every precision; with the FP32 charge
+    source (2) a count may differ only where the oracle's residual lies
+    within 1e-4 (relative) of its threshold."""
     s = w.system(progress=lambda msg: print(f"[inputs] {msg}", flush=True))
     rng = np.random.Generator(np.random.PCG64(w.seed + 17))
     targets = np.sort(rng.choice(s.n, size=sample, replace=False))
@@ -39,11 +42,13 @@ def sampled_parity(torch, w, precisions, steps, sample=512):
     _, op = params_pair(w.box, w.alpha, w.r_cut, w.mesh, w.order, tol=w.tol, k_e=K_E, excl_group=w.excl_group)
     o = O.Oracle(op, s.charges)
     o.set_sr_targets(targets)
-    ref = []
+    ref, ores, othr = [], [], []
     for x in traj:
         f, e, _ = o.compute(x)
         st = o.stats()
         ref.append((f[targets], st.cycles, e[1]))
+        ores.append(list(st.res_hist))
+        othr.append(st.thresh)
         print(f"oracle {w.name}: cycles {st.cycles} solve {st.t_solve:.1f}s", flush=True)
     o.close()
     for precision in precisions:
@@ -60,7 +65,13 @@ def sampled_parity(torch, w, precisions, steps, sample=512):
                 err = rel_rms(fg[targets], fr)
                 print(f"gpu {w.name} precision {precision} step {k}: cycles {st.cycles} err {err:.2e}", flush=True)
                 assert err <= bar, (k, err)
-                assert st.cycles == cyc, (k, st.cycles, cyc)
+                if precision == 2 and st.cycles != cyc:
+                    c = min(st.cycles, cyc)
+                    margin = abs(ores[k][c] - othr[k]) / othr[k]
+                    print(f"  count differs ({st.cycles} vs {cyc}), oracle margin {margin:.2e}", flush=True)
+                    assert margin < 1e-4, (k, st.cycles, cyc, margin)
+                else:
+                    assert st.cycles == cyc, (k, st.cycles, cyc)
                 assert abs(eg[1] - e_lr) <= bar * abs(e_lr), k
         finally:
             g.close()
@@ -68,12 +79,12 @@ def sampled_parity(torch, w, precisions, steps, sample=512):
 
 @pytest.mark.parametrize("i", [0, 1, 2])
 def test_water_sweep_full_size(torch, i):
-    sampled_parity(torch, configs.water_sweep(i), [0, 1] if i < 2 else [1, 0], steps=3)
+    sampled_parity(torch, configs.water_sweep(i), [0, 1, 2] if i < 2 else [1, 2, 0], steps=3)
 
 
 def test_large_water_512_full_size(torch):
     """The large water system (7,999,998 atoms, 512^3, order 5, tolerance
-    1e-6): two mesh steps (cold solve, then a warm step) in both precisions,
+    1e-6): two mesh steps (cold solve, then a warm step) in every precision,
     forces on 1,000 seeded atoms, V-cycle counts and the long-range energy of
     the whole system."""
-    sampled_parity(torch, configs.water_large(), [1, 0], steps=2, sample=1000)
+    sampled_parity(torch, configs.water_large(), [1, 2, 0], steps=2, sample=1000)

@@ -101,9 +101,26 @@ def test_vcycle_schedules(torch, nu):
 # ---------------------------------------------------------------------------
 # whole-step parity on the two small workloads
 # ---------------------------------------------------------------------------
-def check_steps(res, bar):
+def r24_margin(sg, so):
+    """With an FP32 charge source the residual sequence carries a relative
+    perturbation of ~1e-4, so the two runs may stop one cycle apart only
+    when the oracle's residual at the first cycle where their decisions
+    differ lies that close to its threshold: returns that relative margin
+    (0 when the counts are equal)."""
+    if sg.cycles == so.cycles:
+        return 0.0
+    c = min(sg.cycles, so.cycles)
+    return abs(so.res_hist[c] - so.thresh) / so.thresh
+
+
+def check_steps(res, bar, r24=False):
     for k, r in enumerate(res):
         assert r["rcg"] == r["rco"], k
+        if r24 and r["sg"].cycles != r["so"].cycles:
+            m = r24_margin(r["sg"], r["so"])
+            print(f"step {k}: cycles {r['sg'].cycles} vs oracle {r['so'].cycles}, margin {m:.2e}", flush=True)
+            assert m < 1e-4, (k, m)
+            continue
         assert r["sg"].cycles == r["so"].cycles, (k, r["sg"].cycles, r["so"].cycles,
                                                   list(r["sg"].res_hist)[:r["sg"].cycles + 1],
                                                   list(r["so"].res_hist)[:r["so"].cycles + 1])
@@ -115,30 +132,34 @@ def check_steps(res, bar):
         assert dphi <= bar * 10, (k, dphi)
 
 
-@pytest.mark.parametrize("precision,bar", [(0, FP64_BAR), (1, MIXED_BAR)])
+# The FP32 charge source (2) is meant for tolerances of 1e-6 and above: its
+# rounding noise (~1e-7 of max|q^s|, different every step and amplified by
+# the multiplier extrapolation) costs extra V-cycles at 1e-8.  It is checked
+# here at 1e-6 on the same systems.
+@pytest.mark.parametrize("precision,bar", [(0, FP64_BAR), (1, MIXED_BAR), (2, MIXED_BAR)])
 def test_nacl_512_steps(torch, precision, bar):
     w = configs.nacl_512()
     s = w.system()
-    gp, op = params_pair(w.box, w.alpha, w.r_cut, w.mesh, w.order, tol=w.tol, precision=precision,
-                         k_e=K_E, predictor=3)
+    gp, op = params_pair(w.box, w.alpha, w.r_cut, w.mesh, w.order, tol=w.tol if precision < 2 else 1e-6,
+                         precision=precision, k_e=K_E, predictor=3)
     res = run_pair(torch, s, gp, op, steps=6)
-    check_steps(res, bar)
+    check_steps(res, bar, r24=precision == 2)
     assert res[0]["sg"].cold == 1 and res[1]["sg"].cold == 0
 
 
-@pytest.mark.parametrize("precision,bar", [(0, FP64_BAR), (1, MIXED_BAR)])
+@pytest.mark.parametrize("precision,bar", [(0, FP64_BAR), (1, MIXED_BAR), (2, MIXED_BAR)])
 def test_water_3000_steps(torch, precision, bar):
     w = configs.water_3000()
     s = w.system()
-    gp, op = params_pair(w.box, w.alpha, w.r_cut, w.mesh, w.order, tol=w.tol, precision=precision,
-                         k_e=K_E, predictor=3, excl_group=3)
+    gp, op = params_pair(w.box, w.alpha, w.r_cut, w.mesh, w.order, tol=w.tol if precision < 2 else 1e-6,
+                         precision=precision, k_e=K_E, predictor=3, excl_group=3)
     res = run_pair(torch, s, gp, op, steps=4)
-    check_steps(res, bar)
+    check_steps(res, bar, r24=precision == 2)
 
 
 @pytest.mark.parametrize("order", [2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("mesh", [8, 32])
-@pytest.mark.parametrize("precision,bar", [(0, FP64_BAR), (1, MIXED_BAR)])
+@pytest.mark.parametrize("precision,bar", [(0, FP64_BAR), (1, MIXED_BAR), (2, MIXED_BAR)])
 def test_forces_every_order(torch, order, mesh, precision, bar):
     # every assignment order of the spread and gather kernels, on a one-tile
     # mesh (stencils wrap onto the same tile) and on a 4^3-tile mesh; 300
@@ -146,9 +167,30 @@ def test_forces_every_order(torch, order, mesh, precision, bar):
     # holds at the high orders
     s = inputs.random_neutral(300, 12.0, seed=100 + 10 * order + mesh, dmin=0.7)
     alpha = 0.25 if mesh == 8 else 0.45
-    gp, op = params_pair(12.0, alpha, 5.0, mesh, order, tol=1e-9, precision=precision)
+    gp, op = params_pair(12.0, alpha, 5.0, mesh, order, tol=1e-9 if precision < 2 else 1e-6, precision=precision)
     res = run_pair(torch, s, gp, op, steps=2)
-    check_steps(res, bar)
+    check_steps(res, bar, r24=precision == 2)
+
+
+@pytest.mark.parametrize("order", [2, 5, 7])
+@pytest.mark.parametrize("mesh", [8, 32])
+def test_spread_and_smoothing_fp32_source(torch, order, mesh):
+    """MIXED32: assigned and smoothed charges in FP32 against the FP64
+    oracle at FP32 rounding; sigma_p (formed in FP64 from them) likewise."""
+    s = inputs.random_neutral(37, 10.0, seed=order * 10 + mesh, dmin=0.8)
+    alpha = 0.45 if mesh >= 16 else 0.25
+    gp, op = params_pair(10.0, alpha, 4.0, mesh, order, precision=2)
+    g = GpuCtx(gp, s.charges, torch)
+    o = O.Oracle(op, s.charges)
+    try:
+        g.compute(s.pos)
+        o.compute(s.pos)
+        for which, ow in [(0, O.MESH_Q), (1, O.MESH_QS), (2, O.MESH_SIGMA_P)]:
+            a, b = g.get_mesh(which), o.get_mesh(ow)
+            assert np.max(np.abs(a - b)) <= 2e-6 * np.max(np.abs(b)), (which, np.max(np.abs(a - b)))
+            assert a.dtype == np.float64
+    finally:
+        g.close()
 
 
 @pytest.mark.parametrize("pred", [0, 1, 2])
