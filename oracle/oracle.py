@@ -31,7 +31,7 @@ class Params(C.Structure):
                 ("mesh", C.c_int32), ("order", C.c_int32), ("tol", C.c_double),
                 ("tol_mode", C.c_int32), ("max_cycles", C.c_int32), ("predictor", C.c_int32),
                 ("coulomb_k", C.c_double), ("nu_pre", C.c_int32), ("nu_post", C.c_int32),
-                ("excl_group", C.c_int32)]
+                ("excl_group", C.c_int32), ("stencil", C.c_int32)]
 
 
 class Plan(C.Structure):
@@ -115,6 +115,10 @@ def lib() -> C.CDLL:
         L.orc_assign.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int64, dp, dp, dp]
         L.orc_smooth.argtypes = [C.c_int, C.c_int, C.c_double, dp]
         L.orc_apply_m.argtypes = [C.c_int, dp, dp]
+        L.orc_apply_a19.argtypes = [C.c_int, dp, dp]
+        L.orc_apply_a19.restype = None
+        L.orc_apply_b.argtypes = [C.c_int, dp, dp]
+        L.orc_apply_b.restype = None
         L.orc_rbgs.argtypes = [C.c_int, dp, dp, C.c_int]
         L.orc_restrict.argtypes = [C.c_int, dp, dp]
         L.orc_prolong_add.argtypes = [C.c_int, dp, dp]
@@ -155,9 +159,9 @@ def _dp(a: np.ndarray):
 
 
 def make_params(box, alpha, r_cut, mesh, order, tol=1e-8, tol_mode=0, max_cycles=50,
-                predictor=3, coulomb_k=1.0, nu_pre=2, nu_post=2, excl_group=0) -> Params:
+                predictor=3, coulomb_k=1.0, nu_pre=2, nu_post=2, excl_group=0, stencil=0) -> Params:
     return Params(box, alpha, r_cut, mesh, order, tol, tol_mode, max_cycles, predictor,
-                  coulomb_k, nu_pre, nu_post, excl_group)
+                  coulomb_k, nu_pre, nu_post, excl_group, stencil)
 
 
 def plan(p: Params) -> Plan:
@@ -204,6 +208,20 @@ def apply_m(v):
     v = np.ascontiguousarray(v, dtype=np.float64)
     out = np.empty_like(v)
     lib().orc_apply_m(v.shape[0], _dp(v), _dp(out))
+    return out
+
+
+def apply_a19(v):
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    out = np.empty_like(v)
+    lib().orc_apply_a19(v.shape[0], _dp(v), _dp(out))
+    return out
+
+
+def apply_b(v):
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    out = np.empty_like(v)
+    lib().orc_apply_b(v.shape[0], _dp(v), _dp(out))
     return out
 
 

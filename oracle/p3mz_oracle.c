@@ -92,7 +92,7 @@ int orc_plan_make(const orc_params* p, orc_plan* pl) {
   if (p->order < 2 || p->order > 7 || !(p->tol > 0) || p->max_cycles < 0 ||
       p->max_cycles > ORC_MAX_CYCLES || p->predictor < 0 || p->predictor > 3 ||
       p->nu_pre < 0 || p->nu_post < 0 || p->nu_pre + p->nu_post < 1 ||
-      p->tol_mode < 0 || p->tol_mode > 1 || p->excl_group < 0)
+      p->tol_mode < 0 || p->tol_mode > 1 || p->excl_group < 0 || p->stencil < 0 || p->stencil > 1)
     return ORC_ERR_INVALID_ARG;
   int n = p->mesh;
   if (n < 8) return ORC_ERR_MESH_SHAPE;
@@ -104,7 +104,11 @@ int orc_plan_make(const orc_params* p, orc_plan* pl) {
   pl->sigma = 1.0 / (sqrt(2.0) * p->alpha);
   pl->sigma_s2 = pl->sigma * pl->sigma - p->order * pl->h * pl->h / 6.0;
   if (!(pl->sigma_s2 > 0)) return ORC_ERR_MESH_SHAPE; /* mesh too coarse for sigma */
-  pl->K = (int)ceil(2.0 * pl->sigma_s2 / (pl->h * pl->h));
+  /* K steps of weight nu = sigma_s^2 / (2 K h^2): nu <= 1/4 in general; for
+   * the fourth-order discretisation nu <= 1/6, where the K-step diffusion
+   * also matches the Gaussian's fourth cumulant up to O(h^4) (the quartic
+   * term K nu (1/12 - nu/2) (k h)^4 of its symbol vanishes at nu = 1/6) */
+  pl->K = (int)ceil((p->stencil == 1 ? 3.0 : 2.0) * pl->sigma_s2 / (pl->h * pl->h));
   if (pl->K < 1) pl->K = 1;
   pl->nu_smooth = pl->sigma_s2 / (2.0 * pl->K * pl->h * pl->h);
   int l = 0;
@@ -214,6 +218,37 @@ void orc_apply_m(int n, const double* v, double* out) {
     for (int j = 0; j < n; j++)
       for (int i = 0; i < n; i++)
         out[IDX(n, i, j, k)] = nbr_sum(n, v, i, j, k) - 6.0 * v[IDX(n, i, j, k)];
+}
+
+/* Higher-order discretisation (the paper's remark after Eq. 21 that
+ * Hermitian discretisations could replace the seven-point stencil): the
+ * Mehrstellen scheme for the Laplacian, A phi = B f with
+ *   A = (1/6) [2 (sum of the 6 face neighbours) + (sum of the 12 edge
+ *       neighbours) - 24 (centre)]            (19-point Laplacian times h^2)
+ *   B = (1/12) [(sum of the 6 face neighbours) + 6 (centre)]
+ * which is fourth-order accurate: the symbol ratio B(k)/A(k) equals
+ * -1/(k h)^2 up to O((k h)^4). */
+void orc_apply_a19(int n, const double* v, double* out) {
+#pragma omp parallel for
+  for (int k = 0; k < n; k++)
+    for (int j = 0; j < n; j++)
+      for (int i = 0; i < n; i++) {
+        int im = wrapi(i - 1, n), ip = wrapi(i + 1, n);
+        int jm = wrapi(j - 1, n), jp = wrapi(j + 1, n);
+        int km = wrapi(k - 1, n), kp = wrapi(k + 1, n);
+        double faces = nbr_sum(n, v, i, j, k);
+        double edges = (v[IDX(n, im, jm, k)] + v[IDX(n, ip, jm, k)] + v[IDX(n, im, jp, k)] + v[IDX(n, ip, jp, k)]) +
+                       (v[IDX(n, im, j, km)] + v[IDX(n, ip, j, km)] + v[IDX(n, im, j, kp)] + v[IDX(n, ip, j, kp)]) +
+                       (v[IDX(n, i, jm, km)] + v[IDX(n, i, jp, km)] + v[IDX(n, i, jm, kp)] + v[IDX(n, i, jp, kp)]);
+        out[IDX(n, i, j, k)] = (2.0 * faces + edges - 24.0 * v[IDX(n, i, j, k)]) / 6.0;
+      }
+}
+
+void orc_apply_b(int n, const double* v, double* out) {
+#pragma omp parallel for
+  for (int k = 0; k < n; k++)
+    for (int j = 0; j < n; j++)
+      for (int i = 0; i < n; i++) out[IDX(n, i, j, k)] = (nbr_sum(n, v, i, j, k) + 6.0 * v[IDX(n, i, j, k)]) / 12.0;
 }
 
 /* One Gauss-Seidel half-sweep for M e = r over the points of one colour
@@ -576,7 +611,10 @@ int orc_compute(orc_state* s, const double* pos, double* force, double* energy4)
 
   /* Verlet prediction phi_p = 2 phi^k - phi^{k-1} (zero on a cold solve) and
    * the constraint at the prediction, sigma_p = (h/4pi) M phi_p + q^s (Eq. 17),
-   * projected to zero mean. */
+   * projected to zero mean.  With the fourth-order discretisation the
+   * constraint is A phi = -(4 pi / h) B q^s, so sigma_p = (h/4pi) A phi_p +
+   * B q^s and the correction problem below is A y = sigma_p. */
+  const int ho = P->stencil == 1;
   const int cold = !s->have_hist;
   double* phi_p = s->phi_p;
   if (cold) {
@@ -584,8 +622,14 @@ int orc_compute(orc_state* s, const double* pos, double* force, double* energy4)
   } else {
     for (size_t t = 0; t < n3; t++) phi_p[t] = 2.0 * s->phi_k[t] - s->phi_km1[t];
   }
-  orc_apply_m(n, phi_p, s->sigma_p);
-  for (size_t t = 0; t < n3; t++) s->sigma_p[t] = h / (4.0 * M_PI) * s->sigma_p[t] + s->qs[t];
+  if (ho) {
+    orc_apply_a19(n, phi_p, s->sigma_p);
+    orc_apply_b(n, s->qs, s->r);   /* B q^s, r is free here */
+    for (size_t t = 0; t < n3; t++) s->sigma_p[t] = h / (4.0 * M_PI) * s->sigma_p[t] + s->r[t];
+  } else {
+    orc_apply_m(n, phi_p, s->sigma_p);
+    for (size_t t = 0; t < n3; t++) s->sigma_p[t] = h / (4.0 * M_PI) * s->sigma_p[t] + s->qs[t];
+  }
   double ms = mean_of(s->sigma_p, n3);
   for (size_t t = 0; t < n3; t++) s->sigma_p[t] -= ms;
 
@@ -602,12 +646,19 @@ int orc_compute(orc_state* s, const double* pos, double* force, double* energy4)
   memcpy(s->y_start, s->y, sizeof(double) * n3);
 
   /* correction problem M y = sigma_p (Eq. 16) by V-cycles; the residual
-   * max|M y - sigma_p| (Eq. 26) is tested before every cycle */
+   * max|M y - sigma_p| (Eq. 26) is tested before every cycle.  For the
+   * fourth-order operator A the residual uses A and each V-cycle (on the
+   * seven-point M) gives the correction: defect correction, which
+   * converges because A and M agree on the smooth modes that carry the
+   * Gaussian-smoothed charge. */
   double norm = maxabs_of(s->qs, n3);
   double thresh = P->tol_mode == 0 ? P->tol * norm : P->tol;
   int cycles = 0, status = ORC_OK;
   for (;;) {
-    orc_apply_m(n, s->y, s->r);
+    if (ho)
+      orc_apply_a19(n, s->y, s->r);
+    else
+      orc_apply_m(n, s->y, s->r);
     for (size_t t = 0; t < n3; t++) s->r[t] = s->sigma_p[t] - s->r[t];
     double res = maxabs_of(s->r, n3);
     s->st.res_hist[cycles] = res;
@@ -638,7 +689,8 @@ int orc_compute(orc_state* s, const double* pos, double* force, double* energy4)
   double t2 = now_s();
 
   /* long-range force (Eq. 21): -Q sum_n W(r - r_n) (D phi)_n with the
-   * central difference D, and the long-range energy 1/2 Q (W * phi)(r) */
+   * central difference D (two-point; four-point, fourth order, with the
+   * Mehrstellen Laplacian), and the long-range energy 1/2 Q (W * phi)(r) */
   const double* phi = s->phi_k;
   double* e_at = (double*)malloc(sizeof(double) * (size_t)s->n);
   if (!e_at) return ORC_ERR_OUT_OF_MEMORY;
@@ -655,9 +707,20 @@ int orc_compute(orc_state* s, const double* pos, double* force, double* energy4)
         for (int d = 0; d < p; d++) {
           int i = ix[d], j = iy[b], k = iz[c];
           double W = wx[d] * wy[b] * wz[c];
-          double dx = (phi[IDX(n, wrapi(i + 1, n), j, k)] - phi[IDX(n, wrapi(i - 1, n), j, k)]) / (2.0 * h);
-          double dy = (phi[IDX(n, i, wrapi(j + 1, n), k)] - phi[IDX(n, i, wrapi(j - 1, n), k)]) / (2.0 * h);
-          double dz = (phi[IDX(n, i, j, wrapi(k + 1, n))] - phi[IDX(n, i, j, wrapi(k - 1, n))]) / (2.0 * h);
+          double dx, dy, dz;
+          if (ho) {
+            /* (8 (f_{+1} - f_{-1}) - (f_{+2} - f_{-2})) / (12 h) */
+            dx = (8.0 * (phi[IDX(n, wrapi(i + 1, n), j, k)] - phi[IDX(n, wrapi(i - 1, n), j, k)]) -
+                  (phi[IDX(n, wrapi(i + 2, n), j, k)] - phi[IDX(n, wrapi(i - 2, n), j, k)])) / (12.0 * h);
+            dy = (8.0 * (phi[IDX(n, i, wrapi(j + 1, n), k)] - phi[IDX(n, i, wrapi(j - 1, n), k)]) -
+                  (phi[IDX(n, i, wrapi(j + 2, n), k)] - phi[IDX(n, i, wrapi(j - 2, n), k)])) / (12.0 * h);
+            dz = (8.0 * (phi[IDX(n, i, j, wrapi(k + 1, n))] - phi[IDX(n, i, j, wrapi(k - 1, n))]) -
+                  (phi[IDX(n, i, j, wrapi(k + 2, n))] - phi[IDX(n, i, j, wrapi(k - 2, n))])) / (12.0 * h);
+          } else {
+            dx = (phi[IDX(n, wrapi(i + 1, n), j, k)] - phi[IDX(n, wrapi(i - 1, n), j, k)]) / (2.0 * h);
+            dy = (phi[IDX(n, i, wrapi(j + 1, n), k)] - phi[IDX(n, i, wrapi(j - 1, n), k)]) / (2.0 * h);
+            dz = (phi[IDX(n, i, j, wrapi(k + 1, n))] - phi[IDX(n, i, j, wrapi(k - 1, n))]) / (2.0 * h);
+          }
           gx += W * dx; gy += W * dy; gz += W * dz;
           pot += W * phi[IDX(n, i, j, k)];
         }

@@ -59,6 +59,9 @@ typedef struct {
   int32_t nu_pre;      /* red-black Gauss-Seidel sweeps before restriction   */
   int32_t nu_post;     /* ... after prolongation                             */
   int32_t excl_group;  /* 0: none; g > 0: atoms i, j with i/g == j/g excluded */
+  int32_t stencil;     /* 0: 7-point Laplacian, 2-point central gradient;
+                          1: 19-point Mehrstellen (Hermitian) Laplacian with
+                          its right-hand-side operator, 4-point gradient     */
 } orc_params;
 
 typedef struct {
@@ -137,6 +140,14 @@ void orc_philox4x32_10(const uint32_t counter[4], const uint32_t key[2], uint32_
 void orc_thermo_normals(uint64_t seed, int64_t a, int64_t step, int half, double z[3]);
 int  orc_nonelectrostatic(const orc_mdterms* t, int64_t n_atoms, const double* pos,
                           double box, double r_cut, double* force, double* energy);
+
+/* Fourth-order (Hermitian, Mehrstellen) mesh operators of the stencil-1
+ * discretisation: out = A v with A = (1/6)(2 sum_faces + sum_edges - 24),
+ * the 19-point Laplacian times h^2, and out = B v with
+ * B = 1/2 + (1/12) sum_faces, its right-hand-side operator; the discrete
+ * Poisson equation is then A phi = -(4 pi / h) B q. */
+void orc_apply_a19(int n, const double* v, double* out);
+void orc_apply_b(int n, const double* v, double* out);
 
 #ifdef __cplusplus
 }
