@@ -96,6 +96,16 @@ typedef struct {
   int32_t excl_group;  /* 0: no exclusions; g > 0: atoms i, j with i/g == j/g interact
                           only through the mesh minus its erf part (rigid-molecule
                           exclusion, e.g. g = 3 for O,H,H water)                      */
+  int32_t stencil;     /* mesh discretisation.  0: the seven-point Laplacian M and the
+                          two-point central gradient (second order; Eq. 10, Eq. 21).
+                          1: fourth order, the Hermitian (Mehrstellen) form the paper
+                          names after Eq. 21 as the higher-order option: the
+                          constraint A phi = -(4 pi / h) B q^s with the 19-point
+                          A = (1/6)(2 sum_faces + sum_edges - 24) and
+                          B = (1/12)(sum_faces + 6), the four-point gradient
+                          (8 (f+1 - f-1) - (f+2 - f-2)) / 12h, smoothing weight
+                          nu <= 1/6; the V-cycles keep M (defect correction, more
+                          cycles per step).  Needs order <= 5                         */
 } p3mz_params;
 
 typedef struct {

@@ -57,6 +57,8 @@ p3mz_status make_plan(const p3mz_params& P, Plan* pl) {
     return fail(P3MZ_ERR_INVALID_ARG, "bad precision");
   if (P.nu_pre < -1 || P.nu_post < -1 || P.nu_pre > 16 || P.nu_post > 16) return fail(P3MZ_ERR_INVALID_ARG, "bad sweep counts");
   if (P.excl_group < 0) return fail(P3MZ_ERR_INVALID_ARG, "excl_group must be >= 0");
+  if (P.stencil < 0 || P.stencil > 1) return fail(P3MZ_ERR_INVALID_ARG, "stencil must be 0 or 1");
+  if (P.stencil == 1 && P.order > 5) return fail(P3MZ_ERR_INVALID_ARG, "the fourth-order stencil needs order <= 5");
   const int n = P.mesh;
   int m = n;
   while (m > 4 && (m & 1) == 0) m >>= 1;
@@ -67,7 +69,9 @@ p3mz_status make_plan(const p3mz_params& P, Plan* pl) {
   pl->sigma = 1.0 / (sqrt(2.0) * P.alpha);
   pl->sigma_s2 = pl->sigma * pl->sigma - P.order * pl->h * pl->h / 6.0;
   if (!(pl->sigma_s2 > 0)) return fail(P3MZ_ERR_MESH_SHAPE, "mesh spacing too coarse for the Gaussian width");
-  pl->K = std::max(1, (int)ceil(2.0 * pl->sigma_s2 / (pl->h * pl->h)));
+  // step weight nu <= 1/4; <= 1/6 for the fourth-order stencil, where the
+  // K-step diffusion matches the Gaussian's fourth cumulant to O(h^4)
+  pl->K = std::max(1, (int)ceil((P.stencil == 1 ? 3.0 : 2.0) * pl->sigma_s2 / (pl->h * pl->h)));
   pl->nu_s = pl->sigma_s2 / (2.0 * pl->K * pl->h * pl->h);
   pl->levels = 0;
   for (int q = n; q >= 4; q >>= 1) pl->levels++;
@@ -663,14 +667,14 @@ p3mz_status enq_pre(p3mz_ctx* c, const double* pos, hipStream_t s) {
   const bool fold = !g_recorder;
   P3MZ_HIP_TRY(launch_sigma(n, pl.h, c->src32, c->d_qs, c->d_phi[0], c->d_phi[1], c->d_yh[0], c->d_yh[1], c->d_yh[2],
                             c->d_sigma, c->d_y[0], c->P.tol, c->P.tol_mode, fold ? c->d_spart : c->d_partial,
-                            c->d_ctl, s, !fold));
+                            c->d_ctl, s, !fold, c->P.stencil));
   kt_end(KT_SIGMA, 0, (56.0 + qsz) * N3, s);
   const LevelBufs& f = c->lv[0];
   rec_key(111);
   kt_begin(KT_OUTER, 0, s);
   P3MZ_HIP_TRY(launch_outer(c->fp64, n, 1, c->P.max_cycles, c->d_sigma, c->d_y[0], c->d_y[1], f.e0, f.e1, f.r0, f.r1,
                             c->d_partial, c->d_ctl, s, !fold, fold ? c->d_spart : nullptr, c->P.tol,
-                            c->P.tol_mode));
+                            c->P.tol_mode, c->P.stencil));
   kt_end(KT_OUTER, 0, (16.0 + ts) * N3, s);
   return P3MZ_OK;
 }
@@ -693,7 +697,7 @@ p3mz_status enq_cycle(p3mz_ctx* c, hipStream_t s) {
   rec_key(4100);
   kt_begin(KT_OUTER, 0, s);
   P3MZ_HIP_TRY(launch_outer(c->fp64, pl.n, 0, c->P.max_cycles, c->d_sigma, c->d_y[0], c->d_y[1], f.e0, f.e1, f.r0,
-                            f.r1, c->d_partial, c->d_ctl, s, !defer));
+                            f.r1, c->d_partial, c->d_ctl, s, !defer, nullptr, 0.0, 0, c->P.stencil));
   kt_end(KT_OUTER, 0, (24.0 + 2.0 * ts) * N3, s);
   return P3MZ_OK;
 }
@@ -715,7 +719,8 @@ p3mz_status enq_post1(p3mz_ctx* c, double* force, hipStream_t s) {
   rec_key(5001);
   kt_begin(KT_GATHER, 0, s);
   P3MZ_HIP_TRY(launch_gather(c->fp64, na, n, pl.p, kTile, c->ntx, pl.h, c->P.coulomb_k, c->d_start, c->d_rb, c->d_rq,
-                             c->d_phi[0], c->d_phi[1], c->d_phi32, force, c->d_partial, c->d_ctl, s));
+                             c->d_phi[0], c->d_phi[1], c->d_phi32, force, c->d_partial, c->d_ctl, s, true,
+                             c->P.stencil));
   // algorithmic bytes: the potential once, plus each atom's 40-byte record
   // and its force (the (p+2)^3 neighbourhood reads are shared by atoms)
   kt_end(KT_GATHER, 0, N3 * (c->fp64 ? 8.0 : 4.0) + (double)na * 64.0, s);
@@ -1672,12 +1677,12 @@ p3mz_status p3mz_kernel_bench(p3mz_ctx* ctx, int32_t kernel_id, int32_t reps, vo
       // the cycle form without its finalize pass; both multiplier buffers
       // are scratch between steps (the multiplier is kept in the history slots)
       e = launch_outer(ctx->fp64, n, 0, ctx->P.max_cycles, ctx->d_sigma, ctx->d_y[0], ctx->d_y[1], f.e0, f.e1, f.r0,
-                       f.r1, ctx->d_partial, ctx->d_ctl, s, false);
+                       f.r1, ctx->d_partial, ctx->d_ctl, s, false, nullptr, 0.0, 0, ctx->P.stencil);
       bytes = (24.0 + 2.0 * ts) * N3;
     } else if (kernel_id == KT_SIGMA) {
       e = launch_sigma(n, ctx->pl.h, ctx->src32, ctx->d_qs, ctx->d_phi[0], ctx->d_phi[1], ctx->d_yh[0], ctx->d_yh[1],
                        ctx->d_yh[2], ctx->d_sigma, ctx->d_y[0], ctx->P.tol, ctx->P.tol_mode, ctx->d_partial, ctx->d_ctl,
-                       s, false);
+                       s, false, ctx->P.stencil);
       bytes = (ctx->src32 ? 60.0 : 64.0) * N3;
     } else if (kernel_id == KT_SPREAD) {
       e = launch_spread(!ctx->src32, n, p, kTile, ctx->ntx, ctx->P.box, ctx->d_start, ctx->d_cls, ctx->d_rb, ctx->d_rq,
@@ -1686,7 +1691,7 @@ p3mz_status p3mz_kernel_bench(p3mz_ctx* ctx, int32_t kernel_id, int32_t reps, vo
     } else if (kernel_id == KT_GATHER) {
       e = launch_gather(ctx->fp64, (int)ctx->n_atoms, n, p, kTile, ctx->ntx, ctx->pl.h, ctx->P.coulomb_k, ctx->d_start,
                         ctx->d_rb, ctx->d_rq, ctx->d_phi[0], ctx->d_phi[1], ctx->d_phi32, nullptr,
-                        ctx->d_partial, ctx->d_ctl, s, false);
+                        ctx->d_partial, ctx->d_ctl, s, false, ctx->P.stencil);
       bytes = N3 * (ctx->fp64 ? 8.0 : 4.0) + 64.0 * na;
     } else {
       e = launch_vcycle_kernel(ctx->fp64, kernel_id, ctx->lv, ctx->pl.levels, ctx->pl.tail, ctx->nu1, ctx->nu2,

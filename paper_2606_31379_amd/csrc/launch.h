@@ -48,7 +48,8 @@ hipError_t launch_sort_pack(int nbins, const int* start, const int* perm_raw, in
 hipError_t launch_spread(bool fp64, int n, int p, int tile, int ntx, double box, const int* start, const int* cls,
                          const void* rb, const void* rq, void* q, hipStream_t s);
 // Long-range force and energy by interpolating the central-difference
-// gradient of phi (precision of phi: fp64 or float).
+// gradient of phi (precision of phi: fp64 or float): two-point, or
+// four-point with stencil 1 (orders p <= 5).
 // phi: FP64 mode reads the new potential from phi0/phi1 (selected on the
 // device), mixed mode reads the FP32 copy phi32.
 // finalize = false launches the per-atom kernel only (back-to-back timing);
@@ -57,7 +58,7 @@ hipError_t launch_spread(bool fp64, int n, int p, int tile, int ntx, double box,
 hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, int tile, int ntx, double h, double k_e,
                          const int* start, const void* rb, const void* rq, const double* phi0, const double* phi1,
                          const float* phi32, double* force, double* partial, Ctl* ctl, hipStream_t s,
-                         bool finalize = true);
+                         bool finalize = true, int stencil = 0);
 // Short-range erfc pairs (neighbour lists or the cell list), exclusion correction, energy
 // assembly into energy_out[4] (may be NULL).  force += F_sr; the sum of the
 // final forces goes to ctl->net_force (nfpart: 3 * kPartialSlots doubles).
@@ -94,6 +95,8 @@ hipError_t launch_smooth(bool fp64, int n, int axis, int tile, int ntaps, int ha
 int smooth_tile_count();
 bool smooth_tile_ok(int tile, int n, int ntaps);
 void smooth_tile_shape(int tile, int* lines_per_workgroup, int* outputs_per_thread);
+// stencil 1 (fourth order): sigma_p = (h/4pi) A phi_p + B q^s and the outer
+// residual with the 19-point A (see the kernels).
 // sigma_p = (h/4pi) M (2 phi^k - phi^{k-1}) + q^s (cold: q^s) and the
 // multiplier predictor into y; a one-workgroup pass then forms the mean of
 // sigma_p, max|q^s| and the threshold and opens the solve.  History buffers
@@ -101,7 +104,8 @@ void smooth_tile_shape(int tile, int* lines_per_workgroup, int* outputs_per_thre
 // qs: the smoothed charges in FP32 (qs32) or FP64.
 hipError_t launch_sigma(int n, double h, bool qs32, const void* qs, const double* phi0, const double* phi1,
                         const double* yb0, const double* yb1, const double* yb2, double* sigma, double* y,
-                        double tol, int tol_mode, double* partial, Ctl* ctl, hipStream_t s, bool finalize = true);
+                        double tol, int tol_mode, double* partial, Ctl* ctl, hipStream_t s, bool finalize = true,
+                        int stencil = 0);
 // Outer FP64 residual r = sigma - mean - M y: cycle 0 (first) on the
 // predicted y in y0; cycle c > 0 on y + e, the previous cycle's y (y0 or y1
 // by parity) plus this cycle's correction, written to the other buffer; r
@@ -113,7 +117,7 @@ hipError_t launch_sigma(int n, double h, bool qs32, const void* qs, const double
 hipError_t launch_outer(bool fp64, int n, int first, int max_cycles, const double* sigma, double* y0, double* y1,
                         const void* e0, const void* e1, void* r0, void* r1, double* partial, Ctl* ctl,
                         hipStream_t s, bool finalize = true, const double* spart = nullptr, double tol = 0.0,
-                        int tol_mode = 0);
+                        int tol_mode = 0, int stencil = 0);
 // The stop decision of an outer residual: its partials (nb workgroups,
 // max then sum) on a fine mesh of n3 points, with the cycle cap.
 struct Decide {

@@ -508,6 +508,158 @@ __device__ void Outer<T>::run(const Args& A, Grid G) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fourth-order (Hermitian, Mehrstellen) discretisation, the higher-order
+// option the paper mentions after Eq. 21: the constraint becomes
+// A phi = -(4 pi / h) B q^s with the 19-point operator
+// A = (1/6)(2 sum_faces + sum_edges - 24) and B = (1/12)(sum_faces + 6), so
+// sigma_p = (h/4pi) A phi_p + B q^s and the outer residual is
+// r = sigma_p - mean - A y.  The V-cycle keeps the seven-point operator:
+// each cycle is a defect-correction step, which converges because A and M
+// agree on the smooth modes the Gaussian-smoothed charge carries.  These
+// kernels handle one point at a time with direct neighbour loads (the
+// seven-point kernels are the tuned path); their grids and partials match
+// Sigma / Outer, so the stop decisions are made the same way.
+// ---------------------------------------------------------------------------
+// v at (i, j, k) + the sums of its 6 face and 12 edge neighbours.
+template <typename F>
+__device__ __forceinline__ void stencil19(int n, int i, int j, int k, F v, double* c, double* faces, double* edges) {
+  const int msk = n - 1;
+  const int im = (i - 1) & msk, ip = (i + 1) & msk, jm = (j - 1) & msk, jp = (j + 1) & msk;
+  const int km = (k - 1) & msk, kp = (k + 1) & msk;
+  *c = v(i, j, k);
+  *faces = ((v(im, j, k) + v(ip, j, k)) + (v(i, jm, k) + v(i, jp, k))) + (v(i, j, km) + v(i, j, kp));
+  *edges = (v(im, jm, k) + v(ip, jm, k) + v(im, jp, k) + v(ip, jp, k)) +
+           (v(im, j, km) + v(ip, j, km) + v(im, j, kp) + v(ip, j, kp)) +
+           (v(i, jm, km) + v(i, jp, km) + v(i, jm, kp) + v(i, jp, kp));
+}
+
+template <typename TQ>
+struct SigmaHO {
+  using Args = typename Sigma<TQ>::Args;
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G) {
+    const int n = A.n, msk = n - 1, l2 = __builtin_ctz(n);
+    const double h = A.h;
+    const Ctl* ctl = A.ctl;
+    __shared__ double sh[kBlock / 64];
+    const int cold = ctl->cold, m_eff = ctl->m_eff;
+    const double* pk = ctl->k_idx ? A.phi1 : A.phi0;
+    const double* pkm1 = ctl->k_idx ? A.phi0 : A.phi1;
+    const double* const yb[3] = {A.yb0, A.yb1, A.yb2};
+    const double* y0 = yb[ctl->yh0];
+    const double* y1 = yb[ctl->yh1];
+    const double* y2 = yb[ctl->yh2];
+    double sv = 0.0, qmax = 0.0;
+    auto Q = [&](int x, int y, int z) { return (double)A.qs[nat_idx(n, x, y, z)]; };
+    auto P = [&](int x, int y, int z) {
+      const int a = nat_idx(n, x, y, z);
+      return 2.0 * pk[a] - pkm1[a];
+    };
+    march4(G, n, [&](int t) {
+      const int i0 = t & msk, j = (t >> l2) & msk, k = t >> (2 * l2);
+      double sg[4], yv[4];
+      for (int q = 0; q < 4; q++) {
+        const int i = i0 + q, a = t + q;
+        double qc, qf, qe;
+        stencil19(n, i, j, k, Q, &qc, &qf, &qe);
+        const double bq = (qf + 6.0 * qc) / 12.0;
+        double v = bq;
+        if (!cold) {
+          double pc, pf, pe;
+          stencil19(n, i, j, k, P, &pc, &pf, &pe);
+          v = h / (4.0 * kPi) * ((2.0 * pf + pe - 24.0 * pc) / 6.0) + bq;
+        }
+        sg[q] = v;
+        double yy = 0.0;
+        if (m_eff == 1) yy = y0[a];
+        else if (m_eff == 2) yy = 2.0 * y0[a] - y1[a];
+        else if (m_eff == 3) yy = 3.0 * y0[a] - 3.0 * y1[a] + y2[a];
+        yv[q] = yy;
+        sv += v;
+        qmax = fmax(qmax, fabs(qc));
+      }
+      st4(A.sigma, t, sg);
+      st4(A.y, t, yv);
+    });
+    double bs = block_sum(sv, sh);
+    double bm = block_max(qmax, sh);
+    if (threadIdx.x == 0) {
+      A.partial[G.b] = bs;
+      A.partial[G.g + G.b] = bm;
+    }
+  }
+};
+
+template <typename T>
+struct OuterHO {
+  using Args = typename Outer<T>::Args;
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G) {
+    const int n = A.n, first = A.first, msk = n - 1, l2 = __builtin_ctz(n);
+    Ctl* ctl = A.ctl;
+    __shared__ double sh[kBlock / 64];
+    __shared__ double s_mean;
+    const CsGeo g(n);
+    const int n3 = n * n * n;
+    double mean_sigma;
+    if (first && A.spart) {
+      const int snb = G.g;
+      const double tot = reduce_partials_sum(A.spart, snb, sh);
+      const double mx = reduce_partials_max(A.spart + snb, snb, sh);
+      if (threadIdx.x == 0) {
+        s_mean = tot / (double)n3;
+        if (G.b == 0) {
+          ctl->mean_sigma = s_mean;
+          ctl->norm_qs = mx;
+          ctl->thresh = A.tol_mode == 0 ? A.tol * mx : A.tol;
+          ctl->done = 0;
+          ctl->cycles = 0;
+          ctl->status = 0;
+          ctl->final_buf = 0;
+        }
+      }
+      __syncthreads();
+      mean_sigma = s_mean;
+    } else {
+      if (ctl->done) return;
+      mean_sigma = ctl->mean_sigma;
+    }
+    const int c = first ? 0 : ctl->cycles + 1;
+    const double* yo = (c & 1) ? A.y0 : A.y1;
+    const double* ys = c == 0 ? A.y0 : yo;
+    // y of cycle c: the stored y (cycle 0) or the previous y plus this cycle's correction
+    auto Y = [&](int x, int y, int z) {
+      double v = ys[nat_idx(n, x, y, z)];
+      if (c > 0) v += (double)(((x + y + z) & 1) ? A.e1 : A.e0)[cs_index(g, x, y, z)];
+      return v;
+    };
+    double rmax = 0.0, ysum = 0.0;
+    march4(G, n, [&](int t) {
+      const int i0 = t & msk, j = (t >> l2) & msk, k = t >> (2 * l2);
+      double yv[4];
+      for (int q = 0; q < 4; q++) {
+        const int i = i0 + q;
+        double yc, yf, ye;
+        stencil19(n, i, j, k, Y, &yc, &yf, &ye);
+        const double r = (A.sigma[t + q] - mean_sigma) - (2.0 * yf + ye - 24.0 * yc) / 6.0;
+        yv[q] = yc;
+        (((i + j + k) & 1) ? A.r1 : A.r0)[cs_index(g, i, j, k)] = (T)r;
+        rmax = fmax(rmax, fabs(r));
+        ysum += yc;
+      }
+      if (c > 0) st4((c & 1) ? A.y1 : A.y0, t, yv);
+    });
+    double bm = block_max(rmax, sh);
+    double bs = block_sum(ysum, sh);
+    if (threadIdx.x == 0) {
+      A.partial[G.b] = bm;
+      A.partial[G.g + G.b] = bs;
+      if (G.b == 0) ctl->pending = c + 1;
+    }
+  }
+};
+
 // The stop decision's two reductions over the outer residual's partials
 // (max of the first nb, sum of the next nb) with the split and tree of a
 // 1024-thread workgroup: virtual thread v folds partials v, v + 1024, ...,
@@ -2213,9 +2365,17 @@ hipError_t smooth_configure() {
 
 hipError_t launch_sigma(int n, double h, bool qs32, const void* qs, const double* phi0, const double* phi1,
                         const double* yb0, const double* yb1, const double* yb2, double* sigma, double* y,
-                        double tol, int tol_mode, double* partial, Ctl* ctl, hipStream_t s, bool finalize) {
+                        double tol, int tol_mode, double* partial, Ctl* ctl, hipStream_t s, bool finalize,
+                        int stencil) {
   const int n3 = n * n * n, nb = red_blocks(n3 / 4);   // four points per thread
-  if (qs32)
+  if (stencil == 1) {
+    if (qs32)
+      P3MZ_LAUNCH(go<SigmaHO<float>>({n, h, (const float*)qs, phi0, phi1, yb0, yb1, yb2, sigma, y, partial, ctl}, nb,
+                                     0, s));
+    else
+      P3MZ_LAUNCH(go<SigmaHO<double>>({n, h, (const double*)qs, phi0, phi1, yb0, yb1, yb2, sigma, y, partial, ctl}, nb,
+                                      0, s));
+  } else if (qs32)
     P3MZ_LAUNCH(go<Sigma<float>>({n, h, (const float*)qs, phi0, phi1, yb0, yb1, yb2, sigma, y, partial, ctl}, nb, 0, s));
   else
     P3MZ_LAUNCH(go<Sigma<double>>({n, h, (const double*)qs, phi0, phi1, yb0, yb1, yb2, sigma, y, partial, ctl}, nb, 0,
@@ -2226,10 +2386,16 @@ hipError_t launch_sigma(int n, double h, bool qs32, const void* qs, const double
 
 hipError_t launch_outer(bool fp64, int n, int first, int max_cycles, const double* sigma, double* y0, double* y1,
                         const void* e0, const void* e1, void* r0, void* r1, double* partial, Ctl* ctl,
-                        hipStream_t s, bool finalize, const double* spart, double tol, int tol_mode) {
+                        hipStream_t s, bool finalize, const double* spart, double tol, int tol_mode, int stencil) {
   const int n3 = n * n * n, nb = red_blocks(n3 / 4);   // four points per thread (sigma's grid too)
   if (!first) spart = nullptr;
-  if (fp64)
+  if (stencil == 1 && fp64)
+    P3MZ_LAUNCH(go<OuterHO<double>>({n, first, sigma, y0, y1, (const double*)e0, (const double*)e1, (double*)r0,
+                                     (double*)r1, partial, ctl, spart, tol_mode, tol}, nb, 0, s));
+  else if (stencil == 1)
+    P3MZ_LAUNCH(go<OuterHO<float>>({n, first, sigma, y0, y1, (const float*)e0, (const float*)e1, (float*)r0,
+                                    (float*)r1, partial, ctl, spart, tol_mode, tol}, nb, 0, s));
+  else if (fp64)
     P3MZ_LAUNCH(go<Outer<double>>({n, first, sigma, y0, y1, (const double*)e0, (const double*)e1, (double*)r0,
                                    (double*)r1, partial, ctl, spart, tol_mode, tol}, nb, 0, s));
   else

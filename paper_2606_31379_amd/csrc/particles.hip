@@ -545,7 +545,10 @@ __device__ void Spread<TO, TS, P>::run(const Args& A, Grid G) {
 // LDS once; the tile's atoms (its bin, sorted) are then evaluated from LDS,
 // one thread per (atom, z-plane of the neighbourhood); the plane partial sums
 // are added in a fixed order.
-template <typename T, typename TP, int TS, int P>
+// HO = 1 takes the fourth-order gradient (8 (f_{+1} - f_{-1}) - (f_{+2} -
+// f_{-2})) / 12h of the Mehrstellen discretisation instead, on a (p+4)^3
+// neighbourhood.
+template <typename T, typename TP, int TS, int P, int HO>
 struct Gather {
   struct Args {
     int n_atoms, n, p, ntx;
@@ -559,12 +562,13 @@ struct Gather {
     const Ctl* gate;   // non-null: do nothing unless gate->done (solve converged)
   };
   static constexpr int kThreads = kBlock;
-  static constexpr int E = TS + P + 1;   // halo tile edge
-  static constexpr int PE = P + 2;       // neighbourhood edge (stencil plus the difference)
+  static constexpr int GR = 1 + HO;          // reach of the difference
+  static constexpr int E = TS + P - 1 + 2 * GR;   // halo tile edge
+  static constexpr int PE = P + 2 * GR;      // neighbourhood edge (stencil plus the difference)
   __device__ static void run(const Args& A, Grid G);
 };
-template <typename T, typename TP, int TS, int P>
-__device__ void Gather<T, TP, TS, P>::run(const Args& A, Grid G) {
+template <typename T, typename TP, int TS, int P, int HO>
+__device__ void Gather<T, TP, TS, P, HO>::run(const Args& A, Grid G) {
   static_assert(E * E <= kBlock, "one halo column per thread");
   const int n = A.n, ntx = A.ntx;
   const double h = A.h, k_e = A.k_e;
@@ -582,6 +586,7 @@ __device__ void Gather<T, TP, TS, P>::run(const Args& A, Grid G) {
   const TP* __restrict__ phi = (ctl->cold ? ctl->k_idx : 1 - ctl->k_idx) ? A.phi1 : A.phi0;
   constexpr int per_round = kBlock / PE;   // atoms evaluated per round
   const T inv2h = (T)(0.5 / h);
+  const T inv12h = (T)(1.0 / (12.0 * h));
   const int tid = threadIdx.x;
   double e_sum = 0.0;
   const int ntiles = ntx * ntx * ntx;
@@ -592,7 +597,7 @@ __device__ void Gather<T, TP, TS, P>::run(const Args& A, Grid G) {
   int nlo = 0, nhi = 0;
   auto fetch = [&](int t) {
     const int tx = t % ntx, ty = (t / ntx) % ntx, tz = t / (ntx * ntx);
-    const int ox = tx * TS - 1, oy = ty * TS - 1, oz = tz * TS - 1;   // halo origin
+    const int ox = tx * TS - GR, oy = ty * TS - GR, oz = tz * TS - GR;   // halo origin
     if (tid < E * E) {
       const int lx = tid % E, ly = tid / E;
       const TP* col = phi + (size_t)((oy + ly) & (n - 1)) * n + ((ox + lx) & (n - 1));
@@ -640,7 +645,7 @@ __device__ void Gather<T, TP, TS, P>::run(const Args& A, Grid G) {
   if (G.b < ntiles) fetch(G.b);
   for (int t = G.b; t < ntiles; t += G.g) {
     const int tx = t % ntx, ty = (t / ntx) % ntx, tz = t / (ntx * ntx);
-    const int ox = tx * TS - 1, oy = ty * TS - 1, oz = tz * TS - 1;   // halo origin
+    const int ox = tx * TS - GR, oy = ty * TS - GR, oz = tz * TS - GR;   // halo origin
     const int a0 = nlo, na_t = nhi - nlo;
     load_round(a0, na_t, 0);
     __syncthreads();   // the previous tile's LDS reads are done
@@ -654,31 +659,39 @@ __device__ void Gather<T, TP, TS, P>::run(const Args& A, Grid G) {
       const int ai = ag + tid / PE, c = tid % PE;
       if (tid < per_round * PE && ai < na_t) {
         form_weights();
-        // extended index j <-> stencil offset j-1; d[j] = (w[j-1] - w[j+1]) / 2h
+        // extended index j <-> stencil offset j - GR; the derivative weight of
+        // point j: d[j] = (w[j-1] - w[j+1]) / 2h, or for the fourth-order
+        // difference (8 (w[j-1] - w[j+1]) - (w[j-2] - w[j+2])) / 12h
         T wx[PE], wy[PE], dx[PE], dy[PE], wz[PE];
 #pragma unroll
         for (int j = 0; j < PE; j++) {
-          wx[j] = (j >= 1 && j <= P) ? rwx[j - 1] : T(0);
-          wy[j] = (j >= 1 && j <= P) ? rwy[j - 1] : T(0);
-          wz[j] = (j >= 1 && j <= P) ? rwz[j - 1] : T(0);
+          wx[j] = (j >= GR && j < GR + P) ? rwx[j - GR] : T(0);
+          wy[j] = (j >= GR && j < GR + P) ? rwy[j - GR] : T(0);
+          wz[j] = (j >= GR && j < GR + P) ? rwz[j - GR] : T(0);
         }
+        auto dif = [&](const T* w, int j) -> T {
+          const T lo = j >= 1 ? w[j - 1] : T(0), hi = j + 1 < PE ? w[j + 1] : T(0);
+          if constexpr (HO == 0) {
+            return (lo - hi) * inv2h;
+          } else {
+            const T lo2 = j >= 2 ? w[j - 2] : T(0), hi2 = j + 2 < PE ? w[j + 2] : T(0);
+            return (T(8) * (lo - hi) - (lo2 - hi2)) * inv12h;
+          }
+        };
 #pragma unroll
         for (int j = 0; j < PE; j++) {
-          const T lo = j >= 1 ? wx[j - 1] : T(0), hi = j + 1 < PE ? wx[j + 1] : T(0);
-          dx[j] = (lo - hi) * inv2h;
-          const T loy = j >= 1 ? wy[j - 1] : T(0), hiy = j + 1 < PE ? wy[j + 1] : T(0);
-          dy[j] = (loy - hiy) * inv2h;
+          dx[j] = dif(wx, j);
+          dy[j] = dif(wy, j);
         }
         T wz_c = T(0), dz_c = T(0);
 #pragma unroll
         for (int j = 0; j < PE; j++)
           if (j == c) {
             wz_c = wz[j];
-            const T loz = j >= 1 ? wz[j - 1] : T(0), hiz = j + 1 < PE ? wz[j + 1] : T(0);
-            dz_c = (loz - hiz) * inv2h;
+            dz_c = dif(wz, j);
           }
-        // neighbourhood origin in the halo tile: base - 1 - (tile origin - 1)
-        const int lx0 = org_x(rorg) - (ox + 1), ly0 = org_y(rorg) - (oy + 1), lz0 = org_z(rorg) - (oz + 1);
+        // neighbourhood origin in the halo tile: base - GR - (tile origin - GR)
+        const int lx0 = org_x(rorg) - (ox + GR), ly0 = org_y(rorg) - (oy + GR), lz0 = org_z(rorg) - (oz + GR);
         double fx = 0, fy = 0, fz = 0, pot = 0;
         const T* plane = sphi + (lz0 + c) * E * E;
 #pragma unroll
@@ -1211,15 +1224,15 @@ hipError_t launch_spread(bool fp64, int n, int p, int tile, int ntx, double box,
 }
 
 namespace {
-template <int P>
+template <int P, int HO>
 hipError_t gather_p(bool fp64, int n_atoms, int n, int ntx, double h, double k_e, const int* start, const void* rb,
                     const void* rq, const double* phi0, const double* phi1, const float* phi32, double* force,
                     double* partial, Ctl* ctl, const Ctl* gate, int nb, hipStream_t s) {
   if (fp64)
-    return go<Gather<double, double, 8, P>>({n_atoms, n, P, ntx, h, k_e, start, (const int2*)rb, (const double4*)rq,
+    return go<Gather<double, double, 8, P, HO>>({n_atoms, n, P, ntx, h, k_e, start, (const int2*)rb, (const double4*)rq,
                                              phi0, phi1, force,
                                              partial, ctl, gate}, nb, 0, s);
-  return go<Gather<float, float, 8, P>>({n_atoms, n, P, ntx, h, k_e, start, (const int2*)rb, (const double4*)rq,
+  return go<Gather<float, float, 8, P, HO>>({n_atoms, n, P, ntx, h, k_e, start, (const int2*)rb, (const double4*)rq,
                                          phi32, phi32, force,
                                          partial, ctl, gate}, nb, 0, s);
 }
@@ -1227,19 +1240,24 @@ hipError_t gather_p(bool fp64, int n_atoms, int n, int ntx, double h, double k_e
 
 hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, int tile, int ntx, double h, double k_e,
                          const int* start, const void* rb, const void* rq, const double* phi0, const double* phi1,
-                         const float* phi32, double* force, double* partial, Ctl* ctl, hipStream_t s, bool finalize) {
-  if (tile != 8) return hipErrorInvalidValue;
+                         const float* phi32, double* force, double* partial, Ctl* ctl, hipStream_t s, bool finalize,
+                         int stencil) {
+  if (tile != 8 || (stencil == 1 && p > 5)) return hipErrorInvalidValue;
   const int nb = std::min(ntx * ntx * ntx, kMaxRedBlocks);
   // the step's gather (finalize) waits for a converged solve
   const Ctl* gate = finalize ? ctl : nullptr;
   hipError_t e;
   switch (p) {
-    case 2: e = gather_p<2>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rq, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
-    case 3: e = gather_p<3>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rq, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
-    case 4: e = gather_p<4>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rq, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
-    case 5: e = gather_p<5>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rq, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
-    case 6: e = gather_p<6>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rq, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
-    case 7: e = gather_p<7>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rq, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
+    case 2: e = stencil == 1 ? gather_p<2, 1>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rq, phi0, phi1, phi32, force, partial, ctl, gate, nb, s)
+                          : gather_p<2, 0>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rq, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
+    case 3: e = stencil == 1 ? gather_p<3, 1>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rq, phi0, phi1, phi32, force, partial, ctl, gate, nb, s)
+                          : gather_p<3, 0>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rq, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
+    case 4: e = stencil == 1 ? gather_p<4, 1>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rq, phi0, phi1, phi32, force, partial, ctl, gate, nb, s)
+                          : gather_p<4, 0>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rq, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
+    case 5: e = stencil == 1 ? gather_p<5, 1>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rq, phi0, phi1, phi32, force, partial, ctl, gate, nb, s)
+                          : gather_p<5, 0>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rq, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
+    case 6: e = gather_p<6, 0>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rq, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
+    case 7: e = gather_p<7, 0>(fp64, n_atoms, n, ntx, h, k_e, start, rb, rq, phi0, phi1, phi32, force, partial, ctl, gate, nb, s); break;
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess || !finalize) return e;

@@ -50,7 +50,7 @@ class p3mz_params(C.Structure):
                 ("mesh", C.c_int32), ("order", C.c_int32), ("tol", C.c_double),
                 ("tol_mode", C.c_int32), ("max_cycles", C.c_int32), ("predictor", C.c_int32),
                 ("precision", C.c_int32), ("coulomb_k", C.c_double), ("nu_pre", C.c_int32),
-                ("nu_post", C.c_int32), ("excl_group", C.c_int32)]
+                ("nu_post", C.c_int32), ("excl_group", C.c_int32), ("stencil", C.c_int32)]
 
 
 class p3mz_stats(C.Structure):
@@ -358,6 +358,6 @@ def p3mz_version() -> str:
 
 def make_params(box, alpha, r_cut, mesh, order, tol=1e-8, tol_mode=0, max_cycles=50, predictor=3,
                 precision=P3MZ_PREC_FP64, coulomb_k=1.0, nu_pre=2, nu_post=2,
-                excl_group=0) -> p3mz_params:
+                excl_group=0, stencil=0) -> p3mz_params:
     return p3mz_params(box, alpha, r_cut, mesh, order, tol, tol_mode, max_cycles, predictor,
-                       precision, coulomb_k, nu_pre, nu_post, excl_group)
+                       precision, coulomb_k, nu_pre, nu_post, excl_group, stencil)

@@ -63,15 +63,15 @@ class GpuCtx:
 
 
 def params_pair(box, alpha, r_cut, mesh, order, tol=1e-8, precision=0, predictor=3, max_cycles=50,
-                k_e=1.0, nu_pre=2, nu_post=2, excl_group=0, tol_mode=0):
+                k_e=1.0, nu_pre=2, nu_post=2, excl_group=0, tol_mode=0, stencil=0):
     """Matching parameter structs for the library and the oracle."""
     from paper_2606_31379_amd import p3maze as P
     g = P.make_params(box, alpha, r_cut, mesh, order, tol=tol, tol_mode=tol_mode, max_cycles=max_cycles,
                       predictor=predictor, precision=precision, coulomb_k=k_e, nu_pre=nu_pre,
-                      nu_post=nu_post, excl_group=excl_group)
+                      nu_post=nu_post, excl_group=excl_group, stencil=stencil)
     o = O.make_params(box, alpha, r_cut, mesh, order, tol=tol, tol_mode=tol_mode, max_cycles=max_cycles,
                       predictor=predictor, coulomb_k=k_e, nu_pre=nu_pre, nu_post=nu_post,
-                      excl_group=excl_group)
+                      excl_group=excl_group, stencil=stencil)
     return g, o
 
 

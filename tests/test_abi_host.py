@@ -82,3 +82,12 @@ def test_null_context_rejected_by_the_md_and_pair_options():
     assert L.p3mz_set_thermostat(None, 0.1, 0.025, 1) == P.P3MZ_ERR_INVALID_ARG
     b, o, c = C.c_int64(), C.c_int64(), C.c_int32()
     assert L.p3mz_get_neighbor_stats(None, C.byref(b), C.byref(o), C.byref(c)) == P.P3MZ_ERR_INVALID_ARG
+
+
+def test_stencil_validated_before_allocation():
+    from paper_2606_31379_amd import p3maze as P
+    q = np.array([1.0, -1.0])
+    for kw in (dict(order=6, stencil=1), dict(order=4, stencil=2), dict(order=4, stencil=-1)):
+        with pytest.raises(P.P3MZError) as ei:
+            P.p3mz_create(P.make_params(10.0, 0.5, 4.0, 16, **kw), q)
+        assert ei.value.code == P.P3MZ_ERR_INVALID_ARG

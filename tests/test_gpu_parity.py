@@ -420,3 +420,34 @@ def test_dense_system_md_nonelectrostatic(torch):
         assert np.max(np.abs(eg - elog_o)) <= 1e-9 * np.max(np.abs(elog_o))
     finally:
         g.close()
+
+
+# ---------------------------------------------------------------------------
+# fourth-order (Mehrstellen) discretisation, stencil 1
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("precision,bar", [(0, FP64_BAR), (1, MIXED_BAR)])
+@pytest.mark.parametrize("workload", ["nacl-512", "water-3000"])
+def test_fourth_order_steps(torch, workload, precision, bar):
+    """Whole steps with the 19-point operator and the four-point gradient on
+    the 32^3 (NaCl) and 64^3 (water) workloads: forces, energies, potentials
+    and V-cycle counts against the oracle's stencil-1 step."""
+    w = configs.WORKLOADS[workload]()
+    s = w.system()
+    gp, op = params_pair(w.box, w.alpha, w.r_cut, w.mesh, w.order, tol=w.tol, precision=precision, k_e=K_E,
+                         predictor=3, excl_group=w.excl_group, stencil=1)
+    res = run_pair(torch, s, gp, op, steps=4)
+    check_steps(res, bar)
+
+
+@pytest.mark.parametrize("order", [2, 3, 4, 5])
+@pytest.mark.parametrize("mesh", [8, 32])
+@pytest.mark.parametrize("precision,bar", [(0, FP64_BAR), (1, MIXED_BAR)])
+def test_fourth_order_forces_every_order(torch, order, mesh, precision, bar):
+    """The four-point-gradient gather for every order it supports, on a
+    one-tile mesh (the halo wraps onto the tile) and a 4^3-tile mesh."""
+    s = inputs.random_neutral(300, 12.0, seed=200 + 10 * order + mesh, dmin=0.7)
+    alpha = 0.25 if mesh == 8 else 0.45
+    gp, op = params_pair(12.0, alpha, 5.0, mesh, order, tol=1e-9, precision=precision, stencil=1)
+    res = run_pair(torch, s, gp, op, steps=2)
+    check_steps(res, bar)
+
