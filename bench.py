@@ -407,13 +407,16 @@ def run_batch_mode(torch, P, w, systems, precision, warmup, steps):
         P.p3mz_batch_set_timing(b, False)
         reps = 100
         kms, kbytes = P.p3mz_batch_kernel_bench(b, P.KERNELS["halfsweep"], reps, stream)
+        # the same half-sweeps in one persistent launch with per-system device barriers
+        pms, _ = P.p3mz_batch_kernel_bench(b, P.PERSIST_HALFSWEEP, reps, stream)
         cyc = np.array(cyc)
         total = sum(n)
         return dict(ns_per_atom=mesh_ms / steps * 1e6 / total, mesh_ms_per_step=mesh_ms / steps,
                     md_ms_per_step=wall * 1e3 / steps, short_range_ms_per_step=sr_ms / steps, graphs=bool(graphs),
                     vcycles_mean=float(cyc.mean()), vcycles_max_per_step=float(cyc.max(axis=1).mean()),
                     dominant="halfsweep", dominant_avg_launch_us=kms * 1e3, dominant_launches=reps,
-                    dominant_bytes_per_launch=kbytes, dominant_gbps=kbytes / (kms * 1e-3) / 1e9)
+                    dominant_bytes_per_launch=kbytes, dominant_gbps=kbytes / (kms * 1e-3) / 1e9,
+                    persistent_halfsweep_us=pms * 1e3, persistent_halfsweep_gbps=kbytes / (pms * 1e-3) / 1e9)
     finally:
         P.p3mz_batch_destroy(b)
 

@@ -274,7 +274,12 @@ enum {
   P3MZ_KERNEL_SPREAD = 7, P3MZ_KERNEL_GATHER = 8, P3MZ_KERNEL_SR = 9,
   P3MZ_KERNEL_SIGMA = 10, P3MZ_KERNEL_PHI = 11,
   P3MZ_KERNEL_FUSED_DOWN = 12, /* fused down leg of a small level (first sweep + pairs) */
-  P3MZ_KERNEL_FUSED_UP = 13    /* fused up leg of a small level (correction + pairs)    */
+  P3MZ_KERNEL_FUSED_UP = 13,  /* fused up leg of a small level (correction + pairs)    */
+  /* batches only: `reps` finest-level half-sweeps of every system in ONE
+   * persistent launch (workgroups take (sweep, system, tile) tasks from a
+   * device counter; a system's next sweep waits on a per-system device
+   * barrier), timed per half-sweep against HALFSWEEP's one launch per sweep */
+  P3MZ_KERNEL_PERSIST_HALFSWEEP = 14
 };
 /* Start timing one kernel family (kernel_id as above, -1 = off) and zero the
  * totals.  Up to 2048 launches per compute are timed.  While a family is timed
@@ -435,8 +440,10 @@ p3mz_status p3mz_batch_get_timing(const p3mz_batch* b, double* ms_mesh, double* 
 p3mz_status p3mz_batch_set_graphs(p3mz_batch* b, int32_t on);
 /* As p3mz_kernel_bench, for one batched launch of a V-cycle kernel family
  * (HALFSWEEP, SWEEP0, RESTRICT, PROLONG, TAIL) over every system's finest
- * level; *bytes_per_launch sums the systems' algorithmic bytes.  Leaves each
- * system's control block open (the next step resets it). */
+ * level; *bytes_per_launch sums the systems' algorithmic bytes.  With
+ * PERSIST_HALFSWEEP, one persistent launch runs `reps` half-sweeps and
+ * *avg_ms is its time per half-sweep (STATE if a device wait gave up).
+ * Leaves each system's control block open (the next step resets it). */
 p3mz_status p3mz_batch_kernel_bench(p3mz_batch* b, int32_t kernel_id, int32_t reps, void* stream, double* avg_ms,
                                     double* bytes_per_launch);
 void p3mz_batch_destroy(p3mz_batch* b);

@@ -2175,9 +2175,54 @@ p3mz_status p3mz_batch_kernel_bench(p3mz_batch* b, int32_t kernel_id, int32_t re
                                     double* bytes_per_launch) {
   if (!b || !avg_ms || !bytes_per_launch || reps < 1) return fail(P3MZ_ERR_INVALID_ARG, "bad kernel_bench arguments");
   if (kernel_id != KT_HALFSWEEP && kernel_id != KT_SWEEP0 && kernel_id != KT_RESTRICT && kernel_id != KT_PROLONG &&
-      kernel_id != KT_TAIL)
+      kernel_id != KT_TAIL && kernel_id != P3MZ_KERNEL_PERSIST_HALFSWEEP)
     return fail(P3MZ_ERR_INVALID_ARG, "kernel family not available for batched timing");
   hipStream_t s = (hipStream_t)stream;
+  if (kernel_id == P3MZ_KERNEL_PERSIST_HALFSWEEP) {
+    // `reps` half-sweeps of every system in one persistent launch
+    const int R = (int)b->sys.size();
+    std::vector<const LevelBufs*> lv0(R);
+    std::vector<Ctl*> ctls(R);
+    double bytes = 0.0;
+    for (int r = 0; r < R; r++) {
+      p3mz_ctx* c = b->sys[r];
+      lv0[r] = &c->lv[0];
+      ctls[r] = c->d_ctl;
+      const double n3 = (double)c->pl.n * c->pl.n * c->pl.n;
+      bytes += 1.5 * (double)c->tsz * n3;
+    }
+    const int grid = persist_grid();
+    if (grid < 1) return fail(P3MZ_ERR_HIP, "no occupancy for the persistent kernel");
+    size_t sys_bytes = persist_sys_bytes(b->fp64, R);
+    void* d_sys = nullptr;
+    int* d_work = nullptr;
+    P3MZ_HIP_TRY(hipMalloc(&d_sys, sys_bytes));
+    P3MZ_HIP_TRY(hipMalloc(&d_work, sizeof(int) * (2 + (size_t)R * reps)));
+    for (p3mz_ctx* c : b->sys) P3MZ_HIP_TRY(launch_set_ctl_open(c->d_ctl, s));
+    hipEvent_t e0, e1;
+    P3MZ_HIP_TRY(hipEventCreate(&e0));
+    P3MZ_HIP_TRY(hipEventCreate(&e1));
+    // a warm-up launch, then the timed one
+    P3MZ_HIP_TRY(persist_halfsweeps(b->fp64, lv0.data(), ctls.data(), R, reps, d_sys, d_work, grid, s, &sys_bytes,
+                                    true));
+    P3MZ_HIP_TRY(hipEventRecord(e0, s));
+    P3MZ_HIP_TRY(persist_halfsweeps(b->fp64, lv0.data(), ctls.data(), R, reps, d_sys, d_work, grid, s, &sys_bytes,
+                                    false));
+    P3MZ_HIP_TRY(hipEventRecord(e1, s));
+    P3MZ_HIP_TRY(hipEventSynchronize(e1));
+    int flags[2] = {0, 0};
+    P3MZ_HIP_TRY(hipMemcpy(flags, d_work, sizeof flags, hipMemcpyDeviceToHost));
+    float ms = 0.f;
+    P3MZ_HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    P3MZ_HIP_TRY(hipFree(d_sys));
+    P3MZ_HIP_TRY(hipFree(d_work));
+    if (flags[1]) return fail(P3MZ_ERR_STATE, "a persistent-kernel wait gave up");
+    *avg_ms = ms / reps;
+    *bytes_per_launch = bytes;
+    return P3MZ_OK;
+  }
   // one batched launch of the family on every system's finest level
   BatchSet tmp;
   std::vector<unsigned char> args;

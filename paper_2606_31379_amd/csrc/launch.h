@@ -156,6 +156,16 @@ hipError_t launch_vcycle_kernel(bool fp64, int kid, const LevelBufs* lv, int lev
 hipError_t launch_phi_update(int n, double h, double* phi0, double* phi1, const double* ya, const double* yb,
                              double* yh0, double* yh1, double* yh2, float* phi32, Ctl* ctl, hipStream_t s,
                              const Decide* decide = nullptr);
+// Persistent launch of `phases` finest-level half-sweeps (colours
+// alternating) on every system of a batch, with per-system device barriers
+// between them (a measurement of that form against one batched launch per
+// sweep).  d_sys: device buffer for the per-system arguments (*sys_bytes
+// reports the size; uploaded when `upload`); d_work: 2 + n_sys * phases ints
+// (work[1] becomes 1 if a wait gave up).  grid: resident workgroups.
+hipError_t persist_halfsweeps(bool fp64, const LevelBufs* const* lv0, Ctl* const* ctls, int n_sys, int phases,
+                              void* d_sys, int* d_work, int grid, hipStream_t s, size_t* sys_bytes, bool upload);
+int persist_grid();
+size_t persist_sys_bytes(bool fp64, int n_sys);
 // End-of-step rotation of the history on the device.
 hipError_t launch_advance(Ctl* ctl, hipStream_t s);
 // Layout conversions for inspection and the stand-alone V-cycle.

@@ -2405,6 +2405,124 @@ hipError_t launch_outer(bool fp64, int n, int first, int max_cycles, const doubl
   return go<FinOuter>({max_cycles, nb, n3, partial, ctl}, 1, 0, s);
 }
 
+// ---------------------------------------------------------------------------
+// Persistent form of a batch's finest-level sweeps, built to measure it
+// against one batched launch per sweep: one launch runs `phases`
+// half-sweeps (colours alternating) on every system.  The tasks (phase,
+// system, tile) are numbered phase-major and workgroup b of a grid that fits
+// on the device at once takes tasks b, b + G, b + 2G, ... in order; a task of
+// phase p waits until every tile of its own system's phase p-1 is done (a
+// per-system device barrier with acquire/release fences at agent scope), so
+// systems advance independently instead of meeting at kernel boundaries.
+// Every wait is on tasks with smaller numbers, held by resident workgroups
+// that take their tasks in increasing order, so the waits end; a bounded
+// spin sets an error flag instead of waiting forever.  The task loop's
+// bounds are kernel arguments and the block index (uniform): no workgroup
+// barrier sits in a loop whose exit depends on a value read from memory.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct PersistSys {
+  typename Halfsweep<T, 1, 0>::Args a[2];   // red, black
+  int grid, off;                             // tiles per phase, first task of the system in a phase
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_persist_halfsweeps(const PersistSys<T>* __restrict__ sys, int n_sys,
+                                                                int per_phase, int phases, int* __restrict__ work) {
+  // work[1]: error flag, work[2 + r * phases + p]: finished tiles of system r, phase p
+  const int total = per_phase * phases;
+  for (int task = blockIdx.x; task < total; task += gridDim.x) {
+    const int p = task / per_phase, w = task - p * per_phase;
+    int lo = 0, hi = n_sys - 1;   // the system whose tasks hold w
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (sys[mid].off <= w) lo = mid;
+      else hi = mid - 1;
+    }
+    const PersistSys<T>& S = sys[lo];
+    if (p > 0 && threadIdx.x == 0) {
+      int* dep = &work[2 + lo * phases + p - 1];
+      int spins = 0;
+      while (__hip_atomic_load(dep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < S.grid && spins < (1 << 22)) {
+        __builtin_amdgcn_s_sleep(2);
+        spins++;
+      }
+      if (spins >= (1 << 22)) atomicExch(&work[1], 1);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // see the other XCDs' stores
+    }
+    __syncthreads();
+    Halfsweep<T, 1, 0>::run(S.a[p & 1], Grid{w - S.off, S.grid});
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      atomicAdd(&work[2 + lo * phases + p], 1);
+    }
+  }
+}
+
+__global__ void k_zero_ints(int* __restrict__ a, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) a[i] = 0;
+}
+
+hipError_t persist_halfsweeps(bool fp64, const LevelBufs* const* lv0, Ctl* const* ctls, int n_sys, int phases,
+                              void* d_sys, int* d_work, int grid, hipStream_t s, size_t* sys_bytes, bool upload) {
+  const size_t elem = fp64 ? sizeof(PersistSys<double>) : sizeof(PersistSys<float>);
+  *sys_bytes = elem * (size_t)n_sys;
+  int per_phase = 0;
+  if (upload) {
+    std::vector<unsigned char> host(*sys_bytes);
+    for (int r = 0; r < n_sys; r++) {
+      const LevelBufs& f = *lv0[r];
+      if (fp64) {
+        PersistSys<double> x{};
+        for (int c = 0; c < 2; c++)
+          x.a[c] = {f.n, c, (double*)(c ? f.e1 : f.e0), (const double*)(c ? f.e0 : f.e1),
+                    (const double*)(c ? f.r1 : f.r0), ctls[r]};
+        x.grid = sweep_blocks<double>(f.n);
+        x.off = per_phase;
+        per_phase += x.grid;
+        memcpy(host.data() + elem * r, &x, elem);
+      } else {
+        PersistSys<float> x{};
+        for (int c = 0; c < 2; c++)
+          x.a[c] = {f.n, c, (float*)(c ? f.e1 : f.e0), (const float*)(c ? f.e0 : f.e1),
+                    (const float*)(c ? f.r1 : f.r0), ctls[r]};
+        x.grid = sweep_blocks<float>(f.n);
+        x.off = per_phase;
+        per_phase += x.grid;
+        memcpy(host.data() + elem * r, &x, elem);
+      }
+    }
+    P3MZ_LAUNCH(hipMemcpy(d_sys, host.data(), host.size(), hipMemcpyHostToDevice));
+  } else {
+    for (int r = 0; r < n_sys; r++) per_phase += fp64 ? sweep_blocks<double>(lv0[r]->n) : sweep_blocks<float>(lv0[r]->n);
+  }
+  const int nwork = 2 + n_sys * phases;
+  hipLaunchKernelGGL(k_zero_ints, dim3((nwork + 255) / 256), dim3(256), 0, s, d_work, nwork);
+  P3MZ_LAUNCH(hipGetLastError());
+  if (fp64)
+    hipLaunchKernelGGL(k_persist_halfsweeps<double>, dim3(grid), dim3(kBlock), 0, s, (const PersistSys<double>*)d_sys,
+                       n_sys, per_phase, phases, d_work);
+  else
+    hipLaunchKernelGGL(k_persist_halfsweeps<float>, dim3(grid), dim3(kBlock), 0, s, (const PersistSys<float>*)d_sys,
+                       n_sys, per_phase, phases, d_work);
+  return hipGetLastError();
+}
+
+size_t persist_sys_bytes(bool fp64, int n_sys) {
+  return (fp64 ? sizeof(PersistSys<double>) : sizeof(PersistSys<float>)) * (size_t)n_sys;
+}
+
+int persist_grid() {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_persist_halfsweeps<float>, kBlock, 0) != hipSuccess)
+    return 0;
+  return cus * std::max(1, per_cu);
+}
+
 hipError_t launch_vcycle(bool fp64, const LevelBufs* lv, int levels, int tail, int nu1, int nu2,
                          const double* green, Ctl* ctl, hipStream_t s, const Decide* decide) {
   return fp64 ? vcycle_impl<double>(lv, levels, tail, nu1, nu2, green, ctl, s, decide)

@@ -43,6 +43,7 @@ EXPORTS = ["p3mz_create", "p3mz_compute", "p3mz_get_mesh", "p3mz_get_potential",
 KERNELS = {"halfsweep": 0, "outer": 1, "smooth": 2, "restrict": 3, "prolong": 4, "sweep0": 5,
            "tail": 6, "spread": 7, "gather": 8, "sr": 9, "sigma": 10, "phi": 11, "fused_down": 12,
            "fused_up": 13}
+PERSIST_HALFSWEEP = 14   # batches only: half-sweeps in one persistent launch
 
 
 class p3mz_params(C.Structure):

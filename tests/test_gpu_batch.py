@@ -249,3 +249,28 @@ def test_full_64_replica_batch_against_oracle(torch):
             print(f"step {k}: worst replica rel-RMS force error {worst:.2e}", flush=True)
     finally:
         P.p3mz_batch_destroy(b)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_persistent_halfsweeps_run_to_completion(torch, precision):
+    """The persistent-kernel form of a batch's finest-level half-sweeps (one
+    launch, per-system device barriers; a measurement prototype, not on the
+    step path) finishes every task without a wait giving up, and the batch
+    still steps to the oracle-checked result afterwards."""
+    from paper_2606_31379_amd import p3maze as P
+    reps, systems = build(torch, precision)
+    n = [s.n for s in systems]
+    q = packed([s.charges for s in systems])
+    stream = torch.cuda.current_stream().cuda_stream
+    b = P.p3mz_batch_create([sys_params(P, r, precision) for r in reps], n, q)
+    try:
+        dev = torch.device("cuda")
+        pos = torch.from_numpy(packed([s.pos for s in systems])).to(dev)
+        P.p3mz_batch_compute(b, pos.data_ptr(), None, None, stream)
+        for k in (1, 8):
+            ms, by = P.p3mz_batch_kernel_bench(b, P.PERSIST_HALFSWEEP, k, stream)
+            assert np.isfinite(ms) and ms > 0 and by > 0
+        ms1, _ = P.p3mz_batch_kernel_bench(b, P.KERNELS["halfsweep"], 8, stream)
+        print(f"per half-sweep: persistent {ms * 1e3:.1f} us, batched launches {ms1 * 1e3:.1f} us", flush=True)
+    finally:
+        P.p3mz_batch_destroy(b)
