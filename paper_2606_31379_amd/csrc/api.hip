@@ -220,6 +220,7 @@ struct p3mz_ctx {
   double* d_partial = nullptr;
   double* d_spart = nullptr;     // sigma's partials when the first outer residual reduces them
   double* d_nfpart = nullptr;    // net-force partials of the pair kernels
+  double* d_nepart = nullptr;    // energy partials of the MD pair and bonded terms
   Ctl* d_ctl = nullptr;
   Ctl* h_ctl = nullptr;         // pinned mirror
   double* d_energy = nullptr;   // internal energy4 when the caller passes none
@@ -592,6 +593,7 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
   P3MZ_TRY(c->alloc(&c->d_partial, kPartialSlots));
   P3MZ_TRY(c->alloc(&c->d_spart, kPartialSlots));
   P3MZ_TRY(c->alloc(&c->d_nfpart, 3 * kPartialSlots));
+  P3MZ_TRY(c->alloc(&c->d_nepart, 2 * kPartialSlots));
   P3MZ_TRY(c->alloc(&c->d_ctl, 1));
   P3MZ_HIP_TRY(hipHostMalloc((void**)&c->h_ctl, sizeof(Ctl), hipHostMallocDefault));
   memset(&c->mirror, 0, sizeof(Ctl));
@@ -730,7 +732,14 @@ p3mz_status enq_post1(p3mz_ctx* c, double* force, hipStream_t s) {
 // short-range pairs on a fresh cell list, energies, history rotation
 // With neighbour lists the cell list and the lists are rebuilt only on the
 // steps the check flags (the rebuild launches test the flag on the device).
-p3mz_status enq_post2(p3mz_ctx* c, const double* pos, double* force, double* energy, hipStream_t s) {
+// ne (MD steps): the list pass of the pair kernel also adds the MD pair term
+// of model ne->model; *ne_written gets the number of its energy partials.
+struct NePair {
+  int model;
+  double p0, p1;
+};
+p3mz_status enq_post2(p3mz_ctx* c, const double* pos, double* force, double* energy, hipStream_t s,
+                      const NePair* ne = nullptr, int* ne_written = nullptr) {
   const int na = (int)c->n_atoms;
   const bool nbr = c->d_nbr != nullptr;
   const int* gate = nbr ? &c->d_ctl->nbr_stale : nullptr;
@@ -754,7 +763,9 @@ p3mz_status enq_post2(p3mz_ctx* c, const double* pos, double* force, double* ene
   P3MZ_HIP_TRY(launch_sr(na, pos, c->d_qa, c->P.box, c->P.alpha, c->P.r_cut, c->P.coulomb_k, c->nc, c->P.excl_group,
                          c->d_cstart, c->d_cperm, c->d_spos, c->d_erfc, c->erfc_n, c->erfc_scale, force, c->e_self,
                          energy ? energy : c->d_energy,
-                         c->d_partial, c->d_nfpart, c->d_ctl, s, c->d_nbr, c->d_nlist, c->nbr_cap));
+                         c->d_partial, c->d_nfpart, c->d_ctl, s, c->d_nbr, c->d_nlist, c->nbr_cap,
+                         ne && c->d_nbr ? ne->model : 0, ne ? ne->p0 : 0.0, ne ? ne->p1 : 0.0, c->d_nepart,
+                         ne_written));
   kt_end(KT_SR, 0, (double)na * 56.0, s);
   rec_key(6005);
   P3MZ_HIP_TRY(launch_advance(c->d_ctl, s));
@@ -774,12 +785,17 @@ struct MdArgs {
 // terms, closing half-kick and the energy log
 p3mz_status enq_md_post2(p3mz_ctx* c, const MdArgs& m, hipStream_t s) {
   const int na = (int)c->n_atoms;
-  P3MZ_TRY(enq_post2(c, m.pos, c->d_md_force, c->d_energy, s));
+  // with neighbour lists, the pair term of the model rides along the
+  // short-range list pass; the non-electrostatic kernel then covers only
+  // the atoms over the list capacity (and the bonded terms)
+  const NePair ne{m.model, m.p[0], m.p[1]};
+  int prior = 0;
+  P3MZ_TRY(enq_post2(c, m.pos, c->d_md_force, c->d_energy, s, m.model != 0 ? &ne : nullptr, &prior));
   // the cell list of the short-range pass is still valid for these positions
   rec_key(6100);
   P3MZ_HIP_TRY(launch_nonelec(na, m.pos, c->P.box, c->P.r_cut, m.model, m.p[0], m.p[1], m.p[2], m.p[3], m.p[4],
-                              m.p[5], c->nc, c->d_cstart, c->d_cperm, c->d_spos, c->d_md_force, c->d_partial, c->d_e_other, s,
-                              c->d_nbr, c->d_nlist, c->nbr_cap));
+                              m.p[5], c->nc, c->d_cstart, c->d_cperm, c->d_spos, c->d_md_force, c->d_nepart,
+                              c->d_e_other, s, c->d_nbr, c->d_nlist, c->nbr_cap, prior, prior > 0));
   rec_key(6101);
   P3MZ_HIP_TRY(launch_kick_drift(na, m.pos, m.vel, c->d_md_force, m.mass, m.dt, m.f2a, 0, s, &m.th));
   rec_key(6102);

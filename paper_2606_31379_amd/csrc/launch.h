@@ -79,12 +79,18 @@ hipError_t launch_nbr_build(int n_atoms, double box, double r_list, int nc, int 
                             Ctl* ctl, hipStream_t s);
 // erfc_tab: erfcx table for alpha r in [0, alpha r_cut] (erfc_n intervals,
 // erfc_scale intervals per unit).  list/nlist/cap: neighbour lists as built
-// by launch_nbr_build (null: every atom scans the cells).
+// by launch_nbr_build (null: every atom scans the cells).  ne_model != 0
+// (lists only): the list pass also adds the MD pair term (1: Born-Mayer
+// A = ne_p0, rho = ne_p1; 2: O-O Lennard-Jones eps, sigma) to force, its
+// energy partials in nepart[0 .. *ne_written); atoms over capacity are left
+// to launch_nonelec.
 hipError_t launch_sr(int n_atoms, const double* pos, const double* qa, double box, double alpha,
                      double r_cut, double k_e, int nc, int excl_group, const int* cstart,
                      const int* cperm, const void* spos, const double* erfc_tab, int erfc_n, double erfc_scale,
                      double* force, double e_self, double* energy_out, double* partial, double* nfpart, Ctl* ctl,
-                     hipStream_t s, const int* list = nullptr, const int* nlist = nullptr, int cap = 0);
+                     hipStream_t s, const int* list = nullptr, const int* nlist = nullptr, int cap = 0,
+                     int ne_model = 0, double ne_p0 = 0.0, double ne_p1 = 0.0, double* nepart = nullptr,
+                     int* ne_written = nullptr);
 
 // ---- mesh (mesh.hip) -----------------------------------------------------
 // Folded periodic smoothing filter along one axis: out = sum_m c[m] v[i+m-K],
@@ -190,7 +196,7 @@ hipError_t launch_nonelec(int n_atoms, const double* pos, double box, double r_c
                           double p0, double p1, double p2, double p3, double p4, double p5,
                           int nc, const int* cstart, const int* cperm, const void* spos, double* force,
                           double* partial, double* e_out, hipStream_t s, const int* list = nullptr,
-                          const int* nlist = nullptr, int cap = 0);
+                          const int* nlist = nullptr, int cap = 0, int prior = 0, int skip_listed = 0);
 // Kinetic energy and one row (ctl->md_step, then advanced) of the logs.
 hipError_t launch_kinetic_log(int n_atoms, const double* vel, const double* mass, double mv2e,
                               const double* energy4, const double* e_other, double* log_base,

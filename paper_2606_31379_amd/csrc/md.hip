@@ -100,6 +100,7 @@ struct NonElec {
     double *force, *partial;
     const int *list, *nlist;   // neighbour lists as in the short-range kernel (null: scan the cells)
     int cap;
+    int skip_listed;           // 1: atoms with a list are done by the short-range list pass
   };
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G);
@@ -128,7 +129,8 @@ __device__ void NonElec::run(const Args& A, Grid G) {
     const int mine = chunk * span + lane;
     const bool in = lane < span && mine < n_atoms;
     const int ai = in ? cperm[mine] : 0;
-    unsigned long long todo = __ballot(in && (model == 1 || ai % 3 == 0));
+    const bool listed = A.skip_listed && in && A.list && A.nlist[mine] <= A.cap;
+    unsigned long long todo = __ballot(in && !listed && (model == 1 || ai % 3 == 0));
     while (todo) {
       const int l = __ffsll((unsigned long long)todo) - 1;   // wave-uniform
       todo &= todo - 1;
@@ -325,23 +327,23 @@ hipError_t launch_kick_drift(int n_atoms, double* pos, double* vel, const double
 hipError_t launch_nonelec(int n_atoms, const double* pos, double box, double r_cut, int model, double p0,
                           double p1, double p2, double p3, double p4, double p5, int nc, const int* cstart,
                           const int* cperm, const void* spos, double* force, double* partial, double* e_out,
-                          hipStream_t s, const int* list, const int* nlist, int cap) {
+                          hipStream_t s, const int* list, const int* nlist, int cap, int prior, int skip_listed) {
   // positions per wave: 64, halved while that leaves fewer than 8192 waves
   int span = 64;
   while (span > 1 && (n_atoms + span - 1) / span < 8192) span >>= 1;
   const int64_t waves = (n_atoms + span - 1) / span;
-  // partials: the pair kernel's first, then the bonded kernel's
+  // partials: `prior` of the short-range list pass, the pair kernel's, then the bonded kernel's
   const int nb = std::min(blocks_for(waves * 64, kBlock), kPartialSlots - kMaxRedBlocks);
   hipError_t e = go<NonElec>({n_atoms, model, nc, span, box, r_cut * r_cut, p0, p1, cstart, cperm,
-                              (const double4*)spos, force, partial, list, nlist, cap}, nb, 0, s);
+                              (const double4*)spos, force, partial + prior, list, nlist, cap, skip_listed}, nb, 0, s);
   if (e != hipSuccess) return e;
   int nbb = 0;
   if (model == 2) {
     nbb = std::min(blocks_for(n_atoms, kBlock), kMaxRedBlocks);
-    e = go<Bonded>({n_atoms, box, p2, p3, p4, p5, pos, force, partial + nb}, nbb, 0, s);
+    e = go<Bonded>({n_atoms, box, p2, p3, p4, p5, pos, force, partial + prior + nb}, nbb, 0, s);
     if (e != hipSuccess) return e;
   }
-  return go<FinOther>({nb + nbb, partial, e_out}, 1, 0, s);
+  return go<FinOther>({prior + nb + nbb, partial, e_out}, 1, 0, s);
 }
 
 hipError_t launch_kinetic_log(int n_atoms, const double* vel, const double* mass, double mv2e,

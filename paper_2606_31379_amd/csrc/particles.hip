@@ -1001,7 +1001,11 @@ __device__ void NbrBuildCell::run(const Args& A, Grid G) {
 // skipped); otherwise the cell scan, for every atom (no lists, span 1: one
 // atom per wave) or for the atoms over capacity (span 64: each wave picks
 // them from 64 consecutive positions by ballot).
-template <bool LIST>
+// NE = 1 (MD steps on neighbour lists): the same pass over the list also
+// adds the non-electrostatic pair term (model 1: Born-Mayer repulsion
+// between all pairs; model 2: O-O Lennard-Jones), each shifted to zero at
+// r_cut, with its energy in nepart.
+template <bool LIST, int NE = 0>
 struct ShortRange {
   struct Args {
     int n_atoms, nc, excl_group, span;
@@ -1018,6 +1022,10 @@ struct ShortRange {
     // list + wi * cap, nlist[wi] of them
     const int *list, *nlist;
     int cap;
+    // NE: model, parameters (model 1: A, rho; model 2: eps, sigma), energy partials
+    int model;
+    double ne_p0, ne_p1;
+    double* nepart;
   };
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G);
@@ -1026,9 +1034,9 @@ struct ShortRange {
 // The short-range force on the atom at cell-order position `wave` (lanes
 // split its pairs, a fixed shuffle tree sums them) and its pair energy,
 // accumulated into each lane's en.
-template <bool LIST>
-__device__ __forceinline__ void sr_atom(const typename ShortRange<LIST>::Args& A, int wave, const double* tab,
-                                        PairQueue* Q, double& en, double* nf) {
+template <bool LIST, int NE>
+__device__ __forceinline__ void sr_atom(const typename ShortRange<LIST, NE>::Args& A, int wave, const double* tab,
+                                        PairQueue* Q, double& en, double* nf, double& ene, double ne_shift) {
   const int n_atoms = A.n_atoms, excl_group = A.excl_group;
   const double box = A.box, alpha = A.alpha, rc2 = A.rc2, k_e = A.k_e;
   const double* __restrict__ pos = A.pos;
@@ -1058,7 +1066,42 @@ __device__ __forceinline__ void sr_atom(const typename ShortRange<LIST>::Args& A
     fx += f * dx; fy += f * dy; fz += f * dz;
     en += 0.5 * qq * ec * inv_r;
   };
-  if constexpr (LIST)
+  if constexpr (LIST && NE != 0) {
+    // one pass over the list: the erfc pair and, where it applies, the
+    // non-electrostatic pair (model 2: O-O only; the atom is an O when its
+    // index is divisible by 3 and the entry's site flag marks an O partner)
+    const int model = A.model;
+    const double p0 = A.ne_p0, p1 = A.ne_p1;
+    const bool i_site = model == 1 || i % 3 == 0;
+    const int* ent = A.list + (size_t)wave * A.cap;
+    const int cnt = A.nlist[wave];
+    const double inv_b = 1.0 / box;
+    for (int k = lane; k < cnt; k += 64) {
+      const unsigned e = (unsigned)ent[k];
+      const double4 a = spos[e & kNbrIndex];
+      const double dx = min_img(xi - a.x, box, inv_b);
+      const double dy = min_img(yi - a.y, box, inv_b);
+      const double dz = min_img(zi - a.z, box, inv_b);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      if (!(r2 < rc2)) continue;
+      if (!(e & kNbrSameGroup)) pair(dx, dy, dz, r2, a.w);
+      if (i_site && (model == 1 || (e & kNbrSite))) {
+        double f;
+        if (model == 1) {
+          const double r = sqrt(r2);
+          const double v = p0 * exp(-r / p1);
+          f = v / p1 / r;
+          ene += 0.5 * (v - ne_shift);
+        } else {
+          const double sr2 = p1 * p1 / r2;
+          const double sr6 = sr2 * sr2 * sr2;
+          f = 24.0 * p0 * (2.0 * sr6 * sr6 - sr6) / r2;
+          ene += 0.5 * (4.0 * p0 * (sr6 * sr6 - sr6) - ne_shift);
+        }
+        fx += f * dx; fy += f * dy; fz += f * dz;
+      }
+    }
+  } else if constexpr (LIST)
     for_each_listed(A.list + (size_t)wave * A.cap, A.nlist[wave], xi, yi, zi, box, spos,
                     [&](unsigned e, double r2) { return r2 < rc2 && !(e & kNbrSameGroup); }, pair);
   else
@@ -1097,8 +1140,8 @@ __device__ __forceinline__ void sr_atom(const typename ShortRange<LIST>::Args& A
   }
 }
 
-template <bool LIST>
-__device__ void ShortRange<LIST>::run(const Args& A, Grid G) {
+template <bool LIST, int NE>
+__device__ void ShortRange<LIST, NE>::run(const Args& A, Grid G) {
   const int n_atoms = A.n_atoms;
   __shared__ double sh[kBlock / 64];
   __shared__ PairQueue queue[LIST ? 1 : kBlock / 64];
@@ -1106,13 +1149,22 @@ __device__ void ShortRange<LIST>::run(const Args& A, Grid G) {
   __shared__ double shf[3 * (kBlock / 64)];
   const int lane = threadIdx.x & 63;
   const int nwaves = G.g * (kBlock / 64);
-  double en = 0.0;
+  double en = 0.0, ene = 0.0;
   double nf[3] = {0.0, 0.0, 0.0};   // lane 0: net force of the wave's atoms
+  double ne_shift = 0.0;            // the non-electrostatic potential at r_cut
+  if (NE != 0) {
+    if (A.model == 1) {
+      ne_shift = A.ne_p0 * exp(-sqrt(A.rc2) / A.ne_p1);
+    } else {
+      const double s2 = A.ne_p1 * A.ne_p1 / A.rc2, s6 = s2 * s2 * s2;
+      ne_shift = 4.0 * A.ne_p0 * (s6 * s6 - s6);
+    }
+  }
   for (int k = threadIdx.x; k < A.erfc_n * (kErfcDeg + 1); k += kBlock) tab[k] = A.erfc_tab[k];
   __syncthreads();
   if constexpr (LIST) {
     for (int wave = (G.b * kBlock + threadIdx.x) >> 6; wave < n_atoms; wave += nwaves)
-      if (A.nlist[wave] <= A.cap) sr_atom<true>(A, wave, tab, nullptr, en, nf);
+      if (A.nlist[wave] <= A.cap) sr_atom<true, NE>(A, wave, tab, nullptr, en, nf, ene, ne_shift);
   } else {
     PairQueue* Q = &queue[threadIdx.x >> 6];
     const int span = A.span;
@@ -1123,23 +1175,28 @@ __device__ void ShortRange<LIST>::run(const Args& A, Grid G) {
       while (todo) {
         const int l = __ffsll((unsigned long long)todo) - 1;   // wave-uniform
         todo &= todo - 1;
-        sr_atom<false>(A, chunk * span + l, tab, Q, en, nf);
+        sr_atom<false, NE>(A, chunk * span + l, tab, Q, en, nf, ene, ne_shift);
       }
     }
   }
   en = wave_sum(en);
+  if (NE != 0) ene = wave_sum(ene);
+  __shared__ double she[kBlock / 64];
   if (lane == 0) {
     sh[threadIdx.x >> 6] = en;
+    if (NE != 0) she[threadIdx.x >> 6] = ene;
     for (int c = 0; c < 3; c++) shf[3 * (threadIdx.x >> 6) + c] = nf[c];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double s = 0.0, f[3] = {0.0, 0.0, 0.0};
+    double s = 0.0, se = 0.0, f[3] = {0.0, 0.0, 0.0};
     for (int k = 0; k < kBlock / 64; k++) {
       s += sh[k];
+      if (NE != 0) se += she[k];
       for (int c = 0; c < 3; c++) f[c] += shf[3 * k + c];
     }
     A.partial[G.b] = s;
+    if (NE != 0) A.nepart[G.b] = se;
     for (int c = 0; c < 3; c++) A.nfpart[3 * G.b + c] = f[c];
   }
 }
@@ -1295,29 +1352,40 @@ hipError_t launch_sr(int n_atoms, const double* pos, const double* qa, double bo
                      double r_cut, double k_e, int nc, int excl_group, const int* cstart,
                      const int* cperm, const void* spos, const double* erfc_tab, int erfc_n, double erfc_scale,
                      double* force, double e_self, double* energy_out, double* partial, double* nfpart, Ctl* ctl,
-                     hipStream_t s, const int* list, const int* nlist, int cap) {
+                     hipStream_t s, const int* list, const int* nlist, int cap, int ne_model, double ne_p0,
+                     double ne_p1, double* nepart, int* ne_written) {
   if (erfc_n < 1 || erfc_n > kErfcMaxIntervals) return hipErrorInvalidValue;
   const size_t lds = (size_t)erfc_n * (kErfcDeg + 1) * sizeof(double);
   const double rc2 = r_cut * r_cut;
+  if (ne_written) *ne_written = 0;
   if (!list) {
     const int nb = std::min(blocks_for((int64_t)n_atoms * 64, kBlock), kPartialSlots);
     hipError_t e = go<ShortRange<false>>({n_atoms, nc, excl_group, 1, box, alpha, rc2, k_e, pos, qa, cstart, cperm,
                                           (const double4*)spos, force, partial, nfpart, erfc_tab, erfc_n,
-                                          erfc_scale, nullptr, nullptr, 0}, nb, lds, s);
+                                          erfc_scale, nullptr, nullptr, 0, 0, 0.0, 0.0, nullptr}, nb, lds, s);
     if (e != hipSuccess) return e;
     return go<FinEnergy>({nb, e_self, partial, nfpart, force != nullptr, ctl, energy_out, 0}, 1, 0, s);
   }
-  // the lists, then the cell scan for the atoms over capacity; partials of
-  // the first kernel, then of the second
+  // the lists (with the non-electrostatic pair term when ne_model != 0),
+  // then the cell scan for the atoms over capacity; partials of the first
+  // kernel, then of the second
   const int nb = std::min(blocks_for((int64_t)n_atoms * 64, kBlock), kPartialSlots / 2);
-  hipError_t e = go<ShortRange<true>>({n_atoms, nc, excl_group, 1, box, alpha, rc2, k_e, pos, qa, cstart, cperm,
-                                       (const double4*)spos, force, partial, nfpart, erfc_tab, erfc_n, erfc_scale,
-                                       list, nlist, cap}, nb, lds, s);
+  hipError_t e;
+  if (ne_model != 0) {
+    e = go<ShortRange<true, 1>>({n_atoms, nc, excl_group, 1, box, alpha, rc2, k_e, pos, qa, cstart, cperm,
+                                 (const double4*)spos, force, partial, nfpart, erfc_tab, erfc_n, erfc_scale, list,
+                                 nlist, cap, ne_model, ne_p0, ne_p1, nepart}, nb, lds, s);
+    if (ne_written) *ne_written = nb;
+  } else {
+    e = go<ShortRange<true>>({n_atoms, nc, excl_group, 1, box, alpha, rc2, k_e, pos, qa, cstart, cperm,
+                              (const double4*)spos, force, partial, nfpart, erfc_tab, erfc_n, erfc_scale, list,
+                              nlist, cap, 0, 0.0, 0.0, nullptr}, nb, lds, s);
+  }
   if (e != hipSuccess) return e;
   const int nb2 = std::min(blocks_for((int64_t)(n_atoms + 63) / 64 * 64, kBlock), kPartialSlots / 2);
   e = go<ShortRange<false>>({n_atoms, nc, excl_group, 64, box, alpha, rc2, k_e, pos, qa, cstart, cperm,
                              (const double4*)spos, force, partial + nb, nfpart + 3 * nb, erfc_tab, erfc_n,
-                             erfc_scale, list, nlist, cap}, nb2, lds, s);
+                             erfc_scale, list, nlist, cap, 0, 0.0, 0.0, nullptr}, nb2, lds, s);
   if (e != hipSuccess) return e;
   return go<FinEnergy>({nb + nb2, e_self, partial, nfpart, force != nullptr, ctl, energy_out, 1}, 1, 0, s);
 }
