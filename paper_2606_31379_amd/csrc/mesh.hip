@@ -260,28 +260,25 @@ __device__ void Sigma<TQ>::run(const Args& A, Grid G) {
   const double* y2 = yb[ctl->yh2];
   double sv = 0.0, qmax = 0.0;
   const int l2 = __builtin_ctz(n), msk = n - 1;
-  // four consecutive points of one row per thread
-  march4(G, n, [&](int t) {
-    const int i0 = t & msk, j = (t >> l2) & msk, k = t >> (2 * l2);
+  // Verlet-predicted potential P = 2 phi^k - phi^{k-1} on four points of a row
+  auto P4 = [&](int a) {
+    const D4 u = ld4(pk, a), w = ld4(pkm1, a);
+    D4 r;
+#pragma unroll
+    for (int c = 0; c < 4; c++) r.v[c] = 2.0 * u.v[c] - w.v[c];
+    return r;
+  };
+  auto P1 = [&](int a) { return 2.0 * pk[a] - pkm1[a]; };
+  // sigma_p and the predicted y of four points from the P rows of the
+  // point and its y and z neighbours (unused on a cold solve)
+  auto point4 = [&](int t, int i0, int j, int k, const D4& own, const D4& ym, const D4& yp, const D4& zm,
+                    const D4& zp) {
     const D4 q4 = ld4q(qs, t);
     double sg[4];
 #pragma unroll
     for (int c = 0; c < 4; c++) sg[c] = q4.v[c];
     if (!cold) {
-      // Verlet-predicted potential P = 2 phi^k - phi^{k-1} on the row and its
-      // four neighbour rows, plus the two x neighbours beyond the vector
       const int row = t - i0;
-      const int rym = nat_idx(n, 0, (j - 1) & msk, k), ryp = nat_idx(n, 0, (j + 1) & msk, k);
-      const int rzm = nat_idx(n, 0, j, (k - 1) & msk), rzp = nat_idx(n, 0, j, (k + 1) & msk);
-      auto P4 = [&](int a) {
-        const D4 u = ld4(pk, a), w = ld4(pkm1, a);
-        D4 r;
-#pragma unroll
-        for (int c = 0; c < 4; c++) r.v[c] = 2.0 * u.v[c] - w.v[c];
-        return r;
-      };
-      auto P1 = [&](int a) { return 2.0 * pk[a] - pkm1[a]; };
-      const D4 own = P4(t), ym = P4(rym + i0), yp = P4(ryp + i0), zm = P4(rzm + i0), zp = P4(rzp + i0);
       const double xl = P1(row + ((i0 - 1) & msk)), xr = P1(row + ((i0 + 4) & msk));
 #pragma unroll
       for (int c = 0; c < 4; c++) {
@@ -311,7 +308,45 @@ __device__ void Sigma<TQ>::run(const Args& A, Grid G) {
       sv += sg[c];
       qmax = fmax(qmax, fabs(q4.v[c]));
     }
-  });
+  };
+  const D4 zero4{{0.0, 0.0, 0.0, 0.0}};
+  if (n >= 64) {
+    // the column walk of march4 with the z-neighbour rows of P kept in
+    // registers from plane to plane
+    const int JB = (4 * kBlock) >> l2, nj = n / JB, nz = G.g / nj, KB = n / nz;
+    const int jb = G.b % nj, zr = G.b / nj;
+    const int j = jb * JB + ((4 * (int)threadIdx.x) >> l2), i0 = (4 * (int)threadIdx.x) & msk;
+    const int jm = (j - 1) & msk, jp = (j + 1) & msk, k0 = zr * KB;
+    D4 zm = zero4, own = zero4;
+    if (!cold) {
+      zm = P4(nat_idx(n, i0, j, (k0 - 1) & msk));
+      own = P4(nat_idx(n, i0, j, k0));
+    }
+    for (int kk = 0; kk < KB; kk++) {
+      const int k = k0 + kk;
+      D4 zp = zero4, ym = zero4, yp = zero4;
+      if (!cold) {
+        zp = P4(nat_idx(n, i0, j, (k + 1) & msk));
+        ym = P4(nat_idx(n, i0, jm, k));
+        yp = P4(nat_idx(n, i0, jp, k));
+      }
+      point4(((k << l2) + j) * n + i0, i0, j, k, own, ym, yp, zm, zp);
+      zm = own;
+      own = zp;
+    }
+  } else {
+    // four consecutive points of one row per thread
+    march4(G, n, [&](int t) {
+      const int i0 = t & msk, j = (t >> l2) & msk, k = t >> (2 * l2);
+      if (cold) {
+        point4(t, i0, j, k, zero4, zero4, zero4, zero4, zero4);
+        return;
+      }
+      const int rym = nat_idx(n, 0, (j - 1) & msk, k), ryp = nat_idx(n, 0, (j + 1) & msk, k);
+      const int rzm = nat_idx(n, 0, j, (k - 1) & msk), rzp = nat_idx(n, 0, j, (k + 1) & msk);
+      point4(t, i0, j, k, P4(t), P4(rym + i0), P4(ryp + i0), P4(rzm + i0), P4(rzp + i0));
+    });
+  }
   double bs = block_sum(sv, sh);
   double bm = block_max(qmax, sh);
   if (threadIdx.x == 0) {
@@ -441,38 +476,31 @@ __device__ void Outer<T>::run(const Args& A, Grid G) {
   auto E1 = [&](int x, int j, int k) -> double {
     return (double)(((x + j + k) & 1) ? e1 : e0)[cs_index(g, x, j, k)];
   };
-  // four consecutive points of one row per thread
-  march4(G, n, [&](int t) {
-    const int i0 = t & msk, j = (t >> g.l2) & msk, k = t >> (2 * g.l2);
-    const int jm = (j - 1) & msk, jp = (j + 1) & msk, km = (k - 1) & msk, kp = (k + 1) & msk;
-    double r[4], yv[4];
-    const int row = t - i0;
-    // y of cycle c at the point, its four-point row neighbours and the two
-    // x-edge points: the stored y (cycle 0), or the previous cycle's y plus
-    // this cycle's correction
-    const double* yo = (c & 1) ? A.y0 : A.y1;   // cycle c - 1 (cycle 0: the predictor in y0)
-    const double* ys = c == 0 ? A.y0 : yo;
-    D4 own = ld4(ys, t), ym = ld4(ys, nat_idx(n, i0, jm, k)), yp = ld4(ys, nat_idx(n, i0, jp, k));
-    D4 zm = ld4(ys, nat_idx(n, i0, j, km)), zp = ld4(ys, nat_idx(n, i0, j, kp));
-    double xl = ys[row + ((i0 - 1) & msk)], xr = ys[row + ((i0 + 4) & msk)];
+  // y of cycle c on four consecutive points of a row: the stored y (cycle
+  // 0), or the previous cycle's y plus this cycle's correction
+  const double* yo = (c & 1) ? A.y0 : A.y1;   // cycle c - 1 (cycle 0: the predictor in y0)
+  const double* ys = c == 0 ? A.y0 : yo;
+  auto Y4 = [&](int i0, int j, int k) {
+    D4 v = ld4(ys, nat_idx(n, i0, j, k));
     if (c > 0) {
-      D4 eo, eym, eyp, ezm, ezp;
-      E4(j, k, i0, &eo);
-      E4(jm, k, i0, &eym);
-      E4(jp, k, i0, &eyp);
-      E4(j, km, i0, &ezm);
-      E4(j, kp, i0, &ezp);
-      xl += E1((i0 - 1) & msk, j, k);
-      xr += E1((i0 + 4) & msk, j, k);
+      D4 e;
+      E4(j, k, i0, &e);
 #pragma unroll
-      for (int q = 0; q < 4; q++) {
-        own.v[q] += eo.v[q];
-        ym.v[q] += eym.v[q];
-        yp.v[q] += eyp.v[q];
-        zm.v[q] += ezm.v[q];
-        zp.v[q] += ezp.v[q];
-      }
+      for (int q = 0; q < 4; q++) v.v[q] += e.v[q];
     }
+    return v;
+  };
+  auto Y1 = [&](int x, int j, int k) {
+    double v = ys[nat_idx(n, x, j, k)];
+    if (c > 0) v += E1(x, j, k);
+    return v;
+  };
+  // residual and new y of the four points at (i0.., j, k) from the y rows
+  // of the point, its y and z neighbours; stores y (c > 0) and r
+  auto point4 = [&](int t, int i0, int j, int k, const D4& own, const D4& ym, const D4& yp, const D4& zm,
+                    const D4& zp) {
+    const double xl = Y1((i0 - 1) & msk, j, k), xr = Y1((i0 + 4) & msk, j, k);
+    double r[4], yv[4];
     const D4 sg = ld4(sigma, t);
 #pragma unroll
     for (int q = 0; q < 4; q++) {
@@ -498,7 +526,33 @@ __device__ void Outer<T>::run(const Args& A, Grid G) {
       rmax = fmax(rmax, fabs(r[q]));
       ysum += yv[q];
     }
-  });
+  };
+  if (n >= 64) {
+    // the column walk of march4, with the z-neighbour rows kept in
+    // registers from plane to plane: each plane loads only its z+1 row and
+    // its y-neighbour rows (shared through the XCD's L2 with the workgroups
+    // of the adjacent rows)
+    const int JB = (4 * kBlock) >> g.l2, nj = n / JB, nz = G.g / nj, KB = n / nz;
+    const int jb = G.b % nj, zr = G.b / nj;
+    const int j = jb * JB + ((4 * (int)threadIdx.x) >> g.l2), i0 = (4 * (int)threadIdx.x) & msk;
+    const int jm = (j - 1) & msk, jp = (j + 1) & msk, k0 = zr * KB;
+    D4 zm = Y4(i0, j, (k0 - 1) & msk), own = Y4(i0, j, k0);
+    for (int kk = 0; kk < KB; kk++) {
+      const int k = k0 + kk;
+      const D4 zp = Y4(i0, j, (k + 1) & msk);
+      const D4 ym = Y4(i0, jm, k), yp = Y4(i0, jp, k);
+      point4(((k << g.l2) + j) * n + i0, i0, j, k, own, ym, yp, zm, zp);
+      zm = own;
+      own = zp;
+    }
+  } else {
+    // four consecutive points of one row per thread
+    march4(G, n, [&](int t) {
+      const int i0 = t & msk, j = (t >> g.l2) & msk, k = t >> (2 * g.l2);
+      const int jm = (j - 1) & msk, jp = (j + 1) & msk, km = (k - 1) & msk, kp = (k + 1) & msk;
+      point4(t, i0, j, k, Y4(i0, j, k), Y4(i0, jm, k), Y4(i0, jp, k), Y4(i0, j, km), Y4(i0, j, kp));
+    });
+  }
   double bm = block_max(rmax, sh);
   double bs = block_sum(ysum, sh);
   if (threadIdx.x == 0) {

@@ -382,14 +382,17 @@ struct Spread {
 template <typename TO, int TS, int P>
 __device__ void Spread<TO, TS, P>::run(const Args& A, Grid G) {
   // the assignment order is a template parameter: register arrays sized exactly
-  constexpr int V = TS * TS * TS, CH = kChunk, p = P, pw = 3 * P;
+  // each wave's tile copy holds z-planes of TS^2 + 6 points: the padding
+  // spreads a stencil's z-neighbour points over the LDS banks (a 4^3 or 5^3
+  // stencil's 64 lanes then meet at most 2 or 3 to a bank, 4 and 5 unpadded)
+  constexpr int V = TS * TS * TS, CH = kChunk, p = P, pw = 3 * P, SZ = TS * TS + 6, VP = TS * SZ;
   const int n = A.n, ntx = A.ntx;
   const int* __restrict__ start = A.start;
   const int* __restrict__ cls = A.cls;
   const int2* __restrict__ rb = A.rb;
   const double4* __restrict__ rq = A.rq;
   TO* __restrict__ q = A.q;
-  __shared__ T acc[kBlock / 64][V];
+  __shared__ T acc[kBlock / 64][VP];
   __shared__ T sw[CH * pw];      // [CH][3p] weights x | y | z
   __shared__ T sq[CH];
   __shared__ int sb[CH][3];      // stencil start relative to the tile
@@ -398,7 +401,7 @@ __device__ void Spread<TO, TS, P>::run(const Args& A, Grid G) {
   const int tx = t % ntx, ty = (t / ntx) % ntx, tz = t / (ntx * ntx);
   const int ox = tx * TS, oy = ty * TS, oz = tz * TS;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int i = threadIdx.x; i < (kBlock / 64) * V; i += kBlock) (&acc[0][0])[i] = T(0);
+  for (int i = threadIdx.x; i < (kBlock / 64) * VP; i += kBlock) (&acc[0][0])[i] = T(0);
   // the ranges: lane k = (d, c) of the first wave, d = k >> 3 the lower
   // neighbour, c = k & 7 the class; used when c contains d (all classes of
   // the tile's own bin; with one tile per axis, only the own bin)
@@ -506,7 +509,7 @@ __device__ void Spread<TO, TS, P>::run(const Args& A, Grid G) {
         }
         if ((unsigned)lx < (unsigned)TS && (unsigned)ly < (unsigned)TS && (unsigned)lz < (unsigned)TS) {
           c[it] = qi * wi[ax] * wi[p + ay] * wi[2 * p + az];
-          at[it] = (lz * TS + ly) * TS + lx;
+          at[it] = lz * SZ + ly * TS + lx;
         }
       }
     };
@@ -528,9 +531,9 @@ __device__ void Spread<TO, TS, P>::run(const Args& A, Grid G) {
     __syncthreads();
   }
   for (int i = threadIdx.x; i < V; i += kBlock) {
-    T s = acc[0][i];
-    for (int k = 1; k < kBlock / 64; k++) s += acc[k][i];
-    const int lx = i % TS, ly = (i / TS) % TS, lz = i / (TS * TS);
+    const int lx = i % TS, ly = (i / TS) % TS, lz = i / (TS * TS), a = lz * SZ + ly * TS + lx;
+    T s = acc[0][a];
+    for (int k = 1; k < kBlock / 64; k++) s += acc[k][a];
     q[nat_idx(n, ox + lx, oy + ly, oz + lz)] = (TO)s;
   }
 }
