@@ -2230,7 +2230,8 @@ hipError_t vcycle_impl(const LevelBufs* lv, int levels, int tail, int nu1, int n
     T *c0 = (T*)lv[l + 1].r0, *c1 = (T*)lv[l + 1].r1;
     P3MZ_LAUNCH(l == 0 ? launch_restrict<T, 1>(n, nu1 >= 1, e0, e1, r0, r1, c0, c1, ctl, s)
                        : launch_restrict<T, 0>(n, nu1 >= 1, e0, e1, r0, r1, c0, c1, ctl, s));
-    kt_end(KT_RESTRICT, l, 2.125 * ts * n3, s);
+    // red-only restriction: e0, e1, r0 read, the coarse right-hand side written
+    kt_end(KT_RESTRICT, l, (nu1 >= 1 ? 1.625 : 2.125) * ts * n3, s);
   }
   {
     const double nt3 = (double)lv[tail].n * lv[tail].n * lv[tail].n;
@@ -2296,7 +2297,7 @@ hipError_t one_kernel(int kid, const LevelBufs* lv, int levels, int tail, int nu
       return launch_sweep0<T, 1>(n, r0, r1, e0, e1, ctl, s);
     case KT_RESTRICT:
       if (tail == 0) return hipErrorInvalidValue;
-      *bytes = 2.125 * ts * n3;
+      *bytes = (nu1 >= 1 ? 1.625 : 2.125) * ts * n3;
       return launch_restrict<T, 1>(n, nu1 >= 1, e0, e1, r0, r1, (T*)lv[1].r0, (T*)lv[1].r1, ctl, s);
     case KT_PROLONG:
       if (tail == 0) return hipErrorInvalidValue;
