@@ -184,7 +184,8 @@ hipError_t launch_sub_scalar(int64_t count, const double* in, double* out, const
 hipError_t tail_configure(bool fp64, int n_tail, int levels_tail, size_t* lds_bytes);
 // Allows the smoothing kernels the LDS they need on an n^3 mesh.
 hipError_t smooth_configure();
-// Allows the fused-leg kernels their LDS.
+// Allows the fused-leg kernels and the shared-row column walk (sigma_p,
+// outer residual) their LDS.
 hipError_t fused_configure();
 
 // ---- molecular dynamics (md.hip) ----------------------------------------

@@ -216,17 +216,122 @@ __device__ __forceinline__ void march4(const Grid& G, int n, F f) {
   }
 }
 
-template <typename TQ>
-struct Sigma {
-  struct Args {
-    int n;
-    double h;
-    const TQ* qs;
-    const double *phi0, *phi1, *yb0, *yb1, *yb2;
-    double *sigma, *y, *partial;
-    const Ctl* ctl;
+// Column walk with the rows of a plane shared through LDS (meshes from
+// 256^3 up, single systems).  A workgroup of NT threads owns JB = 4 NT / n
+// consecutive rows (four points of one row per thread; a wave lies within one
+// row) of a band of KB z-planes and walks it plane after plane.  The rows of
+// planes k-1, k and k+1 at a thread's own points stay in registers; plane k's
+// JB rows plus one halo row on each side sit in LDS, where the y-neighbour
+// rows are read, and the x-neighbours at the ends of a thread's four points
+// come from the neighbouring lanes (from LDS at the ends of a wave).  Every
+// row, halo rows included, is loaded from memory once per workgroup, one
+// plane ahead of its use; a halo row is the neighbouring column's own row of
+// the same plane, loaded by it at about the same time.  The grid is
+// (n / JB) columns times nz z-bands; the LDS is two plane buffers of
+// (JB + 2) n doubles (dynamic, col_lds_bytes).  load(i0, j, k) returns the
+// four values at (i0.., j, k); point(t, i0, j, k, own, ym, yp, zm, zp, xl, xr)
+// consumes a plane's four points.  Every thread runs the same KB iterations,
+// each ending in one workgroup barrier.
+constexpr int kColThreads = 512;   // workgroup of the shared-row column walk
+constexpr int kColPerCu = 2;       // its workgroups per compute unit
+// Single systems (not recorded into a batch) from 256^3 up: a wave then lies
+// within one row and 2 (4 NT / n + 2) n doubles fit in LDS.
+inline bool col_walk_on(int n) { return n >= 256 && n <= 512 && !g_recorder; }
+template <int NT>
+__device__ __forceinline__ int col_rows(int n) { return (4 * NT) / n; }
+inline size_t col_lds_bytes(int nt, int n) { return 2 * (size_t)(4 * nt + 2 * n) * sizeof(double); }
+// Workgroups of the shared-row column walk: n / JB columns times z-bands,
+// about `per_cu` workgroups per compute unit.
+inline int col_grid(int nt, int n, int per_cu) {
+  const int jb = 4 * nt / n, nj = n / jb;
+  int nz = 1;
+  while (nz < n && nj * nz < 256 * per_cu) nz *= 2;
+  return nj * nz;
+}
+
+template <int NT, typename LoadF, typename PointF>
+__device__ __forceinline__ void col_walk(const Grid& G, int n, double* lds, LoadF load, PointF point) {
+  const int l2 = __builtin_ctz(n), msk = n - 1;
+  const int JB = col_rows<NT>(n), nj = n / JB, nz = G.g / nj, KB = n / nz;
+  const int jb = G.b % nj, zr = G.b / nj;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int jl = (4 * tid) >> l2, i0 = (4 * tid) & msk;
+  const int j0 = jb * JB, j = j0 + jl, k0 = zr * KB;
+  const int row_len = n;   // doubles per LDS row
+  const int buf_len = (JB + 2) * n;
+  // halo rows: threads [0, n/4) hold row j0 - 1 (LDS row 0), threads
+  // [n/4, n/2) row j0 + JB (LDS row JB + 1)
+  const bool halo = tid < (n >> 1);
+  const bool lower = tid < (n >> 2);
+  const int hrow = lower ? 0 : JB + 1;
+  const int hj = (lower ? j0 - 1 : j0 + JB) & msk;
+  auto put = [&](double* b, int row, int x, const D4& v) {
+    double2* p = reinterpret_cast<double2*>(b + row * row_len + x);
+    p[0] = make_double2(v.v[0], v.v[1]);
+    p[1] = make_double2(v.v[2], v.v[3]);
   };
-  static constexpr int kThreads = kBlock;
+  auto get = [&](const double* b, int row, int x) {
+    const double2* p = reinterpret_cast<const double2*>(b + row * row_len + x);
+    const double2 lo = p[0], hi = p[1];
+    return D4{{lo.x, lo.y, hi.x, hi.y}};
+  };
+  double* cur = lds;
+  double* nxt = lds + buf_len;
+  D4 zm = load(i0, j, (k0 - 1) & msk);
+  D4 own = load(i0, j, k0);
+  put(cur, jl + 1, i0, own);
+  if (halo) put(cur, hrow, i0, load(i0, hj, k0));
+  __syncthreads();
+  for (int kk = 0; kk < KB; kk++) {
+    const int k = k0 + kk, kp = (k + 1) & msk;
+    const D4 zp = load(i0, j, kp);
+    D4 hz{{0.0, 0.0, 0.0, 0.0}};
+    if (halo) hz = load(i0, hj, kp);
+    const D4 ym = get(cur, jl, i0), yp = get(cur, jl + 2, i0);
+    double xl = __shfl_up(own.v[3], 1, 64), xr = __shfl_down(own.v[0], 1, 64);
+    if (lane == 0) xl = cur[(jl + 1) * row_len + ((i0 - 1) & msk)];
+    if (lane == 63) xr = cur[(jl + 1) * row_len + ((i0 + 4) & msk)];
+    point(((k << l2) + j) * n + i0, i0, j, k, own, ym, yp, zm, zp, xl, xr);
+    put(nxt, jl + 1, i0, zp);
+    if (halo) put(nxt, hrow, i0, hz);
+    __syncthreads();
+    double* t = cur;
+    cur = nxt;
+    nxt = t;
+    zm = own;
+    own = zp;
+  }
+}
+
+// Partials of a reduction kernel at stride nbp (the count its consumers
+// read): this launch's G.g slots, and zeros (neutral for the max and the sum)
+// in the rest when its grid is smaller.
+__device__ __forceinline__ void put_partials(double* partial, int nbp, const Grid& G, double a, double b) {
+  if (threadIdx.x == 0) {
+    partial[G.b] = a;
+    partial[nbp + G.b] = b;
+  }
+  for (int s = G.g + G.b * (int)blockDim.x + (int)threadIdx.x; s < nbp; s += G.g * (int)blockDim.x) {
+    partial[s] = 0.0;
+    partial[nbp + s] = 0.0;
+  }
+}
+
+template <typename TQ>
+struct SigmaArgs {
+  int n;
+  double h;
+  const TQ* qs;
+  const double *phi0, *phi1, *yb0, *yb1, *yb2;
+  double *sigma, *y, *partial;
+  const Ctl* ctl;
+  int nbp;   // partial stride (>= the grid)
+};
+// NT > kBlock: the shared-row column walk (n >= 256)
+template <typename TQ, int NT = kBlock>
+struct Sigma {
+  using Args = SigmaArgs<TQ>;
+  static constexpr int kThreads = NT;
   __device__ static void run(const Args& A, Grid G);
 };
 // Four consecutive values of the smoothed charges, widened to FP64.
@@ -236,8 +341,8 @@ __device__ __forceinline__ D4 ld4q(const float* __restrict__ a, int t) {
   return D4{{(double)v.x, (double)v.y, (double)v.z, (double)v.w}};
 }
 
-template <typename TQ>
-__device__ void Sigma<TQ>::run(const Args& A, Grid G) {
+template <typename TQ, int NT>
+__device__ void Sigma<TQ, NT>::run(const Args& A, Grid G) {
   const int n = A.n;
   const double h = A.h;
   const TQ* __restrict__ qs = A.qs;
@@ -250,7 +355,7 @@ __device__ void Sigma<TQ>::run(const Args& A, Grid G) {
   double* __restrict__ y = A.y;
   double* __restrict__ partial = A.partial;
   const Ctl* ctl = A.ctl;
-  __shared__ double sh[kBlock / 64];
+  __shared__ double sh[NT / 64];
   const int cold = ctl->cold, m_eff = ctl->m_eff;
   const double* pk = ctl->k_idx ? phi1 : phi0;
   const double* pkm1 = ctl->k_idx ? phi0 : phi1;
@@ -270,16 +375,15 @@ __device__ void Sigma<TQ>::run(const Args& A, Grid G) {
   };
   auto P1 = [&](int a) { return 2.0 * pk[a] - pkm1[a]; };
   // sigma_p and the predicted y of four points from the P rows of the
-  // point and its y and z neighbours (unused on a cold solve)
+  // point and its y and z neighbours and the x-neighbours xl, xr of its
+  // first and last point (unused on a cold solve)
   auto point4 = [&](int t, int i0, int j, int k, const D4& own, const D4& ym, const D4& yp, const D4& zm,
-                    const D4& zp) {
+                    const D4& zp, double xl, double xr) {
     const D4 q4 = ld4q(qs, t);
     double sg[4];
 #pragma unroll
     for (int c = 0; c < 4; c++) sg[c] = q4.v[c];
     if (!cold) {
-      const int row = t - i0;
-      const double xl = P1(row + ((i0 - 1) & msk)), xr = P1(row + ((i0 + 4) & msk));
 #pragma unroll
       for (int c = 0; c < 4; c++) {
         const double xm = c == 0 ? xl : own.v[c - 1], xp = c == 3 ? xr : own.v[c + 1];
@@ -310,7 +414,20 @@ __device__ void Sigma<TQ>::run(const Args& A, Grid G) {
     }
   };
   const D4 zero4{{0.0, 0.0, 0.0, 0.0}};
-  if (n >= 64) {
+  // x-neighbours of the four points at t (row start t - i0)
+  auto xlr = [&](int t, int i0, double* xl, double* xr) {
+    *xl = *xr = 0.0;
+    if (!cold) {
+      *xl = P1(t - i0 + ((i0 - 1) & msk));
+      *xr = P1(t - i0 + ((i0 + 4) & msk));
+    }
+  };
+  if constexpr (NT > kBlock) {
+    extern __shared__ __align__(16) double col_lds[];
+    col_walk<NT>(G, n, col_lds, [&](int i0, int j, int k) { return cold ? zero4 : P4(nat_idx(n, i0, j, k)); },
+                 [&](int t, int i0, int j, int k, const D4& own, const D4& ym, const D4& yp, const D4& zm,
+                     const D4& zp, double xl, double xr) { point4(t, i0, j, k, own, ym, yp, zm, zp, xl, xr); });
+  } else if (n >= 64) {
     // the column walk of march4 with the z-neighbour rows of P kept in
     // registers from plane to plane
     const int JB = (4 * kBlock) >> l2, nj = n / JB, nz = G.g / nj, KB = n / nz;
@@ -330,7 +447,10 @@ __device__ void Sigma<TQ>::run(const Args& A, Grid G) {
         ym = P4(nat_idx(n, i0, jm, k));
         yp = P4(nat_idx(n, i0, jp, k));
       }
-      point4(((k << l2) + j) * n + i0, i0, j, k, own, ym, yp, zm, zp);
+      const int t = ((k << l2) + j) * n + i0;
+      double xl, xr;
+      xlr(t, i0, &xl, &xr);
+      point4(t, i0, j, k, own, ym, yp, zm, zp, xl, xr);
       zm = own;
       own = zp;
     }
@@ -339,20 +459,19 @@ __device__ void Sigma<TQ>::run(const Args& A, Grid G) {
     march4(G, n, [&](int t) {
       const int i0 = t & msk, j = (t >> l2) & msk, k = t >> (2 * l2);
       if (cold) {
-        point4(t, i0, j, k, zero4, zero4, zero4, zero4, zero4);
+        point4(t, i0, j, k, zero4, zero4, zero4, zero4, zero4, 0.0, 0.0);
         return;
       }
       const int rym = nat_idx(n, 0, (j - 1) & msk, k), ryp = nat_idx(n, 0, (j + 1) & msk, k);
       const int rzm = nat_idx(n, 0, j, (k - 1) & msk), rzp = nat_idx(n, 0, j, (k + 1) & msk);
-      point4(t, i0, j, k, P4(t), P4(rym + i0), P4(ryp + i0), P4(rzm + i0), P4(rzp + i0));
+      double xl, xr;
+      xlr(t, i0, &xl, &xr);
+      point4(t, i0, j, k, P4(t), P4(rym + i0), P4(ryp + i0), P4(rzm + i0), P4(rzp + i0), xl, xr);
     });
   }
   double bs = block_sum(sv, sh);
   double bm = block_max(qmax, sh);
-  if (threadIdx.x == 0) {
-    partial[G.b] = bs;
-    partial[G.g + G.b] = bm;
-  }
+  put_partials(partial, A.nbp, G, bs, bm);
 }
 
 // One workgroup: mean of sigma_p, max|q^s|, threshold; opens the step's solve.
@@ -398,26 +517,30 @@ __device__ void FinSigma::run(const Args& A, Grid) {
 // running mean of y and the stop decision.
 // ---------------------------------------------------------------------------
 template <typename T>
+struct OuterArgs {
+  int n, first;
+  const double* sigma;
+  double *y0, *y1;
+  const T *e0, *e1;
+  T *r0, *r1;
+  double* partial;
+  Ctl* ctl;
+  // first residual of a single system: sigma's partials (null: the
+  // control block already holds the step's mean, FinSigma)
+  const double* spart;
+  int tol_mode;
+  double tol;
+  int nbp;   // partial stride of this launch and of sigma's (>= the grid)
+};
+// NT > kBlock: the shared-row column walk (n >= 256)
+template <typename T, int NT = kBlock>
 struct Outer {
-  struct Args {
-    int n, first;
-    const double* sigma;
-    double *y0, *y1;
-    const T *e0, *e1;
-    T *r0, *r1;
-    double* partial;
-    Ctl* ctl;
-    // first residual of a single system: sigma's partials (null: the
-    // control block already holds the step's mean, FinSigma)
-    const double* spart;
-    int tol_mode;
-    double tol;
-  };
-  static constexpr int kThreads = kBlock;
+  using Args = OuterArgs<T>;
+  static constexpr int kThreads = NT;
   __device__ static void run(const Args& A, Grid G);
 };
-template <typename T>
-__device__ void Outer<T>::run(const Args& A, Grid G) {
+template <typename T, int NT>
+__device__ void Outer<T, NT>::run(const Args& A, Grid G) {
   const int n = A.n, first = A.first;
   const double* __restrict__ sigma = A.sigma;
   const T* __restrict__ e0 = A.e0;
@@ -426,7 +549,7 @@ __device__ void Outer<T>::run(const Args& A, Grid G) {
   T* __restrict__ r1 = A.r1;
   double* __restrict__ partial = A.partial;
   Ctl* ctl = A.ctl;
-  __shared__ double sh[kBlock / 64];
+  __shared__ double sh[NT / 64];
   __shared__ double s_mean;
   const CsGeo g(n);
   const int n3 = n * n * n, msk = n - 1;
@@ -435,7 +558,7 @@ __device__ void Outer<T>::run(const Args& A, Grid G) {
     // FinSigma's reduction in every workgroup (same split and tree, so the
     // same mean); the first workgroup opens the step's solve in the control
     // block
-    const int snb = G.g;
+    const int snb = A.nbp;
     const double tot = reduce_partials_sum(A.spart, snb, sh);
     const double mx = reduce_partials_max(A.spart + snb, snb, sh);
     if (threadIdx.x == 0) {
@@ -496,10 +619,10 @@ __device__ void Outer<T>::run(const Args& A, Grid G) {
     return v;
   };
   // residual and new y of the four points at (i0.., j, k) from the y rows
-  // of the point, its y and z neighbours; stores y (c > 0) and r
+  // of the point, its y and z neighbours and the x-neighbours xl, xr of its
+  // first and last point; stores y (c > 0) and r
   auto point4 = [&](int t, int i0, int j, int k, const D4& own, const D4& ym, const D4& yp, const D4& zm,
-                    const D4& zp) {
-    const double xl = Y1((i0 - 1) & msk, j, k), xr = Y1((i0 + 4) & msk, j, k);
+                    const D4& zp, double xl, double xr) {
     double r[4], yv[4];
     const D4 sg = ld4(sigma, t);
 #pragma unroll
@@ -527,7 +650,12 @@ __device__ void Outer<T>::run(const Args& A, Grid G) {
       ysum += yv[q];
     }
   };
-  if (n >= 64) {
+  if constexpr (NT > kBlock) {
+    extern __shared__ __align__(16) double col_lds[];
+    col_walk<NT>(G, n, col_lds, Y4,
+                 [&](int t, int i0, int j, int k, const D4& own, const D4& ym, const D4& yp, const D4& zm,
+                     const D4& zp, double xl, double xr) { point4(t, i0, j, k, own, ym, yp, zm, zp, xl, xr); });
+  } else if (n >= 64) {
     // the column walk of march4, with the z-neighbour rows kept in
     // registers from plane to plane: each plane loads only its z+1 row and
     // its y-neighbour rows (shared through the XCD's L2 with the workgroups
@@ -541,7 +669,8 @@ __device__ void Outer<T>::run(const Args& A, Grid G) {
       const int k = k0 + kk;
       const D4 zp = Y4(i0, j, (k + 1) & msk);
       const D4 ym = Y4(i0, jm, k), yp = Y4(i0, jp, k);
-      point4(((k << g.l2) + j) * n + i0, i0, j, k, own, ym, yp, zm, zp);
+      point4(((k << g.l2) + j) * n + i0, i0, j, k, own, ym, yp, zm, zp, Y1((i0 - 1) & msk, j, k),
+             Y1((i0 + 4) & msk, j, k));
       zm = own;
       own = zp;
     }
@@ -550,16 +679,14 @@ __device__ void Outer<T>::run(const Args& A, Grid G) {
     march4(G, n, [&](int t) {
       const int i0 = t & msk, j = (t >> g.l2) & msk, k = t >> (2 * g.l2);
       const int jm = (j - 1) & msk, jp = (j + 1) & msk, km = (k - 1) & msk, kp = (k + 1) & msk;
-      point4(t, i0, j, k, Y4(i0, j, k), Y4(i0, jm, k), Y4(i0, jp, k), Y4(i0, j, km), Y4(i0, j, kp));
+      point4(t, i0, j, k, Y4(i0, j, k), Y4(i0, jm, k), Y4(i0, jp, k), Y4(i0, j, km), Y4(i0, j, kp),
+             Y1((i0 - 1) & msk, j, k), Y1((i0 + 4) & msk, j, k));
     });
   }
   double bm = block_max(rmax, sh);
   double bs = block_sum(ysum, sh);
-  if (threadIdx.x == 0) {
-    partial[G.b] = bm;
-    partial[G.g + G.b] = bs;
-    if (G.b == 0) ctl->pending = c + 1;
-  }
+  put_partials(partial, A.nbp, G, bm, bs);
+  if (threadIdx.x == 0 && G.b == 0) ctl->pending = c + 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -590,7 +717,7 @@ __device__ __forceinline__ void stencil19(int n, int i, int j, int k, F v, doubl
 
 template <typename TQ>
 struct SigmaHO {
-  using Args = typename Sigma<TQ>::Args;
+  using Args = SigmaArgs<TQ>;
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G) {
     const int n = A.n, msk = n - 1, l2 = __builtin_ctz(n);
@@ -638,16 +765,13 @@ struct SigmaHO {
     });
     double bs = block_sum(sv, sh);
     double bm = block_max(qmax, sh);
-    if (threadIdx.x == 0) {
-      A.partial[G.b] = bs;
-      A.partial[G.g + G.b] = bm;
-    }
+    put_partials(A.partial, A.nbp, G, bs, bm);
   }
 };
 
 template <typename T>
 struct OuterHO {
-  using Args = typename Outer<T>::Args;
+  using Args = OuterArgs<T>;
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G) {
     const int n = A.n, first = A.first, msk = n - 1, l2 = __builtin_ctz(n);
@@ -658,7 +782,7 @@ struct OuterHO {
     const int n3 = n * n * n;
     double mean_sigma;
     if (first && A.spart) {
-      const int snb = G.g;
+      const int snb = A.nbp;
       const double tot = reduce_partials_sum(A.spart, snb, sh);
       const double mx = reduce_partials_max(A.spart + snb, snb, sh);
       if (threadIdx.x == 0) {
@@ -706,11 +830,8 @@ struct OuterHO {
     });
     double bm = block_max(rmax, sh);
     double bs = block_sum(ysum, sh);
-    if (threadIdx.x == 0) {
-      A.partial[G.b] = bm;
-      A.partial[G.g + G.b] = bs;
-      if (G.b == 0) ctl->pending = c + 1;
-    }
+    put_partials(A.partial, A.nbp, G, bm, bs);
+    if (threadIdx.x == 0 && G.b == 0) ctl->pending = c + 1;
   }
 };
 
@@ -2423,18 +2544,27 @@ hipError_t launch_sigma(int n, double h, bool qs32, const void* qs, const double
                         double tol, int tol_mode, double* partial, Ctl* ctl, hipStream_t s, bool finalize,
                         int stencil) {
   const int n3 = n * n * n, nb = red_blocks(n3 / 4);   // four points per thread
+  const float* q32 = (const float*)qs;
+  const double* q64 = (const double*)qs;
   if (stencil == 1) {
     if (qs32)
-      P3MZ_LAUNCH(go<SigmaHO<float>>({n, h, (const float*)qs, phi0, phi1, yb0, yb1, yb2, sigma, y, partial, ctl}, nb,
-                                     0, s));
+      P3MZ_LAUNCH(go<SigmaHO<float>>({n, h, q32, phi0, phi1, yb0, yb1, yb2, sigma, y, partial, ctl, nb}, nb, 0, s));
     else
-      P3MZ_LAUNCH(go<SigmaHO<double>>({n, h, (const double*)qs, phi0, phi1, yb0, yb1, yb2, sigma, y, partial, ctl}, nb,
-                                      0, s));
-  } else if (qs32)
-    P3MZ_LAUNCH(go<Sigma<float>>({n, h, (const float*)qs, phi0, phi1, yb0, yb1, yb2, sigma, y, partial, ctl}, nb, 0, s));
-  else
-    P3MZ_LAUNCH(go<Sigma<double>>({n, h, (const double*)qs, phi0, phi1, yb0, yb1, yb2, sigma, y, partial, ctl}, nb, 0,
-                                  s));
+      P3MZ_LAUNCH(go<SigmaHO<double>>({n, h, q64, phi0, phi1, yb0, yb1, yb2, sigma, y, partial, ctl, nb}, nb, 0, s));
+  } else if (col_walk_on(n)) {
+    const int grid = col_grid(kColThreads, n, kColPerCu);
+    const size_t lds = col_lds_bytes(kColThreads, n);
+    if (qs32)
+      P3MZ_LAUNCH(go<Sigma<float, kColThreads>>({n, h, q32, phi0, phi1, yb0, yb1, yb2, sigma, y, partial, ctl, nb},
+                                                grid, lds, s));
+    else
+      P3MZ_LAUNCH(go<Sigma<double, kColThreads>>({n, h, q64, phi0, phi1, yb0, yb1, yb2, sigma, y, partial, ctl, nb},
+                                                 grid, lds, s));
+  } else if (qs32) {
+    P3MZ_LAUNCH(go<Sigma<float>>({n, h, q32, phi0, phi1, yb0, yb1, yb2, sigma, y, partial, ctl, nb}, nb, 0, s));
+  } else {
+    P3MZ_LAUNCH(go<Sigma<double>>({n, h, q64, phi0, phi1, yb0, yb1, yb2, sigma, y, partial, ctl, nb}, nb, 0, s));
+  }
   if (!finalize) return hipSuccess;
   return go<FinSigma>({nb, n3, tol_mode, tol, partial, ctl}, 1, 0, s);
 }
@@ -2442,20 +2572,33 @@ hipError_t launch_sigma(int n, double h, bool qs32, const void* qs, const double
 hipError_t launch_outer(bool fp64, int n, int first, int max_cycles, const double* sigma, double* y0, double* y1,
                         const void* e0, const void* e1, void* r0, void* r1, double* partial, Ctl* ctl,
                         hipStream_t s, bool finalize, const double* spart, double tol, int tol_mode, int stencil) {
-  const int n3 = n * n * n, nb = red_blocks(n3 / 4);   // four points per thread (sigma's grid too)
+  const int n3 = n * n * n, nb = red_blocks(n3 / 4);   // four points per thread (sigma's partial count too)
   if (!first) spart = nullptr;
+  const double *d0 = (const double*)e0, *d1 = (const double*)e1;
+  const float *f0 = (const float*)e0, *f1 = (const float*)e1;
+  double *dr0 = (double*)r0, *dr1 = (double*)r1;
+  float *fr0 = (float*)r0, *fr1 = (float*)r1;
   if (stencil == 1 && fp64)
-    P3MZ_LAUNCH(go<OuterHO<double>>({n, first, sigma, y0, y1, (const double*)e0, (const double*)e1, (double*)r0,
-                                     (double*)r1, partial, ctl, spart, tol_mode, tol}, nb, 0, s));
+    P3MZ_LAUNCH(go<OuterHO<double>>(
+        {n, first, sigma, y0, y1, d0, d1, dr0, dr1, partial, ctl, spart, tol_mode, tol, nb}, nb, 0, s));
   else if (stencil == 1)
-    P3MZ_LAUNCH(go<OuterHO<float>>({n, first, sigma, y0, y1, (const float*)e0, (const float*)e1, (float*)r0,
-                                    (float*)r1, partial, ctl, spart, tol_mode, tol}, nb, 0, s));
-  else if (fp64)
-    P3MZ_LAUNCH(go<Outer<double>>({n, first, sigma, y0, y1, (const double*)e0, (const double*)e1, (double*)r0,
-                                   (double*)r1, partial, ctl, spart, tol_mode, tol}, nb, 0, s));
+    P3MZ_LAUNCH(go<OuterHO<float>>(
+        {n, first, sigma, y0, y1, f0, f1, fr0, fr1, partial, ctl, spart, tol_mode, tol, nb}, nb, 0, s));
+  else if (col_walk_on(n)) {
+    const int grid = col_grid(kColThreads, n, kColPerCu);
+    const size_t lds = col_lds_bytes(kColThreads, n);
+    if (fp64)
+      P3MZ_LAUNCH(go<Outer<double, kColThreads>>(
+          {n, first, sigma, y0, y1, d0, d1, dr0, dr1, partial, ctl, spart, tol_mode, tol, nb}, grid, lds, s));
+    else
+      P3MZ_LAUNCH(go<Outer<float, kColThreads>>(
+          {n, first, sigma, y0, y1, f0, f1, fr0, fr1, partial, ctl, spart, tol_mode, tol, nb}, grid, lds, s));
+  } else if (fp64)
+    P3MZ_LAUNCH(go<Outer<double>>(
+        {n, first, sigma, y0, y1, d0, d1, dr0, dr1, partial, ctl, spart, tol_mode, tol, nb}, nb, 0, s));
   else
-    P3MZ_LAUNCH(go<Outer<float>>({n, first, sigma, y0, y1, (const float*)e0, (const float*)e1, (float*)r0,
-                                  (float*)r1, partial, ctl, spart, tol_mode, tol}, nb, 0, s));
+    P3MZ_LAUNCH(go<Outer<float>>(
+        {n, first, sigma, y0, y1, f0, f1, fr0, fr1, partial, ctl, spart, tol_mode, tol, nb}, nb, 0, s));
   if (!finalize) return hipSuccess;
   return go<FinOuter>({max_cycles, nb, n3, partial, ctl}, 1, 0, s);
 }
@@ -2619,6 +2762,12 @@ hipError_t fused_configure() {
   P3MZ_LAUNCH((fused_allow<double, 0, 0>()));
   P3MZ_LAUNCH((fused_allow<double, 0, 1>()));
   P3MZ_LAUNCH((fused_allow<double, 1, 0>()));
+  // the shared-row column walk of sigma_p and the outer residual
+  const int col = (int)col_lds_bytes(kColThreads, 512);
+  P3MZ_LAUNCH((allow_lds<Sigma<float, kColThreads>>(col)));
+  P3MZ_LAUNCH((allow_lds<Sigma<double, kColThreads>>(col)));
+  P3MZ_LAUNCH((allow_lds<Outer<float, kColThreads>>(col)));
+  P3MZ_LAUNCH((allow_lds<Outer<double, kColThreads>>(col)));
   done = true;
   return hipSuccess;
 }
