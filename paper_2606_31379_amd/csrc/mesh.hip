@@ -1287,6 +1287,212 @@ __device__ void RestrictRed<T, FIN, SPEC>::run(const Args& A, Grid G) {
   }
 }
 
+// The red-only restriction as a column walk over fine z-planes (fine levels
+// from 256^3 up, single systems).  RestrictRed recomputes every fine red
+// residual for each coarse point whose 27-point stencil covers it, 3.4
+// times on average, each with its own neighbour loads; here a workgroup owns
+// JB coarse rows of a band of KB coarse planes and walks the fine planes
+// 2 K0 - 1 .. 2 (K0 + KB) - 1 once:
+//  * each thread owns W red points of one fine row (the workgroup's 2 JB
+//    fine rows 2 J0 .. 2 J0 + 2 JB - 1, plus the halo row 2 J0 - 1 taken by the
+//    first G_x = n / (2 W) threads) and keeps that row's black values of
+//    planes z-1, z, z+1 in registers;
+//  * plane z's black rows 2 J0 - 2 .. 2 J0 + 2 JB sit in LDS for the x- and
+//    y-neighbours, so each fine value is loaded once per workgroup;
+//  * the red residuals of plane z go to LDS, and the threads of the even
+//    fine rows (one per W coarse points of coarse row J) add the plane's three
+//    weighted rows to the running sums of coarse planes K (z = 2K - 1, 2K,
+//    2K + 1); a coarse plane is written when its last fine plane is done.
+// Per coarse point the terms are added in RestrictRed's order (planes, then
+// rows, ascending), each formed with its arithmetic, so the results agree
+// with it to the rounding of the contracted products.  One workgroup
+// barrier per fine plane; LDS holds two buffers of each kind.
+template <typename T>
+struct RestrictColGeo {
+  int nc, W, gx, JB, erows, rrows;
+  __host__ __device__ RestrictColGeo(int n, int nt) {
+    W = 16 / (int)sizeof(T);
+    nc = n / 2;
+    gx = nc / W;                // threads per fine row
+    JB = nt / (2 * gx);         // coarse rows per workgroup
+    erows = 2 * JB + 3;         // black rows 2 J0 - 2 .. 2 J0 + 2 JB
+    rrows = 2 * JB + 1;         // residual rows 2 J0 - 1 .. 2 J0 + 2 JB - 1
+  }
+  __host__ __device__ int lds_elems() const { return 2 * (erows + rrows) * nc; }
+};
+constexpr int kRestrictColThreads = 512;
+// Single systems (not recorded into a batch), fine levels 256^3 and 512^3.
+inline bool restrict_col_on(int n) { return n >= 256 && n <= 512 && !g_recorder; }
+
+template <typename T, int FIN>
+struct RestrictCol {
+  using Args = typename ResidRestrict<T, FIN, 0>::Args;
+  static constexpr int kThreads = kRestrictColThreads;
+  __device__ static void run(const Args& A, Grid G);
+};
+template <typename T, int FIN>
+__device__ void RestrictCol<T, FIN>::run(const Args& A, Grid G) {
+  constexpr int W = Vec<T>::W;
+  using V = typename Vec<T>::type;
+  if (A.ctl->done) return;
+  const int n = A.n, msk = n - 1;
+  const CsGeo g(n), gc(n >> 1);
+  const RestrictColGeo<T> cg(n, kThreads);
+  const int nc = cg.nc, gx = cg.gx, JB = cg.JB, cmsk = nc - 1;
+  const int nj = nc / JB, nz = G.g / nj, KB = nc / nz;
+  const int jb = G.b % nj, zr = G.b / nj;
+  const int J0 = jb * JB, K0 = zr * KB;
+  const int tid = threadIdx.x;
+  const int f = tid / gx, m0 = (tid % gx) * W;   // own fine row 2 J0 + f, red entries m0 .. m0 + W - 1
+  const bool halo = tid < gx;                     // also the residual row 2 J0 - 1
+  const bool top = tid >= gx && tid < 2 * gx;     // loads black row 2 J0 + 2 JB
+  extern __shared__ __align__(16) unsigned char rcol_lds[];
+  T* const ebuf = reinterpret_cast<T*>(rcol_lds);          // [2][erows][nc]
+  T* const rbuf = ebuf + 2 * cg.erows * nc;                 // [2][rrows][nc]
+  const T* __restrict__ e0 = A.e0;
+  const T* __restrict__ e1 = A.e1;
+  const T* __restrict__ r0 = A.r0;
+  const int yo = (2 * J0 + f) & msk, yh = (2 * J0 - 1) & msk;
+  const int yb = (2 * J0 - 2) & msk, yt = (2 * J0 + 2 * JB) & msk;
+  auto at = [&](const T* a, int y, int z) {
+    return *reinterpret_cast<const V*>(a + ((((z & msk) << g.l2) + y) << (g.l2 - 1)) + m0);
+  };
+  auto eput = [&](int buf, int ly, const V& v) {
+    *reinterpret_cast<V*>(ebuf + (buf * cg.erows + ly) * nc + m0) = v;
+  };
+  // red residuals of W points of fine row y (LDS black row ly) at plane z
+  auto rho_row = [&](int buf, int ly, int y, int z, const V& bzm, const V& bzp, T* rho) {
+    const T* row = ebuf + (buf * cg.erows + ly) * nc;
+    const int par = (y + z) & 1;
+    const V own = *reinterpret_cast<const V*>(row + m0);
+    const T edge = par ? row[(m0 + W) & cmsk] : row[(m0 - 1) & cmsk];
+    const V vym = *reinterpret_cast<const V*>(row - nc + m0), vyp = *reinterpret_cast<const V*>(row + nc + m0);
+    const V ev = at(e0, y, z), rv = at(r0, y, z);
+#pragma unroll
+    for (int q = 0; q < W; q++) {
+      const T xm = par ? vget<T>(own, q) : (q == 0 ? edge : vget<T>(own, q - 1));
+      const T xp = par ? (q == W - 1 ? edge : vget<T>(own, q + 1)) : vget<T>(own, q);
+      const T nb = ((xm + xp) + (vget<T>(vym, q) + vget<T>(vyp, q))) + (vget<T>(bzm, q) + vget<T>(bzp, q));
+      rho[q] = vget<T>(rv, q) - (nb - T(6) * vget<T>(ev, q));
+    }
+  };
+  const int zs = 2 * K0 - 1, ze = 2 * (K0 + KB) - 1;
+  // black values of the own (and halo) row at planes z - 1, z, z + 1
+  V om = at(e1, yo, zs - 1), oc = at(e1, yo, zs), hm{}, hc{};
+  eput(0, f + 2, oc);
+  if (halo) {
+    hm = at(e1, yh, zs - 1);
+    hc = at(e1, yh, zs);
+    eput(0, 1, hc);
+    eput(0, 0, at(e1, yb, zs));
+  }
+  if (top) eput(0, 2 * JB + 2, at(e1, yt, zs));
+  __syncthreads();
+  const bool coarse = (f & 1) == 0;   // threads of even fine rows: coarse row J0 + f / 2
+  const int Jl = f >> 1;
+  const T wt[3] = {T(0.25), T(0.5), T(0.25)};
+  T sk[W], sn[W];   // running sums of coarse planes K and K + 1
+#pragma unroll
+  for (int q = 0; q < W; q++) sk[q] = sn[q] = T(0);
+  int cur = 0;
+  for (int z = zs; z <= ze; z++) {
+    const int nxt = cur ^ 1;
+    const V op = at(e1, yo, z + 1);
+    V hp{};
+    if (halo) hp = at(e1, yh, z + 1);
+    T rho[W];
+    rho_row(cur, f + 2, yo, z, om, op, rho);
+    {
+      V rv;
+#pragma unroll
+      for (int q = 0; q < W; q++) vset<T>(rv, q, rho[q]);
+      *reinterpret_cast<V*>(rbuf + (cur * cg.rrows + f + 1) * nc + m0) = rv;
+    }
+    if (halo) {
+      T rh[W];
+      rho_row(cur, 1, yh, z, hm, hp, rh);
+      V rv;
+#pragma unroll
+      for (int q = 0; q < W; q++) vset<T>(rv, q, rh[q]);
+      *reinterpret_cast<V*>(rbuf + (cur * cg.rrows) * nc + m0) = rv;
+    }
+    // plane z + 1's black rows for the next step
+    eput(nxt, f + 2, op);
+    if (halo) {
+      eput(nxt, 1, hp);
+      eput(nxt, 0, at(e1, yb, z + 1));
+    }
+    if (top) eput(nxt, 2 * JB + 2, at(e1, yt, z + 1));
+    __syncthreads();
+    if (coarse) {
+      // fine rows 2J - 1, 2J, 2J + 1 of plane z: residual rows 2 Jl .. 2 Jl + 2
+      const int cz = z & 1 ? 1 : 0;   // odd z = 2K + 1: last plane of K, first of K + 1
+#pragma unroll
+      for (int b = -1; b <= 1; b++) {
+        const int y = (2 * (J0 + Jl) + b) & msk;
+        const int par = (y + z) & 1;
+        const T* rr = rbuf + (cur * cg.rrows + 2 * Jl + b + 1) * nc;
+        const V rv = *reinterpret_cast<const V*>(rr + m0);
+        T row[W];
+        if (par == 0) {
+#pragma unroll
+          for (int q = 0; q < W; q++) {
+            T r = T(0);
+            r += wt[1] * vget<T>(rv, q);
+            row[q] = r;
+          }
+        } else {
+          const T re = rr[(m0 - 1) & cmsk];
+#pragma unroll
+          for (int q = 0; q < W; q++) {
+            T r = T(0);
+            r += wt[0] * (q == 0 ? re : vget<T>(rv, q - 1));
+            r += wt[2] * vget<T>(rv, q);
+            row[q] = r;
+          }
+        }
+        if (cz) {
+          if (z > zs) {
+            const T w = wt[b + 1] * wt[2];
+#pragma unroll
+            for (int q = 0; q < W; q++) sk[q] += w * row[q];
+          }
+          if (z < ze) {
+            const T w = wt[b + 1] * wt[0];
+#pragma unroll
+            for (int q = 0; q < W; q++) sn[q] += w * row[q];
+          }
+        } else {
+          const T w = wt[b + 1] * wt[1];
+#pragma unroll
+          for (int q = 0; q < W; q++) sk[q] += w * row[q];
+        }
+      }
+      if (cz) {
+        if (z > zs) {
+          const int K = (z - 1) >> 1, J = J0 + Jl;
+#pragma unroll
+          for (int q = 0; q < W; q++) {
+            const int I = m0 + q;
+            T* out = ((I + J + K) & 1) ? A.rc1 : A.rc0;
+            out[cs_index(gc, I, J, K)] = T(4) * sk[q];
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < W; q++) {
+          sk[q] = sn[q];
+          sn[q] = T(0);
+        }
+      }
+    }
+    om = oc;
+    oc = op;
+    hm = hc;
+    hc = hp;
+    cur = nxt;
+  }
+}
+
 // Trilinear interpolation of the coarse correction (colour-split, geometry
 // gc) at fine point (x,y,z).
 template <typename T>
@@ -2211,6 +2417,14 @@ hipError_t launch_restrict(int n, int red_only, const T* e0, const T* e1, const 
                            Ctl* ctl, hipStream_t s) {
   const int nc = n / 2;
   const int nb = blocks_for(nc * nc * nc, ResidRestrict<T, FIN, 0>::kThreads);
+  if (red_only && restrict_col_on(n)) {
+    const RestrictColGeo<T> cg(n, kRestrictColThreads);
+    const int nj = nc / cg.JB;
+    int nz = 1;
+    while (nz < nc && nj * nz < 512) nz *= 2;
+    return go<RestrictCol<T, FIN>>({n, red_only, e0, e1, r0, r1, rc0, rc1, ctl}, nj * nz,
+                                   (size_t)cg.lds_elems() * sizeof(T), s);
+  }
   if (red_only) {
     const int nbv = blocks_for(nc * nc * nc / Vec<T>::W, RestrictRed<T, FIN, 0>::kThreads);
     if (speculate(n)) return go<RestrictRed<T, FIN, 1>>({n, red_only, e0, e1, r0, r1, rc0, rc1, ctl}, nbv, 0, s);
@@ -2768,6 +2982,13 @@ hipError_t fused_configure() {
   P3MZ_LAUNCH((allow_lds<Sigma<double, kColThreads>>(col)));
   P3MZ_LAUNCH((allow_lds<Outer<float, kColThreads>>(col)));
   P3MZ_LAUNCH((allow_lds<Outer<double, kColThreads>>(col)));
+  // the column-walk restriction
+  const int rf = RestrictColGeo<float>(512, kRestrictColThreads).lds_elems() * 4;
+  const int rd = RestrictColGeo<double>(512, kRestrictColThreads).lds_elems() * 8;
+  P3MZ_LAUNCH((allow_lds<RestrictCol<float, 0>>(rf)));
+  P3MZ_LAUNCH((allow_lds<RestrictCol<float, 1>>(rf)));
+  P3MZ_LAUNCH((allow_lds<RestrictCol<double, 0>>(rd)));
+  P3MZ_LAUNCH((allow_lds<RestrictCol<double, 1>>(rd)));
   done = true;
   return hipSuccess;
 }
