@@ -95,19 +95,44 @@ __device__ void Smooth<T, AXIS, W, R>::run(const Args& A, Grid G) {
   const int i_seg = seg * S;
   size_t row0 = 0;
   int x0 = 0, o = 0;
+  // Staging: the loads of a batch are all issued before the first LDS
+  // store, so their memory round trips overlap (a load followed at once by
+  // its store would wait for each in turn).
   if (AXIS == 0) {
     row0 = (size_t)grp * W;
-    for (int r = 0; r < W; r++)
-      for (int k = tid; k < L; k += kBlock) buf[r * ld + k] = in[(row0 + r) * n + ((i_seg + k - half) & msk)];
+    // one position k of all W lines per batch
+    for (int kc = 0; kc < L; kc += kBlock) {
+      const int k = kc + tid;
+      const bool ok = k < L;
+      const size_t src = (size_t)((i_seg + k - half) & msk);
+      T v[W];
+#pragma unroll
+      for (int r = 0; r < W; r++) v[r] = ok ? in[(row0 + r) * n + src] : T(0);
+      if (ok) {
+#pragma unroll
+        for (int r = 0; r < W; r++) buf[r * ld + k] = v[r];
+      }
+    }
   } else {
     const int ncol = n / W;
     x0 = (grp % ncol) * W;
     o = grp / ncol;
-    for (int e = tid; e < L * W; e += kBlock) {
-      const int k = e / W, c = e & (W - 1);
-      const int t = (i_seg + k - half) & msk;
-      const size_t a = AXIS == 1 ? ((size_t)o * n + t) * n + x0 + c : ((size_t)t * n + o) * n + x0 + c;
-      buf[k * ld + c] = in[a];
+    constexpr int B = 8;   // elements per thread and batch
+    for (int e0 = tid; e0 < L * W; e0 += B * kBlock) {
+      T v[B];
+#pragma unroll
+      for (int u = 0; u < B; u++) {
+        const int e = e0 + u * kBlock;
+        const int k = e / W, c = e & (W - 1);
+        const int t = (i_seg + k - half) & msk;
+        const size_t a = AXIS == 1 ? ((size_t)o * n + t) * n + x0 + c : ((size_t)t * n + o) * n + x0 + c;
+        v[u] = e < L * W ? in[a] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < B; u++) {
+        const int e = e0 + u * kBlock;
+        if (e < L * W) buf[(e / W) * ld + (e & (W - 1))] = v[u];
+      }
     }
   }
   __syncthreads();
@@ -1602,6 +1627,96 @@ __device__ void ProlongBlack<T, FIN, SPEC>::run(const Args& A, Grid G) {
   *reinterpret_cast<V*>(e1 + t) = out;
 }
 
+// ProlongBlack from 256^3 up: each thread walks kProlongPlanes fine z-planes
+// of its W black points, keeping the coarse rows of the two coarse planes it
+// interpolates between in registers, so each coarse row is loaded once per
+// two fine planes instead of four times per plane.  Per point the terms are
+// those of prolong_black_vec in the same order (the same rows, weights and
+// exact zeros), so the result is bitwise the same.
+constexpr int kProlongPlanes = 16;
+template <typename T, int FIN>
+struct ProlongCol {
+  using Args = typename ProlongBlack<T, FIN, 0>::Args;
+  static constexpr int kThreads = kBlock;
+  __device__ static void run(const Args& A, Grid G);
+};
+template <typename T, int FIN>
+__device__ void ProlongCol<T, FIN>::run(const Args& A, Grid G) {
+  constexpr int W = Vec<T>::W;
+  using V = typename Vec<T>::type;
+  if (A.ctl->done) return;
+  const int n = A.n;
+  T* __restrict__ e1 = A.e1;
+  const T* __restrict__ ec0 = A.ec0;
+  const T* __restrict__ ec1 = A.ec1;
+  const CsGeo g(n), gc(n >> 1);
+  const int per_plane = g.plane / W;                  // threads of one fine plane
+  const int tp = (G.b * kBlock + threadIdx.x);
+  const int band = tp / per_plane, u = tp % per_plane;
+  const int m0 = (u * W) & (g.hn - 1), j = (u * W) >> (g.l2 - 1);
+  const int k0 = band * kProlongPlanes;
+  if (k0 >= n) return;
+  const int cm = gc.n - 1, y0 = j >> 1;
+  const int ys[2] = {y0, (j & 1) ? ((y0 + 1) & cm) : y0};
+  const T hy = (j & 1) ? T(0.5) : T(1);
+  const T wy[2] = {hy, (j & 1) ? hy : T(0)};
+  // coarse values at X = m0 .. m0 + W of rows ys[0], ys[1] of coarse plane Z
+  auto load_plane = [&](int Z, T (*cv)[W + 1]) {
+#pragma unroll
+    for (int b = 0; b < 2; b++) {
+      const int Y = ys[b];
+      const int crow = ((Z << gc.l2) + Y) << (gc.l2 - 1);
+#pragma unroll
+      for (int q = 0; q <= W; q++) {
+        const int X = (m0 + q) & cm;
+        cv[b][q] = (((X + Y + Z) & 1) ? ec1 : ec0)[crow + (X >> 1)];
+      }
+    }
+  };
+  T lo[2][W + 1], hi[2][W + 1];   // coarse planes k >> 1 and (k >> 1) + 1
+  load_plane((k0 >> 1) & cm, lo);
+  for (int kk = 0; kk < kProlongPlanes; kk++) {
+    const int k = k0 + kk;
+    if ((k & 1) == 0) {
+      if (kk > 0) {
+#pragma unroll
+        for (int b = 0; b < 2; b++)
+#pragma unroll
+          for (int q = 0; q <= W; q++) lo[b][q] = hi[b][q];
+      }
+      load_plane(((k >> 1) + 1) & cm, hi);
+    } else if (kk == 0) {
+      load_plane(((k >> 1) + 1) & cm, hi);
+    }
+    const int t = ((k << g.l2) + j) * g.hn + m0;
+    const int sx = (1 + j + k) & 1;
+    const T hx = sx ? T(0.5) : T(1), hz = (k & 1) ? T(0.5) : T(1);
+    const T wz[2] = {hz, (k & 1) ? hz : T(0)};
+    const T wx1 = sx ? T(1) : T(0);
+    T acc[W];
+#pragma unroll
+    for (int q = 0; q < W; q++) acc[q] = T(0);
+#pragma unroll
+    for (int c = 0; c < 2; c++)
+#pragma unroll
+      for (int b = 0; b < 2; b++) {
+        // the second z entry of an even fine plane is the first coarse plane again (weight 0)
+        const T* cv = (c == 1 && (k & 1)) ? hi[b] : lo[b];
+        const T w = hx * wy[b] * wz[c];
+#pragma unroll
+        for (int q = 0; q < W; q++) {
+          acc[q] += w * cv[q];
+          acc[q] += (w * wx1) * cv[q + 1];
+        }
+      }
+    const V old = *reinterpret_cast<const V*>(e1 + t);
+    V out;
+#pragma unroll
+    for (int q = 0; q < W; q++) vset<T>(out, q, vget<T>(old, q) + acc[q]);
+    *reinterpret_cast<V*>(e1 + t) = out;
+  }
+}
+
 template <typename T>
 struct ProlongAdd {
   struct Args {
@@ -2435,6 +2550,9 @@ hipError_t launch_restrict(int n, int red_only, const T* e0, const T* e1, const 
 }
 template <typename T, int FIN>
 hipError_t launch_prolong_black(int n, T* e1, const T* c0, const T* c1, Ctl* ctl, hipStream_t s) {
+  if (n >= 256 && !g_recorder)
+    return go<ProlongCol<T, FIN>>({n, e1, c0, c1, ctl}, blocks_for((int64_t)n * n / 2 / Vec<T>::W * (n / kProlongPlanes),
+                                                                    kBlock), 0, s);
   if (speculate(n)) return go<ProlongBlack<T, FIN, 1>>({n, e1, c0, c1, ctl}, sweep_blocks<T>(n), 0, s);
   return go<ProlongBlack<T, FIN, 0>>({n, e1, c0, c1, ctl}, sweep_blocks<T>(n), 0, s);
 }
