@@ -157,7 +157,8 @@ def autotune_schedule(torch, P, w, system, precision, warmup, n_frames=8):
         P.p3mz_load_state(ctx, blob)
         r = P.p3mz_autotune(ctx, frames.data_ptr(), n_frames, stream)
         cands = [dict(nu_pre=r.cand_nu_pre[k], nu_post=r.cand_nu_post[k], ms=r.cand_ms[k],
-                      cycles=r.cand_cycles[k]) for k in range(r.n_candidates)]
+                      cycles=r.cand_cycles[k], ms_cycle=r.cand_ms_cycle[k], cycles_frac=r.cand_cycles_frac[k],
+                      expected_ms=r.cand_expected_ms[k]) for k in range(r.n_candidates)]
         return dict(nu_pre=r.nu_pre, nu_post=r.nu_post, smooth_tile=r.smooth_tile, ms_best=r.ms_best,
                     ms_default=r.ms_default, ms_smooth=r.ms_smooth, frames=n_frames, candidates=cands)
     finally:

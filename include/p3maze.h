@@ -362,15 +362,22 @@ typedef struct {
   double ms_default;         /* the same for the default (2, 2)                        */
   double ms_smooth;          /* three smoothing passes with the chosen shape           */
   int32_t cand_nu_pre[16], cand_nu_post[16], cand_cycles[16];
-  double cand_ms[16];
+  double cand_ms[16];         /* mean measured mesh-step milliseconds per frame          */
+  double cand_ms_cycle[16];   /* milliseconds of one V-cycle plus the outer residual      */
+  double cand_cycles_frac[16];   /* mean fractional cycle count (residual interpolated)   */
+  double cand_expected_ms[16];   /* the criterion: cand_ms corrected to the expected count */
 } p3mz_tune_result;
 
 /* Autotuner.  Times the smoothing launch shapes back to back, then every
  * candidate V-cycle schedule by time to tolerance: each candidate restarts
  * from the context's current history and runs mesh steps on the caller's
  * frames_dev [n_frames][n_atoms][3] (1 <= n_frames <= 64, e.g. the next
- * positions of a trajectory), and the schedule with the least mean
- * mesh-step time wins.  The context is left with its history unchanged and
+ * positions of a trajectory).  A step's cycle count is its fractional count
+ * X (where the residual, interpolated geometrically within the last cycle,
+ * crosses the threshold) rounded up, so over a trajectory it averages about
+ * mean X + 1/2; the measured mean mesh-step time is corrected to that count
+ * with the candidate's time per cycle (one V-cycle and the outer residual),
+ * and the schedule with the least corrected time wins.  The context is left with its history unchanged and
  * the chosen schedule applied; the choice is stored in the tuning cache
  * (JSON; path from the environment variable P3MZ_TUNE_CACHE, default
  * $HOME/.cache/p3maze/tune.json) under (device, mesh, order, precision),

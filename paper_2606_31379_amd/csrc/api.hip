@@ -8,6 +8,7 @@
 #include <sys/stat.h>
 
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -1832,33 +1833,78 @@ p3mz_status p3mz_autotune(p3mz_ctx* ctx, const double* frames_dev, int32_t n_fra
   const bool timing_0 = ctx->timing;
   const bool have_force_0 = ctx->md_have_force;
   P3MZ_TRY(p3mz_set_timing(ctx, 1));
+  // A frame's cycle count is the fractional count X at which the residual
+  // crosses the threshold, rounded up; a few frames can show two schedules
+  // with equal counts where one crosses just in time and the other with a
+  // margin.  The expected count over a trajectory is E[ceil X] ~ mean X + 1/2
+  // (fractional parts spread over [0, 1)), so each candidate's measured time
+  // is corrected by (mean X + 1/2 - mean count) times its measured time per
+  // cycle (one V-cycle plus the outer residual, launched back to back).
+  // X interpolates log(residual) within the last cycle: with C cycles,
+  // X = C - 1 + log(res[C-1] / thresh) / log(res[C-1] / res[C]).
+  hipEvent_t c0, c1;
+  P3MZ_HIP_TRY(hipEventCreate(&c0));
+  P3MZ_HIP_TRY(hipEventCreate(&c1));
   int best = 0;
   for (int k = 0; k < ncand; k++) {
     P3MZ_TRY(p3mz_set_schedule(ctx, cand[k][0], cand[k][1], best_tile));
-    double total = 0.0;
+    double total = 0.0, xsum = 0.0;
     int cycles = 0;
     for (int pass = 0; pass < 2; pass++) {   // the first pass captures the graphs
       P3MZ_TRY(p3mz_load_state(ctx, blob.data(), bytes));
       total = 0.0;
+      xsum = 0.0;
       cycles = 0;
       for (int f = 0; f < n_frames; f++) {
         p3mz_status st = compute_step(ctx, frames_dev + (size_t)3 * ctx->n_atoms * f, nullptr, nullptr, s);
         if (st < 0) return st;
         total += ctx->st.ms_mesh;
-        cycles += ctx->st.cycles;
+        const int C = ctx->st.cycles;
+        cycles += C;
+        double x = (double)C;
+        if (C >= 1) {
+          const double a = ctx->st.res_hist[C - 1], b = ctx->st.res_hist[C], t = ctx->st.thresh;
+          if (a > t && b > 0.0 && b < a) x = (double)(C - 1) + std::min(1.0, std::log(a / t) / std::log(a / b));
+        }
+        xsum += x;
       }
+    }
+    // time per cycle: a V-cycle and the outer residual on the last frame's
+    // level data (scratch of the step; the history is restored below)
+    const LevelBufs& f0 = ctx->lv[0];
+    const int reps = 4;
+    float cyc_ms = 0.f;
+    for (int pass = 0; pass < 2; pass++) {   // the first pass warms up
+      P3MZ_HIP_TRY(hipEventRecord(c0, s));
+      for (int r = 0; r < reps; r++) {
+        P3MZ_HIP_TRY(launch_set_ctl_open(ctx->d_ctl, s));
+        P3MZ_HIP_TRY(launch_vcycle(ctx->fp64, ctx->lv, ctx->pl.levels, ctx->pl.tail, ctx->nu1, ctx->nu2,
+                                   ctx->d_green, ctx->d_ctl, s, nullptr));
+        P3MZ_HIP_TRY(launch_outer(ctx->fp64, n, 0, ctx->P.max_cycles, ctx->d_sigma, ctx->d_y[0], ctx->d_y[1], f0.e0,
+                                  f0.e1, f0.r0, f0.r1, ctx->d_partial, ctx->d_ctl, s, false, nullptr, 0.0, 0,
+                                  ctx->P.stencil));
+      }
+      P3MZ_HIP_TRY(hipEventRecord(c1, s));
+      P3MZ_HIP_TRY(hipEventSynchronize(c1));
+      P3MZ_HIP_TRY(hipEventElapsedTime(&cyc_ms, c0, c1));
     }
     out->cand_nu_pre[k] = cand[k][0];
     out->cand_nu_post[k] = cand[k][1];
     out->cand_ms[k] = total / n_frames;
     out->cand_cycles[k] = cycles;
-    if (out->cand_ms[k] < out->cand_ms[best]) best = k;
+    out->cand_ms_cycle[k] = cyc_ms / reps;
+    out->cand_cycles_frac[k] = xsum / n_frames;
+    out->cand_expected_ms[k] =
+        out->cand_ms[k] + out->cand_ms_cycle[k] * (out->cand_cycles_frac[k] + 0.5 - (double)cycles / n_frames);
+    if (out->cand_expected_ms[k] < out->cand_expected_ms[best]) best = k;
   }
+  (void)hipEventDestroy(c0);
+  (void)hipEventDestroy(c1);
   out->n_candidates = ncand;
   out->nu_pre = cand[best][0];
   out->nu_post = cand[best][1];
-  out->ms_best = out->cand_ms[best];
-  out->ms_default = out->cand_ms[0];
+  out->ms_best = out->cand_expected_ms[best];
+  out->ms_default = out->cand_expected_ms[0];
   // restore the history, apply the choice and store it
   P3MZ_TRY(p3mz_load_state(ctx, blob.data(), bytes));
   P3MZ_TRY(p3mz_set_timing(ctx, timing_0));

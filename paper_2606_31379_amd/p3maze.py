@@ -76,7 +76,9 @@ class p3mz_tune_result(C.Structure):
     _fields_ = [("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("smooth_tile", C.c_int32),
                 ("n_candidates", C.c_int32), ("ms_best", C.c_double), ("ms_default", C.c_double),
                 ("ms_smooth", C.c_double), ("cand_nu_pre", C.c_int32 * 16), ("cand_nu_post", C.c_int32 * 16),
-                ("cand_cycles", C.c_int32 * 16), ("cand_ms", C.c_double * 16)]
+                ("cand_cycles", C.c_int32 * 16), ("cand_ms", C.c_double * 16),
+                ("cand_ms_cycle", C.c_double * 16), ("cand_cycles_frac", C.c_double * 16),
+                ("cand_expected_ms", C.c_double * 16)]
 
 
 SMOOTH_TILES = 7
