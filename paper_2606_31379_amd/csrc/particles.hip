@@ -351,18 +351,24 @@ __device__ void SortBins::run(const Args& A, Grid G) {
   }
 }
 
-// Owner-computes spread.  One workgroup per TS^3 tile of the mesh; atoms are
-// keyed by the tile holding their first stencil index (p <= TS, so a
-// stencil reaches at most the next tile along each axis).  The atoms that
-// reach the tile are those of its own bin and, from the bin of the tile d
-// below it (d in {0,1}^3), those whose class (the faces their stencil
-// crosses) contains d: at most 27 contiguous ranges of class-sorted bins,
-// staged in LDS in chunks in a fixed order (ranges, then positions), one
-// atom per thread, which also forms the atom's B-spline weights.  Each wave
-// then adds whole atoms from LDS, one stencil point per lane, into its own
-// LDS copy of the tile (lanes of one atom touch distinct points); the four
-// wave copies are summed in a fixed order.  No global atomics,
-// bitwise-reproducible.  The sums are formed in FP64; TO is the stored
+// Owner-computes spread.  The mesh is cut into TS^3 tiles; atoms are keyed
+// by the tile holding their first stencil index (p <= TS, so a stencil
+// reaches at most the next tile along each axis).  The atoms that reach a
+// tile are those of its own bin and, from the bin of the tile d below it
+// (d in {0,1}^3), those whose class (the faces their stencil crosses)
+// contains d: at most 27 contiguous ranges of class-sorted bins.
+//
+// One wave per tile, one lane per (x, y) column of it, the column's TS
+// values held in registers.  The tile's candidate atoms are staged in the
+// wave's part of LDS in chunks of 64 (ranges, then positions), one atom per
+// lane, which also forms the atom's B-spline weights: q w_x and w_y, and w_z
+// laid out over the tile's TS z-positions (zero where the stencil does not
+// reach); the lanes then walk the staged atoms in order and every lane whose
+// column the atom's stencil covers adds the atom's terms ((q w_x) w_y) w_z to
+// its column (exact zeros elsewhere along z).  Each mesh value is a sum in a fixed order (the candidates' order)
+// formed in one register: no atomics of any kind, bitwise reproducible, and
+// the tile is written once.  The next chunk's records are loaded while the
+// current chunk is walked.  The sums are formed in FP64; TO is the stored
 // precision of q (FP64, or FP32 for the FP32 charge source).
 template <typename TO, int TS, int P>
 struct Spread {
@@ -375,37 +381,34 @@ struct Spread {
     const double4* rq;
     TO* q;
   };
-  static constexpr int kThreads = kBlock;
-  static constexpr int kChunk = 128;   // staged atoms per round
+  static constexpr int kThreads = kBlock;   // four waves, four tiles
+  static constexpr int kChunk = 64;         // staged atoms per round (one per lane)
   __device__ static void run(const Args& A, Grid G);
 };
 template <typename TO, int TS, int P>
 __device__ void Spread<TO, TS, P>::run(const Args& A, Grid G) {
-  // the assignment order is a template parameter: register arrays sized exactly
-  // each wave's tile copy holds z-planes of TS^2 + 6 points: the padding
-  // spreads a stencil's z-neighbour points over the LDS banks (a 4^3 or 5^3
-  // stencil's 64 lanes then meet at most 2 or 3 to a bank, 4 and 5 unpadded)
-  constexpr int V = TS * TS * TS, CH = kChunk, p = P, pw = 3 * P, SZ = TS * TS + 6, VP = TS * SZ;
+  static_assert(TS * TS == 64, "one lane per column of the tile");
+  constexpr int NW = kBlock / 64, CH = kChunk, WPA = 2 * P + TS;   // per atom: q w_x [P], w_y [P], w_z over the tile [TS]
   const int n = A.n, ntx = A.ntx;
   const int* __restrict__ start = A.start;
   const int* __restrict__ cls = A.cls;
   const int2* __restrict__ rb = A.rb;
   const double4* __restrict__ rq = A.rq;
   TO* __restrict__ q = A.q;
-  __shared__ T acc[kBlock / 64][VP];
-  __shared__ T sw[CH * pw];      // [CH][3p] weights x | y | z
-  __shared__ T sq[CH];
-  __shared__ int sb[CH][3];      // stencil start relative to the tile
-  __shared__ int r_lo[64], r_off[65];   // staged ranges: first position, prefix of lengths
-  const int t = G.b;
+  __shared__ T sw[NW][CH * WPA];
+  __shared__ int r_lo[NW][64], r_off[NW][65];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ntiles = ntx * ntx * ntx;
+  const int t = G.b * NW + wv;
+  if (t >= ntiles) return;   // per wave: the kernel has no workgroup barriers
   const int tx = t % ntx, ty = (t / ntx) % ntx, tz = t / (ntx * ntx);
   const int ox = tx * TS, oy = ty * TS, oz = tz * TS;
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int i = threadIdx.x; i < (kBlock / 64) * VP; i += kBlock) (&acc[0][0])[i] = T(0);
-  // the ranges: lane k = (d, c) of the first wave, d = k >> 3 the lower
-  // neighbour, c = k & 7 the class; used when c contains d (all classes of
-  // the tile's own bin; with one tile per axis, only the own bin)
-  if (wv == 0) {
+  const int lx = lane % TS, ly = lane / TS;
+  // the ranges: lane k = (d, c), d = k >> 3 the lower neighbour, c = k & 7
+  // the class; used when c contains d (all classes of the tile's own bin;
+  // with one tile per axis, only the own bin)
+  int tot;
+  {
     const int nd = ntx > 1 ? 2 : 1;
     const int d = lane >> 3, c = lane & 7;
     const int dx = d & 1, dy = (d >> 1) & 1, dz = d >> 2;
@@ -419,123 +422,110 @@ __device__ void Spread<TO, TS, P>::run(const Args& A, Grid G) {
       lo = cls[8 * b + c];
       len = (c < 7 ? cls[8 * b + c + 1] : start[b + 1]) - lo;
     }
-    // inclusive scan of the lengths over the wave
     int incl = len;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       const int u = __shfl_up(incl, o, 64);
       incl += lane >= o ? u : 0;
     }
-    r_lo[lane] = lo;
-    r_off[lane + 1] = incl;
-    if (lane == 0) r_off[0] = 0;
+    r_lo[wv][lane] = lo;
+    r_off[wv][lane + 1] = incl;
+    if (lane == 0) r_off[wv][0] = 0;
+    tot = __shfl(incl, 63, 64);
   }
-  __syncthreads();
-  const int total = r_off[64];
-  const int p2 = p * p, p3 = p2 * p;
-  // this lane's stencil points of an atom, l = lane + 64 it (fixed for the
-  // whole kernel; p^3 <= 343 needs up to 6 per lane); invalid slots get an
-  // offset that fails the in-tile test
-  constexpr int kMaxIt = (P * P * P + 63) / 64;
-  int sax[kMaxIt], say[kMaxIt], saz[kMaxIt];
-  const int n_it = (p3 + 63) / 64;
-#pragma unroll
-  for (int it = 0; it < kMaxIt; it++) {
-    const int l = lane + 64 * it;
-    const bool ok = l < p3;
-    sax[it] = ok ? l % p : 0;
-    say[it] = ok ? (l / p) % p : 0;
-    saz[it] = ok ? l / p2 : 1 << 20;
-  }
-  // Staged atoms CH at a time, one per thread.  The records of the next
-  // chunk are loaded into registers while the current chunk is being added,
-  // so only the first chunk waits for memory.
   int2 nr = make_int2(0, 0);
   double4 nq = make_double4(0.0, 0.0, 0.0, 0.0);
   auto fetch = [&](int c0) {
-    if ((int)threadIdx.x < min(CH, total - c0)) {
-      const int c = c0 + threadIdx.x;
+    if (lane < min(CH, tot - c0)) {
+      const int c = c0 + lane;
       int lo = 0, hi = 63;   // last range whose offset is <= c
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (r_off[mid] <= c) lo = mid;
+        if (r_off[wv][mid] <= c) lo = mid;
         else hi = mid - 1;
       }
-      const int ps = r_lo[lo] + (c - r_off[lo]);   // position in bin order
+      const int ps = r_lo[wv][lo] + (c - r_off[wv][lo]);   // position in bin order
       nr = rb[ps];
       nq = rq[ps];
     }
   };
+  T acc[TS];
+#pragma unroll
+  for (int z = 0; z < TS; z++) acc[z] = T(0);
   fetch(0);
-  for (int c0 = 0; c0 < total; c0 += CH) {
-    const int m = min(CH, total - c0);
-    if ((int)threadIdx.x < m) {
-      const int i = threadIdx.x;
-      sq[i] = (T)nq.x;
+  T* const wsw = sw[wv];
+  int my_rx = 0, my_ry = 0;   // stencil start (x, y) of this lane's staged atom, relative to the tile
+  for (int c0 = 0; c0 < tot; c0 += CH) {
+    const int m = min(CH, tot - c0);
+    if (lane < m) {
       const double tau3[3] = {nq.y, nq.z, nq.w};
       const int b3[3] = {org_x(nr.x), org_y(nr.x), org_z(nr.x)}, o3[3] = {ox, oy, oz};
+      int rel3[3];
+      T* wi = wsw + lane * WPA;
       for (int d = 0; d < 3; d++) {
         double wl[P];
-        bspline_weights<double>(p, tau3[d], wl);
-#pragma unroll
-        for (int j = 0; j < P; j++) sw[i * pw + d * p + j] = (T)wl[j];
+        bspline_weights<double>(P, tau3[d], wl);
         int rel = b3[d] - o3[d];              // stencil start relative to the tile, mod n
         rel += rel < 0 ? n : 0;
-        sb[i][d] = rel < TS ? rel : rel - n;   // in [-(p-1), TS)
-      }
-    }
-    __syncthreads();
-    if (c0 + CH < total) fetch(c0 + CH);
-    // staged atoms round-robin over the waves, in chunk order per wave: this
-    // wave's j-th atom is wv + 4 j.  Two atoms are prepared at a time and
-    // added in order, so the loads of the second overlap the first; lanes
-    // of one atom hit distinct points and a wave's adds to one point execute
-    // in program order, so the sums stay deterministic (no-return LDS adds).
-    const int nmine = (m - wv + kBlock / 64 - 1) / (kBlock / 64);
-    auto prep = [&](int i, T* c, int* at) {
-      const int rx = sb[i][0], ry = sb[i][1], rz = sb[i][2];
-      const T* wi = sw + i * pw;
-      const T qi = sq[i];
+        rel3[d] = rel < TS ? rel : rel - n;   // in [-(p-1), TS)
+        if (d < 2) {
 #pragma unroll
-      for (int it = 0; it < kMaxIt; it++) {
-        at[it] = -1;
-        if (it >= n_it) break;
-        const int ax = sax[it], ay = say[it], az = saz[it];
-        int lx = rx + ax, ly = ry + ay, lz = rz + az;
+          for (int j = 0; j < P; j++) wi[d * P + j] = d == 0 ? nq.x * wl[j] : wl[j];
+        } else {
+#pragma unroll
+          for (int z = 0; z < TS; z++) {
+            int dz = z - rel3[2];
+            if (ntx == 1) dz &= n - 1;   // the tile is the whole periodic mesh
+            T w = T(0);
+#pragma unroll
+            for (int j = 0; j < P; j++) w = dz == j ? wl[j] : w;
+            wi[2 * P + z] = w;
+          }
+        }
+      }
+      my_rx = rel3[0];
+      my_ry = rel3[1];
+    }
+    // the wave's LDS stores precede its loads below (one wave, in order)
+    __builtin_amdgcn_wave_barrier();
+    if (c0 + CH < tot) fetch(c0 + CH);
+    // atom j's stencil start comes from lane j's registers (no LDS round
+    // trip); a lane outside the atom's x-y footprint adds exact zeros, so
+    // the loop has no branches and the loads of consecutive atoms overlap
+    for (int j = 0; j < m; j += 2) {
+      // atoms j and j + 1 (a repeat of j, adding zeros, past the end)
+      T a[2], b[2], wz[2][TS];
+      bool in[2];
+#pragma unroll
+      for (int u = 0; u < 2; u++) {
+        const int ju = min(j + u, m - 1);
+        int dx = lx - __builtin_amdgcn_readlane(my_rx, ju), dy = ly - __builtin_amdgcn_readlane(my_ry, ju);
         if (ntx == 1) {   // the tile is the whole periodic mesh: stencils wrap onto it
-          lx &= n - 1;
-          ly &= n - 1;
-          lz = az < p ? lz & (n - 1) : lz;
+          dx &= n - 1;
+          dy &= n - 1;
         }
-        if ((unsigned)lx < (unsigned)TS && (unsigned)ly < (unsigned)TS && (unsigned)lz < (unsigned)TS) {
-          c[it] = qi * wi[ax] * wi[p + ay] * wi[2 * p + az];
-          at[it] = lz * SZ + ly * TS + lx;
+        in[u] = j + u < m && (unsigned)dx < (unsigned)P && (unsigned)dy < (unsigned)P;
+        const T* wj = wsw + ju * WPA;
+        a[u] = wj[in[u] ? dx : 0];
+        b[u] = wj[P + (in[u] ? dy : 0)];
+#pragma unroll
+        for (int z = 0; z < TS; z += 2) {
+          const double2 v = *reinterpret_cast<const double2*>(wj + 2 * P + z);
+          wz[u][z] = v.x;
+          wz[u][z + 1] = v.y;
         }
       }
-    };
-    auto add = [&](const T* c, const int* at) {
 #pragma unroll
-      for (int it = 0; it < kMaxIt; it++)
-        if (at[it] >= 0)
-          __hip_atomic_fetch_add(&acc[wv][at[it]], c[it], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    };
-    for (int j = 0; j < nmine; j += 2) {
-      T c0v[kMaxIt], c1v[kMaxIt];
-      int at0[kMaxIt], at1[kMaxIt];
-      prep(wv + (kBlock / 64) * j, c0v, at0);
-      const bool two = j + 1 < nmine;
-      if (two) prep(wv + (kBlock / 64) * (j + 1), c1v, at1);
-      add(c0v, at0);
-      if (two) add(c1v, at1);
+      for (int u = 0; u < 2; u++) {
+        const T txy = in[u] ? a[u] * b[u] : T(0);   // (q w_x) w_y
+#pragma unroll
+        for (int z = 0; z < TS; z++) acc[z] += txy * wz[u][z];
+      }
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
   }
-  for (int i = threadIdx.x; i < V; i += kBlock) {
-    const int lx = i % TS, ly = (i / TS) % TS, lz = i / (TS * TS), a = lz * SZ + ly * TS + lx;
-    T s = acc[0][a];
-    for (int k = 1; k < kBlock / 64; k++) s += acc[k][a];
-    q[nat_idx(n, ox + lx, oy + ly, oz + lz)] = (TO)s;
-  }
+#pragma unroll
+  for (int z = 0; z < TS; z++) q[nat_idx(n, ox + lx, oy + ly, oz + z)] = (TO)acc[z];
 }
 
 // Gather: F = -k Q sum_n W(r - r_n) (D phi)_n with the central difference D,
@@ -1261,10 +1251,11 @@ template <int P>
 hipError_t spread_p(bool fp64, int n, int ntx, double box, const int* start, const int* cls, const void* rb,
                     const void* rq, void* q, hipStream_t s) {
   const int ntiles = ntx * ntx * ntx;
+  const int grid = (ntiles + 3) / 4;   // one wave per tile
   if (fp64)
-    return go<Spread<double, 8, P>>({n, ntx, box, start, cls, (const int2*)rb, (const double4*)rq, (double*)q}, ntiles,
+    return go<Spread<double, 8, P>>({n, ntx, box, start, cls, (const int2*)rb, (const double4*)rq, (double*)q}, grid,
                                     0, s);
-  return go<Spread<float, 8, P>>({n, ntx, box, start, cls, (const int2*)rb, (const double4*)rq, (float*)q}, ntiles, 0,
+  return go<Spread<float, 8, P>>({n, ntx, box, start, cls, (const int2*)rb, (const double4*)rq, (float*)q}, grid, 0,
                                  s);
 }
 }  // namespace
