@@ -361,11 +361,12 @@ __device__ void SortBins::run(const Args& A, Grid G) {
 // One wave per tile, one lane per (x, y) column of it, the column's TS
 // values held in registers.  The tile's candidate atoms are staged in the
 // wave's part of LDS in chunks of 64 (ranges, then positions), one atom per
-// lane, which also forms the atom's B-spline weights: q w_x and w_y, and w_z
-// laid out over the tile's TS z-positions (zero where the stencil does not
-// reach); the lanes then walk the staged atoms in order and every lane whose
-// column the atom's stencil covers adds the atom's terms ((q w_x) w_y) w_z to
-// its column (exact zeros elsewhere along z).  Each mesh value is a sum in a fixed order (the candidates' order)
+// lane, which also forms the atom's B-spline weights laid out over the
+// tile: q w_x at the TS x-positions, w_y and w_z likewise, zero where the
+// stencil does not reach; the lanes then walk the staged atoms in order and
+// every lane adds the atom's terms ((q w_x) w_y) w_z to its column, reading
+// its own x and y entries (exact zeros outside the atom's reach, so the walk
+// has no branches and no index arithmetic).  Each mesh value is a sum in a fixed order (the candidates' order)
 // formed in one register: no atomics of any kind, bitwise reproducible, and
 // the tile is written once.  The next chunk's records are loaded while the
 // current chunk is walked.  The sums are formed in FP64; TO is the stored
@@ -388,7 +389,9 @@ struct Spread {
 template <typename TO, int TS, int P>
 __device__ void Spread<TO, TS, P>::run(const Args& A, Grid G) {
   static_assert(TS * TS == 64, "one lane per column of the tile");
-  constexpr int NW = kBlock / 64, CH = kChunk, WPA = 2 * P + TS;   // per atom: q w_x [P], w_y [P], w_z over the tile [TS]
+  // per atom: q w_x, w_y and w_z each laid out over the tile's TS positions
+  // along its axis (zero where the stencil does not reach)
+  constexpr int NW = kBlock / 64, CH = kChunk, WPA = 3 * TS;
   const int n = A.n, ntx = A.ntx;
   const int* __restrict__ start = A.start;
   const int* __restrict__ cls = A.cls;
@@ -454,73 +457,65 @@ __device__ void Spread<TO, TS, P>::run(const Args& A, Grid G) {
   for (int z = 0; z < TS; z++) acc[z] = T(0);
   fetch(0);
   T* const wsw = sw[wv];
-  int my_rx = 0, my_ry = 0;   // stencil start (x, y) of this lane's staged atom, relative to the tile
   for (int c0 = 0; c0 < tot; c0 += CH) {
-    const int m = min(CH, tot - c0);
+    const int m = __builtin_amdgcn_readfirstlane(min(CH, tot - c0));
     if (lane < m) {
       const double tau3[3] = {nq.y, nq.z, nq.w};
       const int b3[3] = {org_x(nr.x), org_y(nr.x), org_z(nr.x)}, o3[3] = {ox, oy, oz};
-      int rel3[3];
       T* wi = wsw + lane * WPA;
       for (int d = 0; d < 3; d++) {
         double wl[P];
         bspline_weights<double>(P, tau3[d], wl);
-        int rel = b3[d] - o3[d];              // stencil start relative to the tile, mod n
+        int rel = b3[d] - o3[d];   // stencil start relative to the tile, mod n
         rel += rel < 0 ? n : 0;
-        rel3[d] = rel < TS ? rel : rel - n;   // in [-(p-1), TS)
-        if (d < 2) {
+        rel = rel < TS ? rel : rel - n;   // in [-(p-1), TS)
+        // zeros over the tile, then the weights at the positions the
+        // stencil reaches (this lane's stores land in order)
+        T* wd = wi + d * TS;
 #pragma unroll
-          for (int j = 0; j < P; j++) wi[d * P + j] = d == 0 ? nq.x * wl[j] : wl[j];
-        } else {
+        for (int x = 0; x < TS; x += 2) *reinterpret_cast<double2*>(wd + x) = make_double2(0.0, 0.0);
 #pragma unroll
-          for (int z = 0; z < TS; z++) {
-            int dz = z - rel3[2];
-            if (ntx == 1) dz &= n - 1;   // the tile is the whole periodic mesh
-            T w = T(0);
-#pragma unroll
-            for (int j = 0; j < P; j++) w = dz == j ? wl[j] : w;
-            wi[2 * P + z] = w;
-          }
+        for (int j = 0; j < P; j++) {
+          int x = rel + j;
+          if (ntx == 1) x &= n - 1;   // the tile is the whole periodic mesh
+          if ((unsigned)x < (unsigned)TS) wd[x] = d == 0 ? nq.x * wl[j] : wl[j];
         }
       }
-      my_rx = rel3[0];
-      my_ry = rel3[1];
     }
     // the wave's LDS stores precede its loads below (one wave, in order)
     __builtin_amdgcn_wave_barrier();
     if (c0 + CH < tot) fetch(c0 + CH);
-    // atom j's stencil start comes from lane j's registers (no LDS round
-    // trip); a lane outside the atom's x-y footprint adds exact zeros, so
-    // the loop has no branches and the loads of consecutive atoms overlap
-    for (int j = 0; j < m; j += 2) {
-      // atoms j and j + 1 (a repeat of j, adding zeros, past the end)
-      T a[2], b[2], wz[2][TS];
-      bool in[2];
+    // one staged atom's terms for this lane's column: (q w_x) w_y times w_z
+    // at each z
+    auto load_atom = [&](int j, T* a, T* b, T* wz) {
+      const T* wj = wsw + j * WPA;
+      *a = wj[lx];
+      *b = wj[TS + ly];
 #pragma unroll
-      for (int u = 0; u < 2; u++) {
-        const int ju = min(j + u, m - 1);
-        int dx = lx - __builtin_amdgcn_readlane(my_rx, ju), dy = ly - __builtin_amdgcn_readlane(my_ry, ju);
-        if (ntx == 1) {   // the tile is the whole periodic mesh: stencils wrap onto it
-          dx &= n - 1;
-          dy &= n - 1;
-        }
-        in[u] = j + u < m && (unsigned)dx < (unsigned)P && (unsigned)dy < (unsigned)P;
-        const T* wj = wsw + ju * WPA;
-        a[u] = wj[in[u] ? dx : 0];
-        b[u] = wj[P + (in[u] ? dy : 0)];
-#pragma unroll
-        for (int z = 0; z < TS; z += 2) {
-          const double2 v = *reinterpret_cast<const double2*>(wj + 2 * P + z);
-          wz[u][z] = v.x;
-          wz[u][z + 1] = v.y;
-        }
+      for (int z = 0; z < TS; z += 2) {
+        const double2 v = *reinterpret_cast<const double2*>(wj + 2 * TS + z);
+        wz[z] = v.x;
+        wz[z + 1] = v.y;
       }
+    };
+    int j = 0;
+    for (; j + 1 < m; j += 2) {   // two atoms' loads in flight, added in order
+      T a[2], b[2], wz[2][TS];
+      load_atom(j, &a[0], &b[0], wz[0]);
+      load_atom(j + 1, &a[1], &b[1], wz[1]);
 #pragma unroll
       for (int u = 0; u < 2; u++) {
-        const T txy = in[u] ? a[u] * b[u] : T(0);   // (q w_x) w_y
+        const T txy = a[u] * b[u];
 #pragma unroll
         for (int z = 0; z < TS; z++) acc[z] += txy * wz[u][z];
       }
+    }
+    if (j < m) {
+      T a, b, wz[TS];
+      load_atom(j, &a, &b, wz);
+      const T txy = a * b;
+#pragma unroll
+      for (int z = 0; z < TS; z++) acc[z] += txy * wz[z];
     }
     __builtin_amdgcn_wave_barrier();
   }
