@@ -1518,6 +1518,221 @@ __device__ void RestrictCol<T, FIN>::run(const Args& A, Grid G) {
   }
 }
 
+// The down leg of a fine level with a single pre-smoothing sweep (nu1 = 1)
+// followed by black-only prolongation (nu2 >= 1), as one column walk (FP32,
+// fine levels 256^3 and 512^3, single systems): the first sweep from e = 0
+// (red e = -r/6, black e = (sum of its red neighbours' -r/6 - r) / 6, as
+// SweepZero) and the red-only restriction of the residual it leaves (as
+// RestrictCol).  Each workgroup owns JB coarse rows of a band of KB coarse
+// planes and walks the fine planes; per plane z it forms the black values of
+// plane z + 1 from the red residuals of planes z .. z + 2, then the red
+// residuals of plane z from those black values, and adds them to the coarse
+// sums.  Nothing of the red values is stored: after this restriction the
+// black-only prolongation and the red half-sweep that follows overwrite
+// every red value without reading it, so the red values of this sweep are
+// used only here and formed on the fly.  The black values of the
+// workgroup's own fine rows are written (the up leg corrects them).
+// Thread rows: r0 rows 2 J0 - 3 .. 2 J0 + 2 JB + 1 (the middle plane's in
+// LDS for x- and y-neighbours), of which the black rows 2 J0 - 2 .. 2 J0 +
+// 2 JB are computed (in LDS for the residual's neighbours) and the
+// residual rows 2 J0 - 1 .. 2 J0 + 2 JB - 1 evaluated; every value is
+// computed with the arithmetic and in the order of SweepZero and
+// RestrictCol, so the coarse right-hand side and the black values are
+// bitwise theirs.  Two workgroup barriers per fine plane.
+struct SweepRestrictGeo {
+  int nc, W, gx, rows, JB;
+  __host__ __device__ SweepRestrictGeo(int n, int nt) {
+    W = 4;
+    nc = n / 2;
+    gx = nc / W;   // threads per row
+    rows = nt / gx;
+    JB = 1;
+    while (2 * (2 * JB) + 5 <= rows && nc % (2 * JB) == 0) JB *= 2;
+  }
+  __host__ __device__ int r0_rows() const { return 2 * JB + 5; }
+  __host__ __device__ int e1_rows() const { return 2 * JB + 3; }
+  __host__ __device__ int rho_rows() const { return 2 * JB + 1; }
+  __host__ __device__ int lds_floats() const { return (r0_rows() + 2 * e1_rows() + rho_rows()) * nc; }
+};
+constexpr int kSweepRestrictThreads = 1024;
+
+struct SweepRestrict {
+  struct Args {
+    int n;
+    const float *r0, *r1;
+    float *e1, *rc0, *rc1;
+    const Ctl* ctl;
+  };
+  static constexpr int kThreads = kSweepRestrictThreads;
+  __device__ static void run(const Args& A, Grid G);
+};
+__device__ void SweepRestrict::run(const Args& A, Grid G) {
+  using T = float;
+  using V = float4;
+  constexpr int W = 4;
+  if (A.ctl->done) return;
+  const int n = A.n, msk = n - 1;
+  const CsGeo g(n), gc(n >> 1);
+  const SweepRestrictGeo sg(n, kThreads);
+  const int nc = sg.nc, gx = sg.gx, JB = sg.JB, cmsk = nc - 1;
+  const int nj = nc / JB, nz = G.g / nj, KB = nc / nz;
+  const int jb = G.b % nj, zr = G.b / nj;
+  const int J0 = jb * JB, K0 = zr * KB;
+  const int tid = threadIdx.x;
+  const int lr0 = tid / gx, m0 = (tid % gx) * W;   // thread row: r0 row 2 J0 - 3 + lr0
+  const bool r_on = lr0 < sg.r0_rows();
+  const bool e_on = lr0 >= 1 && lr0 < 1 + sg.e1_rows();      // black row (LDS row lr0 - 1)
+  const bool rho_on = lr0 >= 2 && lr0 < 2 + sg.rho_rows();   // residual row (LDS row lr0 - 2)
+  const bool own = lr0 >= 3 && lr0 < 3 + 2 * JB;               // the workgroup's own fine row
+  const int y = (2 * J0 - 3 + lr0) & msk;
+  extern __shared__ __align__(16) unsigned char sr_lds[];
+  T* const rbuf0 = reinterpret_cast<T*>(sr_lds);           // [r0_rows][nc]  r0 of the middle plane
+  T* const ebuf = rbuf0 + sg.r0_rows() * nc;                // [2][e1_rows][nc]
+  T* const hbuf = ebuf + 2 * sg.e1_rows() * nc;             // [rho_rows][nc]
+  const T* __restrict__ r0 = A.r0;
+  const T* __restrict__ r1 = A.r1;
+  T* __restrict__ e1g = A.e1;
+  auto at = [&](const T* a, int yy, int z) {
+    return *reinterpret_cast<const V*>(a + ((((z & msk) << g.l2) + yy) << (g.l2 - 1)) + m0);
+  };
+  auto vput = [&](T* b, const V& v) { *reinterpret_cast<V*>(b + m0) = v; };
+  auto neg6 = [](const V& v) { return make_float4(neg_sixth(v.x), neg_sixth(v.y), neg_sixth(v.z), neg_sixth(v.w)); };
+  const int zs = 2 * K0 - 1, ze = 2 * (K0 + KB) - 1;
+  const T sixth = T(1.0 / 6.0);
+  // registers: r0 of planes z, z + 1 (+ z + 2 loaded each step); black of planes z - 1, z, z + 1
+  // (loads run one plane ahead: r0 of plane z + 3 and r1 of plane z + 2 are
+  // issued while plane z is processed)
+  V rz = r_on ? at(r0, y, zs - 2) : V{}, rz1 = r_on ? at(r0, y, zs - 1) : V{};
+  V rz2n = r_on ? at(r0, y, zs) : V{}, rb1n = e_on ? at(r1, y, zs - 1) : V{};
+  V bm{}, bc{};
+  const int cur0 = 0;
+  int cur = cur0;
+  const bool coarse = own && ((lr0 - 3) & 1) == 0;
+  const int Jl = (lr0 - 3) >> 1;
+  const T wt[3] = {T(0.25), T(0.5), T(0.25)};
+  T sk[W], sn[W];
+#pragma unroll
+  for (int q = 0; q < W; q++) sk[q] = sn[q] = T(0);
+  for (int z = zs - 2; z <= ze; z++) {
+    const int nxt = cur ^ 1;
+    const V rz2 = rz2n, rb1 = rb1n;
+    if (z < ze) {
+      if (r_on) rz2n = at(r0, y, z + 3);
+      if (e_on) rb1n = at(r1, y, z + 2);
+    }
+    if (r_on) vput(rbuf0 + lr0 * nc, rz1);   // r0 of plane z + 1
+    __syncthreads();
+    // black values of plane z + 1 (SweepZero's arithmetic: neighbours -r0/6)
+    V bp{};
+    if (e_on) {
+      const T* row = rbuf0 + lr0 * nc;
+      const int par = (1 + y + z + 1) & 1;   // x-parity of the black points' red neighbours
+      const V o = neg6(*reinterpret_cast<const V*>(row + m0));
+      const T edge = neg_sixth(par ? row[(m0 + W) & cmsk] : row[(m0 - 1) & cmsk]);
+      const V vym = neg6(*reinterpret_cast<const V*>(row - nc + m0));
+      const V vyp = neg6(*reinterpret_cast<const V*>(row + nc + m0));
+      const V vzm = neg6(rz), vzp = neg6(rz2);
+      T out[W];
+#pragma unroll
+      for (int q = 0; q < W; q++) {
+        const T xm = par ? vget<T>(o, q) : (q == 0 ? edge : vget<T>(o, q - 1));
+        const T xp = par ? (q == W - 1 ? edge : vget<T>(o, q + 1)) : vget<T>(o, q);
+        const T nb = ((xm + xp) + (vget<T>(vym, q) + vget<T>(vyp, q))) + (vget<T>(vzm, q) + vget<T>(vzp, q));
+        out[q] = (nb - vget<T>(rb1, q)) * sixth;
+      }
+      bp = make_float4(out[0], out[1], out[2], out[3]);
+      vput(ebuf + (nxt * sg.e1_rows() + lr0 - 1) * nc, bp);
+      const int wz = z + 1;
+      if (own && wz >= 2 * K0 && wz < 2 * (K0 + KB))
+        *reinterpret_cast<V*>(e1g + ((((wz & msk) << g.l2) + y) << (g.l2 - 1)) + m0) = bp;
+    }
+    // red residuals of plane z (RestrictCol's arithmetic), red values -r0/6
+    if (z >= zs && rho_on) {
+      const T* row = ebuf + (cur * sg.e1_rows() + lr0 - 1) * nc;
+      const int par = (y + z) & 1;
+      const V ow = *reinterpret_cast<const V*>(row + m0);
+      const T edge = par ? row[(m0 + W) & cmsk] : row[(m0 - 1) & cmsk];
+      const V vym = *reinterpret_cast<const V*>(row - nc + m0), vyp = *reinterpret_cast<const V*>(row + nc + m0);
+      T rho[W];
+#pragma unroll
+      for (int q = 0; q < W; q++) {
+        const T xm = par ? vget<T>(ow, q) : (q == 0 ? edge : vget<T>(ow, q - 1));
+        const T xp = par ? (q == W - 1 ? edge : vget<T>(ow, q + 1)) : vget<T>(ow, q);
+        const T nb = ((xm + xp) + (vget<T>(vym, q) + vget<T>(vyp, q))) + (vget<T>(bm, q) + vget<T>(bp, q));
+        const T ev = neg_sixth(vget<T>(rz, q));
+        rho[q] = vget<T>(rz, q) - (nb - T(6) * ev);
+      }
+      vput(hbuf + (lr0 - 2) * nc, make_float4(rho[0], rho[1], rho[2], rho[3]));
+    }
+    __syncthreads();
+    if (z >= zs && coarse) {
+      const int cz = z & 1;   // odd z = 2K + 1: last plane of K, first of K + 1
+#pragma unroll
+      for (int b = -1; b <= 1; b++) {
+        const int yy = (2 * (J0 + Jl) + b) & msk;
+        const int par = (yy + z) & 1;
+        const T* rr = hbuf + (2 * Jl + b + 1) * nc;
+        const V rv = *reinterpret_cast<const V*>(rr + m0);
+        T row[W];
+        if (par == 0) {
+#pragma unroll
+          for (int q = 0; q < W; q++) {
+            T r = T(0);
+            r += wt[1] * vget<T>(rv, q);
+            row[q] = r;
+          }
+        } else {
+          const T re = rr[(m0 - 1) & cmsk];
+#pragma unroll
+          for (int q = 0; q < W; q++) {
+            T r = T(0);
+            r += wt[0] * (q == 0 ? re : vget<T>(rv, q - 1));
+            r += wt[2] * vget<T>(rv, q);
+            row[q] = r;
+          }
+        }
+        if (cz) {
+          if (z > zs) {
+            const T w = wt[b + 1] * wt[2];
+#pragma unroll
+            for (int q = 0; q < W; q++) sk[q] += w * row[q];
+          }
+          if (z < ze) {
+            const T w = wt[b + 1] * wt[0];
+#pragma unroll
+            for (int q = 0; q < W; q++) sn[q] += w * row[q];
+          }
+        } else {
+          const T w = wt[b + 1] * wt[1];
+#pragma unroll
+          for (int q = 0; q < W; q++) sk[q] += w * row[q];
+        }
+      }
+      if (cz) {
+        if (z > zs) {
+          const int K = (z - 1) >> 1, J = J0 + Jl;
+#pragma unroll
+          for (int q = 0; q < W; q++) {
+            const int I = m0 + q;
+            T* out = ((I + J + K) & 1) ? A.rc1 : A.rc0;
+            out[cs_index(gc, I, J, K)] = T(4) * sk[q];
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < W; q++) {
+          sk[q] = sn[q];
+          sn[q] = T(0);
+        }
+      }
+    }
+    rz = rz1;
+    rz1 = rz2;
+    bm = bc;
+    bc = bp;
+    cur = nxt;
+  }
+}
+
 // Trilinear interpolation of the coarse correction (colour-split, geometry
 // gc) at fine point (x,y,z).
 template <typename T>
@@ -2548,6 +2763,21 @@ hipError_t launch_restrict(int n, int red_only, const T* e0, const T* e1, const 
   if (speculate(n)) return go<ResidRestrict<T, FIN, 1>>({n, red_only, e0, e1, r0, r1, rc0, rc1, ctl}, nb, 0, s);
   return go<ResidRestrict<T, FIN, 0>>({n, red_only, e0, e1, r0, r1, rc0, rc1, ctl}, nb, 0, s);
 }
+// SweepRestrict applies to single systems' FP32 fine levels of 256^3 and
+// 512^3 when the down leg is one sweep and the up leg starts with the
+// black-only prolongation.
+template <typename T>
+bool sweep_restrict_on(int n, int nu1, int nu2) {
+  return sizeof(T) == 4 && nu1 == 1 && nu2 >= 1 && n >= 256 && n <= 512 && !g_recorder;
+}
+hipError_t launch_sweep_restrict(int n, const float* r0, const float* r1, float* e1, float* rc0, float* rc1, Ctl* ctl,
+                                 hipStream_t s) {
+  const SweepRestrictGeo sg(n, kSweepRestrictThreads);
+  const int nj = sg.nc / sg.JB;
+  int nz = 1;
+  while (nz < sg.nc && nj * nz < 512) nz *= 2;
+  return go<SweepRestrict>({n, r0, r1, e1, rc0, rc1, ctl}, nj * nz, (size_t)sg.lds_floats() * 4, s);
+}
 template <typename T, int FIN>
 hipError_t launch_prolong_black(int n, T* e1, const T* c0, const T* c1, Ctl* ctl, hipStream_t s) {
   if (n >= 256 && !g_recorder)
@@ -2640,6 +2870,15 @@ hipError_t vcycle_impl(const LevelBufs* lv, int levels, int tail, int nu1, int n
     const int n = lv[l].n, half = n * n * n / 2;
     const double n3 = (double)n * n * n;
     T *e0 = (T*)lv[l].e0, *e1 = (T*)lv[l].e1, *r0 = (T*)lv[l].r0, *r1 = (T*)lv[l].r1;
+    if (sweep_restrict_on<T>(n, nu1, nu2)) {
+      // the single pre-smoothing sweep and the restriction in one walk
+      rec_key(key_down(l, 63));
+      kt_begin(KT_RESTRICT, l, s);
+      P3MZ_LAUNCH(launch_sweep_restrict(n, (const float*)r0, (const float*)r1, (float*)e1, (float*)lv[l + 1].r0,
+                                        (float*)lv[l + 1].r1, ctl, s));
+      kt_end(KT_RESTRICT, l, 1.625 * ts * n3, s);
+      continue;
+    }
     if (fused_restricts<T>(lv[l], nu1, nu2)) {
       rec_key(key_down(l, 61));
       kt_begin(KT_FUSED_DOWN, l, s);
@@ -3100,7 +3339,9 @@ hipError_t fused_configure() {
   P3MZ_LAUNCH((allow_lds<Sigma<double, kColThreads>>(col)));
   P3MZ_LAUNCH((allow_lds<Outer<float, kColThreads>>(col)));
   P3MZ_LAUNCH((allow_lds<Outer<double, kColThreads>>(col)));
-  // the column-walk restriction
+  // the column-walk restriction and the fused first sweep and restriction
+  P3MZ_LAUNCH((allow_lds<SweepRestrict>(std::max(SweepRestrictGeo(256, kSweepRestrictThreads).lds_floats(),
+                                                  SweepRestrictGeo(512, kSweepRestrictThreads).lds_floats()) * 4)));
   const int rf = RestrictColGeo<float>(512, kRestrictColThreads).lds_elems() * 4;
   const int rd = RestrictColGeo<double>(512, kRestrictColThreads).lds_elems() * 8;
   P3MZ_LAUNCH((allow_lds<RestrictCol<float, 0>>(rf)));

@@ -31,15 +31,17 @@ def torch():
     return _t
 
 
-def sampled_parity(torch, w, precisions, steps, sample=512):
+def sampled_parity(torch, w, precisions, steps, sample=512, schedule=(2, 2)):
     """V-cycle counts must be equal in every precision; with the FP32 charge
     source (2) a count may differ only where the oracle's residual lies
-    within 1e-4 (relative) of its threshold."""
+    within 1e-4 (relative) of its threshold.  `schedule` is the (nu_pre,
+    nu_post) both sides run."""
     s = w.system(progress=lambda msg: print(f"[inputs] {msg}", flush=True))
     rng = np.random.Generator(np.random.PCG64(w.seed + 17))
     targets = np.sort(rng.choice(s.n, size=sample, replace=False))
     traj = [s.pos + k * w.dt_fs * s.vel for k in range(steps)]
-    _, op = params_pair(w.box, w.alpha, w.r_cut, w.mesh, w.order, tol=w.tol, k_e=K_E, excl_group=w.excl_group)
+    _, op = params_pair(w.box, w.alpha, w.r_cut, w.mesh, w.order, tol=w.tol, k_e=K_E, excl_group=w.excl_group,
+                        nu_pre=schedule[0], nu_post=schedule[1])
     o = O.Oracle(op, s.charges)
     o.set_sr_targets(targets)
     ref, ores, othr = [], [], []
@@ -53,7 +55,7 @@ def sampled_parity(torch, w, precisions, steps, sample=512):
     o.close()
     for precision in precisions:
         gp, _ = params_pair(w.box, w.alpha, w.r_cut, w.mesh, w.order, tol=w.tol, precision=precision, k_e=K_E,
-                            excl_group=w.excl_group)
+                            excl_group=w.excl_group, nu_pre=schedule[0], nu_post=schedule[1])
         g = GpuCtx(gp, s.charges, torch)
         bar = FP64_BAR if precision == 0 else MIXED_BAR
         try:
@@ -88,3 +90,17 @@ def test_large_water_512_full_size(torch):
     forces on 1,000 seeded atoms, V-cycle counts and the long-range energy of
     the whole system."""
     sampled_parity(torch, configs.water_large(), [1, 2, 0], steps=2, sample=1000)
+
+
+@pytest.mark.parametrize("i", [2])
+def test_water_sweep_schedule_1_2(torch, i):
+    """The (1, 2) schedule the autotuner picks from 64^3 up: on 256^3 the
+    single pre-smoothing sweep and the red-only restriction run as one walk
+    over the fine planes (FP32 modes)."""
+    sampled_parity(torch, configs.water_sweep(i), [1, 2, 0], steps=3, schedule=(1, 2))
+
+
+def test_large_water_512_schedule_1_2(torch):
+    """The benchmark's configuration: 512^3 with the (1, 2) schedule, FP32
+    charge source, two steps."""
+    sampled_parity(torch, configs.water_large(), [2, 1], steps=2, sample=1000, schedule=(1, 2))
