@@ -589,6 +589,10 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
       P3MZ_TRY(c->allocb(&b.d1, half * c->tsz));
       b.fty = b.ftz = fused_tile(nl);
     }
+    if (l == 0 && l < pl.tail && nl == 512 && !c->fp64) {   // output of the fused post-smoothing
+      P3MZ_TRY(c->allocb(&b.s0, half * c->tsz));
+      P3MZ_TRY(c->allocb(&b.s1, half * c->tsz));
+    }
   }
   // every reduction grid is capped, so one fixed-size partial buffer fits all
   P3MZ_TRY(c->alloc(&c->d_partial, kPartialSlots));
@@ -699,7 +703,8 @@ p3mz_status enq_cycle(p3mz_ctx* c, hipStream_t s) {
                              defer ? &d : nullptr));
   rec_key(4100);
   kt_begin(KT_OUTER, 0, s);
-  P3MZ_HIP_TRY(launch_outer(c->fp64, pl.n, 0, c->P.max_cycles, c->d_sigma, c->d_y[0], c->d_y[1], f.e0, f.e1, f.r0,
+  P3MZ_HIP_TRY(launch_outer(c->fp64, pl.n, 0, c->P.max_cycles, c->d_sigma, c->d_y[0], c->d_y[1],
+                            cycle_e0(f, c->fp64, c->nu2), cycle_e1(f, c->fp64, c->nu2), f.r0,
                             f.r1, c->d_partial, c->d_ctl, s, !defer, nullptr, 0.0, 0, c->P.stencil));
   kt_end(KT_OUTER, 0, (24.0 + 2.0 * ts) * N3, s);
   return P3MZ_OK;
@@ -1454,7 +1459,8 @@ p3mz_status p3mz_vcycle(p3mz_ctx* ctx, const double* r_dev, double* e_dev, void*
   P3MZ_HIP_TRY(launch_nat_to_cs(ctx->fp64, ctx->pl.n, r_dev, f.r0, f.r1, s));
   P3MZ_HIP_TRY(launch_vcycle(ctx->fp64, ctx->lv, ctx->pl.levels, ctx->pl.tail, ctx->nu1, ctx->nu2, ctx->d_green,
                              ctx->d_ctl, s));
-  P3MZ_HIP_TRY(launch_cs_to_nat(ctx->fp64, ctx->pl.n, f.e0, f.e1, e_dev, s));
+  P3MZ_HIP_TRY(launch_cs_to_nat(ctx->fp64, ctx->pl.n, cycle_e0(f, ctx->fp64, ctx->nu2), cycle_e1(f, ctx->fp64, ctx->nu2),
+                                e_dev, s));
   return P3MZ_OK;
 }
 
@@ -1693,7 +1699,8 @@ p3mz_status p3mz_kernel_bench(p3mz_ctx* ctx, int32_t kernel_id, int32_t reps, vo
     } else if (kernel_id == KT_OUTER) {
       // the cycle form without its finalize pass; both multiplier buffers
       // are scratch between steps (the multiplier is kept in the history slots)
-      e = launch_outer(ctx->fp64, n, 0, ctx->P.max_cycles, ctx->d_sigma, ctx->d_y[0], ctx->d_y[1], f.e0, f.e1, f.r0,
+      e = launch_outer(ctx->fp64, n, 0, ctx->P.max_cycles, ctx->d_sigma, ctx->d_y[0], ctx->d_y[1],
+                       cycle_e0(f, ctx->fp64, ctx->nu2), cycle_e1(f, ctx->fp64, ctx->nu2), f.r0,
                        f.r1, ctx->d_partial, ctx->d_ctl, s, false, nullptr, 0.0, 0, ctx->P.stencil);
       bytes = (24.0 + 2.0 * ts) * N3;
     } else if (kernel_id == KT_SIGMA) {
@@ -1880,8 +1887,8 @@ p3mz_status p3mz_autotune(p3mz_ctx* ctx, const double* frames_dev, int32_t n_fra
         P3MZ_HIP_TRY(launch_set_ctl_open(ctx->d_ctl, s));
         P3MZ_HIP_TRY(launch_vcycle(ctx->fp64, ctx->lv, ctx->pl.levels, ctx->pl.tail, ctx->nu1, ctx->nu2,
                                    ctx->d_green, ctx->d_ctl, s, nullptr));
-        P3MZ_HIP_TRY(launch_outer(ctx->fp64, n, 0, ctx->P.max_cycles, ctx->d_sigma, ctx->d_y[0], ctx->d_y[1], f0.e0,
-                                  f0.e1, f0.r0, f0.r1, ctx->d_partial, ctx->d_ctl, s, false, nullptr, 0.0, 0,
+        P3MZ_HIP_TRY(launch_outer(ctx->fp64, n, 0, ctx->P.max_cycles, ctx->d_sigma, ctx->d_y[0], ctx->d_y[1],
+                                  cycle_e0(f0, ctx->fp64, ctx->nu2), cycle_e1(f0, ctx->fp64, ctx->nu2), f0.r0, f0.r1, ctx->d_partial, ctx->d_ctl, s, false, nullptr, 0.0, 0,
                                   ctx->P.stencil));
       }
       P3MZ_HIP_TRY(hipEventRecord(c1, s));

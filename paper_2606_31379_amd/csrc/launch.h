@@ -138,7 +138,21 @@ struct LevelBufs {
   // the up leg reads d1 and writes e0/e1
   void* d0 = nullptr; void* d1 = nullptr;
   int fty = 0, ftz = 0;
+  // the two post-smoothing sweeps as one walk (post_sweeps_fused) write the
+  // level's final correction here instead of e0/e1
+  void* s0 = nullptr; void* s1 = nullptr;
 };
+// True when the V-cycle's post-smoothing on level buffers b runs as one
+// walk (FP32 512^3 single systems, two sweeps after the black-only
+// prolongation): the level's correction after the cycle is then in s0/s1.
+bool post_sweeps_fused(const LevelBufs& b, bool fp64, int nu2);
+// The colour-split buffers holding the finest level's correction after a V-cycle.
+inline const void* cycle_e0(const LevelBufs& b, bool fp64, int nu2) {
+  return post_sweeps_fused(b, fp64, nu2) ? b.s0 : b.e0;
+}
+inline const void* cycle_e1(const LevelBufs& b, bool fp64, int nu2) {
+  return post_sweeps_fused(b, fp64, nu2) ? b.s1 : b.e1;
+}
 // Largest level edge that gets the fused-leg buffers.
 constexpr int kFusedEdgeMax = 64;
 // Tile rows of a fused level of edge n (0: the level is not fused).

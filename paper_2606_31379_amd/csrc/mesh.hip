@@ -1733,6 +1733,142 @@ __device__ void SweepRestrict::run(const Args& A, Grid G) {
   }
 }
 
+// The up leg's two Gauss-Seidel sweeps after the black-only prolongation
+// (red, black, red, black half-sweeps), FP32 on a 512^3 fine level of a
+// single system, as one column walk instead of four launches: the input
+// black values e1 are read once and the final red and black values written
+// once (to s0 / s1: a workgroup reads its neighbours' input rows while they
+// write their output, so the two must differ).  A workgroup owns JB = 8
+// fine rows of a band of KB planes; its 16 thread rows are the owned rows
+// with 4 more on each side, the y-halo the four dependent half-sweeps need.
+// At step k the first half-sweep updates plane k, the second plane k - 1,
+// the third k - 2 and the fourth k - 3: each reads the previous half-sweep's
+// plane in LDS (written one step before) for its x- and y-neighbours and
+// its own row's neighbouring planes from registers.  Every value is formed
+// with Halfsweep's arithmetic in its order, so the result is bitwise that of
+// the four launches.  One workgroup barrier per step; LDS holds two buffers
+// per half-sweep input.
+constexpr int kPostThreads = 1024;
+constexpr int kPostRows = 8;   // owned fine rows per workgroup
+struct PostGeo {
+  int nc, gx, rows;
+  __host__ __device__ explicit PostGeo(int n) : nc(n / 2), gx(n / 8), rows(kPostRows + 8) {}
+  // LDS floats: two buffers of the inputs of the four half-sweeps (16, 14, 12, 10 rows)
+  __host__ __device__ int lds_floats() const { return 2 * (4 * kPostRows + 20) * nc; }
+};
+struct PostSweeps {
+  struct Args {
+    int n;
+    const float *e1, *r0, *r1;
+    float *s0, *s1;
+    const Ctl* ctl;
+  };
+  static constexpr int kThreads = kPostThreads;
+  __device__ static void run(const Args& A, Grid G);
+};
+__device__ void PostSweeps::run(const Args& A, Grid G) {
+  using T = float;
+  using V = float4;
+  constexpr int W = 4, JB = kPostRows;
+  if (A.ctl->done) return;
+  const int n = A.n, msk = n - 1;
+  const CsGeo g(n);
+  const PostGeo pg(n);
+  const int nc = pg.nc, gx = pg.gx, cmsk = nc - 1;
+  const int nj = n / JB, nz = G.g / nj, KB = n / nz;
+  const int jb = G.b % nj, zr = G.b / nj;
+  const int j0 = jb * JB, k0 = zr * KB;
+  const int tid = threadIdx.x;
+  const int r = tid / gx, m0 = (tid % gx) * W;   // thread row r: fine row j0 - 4 + r
+  const int y = (j0 - 4 + r) & msk;
+  const bool in1 = r >= 1 && r < JB + 7, in2 = r >= 2 && r < JB + 6, in3 = r >= 3 && r < JB + 5;
+  const bool in4 = r >= 4 && r < JB + 4;   // the workgroup's own rows
+  extern __shared__ __align__(16) unsigned char ps_lds[];
+  T* const L0 = reinterpret_cast<T*>(ps_lds);   // [2][16][nc] input black values
+  T* const L1 = L0 + 2 * (JB + 8) * nc;         // [2][14][nc] first red
+  T* const L2 = L1 + 2 * (JB + 6) * nc;         // [2][12][nc] first black
+  T* const L3 = L2 + 2 * (JB + 4) * nc;         // [2][10][nc] second red
+  auto at = [&](const T* a, int z) {
+    return *reinterpret_cast<const V*>(a + ((((z & msk) << g.l2) + y) << (g.l2 - 1)) + m0);
+  };
+  auto lds_row = [&](T* base, int nrows, int buf, int row) { return base + (buf * nrows + row) * nc; };
+  // Halfsweep's update of W points of this row: neighbours of the other
+  // colour from the LDS row (x and y) and the planes below / above (z)
+  auto half = [&](const T* row, const V& zm, const V& zp, int par, const V& rc) {
+    const V o = *reinterpret_cast<const V*>(row + m0);
+    const T edge = par ? row[(m0 + W) & cmsk] : row[(m0 - 1) & cmsk];
+    const V vym = *reinterpret_cast<const V*>(row - nc + m0), vyp = *reinterpret_cast<const V*>(row + nc + m0);
+    T out[W];
+#pragma unroll
+    for (int q = 0; q < W; q++) {
+      const T xm = par ? vget<T>(o, q) : (q == 0 ? edge : vget<T>(o, q - 1));
+      const T xp = par ? (q == W - 1 ? edge : vget<T>(o, q + 1)) : vget<T>(o, q);
+      const T nb = ((xm + xp) + (vget<T>(vym, q) + vget<T>(vyp, q))) + (vget<T>(zm, q) + vget<T>(zp, q));
+      out[q] = (nb - vget<T>(rc, q)) * T(1.0 / 6.0);
+    }
+    return make_float4(out[0], out[1], out[2], out[3]);
+  };
+  auto put = [&](T* p, const V& v) { *reinterpret_cast<V*>(p + m0) = v; };
+  const int kb = k0 - 3, ke = k0 + KB + 2;
+  // register windows (this thread's row): input e of planes k-1, k, k+1;
+  // first red at k-2, k-1; first black at k-3, k-2; second red at k-4, k-3;
+  // r0 at k-1, k-2; r1 at k-2, k-3 (r0(k) and r1(k-1) arrive each step)
+  V em = at(A.e1, kb - 1), ec = at(A.e1, kb), ep = at(A.e1, kb + 1), en = at(A.e1, kb + 2);
+  V a1m{}, a1c{}, b2m{}, b2c{}, a3m{}, a3c{};
+  V r0m = at(A.r0, kb - 1), r0mm = at(A.r0, kb - 2), r1m = at(A.r1, kb - 2), r1mm = at(A.r1, kb - 3);
+  V r0n = at(A.r0, kb), r1n = at(A.r1, kb - 1);
+  put(lds_row(L0, JB + 8, 0, r), ec);
+  __syncthreads();
+  int cur = 0;
+  for (int k = kb; k <= ke; k++) {
+    const int nxt = cur ^ 1;
+    const V r0k = r0n, r1k = r1n, e_next = en;   // r0(k), r1(k-1), e(k+2)
+    if (k < ke) {
+      en = at(A.e1, k + 3);
+      r0n = at(A.r0, k + 1);
+      r1n = at(A.r1, k);
+    }
+    V a1{}, b2{}, a3{};
+    if (in1) {   // first red half-sweep, plane k
+      a1 = half(lds_row(L0, JB + 8, cur, r), em, ep, (y + k) & 1, r0k);
+      put(lds_row(L1, JB + 6, nxt, r - 1), a1);
+    }
+    if (in2) {   // first black half-sweep, plane k - 1
+      b2 = half(lds_row(L1, JB + 6, cur, r - 1), a1m, a1, (1 + y + k - 1) & 1, r1k);
+      put(lds_row(L2, JB + 4, nxt, r - 2), b2);
+    }
+    if (in3) {   // second red half-sweep, plane k - 2
+      a3 = half(lds_row(L2, JB + 4, cur, r - 2), b2m, b2, (y + k - 2) & 1, r0mm);
+      put(lds_row(L3, JB + 2, nxt, r - 3), a3);
+      const int z = k - 2;
+      if (in4 && z >= k0 && z < k0 + KB)
+        *reinterpret_cast<V*>(A.s0 + ((((z & msk) << g.l2) + y) << (g.l2 - 1)) + m0) = a3;
+    }
+    if (in4) {   // second black half-sweep, plane k - 3
+      const V b4 = half(lds_row(L3, JB + 2, cur, r - 3), a3m, a3, (1 + y + k - 3) & 1, r1mm);
+      const int z = k - 3;
+      if (z >= k0 && z < k0 + KB)
+        *reinterpret_cast<V*>(A.s1 + ((((z & msk) << g.l2) + y) << (g.l2 - 1)) + m0) = b4;
+    }
+    put(lds_row(L0, JB + 8, nxt, r), ep);   // the input's plane k + 1 for the next step
+    __syncthreads();
+    em = ec;
+    ec = ep;
+    ep = e_next;
+    a1m = a1c;
+    a1c = a1;
+    b2m = b2c;
+    b2c = b2;
+    a3m = a3c;
+    a3c = a3;
+    r0mm = r0m;
+    r0m = r0k;
+    r1mm = r1m;
+    r1m = r1k;
+    cur = nxt;
+  }
+}
+
 // Trilinear interpolation of the coarse correction (colour-split, geometry
 // gc) at fine point (x,y,z).
 template <typename T>
@@ -2763,6 +2899,22 @@ hipError_t launch_restrict(int n, int red_only, const T* e0, const T* e1, const 
   if (speculate(n)) return go<ResidRestrict<T, FIN, 1>>({n, red_only, e0, e1, r0, r1, rc0, rc1, ctl}, nb, 0, s);
   return go<ResidRestrict<T, FIN, 0>>({n, red_only, e0, e1, r0, r1, rc0, rc1, ctl}, nb, 0, s);
 }
+}  // namespace
+
+bool post_sweeps_fused(const LevelBufs& b, bool fp64, int nu2) {
+  return !fp64 && nu2 == 2 && b.n == 512 && b.s0 && b.s1 && !g_recorder;
+}
+
+namespace {
+
+hipError_t launch_post_sweeps(int n, const float* e1, const float* r0, const float* r1, float* s0, float* s1, Ctl* ctl,
+                              hipStream_t s) {
+  const int nj = n / kPostRows;
+  int nz = 1;
+  while (nz < n && nj * nz < 256) nz *= 2;
+  return go<PostSweeps>({n, e1, r0, r1, s0, s1, ctl}, nj * nz, (size_t)PostGeo(n).lds_floats() * 4, s);
+}
+
 // SweepRestrict applies to single systems' FP32 fine levels of 256^3 and
 // 512^3 when the down leg is one sweep and the up leg starts with the
 // black-only prolongation.
@@ -2949,6 +3101,15 @@ hipError_t vcycle_impl(const LevelBufs* lv, int levels, int tail, int nu1, int n
       P3MZ_LAUNCH(l == 0 ? launch_prolong_black<T, 1>(n, e1, c0, c1, ctl, s)
                          : launch_prolong_black<T, 0>(n, e1, c0, c1, ctl, s));
       kt_end(KT_PROLONG, l, 1.125 * ts * n3, s);
+      if (post_sweeps_fused(lv[l], sizeof(T) == 8, nu2)) {
+        // both sweeps in one walk; the level's correction goes to s0/s1
+        rec_key(key_up(l, 2));
+        kt_begin(KT_HALFSWEEP, l, s);
+        P3MZ_LAUNCH(launch_post_sweeps(n, (const float*)e1, (const float*)r0, (const float*)r1, (float*)lv[l].s0,
+                                       (float*)lv[l].s1, ctl, s));
+        kt_end(KT_HALFSWEEP, l, 2.5 * ts * n3, s);
+        continue;
+      }
       for (int it = 0; it < nu2; it++) {
         for (int colour = 0; colour < 2; colour++) {
           T* ec = colour ? e1 : e0;
@@ -3339,6 +3500,8 @@ hipError_t fused_configure() {
   P3MZ_LAUNCH((allow_lds<Sigma<double, kColThreads>>(col)));
   P3MZ_LAUNCH((allow_lds<Outer<float, kColThreads>>(col)));
   P3MZ_LAUNCH((allow_lds<Outer<double, kColThreads>>(col)));
+  // the two post-smoothing sweeps as one walk
+  P3MZ_LAUNCH((allow_lds<PostSweeps>(PostGeo(512).lds_floats() * 4)));
   // the column-walk restriction and the fused first sweep and restriction
   P3MZ_LAUNCH((allow_lds<SweepRestrict>(std::max(SweepRestrictGeo(256, kSweepRestrictThreads).lds_floats(),
                                                   SweepRestrictGeo(512, kSweepRestrictThreads).lds_floats()) * 4)));
