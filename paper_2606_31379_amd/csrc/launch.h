@@ -143,7 +143,7 @@ struct LevelBufs {
   void* s0 = nullptr; void* s1 = nullptr;
 };
 // True when the V-cycle's post-smoothing on level buffers b runs as one
-// walk (FP32 512^3 single systems, two sweeps after the black-only
+// walk (FP32 512^3 or 256^3 finest levels of single systems, two sweeps after the black-only
 // prolongation): the level's correction after the cycle is then in s0/s1.
 bool post_sweeps_fused(const LevelBufs& b, bool fp64, int nu2);
 // The colour-split buffers holding the finest level's correction after a V-cycle.

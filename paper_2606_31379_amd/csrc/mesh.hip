@@ -1734,13 +1734,15 @@ __device__ void SweepRestrict::run(const Args& A, Grid G) {
 }
 
 // The up leg's two Gauss-Seidel sweeps after the black-only prolongation
-// (red, black, red, black half-sweeps), FP32 on a 512^3 fine level of a
-// single system, as one column walk instead of four launches: the input
-// black values e1 are read once and the final red and black values written
-// once (to s0 / s1: a workgroup reads its neighbours' input rows while they
-// write their output, so the two must differ).  A workgroup owns JB = 8
-// fine rows of a band of KB planes; its 16 thread rows are the owned rows
-// with 4 more on each side, the y-halo the four dependent half-sweeps need.
+// (red, black, red, black half-sweeps), FP32 on a 512^3 or 256^3 finest
+// level of a single system, as one column walk instead of four launches:
+// the input black values e1 are read once and the final red and black
+// values written once (to s0 / s1: a workgroup reads its neighbours' input
+// rows while they write their output, so the two must differ).  A workgroup
+// owns JB fine rows (8 on 512^3, 16 on 256^3) of a band of KB planes; its
+// JB + 8 thread rows are the owned rows with 4 more on each side, the y-halo
+// the four dependent half-sweeps need (threads beyond them only join the
+// barriers).
 // At step k the first half-sweep updates plane k, the second plane k - 1,
 // the third k - 2 and the fourth k - 3: each reads the previous half-sweep's
 // plane in LDS (written one step before) for its x- and y-neighbours and
@@ -1749,12 +1751,11 @@ __device__ void SweepRestrict::run(const Args& A, Grid G) {
 // the four launches.  One workgroup barrier per step; LDS holds two buffers
 // per half-sweep input.
 constexpr int kPostThreads = 1024;
-constexpr int kPostRows = 8;   // owned fine rows per workgroup
 struct PostGeo {
-  int nc, gx, rows;
-  __host__ __device__ explicit PostGeo(int n) : nc(n / 2), gx(n / 8), rows(kPostRows + 8) {}
-  // LDS floats: two buffers of the inputs of the four half-sweeps (16, 14, 12, 10 rows)
-  __host__ __device__ int lds_floats() const { return 2 * (4 * kPostRows + 20) * nc; }
+  int nc, gx, JB, rows;   // JB owned fine rows per workgroup, rows = JB + 8 thread rows
+  __host__ __device__ explicit PostGeo(int n) : nc(n / 2), gx(n / 8), JB(n >= 512 ? 8 : 16), rows(JB + 8) {}
+  // LDS floats: two buffers of the inputs of the four half-sweeps (JB + 8, + 6, + 4, + 2 rows)
+  __host__ __device__ int lds_floats() const { return 2 * (4 * JB + 20) * nc; }
 };
 struct PostSweeps {
   struct Args {
@@ -1769,18 +1770,19 @@ struct PostSweeps {
 __device__ void PostSweeps::run(const Args& A, Grid G) {
   using T = float;
   using V = float4;
-  constexpr int W = 4, JB = kPostRows;
+  constexpr int W = 4;
   if (A.ctl->done) return;
   const int n = A.n, msk = n - 1;
   const CsGeo g(n);
   const PostGeo pg(n);
-  const int nc = pg.nc, gx = pg.gx, cmsk = nc - 1;
+  const int nc = pg.nc, gx = pg.gx, cmsk = nc - 1, JB = pg.JB;
   const int nj = n / JB, nz = G.g / nj, KB = n / nz;
   const int jb = G.b % nj, zr = G.b / nj;
   const int j0 = jb * JB, k0 = zr * KB;
   const int tid = threadIdx.x;
   const int r = tid / gx, m0 = (tid % gx) * W;   // thread row r: fine row j0 - 4 + r
   const int y = (j0 - 4 + r) & msk;
+  const bool in0 = r < JB + 8;
   const bool in1 = r >= 1 && r < JB + 7, in2 = r >= 2 && r < JB + 6, in3 = r >= 3 && r < JB + 5;
   const bool in4 = r >= 4 && r < JB + 4;   // the workgroup's own rows
   extern __shared__ __align__(16) unsigned char ps_lds[];
@@ -1789,7 +1791,7 @@ __device__ void PostSweeps::run(const Args& A, Grid G) {
   T* const L2 = L1 + 2 * (JB + 6) * nc;         // [2][12][nc] first black
   T* const L3 = L2 + 2 * (JB + 4) * nc;         // [2][10][nc] second red
   auto at = [&](const T* a, int z) {
-    return *reinterpret_cast<const V*>(a + ((((z & msk) << g.l2) + y) << (g.l2 - 1)) + m0);
+    return in0 ? *reinterpret_cast<const V*>(a + ((((z & msk) << g.l2) + y) << (g.l2 - 1)) + m0) : V{};
   };
   auto lds_row = [&](T* base, int nrows, int buf, int row) { return base + (buf * nrows + row) * nc; };
   // Halfsweep's update of W points of this row: neighbours of the other
@@ -1817,7 +1819,7 @@ __device__ void PostSweeps::run(const Args& A, Grid G) {
   V a1m{}, a1c{}, b2m{}, b2c{}, a3m{}, a3c{};
   V r0m = at(A.r0, kb - 1), r0mm = at(A.r0, kb - 2), r1m = at(A.r1, kb - 2), r1mm = at(A.r1, kb - 3);
   V r0n = at(A.r0, kb), r1n = at(A.r1, kb - 1);
-  put(lds_row(L0, JB + 8, 0, r), ec);
+  if (in0) put(lds_row(L0, JB + 8, 0, r), ec);
   __syncthreads();
   int cur = 0;
   for (int k = kb; k <= ke; k++) {
@@ -1850,7 +1852,7 @@ __device__ void PostSweeps::run(const Args& A, Grid G) {
       if (z >= k0 && z < k0 + KB)
         *reinterpret_cast<V*>(A.s1 + ((((z & msk) << g.l2) + y) << (g.l2 - 1)) + m0) = b4;
     }
-    put(lds_row(L0, JB + 8, nxt, r), ep);   // the input's plane k + 1 for the next step
+    if (in0) put(lds_row(L0, JB + 8, nxt, r), ep);   // the input's plane k + 1 for the next step
     __syncthreads();
     em = ec;
     ec = ep;
@@ -2902,14 +2904,14 @@ hipError_t launch_restrict(int n, int red_only, const T* e0, const T* e1, const 
 }  // namespace
 
 bool post_sweeps_fused(const LevelBufs& b, bool fp64, int nu2) {
-  return !fp64 && nu2 == 2 && b.n == 512 && b.s0 && b.s1 && !g_recorder;
+  return !fp64 && nu2 == 2 && (b.n == 512 || b.n == 256) && b.s0 && b.s1 && !g_recorder;
 }
 
 namespace {
 
 hipError_t launch_post_sweeps(int n, const float* e1, const float* r0, const float* r1, float* s0, float* s1, Ctl* ctl,
                               hipStream_t s) {
-  const int nj = n / kPostRows;
+  const int nj = n / PostGeo(n).JB;
   int nz = 1;
   while (nz < n && nj * nz < 256) nz *= 2;
   return go<PostSweeps>({n, e1, r0, r1, s0, s1, ctl}, nj * nz, (size_t)PostGeo(n).lds_floats() * 4, s);
@@ -3501,7 +3503,7 @@ hipError_t fused_configure() {
   P3MZ_LAUNCH((allow_lds<Outer<float, kColThreads>>(col)));
   P3MZ_LAUNCH((allow_lds<Outer<double, kColThreads>>(col)));
   // the two post-smoothing sweeps as one walk
-  P3MZ_LAUNCH((allow_lds<PostSweeps>(PostGeo(512).lds_floats() * 4)));
+  P3MZ_LAUNCH((allow_lds<PostSweeps>(std::max(PostGeo(512).lds_floats(), PostGeo(256).lds_floats()) * 4)));
   // the column-walk restriction and the fused first sweep and restriction
   P3MZ_LAUNCH((allow_lds<SweepRestrict>(std::max(SweepRestrictGeo(256, kSweepRestrictThreads).lds_floats(),
                                                   SweepRestrictGeo(512, kSweepRestrictThreads).lds_floats()) * 4)));
