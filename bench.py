@@ -575,6 +575,8 @@ def main():
                     help="precision modes to run: fp64, mixed (FP32 V-cycle and gather), mixed32 (also an FP32 "
                          "charge source)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default (2,2) V-cycle schedule")
+    ap.add_argument("--schedule", default=None,
+                    help="NU_PRE,NU_POST: run this V-cycle schedule in every mode instead of autotuning")
     ap.add_argument("--gamma", type=float, default=None,
                     help="OVRVO thermostat friction in 1/fs at the workload's temperature (default: none)")
     ap.add_argument("--skin", type=float, default=None,
@@ -612,14 +614,20 @@ def main():
     log(f"device copy ceiling {ceiling:.0f} GB/s")
     res, tune, schedules = {}, {}, {}
     modes = args.modes.split(",")
-    if not args.no_tune and not os.environ.get("P3MZ_TUNE_CACHE"):
+    fixed = None
+    if args.schedule:
+        a, b = (int(v) for v in args.schedule.split(","))
+        fixed = dict(nu_pre=a, nu_post=b, smooth_tile=0)
+    elif args.no_tune:
+        fixed = dict(nu_pre=2, nu_post=2, smooth_tile=0)
+    if fixed is None and not os.environ.get("P3MZ_TUNE_CACHE"):
         import tempfile
         os.environ["P3MZ_TUNE_CACHE"] = os.path.join(tempfile.mkdtemp(prefix="p3mz_tune_"), "tune.json")
     for precision, name in ((0, "fp64"), (1, "mixed"), (2, "mixed32")):
         if name not in modes:
             continue
-        if args.no_tune:
-            schedules[name] = dict(nu_pre=2, nu_post=2, smooth_tile=0)
+        if fixed is not None:
+            schedules[name] = dict(fixed)
         else:
             t = time.perf_counter()
             tune[name] = autotune_schedule(torch, P, w, system, precision, args.warmup)
