@@ -589,7 +589,7 @@ p3mz_status setup(p3mz_ctx* c, const double* charges_host) {
       P3MZ_TRY(c->allocb(&b.d1, half * c->tsz));
       b.fty = b.ftz = fused_tile(nl);
     }
-    if (l == 0 && l < pl.tail && (nl == 512 || nl == 256) && !c->fp64) {   // output of the fused post-smoothing
+    if (l < pl.tail && (nl == 512 || nl == 256) && !c->fp64) {   // output of the fused post-smoothing
       P3MZ_TRY(c->allocb(&b.s0, half * c->tsz));
       P3MZ_TRY(c->allocb(&b.s1, half * c->tsz));
     }

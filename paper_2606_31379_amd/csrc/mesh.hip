@@ -3090,7 +3090,9 @@ hipError_t vcycle_impl(const LevelBufs* lv, int levels, int tail, int nu1, int n
     const int n = lv[l].n, half = n * n * n / 2, nb = blocks_for(half, kBlock);
     const double n3 = (double)n * n * n;
     T *e0 = (T*)lv[l].e0, *e1 = (T*)lv[l].e1, *r0 = (T*)lv[l].r0, *r1 = (T*)lv[l].r1;
-    const T *c0 = (const T*)lv[l + 1].e0, *c1 = (const T*)lv[l + 1].e1;
+    // the coarse level's correction (in s0/s1 when its post-smoothing ran as one walk)
+    const T* c0 = (const T*)cycle_e0(lv[l + 1], sizeof(T) == 8, nu2);
+    const T* c1 = (const T*)cycle_e1(lv[l + 1], sizeof(T) == 8, nu2);
     if (fused_level<T>(lv[l], nu1, nu2)) {
       rec_key(key_up(l, 60));
       kt_begin(KT_FUSED_UP, l, s);
