@@ -570,6 +570,8 @@ __device__ void Gather<T, TP, TS, P, HO>::run(const Args& A, Grid G) {
   __shared__ T sphi[E * E * E];
   __shared__ double part[kBlock][4];
   __shared__ double sh[kBlock / 64];
+  constexpr int kSW = 128;            // atoms of a tile whose weights are formed once, while the halo is staged
+  __shared__ T sw[kSW][3][P];
   // the new potential: written over phi^k on a cold solve, over phi^{k-1} otherwise
   const TP* __restrict__ phi = (ctl->cold ? ctl->k_idx : 1 - ctl->k_idx) ? A.phi1 : A.phi0;
   constexpr int per_round = kBlock / PE;   // atoms evaluated per round
@@ -641,12 +643,31 @@ __device__ void Gather<T, TP, TS, P, HO>::run(const Args& A, Grid G) {
 #pragma unroll
       for (int lz = 0; lz < E; lz++) sphi[lz * E * E + tid] = (T)hv[lz];
     }
+    // each atom's weights, one (atom, dimension) per thread, formed once
+    // instead of by each of the atom's plane threads
+    for (int u = tid; u < 3 * min(na_t, kSW); u += kBlock) {
+      const int ai = u / 3, d = u - 3 * ai;
+      const double4 tq = rq[a0 + ai];
+      double wl[P];
+      bspline_weights<double>(P, d == 0 ? tq.y : d == 1 ? tq.z : tq.w, wl);
+#pragma unroll
+      for (int j = 0; j < P; j++) sw[ai][d][j] = (T)wl[j];
+    }
     if (t + G.g < ntiles) fetch(t + G.g);
     __syncthreads();
     for (int ag = 0; ag < na_t; ag += per_round) {
       const int ai = ag + tid / PE, c = tid % PE;
       if (tid < per_round * PE && ai < na_t) {
-        form_weights();
+        if (ai < kSW) {
+#pragma unroll
+          for (int j = 0; j < P; j++) {
+            rwx[j] = sw[ai][0][j];
+            rwy[j] = sw[ai][1][j];
+            rwz[j] = sw[ai][2][j];
+          }
+        } else {
+          form_weights();
+        }
         // extended index j <-> stencil offset j - GR; the derivative weight of
         // point j: d[j] = (w[j-1] - w[j+1]) / 2h, or for the fourth-order
         // difference (8 (w[j-1] - w[j+1]) - (w[j-2] - w[j+2])) / 12h
