@@ -33,6 +33,10 @@ __device__ __forceinline__ void stencil_origin(double x, double box, int n, int 
 
 // Tile key of every atom (the 8^3 tile holding its first stencil index) and
 // its slot in the tile's count; a non-finite coordinate raises the NaN flag.
+// Consecutive atoms often share a tile (the sites of a molecule), so each
+// run of equal keys among consecutive lanes takes its slots with one atomic
+// add by the run's first lane (the order of slots within a tile is free: the
+// bin sort orders each tile's atoms by class and index).
 struct BinTiles {
   struct Args {
     int n_atoms, n, p, tile, ntx;
@@ -47,24 +51,43 @@ struct BinTiles {
 __device__ void BinTiles::run(const Args& A, Grid G) {
   const int n_atoms = A.n_atoms, n = A.n, p = A.p, tile = A.tile, ntx = A.ntx;
   const int a = G.b * kBlock + threadIdx.x;
-  if (a >= n_atoms) return;
-  int tk[3];
-  for (int d = 0; d < 3; d++) {
-    double x = A.pos[3 * a + d];
-    if (!isfinite(x)) {
-      A.ctl->nan_flag = 1;
-      x = 0.0;
+  const int lane = threadIdx.x & 63;
+  const bool on = a < n_atoms;
+  int k = -1 - lane;   // distinct from every key and from the other lanes' past the end
+  if (on) {
+    int tk[3];
+    for (int d = 0; d < 3; d++) {
+      double x = A.pos[3 * a + d];
+      if (!isfinite(x)) {
+        A.ctl->nan_flag = 1;
+        x = 0.0;
+      }
+      int first;
+      double tau;
+      stencil_origin(x, A.box, n, p, &first, &tau);
+      int f = first % n;
+      if (f < 0) f += n;
+      tk[d] = f / tile;
     }
-    int first;
-    double tau;
-    stencil_origin(x, A.box, n, p, &first, &tau);
-    int f = first % n;
-    if (f < 0) f += n;
-    tk[d] = f / tile;
+    k = (tk[2] * ntx + tk[1]) * ntx + tk[0];
+    A.key[a] = k;
   }
-  const int k = (tk[2] * ntx + tk[1]) * ntx + tk[0];
-  A.key[a] = k;
-  A.slot[a] = atomicAdd(&A.count[k], 1);
+  // runs of equal keys: each lane finds its run's first lane (max-scan of
+  // the run heads) and the next run's first lane (min-scan from the right)
+  const int prev = __shfl_up(k, 1, 64), next = __shfl_down(k, 1, 64);
+  const bool head = lane == 0 || prev != k;
+  const bool tail = lane == 63 || next != k;
+  int first = head ? lane : 0, last = tail ? lane : 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(first, o, 64), v = __shfl_down(last, o, 64);
+    if (lane >= o) first = max(first, u);
+    if (lane + o < 64) last = min(last, v);
+  }
+  int base = 0;
+  if (head && on) base = atomicAdd(&A.count[k], last - first + 1);
+  base = __shfl(base, first, 64);
+  if (on) A.slot[a] = base + (lane - first);
 }
 
 // Atom records in bin order, written by the bin sort: rb[i] = {stencil
@@ -369,11 +392,13 @@ __device__ void SortBins::run(const Args& A, Grid G) {
 // has no branches and no index arithmetic).  Each mesh value is a sum in a fixed order (the candidates' order)
 // formed in one register: no atomics of any kind, bitwise reproducible, and
 // the tile is written once.  The next chunk's records are loaded while the
-// current chunk is walked.  The sums are formed in FP64; TO is the stored
-// precision of q (FP64, or FP32 for the FP32 charge source).
+// current chunk is walked.  TO is the stored precision of q and the
+// precision of the sums: FP64, or FP32 for the FP32 charge source (the
+// weights are formed in FP64 and rounded once; the fixed order keeps the
+// FP32 sums reproducible).
 template <typename TO, int TS, int P>
 struct Spread {
-  using T = double;
+  using T = TO;   // weights and column sums in the stored precision
   struct Args {
     int n, ntx;
     double box;
@@ -398,7 +423,7 @@ __device__ void Spread<TO, TS, P>::run(const Args& A, Grid G) {
   const int2* __restrict__ rb = A.rb;
   const double4* __restrict__ rq = A.rq;
   TO* __restrict__ q = A.q;
-  __shared__ T sw[NW][CH * WPA];
+  __shared__ __align__(16) T sw[NW][CH * WPA];
   __shared__ int r_lo[NW][64], r_off[NW][65];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int ntiles = ntx * ntx * ntx;
@@ -473,12 +498,12 @@ __device__ void Spread<TO, TS, P>::run(const Args& A, Grid G) {
         // stencil reaches (this lane's stores land in order)
         T* wd = wi + d * TS;
 #pragma unroll
-        for (int x = 0; x < TS; x += 2) *reinterpret_cast<double2*>(wd + x) = make_double2(0.0, 0.0);
+        for (int x = 0; x < TS; x++) wd[x] = T(0);
 #pragma unroll
         for (int j = 0; j < P; j++) {
           int x = rel + j;
           if (ntx == 1) x &= n - 1;   // the tile is the whole periodic mesh
-          if ((unsigned)x < (unsigned)TS) wd[x] = d == 0 ? nq.x * wl[j] : wl[j];
+          if ((unsigned)x < (unsigned)TS) wd[x] = (T)(d == 0 ? nq.x * wl[j] : wl[j]);
         }
       }
     }
@@ -491,11 +516,22 @@ __device__ void Spread<TO, TS, P>::run(const Args& A, Grid G) {
       const T* wj = wsw + j * WPA;
       *a = wj[lx];
       *b = wj[TS + ly];
+      if constexpr (sizeof(T) == 4) {
 #pragma unroll
-      for (int z = 0; z < TS; z += 2) {
-        const double2 v = *reinterpret_cast<const double2*>(wj + 2 * TS + z);
-        wz[z] = v.x;
-        wz[z + 1] = v.y;
+        for (int z = 0; z < TS; z += 4) {
+          const float4 v = *reinterpret_cast<const float4*>(wj + 2 * TS + z);
+          wz[z] = v.x;
+          wz[z + 1] = v.y;
+          wz[z + 2] = v.z;
+          wz[z + 3] = v.w;
+        }
+      } else {
+#pragma unroll
+        for (int z = 0; z < TS; z += 2) {
+          const double2 v = *reinterpret_cast<const double2*>(wj + 2 * TS + z);
+          wz[z] = v.x;
+          wz[z + 1] = v.y;
+        }
       }
     };
     int j = 0;
