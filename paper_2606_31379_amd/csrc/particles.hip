@@ -561,8 +561,9 @@ __device__ void Spread<TO, TS, P>::run(const Args& A, Grid G) {
 
 // Gather: F = -k Q sum_n W(r - r_n) (D phi)_n with the central difference D,
 // rewritten as derivative weights on a (p+2)^3 neighbourhood, and the
-// per-atom energy 1/2 k Q (W * phi)(r).  Row sums in precision T (the
-// weights are rounded to T), accumulation over rows in FP64.
+// per-atom energy 1/2 k Q (W * phi)(r).  Sums over a z-plane of the
+// neighbourhood in precision T (the weights are rounded to T), the plane's z
+// weight and the sum over planes in FP64.
 //
 // A capped grid of workgroups walks the TS^3 tiles (the spread's bins).  For
 // each tile the potential on the tile plus its (p+1)-point halo is staged in
@@ -607,6 +608,7 @@ __device__ void Gather<T, TP, TS, P, HO>::run(const Args& A, Grid G) {
   __shared__ double part[kBlock][4];
   __shared__ double sh[kBlock / 64];
   constexpr int kSW = 128;            // atoms of a tile whose weights are formed once, while the halo is staged
+  static_assert(kSW <= kBlock, "one thread per staged atom record");
   __shared__ T sw[kSW][3][P];
   // the new potential: written over phi^k on a cold solve, over phi^{k-1} otherwise
   const TP* __restrict__ phi = (ctl->cold ? ctl->k_idx : 1 - ctl->k_idx) ? A.phi1 : A.phi0;
@@ -616,11 +618,25 @@ __device__ void Gather<T, TP, TS, P, HO>::run(const Args& A, Grid G) {
   const int tid = threadIdx.x;
   double e_sum = 0.0;
   const int ntiles = ntx * ntx * ntx;
-  // The next tile's halo column (this thread's (x, y) position, all z) and
-  // atom range are loaded into registers while the current tile is being
-  // evaluated, so a tile waits for memory only once.
+  // Everything a tile starts with is loaded into registers while the
+  // previous tile is evaluated: its halo column (this thread's (x, y)
+  // position, all z), the fractional offset of this thread's (atom,
+  // dimension) weight task, and atom tid's origin, index and charge.  Their
+  // addresses need the tile's atom range, which is loaded one tile further
+  // ahead.  The staging phase moves them into LDS (weights, records), so the
+  // rounds use no register whose load may still be in flight: the compiler
+  // cannot follow such a load round the loop and waits for every load there,
+  // the next tile's halo included.
   TP hv[E];
-  int nlo = 0, nhi = 0;
+  double tw = 0.0;                       // weight task tid: atom tid / 3, dimension tid % 3
+  int p_org = 0, p_ka = 0;               // atom tid: stencil origin, atom index
+  double p_q = 0.0;                      // atom tid: charge
+  int cur_lo = 0, cur_hi = 0;            // atom range of the tile being prefetched
+  // the tile after it: lane 0 holds its start, lane 1 its end (a vector
+  // load: a scalar load would be waited for at the next barrier)
+  int nxt = 0;
+  __shared__ int s_org[kSW], s_ka[kSW];
+  __shared__ double s_q[kSW];
   auto fetch = [&](int t) {
     const int tx = t % ntx, ty = (t / ntx) % ntx, tz = t / (ntx * ntx);
     const int ox = tx * TS - GR, oy = ty * TS - GR, oz = tz * TS - GR;   // halo origin
@@ -630,153 +646,167 @@ __device__ void Gather<T, TP, TS, P, HO>::run(const Args& A, Grid G) {
 #pragma unroll
       for (int lz = 0; lz < E; lz++) hv[lz] = col[(size_t)((oz + lz) & (n - 1)) * n * n];
     }
-    nlo = start[t];
-    nhi = start[t + 1];
-  };
-  // One round: thread task = (atom ai, z-plane c of its neighbourhood); its
-  // weights and stencil origin are loaded ahead of the evaluation.  Threads
-  // k < per_round also hold atom k's index and charge for the final sums.
-  T rwx[P], rwy[P], rwz[P];
-  int rorg = 0;
-  int ka = 0;
-  double kq = 0.0;
-  double4 rtau = make_double4(0.0, 0.0, 0.0, 0.0);
-  // the round's records are loaded ahead; the weights are formed from the
-  // fractional offsets (FP64, then rounded to T) right before the round
-  auto load_round = [&](int a0, int na_t, int ag) {
-    const int ai = ag + tid / PE;
-    if (tid < per_round * PE && ai < na_t) {
-      const int ps = a0 + ai;
-      rtau = rq[ps];
-      rorg = rb[ps].x;
+    const int na = cur_hi - cur_lo;
+    if (tid < 3 * min(na, kSW)) {
+      const int ai = tid / 3, d = tid - 3 * ai;
+      tw = reinterpret_cast<const double*>(rq + cur_lo + ai)[1 + d];
     }
-    if (tid < per_round && ag + tid < na_t) {
-      const int ps = a0 + ag + tid;
-      ka = rb[ps].y;
-      kq = k_e * rq[ps].x;
+    if (tid < min(na, kSW)) {
+      const int2 r = rb[cur_lo + tid];
+      p_org = r.x;
+      p_ka = r.y;
+      p_q = rq[cur_lo + tid].x;
     }
   };
-  auto form_weights = [&]() {
-    double wl[P];
-    bspline_weights<double>(P, rtau.y, wl);
-#pragma unroll
-    for (int j = 0; j < P; j++) rwx[j] = (T)wl[j];
-    bspline_weights<double>(P, rtau.z, wl);
-#pragma unroll
-    for (int j = 0; j < P; j++) rwy[j] = (T)wl[j];
-    bspline_weights<double>(P, rtau.w, wl);
-#pragma unroll
-    for (int j = 0; j < P; j++) rwz[j] = (T)wl[j];
-  };
-  if (G.b < ntiles) fetch(G.b);
+  if (G.b < ntiles) {
+    cur_lo = start[G.b];
+    cur_hi = start[G.b + 1];
+    fetch(G.b);
+    if (G.b + G.g < ntiles) nxt = start[G.b + G.g + (tid & 1)];
+  }
   for (int t = G.b; t < ntiles; t += G.g) {
     const int tx = t % ntx, ty = (t / ntx) % ntx, tz = t / (ntx * ntx);
     const int ox = tx * TS - GR, oy = ty * TS - GR, oz = tz * TS - GR;   // halo origin
-    const int a0 = nlo, na_t = nhi - nlo;
-    load_round(a0, na_t, 0);
+    const int a0 = cur_lo, na_t = cur_hi - cur_lo;
     __syncthreads();   // the previous tile's LDS reads are done
     if (tid < E * E) {
 #pragma unroll
       for (int lz = 0; lz < E; lz++) sphi[lz * E * E + tid] = (T)hv[lz];
     }
+    if (tid < min(na_t, kSW)) {
+      s_org[tid] = p_org;
+      s_ka[tid] = p_ka;
+      s_q[tid] = p_q;
+    }
     // each atom's weights, one (atom, dimension) per thread, formed once
-    // instead of by each of the atom's plane threads
+    // instead of by each of the atom's plane threads (tasks past the first
+    // kBlock, in tiles of more than kBlock / 3 atoms, load their offset here)
     for (int u = tid; u < 3 * min(na_t, kSW); u += kBlock) {
       const int ai = u / 3, d = u - 3 * ai;
-      const double4 tq = rq[a0 + ai];
+      const double x = u == tid ? tw : reinterpret_cast<const double*>(rq + a0 + ai)[1 + d];
       double wl[P];
-      bspline_weights<double>(P, d == 0 ? tq.y : d == 1 ? tq.z : tq.w, wl);
+      bspline_weights<double>(P, x, wl);
 #pragma unroll
       for (int j = 0; j < P; j++) sw[ai][d][j] = (T)wl[j];
     }
-    if (t + G.g < ntiles) fetch(t + G.g);
+    if (t + G.g < ntiles) {
+      cur_lo = __builtin_amdgcn_readlane(nxt, 0);
+      cur_hi = __builtin_amdgcn_readlane(nxt, 1);
+      fetch(t + G.g);
+      if (t + 2 * G.g < ntiles) nxt = start[t + 2 * G.g + (tid & 1)];
+    }
     __syncthreads();
-    for (int ag = 0; ag < na_t; ag += per_round) {
-      const int ai = ag + tid / PE, c = tid % PE;
-      if (tid < per_round * PE && ai < na_t) {
-        if (ai < kSW) {
+    // the tile's atoms in chunks of kSW staged records and weights; a chunk
+    // after the first (tiles of more than kSW atoms) is staged here, from
+    // memory
+    for (int c0 = 0; c0 < na_t; c0 += kSW) {
+      const int nc = min(kSW, na_t - c0);
+      if (c0 > 0) {
+        __syncthreads();   // the previous chunk's LDS reads are done
+        if (tid < nc) {
+          const int ps = a0 + c0 + tid;
+          const int2 r = rb[ps];
+          s_org[tid] = r.x;
+          s_ka[tid] = r.y;
+          s_q[tid] = rq[ps].x;
+        }
+        for (int u = tid; u < 3 * nc; u += kBlock) {
+          const int ai = u / 3, d = u - 3 * ai;
+          double wl[P];
+          bspline_weights<double>(P, reinterpret_cast<const double*>(rq + a0 + c0 + ai)[1 + d], wl);
+#pragma unroll
+          for (int j = 0; j < P; j++) sw[ai][d][j] = (T)wl[j];
+        }
+        __syncthreads();
+      }
+      for (int ag = 0; ag < nc; ag += per_round) {
+        const int ai = ag + tid / PE, c = tid % PE;
+        if (tid < per_round * PE && ai < nc) {
+          T rwx[P], rwy[P], rwz[P];
 #pragma unroll
           for (int j = 0; j < P; j++) {
             rwx[j] = sw[ai][0][j];
             rwy[j] = sw[ai][1][j];
             rwz[j] = sw[ai][2][j];
           }
-        } else {
-          form_weights();
-        }
-        // extended index j <-> stencil offset j - GR; the derivative weight of
-        // point j: d[j] = (w[j-1] - w[j+1]) / 2h, or for the fourth-order
-        // difference (8 (w[j-1] - w[j+1]) - (w[j-2] - w[j+2])) / 12h
-        T wx[PE], wy[PE], dx[PE], dy[PE], wz[PE];
-#pragma unroll
-        for (int j = 0; j < PE; j++) {
-          wx[j] = (j >= GR && j < GR + P) ? rwx[j - GR] : T(0);
-          wy[j] = (j >= GR && j < GR + P) ? rwy[j - GR] : T(0);
-          wz[j] = (j >= GR && j < GR + P) ? rwz[j - GR] : T(0);
-        }
-        auto dif = [&](const T* w, int j) -> T {
-          const T lo = j >= 1 ? w[j - 1] : T(0), hi = j + 1 < PE ? w[j + 1] : T(0);
-          if constexpr (HO == 0) {
-            return (lo - hi) * inv2h;
-          } else {
-            const T lo2 = j >= 2 ? w[j - 2] : T(0), hi2 = j + 2 < PE ? w[j + 2] : T(0);
-            return (T(8) * (lo - hi) - (lo2 - hi2)) * inv12h;
-          }
-        };
-#pragma unroll
-        for (int j = 0; j < PE; j++) {
-          dx[j] = dif(wx, j);
-          dy[j] = dif(wy, j);
-        }
-        T wz_c = T(0), dz_c = T(0);
-#pragma unroll
-        for (int j = 0; j < PE; j++)
-          if (j == c) {
-            wz_c = wz[j];
-            dz_c = dif(wz, j);
-          }
-        // neighbourhood origin in the halo tile: base - GR - (tile origin - GR)
-        const int lx0 = org_x(rorg) - (ox + GR), ly0 = org_y(rorg) - (oy + GR), lz0 = org_z(rorg) - (oz + GR);
-        double fx = 0, fy = 0, fz = 0, pot = 0;
-        const T* plane = sphi + (lz0 + c) * E * E;
-#pragma unroll
-        for (int b = 0; b < PE; b++) {
-          const T* row = plane + (ly0 + b) * E + lx0;
-          T sx = T(0), s0 = T(0);
+          const int rorg = s_org[ai];
+          // extended index j <-> stencil offset j - GR; the derivative weight of
+          // point j: d[j] = (w[j-1] - w[j+1]) / 2h, or for the fourth-order
+          // difference (8 (w[j-1] - w[j+1]) - (w[j-2] - w[j+2])) / 12h
+          T wx[PE], wy[PE], dx[PE], dy[PE], wz[PE];
 #pragma unroll
           for (int j = 0; j < PE; j++) {
-            const T v = row[j];
-            sx += dx[j] * v;
-            s0 += wx[j] * v;
+            wx[j] = (j >= GR && j < GR + P) ? rwx[j - GR] : T(0);
+            wy[j] = (j >= GR && j < GR + P) ? rwy[j - GR] : T(0);
+            wz[j] = (j >= GR && j < GR + P) ? rwz[j - GR] : T(0);
           }
-          fx += (double)(wy[b] * wz_c) * (double)sx;
-          fy += (double)(dy[b] * wz_c) * (double)s0;
-          fz += (double)(wy[b] * dz_c) * (double)s0;
-          pot += (double)(wy[b] * wz_c) * (double)s0;
+          auto dif = [&](const T* w, int j) -> T {
+            const T lo = j >= 1 ? w[j - 1] : T(0), hi = j + 1 < PE ? w[j + 1] : T(0);
+            if constexpr (HO == 0) {
+              return (lo - hi) * inv2h;
+            } else {
+              const T lo2 = j >= 2 ? w[j - 2] : T(0), hi2 = j + 2 < PE ? w[j + 2] : T(0);
+              return (T(8) * (lo - hi) - (lo2 - hi2)) * inv12h;
+            }
+          };
+#pragma unroll
+          for (int j = 0; j < PE; j++) {
+            dx[j] = dif(wx, j);
+            dy[j] = dif(wy, j);
+          }
+          T wz_c = T(0), dz_c = T(0);
+#pragma unroll
+          for (int j = 0; j < PE; j++)
+            if (j == c) {
+              wz_c = wz[j];
+              dz_c = dif(wz, j);
+            }
+          // neighbourhood origin in the halo tile: base - GR - (tile origin - GR)
+          const int lx0 = org_x(rorg) - (ox + GR), ly0 = org_y(rorg) - (oy + GR), lz0 = org_z(rorg) - (oz + GR);
+          // the plane's sums: gx = sum_b w_y[b] (d_x . row b), gy = sum_b
+          // d_y[b] (w_x . row b), g0 = sum_b w_y[b] (w_x . row b); the
+          // plane's z factor is applied once, in FP64
+          T gx = T(0), gy = T(0), g0 = T(0);
+          const T* plane = sphi + (lz0 + c) * E * E;
+#pragma unroll
+          for (int b = 0; b < PE; b++) {
+            const T* row = plane + (ly0 + b) * E + lx0;
+            T sx = T(0), s0 = T(0);
+#pragma unroll
+            for (int j = 0; j < PE; j++) {
+              const T v = row[j];
+              sx += dx[j] * v;
+              s0 += wx[j] * v;
+            }
+            gx += wy[b] * sx;
+            gy += dy[b] * s0;
+            g0 += wy[b] * s0;
+          }
+          part[tid][0] = (double)wz_c * (double)gx;
+          part[tid][1] = (double)wz_c * (double)gy;
+          part[tid][2] = (double)dz_c * (double)g0;
+          part[tid][3] = (double)wz_c * (double)g0;
         }
-        part[tid][0] = fx;
-        part[tid][1] = fy;
-        part[tid][2] = fz;
-        part[tid][3] = pot;
+        __syncthreads();
+        if (tid < per_round && ag + tid < nc) {
+          double fx = 0, fy = 0, fz = 0, pot = 0;
+          for (int cc = 0; cc < PE; cc++) {
+            fx += part[tid * PE + cc][0];
+            fy += part[tid * PE + cc][1];
+            fz += part[tid * PE + cc][2];
+            pot += part[tid * PE + cc][3];
+          }
+          const int ka = s_ka[ag + tid];
+          const double kqe = k_e * s_q[ag + tid];
+          if (force) {
+            force[3 * ka] = -kqe * fx;
+            force[3 * ka + 1] = -kqe * fy;
+            force[3 * ka + 2] = -kqe * fz;
+          }
+          e_sum += 0.5 * kqe * pot;
+        }
+        __syncthreads();
       }
-      __syncthreads();
-      if (tid < per_round && ag + tid < na_t) {
-        double fx = 0, fy = 0, fz = 0, pot = 0;
-        for (int cc = 0; cc < PE; cc++) {
-          fx += part[tid * PE + cc][0];
-          fy += part[tid * PE + cc][1];
-          fz += part[tid * PE + cc][2];
-          pot += part[tid * PE + cc][3];
-        }
-        if (force) {
-          force[3 * ka] = -kq * fx;
-          force[3 * ka + 1] = -kq * fy;
-          force[3 * ka + 2] = -kq * fz;
-        }
-        e_sum += 0.5 * kq * pot;
-      }
-      if (ag + per_round < na_t) load_round(a0, na_t, ag + per_round);
-      __syncthreads();
     }
   }
   double bs = block_sum(e_sum, sh);
