@@ -341,6 +341,9 @@ __device__ void SortBins::run(const Args& A, Grid G) {
     const int i = i0 + lane;
     int f3[3];
     double tau3[3];
+    // the entry's charge is loaded with its position, ahead of the ranking
+    double qi = 0.0;
+    if (mesh && i < cnt) qi = A.qa[perm_raw[s0 + i]];
     const long long v = key_of(i, f3, tau3);
     int rank = 0;
     for (int j0 = 0; j0 < cnt; j0 += 64) {
@@ -357,7 +360,7 @@ __device__ void SortBins::run(const Args& A, Grid G) {
       const int a = (int)(v & 0xffffffffLL);
       if (mesh) {
         A.rb[s0 + rank] = make_int2(org_pack(f3[0], f3[1], f3[2]), a);
-        A.rq[s0 + rank] = make_double4(A.qa[a], tau3[0], tau3[1], tau3[2]);
+        A.rq[s0 + rank] = make_double4(qi, tau3[0], tau3[1], tau3[2]);
       } else {
         A.perm[s0 + rank] = a;
       }
