@@ -1,6 +1,7 @@
 // Particle-side kernels: binning, deterministic bin sort, owner-computes
 // charge spread, force/energy gather and the short-range pair term.
 #include <algorithm>
+#include <type_traits>
 
 #include "kern.h"
 #include "launch.h"
@@ -384,15 +385,18 @@ __device__ void SortBins::run(const Args& A, Grid G) {
 // (d in {0,1}^3), those whose class (the faces their stencil crosses)
 // contains d: at most 27 contiguous ranges of class-sorted bins.
 //
-// One wave per tile, one lane per (x, y) column of it, the column's TS
+// One wave per tile, one lane per 2x2x2 block of it, the block's eight
 // values held in registers.  The tile's candidate atoms are staged in the
 // wave's part of LDS in chunks of 64 (ranges, then positions), one atom per
 // lane, which also forms the atom's B-spline weights laid out over the
 // tile: q w_x at the TS x-positions, w_y and w_z likewise, zero where the
 // stencil does not reach; the lanes then walk the staged atoms in order and
-// every lane adds the atom's terms ((q w_x) w_y) w_z to its column, reading
-// its own x and y entries (exact zeros outside the atom's reach, so the walk
-// has no branches and no index arithmetic).  Each mesh value is a sum in a fixed order (the candidates' order)
+// every lane adds the atom's terms ((q w_x) w_y) w_z to its block, reading
+// its own pair of entries along each axis (exact zeros outside the atom's
+// reach, so the walk has no branches and no index arithmetic).  A block per
+// lane instead of a column cuts the LDS bytes a lane reads per atom from
+// 10 to 6 values (the walk is bound by LDS, the z weights being read by
+// every lane).  Each mesh value is a sum in a fixed order (the candidates' order)
 // formed in one register: no atomics of any kind, bitwise reproducible, and
 // the tile is written once.  The next chunk's records are loaded while the
 // current chunk is walked.  TO is the stored precision of q and the
@@ -416,7 +420,7 @@ struct Spread {
 };
 template <typename TO, int TS, int P>
 __device__ void Spread<TO, TS, P>::run(const Args& A, Grid G) {
-  static_assert(TS * TS == 64, "one lane per column of the tile");
+  static_assert(TS == 8, "one lane per 2x2x2 block of the tile");
   // per atom: q w_x, w_y and w_z each laid out over the tile's TS positions
   // along its axis (zero where the stencil does not reach)
   constexpr int NW = kBlock / 64, CH = kChunk, WPA = 3 * TS;
@@ -434,7 +438,9 @@ __device__ void Spread<TO, TS, P>::run(const Args& A, Grid G) {
   if (t >= ntiles) return;   // per wave: the kernel has no workgroup barriers
   const int tx = t % ntx, ty = (t / ntx) % ntx, tz = t / (ntx * ntx);
   const int ox = tx * TS, oy = ty * TS, oz = tz * TS;
-  const int lx = lane % TS, ly = lane / TS;
+  // this lane's 2x2x2 block of the tile: x = 2 xp + {0, 1}, y = 2 yp + {0,
+  // 1}, z = 2 zp + {0, 1}
+  const int xp = lane & 3, yp = (lane >> 2) & 3, zp = lane >> 4;
   // the ranges: lane k = (d, c), d = k >> 3 the lower neighbour, c = k & 7
   // the class; used when c contains d (all classes of the tile's own bin;
   // with one tile per axis, only the own bin)
@@ -480,9 +486,9 @@ __device__ void Spread<TO, TS, P>::run(const Args& A, Grid G) {
       nq = rq[ps];
     }
   };
-  T acc[TS];
+  T acc[2][2][2];   // [x][y][z] within the lane's block
 #pragma unroll
-  for (int z = 0; z < TS; z++) acc[z] = T(0);
+  for (int u = 0; u < 8; u++) acc[u >> 2][(u >> 1) & 1][u & 1] = T(0);
   fetch(0);
   T* const wsw = sw[wv];
   for (int c0 = 0; c0 < tot; c0 += CH) {
@@ -513,53 +519,53 @@ __device__ void Spread<TO, TS, P>::run(const Args& A, Grid G) {
     // the wave's LDS stores precede its loads below (one wave, in order)
     __builtin_amdgcn_wave_barrier();
     if (c0 + CH < tot) fetch(c0 + CH);
-    // one staged atom's terms for this lane's column: (q w_x) w_y times w_z
-    // at each z
-    auto load_atom = [&](int j, T* a, T* b, T* wz) {
+    // one staged atom's entries for this lane's block: q w_x at its two x,
+    // w_y at its two y and w_z at its two z positions (8-byte aligned pairs)
+    using V2 = typename std::conditional<sizeof(T) == 4, float2, double2>::type;
+    auto load_atom = [&](int j, V2* a, V2* b, V2* c) {
       const T* wj = wsw + j * WPA;
-      *a = wj[lx];
-      *b = wj[TS + ly];
-      if constexpr (sizeof(T) == 4) {
+      *a = *reinterpret_cast<const V2*>(wj + 2 * xp);
+      *b = *reinterpret_cast<const V2*>(wj + TS + 2 * yp);
+      *c = *reinterpret_cast<const V2*>(wj + 2 * TS + 2 * zp);
+    };
+    // the atom's terms ((q w_x) w_y) w_z at the block's eight points
+    auto add_atom = [&](const V2& a, const V2& b, const V2& c) {
+      const T ax[2] = {a.x, a.y}, by[2] = {b.x, b.y}, cz[2] = {c.x, c.y};
 #pragma unroll
-        for (int z = 0; z < TS; z += 4) {
-          const float4 v = *reinterpret_cast<const float4*>(wj + 2 * TS + z);
-          wz[z] = v.x;
-          wz[z + 1] = v.y;
-          wz[z + 2] = v.z;
-          wz[z + 3] = v.w;
-        }
-      } else {
+      for (int i = 0; i < 2; i++)
 #pragma unroll
-        for (int z = 0; z < TS; z += 2) {
-          const double2 v = *reinterpret_cast<const double2*>(wj + 2 * TS + z);
-          wz[z] = v.x;
-          wz[z + 1] = v.y;
+        for (int k = 0; k < 2; k++) {
+          const T txy = ax[i] * by[k];
+#pragma unroll
+          for (int l = 0; l < 2; l++) acc[i][k][l] += txy * cz[l];
         }
-      }
     };
     int j = 0;
     for (; j + 1 < m; j += 2) {   // two atoms' loads in flight, added in order
-      T a[2], b[2], wz[2][TS];
-      load_atom(j, &a[0], &b[0], wz[0]);
-      load_atom(j + 1, &a[1], &b[1], wz[1]);
-#pragma unroll
-      for (int u = 0; u < 2; u++) {
-        const T txy = a[u] * b[u];
-#pragma unroll
-        for (int z = 0; z < TS; z++) acc[z] += txy * wz[u][z];
-      }
+      V2 a[2], b[2], c[2];
+      load_atom(j, &a[0], &b[0], &c[0]);
+      load_atom(j + 1, &a[1], &b[1], &c[1]);
+      add_atom(a[0], b[0], c[0]);
+      add_atom(a[1], b[1], c[1]);
     }
     if (j < m) {
-      T a, b, wz[TS];
-      load_atom(j, &a, &b, wz);
-      const T txy = a * b;
-#pragma unroll
-      for (int z = 0; z < TS; z++) acc[z] += txy * wz[z];
+      V2 a, b, c;
+      load_atom(j, &a, &b, &c);
+      add_atom(a, b, c);
     }
     __builtin_amdgcn_wave_barrier();
   }
+  // two consecutive x values per store (ox + 2 xp is even)
+  using O2 = typename std::conditional<sizeof(TO) == 4, float2, double2>::type;
 #pragma unroll
-  for (int z = 0; z < TS; z++) q[nat_idx(n, ox + lx, oy + ly, oz + z)] = (TO)acc[z];
+  for (int k = 0; k < 2; k++)
+#pragma unroll
+    for (int l = 0; l < 2; l++) {
+      O2 v;
+      v.x = (TO)acc[0][k][l];
+      v.y = (TO)acc[1][k][l];
+      *reinterpret_cast<O2*>(q + nat_idx(n, ox + 2 * xp, oy + 2 * yp + k, oz + 2 * zp + l)) = v;
+    }
 }
 
 // Gather: F = -k Q sum_n W(r - r_n) (D phi)_n with the central difference D,
