@@ -19,6 +19,7 @@
 // packed arguments to the recorder instead, under the current sequence key,
 // so the batch can merge the launch sequences of all its systems by key.
 #pragma once
+#include <type_traits>
 
 #include <cstddef>
 #include <cstring>
@@ -48,15 +49,26 @@ struct Packed {
   int off;    // first workgroup of this system in the batched grid
 };
 
+// Occupancy floor of a kernel family: K::kWavesPerEu waves per SIMD when
+// it names one (the register budget follows), else none.
+template <class K, class = void>
+struct WavesPerEu {
+  static constexpr int v = 1;
+};
 template <class K>
-__global__ void __launch_bounds__(K::kThreads) k_one(typename K::Args a) {
+struct WavesPerEu<K, std::void_t<decltype(K::kWavesPerEu)>> {
+  static constexpr int v = K::kWavesPerEu;
+};
+
+template <class K>
+__global__ void __launch_bounds__(K::kThreads, WavesPerEu<K>::v) k_one(typename K::Args a) {
   K::run(a, Grid{xcd_block(), (int)gridDim.x});
 }
 
 // The XCD renumbering runs over the whole batched grid, so each system's
 // workgroups stay on few XCDs, in logical order.
 template <class K>
-__global__ void __launch_bounds__(K::kThreads) k_many(const Packed<K>* __restrict__ p, int count) {
+__global__ void __launch_bounds__(K::kThreads, WavesPerEu<K>::v) k_many(const Packed<K>* __restrict__ p, int count) {
   const int lam = xcd_block();
   int lo = 0, hi = count - 1;   // last system whose first workgroup is <= lam (uniform)
   while (lo < hi) {
