@@ -319,15 +319,11 @@ struct SortBins {
   static constexpr int kThreads = kBlock;
   __device__ static void run(const Args& A, Grid G);
 };
-__device__ void SortBins::run(const Args& A, Grid G) {
-  if (A.gate && !*A.gate) return;
-  const int nbins = A.nbins;
+// One bin, any size, in chunks of 64 entries.
+__device__ void sort_one_bin(const SortBins::Args& A, int bin, int lane) {
   const int* __restrict__ start = A.start;
   const int* __restrict__ perm_raw = A.perm_raw;
-  const int wave = (G.b * kBlock + threadIdx.x) >> 6;
-  const int lane = threadIdx.x & 63;
-  if (wave >= nbins) return;
-  const int s0 = start[wave], cnt = start[wave + 1] - s0;
+  const int s0 = start[bin], cnt = start[bin + 1] - s0;
   const bool mesh = A.rb != nullptr;
   // key of entry i: (class << 32) | atom index (class 0 for the cell bins)
   auto key_of = [&](int i, int* f3, double* tau3) -> long long {
@@ -372,9 +368,92 @@ __device__ void SortBins::run(const Args& A, Grid G) {
   if (mesh && lane == 0) {
     int off = s0;
     for (int c = 0; c < 8; c++) {
-      A.cls[8 * wave + c] = off;
+      A.cls[8 * bin + c] = off;
       off += ncls[c];
     }
+  }
+}
+
+// Stencil origin (wrapped first index) and fractional offsets of an atom
+// from its already loaded coordinates (the steps of atom_origin).
+__device__ __forceinline__ void origin_of(const double x3[3], int n, int p, double box, int f3[3], double tau3[3]) {
+  for (int d = 0; d < 3; d++) {
+    const double x = isfinite(x3[d]) ? x3[d] : 0.0;
+    int first;
+    stencil_origin(x, box, n, p, &first, &tau3[d]);
+    int f = first % n;
+    if (f < 0) f += n;
+    f3[d] = f;
+  }
+}
+
+__device__ void SortBins::run(const Args& A, Grid G) {
+  if (A.gate && !*A.gate) return;
+  const int nbins = A.nbins;
+  const int wave = (G.b * kBlock + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (!A.rb) {   // cell bins: one per wave
+    if (wave < nbins) sort_one_bin(A, wave, lane);
+    return;
+  }
+  // Tile bins: two adjacent bins per wave.  The sort of one small bin is a
+  // chain of dependent loads (range, entries, positions) with little work
+  // between; when both bins fit a wave, the two chains run side by side.
+  const int b0 = 2 * wave;
+  if (b0 >= nbins) return;
+  const bool two = b0 + 1 < nbins;
+  const int s0 = A.start[b0], s1 = A.start[b0 + 1], s2 = two ? A.start[b0 + 2] : s1;
+  const int c0 = s1 - s0, c1 = s2 - s1;
+  if (c0 > 64 || c1 > 64) {
+    sort_one_bin(A, b0, lane);
+    if (two) sort_one_bin(A, b0 + 1, lane);
+    return;
+  }
+  const int* __restrict__ perm_raw = A.perm_raw;
+  const bool in0 = lane < c0, in1 = lane < c1;
+  int a0 = 0, a1 = 0;
+  if (in0) a0 = perm_raw[s0 + lane];
+  if (in1) a1 = perm_raw[s1 + lane];
+  double x0[3] = {0.0, 0.0, 0.0}, x1[3] = {0.0, 0.0, 0.0}, q0 = 0.0, q1 = 0.0;
+  if (in0) {
+    q0 = A.qa[a0];
+    for (int d = 0; d < 3; d++) x0[d] = A.pos[3 * a0 + d];
+  }
+  if (in1) {
+    q1 = A.qa[a1];
+    for (int d = 0; d < 3; d++) x1[d] = A.pos[3 * a1 + d];
+  }
+  int f0[3], f1[3];
+  double t0[3], t1[3];
+  origin_of(x0, A.n, A.p, A.box, f0, t0);
+  origin_of(x1, A.n, A.p, A.box, f1, t1);
+  constexpr long long kNone = 0x7fffffffffffffffLL;
+  const long long v0 = in0 ? ((long long)cross_class(f0, A.tile, A.p) << 32) | (long long)a0 : kNone;
+  const long long v1 = in1 ? ((long long)cross_class(f1, A.tile, A.p) << 32) | (long long)a1 : kNone;
+  int r0 = 0, r1 = 0;
+  for (int jj = 0; jj < max(c0, c1); jj++) {
+    const long long u0 = __shfl(v0, jj, 64), u1 = __shfl(v1, jj, 64);
+    r0 += (u0 < v0);   // entries past the bin hold kNone: never smaller
+    r1 += (u1 < v1);
+  }
+  if (in0) {
+    A.rb[s0 + r0] = make_int2(org_pack(f0[0], f0[1], f0[2]), a0);
+    A.rq[s0 + r0] = make_double4(q0, t0[0], t0[1], t0[2]);
+  }
+  if (in1) {
+    A.rb[s1 + r1] = make_int2(org_pack(f1[0], f1[1], f1[2]), a1);
+    A.rq[s1 + r1] = make_double4(q1, t1[0], t1[1], t1[2]);
+  }
+  int off0 = s0, off1 = s1;
+  for (int c = 0; c < 8; c++) {
+    const int k0 = __popcll(__ballot(in0 && (int)(v0 >> 32) == c));
+    const int k1 = __popcll(__ballot(in1 && (int)(v1 >> 32) == c));
+    if (lane == 0) {
+      A.cls[8 * b0 + c] = off0;
+      if (two) A.cls[8 * b0 + 8 + c] = off1;
+    }
+    off0 += k0;
+    off1 += k1;
   }
 }
 
@@ -1333,9 +1412,10 @@ hipError_t launch_sort_bins(int nbins, const int* start, const int* perm_raw, in
 hipError_t launch_sort_pack(int nbins, const int* start, const int* perm_raw, int n_atoms, const double* pos,
                             const double* qa, double box, int n, int p, int tile, void* rb, void* rq, int* cls,
                             hipStream_t s) {
+  // two tile bins per wave
   return go<SortBins>({nbins, start, perm_raw, nullptr, n_atoms, n, p, tile, box, pos, qa, (int2*)rb, (double4*)rq,
                        cls, nullptr},
-                      blocks_for((int64_t)nbins * 64, kBlock), 0, s);
+                      blocks_for((int64_t)((nbins + 1) / 2) * 64, kBlock), 0, s);
 }
 
 namespace {
