@@ -675,7 +675,9 @@ struct Gather {
     const Ctl* gate;   // non-null: do nothing unless gate->done (solve converged)
   };
   static constexpr int kThreads = kBlock;
-  static constexpr int kWavesPerEu = sizeof(T) == 4 ? 5 : 3;   // five workgroups per CU in FP32
+  // occupancy floor where the registers allow it (p = 5 second order: five
+  // workgroups per CU in FP32, three in FP64)
+  static constexpr int kWavesPerEu = ((P <= 5 && HO == 0) || P <= 4) ? (sizeof(T) == 4 ? 5 : 3) : 1;
   static constexpr int GR = 1 + HO;          // reach of the difference
   static constexpr int E = TS + P - 1 + 2 * GR;   // halo tile edge
   static constexpr int PE = P + 2 * GR;      // neighbourhood edge (stencil plus the difference)
