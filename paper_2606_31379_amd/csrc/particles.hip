@@ -709,6 +709,8 @@ __device__ void Gather<T, TP, TS, P, HO>::run(const Args& A, Grid G) {
   const int tid = threadIdx.x;
   double e_sum = 0.0;
   const int ntiles = ntx * ntx * ntx;
+  // ntx = n / 8 is a power of two: tile coordinates by shifts and masks
+  const int lt = __builtin_ctz(ntx), tm = ntx - 1;
   // Everything a tile starts with is loaded into registers while the
   // previous tile is evaluated: its halo column (this thread's (x, y)
   // position, all z), the fractional offset of this thread's (atom,
@@ -729,7 +731,7 @@ __device__ void Gather<T, TP, TS, P, HO>::run(const Args& A, Grid G) {
   __shared__ int s_org[kSW], s_ka[kSW];
   __shared__ double s_q[kSW];
   auto fetch = [&](int t) {
-    const int tx = t % ntx, ty = (t / ntx) % ntx, tz = t / (ntx * ntx);
+    const int tx = t & tm, ty = (t >> lt) & tm, tz = t >> (2 * lt);
     const int ox = tx * TS - GR, oy = ty * TS - GR, oz = tz * TS - GR;   // halo origin
     if (tid < E * E) {
       const int lx = tid % E, ly = tid / E;
@@ -756,7 +758,7 @@ __device__ void Gather<T, TP, TS, P, HO>::run(const Args& A, Grid G) {
     if (G.b + G.g < ntiles) nxt = start[G.b + G.g + (tid & 1)];
   }
   for (int t = G.b; t < ntiles; t += G.g) {
-    const int tx = t % ntx, ty = (t / ntx) % ntx, tz = t / (ntx * ntx);
+    const int tx = t & tm, ty = (t >> lt) & tm, tz = t >> (2 * lt);
     const int ox = tx * TS - GR, oy = ty * TS - GR, oz = tz * TS - GR;   // halo origin
     const int a0 = cur_lo, na_t = cur_hi - cur_lo;
     __syncthreads();   // the previous tile's LDS reads are done
@@ -1467,7 +1469,7 @@ hipError_t launch_gather(bool fp64, int n_atoms, int n, int p, int tile, int ntx
                          const int* start, const void* rb, const void* rq, const double* phi0, const double* phi1,
                          const float* phi32, double* force, double* partial, Ctl* ctl, hipStream_t s, bool finalize,
                          int stencil) {
-  if (tile != 8 || (stencil == 1 && p > 5)) return hipErrorInvalidValue;
+  if (tile != 8 || (stencil == 1 && p > 5) || ntx < 1 || (ntx & (ntx - 1))) return hipErrorInvalidValue;
   const int nb = std::min(ntx * ntx * ntx, kMaxRedBlocks);
   // the step's gather (finalize) waits for a converged solve
   const Ctl* gate = finalize ? ctl : nullptr;
