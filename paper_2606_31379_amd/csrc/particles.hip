@@ -1222,10 +1222,11 @@ __device__ __forceinline__ void sr_atom(const typename ShortRange<LIST, NE>::Arg
   const double inv_box = 1.0 / box;
   const double tapi = 2.0 * alpha / sqrt(M_PI);
   const int gi = excl_group > 0 ? i / excl_group : -1;
-  auto pair = [&](double dx, double dy, double dz, double r2, double qj) {
+  // the pair term from r^2 and 1/r (one reciprocal square root serves the
+  // erfc term and the non-electrostatic term of the same pair)
+  auto pair_ir = [&](double dx, double dy, double dz, double r2, double inv_r, double qj) {
     // erfc(a r) = exp(-a^2 r^2) erfcx(a r), erfcx from the table
-    const double r = sqrt(r2);
-    const double inv_r = 1.0 / r;
+    const double r = r2 * inv_r;
     const double x = alpha * r;
     const double g = exp(-x * x);
     const double ec = g * erfcx_table(tab, tab_n, tab_scale, x);
@@ -1234,12 +1235,13 @@ __device__ __forceinline__ void sr_atom(const typename ShortRange<LIST, NE>::Arg
     fx += f * dx; fy += f * dy; fz += f * dz;
     en += 0.5 * qq * ec * inv_r;
   };
+  auto pair = [&](double dx, double dy, double dz, double r2, double qj) { pair_ir(dx, dy, dz, r2, rsqrt(r2), qj); };
   if constexpr (LIST && NE != 0) {
     // one pass over the list: the erfc pair and, where it applies, the
     // non-electrostatic pair (model 2: O-O only; the atom is an O when its
     // index is divisible by 3 and the entry's site flag marks an O partner)
     const int model = A.model;
-    const double p0 = A.ne_p0, p1 = A.ne_p1;
+    const double p0 = A.ne_p0, p1 = A.ne_p1, inv_p1 = 1.0 / p1, p1sq = p1 * p1;
     const bool i_site = model == 1 || i % 3 == 0;
     const int* ent = A.list + (size_t)wave * A.cap;
     const int cnt = A.nlist[wave];
@@ -1252,18 +1254,19 @@ __device__ __forceinline__ void sr_atom(const typename ShortRange<LIST, NE>::Arg
       const double dz = min_img(zi - a.z, box, inv_b);
       const double r2 = dx * dx + dy * dy + dz * dz;
       if (!(r2 < rc2)) continue;
-      if (!(e & kNbrSameGroup)) pair(dx, dy, dz, r2, a.w);
+      const double inv_r = rsqrt(r2);
+      if (!(e & kNbrSameGroup)) pair_ir(dx, dy, dz, r2, inv_r, a.w);
       if (i_site && (model == 1 || (e & kNbrSite))) {
         double f;
         if (model == 1) {
-          const double r = sqrt(r2);
-          const double v = p0 * exp(-r / p1);
-          f = v / p1 / r;
+          const double v = p0 * exp(-(r2 * inv_r) * inv_p1);
+          f = v * inv_p1 * inv_r;
           ene += 0.5 * (v - ne_shift);
         } else {
-          const double sr2 = p1 * p1 / r2;
+          const double inv_r2 = inv_r * inv_r;
+          const double sr2 = p1sq * inv_r2;
           const double sr6 = sr2 * sr2 * sr2;
-          f = 24.0 * p0 * (2.0 * sr6 * sr6 - sr6) / r2;
+          f = 24.0 * p0 * (2.0 * sr6 * sr6 - sr6) * inv_r2;
           ene += 0.5 * (4.0 * p0 * (sr6 * sr6 - sr6) - ne_shift);
         }
         fx += f * dx; fy += f * dy; fz += f * dz;
